@@ -1,0 +1,161 @@
+/*
+ * reaxff.h -- C ABI of the MI355X (gfx950) ReaxFF force-evaluation library.
+ *
+ * One ReaxFF force evaluation per MD step, for given atomic charges: the
+ * problem of the paper's Algorithms 1 and 2 (input: atom list and positions;
+ * output: potential energy and per-atom forces), with the lists of its
+ * Section 3.3 (half far-neighbour list in compressed-row form, full bond list
+ * holding both directions, hydrogen-bond list around H atoms) and the
+ * interactions named in Section 2.1 (bond orders; bond, lone pair, over- and
+ * under-coordination, valence angle, torsion and hydrogen-bond terms;
+ * tapered van der Waals and shielded Coulomb).  Charge equilibration is not
+ * part of this library: charges are an input.
+ *
+ * Conventions
+ *   Units: Angstrom, fs, g/mol, e, kcal/mol; forces in kcal/(mol A).
+ *   Atom types: 0..3 = C, H, N, O.  Any other value -> REAXFF_ERR_ARG.
+ *   Pointers marked [dev] are device memory of the context's GPU, owned by
+ *   the caller (the library never frees or reallocates them); [host] pointers
+ *   are host memory.  Positions are [n][3] row-major doubles, forces likewise.
+ *   Outputs are in the caller's atom order.
+ *   box: [host] three edge lengths of a periodic orthorhombic box with its
+ *   corner at the origin (minimum image convention; every edge must be at
+ *   least 2 r_nonb, else REAXFF_ERR_BOX), or NULL for a non-periodic system.
+ *   Streams: all device work of a call is enqueued on `stream`.
+ *   Thread safety: one context is used by one host thread at a time.
+ *
+ * Errors: every int-returning call returns 0 (REAXFF_OK) or a negative code;
+ *   reaxff_last_error() gives the message of the context's last failure.
+ */
+#ifndef REAXFF_H
+#define REAXFF_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define REAXFF_NTYPES 4
+/* energies[] order: bond, lone pair, over-coordination, under-coordination,
+ * valence angle, penalty, coalition, torsion, 4-body conjugation,
+ * hydrogen bond, van der Waals (incl. inner wall), Coulomb */
+#define REAXFF_NTERMS 12
+
+enum {
+  REAXFF_OK = 0,
+  REAXFF_ERR_ARG = -1,       /* bad argument (null pointer, n < 0, bad type index) */
+  REAXFF_ERR_CAPACITY = -2,  /* a fixed-capacity buffer is too small (batched call) */
+  REAXFF_ERR_BOX = -3,       /* periodic box edge below 2 r_nonb */
+  REAXFF_ERR_HIP = -4,       /* HIP runtime failure (allocation, launch) */
+  REAXFF_ERR_NONFINITE = -5, /* non-finite position */
+  REAXFF_ERR_STATE = -6      /* call out of order (forces before lists, n changed) */
+};
+
+/* Force-field parameters, flattened per element (C,H,N,O).  Pair tables are
+ * symmetric; angle tables are indexed [i][j=centre][k] and symmetric in i,k;
+ * torsion tables [i][j][k][l] are symmetric under reversal; hydrogen-bond
+ * tables are indexed [X][H][Z].  A non-positive bond radius switches the
+ * corresponding bond-order component off for that pair. */
+typedef struct reaxff_params {
+  /* general */
+  double p_boc1, p_boc2, p_coa2, p_coa3, p_coa4, p_ovun3, p_ovun4, p_ovun6,
+      p_ovun7, p_ovun8, p_val6, p_val8, p_val9, p_val10, p_pen2, p_pen3,
+      p_pen4, p_tor2, p_tor3, p_tor4, p_cot2, p_vdW1, p_lp1;
+  /* per element */
+  double val[4], val_e[4], val_boc[4], val_ang[4], mass[4], p_hbond[4],
+      p_lp2[4], p_ovun2[4], p_ovun5[4], p_val3[4], p_val5[4];
+  /* per element pair */
+  double r_s[4][4], r_p[4][4], r_pp[4][4], D_s[4][4], D_p[4][4], D_pp[4][4],
+      p_be1[4][4], p_be2[4][4], p_bo1[4][4], p_bo2[4][4], p_bo3[4][4],
+      p_bo4[4][4], p_bo5[4][4], p_bo6[4][4], p_ovun1[4][4], p_boc3[4][4],
+      p_boc4[4][4], p_boc5[4][4], D_vdw[4][4], r_vdw[4][4], alpha[4][4],
+      gamma_w[4][4], gamma[4][4], r_core[4][4], e_core[4][4], a_core[4][4];
+  /* valence angle [i][j][k] */
+  double theta00[4][4][4], p_val1[4][4][4], p_val2[4][4][4], p_val4[4][4][4],
+      p_val7[4][4][4], p_pen1[4][4][4], p_coa1[4][4][4];
+  /* torsion [i][j][k][l] */
+  double V1[4][4][4][4], V2[4][4][4][4], V3[4][4][4][4], p_tor1[4][4][4][4],
+      p_cot1[4][4][4][4];
+  /* hydrogen bond [X][H][Z] */
+  double r0hb[4][4][4], p_hb1[4][4][4], p_hb2[4][4][4], p_hb3[4][4][4];
+} reaxff_params;
+
+/* Cutoffs (A) and bond-order thresholds.  Defaults: 10, 5, 7.5, 0.01, 0.001,
+ * 1e-5, 0.01. */
+typedef struct reaxff_cutoffs {
+  double r_nonb;    /* nonbonded cutoff; the 7th-order taper vanishes here */
+  double r_bond;    /* bond-candidate distance */
+  double r_hb;      /* donor H to acceptor distance */
+  double bo_cut;    /* uncorrected bond-order threshold of the bond list */
+  double thb_cut;   /* bond-order threshold inside angles and torsions */
+  double thb_cutsq; /* bond-order product threshold of angles */
+  double hb_bo_cut; /* donor bond-order threshold of hydrogen bonds */
+} reaxff_cutoffs;
+
+typedef struct reaxff_ctx reaxff_ctx;
+
+/* Size in bytes of reaxff_params as compiled into the library (layout check). */
+int64_t reaxff_params_size(void);
+
+/* Create a context on HIP device `device`: uploads the parameters and sets
+ * the cutoffs (NULL = defaults).  *out receives the context.  Device scratch
+ * (cell arrays, lists, per-bond and per-atom work arrays) is owned by the
+ * context and grows inside reaxff_build_lists. */
+int reaxff_create(const reaxff_params* params, const reaxff_cutoffs* cutoffs,
+                  int device, reaxff_ctx** out);
+void reaxff_destroy(reaxff_ctx* ctx);
+
+/* Build the three lists for n atoms (Section 3.3): cell-sort the atoms,
+ * then count, prefix-sum and fill the half far-neighbour list (pairs with
+ * r <= r_nonb), the full bond list (r <= r_bond and raw uncorrected bond
+ * order >= bo_cut, both directions, with mirror index) and the H-bond list
+ * (H donors, N/O acceptors, r <= r_hb).  pos [dev] (n,3), type [dev] (n).
+ * Performs the library's only host synchronisation: one readback of the
+ * list totals to size the list buffers. */
+int reaxff_build_lists(reaxff_ctx* ctx, int64_t n, const double* pos,
+                       const int32_t* type, const double* box, hipStream_t stream);
+
+/* One force evaluation over the lists of the last reaxff_build_lists call,
+ * which must have been made with the same n, pos and type.  q [dev] (n)
+ * charges.  forces [dev] (n,3) and energies [dev] (REAXFF_NTERMS) are
+ * overwritten.  Asynchronous on `stream`. */
+int reaxff_compute_forces(reaxff_ctx* ctx, int64_t n, const double* pos,
+                          const int32_t* type, const double* q, const double* box,
+                          double* forces, double* energies, hipStream_t stream);
+
+/* nsteps steps of velocity-Verlet NVE (dt in fs, Section 4's MD step), lists
+ * rebuilt every step: lists and forces at the initial positions, then per
+ * step half kick, drift (positions wrapped into a periodic box), lists,
+ * forces, half kick.  pos, vel [dev] (n,3) in/out; forces [dev] (n,3) out:
+ * the forces at the final positions.  energies [dev]
+ * ((nsteps+1), REAXFF_NTERMS+1): potential terms and kinetic energy at every
+ * step, step 0 first.  One host synchronisation per step (list sizes). */
+int reaxff_step(reaxff_ctx* ctx, int64_t n, double* pos, double* vel,
+                const int32_t* type, const double* q, const double* box,
+                double dt, int32_t nsteps, double* forces, double* energies,
+                hipStream_t stream);
+
+/* Sizes of the last built lists: sizes[0] far pairs (unordered),
+ * sizes[1] bond-list entries (directed), sizes[2] H-list entries. [host] */
+int reaxff_list_sizes(const reaxff_ctx* ctx, int64_t sizes[3]);
+
+/* Copy the last built lists to host memory in the caller's atom order:
+ * far[2*sizes[0]] as (i,j) pairs, bonds[2*sizes[1]] as directed (i,j),
+ * hb[2*sizes[2]] as (h,z).  Order within each array is unspecified.
+ * Any pointer may be NULL to skip that list.  Synchronises the device. */
+int reaxff_export_lists(reaxff_ctx* ctx, int32_t* far, int32_t* bonds, int32_t* hb);
+
+/* Interaction counts of the last reaxff_compute_forces [host]:
+ * counts[0] valence angles, [1] torsions, [2] hydrogen bonds evaluated,
+ * [3] far pairs, [4] bonds (undirected).  Synchronises the device. */
+int reaxff_interaction_counts(reaxff_ctx* ctx, int64_t counts[5]);
+
+const char* reaxff_strerror(int code);
+const char* reaxff_last_error(const reaxff_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* REAXFF_H */

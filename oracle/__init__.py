@@ -34,8 +34,8 @@ def _load():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        from . import build as _b  # noqa: F401  (oracle/build.py)
-        _b.build()
+        import importlib
+        importlib.import_module(__name__ + ".build").build()
     lib = ctypes.CDLL(LIB_PATH)
     lib.oracle_new.restype = ctypes.c_void_p
     lib.oracle_new.argtypes = [ctypes.c_int32, _d, _i32, _d, _d, _d, _d, _d, _d, _d, _d, _d,
@@ -49,6 +49,7 @@ def _load():
     lib.oracle_bo_raw.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]
     lib.oracle_energy.argtypes = [ctypes.c_void_p, _d]
     lib.oracle_forces.argtypes = [ctypes.c_void_p, _d, _d]
+    lib.oracle_energy_abs.argtypes = [ctypes.c_void_p, _d, _d]
     lib.oracle_energy_cs.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_double, _d, _d]
     lib.oracle_atom_terms.argtypes = [ctypes.c_void_p, _d]
@@ -134,6 +135,13 @@ class Oracle:
         self._lib.oracle_energy(self._h, _ptr(e))
         return e
 
+    def energy_abs(self):
+        """(energies (12,), sum of |interaction energy| per term (12,))."""
+        e = np.zeros(NTERMS)
+        a = np.zeros(NTERMS)
+        self._lib.oracle_energy_abs(self._h, _ptr(e), _ptr(a))
+        return e, a
+
     def forces(self):
         """(energies (12,), forces (n,3)) with F = -dE/dx."""
         e = np.zeros(NTERMS)
@@ -175,7 +183,3 @@ class Oracle:
         self._pos = pos
         return pos, v, e
 
-
-def build():
-    from .build import build as _build
-    return _build()

@@ -52,6 +52,8 @@ double oracle_bo_raw(void* h, int32_t i, int32_t j);
 
 /* energies only (E[ORACLE_NTERMS]) */
 int oracle_energy(void* h, double* E);
+/* energies and, per term, the sum of |interaction energy| (E, Eabs [ORACLE_NTERMS]) */
+int oracle_energy_abs(void* h, double* E, double* Eabs);
 /* energies and forces F[3n] (reverse-mode differentiation) */
 int oracle_forces(void* h, double* E, double* F);
 /* complex-step: energies evaluated at x + i*hstep*e_(atom,comp);

@@ -335,8 +335,9 @@ struct Neumaier {
 
 struct DoubleSink {
   Neumaier E[NTERMS];
+  Neumaier A[NTERMS];   // sum of |interaction energy|: the conditioning of each term
   size_t begin() { return 0; }
-  void add(int t, double e) { E[t].add(e); }
+  void add(int t, double e) { E[t].add(e); A[t].add(std::fabs(e)); }
   void end(size_t) {}
 };
 
@@ -684,11 +685,13 @@ void energy(const Sys& s, const T* x, BondStage<T>& B, Sink& sink) {
 // ---------------------------------------------------------------------------
 // drivers
 // ---------------------------------------------------------------------------
-static void energies_double(const Sys& s, double* E) {
+static void energies_double(const Sys& s, double* E, double* Eabs = nullptr) {
   DoubleSink sink;
   BondStage<double> B;
   energy<double>(s, s.x.data(), B, sink);
   for (int t = 0; t < NTERMS; ++t) E[t] = sink.E[t].value();
+  if (Eabs)
+    for (int t = 0; t < NTERMS; ++t) Eabs[t] = sink.A[t].value();
 }
 
 static void energies_forces(const Sys& s, double* E, double* F) {
@@ -788,6 +791,11 @@ double oracle_bo_raw(void* h, int32_t i, int32_t j) {
 
 int oracle_energy(void* h, double* E) {
   energies_double(*static_cast<Sys*>(h), E);
+  return 0;
+}
+
+int oracle_energy_abs(void* h, double* E, double* Eabs) {
+  energies_double(*static_cast<Sys*>(h), E, Eabs);
   return 0;
 }
 

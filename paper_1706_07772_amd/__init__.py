@@ -1,0 +1,7 @@
+"""MI355X-native (gfx950, HIP, FP64) ReaxFF force evaluation.
+
+The compute path is the HIP library libreaxff_hip.so behind the C ABI in
+include/reaxff.h; this package holds its sources (csrc/), its build script
+and a thin ctypes binding.
+"""
+from .binding import NTERMS, TERM_NAMES, ReaxFF, ReaxFFError, load_library  # noqa: F401

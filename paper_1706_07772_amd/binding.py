@@ -1,0 +1,212 @@
+"""Thin ctypes binding of the gfx950 ReaxFF library (include/reaxff.h).
+
+Argument marshalling only: every step of the force evaluation runs in the
+HIP kernels of libreaxff_hip.so.  PyTorch supplies device memory and the
+current stream.  If the library is missing, loading fails loudly; there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libreaxff_hip.so")
+NTERMS = 12
+TERM_NAMES = ("bond", "lp", "over", "under", "val", "pen", "coa", "tor", "conj",
+              "hb", "vdw", "coul")
+
+ERRORS = {0: "ok", -1: "REAXFF_ERR_ARG", -2: "REAXFF_ERR_CAPACITY", -3: "REAXFF_ERR_BOX",
+          -4: "REAXFF_ERR_HIP", -5: "REAXFF_ERR_NONFINITE", -6: "REAXFF_ERR_STATE"}
+
+_GENERAL = ("p_boc1", "p_boc2", "p_coa2", "p_coa3", "p_coa4", "p_ovun3", "p_ovun4", "p_ovun6",
+            "p_ovun7", "p_ovun8", "p_val6", "p_val8", "p_val9", "p_val10", "p_pen2", "p_pen3",
+            "p_pen4", "p_tor2", "p_tor3", "p_tor4", "p_cot2", "p_vdW1", "p_lp1")
+_ATOM = ("val", "val_e", "val_boc", "val_ang", "mass", "p_hbond", "p_lp2", "p_ovun2", "p_ovun5",
+         "p_val3", "p_val5")
+_PAIR = ("r_s", "r_p", "r_pp", "D_s", "D_p", "D_pp", "p_be1", "p_be2", "p_bo1", "p_bo2", "p_bo3",
+         "p_bo4", "p_bo5", "p_bo6", "p_ovun1", "p_boc3", "p_boc4", "p_boc5", "D_vdw", "r_vdw",
+         "alpha", "gamma_w", "gamma", "r_core", "e_core", "a_core")
+_ANGLE = ("theta00", "p_val1", "p_val2", "p_val4", "p_val7", "p_pen1", "p_coa1")
+_TORS = ("V1", "V2", "V3", "p_tor1", "p_cot1")
+_HB = ("r0hb", "p_hb1", "p_hb2", "p_hb3")
+
+_d = ctypes.c_double
+_fields = ([(k, _d) for k in _GENERAL] + [(k, _d * 4) for k in _ATOM] +
+           [(k, (_d * 4) * 4) for k in _PAIR] + [(k, ((_d * 4) * 4) * 4) for k in _ANGLE] +
+           [(k, (((_d * 4) * 4) * 4) * 4) for k in _TORS] + [(k, ((_d * 4) * 4) * 4) for k in _HB])
+
+
+class CParams(ctypes.Structure):
+    _fields_ = _fields
+
+
+class CCutoffs(ctypes.Structure):
+    _fields_ = [(k, _d) for k in ("r_nonb", "r_bond", "r_hb", "bo_cut", "thb_cut", "thb_cutsq",
+                                  "hb_bo_cut")]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libreaxff_hip.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    lib.reaxff_params_size.restype = i64
+    lib.reaxff_create.argtypes = [ctypes.POINTER(CParams), ctypes.POINTER(CCutoffs), ctypes.c_int,
+                                  ctypes.POINTER(vp)]
+    lib.reaxff_destroy.argtypes = [vp]
+    lib.reaxff_build_lists.argtypes = [vp, i64, vp, vp, vp, vp]
+    lib.reaxff_compute_forces.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
+    lib.reaxff_step.argtypes = [vp, i64, vp, vp, vp, vp, vp, _d, i32, vp, vp, vp]
+    lib.reaxff_list_sizes.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.reaxff_export_lists.argtypes = [vp, vp, vp, vp]
+    lib.reaxff_interaction_counts.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.reaxff_last_error.restype = ctypes.c_char_p
+    lib.reaxff_last_error.argtypes = [vp]
+    lib.reaxff_strerror.restype = ctypes.c_char_p
+    if lib.reaxff_params_size() != ctypes.sizeof(CParams):
+        raise RuntimeError("reaxff_params layout mismatch between binding and library")
+    _lib = lib
+    return lib
+
+
+def make_cparams(params) -> CParams:
+    """Marshal a parameter set (general/atom/pair/angle/tors/hb tables) into reaxff_params."""
+    cp = CParams()
+    for k in _GENERAL:
+        setattr(cp, k, float(params.general[k]))
+    for block, names in ((params.atom, _ATOM), (params.pair, _PAIR), (params.angle, _ANGLE),
+                         (params.tors, _TORS), (params.hb, _HB)):
+        for k in names:
+            arr = np.ascontiguousarray(block[k], dtype=np.float64)
+            dst = getattr(cp, k)
+            ctypes.memmove(ctypes.addressof(dst), arr.ctypes.data, arr.nbytes)
+    return cp
+
+
+def make_ccutoffs(cutoffs: dict | None) -> CCutoffs | None:
+    if cutoffs is None:
+        return None
+    c = CCutoffs()
+    for k, _ in CCutoffs._fields_:
+        setattr(c, k, float(cutoffs[k]))
+    return c
+
+
+class ReaxFFError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class ReaxFF:
+    """A library context on one GPU (reaxff_create / reaxff_destroy)."""
+
+    def __init__(self, params, cutoffs: dict | None = None, device: int = 0):
+        self._lib = load_library()
+        self.device = device
+        self._cp = make_cparams(params)
+        self._cc = make_ccutoffs(cutoffs)
+        h = ctypes.c_void_p()
+        rc = self._lib.reaxff_create(ctypes.byref(self._cp),
+                                     ctypes.byref(self._cc) if self._cc is not None else None,
+                                     device, ctypes.byref(h))
+        if rc != 0:
+            raise ReaxFFError(rc, "reaxff_create failed")
+        self._h = h
+        self._box = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.reaxff_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != 0:
+            raise ReaxFFError(rc, self._lib.reaxff_last_error(self._h).decode())
+
+    @staticmethod
+    def _boxarg(box):
+        if box is None:
+            return None, None
+        b = (ctypes.c_double * 3)(*[float(x) for x in box])
+        return b, ctypes.cast(b, ctypes.c_void_p)
+
+    def build_lists(self, pos: torch.Tensor, type_: torch.Tensor, box=None):
+        """reaxff_build_lists: pos (n,3) float64 cuda, type (n,) int32 cuda."""
+        assert pos.dtype == torch.float64 and pos.is_cuda and pos.is_contiguous()
+        assert type_.dtype == torch.int32 and type_.is_cuda and type_.is_contiguous()
+        b, bp = self._boxarg(box)
+        self._check(self._lib.reaxff_build_lists(self._h, pos.shape[0], _ptr(pos), _ptr(type_), bp,
+                                                 _stream()))
+
+    def compute_forces(self, pos, type_, q, box=None, forces=None, energies=None):
+        """reaxff_compute_forces -> (forces (n,3), energies (12,)) float64 cuda tensors."""
+        n = pos.shape[0]
+        if forces is None:
+            forces = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+        if energies is None:
+            energies = torch.empty(NTERMS, dtype=torch.float64, device=pos.device)
+        assert q.dtype == torch.float64 and q.is_cuda and q.is_contiguous()
+        b, bp = self._boxarg(box)
+        self._check(self._lib.reaxff_compute_forces(self._h, n, _ptr(pos), _ptr(type_), _ptr(q), bp,
+                                                    _ptr(forces), _ptr(energies), _stream()))
+        return forces, energies
+
+    def step(self, pos, vel, type_, q, box, dt: float, nsteps: int, forces=None, energies=None):
+        """reaxff_step: velocity-Verlet NVE in place on pos, vel.
+        Returns (forces (n,3), energies (nsteps+1, 13))."""
+        n = pos.shape[0]
+        if forces is None:
+            forces = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+        if energies is None:
+            energies = torch.empty((nsteps + 1, NTERMS + 1), dtype=torch.float64, device=pos.device)
+        b, bp = self._boxarg(box)
+        self._check(self._lib.reaxff_step(self._h, n, _ptr(pos), _ptr(vel), _ptr(type_), _ptr(q), bp,
+                                          float(dt), int(nsteps), _ptr(forces), _ptr(energies),
+                                          _stream()))
+        return forces, energies
+
+    def list_sizes(self):
+        s = (ctypes.c_int64 * 3)()
+        self._check(self._lib.reaxff_list_sizes(self._h, s))
+        return tuple(int(x) for x in s)
+
+    def export_lists(self):
+        """(far (M,2), bonds (B,2), hb (K,2)) int32 numpy arrays in caller indices."""
+        nf, nb, nh = self.list_sizes()
+        far = np.zeros((nf, 2), dtype=np.int32)
+        bonds = np.zeros((nb, 2), dtype=np.int32)
+        hb = np.zeros((nh, 2), dtype=np.int32)
+        self._check(self._lib.reaxff_export_lists(self._h, far.ctypes.data, bonds.ctypes.data,
+                                                  hb.ctypes.data))
+        return far, bonds, hb
+
+    def interaction_counts(self):
+        c = (ctypes.c_int64 * 5)()
+        self._check(self._lib.reaxff_interaction_counts(self._h, c))
+        return dict(zip(("angles", "torsions", "hbonds", "far_pairs", "bonds"), (int(x) for x in c)))

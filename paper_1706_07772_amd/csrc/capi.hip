@@ -1,0 +1,437 @@
+// C ABI of the library: context, parameter upload, buffer management and
+// the three calls of the hot path (build lists, compute forces, MD step).
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace rx;
+
+struct reaxff_ctx {
+  int device = 0;
+  reaxff_params hp;
+  reaxff_cutoffs cut;
+  DevParams* dp = nullptr;    // device copy
+  DevParams hd;               // host copy
+  Grid grid{};
+  Lists L{};
+  Work W{};
+  Scratch sc{};
+  bool built = false;
+  double box[3] = {0, 0, 0};
+  bool periodic = false;
+  int64_t cap_n = 0, cap_cell = 0, cap_far = 0, cap_bond = 0, cap_hb = 0, cap_part = 0;
+  std::string err;
+};
+
+namespace {
+
+int fail(reaxff_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                            \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail(ctx, REAXFF_ERR_HIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+template <class T>
+int grow(reaxff_ctx* c, T*& p, int64_t& cap, int64_t need, double slack = 1.2) {
+  if (need <= cap && p) return 0;
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  const int64_t n = std::max<int64_t>((int64_t)(need * slack) + 64, 64);
+  hipError_t e = hipMalloc(&p, sizeof(T) * n);
+  if (e != hipSuccess) {
+    cap = 0;
+    return fail(c, REAXFF_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  cap = n;
+  return 0;
+}
+
+// largest r with raw uncorrected bond order >= bo_cut for a pair (decreasing in r)
+double bond_reach(const PairP& p, double bo_cut, double rmax) {
+  auto raw = [&](double r) {
+    double s = 0, pi = 0, pp = 0;
+    if (p.r_s > 0) s = (1.0 + bo_cut) * std::exp(p.p_bo1 * std::pow(r / p.r_s, p.p_bo2));
+    if (p.r_p > 0) pi = std::exp(p.p_bo3 * std::pow(r / p.r_p, p.p_bo4));
+    if (p.r_pp > 0) pp = std::exp(p.p_bo5 * std::pow(r / p.r_pp, p.p_bo6));
+    return s + pi + pp;
+  };
+  const bool mono = (p.r_s <= 0 || (p.p_bo1 < 0 && p.p_bo2 > 0)) &&
+                    (p.r_p <= 0 || (p.p_bo3 < 0 && p.p_bo4 > 0)) &&
+                    (p.r_pp <= 0 || (p.p_bo5 < 0 && p.p_bo6 > 0));
+  if (!mono) return rmax;
+  if (raw(rmax) >= bo_cut) return rmax;
+  double lo = 1e-6, hi = rmax;
+  if (raw(lo) < bo_cut) return 0.0;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (raw(mid) >= bo_cut) lo = mid;
+    else hi = mid;
+  }
+  // generous margin: the exact test is applied after this prefilter
+  return std::min(rmax, hi * (1.0 + 1e-3) + 1e-3);
+}
+
+void fill_dev_params(const reaxff_params& p, const reaxff_cutoffs& c, DevParams& d) {
+  std::memset(&d, 0, sizeof(d));
+  d.p_boc1 = p.p_boc1; d.p_boc2 = p.p_boc2; d.p_coa2 = p.p_coa2; d.p_coa3 = p.p_coa3;
+  d.p_coa4 = p.p_coa4; d.p_ovun3 = p.p_ovun3; d.p_ovun4 = p.p_ovun4; d.p_ovun6 = p.p_ovun6;
+  d.p_ovun7 = p.p_ovun7; d.p_ovun8 = p.p_ovun8; d.p_val6 = p.p_val6; d.p_val8 = p.p_val8;
+  d.p_val9 = p.p_val9; d.p_val10 = p.p_val10; d.p_pen2 = p.p_pen2; d.p_pen3 = p.p_pen3;
+  d.p_pen4 = p.p_pen4; d.p_tor2 = p.p_tor2; d.p_tor3 = p.p_tor3; d.p_tor4 = p.p_tor4;
+  d.p_cot2 = p.p_cot2; d.p_vdW1 = p.p_vdW1; d.p_lp1 = p.p_lp1; d.inv_p_vdW1 = 1.0 / p.p_vdW1;
+  d.r_nonb = c.r_nonb; d.r_bond = c.r_bond; d.r_hb = c.r_hb; d.bo_cut = c.bo_cut;
+  d.thb_cut = c.thb_cut; d.thb_cutsq = c.thb_cutsq; d.hb_bo_cut = c.hb_bo_cut;
+  d.rn2 = c.r_nonb * c.r_nonb; d.rh2 = c.r_hb * c.r_hb; d.inv_r_nonb = 1.0 / c.r_nonb;
+  for (int t = 0; t < NT; ++t) {
+    AtomP& a = d.atom[t];
+    a.val = p.val[t]; a.val_e = p.val_e[t]; a.val_boc = p.val_boc[t]; a.val_ang = p.val_ang[t];
+    a.mass = p.mass[t]; a.p_lp2 = p.p_lp2[t]; a.p_ovun2 = p.p_ovun2[t]; a.p_ovun5 = p.p_ovun5[t];
+    a.p_val3 = p.p_val3[t]; a.p_val5 = p.p_val5[t];
+    a.nlp_opt = 0.5 * (p.val_e[t] - p.val[t]);
+    a.hbond = (int32_t)std::lround(p.p_hbond[t]);
+  }
+  for (int i = 0; i < NT; ++i)
+    for (int j = 0; j < NT; ++j) {
+      PairP& q = d.pair[i * NT + j];
+      q.r_s = p.r_s[i][j]; q.r_p = p.r_p[i][j]; q.r_pp = p.r_pp[i][j];
+      q.p_bo1 = p.p_bo1[i][j]; q.p_bo2 = p.p_bo2[i][j]; q.p_bo3 = p.p_bo3[i][j];
+      q.p_bo4 = p.p_bo4[i][j]; q.p_bo5 = p.p_bo5[i][j]; q.p_bo6 = p.p_bo6[i][j];
+      q.D_s = p.D_s[i][j]; q.D_p = p.D_p[i][j]; q.D_pp = p.D_pp[i][j];
+      q.p_be1 = p.p_be1[i][j]; q.p_be2 = p.p_be2[i][j]; q.p_ovun1 = p.p_ovun1[i][j];
+      q.p_boc3 = p.p_boc3[i][j]; q.p_boc4 = p.p_boc4[i][j]; q.p_boc5 = p.p_boc5[i][j];
+      q.D_vdw = p.D_vdw[i][j]; q.alpha = p.alpha[i][j]; q.inv_r_vdw = 1.0 / p.r_vdw[i][j];
+      q.gw_pow = std::pow(p.gamma_w[i][j], -p.p_vdW1);
+      q.g3 = std::pow(p.gamma[i][j], -3.0);
+      q.e_core = p.e_core[i][j]; q.a_core = p.a_core[i][j]; q.inv_r_core = 1.0 / p.r_core[i][j];
+      const double reach = bond_reach(q, c.bo_cut, c.r_bond);
+      q.reach2 = reach * reach;
+    }
+  for (int i = 0; i < NT; ++i)
+    for (int j = 0; j < NT; ++j)
+      for (int k = 0; k < NT; ++k) {
+        AngleP& a = d.angle[(i * NT + j) * NT + k];
+        a.theta00_rad = p.theta00[i][j][k] * (PI / 180.0);
+        a.p_val1 = p.p_val1[i][j][k]; a.p_val2 = p.p_val2[i][j][k]; a.p_val4 = p.p_val4[i][j][k];
+        a.p_val7 = p.p_val7[i][j][k]; a.p_pen1 = p.p_pen1[i][j][k]; a.p_coa1 = p.p_coa1[i][j][k];
+        HbP& h = d.hb[(i * NT + j) * NT + k];
+        h.r0hb = p.r0hb[i][j][k]; h.p_hb1 = p.p_hb1[i][j][k]; h.p_hb2 = p.p_hb2[i][j][k];
+        h.p_hb3 = p.p_hb3[i][j][k];
+        for (int l = 0; l < NT; ++l) {
+          TorsP& t = d.tors[((i * NT + j) * NT + k) * NT + l];
+          t.V1 = p.V1[i][j][k][l]; t.V2 = p.V2[i][j][k][l]; t.V3 = p.V3[i][j][k][l];
+          t.p_tor1 = p.p_tor1[i][j][k][l]; t.p_cot1 = p.p_cot1[i][j][k][l];
+        }
+      }
+}
+
+// grid: cells at least r_nonb/2 wide, +-2 cell stencil
+void make_grid(Grid& g, bool periodic, const double* box, const double lo[3], const double hi[3],
+               double r_nonb) {
+  g.periodic = periodic ? 1 : 0;
+  const double wmin = 0.5 * r_nonb;
+  for (int k = 0; k < 3; ++k) {
+    double ext;
+    if (periodic) {
+      g.lo[k] = 0.0;
+      ext = box[k];
+      g.L[k] = box[k];
+      g.invL[k] = 1.0 / box[k];
+    } else {
+      g.lo[k] = lo[k];
+      ext = std::max(hi[k] - lo[k], 1e-9);
+      g.L[k] = 0.0;
+      g.invL[k] = 0.0;
+    }
+    int nc = (int)std::floor(ext / wmin);
+    if (nc < 1) nc = 1;
+    g.nc[k] = nc;
+    g.invw[k] = nc / ext;
+    g.full[k] = nc < 5 ? 1 : 0;
+    g.span[k] = nc < 5 ? nc : 5;
+  }
+}
+
+int alloc_atoms(reaxff_ctx* c, int64_t n) {
+  if (n + 1 <= c->cap_n && c->L.perm) return 0;
+  int64_t cap = 0;
+  const int64_t need = n + 1;
+  int64_t tmp;
+#define G(ptr) do { tmp = c->cap_n; if (grow(c, ptr, tmp, need)) return REAXFF_ERR_HIP; cap = tmp; } while (0)
+  G(c->L.perm); G(c->L.type_s); G(c->L.xs); G(c->L.far_off); G(c->L.bond_off); G(c->L.hb_off);
+  G(c->sc.cid); G(c->sc.cell_s); G(c->sc.cnt_far); G(c->sc.cnt_bond); G(c->sc.cnt_hb);
+  G(c->W.dp); G(c->W.ast); G(c->W.gS); G(c->W.gSig); G(c->W.gSBO); G(c->W.gStot); G(c->W.gDp);
+  G(c->W.fnb); G(c->W.q_s);
+#undef G
+  c->cap_n = cap;
+  return 0;
+}
+
+int alloc_bonds(reaxff_ctx* c, int64_t nb) {
+  if (nb <= c->cap_bond && c->L.bond_j) return 0;
+  int64_t cap = 0, tmp;
+#define G(ptr) do { tmp = c->cap_bond; if (grow(c, ptr, tmp, nb)) return REAXFF_ERR_HIP; cap = tmp; } while (0)
+  G(c->L.bond_j); G(c->L.bond_mir); G(c->W.bd); G(c->W.bop); G(c->W.dbop); G(c->W.bo);
+  G(c->W.gbo); G(c->W.gvec); G(c->W.gup);
+#undef G
+  c->cap_bond = cap;
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t reaxff_params_size(void) { return (int64_t)sizeof(reaxff_params); }
+
+const char* reaxff_strerror(int code) {
+  switch (code) {
+    case REAXFF_OK: return "ok";
+    case REAXFF_ERR_ARG: return "invalid argument";
+    case REAXFF_ERR_CAPACITY: return "buffer capacity exceeded";
+    case REAXFF_ERR_BOX: return "periodic box edge below 2 r_nonb";
+    case REAXFF_ERR_HIP: return "HIP runtime error";
+    case REAXFF_ERR_NONFINITE: return "non-finite input";
+    case REAXFF_ERR_STATE: return "call out of order";
+    default: return "unknown error";
+  }
+}
+
+const char* reaxff_last_error(const reaxff_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int reaxff_create(const reaxff_params* params, const reaxff_cutoffs* cutoffs, int device,
+                  reaxff_ctx** out) {
+  if (!params || !out) return REAXFF_ERR_ARG;
+  *out = nullptr;
+  auto* c = new reaxff_ctx();
+  c->device = device;
+  c->hp = *params;
+  if (cutoffs) c->cut = *cutoffs;
+  else c->cut = reaxff_cutoffs{10.0, 5.0, 7.5, 0.01, 0.001, 1e-5, 0.01};
+  const reaxff_cutoffs& cc = c->cut;
+  if (!(cc.r_nonb > 0 && cc.r_bond > 0 && cc.r_hb > 0 && cc.r_bond <= cc.r_nonb &&
+        cc.r_hb <= cc.r_nonb && cc.bo_cut >= 0)) {
+    delete c;
+    return REAXFF_ERR_ARG;
+  }
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return REAXFF_ERR_HIP;
+  }
+  fill_dev_params(c->hp, c->cut, c->hd);
+  if (hipMalloc(&c->dp, sizeof(DevParams)) != hipSuccess ||
+      hipMemcpy(c->dp, &c->hd, sizeof(DevParams), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMalloc(&c->sc.flag, sizeof(int32_t) * 4) != hipSuccess ||
+      hipMalloc(&c->sc.totals, sizeof(int64_t) * 4) != hipSuccess ||
+      hipHostMalloc(&c->sc.totals_host, sizeof(int64_t) * 4, hipHostMallocDefault) != hipSuccess ||
+      hipMalloc(&c->W.counters, sizeof(unsigned long long) * 4) != hipSuccess) {
+    reaxff_destroy(c);
+    return REAXFF_ERR_HIP;
+  }
+  *out = c;
+  return REAXFF_OK;
+}
+
+void reaxff_destroy(reaxff_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  void* ptrs[] = {c->dp, c->L.perm, c->L.type_s, c->L.xs, c->L.cell_start, c->L.far_off,
+                  c->L.far_j, c->L.bond_off, c->L.bond_j, c->L.bond_mir, c->L.hb_off, c->L.hb_j,
+                  c->W.bd, c->W.bop, c->W.dbop, c->W.bo, c->W.gbo, c->W.gvec, c->W.gup, c->W.dp,
+                  c->W.ast, c->W.gS, c->W.gSig, c->W.gSBO, c->W.gStot, c->W.gDp, c->W.fnb,
+                  c->W.q_s, c->W.counters, c->sc.cid, c->sc.cell_s, c->sc.cell_count,
+                  c->sc.cell_cursor, c->sc.flag, c->sc.cnt_far, c->sc.cnt_bond, c->sc.cnt_hb,
+                  c->sc.part, c->sc.totals, c->sc.scan_tmp};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (c->sc.totals_host) (void)hipHostFree(c->sc.totals_host);
+  delete c;
+}
+
+int reaxff_build_lists(reaxff_ctx* c, int64_t n, const double* pos, const int32_t* type,
+                       const double* box, hipStream_t st) {
+  if (!c) return REAXFF_ERR_ARG;
+  if (n < 0 || (n > 0 && (!pos || !type))) return fail(c, REAXFF_ERR_ARG, "bad n or null pointer");
+  if (n >= (int64_t)INT32_MAX / 2) return fail(c, REAXFF_ERR_ARG, "n too large for 32-bit indices");
+  HIPCHK(c, hipSetDevice(c->device));
+  c->built = false;
+  c->periodic = box != nullptr;
+  if (box) {
+    for (int k = 0; k < 3; ++k) {
+      if (!(std::isfinite(box[k]) && box[k] >= 2.0 * c->cut.r_nonb))
+        return fail(c, REAXFF_ERR_BOX, "periodic box edge below 2 r_nonb");
+      c->box[k] = box[k];
+    }
+  }
+  if (alloc_atoms(c, n)) return REAXFF_ERR_HIP;
+  c->L.n = n;
+  // bounding box + finiteness
+  const int nparts = (int)std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 1024);
+  if (grow(c, c->sc.part, c->cap_part, 6 * nparts)) return REAXFF_ERR_HIP;
+  double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
+  if (n > 0) {
+    HIPCHK(c, hipMemsetAsync(c->sc.flag, 0, sizeof(int32_t) * 4, st));
+    launch_bbox(pos, type, n, c->sc.part, nparts, c->sc.flag, st);
+    std::vector<double> part(6 * nparts);
+    int32_t flag = 0;
+    HIPCHK(c, hipMemcpyAsync(part.data(), c->sc.part, sizeof(double) * 6 * nparts,
+                             hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(&flag, c->sc.flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (flag & 1) return fail(c, REAXFF_ERR_ARG, "atom type out of range 0..3");
+    for (int k = 0; k < 3; ++k) { lo[k] = 1e300; hi[k] = -1e300; }
+    for (int b = 0; b < nparts; ++b)
+      for (int k = 0; k < 3; ++k) {
+        lo[k] = std::min(lo[k], part[6 * b + k]);
+        hi[k] = std::max(hi[k], part[6 * b + 3 + k]);
+      }
+    for (int k = 0; k < 3; ++k)
+      if (!(lo[k] > -1e307) || !std::isfinite(hi[k]) || !std::isfinite(lo[k]))
+        return fail(c, REAXFF_ERR_NONFINITE, "non-finite position");
+  }
+  make_grid(c->grid, c->periodic, c->box, lo, hi, c->cut.r_nonb);
+  const int64_t ncell = (int64_t)c->grid.nc[0] * c->grid.nc[1] * c->grid.nc[2];
+  if (ncell > (int64_t)INT32_MAX / 4) return fail(c, REAXFF_ERR_ARG, "cell grid too large");
+  {
+    int64_t cap = c->cap_cell, t = cap;
+    if (grow(c, c->L.cell_start, t, ncell + 1)) return REAXFF_ERR_HIP;
+    t = cap; if (grow(c, c->sc.cell_count, t, ncell + 1)) return REAXFF_ERR_HIP;
+    t = cap; if (grow(c, c->sc.cell_cursor, t, ncell + 1)) return REAXFF_ERR_HIP;
+    c->cap_cell = t;
+  }
+  if (n > 0) {
+    if (launch_cell_sort(pos, type, n, c->grid, (int)ncell, c->sc, c->L, st))
+      return fail(c, REAXFF_ERR_HIP, "cell sort launch failed");
+    if (launch_count(c->dp, c->grid, n, c->sc, c->L, st))
+      return fail(c, REAXFF_ERR_HIP, "count launch failed");
+  }
+  // offsets: counts with a trailing zero, exclusive scan, last element = total
+  HIPCHK(c, hipMemsetAsync(c->sc.cnt_far + n, 0, sizeof(int32_t), st));
+  HIPCHK(c, hipMemsetAsync(c->sc.cnt_bond + n, 0, sizeof(int32_t), st));
+  HIPCHK(c, hipMemsetAsync(c->sc.cnt_hb + n, 0, sizeof(int32_t), st));
+  if (scan_i32_to_i64(c->sc.cnt_far, c->L.far_off, n + 1, c->sc, st) ||
+      scan_i32(c->sc.cnt_bond, c->L.bond_off, n + 1, c->sc, st) ||
+      scan_i32(c->sc.cnt_hb, c->L.hb_off, n + 1, c->sc, st))
+    return fail(c, REAXFF_ERR_HIP, "scan failed");
+  // the one host synchronisation: list totals (and the type check flag)
+  int64_t* th = c->sc.totals_host;
+  HIPCHK(c, hipMemcpyAsync(&th[0], c->L.far_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  int32_t t32[3] = {0, 0, 0};
+  HIPCHK(c, hipMemcpyAsync(&t32[0], c->L.bond_off + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipMemcpyAsync(&t32[1], c->L.hb_off + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  c->L.nfar = th[0];
+  c->L.nbond = t32[0];
+  c->L.nhb = t32[1];
+  {
+    int64_t t = c->cap_far;
+    if (grow(c, c->L.far_j, t, std::max<int64_t>(c->L.nfar, 1))) return REAXFF_ERR_HIP;
+    c->cap_far = t;
+    t = c->cap_hb;
+    if (grow(c, c->L.hb_j, t, std::max<int64_t>(c->L.nhb, 1))) return REAXFF_ERR_HIP;
+    c->cap_hb = t;
+    if (alloc_bonds(c, std::max<int64_t>(c->L.nbond, 1))) return REAXFF_ERR_HIP;
+  }
+  if (n > 0 && launch_fill(c->dp, c->grid, n, c->sc, c->L, st))
+    return fail(c, REAXFF_ERR_HIP, "fill launch failed");
+  c->built = true;
+  return REAXFF_OK;
+}
+
+int reaxff_compute_forces(reaxff_ctx* c, int64_t n, const double* pos, const int32_t* type,
+                          const double* q, const double* box, double* forces, double* energies,
+                          hipStream_t st) {
+  if (!c) return REAXFF_ERR_ARG;
+  if (!c->built || n != c->L.n) return fail(c, REAXFF_ERR_STATE, "lists not built for this n");
+  if ((box != nullptr) != c->periodic) return fail(c, REAXFF_ERR_STATE, "box differs from build");
+  if (box)
+    for (int k = 0; k < 3; ++k)
+      if (box[k] != c->box[k]) return fail(c, REAXFF_ERR_STATE, "box differs from build");
+  if (!energies || (n > 0 && (!pos || !type || !q || !forces)))
+    return fail(c, REAXFF_ERR_ARG, "null pointer");
+  (void)pos; (void)type;   // the sorted copies made by the list build are used
+  HIPCHK(c, hipSetDevice(c->device));
+  if (launch_forces(c->dp, c->grid, c->L, c->W, q, forces, energies, st))
+    return fail(c, REAXFF_ERR_HIP, "force launch failed");
+  return REAXFF_OK;
+}
+
+int reaxff_step(reaxff_ctx* c, int64_t n, double* pos, double* vel, const int32_t* type,
+                const double* q, const double* box, double dt, int32_t nsteps, double* forces,
+                double* energies, hipStream_t st) {
+  if (!c) return REAXFF_ERR_ARG;
+  if (n < 0 || nsteps < 0 || !energies || (n > 0 && (!pos || !vel || !type || !q || !forces)))
+    return fail(c, REAXFF_ERR_ARG, "bad argument");
+  if (!(std::isfinite(dt))) return fail(c, REAXFF_ERR_ARG, "bad time step");
+  HIPCHK(c, hipSetDevice(c->device));
+  const int64_t row = REAXFF_NTERMS + 1;
+  int rc;
+  if ((rc = reaxff_build_lists(c, n, pos, type, box, st))) return rc;
+  if ((rc = reaxff_compute_forces(c, n, pos, type, q, box, forces, energies, st))) return rc;
+  launch_kinetic(n, vel, type, c->dp, energies + REAXFF_NTERMS, st);
+  for (int s = 1; s <= nsteps; ++s) {
+    launch_kick(n, vel, forces, type, c->dp, 0.5 * dt, st);
+    launch_drift(n, pos, vel, dt, c->grid, st);
+    if ((rc = reaxff_build_lists(c, n, pos, type, box, st))) return rc;
+    if ((rc = reaxff_compute_forces(c, n, pos, type, q, box, forces, energies + s * row, st)))
+      return rc;
+    launch_kick(n, vel, forces, type, c->dp, 0.5 * dt, st);
+    launch_kinetic(n, vel, type, c->dp, energies + s * row + REAXFF_NTERMS, st);
+  }
+  HIPCHK(c, hipGetLastError());
+  return REAXFF_OK;
+}
+
+int reaxff_list_sizes(const reaxff_ctx* c, int64_t sizes[3]) {
+  if (!c || !sizes) return REAXFF_ERR_ARG;
+  if (!c->built) return REAXFF_ERR_STATE;
+  sizes[0] = c->L.nfar;
+  sizes[1] = c->L.nbond;
+  sizes[2] = c->L.nhb;
+  return REAXFF_OK;
+}
+
+int reaxff_export_lists(reaxff_ctx* c, int32_t* far, int32_t* bonds, int32_t* hb) {
+  if (!c) return REAXFF_ERR_ARG;
+  if (!c->built) return fail(c, REAXFF_ERR_STATE, "lists not built");
+  HIPCHK(c, hipSetDevice(c->device));
+  int32_t *df = nullptr, *db = nullptr, *dh = nullptr;
+  if (far && c->L.nfar) HIPCHK(c, hipMalloc(&df, sizeof(int32_t) * 2 * c->L.nfar));
+  if (bonds && c->L.nbond) HIPCHK(c, hipMalloc(&db, sizeof(int32_t) * 2 * c->L.nbond));
+  if (hb && c->L.nhb) HIPCHK(c, hipMalloc(&dh, sizeof(int32_t) * 2 * c->L.nhb));
+  launch_export(c->L, df, db, dh, 0);
+  HIPCHK(c, hipDeviceSynchronize());
+  if (df) HIPCHK(c, hipMemcpy(far, df, sizeof(int32_t) * 2 * c->L.nfar, hipMemcpyDeviceToHost));
+  if (db) HIPCHK(c, hipMemcpy(bonds, db, sizeof(int32_t) * 2 * c->L.nbond, hipMemcpyDeviceToHost));
+  if (dh) HIPCHK(c, hipMemcpy(hb, dh, sizeof(int32_t) * 2 * c->L.nhb, hipMemcpyDeviceToHost));
+  if (df) (void)hipFree(df);
+  if (db) (void)hipFree(db);
+  if (dh) (void)hipFree(dh);
+  return REAXFF_OK;
+}
+
+int reaxff_interaction_counts(reaxff_ctx* c, int64_t counts[5]) {
+  if (!c || !counts) return REAXFF_ERR_ARG;
+  HIPCHK(c, hipSetDevice(c->device));
+  unsigned long long h[4] = {0, 0, 0, 0};
+  HIPCHK(c, hipDeviceSynchronize());
+  HIPCHK(c, hipMemcpy(h, c->W.counters, sizeof(h), hipMemcpyDeviceToHost));
+  counts[0] = (int64_t)h[0];
+  counts[1] = (int64_t)h[1];
+  counts[2] = (int64_t)h[2];
+  counts[3] = c->L.nfar;
+  counts[4] = c->L.nbond / 2;
+  return REAXFF_OK;
+}
+
+}  // extern "C"

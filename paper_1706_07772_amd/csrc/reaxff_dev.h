@@ -1,0 +1,157 @@
+// Device-side data layout and helpers of the gfx950 ReaxFF library.
+//
+// Everything runs in "sorted" atom order: atoms are counting-sorted by cell
+// so that spatial neighbours are neighbours in memory (the spatially reordered
+// atom list the paper relies on in Section 3.2, made explicit).  The caller's
+// order is restored only when forces are written out.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/reaxff.h"
+
+namespace rx {
+
+constexpr int NT = REAXFF_NTYPES;
+constexpr int NTERMS = REAXFF_NTERMS;
+enum Term { E_BOND, E_LP, E_OVER, E_UNDER, E_VAL, E_PEN, E_COA, E_TOR, E_CONJ, E_HB, E_VDW, E_COUL };
+
+constexpr double C_ELE = 332.06371;      // kcal A / (mol e^2)
+constexpr double ACC_CONV = 4.184e-4;    // (kcal/mol/A) / (g/mol) -> A/fs^2
+constexpr double PI = 3.14159265358979323846;
+
+// per element pair, with derived constants the kernels need
+struct PairP {
+  double r_s, r_p, r_pp;            // mixed bond radii (<= 0: component off)
+  double p_bo1, p_bo2, p_bo3, p_bo4, p_bo5, p_bo6;
+  double D_s, D_p, D_pp, p_be1, p_be2, p_ovun1;
+  double p_boc3, p_boc4, p_boc5;
+  double D_vdw, alpha, inv_r_vdw, gw_pow;  // gw_pow = gamma_w^(-p_vdW1)
+  double g3;                                // gamma^(-3)
+  double e_core, a_core, inv_r_core;
+  double reach2;                            // bond prefilter: raw BO' < bo_cut beyond it
+  double pad;
+};
+
+struct AtomP {
+  double val, val_e, val_boc, val_ang, mass, p_lp2, p_ovun2, p_ovun5, p_val3, p_val5;
+  double nlp_opt;
+  int32_t hbond;  // 0 none, 1 donor H, 2 acceptor
+  int32_t pad;
+};
+
+struct AngleP { double theta00_rad, p_val1, p_val2, p_val4, p_val7, p_pen1, p_coa1, pad; };
+struct TorsP { double V1, V2, V3, p_tor1, p_cot1, pad0, pad1, pad2; };
+struct HbP { double r0hb, p_hb1, p_hb2, p_hb3; };
+
+struct DevParams {
+  double p_boc1, p_boc2, p_coa2, p_coa3, p_coa4, p_ovun3, p_ovun4, p_ovun6, p_ovun7, p_ovun8,
+      p_val6, p_val8, p_val9, p_val10, p_pen2, p_pen3, p_pen4, p_tor2, p_tor3, p_tor4, p_cot2,
+      p_vdW1, p_lp1, inv_p_vdW1;
+  double r_nonb, r_bond, r_hb, bo_cut, thb_cut, thb_cutsq, hb_bo_cut;
+  double rn2, rh2, inv_r_nonb;
+  AtomP atom[NT];
+  PairP pair[NT * NT];
+  AngleP angle[NT * NT * NT];
+  TorsP tors[NT * NT * NT * NT];
+  HbP hb[NT * NT * NT];
+};
+
+// geometry of the cell grid (sorted layout)
+struct Grid {
+  int periodic;
+  int nc[3];        // cells per dimension
+  int span[3];      // distinct stencil offsets per dimension (5, or nc when nc < 5)
+  int full[3];      // 1: iterate every cell in this dimension
+  double lo[3];     // origin (0 for periodic)
+  double L[3], invL[3];
+  double invw[3];   // 1 / cell width
+};
+
+// --- lists and work arrays (device pointers, owned by the context) -------
+struct Lists {
+  int64_t n;
+  // sorted layout
+  int32_t* perm;        // sorted slot -> caller index
+  int32_t* type_s;      // sorted types
+  double4* xs;          // sorted positions (w unused)
+  int32_t* cell_start;  // [ncell + 1]
+  // far half list (j > i in sorted order)
+  int64_t* far_off;     // [n + 1]
+  int32_t* far_j;
+  // full bond list
+  int32_t* bond_off;    // [n + 1]
+  int32_t* bond_j;
+  int32_t* bond_mir;
+  // H list
+  int32_t* hb_off;      // [n + 1]
+  int32_t* hb_j;
+  int64_t nfar, nbond, nhb;
+};
+
+// per-atom state of the bond-order stage
+struct AtomState {
+  double S, Delta, Dang, Dlp;   // total bond order, deviations, lone-pair deficit
+  double dnlp;                  // d nlp / d S
+  double SBO2, dSBO2;           // SBO2 and dSBO2/dSBO
+  double prod, W, dW;           // prod_e exp(-BO^8), W = -Dang - p_val8 vlpadj, dW/dS
+  double pad[6];
+};
+
+struct Work {
+  // per directed bond entry
+  double4* bd;     // (dx, dy, dz, r): x_j - x_i
+  double4* bop;    // uncorrected (sigma shifted, pi, pipi, total)
+  double4* dbop;   // d/dr of sigma, pi, pipi
+  double4* bo;     // corrected (BO, BOpi, BOpipi, BOsigma)
+  double4* gbo;    // adjoints (BO, BOpi, BOpipi, S of the outer atom of an angle)
+  double4* gvec;   // vector adjoint dE/d(x_j - x_i)
+  double4* gup;    // adjoints of uncorrected (total, pi, pipi) and Delta' part of own atom
+  // per atom
+  double2* dp;     // (Delta', Delta'boc)
+  AtomState* ast;
+  double* gS;      // dE/dS (direct terms)
+  double* gSig;    // dE/dSigma_pi of the over/under term
+  double* gSBO;    // dE/dSBO
+  double* gStot;   // dE/dS including gathered cross-atom terms
+  double* gDp;     // dE/dDelta' (sum over own bonds)
+  double4* fnb;    // forces from nonbonded and hydrogen-bond Z terms (atomics)
+  double* q_s;     // sorted charges
+  unsigned long long* counters;  // [0] angles [1] torsions [2] hbonds
+};
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double sqr(double x) { return x * x; }
+
+// minimum-image displacement x_j - x_i, rounded exactly as the plain
+// definition spells it: d = xj - xi; d -= L * rint(d * invL)
+__device__ __forceinline__ double min_image(double d, double L, double invL) {
+#pragma clang fp contract(off)
+  const double s = L * rint(d * invL);
+  return d - s;
+}
+
+__device__ __forceinline__ double r2_of(double dx, double dy, double dz) {
+  return fma(dz, dz, fma(dy, dy, dx * dx));
+}
+
+// wave64 + block reduction of one double into *dst (one atomic per block)
+template <int BS>
+__device__ __forceinline__ void block_add(double v, double* dst) {
+  __shared__ double red[BS / 64];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int k = 0; k < BS / 64; ++k) s += red[k];
+    if (s != 0.0) atomicAdd(dst, s);
+  }
+}
+
+}  // namespace rx
