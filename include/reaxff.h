@@ -152,6 +152,17 @@ int reaxff_export_lists(reaxff_ctx* ctx, int32_t* far, int32_t* bonds, int32_t* 
  * [3] far pairs, [4] bonds (undirected).  Synchronises the device. */
 int reaxff_interaction_counts(reaxff_ctx* ctx, int64_t counts[5]);
 
+/* Optional per-kernel timing for measurement: when enabled, every kernel
+ * launch of the context is bracketed by two HIP events recorded on the
+ * launch's stream.  reaxff_profile() resets the accumulators and switches
+ * timing on (enable != 0) or off.  reaxff_profile_read() waits for the
+ * recorded events and writes, for up to `max` kernels, the accumulated
+ * milliseconds, launch counts and static kernel names (any output may be
+ * NULL); it returns the number of kernels reported. */
+int reaxff_profile(reaxff_ctx* ctx, int32_t enable);
+int reaxff_profile_read(reaxff_ctx* ctx, int32_t max, double* ms, int64_t* launches,
+                        const char** names);
+
 const char* reaxff_strerror(int code);
 const char* reaxff_last_error(const reaxff_ctx* ctx);
 

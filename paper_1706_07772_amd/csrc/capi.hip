@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -20,6 +21,7 @@ struct reaxff_ctx {
   Lists L{};
   Work W{};
   Scratch sc{};
+  Prof prof;
   bool built = false;
   double box[3] = {0, 0, 0};
   bool periodic = false;
@@ -167,10 +169,10 @@ int alloc_atoms(reaxff_ctx* c, int64_t n) {
   const int64_t need = n + 1;
   int64_t tmp;
 #define G(ptr) do { tmp = c->cap_n; if (grow(c, ptr, tmp, need)) return REAXFF_ERR_HIP; cap = tmp; } while (0)
-  G(c->L.perm); G(c->L.type_s); G(c->L.xs); G(c->L.far_off); G(c->L.bond_off); G(c->L.hb_off);
-  G(c->sc.cid); G(c->sc.cell_s); G(c->sc.cnt_far); G(c->sc.cnt_bond); G(c->sc.cnt_hb);
+  G(c->L.perm); G(c->L.type_s); G(c->L.xs); G(c->L.far_cnt); G(c->L.bond_off); G(c->L.hb_off);
+  G(c->sc.cid); G(c->sc.cell_s); G(c->sc.cnt_cand); G(c->sc.cnt_bond); G(c->sc.cnt_hb);
   G(c->W.dp); G(c->W.ast); G(c->W.gS); G(c->W.gSig); G(c->W.gSBO); G(c->W.gStot); G(c->W.gDp);
-  G(c->W.fnb); G(c->W.q_s);
+  G(c->W.fnb); G(c->W.xq);
 #undef G
   c->cap_n = cap;
   return 0;
@@ -232,6 +234,7 @@ int reaxff_create(const reaxff_params* params, const reaxff_cutoffs* cutoffs, in
       hipMemcpy(c->dp, &c->hd, sizeof(DevParams), hipMemcpyHostToDevice) != hipSuccess ||
       hipMalloc(&c->sc.flag, sizeof(int32_t) * 4) != hipSuccess ||
       hipMalloc(&c->sc.totals, sizeof(int64_t) * 4) != hipSuccess ||
+      hipMalloc(&c->sc.need, sizeof(int32_t) * 4) != hipSuccess ||
       hipHostMalloc(&c->sc.totals_host, sizeof(int64_t) * 4, hipHostMallocDefault) != hipSuccess ||
       hipMalloc(&c->W.counters, sizeof(unsigned long long) * 4) != hipSuccess) {
     reaxff_destroy(c);
@@ -245,12 +248,13 @@ void reaxff_destroy(reaxff_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
-  void* ptrs[] = {c->dp, c->L.perm, c->L.type_s, c->L.xs, c->L.cell_start, c->L.far_off,
+  void* ptrs[] = {c->dp, c->L.perm, c->L.type_s, c->L.xs, c->L.cell_start, c->L.far_cnt,
                   c->L.far_j, c->L.bond_off, c->L.bond_j, c->L.bond_mir, c->L.hb_off, c->L.hb_j,
                   c->W.bd, c->W.bop, c->W.dbop, c->W.bo, c->W.gbo, c->W.gvec, c->W.gup, c->W.dp,
                   c->W.ast, c->W.gS, c->W.gSig, c->W.gSBO, c->W.gStot, c->W.gDp, c->W.fnb,
-                  c->W.q_s, c->W.counters, c->sc.cid, c->sc.cell_s, c->sc.cell_count,
-                  c->sc.cell_cursor, c->sc.flag, c->sc.cnt_far, c->sc.cnt_bond, c->sc.cnt_hb,
+                  c->W.xq, c->W.counters, c->sc.cid, c->sc.cell_s, c->sc.cell_count,
+                  c->sc.cell_cursor, c->sc.flag, c->sc.cnt_cand, c->sc.cnt_bond, c->sc.cnt_hb,
+                  c->sc.cand_j, c->sc.bond_t, c->sc.hb_t, c->sc.need,
                   c->sc.part, c->sc.totals, c->sc.scan_tmp};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -281,7 +285,7 @@ int reaxff_build_lists(reaxff_ctx* c, int64_t n, const double* pos, const int32_
   double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
   if (n > 0) {
     HIPCHK(c, hipMemsetAsync(c->sc.flag, 0, sizeof(int32_t) * 4, st));
-    launch_bbox(pos, type, n, c->sc.part, nparts, c->sc.flag, st);
+    launch_bbox(pos, type, n, c->sc.part, nparts, c->sc.flag, c->prof, st);
     std::vector<double> part(6 * nparts);
     int32_t flag = 0;
     HIPCHK(c, hipMemcpyAsync(part.data(), c->sc.part, sizeof(double) * 6 * nparts,
@@ -310,40 +314,86 @@ int reaxff_build_lists(reaxff_ctx* c, int64_t n, const double* pos, const int32_
     c->cap_cell = t;
   }
   if (n > 0) {
-    if (launch_cell_sort(pos, type, n, c->grid, (int)ncell, c->sc, c->L, st))
+    if (launch_cell_sort(pos, type, n, c->grid, (int)ncell, c->sc, c->L, c->prof, st))
       return fail(c, REAXFF_ERR_HIP, "cell sort launch failed");
-    if (launch_count(c->dp, c->grid, n, c->sc, c->L, st))
-      return fail(c, REAXFF_ERR_HIP, "count launch failed");
   }
-  // offsets: counts with a trailing zero, exclusive scan, last element = total
-  HIPCHK(c, hipMemsetAsync(c->sc.cnt_far + n, 0, sizeof(int32_t), st));
-  HIPCHK(c, hipMemsetAsync(c->sc.cnt_bond + n, 0, sizeof(int32_t), st));
-  HIPCHK(c, hipMemsetAsync(c->sc.cnt_hb + n, 0, sizeof(int32_t), st));
-  if (scan_i32_to_i64(c->sc.cnt_far, c->L.far_off, n + 1, c->sc, st) ||
-      scan_i32(c->sc.cnt_bond, c->L.bond_off, n + 1, c->sc, st) ||
-      scan_i32(c->sc.cnt_hb, c->L.hb_off, n + 1, c->sc, st))
-    return fail(c, REAXFF_ERR_HIP, "scan failed");
-  // the one host synchronisation: list totals (and the type check flag)
+  // staging widths: first estimates from the density, grown on overflow
+  const int64_t nblock = (n + 63) / 64;
+  {
+    double vol = 1.0;
+    for (int k = 0; k < 3; ++k) vol *= c->periodic ? c->box[k] : std::max(hi[k] - lo[k], 1.0);
+    const double rho = n / vol;
+    auto est = [&](double r) {
+      const double m = rho * 4.18879 * r * r * r;
+      return (int32_t)std::min<double>((double)std::max<int64_t>(n, 1), 1.3 * m + 32.0);
+    };
+    if (c->L.far_w == 0) c->L.far_w = est(c->cut.r_nonb);
+    if (c->sc.hb_w == 0) c->sc.hb_w = est(c->cut.r_hb);
+    if (c->sc.cand_w == 0) c->sc.cand_w = 32;
+    if (c->sc.bond_w == 0) c->sc.bond_w = 16;
+  }
   int64_t* th = c->sc.totals_host;
-  HIPCHK(c, hipMemcpyAsync(&th[0], c->L.far_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-  int32_t t32[3] = {0, 0, 0};
-  HIPCHK(c, hipMemcpyAsync(&t32[0], c->L.bond_off + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  HIPCHK(c, hipMemcpyAsync(&t32[1], c->L.hb_off + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  HIPCHK(c, hipStreamSynchronize(st));
-  c->L.nfar = th[0];
+  int32_t need[4] = {0, 0, 0, 0};
+  int32_t t32[2] = {0, 0};
+  for (int attempt = 0;; ++attempt) {
+    const int64_t rows = std::max<int64_t>(nblock, 1) * 64;
+    {
+      int64_t t = c->cap_far;
+      if (grow(c, c->L.far_j, t, rows * c->L.far_w, 1.0)) return REAXFF_ERR_HIP;
+      c->cap_far = t;
+      t = c->sc.cap_cand;
+      if (grow(c, c->sc.cand_j, t, rows * c->sc.cand_w, 1.0)) return REAXFF_ERR_HIP;
+      c->sc.cap_cand = t;
+      t = c->sc.cap_bondt;
+      if (grow(c, c->sc.bond_t, t, rows * c->sc.bond_w, 1.0)) return REAXFF_ERR_HIP;
+      c->sc.cap_bondt = t;
+      t = c->sc.cap_hbt;
+      if (grow(c, c->sc.hb_t, t, rows * c->sc.hb_w, 1.0)) return REAXFF_ERR_HIP;
+      c->sc.cap_hbt = t;
+    }
+    if (n > 0 && launch_sweep(c->dp, c->grid, n, c->sc, c->L, c->prof, st))
+      return fail(c, REAXFF_ERR_HIP, "sweep launch failed");
+    if (n == 0) HIPCHK(c, hipMemsetAsync(c->sc.totals, 0, sizeof(int64_t) * 4, st));
+    // offsets: counts with a trailing zero, exclusive scan, last element = total
+    HIPCHK(c, hipMemsetAsync(c->sc.cnt_bond + n, 0, sizeof(int32_t), st));
+    HIPCHK(c, hipMemsetAsync(c->sc.cnt_hb + n, 0, sizeof(int32_t), st));
+    c->prof.begin(KID_SCAN, st);
+    const int src = scan_i32(c->sc.cnt_bond, c->L.bond_off, n + 1, c->sc, st) ||
+                    scan_i32(c->sc.cnt_hb, c->L.hb_off, n + 1, c->sc, st);
+    c->prof.end(st);
+    if (src) return fail(c, REAXFF_ERR_HIP, "scan failed");
+    // the one host synchronisation: list totals and overflow report
+    HIPCHK(c, hipMemcpyAsync(&th[0], c->sc.totals, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(&t32[0], c->L.bond_off + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(&t32[1], c->L.hb_off + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    if (n > 0)
+      HIPCHK(c, hipMemcpyAsync(need, c->sc.need, sizeof(need), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    bool again = false;
+    auto widen = [&](int32_t& w, int32_t nd) {
+      if (nd > w) {
+        w = (int32_t)(nd * 1.15) + 16;
+        again = true;
+      }
+    };
+    widen(c->L.far_w, need[0]);
+    widen(c->sc.cand_w, need[1]);
+    widen(c->sc.bond_w, need[2]);
+    widen(c->sc.hb_w, need[3]);
+    if (!again) break;
+    if (attempt >= 3) return fail(c, REAXFF_ERR_CAPACITY, "list widths did not converge");
+  }
+  c->L.nfar = th[0] / 2;
   c->L.nbond = t32[0];
   c->L.nhb = t32[1];
   {
-    int64_t t = c->cap_far;
-    if (grow(c, c->L.far_j, t, std::max<int64_t>(c->L.nfar, 1))) return REAXFF_ERR_HIP;
-    c->cap_far = t;
-    t = c->cap_hb;
+    int64_t t = c->cap_hb;
     if (grow(c, c->L.hb_j, t, std::max<int64_t>(c->L.nhb, 1))) return REAXFF_ERR_HIP;
     c->cap_hb = t;
     if (alloc_bonds(c, std::max<int64_t>(c->L.nbond, 1))) return REAXFF_ERR_HIP;
   }
-  if (n > 0 && launch_fill(c->dp, c->grid, n, c->sc, c->L, st))
-    return fail(c, REAXFF_ERR_HIP, "fill launch failed");
+  if (n > 0 && launch_compact(n, c->sc, c->L, c->prof, st))
+    return fail(c, REAXFF_ERR_HIP, "compact launch failed");
   c->built = true;
   return REAXFF_OK;
 }
@@ -361,7 +411,7 @@ int reaxff_compute_forces(reaxff_ctx* c, int64_t n, const double* pos, const int
     return fail(c, REAXFF_ERR_ARG, "null pointer");
   (void)pos; (void)type;   // the sorted copies made by the list build are used
   HIPCHK(c, hipSetDevice(c->device));
-  if (launch_forces(c->dp, c->grid, c->L, c->W, q, forces, energies, st))
+  if (launch_forces(c->dp, c->grid, c->L, c->W, q, forces, energies, c->prof, st))
     return fail(c, REAXFF_ERR_HIP, "force launch failed");
   return REAXFF_OK;
 }
@@ -409,7 +459,7 @@ int reaxff_export_lists(reaxff_ctx* c, int32_t* far, int32_t* bonds, int32_t* hb
   if (far && c->L.nfar) HIPCHK(c, hipMalloc(&df, sizeof(int32_t) * 2 * c->L.nfar));
   if (bonds && c->L.nbond) HIPCHK(c, hipMalloc(&db, sizeof(int32_t) * 2 * c->L.nbond));
   if (hb && c->L.nhb) HIPCHK(c, hipMalloc(&dh, sizeof(int32_t) * 2 * c->L.nhb));
-  launch_export(c->L, df, db, dh, 0);
+  if (launch_export(c->L, df, db, dh, c->sc, 0)) return fail(c, REAXFF_ERR_HIP, "export failed");
   HIPCHK(c, hipDeviceSynchronize());
   if (df) HIPCHK(c, hipMemcpy(far, df, sizeof(int32_t) * 2 * c->L.nfar, hipMemcpyDeviceToHost));
   if (db) HIPCHK(c, hipMemcpy(bonds, db, sizeof(int32_t) * 2 * c->L.nbond, hipMemcpyDeviceToHost));
@@ -418,6 +468,26 @@ int reaxff_export_lists(reaxff_ctx* c, int32_t* far, int32_t* bonds, int32_t* hb
   if (db) (void)hipFree(db);
   if (dh) (void)hipFree(dh);
   return REAXFF_OK;
+}
+
+int reaxff_profile(reaxff_ctx* c, int32_t enable) {
+  if (!c) return REAXFF_ERR_ARG;
+  c->prof.reset();
+  c->prof.on = enable != 0;
+  return REAXFF_OK;
+}
+
+int reaxff_profile_read(reaxff_ctx* c, int32_t max, double* ms, int64_t* launches,
+                        const char** names) {
+  if (!c) return REAXFF_ERR_ARG;
+  c->prof.collect();
+  const int k = std::min<int>(max, KID_COUNT);
+  for (int i = 0; i < k; ++i) {
+    if (ms) ms[i] = c->prof.ms[i];
+    if (launches) launches[i] = c->prof.calls[i];
+    if (names) names[i] = kKernelNames[i];
+  }
+  return k;
 }
 
 int reaxff_interaction_counts(reaxff_ctx* c, int64_t counts[5]) {

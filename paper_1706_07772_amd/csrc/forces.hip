@@ -14,8 +14,8 @@
 // Race freedom (the paper's Section 3.1 concern): a kernel with one thread
 // per atom writes only that atom's entries; cross-atom quantities are stored
 // per entry and gathered through the mirror index.  Only the torsion terms
-// (which touch entries of both central atoms), the nonbonded partner j and the
-// hydrogen-bond acceptor use atomic adds.
+// (which touch entries of both central atoms) and the hydrogen-bond acceptor
+// use atomic adds; the nonbonded pairs are evaluated from both sides instead.
 #include "internal.h"
 
 namespace rx {
@@ -634,21 +634,35 @@ __global__ __launch_bounds__(BS) void k_hbonds(const DevParams* __restrict__ P, 
 }
 
 // ---------------------------------------------------------------------------
-// (9) van der Waals and Coulomb over the half far list
+// (9) van der Waals and Coulomb.  Each lane owns one atom and walks its full
+//     neighbour list, so every pair is evaluated twice (once from each side)
+//     and no force is scattered: the redundant-computation choice that the
+//     paper cites as the better one for pairwise terms on massively parallel
+//     processors (Section 3.1).  Energies count each visit with weight 1/2.
 // ---------------------------------------------------------------------------
+struct NbP { double D, alpha, inv_rv, gw_pow, g3, e_core, a_core, inv_rc; };
+
 __global__ __launch_bounds__(BS) void k_nonbonded(const DevParams* __restrict__ P, Grid g, Lists L,
                                                   Work W, double* __restrict__ energies) {
+  __shared__ NbP sp[NT * NT];
+  if (threadIdx.x < NT * NT) {
+    const PairP& p = P->pair[threadIdx.x];
+    sp[threadIdx.x] = NbP{p.D_vdw, p.alpha, p.inv_r_vdw, p.gw_pow, p.g3, p.e_core, p.a_core, p.inv_r_core};
+  }
+  __syncthreads();
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   double evdw = 0.0, ecoul = 0.0;
   if (i < L.n) {
-    const double4 xi = L.xs[i];
+    const double4 xi = W.xq[i];
     const int ti = L.type_s[i];
-    const double qi = W.q_s[i] * C_ELE;
+    const double qi = xi.w * C_ELE;
     const double iR = P->inv_r_nonb, pv = P->p_vdW1, ipv = P->inv_p_vdW1;
     double fx = 0.0, fy = 0.0, fz = 0.0;
-    for (int64_t s = L.far_off[i]; s < L.far_off[i + 1]; ++s) {
-      const int j = L.far_j[s];
-      const double4 xj = L.xs[j];
+    const int cnt = L.far_cnt[i];
+    const int32_t* __restrict__ lj = L.far_j + blk_index(i, 0, L.far_w);
+    for (int k = 0; k < cnt; ++k) {
+      const int j = lj[(int64_t)k * 64];
+      const double4 xj = W.xq[j];
       double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
       if (g.periodic) {
         dx = min_image(dx, g.L[0], g.invL[0]);
@@ -657,7 +671,7 @@ __global__ __launch_bounds__(BS) void k_nonbonded(const DevParams* __restrict__ 
       }
       const double r2 = dx * dx + dy * dy + dz * dz;
       const double r = sqrt(r2);
-      const PairP& p = P->pair[ti * NT + L.type_s[j]];
+      const NbP p = sp[ti * NT + L.type_s[j]];
       // taper
       const double u = r * iR, u2 = u * u, u3 = u2 * u, u4 = u2 * u2;
       const double tap = 20.0 * u4 * u3 - 70.0 * u4 * u2 + 84.0 * u4 * u - 35.0 * u4 + 1.0;
@@ -667,17 +681,17 @@ __global__ __launch_bounds__(BS) void k_nonbonded(const DevParams* __restrict__ 
       const double sum = pw + p.gw_pow;
       const double f13 = exp(ipv * log(sum));
       const double df13 = f13 / sum * pw / r;
-      const double t = 1.0 - f13 * p.inv_r_vdw;
+      const double t = 1.0 - f13 * p.inv_rv;
       const double e2 = exp(0.5 * p.alpha * t);
       const double e1 = e2 * e2;
-      const double ev = p.D_vdw * (e1 - 2.0 * e2);
-      const double dev = -p.D_vdw * p.alpha * p.inv_r_vdw * (e1 - e2) * df13;
-      const double ecr = p.e_core * exp(p.a_core * (1.0 - r * p.inv_r_core));
-      const double decr = -ecr * p.a_core * p.inv_r_core;
+      const double ev = p.D * (e1 - 2.0 * e2);
+      const double dev = -p.D * p.alpha * p.inv_rv * (e1 - e2) * df13;
+      const double ecr = p.e_core * exp(p.a_core * (1.0 - r * p.inv_rc));
+      const double decr = -ecr * p.a_core * p.inv_rc;
       // shielded Coulomb
       const double s3 = r2 * r + p.g3;
       const double den = cbrt(s3);
-      const double eq = qi * W.q_s[j] / den;
+      const double eq = qi * xj.w / den;
       const double deq = -eq * r2 / s3;
       const double Ev = ev + ecr;
       evdw += tap * Ev;
@@ -687,12 +701,11 @@ __global__ __launch_bounds__(BS) void k_nonbonded(const DevParams* __restrict__ 
       fx += f * dx;
       fy += f * dy;
       fz += f * dz;
-      atomic_add3(&W.fnb[j], -f * dx, -f * dy, -f * dz);
     }
-    atomic_add3(&W.fnb[i], fx, fy, fz);
+    W.fnb[i] = make_double4(fx, fy, fz, 0.0);
   }
-  block_add<BS>(evdw, energies + E_VDW);
-  block_add<BS>(ecoul, energies + E_COUL);
+  block_add<BS>(0.5 * evdw, energies + E_VDW);
+  block_add<BS>(0.5 * ecoul, energies + E_COUL);
 }
 
 // ---------------------------------------------------------------------------
@@ -794,41 +807,58 @@ __global__ __launch_bounds__(BS) void k_forces(Lists L, Work W, double* __restri
   forces[3 * (int64_t)o + 2] = fz;
 }
 
-__global__ void k_gather_q(const double* __restrict__ q, const int32_t* __restrict__ perm, int64_t n,
-                           double* __restrict__ q_s) {
+__global__ void k_gather_q(const double* __restrict__ q, const int32_t* __restrict__ perm,
+                           const double4* __restrict__ xs, int64_t n, double4* __restrict__ xq) {
   const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (s < n) q_s[s] = q[perm[s]];
+  if (s < n) {
+    const double4 x = xs[s];
+    xq[s] = make_double4(x.x, x.y, x.z, q[perm[s]]);
+  }
 }
 
+const char* const kKernelNames[KID_COUNT] = {
+    "bbox", "cell_hist", "cell_scatter", "cell_sort", "gather_sorted", "list_sweep", "scan",
+    "compact", "mirror", "zero", "gather_q", "bo_prime", "delta_prime", "bo_corr", "atom_state",
+    "atom_energy", "angles", "torsions", "hbonds", "nonbonded", "back_s", "back_corr", "back_dp",
+    "forces"};
+
 int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, const double* q,
-                  double* forces, double* energies, hipStream_t st) {
+                  double* forces, double* energies, Prof& pf, hipStream_t st) {
   const int64_t n = L.n, nb = L.nbond;
-  hipMemsetAsync(energies, 0, sizeof(double) * NTERMS, st);
-  hipMemsetAsync(W.counters, 0, sizeof(unsigned long long) * 4, st);
+  pf.begin(KID_ZERO, st);
+  (void)hipMemsetAsync(energies, 0, sizeof(double) * NTERMS, st);
+  (void)hipMemsetAsync(W.counters, 0, sizeof(unsigned long long) * 4, st);
   if (nb > 0) {
-    hipMemsetAsync(W.gbo, 0, sizeof(double4) * nb, st);
-    hipMemsetAsync(W.gvec, 0, sizeof(double4) * nb, st);
+    (void)hipMemsetAsync(W.gbo, 0, sizeof(double4) * nb, st);
+    (void)hipMemsetAsync(W.gvec, 0, sizeof(double4) * nb, st);
   }
-  if (n > 0) {
-    hipMemsetAsync(W.fnb, 0, sizeof(double4) * n, st);
-    hipMemsetAsync(W.gSBO, 0, sizeof(double) * n, st);
-  }
+  if (n > 0) (void)hipMemsetAsync(W.gSBO, 0, sizeof(double) * n, st);
+  pf.end(st);
   if (n == 0) return hipGetLastError() == hipSuccess ? 0 : -1;
   const dim3 grid(nblk(n, BS)), blk(BS);
-  hipLaunchKernelGGL(k_gather_q, grid, blk, 0, st, q, L.perm, n, W.q_s);
-  hipLaunchKernelGGL(k_bo_prime, grid, blk, 0, st, P, g, L, W);
-  hipLaunchKernelGGL(k_delta_prime, grid, blk, 0, st, P, L, W);
-  hipLaunchKernelGGL(k_bo_corr, grid, blk, 0, st, P, L, W);
-  hipLaunchKernelGGL(k_atom_state, grid, blk, 0, st, P, L, W);
-  hipLaunchKernelGGL(k_atom_energy, grid, blk, 0, st, P, L, W, energies);
-  hipLaunchKernelGGL(k_angles, grid, blk, 0, st, P, L, W, energies);
-  hipLaunchKernelGGL(k_torsions, grid, blk, 0, st, P, L, W, energies);
-  hipLaunchKernelGGL(k_hbonds, grid, blk, 0, st, P, g, L, W, energies);
-  hipLaunchKernelGGL(k_nonbonded, grid, blk, 0, st, P, g, L, W, energies);
-  hipLaunchKernelGGL(k_back_s, grid, blk, 0, st, L, W);
-  hipLaunchKernelGGL(k_back_corr, grid, blk, 0, st, P, L, W);
-  hipLaunchKernelGGL(k_back_dp, grid, blk, 0, st, L, W);
-  hipLaunchKernelGGL(k_forces, grid, blk, 0, st, L, W, forces);
+#define LAUNCH(id, ...)                                  \
+  do {                                                   \
+    pf.begin(id, st);                                    \
+    hipLaunchKernelGGL(__VA_ARGS__);                     \
+    pf.end(st);                                          \
+  } while (0)
+  LAUNCH(KID_GATHER_Q, k_gather_q, grid, blk, 0, st, q, L.perm, L.xs, n, W.xq);
+  // nonbonded first: it initialises the per-atom force accumulator that the
+  // hydrogen-bond kernel adds to
+  LAUNCH(KID_NONBONDED, k_nonbonded, grid, blk, 0, st, P, g, L, W, energies);
+  LAUNCH(KID_BO_PRIME, k_bo_prime, grid, blk, 0, st, P, g, L, W);
+  LAUNCH(KID_DELTA_PRIME, k_delta_prime, grid, blk, 0, st, P, L, W);
+  LAUNCH(KID_BO_CORR, k_bo_corr, grid, blk, 0, st, P, L, W);
+  LAUNCH(KID_ATOM_STATE, k_atom_state, grid, blk, 0, st, P, L, W);
+  LAUNCH(KID_ATOM_ENERGY, k_atom_energy, grid, blk, 0, st, P, L, W, energies);
+  LAUNCH(KID_ANGLES, k_angles, grid, blk, 0, st, P, L, W, energies);
+  LAUNCH(KID_TORSIONS, k_torsions, grid, blk, 0, st, P, L, W, energies);
+  LAUNCH(KID_HBONDS, k_hbonds, grid, blk, 0, st, P, g, L, W, energies);
+  LAUNCH(KID_BACK_S, k_back_s, grid, blk, 0, st, L, W);
+  LAUNCH(KID_BACK_CORR, k_back_corr, grid, blk, 0, st, P, L, W);
+  LAUNCH(KID_BACK_DP, k_back_dp, grid, blk, 0, st, L, W);
+  LAUNCH(KID_FORCES, k_forces, grid, blk, 0, st, L, W, forces);
+#undef LAUNCH
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -877,7 +907,7 @@ int launch_drift(int64_t n, double* pos, const double* vel, double dt, const Gri
 }
 int launch_kinetic(int64_t n, const double* vel, const int32_t* type, const DevParams* P, double* out,
                    hipStream_t st) {
-  hipMemsetAsync(out, 0, sizeof(double), st);
+  (void)hipMemsetAsync(out, 0, sizeof(double), st);
   if (n > 0) hipLaunchKernelGGL(k_kinetic, dim3(nblk(n, BS)), dim3(BS), 0, st, n, vel, type, P, out);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

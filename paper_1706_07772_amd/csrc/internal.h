@@ -1,9 +1,66 @@
 // Host-side internals shared by the library's translation units.
 #pragma once
 
+#include <vector>
+
 #include "reaxff_dev.h"
 
 namespace rx {
+
+// kernels timed by the optional event profiler (reaxff_profile)
+enum KernelId {
+  KID_BBOX, KID_CELL_HIST, KID_CELL_SCATTER, KID_CELL_SORT, KID_GATHER, KID_LIST_SWEEP, KID_SCAN,
+  KID_COMPACT, KID_MIRROR, KID_ZERO, KID_GATHER_Q, KID_BO_PRIME, KID_DELTA_PRIME, KID_BO_CORR,
+  KID_ATOM_STATE, KID_ATOM_ENERGY, KID_ANGLES, KID_TORSIONS, KID_HBONDS, KID_NONBONDED,
+  KID_BACK_S, KID_BACK_CORR, KID_BACK_DP, KID_FORCES, KID_COUNT
+};
+extern const char* const kKernelNames[KID_COUNT];
+
+// pairs of HIP events recorded around kernel launches on the launch stream
+struct Prof {
+  bool on = false;
+  struct Pending { int id; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  double ms[KID_COUNT] = {};
+  int64_t calls[KID_COUNT] = {};
+  hipEvent_t get() {
+    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+    hipEvent_t e;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  void begin(int id, hipStream_t st) {
+    if (!on) return;
+    Pending p{id, get(), get()};
+    (void)hipEventRecord(p.a, st);
+    pending.push_back(p);
+  }
+  void end(hipStream_t st) {
+    if (!on || pending.empty()) return;
+    (void)hipEventRecord(pending.back().b, st);
+  }
+  void collect() {
+    for (auto& p : pending) {
+      (void)hipEventSynchronize(p.b);
+      float t = 0.f;
+      (void)hipEventElapsedTime(&t, p.a, p.b);
+      ms[p.id] += t;
+      calls[p.id] += 1;
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pending.clear();
+  }
+  void reset() {
+    collect();
+    for (int k = 0; k < KID_COUNT; ++k) { ms[k] = 0; calls[k] = 0; }
+  }
+  ~Prof() {
+    for (auto& p : pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
 
 // scratch owned by the context (device pointers)
 struct Scratch {
@@ -12,9 +69,16 @@ struct Scratch {
   int32_t* cell_count = nullptr;  // [ncell + 1]
   int32_t* cell_cursor = nullptr; // [ncell + 1]
   int32_t* flag = nullptr;        // error flags written by kernels
-  int32_t* cnt_far = nullptr;     // [n + 1]
   int32_t* cnt_bond = nullptr;    // [n + 1]
   int32_t* cnt_hb = nullptr;      // [n + 1]
+  int32_t* cnt_cand = nullptr;    // [n] bond candidates
+  // fixed-width wave-blocked staging of the sweep (see blk_index)
+  int32_t* cand_j = nullptr;      // bond candidates, width cand_w
+  int32_t* bond_t = nullptr;      // bonds, width bond_w
+  int32_t* hb_t = nullptr;        // H-list entries, width hb_w
+  int32_t cand_w = 0, bond_w = 0, hb_w = 0;
+  int64_t cap_cand = 0, cap_bondt = 0, cap_hbt = 0;
+  int32_t* need = nullptr;        // device [4]: largest counts seen (far, cand, bond, hb)
   double* part = nullptr;         // bbox partials
   int64_t* totals = nullptr;      // device [4]
   int64_t* totals_host = nullptr; // pinned host [4]
@@ -28,15 +92,17 @@ int scan_i32(const int32_t* in, int32_t* out, int64_t n, Scratch& sc, hipStream_
 int scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, Scratch& sc, hipStream_t st);
 
 int launch_bbox(const double* pos, const int32_t* type, int64_t n, double* part, int nparts,
-                int32_t* flag, hipStream_t st);
+                int32_t* flag, Prof& pf, hipStream_t st);
 int launch_cell_sort(const double* pos, const int32_t* type, int64_t n, const Grid& g, int ncell,
-                     Scratch& sc, Lists& L, hipStream_t st);
-int launch_count(const DevParams* P, const Grid& g, int64_t n, Scratch& sc, Lists& L, hipStream_t st);
-int launch_fill(const DevParams* P, const Grid& g, int64_t n, Scratch& sc, Lists& L, hipStream_t st);
-int launch_export(const Lists& L, int32_t* far, int32_t* bonds, int32_t* hb, hipStream_t st);
+                     Scratch& sc, Lists& L, Prof& pf, hipStream_t st);
+int launch_sweep(const DevParams* P, const Grid& g, int64_t n, Scratch& sc, Lists& L, Prof& pf,
+                 hipStream_t st);
+int launch_compact(int64_t n, Scratch& sc, Lists& L, Prof& pf, hipStream_t st);
+int launch_export(const Lists& L, int32_t* far, int32_t* bonds, int32_t* hb, Scratch& sc,
+                  hipStream_t st);
 
 int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, const double* q,
-                  double* forces, double* energies, hipStream_t st);
+                  double* forces, double* energies, Prof& pf, hipStream_t st);
 int launch_kick(int64_t n, double* vel, const double* forces, const int32_t* type,
                 const DevParams* P, double half_dt, hipStream_t st);
 int launch_drift(int64_t n, double* pos, const double* vel, double dt, const Grid& g, hipStream_t st);

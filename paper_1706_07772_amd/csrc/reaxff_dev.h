@@ -75,11 +75,15 @@ struct Lists {
   // sorted layout
   int32_t* perm;        // sorted slot -> caller index
   int32_t* type_s;      // sorted types
-  double4* xs;          // sorted positions (w unused)
+  double4* xs;          // sorted positions, w = type (as a double)
   int32_t* cell_start;  // [ncell + 1]
-  // far half list (j > i in sorted order)
-  int64_t* far_off;     // [n + 1]
+  // far-neighbour list, full (both directions of every pair), wave-blocked
+  // with a fixed width far_w: entry k of atom i is stored at
+  // far_j[(i / 64) * 64 * far_w + 64 k + i % 64], so a wavefront reading its
+  // atoms' k-th entries touches one contiguous 256-byte segment
+  int32_t* far_cnt;     // [n]
   int32_t* far_j;
+  int32_t far_w;
   // full bond list
   int32_t* bond_off;    // [n + 1]
   int32_t* bond_j;
@@ -87,8 +91,13 @@ struct Lists {
   // H list
   int32_t* hb_off;      // [n + 1]
   int32_t* hb_j;
-  int64_t nfar, nbond, nhb;
+  int64_t nfar;         // unordered pairs (half the entries)
+  int64_t nbond, nhb;
 };
+
+__device__ __forceinline__ int64_t blk_index(int64_t i, int64_t k, int w) {
+  return (i >> 6) * 64 * (int64_t)w + 64 * k + (i & 63);
+}
 
 // per-atom state of the bond-order stage
 struct AtomState {
@@ -117,7 +126,7 @@ struct Work {
   double* gStot;   // dE/dS including gathered cross-atom terms
   double* gDp;     // dE/dDelta' (sum over own bonds)
   double4* fnb;    // forces from nonbonded and hydrogen-bond Z terms (atomics)
-  double* q_s;     // sorted charges
+  double4* xq;     // sorted positions with charge in w
   unsigned long long* counters;  // [0] angles [1] torsions [2] hbonds
 };
 
