@@ -169,10 +169,11 @@ int alloc_atoms(reaxff_ctx* c, int64_t n) {
   const int64_t need = n + 1;
   int64_t tmp;
 #define G(ptr) do { tmp = c->cap_n; if (grow(c, ptr, tmp, need)) return REAXFF_ERR_HIP; cap = tmp; } while (0)
-  G(c->L.perm); G(c->L.type_s); G(c->L.xs); G(c->L.far_cnt); G(c->L.bond_off); G(c->L.hb_off);
-  G(c->sc.cid); G(c->sc.cell_s); G(c->sc.cnt_cand); G(c->sc.cnt_bond); G(c->sc.cnt_hb);
+  G(c->L.perm); G(c->L.type_s); G(c->L.xs); G(c->L.far_cnt); G(c->L.bond_off); G(c->L.hb_cnt);
+  G(c->sc.cid); G(c->sc.cell_s); G(c->sc.cnt_cand); G(c->sc.cnt_bond);
   G(c->W.dp); G(c->W.ast); G(c->W.gS); G(c->W.gSig); G(c->W.gSBO); G(c->W.gStot); G(c->W.gDp);
-  G(c->W.fnb); G(c->W.xq);
+  G(c->W.fnb); G(c->W.xq); G(c->W.cnt_ang); G(c->W.cnt_tor); G(c->W.cnt_don); G(c->W.off_ang);
+  G(c->W.off_tor); G(c->W.off_don);
 #undef G
   c->cap_n = cap;
   return 0;
@@ -182,7 +183,7 @@ int alloc_bonds(reaxff_ctx* c, int64_t nb) {
   if (nb <= c->cap_bond && c->L.bond_j) return 0;
   int64_t cap = 0, tmp;
 #define G(ptr) do { tmp = c->cap_bond; if (grow(c, ptr, tmp, nb)) return REAXFF_ERR_HIP; cap = tmp; } while (0)
-  G(c->L.bond_j); G(c->L.bond_mir); G(c->W.bd); G(c->W.bop); G(c->W.dbop); G(c->W.bo);
+  G(c->L.bond_j); G(c->L.bond_i); G(c->L.bond_mir); G(c->W.bd); G(c->W.bop); G(c->W.dbop); G(c->W.bo);
   G(c->W.gbo); G(c->W.gvec); G(c->W.gup);
 #undef G
   c->cap_bond = cap;
@@ -233,9 +234,9 @@ int reaxff_create(const reaxff_params* params, const reaxff_cutoffs* cutoffs, in
   if (hipMalloc(&c->dp, sizeof(DevParams)) != hipSuccess ||
       hipMemcpy(c->dp, &c->hd, sizeof(DevParams), hipMemcpyHostToDevice) != hipSuccess ||
       hipMalloc(&c->sc.flag, sizeof(int32_t) * 4) != hipSuccess ||
-      hipMalloc(&c->sc.totals, sizeof(int64_t) * 4) != hipSuccess ||
+      hipMalloc(&c->sc.totals, sizeof(int64_t) * 8) != hipSuccess ||
       hipMalloc(&c->sc.need, sizeof(int32_t) * 4) != hipSuccess ||
-      hipHostMalloc(&c->sc.totals_host, sizeof(int64_t) * 4, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(&c->sc.totals_host, sizeof(int64_t) * 8, hipHostMallocDefault) != hipSuccess ||
       hipMalloc(&c->W.counters, sizeof(unsigned long long) * 4) != hipSuccess) {
     reaxff_destroy(c);
     return REAXFF_ERR_HIP;
@@ -249,12 +250,14 @@ void reaxff_destroy(reaxff_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   void* ptrs[] = {c->dp, c->L.perm, c->L.type_s, c->L.xs, c->L.cell_start, c->L.far_cnt,
-                  c->L.far_j, c->L.bond_off, c->L.bond_j, c->L.bond_mir, c->L.hb_off, c->L.hb_j,
+                  c->L.far_j, c->L.bond_off, c->L.bond_j, c->L.bond_mir, c->L.hb_cnt, c->L.hb_j,
                   c->W.bd, c->W.bop, c->W.dbop, c->W.bo, c->W.gbo, c->W.gvec, c->W.gup, c->W.dp,
                   c->W.ast, c->W.gS, c->W.gSig, c->W.gSBO, c->W.gStot, c->W.gDp, c->W.fnb,
-                  c->W.xq, c->W.counters, c->sc.cid, c->sc.cell_s, c->sc.cell_count,
-                  c->sc.cell_cursor, c->sc.flag, c->sc.cnt_cand, c->sc.cnt_bond, c->sc.cnt_hb,
-                  c->sc.cand_j, c->sc.bond_t, c->sc.hb_t, c->sc.need,
+                  c->W.xq, c->W.counters, c->W.cnt_ang, c->W.cnt_tor, c->W.cnt_don,
+                  c->W.off_ang, c->W.off_tor, c->W.off_don, c->W.ang, c->W.tor, c->W.don,
+                  c->L.bond_i, c->sc.cid, c->sc.cell_s, c->sc.cell_count,
+                  c->sc.cell_cursor, c->sc.flag, c->sc.cnt_cand, c->sc.cnt_bond,
+                  c->sc.cand_j, c->sc.bond_t, c->sc.need,
                   c->sc.part, c->sc.totals, c->sc.scan_tmp};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -304,6 +307,13 @@ int reaxff_build_lists(reaxff_ctx* c, int64_t n, const double* pos, const int32_
         return fail(c, REAXFF_ERR_NONFINITE, "non-finite position");
   }
   make_grid(c->grid, c->periodic, c->box, lo, hi, c->cut.r_nonb);
+  c->grid.shift_ok = 0;
+  if (c->periodic && n > 0) {
+    bool ok = true;
+    for (int k = 0; k < 3; ++k)
+      ok = ok && lo[k] >= 0.0 && hi[k] < c->box[k] && c->grid.nc[k] >= 7;
+    c->grid.shift_ok = ok ? 1 : 0;
+  }
   const int64_t ncell = (int64_t)c->grid.nc[0] * c->grid.nc[1] * c->grid.nc[2];
   if (ncell > (int64_t)INT32_MAX / 4) return fail(c, REAXFF_ERR_ARG, "cell grid too large");
   {
@@ -328,7 +338,7 @@ int reaxff_build_lists(reaxff_ctx* c, int64_t n, const double* pos, const int32_
       return (int32_t)std::min<double>((double)std::max<int64_t>(n, 1), 1.3 * m + 32.0);
     };
     if (c->L.far_w == 0) c->L.far_w = est(c->cut.r_nonb);
-    if (c->sc.hb_w == 0) c->sc.hb_w = est(c->cut.r_hb);
+    if (c->L.hb_w == 0) c->L.hb_w = est(c->cut.r_hb);
     if (c->sc.cand_w == 0) c->sc.cand_w = 32;
     if (c->sc.bond_w == 0) c->sc.bond_w = 16;
   }
@@ -336,7 +346,7 @@ int reaxff_build_lists(reaxff_ctx* c, int64_t n, const double* pos, const int32_
   int32_t need[4] = {0, 0, 0, 0};
   int32_t t32[2] = {0, 0};
   for (int attempt = 0;; ++attempt) {
-    const int64_t rows = std::max<int64_t>(nblock, 1) * 64;
+    const int64_t rows = std::max<int64_t>(n, 1);
     {
       int64_t t = c->cap_far;
       if (grow(c, c->L.far_j, t, rows * c->L.far_w, 1.0)) return REAXFF_ERR_HIP;
@@ -347,25 +357,22 @@ int reaxff_build_lists(reaxff_ctx* c, int64_t n, const double* pos, const int32_
       t = c->sc.cap_bondt;
       if (grow(c, c->sc.bond_t, t, rows * c->sc.bond_w, 1.0)) return REAXFF_ERR_HIP;
       c->sc.cap_bondt = t;
-      t = c->sc.cap_hbt;
-      if (grow(c, c->sc.hb_t, t, rows * c->sc.hb_w, 1.0)) return REAXFF_ERR_HIP;
-      c->sc.cap_hbt = t;
+      t = c->cap_hb;
+      if (grow(c, c->L.hb_j, t, rows * c->L.hb_w, 1.0)) return REAXFF_ERR_HIP;
+      c->cap_hb = t;
     }
-    if (n > 0 && launch_sweep(c->dp, c->grid, n, c->sc, c->L, c->prof, st))
+    if (n > 0 && launch_sweep(c->dp, c->grid, n, (int)ncell, c->sc, c->L, c->prof, st))
       return fail(c, REAXFF_ERR_HIP, "sweep launch failed");
-    if (n == 0) HIPCHK(c, hipMemsetAsync(c->sc.totals, 0, sizeof(int64_t) * 4, st));
-    // offsets: counts with a trailing zero, exclusive scan, last element = total
+    if (n == 0) HIPCHK(c, hipMemsetAsync(c->sc.totals, 0, sizeof(int64_t) * 8, st));
+    // bond offsets: counts with a trailing zero, exclusive scan, last element = total
     HIPCHK(c, hipMemsetAsync(c->sc.cnt_bond + n, 0, sizeof(int32_t), st));
-    HIPCHK(c, hipMemsetAsync(c->sc.cnt_hb + n, 0, sizeof(int32_t), st));
     c->prof.begin(KID_SCAN, st);
-    const int src = scan_i32(c->sc.cnt_bond, c->L.bond_off, n + 1, c->sc, st) ||
-                    scan_i32(c->sc.cnt_hb, c->L.hb_off, n + 1, c->sc, st);
+    const int src = scan_i32(c->sc.cnt_bond, c->L.bond_off, n + 1, c->sc, st);
     c->prof.end(st);
     if (src) return fail(c, REAXFF_ERR_HIP, "scan failed");
     // the one host synchronisation: list totals and overflow report
-    HIPCHK(c, hipMemcpyAsync(&th[0], c->sc.totals, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(th, c->sc.totals, sizeof(int64_t) * 8, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipMemcpyAsync(&t32[0], c->L.bond_off + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipMemcpyAsync(&t32[1], c->L.hb_off + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     if (n > 0)
       HIPCHK(c, hipMemcpyAsync(need, c->sc.need, sizeof(need), hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
@@ -379,19 +386,28 @@ int reaxff_build_lists(reaxff_ctx* c, int64_t n, const double* pos, const int32_
     widen(c->L.far_w, need[0]);
     widen(c->sc.cand_w, need[1]);
     widen(c->sc.bond_w, need[2]);
-    widen(c->sc.hb_w, need[3]);
+    widen(c->L.hb_w, need[3]);
     if (!again) break;
     if (attempt >= 3) return fail(c, REAXFF_ERR_CAPACITY, "list widths did not converge");
   }
   c->L.nfar = th[0] / 2;
   c->L.nbond = t32[0];
-  c->L.nhb = t32[1];
+  c->L.nhb = th[4];
+  c->L.bound_ang = th[1];
+  c->L.bound_tor = th[2];
+  c->L.bound_don = th[3];
   {
-    int64_t t = c->cap_hb;
-    if (grow(c, c->L.hb_j, t, std::max<int64_t>(c->L.nhb, 1))) return REAXFF_ERR_HIP;
-    c->cap_hb = t;
-    if (alloc_bonds(c, std::max<int64_t>(c->L.nbond, 1))) return REAXFF_ERR_HIP;
+    int64_t t = c->W.cap_ang;
+    if (grow(c, c->W.ang, t, std::max<int64_t>(c->L.bound_ang, 1))) return REAXFF_ERR_HIP;
+    c->W.cap_ang = t;
+    t = c->W.cap_tor;
+    if (grow(c, c->W.tor, t, std::max<int64_t>(c->L.bound_tor, 1))) return REAXFF_ERR_HIP;
+    c->W.cap_tor = t;
+    t = c->W.cap_don;
+    if (grow(c, c->W.don, t, std::max<int64_t>(c->L.bound_don, 1))) return REAXFF_ERR_HIP;
+    c->W.cap_don = t;
   }
+  if (alloc_bonds(c, std::max<int64_t>(c->L.nbond, 1))) return REAXFF_ERR_HIP;
   if (n > 0 && launch_compact(n, c->sc, c->L, c->prof, st))
     return fail(c, REAXFF_ERR_HIP, "compact launch failed");
   c->built = true;
@@ -411,7 +427,7 @@ int reaxff_compute_forces(reaxff_ctx* c, int64_t n, const double* pos, const int
     return fail(c, REAXFF_ERR_ARG, "null pointer");
   (void)pos; (void)type;   // the sorted copies made by the list build are used
   HIPCHK(c, hipSetDevice(c->device));
-  if (launch_forces(c->dp, c->grid, c->L, c->W, q, forces, energies, c->prof, st))
+  if (launch_forces(c->dp, c->grid, c->L, c->W, q, forces, energies, c->sc, c->prof, st))
     return fail(c, REAXFF_ERR_HIP, "force launch failed");
   return REAXFF_OK;
 }

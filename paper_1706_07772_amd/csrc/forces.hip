@@ -190,7 +190,80 @@ __global__ __launch_bounds__(BS) void k_atom_state(const DevParams* __restrict__
   } else {
     st.SBO2 = 2.0; st.dSBO2 = 0.0;
   }
+  // centre factors of the valence-angle family
+  const double ex10 = exp(-P->p_val10 * (2.0 - st.SBO2));
+  st.th0f = 1.0 - ex10;
+  st.dth0f = -ex10 * P->p_val10;                 // d th0f / d SBO2
+  st.e6 = exp(P->p_val6 * st.Dang);
+  const double ep3 = exp(-P->p_pen3 * st.Delta), ep4 = exp(P->p_pen4 * st.Delta);
+  const double f9d = 1.0 + ep3 + ep4;
+  st.f9 = (2.0 + ep3) / f9d;
+  st.df9 = (-P->p_pen3 * ep3 * f9d - (2.0 + ep3) * (-P->p_pen3 * ep3 + P->p_pen4 * ep4)) / (f9d * f9d);
+  const double ec = exp(P->p_coa2 * st.Dang);
+  st.fc = 1.0 / (1.0 + ec);
+  st.dfc = -P->p_coa2 * ec * st.fc * st.fc;
   W.ast[i] = st;
+}
+
+// ---------------------------------------------------------------------------
+// interaction task lists, built as the paper builds its 3-body list
+// (Section 3.3): count the interactions each atom owns, prefix-sum the
+// counts, then store each interaction at its owner's offset.  Owners: the
+// centre atom of a valence angle; the lower-index atom of a torsion's central
+// bond; the H atom of a donor bond H-X.
+// ---------------------------------------------------------------------------
+template <bool FILL>
+__global__ __launch_bounds__(BS) void k_tasks(const DevParams* __restrict__ P, Lists L, Work W) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= L.n) return;
+  const double thb = P->thb_cut, thb2 = P->thb_cutsq;
+  const int e0 = L.bond_off[j], e1 = L.bond_off[j + 1];
+  int na = 0, nt = 0, nd = 0;
+  int oa = FILL ? W.off_ang[j] : 0, ot = FILL ? W.off_tor[j] : 0, od = FILL ? W.off_don[j] : 0;
+  const bool hyd = P->atom[L.type_s[j]].hbond == 1;
+  for (int u = e0; u < e1; ++u) {
+    const double bu = W.bo[u].x;
+    // angles (u, v), u < v
+    if (bu - thb > 0.0) {
+      for (int v = u + 1; v < e1; ++v) {
+        const double bv = W.bo[v].x;
+        if (bv - thb > 0.0 && bu * bv > thb2) {
+          if (FILL) W.ang[oa + na] = make_int2(u, v);
+          ++na;
+        }
+      }
+    }
+    // torsions about the central bond u = j->k, k > j
+    const int k = L.bond_j[u];
+    if (k > (int)j && bu > thb) {
+      const int f0 = L.bond_off[k], f1 = L.bond_off[k + 1];
+      for (int a = e0; a < e1; ++a) {
+        if (a == u) continue;
+        const double ba = W.bo[a].x;
+        if (!(ba > thb)) continue;
+        const int i = L.bond_j[a];
+        for (int b = f0; b < f1; ++b) {
+          const int l = L.bond_j[b];
+          if (l == (int)j || l == i) continue;
+          const double bb = W.bo[b].x;
+          if (!(bb > thb)) continue;
+          if (!(ba * bu * bb > thb)) continue;
+          if (FILL) W.tor[ot + nt] = make_int4(u, a, b, 0);
+          ++nt;
+        }
+      }
+    }
+    // donor bonds
+    if (hyd && P->atom[L.type_s[k]].hbond == 2 && bu >= P->hb_bo_cut && L.hb_cnt[j] > 0) {
+      if (FILL) W.don[od + nd] = u;
+      ++nd;
+    }
+  }
+  if (!FILL) {
+    W.cnt_ang[j] = na;
+    W.cnt_tor[j] = nt;
+    W.cnt_don[j] = nd;
+  }
 }
 
 // (5) bond energy (once per bond, from its lower-index entry), lone pair,
@@ -273,131 +346,97 @@ __global__ __launch_bounds__(BS) void k_atom_energy(const DevParams* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// (6) valence angle, penalty, coalition: one thread per centre atom j,
-//     expanding the unordered pairs of its bond entries on the fly
+// (6) valence angle, penalty, coalition: one thread per angle task
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void atomic_add3(double4* p, double3 v) { atomic_add3(p, v.x, v.y, v.z); }
+
 __global__ __launch_bounds__(BS) void k_angles(const DevParams* __restrict__ P, Lists L, Work W,
                                                double* __restrict__ energies) {
-  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t ntask = W.off_ang[L.n];
+  const double thb = P->thb_cut;
   double eval = 0.0, epen = 0.0, ecoa = 0.0;
-  unsigned long long nang = 0;
-  if (j < L.n) {
-    const int tj = L.type_s[j];
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ntask;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int2 uv = W.ang[t];
+    const int u = uv.x, v = uv.y;
+    const int j = L.bond_i[u], i = L.bond_j[u], k = L.bond_j[v];
+    const int ti = L.type_s[i], tj = L.type_s[j], tk = L.type_s[k];
     const AtomP& aj = P->atom[tj];
-    const AtomState st = W.ast[j];
-    const double thb = P->thb_cut, thb2 = P->thb_cutsq;
-    const double th0f = 1.0 - exp(-P->p_val10 * (2.0 - st.SBO2));
-    const double dth0f = -exp(-P->p_val10 * (2.0 - st.SBO2)) * P->p_val10;  // d th0f / d SBO2
-    const double e6 = exp(P->p_val6 * st.Dang);
-    const double ep3 = exp(-P->p_pen3 * st.Delta), ep4 = exp(P->p_pen4 * st.Delta);
-    const double f9d = 1.0 + ep3 + ep4;
-    const double f9 = (2.0 + ep3) / f9d;
-    const double df9 = (-P->p_pen3 * ep3 * f9d - (2.0 + ep3) * (-P->p_pen3 * ep3 + P->p_pen4 * ep4)) /
-                       (f9d * f9d);
-    const double ec = exp(P->p_coa2 * st.Dang);
-    const double fc = 1.0 / (1.0 + ec);
-    const double dfc = -P->p_coa2 * ec * fc * fc;
-    double gS = 0.0, gSBO2 = 0.0;
-    const int e0 = L.bond_off[j], e1 = L.bond_off[j + 1];
-    for (int u = e0; u < e1; ++u) {
-      const double4 bu = W.bo[u];
-      if (!(bu.x - thb > 0.0)) continue;
-      const int i = L.bond_j[u];
-      const int ti = L.type_s[i];
-      const double4 ru = W.bd[u];
-      const double Si = W.ast[i].S;
-      for (int v = u + 1; v < e1; ++v) {
-        const double4 bv = W.bo[v];
-        if (!(bv.x - thb > 0.0 && bu.x * bv.x > thb2)) continue;
-        const int k = L.bond_j[v];
-        const int tk = L.type_s[k];
-        const double4 rv = W.bd[v];
-        const double Sk = W.ast[k].S;
-        const AngleP& ap = P->angle[(ti * NT + tj) * NT + tk];
-        ++nang;
-        const double B1 = bu.x - thb, B2 = bv.x - thb;
-        // angle between r_ji (= bd[u]) and r_jk (= bd[v])
-        const double il1 = 1.0 / ru.w, il2 = 1.0 / rv.w;
-        double c = (ru.x * rv.x + ru.y * rv.y + ru.z * rv.z) * il1 * il2;
-        c = c > 1.0 ? 1.0 : (c < -1.0 ? -1.0 : c);
-        const double th = acos(c);
-        const double sn = fmax(sqrt(1.0 - c * c), 1e-5);
-        const double th0 = PI - ap.theta00_rad * th0f;
-        const double dth0 = -ap.theta00_rad * dth0f;     // d th0 / d SBO2
-        // f7
-        const double x1 = pow(B1, ap.p_val4), x2 = pow(B2, ap.p_val4);
-        const double g1 = exp(-aj.p_val3 * x1), g2 = exp(-aj.p_val3 * x2);
-        const double f7a = 1.0 - g1, f7b = 1.0 - g2;
-        const double df7a = aj.p_val3 * ap.p_val4 * x1 / B1 * g1;
-        const double df7b = aj.p_val3 * ap.p_val4 * x2 / B2 * g2;
-        // f8
-        const double e7 = exp(-ap.p_val7 * st.Dang);
-        const double f8d = 1.0 + e6 + e7;
-        const double f8 = aj.p_val5 - (aj.p_val5 - 1.0) * (2.0 + e6) / f8d;
-        const double df8 = -(aj.p_val5 - 1.0) *
-                           (P->p_val6 * e6 * f8d - (2.0 + e6) * (P->p_val6 * e6 - ap.p_val7 * e7)) /
-                           (f8d * f8d);
-        const double dt = th0 - th;
-        const double ev = exp(-ap.p_val2 * dt * dt);
-        const double Ea = f7a * f7b * f8 * ap.p_val1;
-        const double Ev = Ea * (1.0 - ev);
-        const double gdt = Ea * ev * 2.0 * ap.p_val2 * dt;   // dE/d(th0 - th)
-        double gB1 = df7a * f7b * f8 * ap.p_val1 * (1.0 - ev);
-        double gB2 = f7a * df7b * f8 * ap.p_val1 * (1.0 - ev);
-        gS += f7a * f7b * df8 * ap.p_val1 * (1.0 - ev);      // via Dang
-        gSBO2 += gdt * dth0;
-        double gth = -gdt;                                   // dE/dtheta
-        // penalty
-        const double pe1 = exp(-P->p_pen2 * sqr(B1 - 2.0)), pe2 = exp(-P->p_pen2 * sqr(B2 - 2.0));
-        const double Ep = ap.p_pen1 * f9 * pe1 * pe2;
-        gB1 += Ep * (-2.0 * P->p_pen2 * (B1 - 2.0));
-        gB2 += Ep * (-2.0 * P->p_pen2 * (B2 - 2.0));
-        gS += ap.p_pen1 * df9 * pe1 * pe2;                   // via Delta
-        // coalition
-        const double ci = exp(-P->p_coa3 * sqr(Si - B1)), ck = exp(-P->p_coa3 * sqr(Sk - B2));
-        const double cb1 = exp(-P->p_coa4 * sqr(B1 - 1.5)), cb2 = exp(-P->p_coa4 * sqr(B2 - 1.5));
-        const double Ec = ap.p_coa1 * fc * ci * ck * cb1 * cb2;
-        gS += ap.p_coa1 * dfc * ci * ck * cb1 * cb2;         // via Dang
-        const double gSi = Ec * (-2.0 * P->p_coa3 * (Si - B1));
-        const double gSk = Ec * (-2.0 * P->p_coa3 * (Sk - B2));
-        gB1 += Ec * (2.0 * P->p_coa3 * (Si - B1) - 2.0 * P->p_coa4 * (B1 - 1.5));
-        gB2 += Ec * (2.0 * P->p_coa3 * (Sk - B2) - 2.0 * P->p_coa4 * (B2 - 1.5));
-        eval += Ev;
-        epen += Ep;
-        ecoa += Ec;
-        // geometry: dtheta/dc = -1/sin
-        const double gc = -gth / sn;
-        const double ca = c * il1 * il1, cb = c * il2 * il2, ab = il1 * il2;
-        double4 gu = W.gvec[u], gv = W.gvec[v];
-        gu.x += gc * (rv.x * ab - ru.x * ca);
-        gu.y += gc * (rv.y * ab - ru.y * ca);
-        gu.z += gc * (rv.z * ab - ru.z * ca);
-        gv.x += gc * (ru.x * ab - rv.x * cb);
-        gv.y += gc * (ru.y * ab - rv.y * cb);
-        gv.z += gc * (ru.z * ab - rv.z * cb);
-        W.gvec[u] = gu;
-        W.gvec[v] = gv;
-        double4 gbu = W.gbo[u], gbv = W.gbo[v];
-        gbu.x += gB1;
-        gbu.w += gSi;
-        gbv.x += gB2;
-        gbv.w += gSk;
-        W.gbo[u] = gbu;
-        W.gbo[v] = gbv;
-      }
-    }
-    W.gS[j] += gS;
-    W.gSBO[j] = gSBO2 * st.dSBO2;
+    const AngleP& ap = P->angle[(ti * NT + tj) * NT + tk];
+    const AtomState& st = W.ast[j];
+    const double4 ru = W.bd[u], rv = W.bd[v];
+    const double B1 = W.bo[u].x - thb, B2 = W.bo[v].x - thb;
+    const double Si = W.ast[i].S, Sk = W.ast[k].S;
+    // angle between r_ji (= bd[u]) and r_jk (= bd[v])
+    const double il1 = 1.0 / ru.w, il2 = 1.0 / rv.w;
+    double c = (ru.x * rv.x + ru.y * rv.y + ru.z * rv.z) * il1 * il2;
+    c = c > 1.0 ? 1.0 : (c < -1.0 ? -1.0 : c);
+    const double th = acos(c);
+    const double sn = fmax(sqrt(1.0 - c * c), 1e-5);
+    const double th0 = PI - ap.theta00_rad * st.th0f;
+    const double dth0 = -ap.theta00_rad * st.dth0f;     // d th0 / d SBO2
+    // f7
+    const double x1 = pow(B1, ap.p_val4), x2 = pow(B2, ap.p_val4);
+    const double g1 = exp(-aj.p_val3 * x1), g2 = exp(-aj.p_val3 * x2);
+    const double f7a = 1.0 - g1, f7b = 1.0 - g2;
+    const double df7a = aj.p_val3 * ap.p_val4 * x1 / B1 * g1;
+    const double df7b = aj.p_val3 * ap.p_val4 * x2 / B2 * g2;
+    // f8
+    const double e6 = st.e6;
+    const double e7 = exp(-ap.p_val7 * st.Dang);
+    const double f8d = 1.0 + e6 + e7;
+    const double f8 = aj.p_val5 - (aj.p_val5 - 1.0) * (2.0 + e6) / f8d;
+    const double df8 = -(aj.p_val5 - 1.0) *
+                       (P->p_val6 * e6 * f8d - (2.0 + e6) * (P->p_val6 * e6 - ap.p_val7 * e7)) /
+                       (f8d * f8d);
+    const double dt = th0 - th;
+    const double ev = exp(-ap.p_val2 * dt * dt);
+    const double Ea = f7a * f7b * f8 * ap.p_val1;
+    const double Ev = Ea * (1.0 - ev);
+    const double gdt = Ea * ev * 2.0 * ap.p_val2 * dt;   // dE/d(th0 - th)
+    double gB1 = df7a * f7b * f8 * ap.p_val1 * (1.0 - ev);
+    double gB2 = f7a * df7b * f8 * ap.p_val1 * (1.0 - ev);
+    double gS = f7a * f7b * df8 * ap.p_val1 * (1.0 - ev);      // via Dang
+    const double gSBO2 = gdt * dth0;
+    // penalty
+    const double pe1 = exp(-P->p_pen2 * sqr(B1 - 2.0)), pe2 = exp(-P->p_pen2 * sqr(B2 - 2.0));
+    const double Ep = ap.p_pen1 * st.f9 * pe1 * pe2;
+    gB1 += Ep * (-2.0 * P->p_pen2 * (B1 - 2.0));
+    gB2 += Ep * (-2.0 * P->p_pen2 * (B2 - 2.0));
+    gS += ap.p_pen1 * st.df9 * pe1 * pe2;                       // via Delta
+    // coalition
+    const double ci = exp(-P->p_coa3 * sqr(Si - B1)), ck = exp(-P->p_coa3 * sqr(Sk - B2));
+    const double cb1 = exp(-P->p_coa4 * sqr(B1 - 1.5)), cb2 = exp(-P->p_coa4 * sqr(B2 - 1.5));
+    const double Ec = ap.p_coa1 * st.fc * ci * ck * cb1 * cb2;
+    gS += ap.p_coa1 * st.dfc * ci * ck * cb1 * cb2;            // via Dang
+    const double gSi = Ec * (-2.0 * P->p_coa3 * (Si - B1));
+    const double gSk = Ec * (-2.0 * P->p_coa3 * (Sk - B2));
+    gB1 += Ec * (2.0 * P->p_coa3 * (Si - B1) - 2.0 * P->p_coa4 * (B1 - 1.5));
+    gB2 += Ec * (2.0 * P->p_coa3 * (Sk - B2) - 2.0 * P->p_coa4 * (B2 - 1.5));
+    eval += Ev;
+    epen += Ep;
+    ecoa += Ec;
+    // geometry: dtheta/dc = -1/sin;  dE/dc = dE/dtheta * dtheta/dc = gdt / sin
+    const double gc = gdt / sn;
+    const double ca = c * il1 * il1, cb = c * il2 * il2, ab = il1 * il2;
+    atomic_add3(&W.gvec[u], gc * (rv.x * ab - ru.x * ca), gc * (rv.y * ab - ru.y * ca),
+                gc * (rv.z * ab - ru.z * ca));
+    atomic_add3(&W.gvec[v], gc * (ru.x * ab - rv.x * cb), gc * (ru.y * ab - rv.y * cb),
+                gc * (ru.z * ab - rv.z * cb));
+    atomicAdd(&W.gbo[u].x, gB1);
+    atomicAdd(&W.gbo[u].w, gSi);
+    atomicAdd(&W.gbo[v].x, gB2);
+    atomicAdd(&W.gbo[v].w, gSk);
+    atomicAdd(&W.gS[j], gS);
+    atomicAdd(&W.gSBO[j], gSBO2);
   }
   block_add<BS>(eval, energies + E_VAL);
   block_add<BS>(epen, energies + E_PEN);
   block_add<BS>(ecoa, energies + E_COA);
-  if (nang) atomicAdd(&W.counters[0], nang);
 }
 
 // ---------------------------------------------------------------------------
-// (7) torsion and 4-body conjugation: one thread per central bond j-k (the
-//     entry of the lower index), expanding i in B(j)\{k}, l in B(k)\{j,i}
+// (7) torsion and 4-body conjugation: one thread per torsion task
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double3 cross(double3 a, double3 b) {
   return make_double3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
@@ -408,239 +447,190 @@ __device__ __forceinline__ double3 axpy(double a, double3 x, double3 y) {
   return make_double3(a * x.x + y.x, a * x.y + y.y, a * x.z + y.z);
 }
 __device__ __forceinline__ double3 scale(double a, double3 x) { return make_double3(a * x.x, a * x.y, a * x.z); }
+__device__ __forceinline__ double3 add3(double3 a, double3 b) { return make_double3(a.x + b.x, a.y + b.y, a.z + b.z); }
 
 __global__ __launch_bounds__(BS) void k_torsions(const DevParams* __restrict__ P, Lists L, Work W,
                                                  double* __restrict__ energies) {
-  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t ntask = W.off_tor[L.n];
+  const double thb = P->thb_cut, pt2 = P->p_tor2, pc2 = P->p_cot2;
   double etor = 0.0, econj = 0.0;
-  unsigned long long ntor = 0;
-  if (j < L.n) {
-    const int tj = L.type_s[j];
-    const double thb = P->thb_cut;
-    const double pt2 = P->p_tor2, pc2 = P->p_cot2;
-    const int ej0 = L.bond_off[j], ej1 = L.bond_off[j + 1];
-    for (int ejk = ej0; ejk < ej1; ++ejk) {
-      const int k = L.bond_j[ejk];
-      if (k <= (int)j) continue;
-      const double4 bjk = W.bo[ejk];
-      if (!(bjk.x > thb)) continue;
-      const int tk = L.type_s[k];
-      const double4 r2v = W.bd[ejk];              // b2 = x_k - x_j
-      const double3 b2 = d3(r2v);
-      const double l2 = r2v.w;
-      const double Dsum = W.ast[j].Dang + W.ast[k].Dang;
-      const double et3 = exp(-P->p_tor3 * Dsum), et4 = exp(P->p_tor4 * Dsum);
-      const double f11d = 1.0 + et3 + et4;
-      const double f11 = (2.0 + et3) / f11d;
-      const double df11 = (-P->p_tor3 * et3 * f11d - (2.0 + et3) * (-P->p_tor3 * et3 + P->p_tor4 * et4)) /
-                          (f11d * f11d);
-      const double Bjk = bjk.x - thb;
-      const double hjk = 1.0 - exp(-pt2 * Bjk), dhjk = pt2 * exp(-pt2 * Bjk);
-      const double cjk = exp(-pc2 * sqr(Bjk - 1.5));
-      const double pi2 = 2.0 - bjk.y - f11;
-      const int ek0 = L.bond_off[k], ek1 = L.bond_off[k + 1];
-      // accumulated adjoints of the central bond
-      double gBjk = 0.0, gPjk = 0.0, gD = 0.0;
-      double3 g2 = make_double3(0.0, 0.0, 0.0);
-      for (int eji = ej0; eji < ej1; ++eji) {
-        const int i = L.bond_j[eji];
-        if (i == k) continue;
-        const double4 bij = W.bo[eji];
-        if (!(bij.x > thb)) continue;
-        const int ti = L.type_s[i];
-        const double4 r1v = W.bd[eji];            // r_ji = x_i - x_j = -b1
-        const double3 b1 = make_double3(-r1v.x, -r1v.y, -r1v.z);
-        const double l1 = r1v.w;
-        const double Bij = bij.x - thb;
-        const double hij = 1.0 - exp(-pt2 * Bij), dhij = pt2 * exp(-pt2 * Bij);
-        const double cij = exp(-pc2 * sqr(Bij - 1.5));
-        // angle i-j-k: cos = (r_ji . r_jk)/(l1 l2) = -(b1.b2)/(l1 l2)
-        const double c1 = -dot(b1, b2) / (l1 * l2);
-        const double s1sq = fmax(1.0 - c1 * c1, 0.0);
-        const double s1 = sqrt(s1sq);
-        const double3 m = cross(b1, b2);
-        const double mm = dot(m, m);
-        const double nm = fmax(sqrt(mm), 1e-20);
-        double gBij = 0.0;
-        double3 g1 = make_double3(0.0, 0.0, 0.0);
-        for (int ekl = ek0; ekl < ek1; ++ekl) {
-          const int l = L.bond_j[ekl];
-          if (l == (int)j || l == i) continue;
-          const double4 bkl = W.bo[ekl];
-          if (!(bkl.x > thb)) continue;
-          if (!(bij.x * bjk.x * bkl.x > thb)) continue;
-          const int tl = L.type_s[l];
-          const TorsP& tp = P->tors[((ti * NT + tj) * NT + tk) * NT + tl];
-          ++ntor;
-          const double4 r3v = W.bd[ekl];          // b3 = x_l - x_k
-          const double3 b3 = d3(r3v);
-          const double l3 = r3v.w;
-          const double Bkl = bkl.x - thb;
-          const double hkl = 1.0 - exp(-pt2 * Bkl), dhkl = pt2 * exp(-pt2 * Bkl);
-          const double ckl = exp(-pc2 * sqr(Bkl - 1.5));
-          // angle j-k-l: cos = (r_kj . r_kl)/(l2 l3) = -(b2.b3)/(l2 l3)
-          const double c2 = -dot(b2, b3) / (l2 * l3);
-          const double s2sq = fmax(1.0 - c2 * c2, 0.0);
-          const double s2 = sqrt(s2sq);
-          const double3 nv = cross(b2, b3);
-          const double nn = fmax(sqrt(dot(nv, nv)), 1e-20);
-          const double cw = dot(m, nv) / (nm * nn);
-          const double ss = s1 * s2;
-          const double f10 = hij * hjk * hkl;
-          const double exv = exp(tp.p_tor1 * pi2 * pi2);
-          const double c2w = 2.0 * cw * cw - 1.0;
-          const double c3w = 4.0 * cw * cw * cw - 3.0 * cw;
-          const double Vt = 0.5 * (tp.V1 * (1.0 + cw) + tp.V2 * exv * (1.0 - c2w) + tp.V3 * (1.0 + c3w));
-          const double Et = f10 * ss * Vt;
-          const double f12 = cij * cjk * ckl;
-          const double Ec = tp.p_cot1 * f12 * (1.0 + (cw * cw - 1.0) * ss);
-          etor += Et;
-          econj += Ec;
-          // scalar adjoints
-          const double dVt_dcw = 0.5 * (tp.V1 - 4.0 * tp.V2 * exv * cw + tp.V3 * (12.0 * cw * cw - 3.0));
-          const double dex = 0.5 * tp.V2 * (1.0 - c2w) * exv * tp.p_tor1 * 2.0 * pi2 * (-1.0);
-          // d exv / d BOpi_jk and d f11 both have the factor -1 * 2 pi2 * p_tor1 * exv
-          gPjk += f10 * ss * dex;
-          gD += f10 * ss * dex * df11;
-          const double gss = f10 * Vt + tp.p_cot1 * f12 * (cw * cw - 1.0);
-          const double gcw = f10 * ss * dVt_dcw + tp.p_cot1 * f12 * 2.0 * cw * ss;
-          gBij += dhij * hjk * hkl * ss * Vt + Ec * (-2.0 * pc2 * (Bij - 1.5));
-          gBjk += hij * dhjk * hkl * ss * Vt + Ec * (-2.0 * pc2 * (Bjk - 1.5));
-          const double gBkl = hij * hjk * dhkl * ss * Vt + Ec * (-2.0 * pc2 * (Bkl - 1.5));
-          // cos w gradients w.r.t. b1, b2, b3
-          const double inm = 1.0 / (nm * nn);
-          const double3 Gm = axpy(-cw / (nm * nm), m, scale(inm, nv));
-          const double3 Gn = axpy(-cw / (nn * nn), nv, scale(inm, m));
-          const double3 dcw_b1 = cross(b2, Gm);
-          const double3 dcw_b2 = make_double3(cross(Gm, b1).x + cross(b3, Gn).x,
-                                              cross(Gm, b1).y + cross(b3, Gn).y,
-                                              cross(Gm, b1).z + cross(b3, Gn).z);
-          const double3 dcw_b3 = cross(Gn, b2);
-          // sin gradients: s = sqrt(1 - c^2), ds/dc = -c/s
-          const double gs1 = gss * s2, gs2 = gss * s1;
-          const double gc1 = s1 > 1e-10 ? gs1 * (-c1 / s1) : 0.0;
-          const double gc2 = s2 > 1e-10 ? gs2 * (-c2 / s2) : 0.0;
-          // c1 = -(b1.b2)/(l1 l2): dc1/db1 = -b2/(l1 l2) - c1 b1/l1^2 ; dc1/db2 = -b1/(l1 l2) - c1 b2/l2^2
-          const double i12 = 1.0 / (l1 * l2), i23 = 1.0 / (l2 * l3);
-          const double3 dc1_b1 = axpy(-c1 / (l1 * l1), b1, scale(-i12, b2));
-          const double3 dc1_b2 = axpy(-c1 / (l2 * l2), b2, scale(-i12, b1));
-          const double3 dc2_b2 = axpy(-c2 / (l2 * l2), b2, scale(-i23, b3));
-          const double3 dc2_b3 = axpy(-c2 / (l3 * l3), b3, scale(-i23, b2));
-          // dE/db1, dE/db2, dE/db3
-          const double3 gb1 = axpy(gc1, dc1_b1, scale(gcw, dcw_b1));
-          const double3 gb2 = axpy(gc2, dc2_b2, axpy(gc1, dc1_b2, scale(gcw, dcw_b2)));
-          const double3 gb3 = axpy(gc2, dc2_b3, scale(gcw, dcw_b3));
-          g1 = axpy(1.0, gb1, g1);
-          g2 = axpy(1.0, gb2, g2);
-          // entry k->l: vector r_kl = b3
-          atomic_add3(&W.gvec[ekl], gb3.x, gb3.y, gb3.z);
-          atomicAdd(&W.gbo[ekl].x, gBkl);
-        }
-        // entry j->i: vector r_ji = -b1
-        if (gBij != 0.0 || g1.x != 0.0 || g1.y != 0.0 || g1.z != 0.0) {
-          atomic_add3(&W.gvec[eji], -g1.x, -g1.y, -g1.z);
-          atomicAdd(&W.gbo[eji].x, gBij);
-        }
-      }
-      if (gBjk != 0.0 || gPjk != 0.0 || g2.x != 0.0 || g2.y != 0.0 || g2.z != 0.0) {
-        atomic_add3(&W.gvec[ejk], g2.x, g2.y, g2.z);   // entry j->k: r_jk = b2
-        atomicAdd(&W.gbo[ejk].x, gBjk);
-        atomicAdd(&W.gbo[ejk].y, gPjk);
-        atomicAdd(&W.gS[j], gD);
-        atomicAdd(&W.gS[k], gD);
-      }
-    }
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ntask;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int4 q = W.tor[t];
+    const int ejk = q.x, eji = q.y, ekl = q.z;
+    const int j = L.bond_i[ejk], k = L.bond_j[ejk], i = L.bond_j[eji], l = L.bond_j[ekl];
+    const int ti = L.type_s[i], tj = L.type_s[j], tk = L.type_s[k], tl = L.type_s[l];
+    const TorsP& tp = P->tors[((ti * NT + tj) * NT + tk) * NT + tl];
+    const double4 bjk = W.bo[ejk];
+    const double bij = W.bo[eji].x, bkl = W.bo[ekl].x;
+    // f11 of the central bond
+    const double Dsum = W.ast[j].Dang + W.ast[k].Dang;
+    const double et3 = exp(-P->p_tor3 * Dsum), et4 = exp(P->p_tor4 * Dsum);
+    const double f11d = 1.0 + et3 + et4;
+    const double f11 = (2.0 + et3) / f11d;
+    const double df11 = (-P->p_tor3 * et3 * f11d - (2.0 + et3) * (-P->p_tor3 * et3 + P->p_tor4 * et4)) /
+                        (f11d * f11d);
+    const double Bij = bij - thb, Bjk = bjk.x - thb, Bkl = bkl - thb;
+    const double xij = exp(-pt2 * Bij), xjk = exp(-pt2 * Bjk), xkl = exp(-pt2 * Bkl);
+    const double hij = 1.0 - xij, hjk = 1.0 - xjk, hkl = 1.0 - xkl;
+    const double dhij = pt2 * xij, dhjk = pt2 * xjk, dhkl = pt2 * xkl;
+    const double cij = exp(-pc2 * sqr(Bij - 1.5)), cjk = exp(-pc2 * sqr(Bjk - 1.5)),
+                 ckl = exp(-pc2 * sqr(Bkl - 1.5));
+    const double pi2 = 2.0 - bjk.y - f11;
+    // geometry: b1 = x_j - x_i = -r_ji, b2 = x_k - x_j, b3 = x_l - x_k
+    const double4 r1v = W.bd[eji], r2v = W.bd[ejk], r3v = W.bd[ekl];
+    const double3 b1 = make_double3(-r1v.x, -r1v.y, -r1v.z), b2 = d3(r2v), b3 = d3(r3v);
+    const double l1 = r1v.w, l2 = r2v.w, l3 = r3v.w;
+    const double c1 = -dot(b1, b2) / (l1 * l2);   // cos of angle i-j-k
+    const double c2 = -dot(b2, b3) / (l2 * l3);   // cos of angle j-k-l
+    const double s1 = sqrt(fmax(1.0 - c1 * c1, 0.0)), s2 = sqrt(fmax(1.0 - c2 * c2, 0.0));
+    const double3 m = cross(b1, b2), nv = cross(b2, b3);
+    const double nm = fmax(sqrt(dot(m, m)), 1e-20), nn = fmax(sqrt(dot(nv, nv)), 1e-20);
+    const double cw = dot(m, nv) / (nm * nn);
+    const double ss = s1 * s2;
+    const double f10 = hij * hjk * hkl;
+    const double exv = exp(tp.p_tor1 * pi2 * pi2);
+    const double c2w = 2.0 * cw * cw - 1.0;
+    const double c3w = 4.0 * cw * cw * cw - 3.0 * cw;
+    const double Vt = 0.5 * (tp.V1 * (1.0 + cw) + tp.V2 * exv * (1.0 - c2w) + tp.V3 * (1.0 + c3w));
+    const double Et = f10 * ss * Vt;
+    const double f12 = cij * cjk * ckl;
+    const double Ec = tp.p_cot1 * f12 * (1.0 + (cw * cw - 1.0) * ss);
+    etor += Et;
+    econj += Ec;
+    // scalar adjoints
+    const double dVt_dcw = 0.5 * (tp.V1 - 4.0 * tp.V2 * exv * cw + tp.V3 * (12.0 * cw * cw - 3.0));
+    // d exv / d BOpi_jk = d exv / d f11 = -2 p_tor1 pi2 exv
+    const double dex = 0.5 * tp.V2 * (1.0 - c2w) * exv * tp.p_tor1 * 2.0 * pi2 * (-1.0);
+    const double gPjk = f10 * ss * dex;
+    const double gD = f10 * ss * dex * df11;
+    const double gss = f10 * Vt + tp.p_cot1 * f12 * (cw * cw - 1.0);
+    const double gcw = f10 * ss * dVt_dcw + tp.p_cot1 * f12 * 2.0 * cw * ss;
+    const double gBij = dhij * hjk * hkl * ss * Vt + Ec * (-2.0 * pc2 * (Bij - 1.5));
+    const double gBjk = hij * dhjk * hkl * ss * Vt + Ec * (-2.0 * pc2 * (Bjk - 1.5));
+    const double gBkl = hij * hjk * dhkl * ss * Vt + Ec * (-2.0 * pc2 * (Bkl - 1.5));
+    // cos w gradients
+    const double inm = 1.0 / (nm * nn);
+    const double3 Gm = axpy(-cw / (nm * nm), m, scale(inm, nv));
+    const double3 Gn = axpy(-cw / (nn * nn), nv, scale(inm, m));
+    const double3 dcw_b1 = cross(b2, Gm);
+    const double3 dcw_b2 = add3(cross(Gm, b1), cross(b3, Gn));
+    const double3 dcw_b3 = cross(Gn, b2);
+    // sin = sqrt(1 - c^2): d sin / d c = -c / sin
+    const double gc1 = s1 > 1e-10 ? gss * s2 * (-c1 / s1) : 0.0;
+    const double gc2 = s2 > 1e-10 ? gss * s1 * (-c2 / s2) : 0.0;
+    const double i12 = 1.0 / (l1 * l2), i23 = 1.0 / (l2 * l3);
+    const double3 dc1_b1 = axpy(-c1 / (l1 * l1), b1, scale(-i12, b2));
+    const double3 dc1_b2 = axpy(-c1 / (l2 * l2), b2, scale(-i12, b1));
+    const double3 dc2_b2 = axpy(-c2 / (l2 * l2), b2, scale(-i23, b3));
+    const double3 dc2_b3 = axpy(-c2 / (l3 * l3), b3, scale(-i23, b2));
+    const double3 gb1 = axpy(gc1, dc1_b1, scale(gcw, dcw_b1));
+    const double3 gb2 = axpy(gc2, dc2_b2, axpy(gc1, dc1_b2, scale(gcw, dcw_b2)));
+    const double3 gb3 = axpy(gc2, dc2_b3, scale(gcw, dcw_b3));
+    // entry j->i holds r_ji = -b1; j->k holds b2; k->l holds b3
+    atomic_add3(&W.gvec[eji], -gb1.x, -gb1.y, -gb1.z);
+    atomic_add3(&W.gvec[ejk], gb2);
+    atomic_add3(&W.gvec[ekl], gb3);
+    atomicAdd(&W.gbo[eji].x, gBij);
+    atomicAdd(&W.gbo[ejk].x, gBjk);
+    atomicAdd(&W.gbo[ejk].y, gPjk);
+    atomicAdd(&W.gbo[ekl].x, gBkl);
+    atomicAdd(&W.gS[j], gD);
+    atomicAdd(&W.gS[k], gD);
   }
   block_add<BS>(etor, energies + E_TOR);
   block_add<BS>(econj, energies + E_CONJ);
-  if (ntor) atomicAdd(&W.counters[1], ntor);
 }
 
 // ---------------------------------------------------------------------------
-// (8) hydrogen bonds: one thread per H atom
+// (8) hydrogen bonds: one thread per donor bond H-X, over the H's acceptors Z
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(BS) void k_hbonds(const DevParams* __restrict__ P, Grid g, Lists L, Work W,
                                                double* __restrict__ energies) {
-  const int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t ntask = W.off_don[L.n];
   double ehb = 0.0;
   unsigned long long nhb = 0;
-  if (h < L.n && P->atom[L.type_s[h]].hbond == 1) {
-    const int th = L.type_s[h];
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ntask;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int ex = W.don[t];
+    const int h = L.bond_i[ex], X = L.bond_j[ex];
+    const int th = L.type_s[h], tx = L.type_s[X];
     const double4 xh = L.xs[h];
-    double3 fh = make_double3(0.0, 0.0, 0.0);
-    const int z0 = L.hb_off[h], z1 = L.hb_off[h + 1];
-    for (int ex = L.bond_off[h]; ex < L.bond_off[h + 1]; ++ex) {
-      const int X = L.bond_j[ex];
-      const int tx = L.type_s[X];
-      if (P->atom[tx].hbond != 2) continue;
-      const double bo = W.bo[ex].x;
-      if (!(bo >= P->hb_bo_cut)) continue;
-      const double4 rx = W.bd[ex];     // x_X - x_h
-      const double ilx = 1.0 / rx.w;
-      double gbo = 0.0;
-      double3 gx = make_double3(0.0, 0.0, 0.0);
-      for (int s = z0; s < z1; ++s) {
-        const int Z = L.hb_j[s];
-        if (Z == X) continue;
-        const int tz = L.type_s[Z];
-        const HbP& hp = P->hb[(tx * NT + th) * NT + tz];
-        ++nhb;
-        const double4 xz = L.xs[Z];
-        double dx = xz.x - xh.x, dy = xz.y - xh.y, dz = xz.z - xh.z;
-        if (g.periodic) {
-          dx = min_image(dx, g.L[0], g.invL[0]);
-          dy = min_image(dy, g.L[1], g.invL[1]);
-          dz = min_image(dz, g.L[2], g.invL[2]);
-        }
-        const double rz = sqrt(dx * dx + dy * dy + dz * dz);
-        const double ilz = 1.0 / rz;
-        const double c = (rx.x * dx + rx.y * dy + rx.z * dz) * ilx * ilz;
-        const double hc = 0.5 * (1.0 - c);
-        const double s4 = hc * hc;
-        const double ds4 = -hc;                 // d s4 / d c
-        const double eb = exp(-hp.p_hb2 * bo);
-        const double fbo = 1.0 - eb, dfbo = hp.p_hb2 * eb;
-        const double fr = exp(-hp.p_hb3 * (hp.r0hb * ilz + rz / hp.r0hb - 2.0));
-        const double dfr = fr * (-hp.p_hb3) * (-hp.r0hb * ilz * ilz + 1.0 / hp.r0hb);
-        const double E = hp.p_hb1 * fbo * fr * s4;
-        ehb += E;
-        gbo += hp.p_hb1 * dfbo * fr * s4;
-        const double gc = hp.p_hb1 * fbo * fr * ds4;
-        const double grz = hp.p_hb1 * fbo * dfr * s4;
-        // dE/d r_hX
-        gx.x += gc * (dx * ilx * ilz - c * rx.x * ilx * ilx);
-        gx.y += gc * (dy * ilx * ilz - c * rx.y * ilx * ilx);
-        gx.z += gc * (dz * ilx * ilz - c * rx.z * ilx * ilx);
-        // dE/d r_hZ
-        const double gzx = gc * (rx.x * ilx * ilz - c * dx * ilz * ilz) + grz * dx * ilz;
-        const double gzy = gc * (rx.y * ilx * ilz - c * dy * ilz * ilz) + grz * dy * ilz;
-        const double gzz = gc * (rx.z * ilx * ilz - c * dz * ilz * ilz) + grz * dz * ilz;
-        fh.x += gzx;
-        fh.y += gzy;
-        fh.z += gzz;
-        atomic_add3(&W.fnb[Z], -gzx, -gzy, -gzz);
+    const double bo = W.bo[ex].x;
+    const double4 rx = W.bd[ex];     // x_X - x_h
+    const double ilx = 1.0 / rx.w;
+    double gbo = 0.0;
+    double3 gx = make_double3(0.0, 0.0, 0.0), fh = make_double3(0.0, 0.0, 0.0);
+    const int nz = L.hb_cnt[h];
+    const int32_t* __restrict__ zrow = L.hb_j + (int64_t)h * L.hb_w;
+    // 1 - e^{-p_hb2 BO} depends on the acceptor's type only through p_hb2:
+    // evaluate it once for the first acceptor type met
+    const int tz0 = nz > 0 ? L.type_s[zrow[0] == X && nz > 1 ? zrow[1] : zrow[0]] : 0;
+    const double eb0 = exp(-P->hb[(tx * NT + th) * NT + tz0].p_hb2 * bo);
+    for (int s = 0; s < nz; ++s) {
+      const int Z = zrow[s];
+      if (Z == X) continue;
+      const int tz = L.type_s[Z];
+      const HbP& hp = P->hb[(tx * NT + th) * NT + tz];
+      ++nhb;
+      const double4 xz = L.xs[Z];
+      double dx = xz.x - xh.x, dy = xz.y - xh.y, dz = xz.z - xh.z;
+      if (g.periodic) {
+        dx = min_image(dx, g.L[0], g.invL[0]);
+        dy = min_image(dy, g.L[1], g.invL[1]);
+        dz = min_image(dz, g.L[2], g.invL[2]);
       }
-      double4 gv = W.gvec[ex];
-      gv.x += gx.x;
-      gv.y += gx.y;
-      gv.z += gx.z;
-      W.gvec[ex] = gv;
-      W.gbo[ex].x += gbo;
+      const double rz = sqrt(dx * dx + dy * dy + dz * dz);
+      const double ilz = 1.0 / rz;
+      const double c = (rx.x * dx + rx.y * dy + rx.z * dz) * ilx * ilz;
+      const double hc = 0.5 * (1.0 - c);
+      const double s4 = hc * hc;
+      const double ds4 = -hc;                 // d s4 / d c
+      const double eb = tz == tz0 ? eb0 : exp(-hp.p_hb2 * bo);
+      const double fbo = 1.0 - eb, dfbo = hp.p_hb2 * eb;
+      const double fr = exp(-hp.p_hb3 * (hp.r0hb * ilz + rz / hp.r0hb - 2.0));
+      const double dfr = fr * (-hp.p_hb3) * (-hp.r0hb * ilz * ilz + 1.0 / hp.r0hb);
+      ehb += hp.p_hb1 * fbo * fr * s4;
+      gbo += hp.p_hb1 * dfbo * fr * s4;
+      const double gc = hp.p_hb1 * fbo * fr * ds4;
+      const double grz = hp.p_hb1 * fbo * dfr * s4;
+      // dE/d r_hX
+      gx.x += gc * (dx * ilx * ilz - c * rx.x * ilx * ilx);
+      gx.y += gc * (dy * ilx * ilz - c * rx.y * ilx * ilx);
+      gx.z += gc * (dz * ilx * ilz - c * rx.z * ilx * ilx);
+      // dE/d r_hZ
+      const double gzx = gc * (rx.x * ilx * ilz - c * dx * ilz * ilz) + grz * dx * ilz;
+      const double gzy = gc * (rx.y * ilx * ilz - c * dy * ilz * ilz) + grz * dy * ilz;
+      const double gzz = gc * (rx.z * ilx * ilz - c * dz * ilz * ilz) + grz * dz * ilz;
+      fh.x += gzx;
+      fh.y += gzy;
+      fh.z += gzz;
+      atomic_add3(&W.fnb[Z], -gzx, -gzy, -gzz);
     }
-    if (fh.x != 0.0 || fh.y != 0.0 || fh.z != 0.0) atomic_add3(&W.fnb[h], fh.x, fh.y, fh.z);
+    // the entry h->X belongs to this task alone
+    double4 gv = W.gvec[ex];
+    gv.x += gx.x;
+    gv.y += gx.y;
+    gv.z += gx.z;
+    W.gvec[ex] = gv;
+    W.gbo[ex].x += gbo;
+    atomic_add3(&W.fnb[h], fh);
   }
   block_add<BS>(ehb, energies + E_HB);
-  if (nhb) atomicAdd(&W.counters[2], nhb);
+  for (int off = 32; off > 0; off >>= 1) nhb += __shfl_down(nhb, off, 64);
+  if ((threadIdx.x & 63) == 0 && nhb) atomicAdd(&W.counters[2], nhb);
 }
 
 // ---------------------------------------------------------------------------
-// (9) van der Waals and Coulomb.  Each lane owns one atom and walks its full
-//     neighbour list, so every pair is evaluated twice (once from each side)
-//     and no force is scattered: the redundant-computation choice that the
-//     paper cites as the better one for pairwise terms on massively parallel
-//     processors (Section 3.1).  Energies count each visit with weight 1/2.
+// (9) van der Waals and Coulomb.  One wavefront per atom walks the atom's
+//     full neighbour row, one neighbour per lane, and reduces the atom's
+//     force across the wavefront.  Every pair is evaluated twice (once from
+//     each side) and no force is scattered: the redundant-computation choice
+//     the paper cites as the better one for pairwise terms on massively
+//     parallel processors (Section 3.1).  Energies weigh each visit by 1/2.
 // ---------------------------------------------------------------------------
 struct NbP { double D, alpha, inv_rv, gw_pow, g3, e_core, a_core, inv_rc; };
+constexpr int NB_WAVES = BS / 64;
 
 __global__ __launch_bounds__(BS) void k_nonbonded(const DevParams* __restrict__ P, Grid g, Lists L,
                                                   Work W, double* __restrict__ energies) {
@@ -650,7 +640,8 @@ __global__ __launch_bounds__(BS) void k_nonbonded(const DevParams* __restrict__ 
     sp[threadIdx.x] = NbP{p.D_vdw, p.alpha, p.inv_r_vdw, p.gw_pow, p.g3, p.e_core, p.a_core, p.inv_r_core};
   }
   __syncthreads();
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * NB_WAVES + (threadIdx.x >> 6);
   double evdw = 0.0, ecoul = 0.0;
   if (i < L.n) {
     const double4 xi = W.xq[i];
@@ -659,9 +650,10 @@ __global__ __launch_bounds__(BS) void k_nonbonded(const DevParams* __restrict__ 
     const double iR = P->inv_r_nonb, pv = P->p_vdW1, ipv = P->inv_p_vdW1;
     double fx = 0.0, fy = 0.0, fz = 0.0;
     const int cnt = L.far_cnt[i];
-    const int32_t* __restrict__ lj = L.far_j + blk_index(i, 0, L.far_w);
-    for (int k = 0; k < cnt; ++k) {
-      const int j = lj[(int64_t)k * 64];
+    const int32_t* __restrict__ row = L.far_j + i * (int64_t)L.far_w;
+    const NbP* __restrict__ spi = sp + ti * NT;
+    for (int k = lane; k < cnt; k += 64) {
+      const int j = row[k];
       const double4 xj = W.xq[j];
       double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
       if (g.periodic) {
@@ -670,8 +662,9 @@ __global__ __launch_bounds__(BS) void k_nonbonded(const DevParams* __restrict__ 
         dz = min_image(dz, g.L[2], g.invL[2]);
       }
       const double r2 = dx * dx + dy * dy + dz * dz;
-      const double r = sqrt(r2);
-      const NbP p = sp[ti * NT + L.type_s[j]];
+      const double ir = rsqrt(r2);
+      const double r = r2 * ir;
+      const NbP p = spi[L.type_s[j]];
       // taper
       const double u = r * iR, u2 = u * u, u3 = u2 * u, u4 = u2 * u2;
       const double tap = 20.0 * u4 * u3 - 70.0 * u4 * u2 + 84.0 * u4 * u - 35.0 * u4 + 1.0;
@@ -679,8 +672,9 @@ __global__ __launch_bounds__(BS) void k_nonbonded(const DevParams* __restrict__ 
       // shielded Morse with inner wall
       const double pw = exp(pv * log(r));
       const double sum = pw + p.gw_pow;
+      const double isum = 1.0 / sum;
       const double f13 = exp(ipv * log(sum));
-      const double df13 = f13 / sum * pw / r;
+      const double df13 = f13 * isum * pw * ir;
       const double t = 1.0 - f13 * p.inv_rv;
       const double e2 = exp(0.5 * p.alpha * t);
       const double e1 = e2 * e2;
@@ -688,21 +682,26 @@ __global__ __launch_bounds__(BS) void k_nonbonded(const DevParams* __restrict__ 
       const double dev = -p.D * p.alpha * p.inv_rv * (e1 - e2) * df13;
       const double ecr = p.e_core * exp(p.a_core * (1.0 - r * p.inv_rc));
       const double decr = -ecr * p.a_core * p.inv_rc;
-      // shielded Coulomb
+      // shielded Coulomb: den = (r^3 + gamma^-3)^(1/3), 1/s3 = (1/den)^3
       const double s3 = r2 * r + p.g3;
-      const double den = cbrt(s3);
-      const double eq = qi * xj.w / den;
-      const double deq = -eq * r2 / s3;
+      const double iden = 1.0 / cbrt(s3);
+      const double eq = qi * xj.w * iden;
+      const double deq = -eq * r2 * (iden * iden * iden);
       const double Ev = ev + ecr;
       evdw += tap * Ev;
       ecoul += tap * eq;
       const double dEdr = dtap * (Ev + eq) + tap * (dev + decr + deq);
-      const double f = dEdr / r;
+      const double f = dEdr * ir;
       fx += f * dx;
       fy += f * dy;
       fz += f * dz;
     }
-    W.fnb[i] = make_double4(fx, fy, fz, 0.0);
+    for (int off = 32; off > 0; off >>= 1) {
+      fx += __shfl_down(fx, off, 64);
+      fy += __shfl_down(fy, off, 64);
+      fz += __shfl_down(fz, off, 64);
+    }
+    if (lane == 0) W.fnb[i] = make_double4(fx, fy, fz, 0.0);
   }
   block_add<BS>(0.5 * evdw, energies + E_VDW);
   block_add<BS>(0.5 * ecoul, energies + E_COUL);
@@ -728,7 +727,10 @@ __global__ __launch_bounds__(BS) void k_back_s(Lists L, Work W) {
     gsig += W.gSig[j] * (b.y + b.z);
   }
   g += (1.0 + st.dnlp) * gsig;
-  g += W.gSBO[i] * (1.0 - st.prod) * st.dW;
+  // the angle tasks accumulated dE/dSBO2; convert to dE/dSBO for the next stage
+  const double gsbo = W.gSBO[i] * st.dSBO2;
+  W.gSBO[i] = gsbo;
+  g += gsbo * (1.0 - st.prod) * st.dW;
   W.gStot[i] = g;
 }
 
@@ -818,12 +820,19 @@ __global__ void k_gather_q(const double* __restrict__ q, const int32_t* __restri
 
 const char* const kKernelNames[KID_COUNT] = {
     "bbox", "cell_hist", "cell_scatter", "cell_sort", "gather_sorted", "list_sweep", "scan",
-    "compact", "mirror", "zero", "gather_q", "bo_prime", "delta_prime", "bo_corr", "atom_state",
-    "atom_energy", "angles", "torsions", "hbonds", "nonbonded", "back_s", "back_corr", "back_dp",
-    "forces"};
+    "bondtest", "compact", "mirror", "zero", "gather_q", "bo_prime", "delta_prime", "bo_corr", "atom_state",
+    "atom_energy", "tasks", "angles", "torsions", "hbonds", "nonbonded", "back_s", "back_corr",
+    "back_dp", "forces"};
+
+// grid of a grid-stride task kernel: enough blocks to fill the chip, no more
+// than the task bound needs
+static unsigned task_grid(int64_t bound) {
+  const int64_t b = (bound + BS - 1) / BS;
+  return (unsigned)(b < 1 ? 1 : (b > 8192 ? 8192 : b));
+}
 
 int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, const double* q,
-                  double* forces, double* energies, Prof& pf, hipStream_t st) {
+                  double* forces, double* energies, Scratch& sc, Prof& pf, hipStream_t st) {
   const int64_t n = L.n, nb = L.nbond;
   pf.begin(KID_ZERO, st);
   (void)hipMemsetAsync(energies, 0, sizeof(double) * NTERMS, st);
@@ -845,15 +854,29 @@ int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, co
   LAUNCH(KID_GATHER_Q, k_gather_q, grid, blk, 0, st, q, L.perm, L.xs, n, W.xq);
   // nonbonded first: it initialises the per-atom force accumulator that the
   // hydrogen-bond kernel adds to
-  LAUNCH(KID_NONBONDED, k_nonbonded, grid, blk, 0, st, P, g, L, W, energies);
+  LAUNCH(KID_NONBONDED, k_nonbonded, dim3(nblk(n, NB_WAVES)), blk, 0, st, P, g, L, W, energies);
   LAUNCH(KID_BO_PRIME, k_bo_prime, grid, blk, 0, st, P, g, L, W);
   LAUNCH(KID_DELTA_PRIME, k_delta_prime, grid, blk, 0, st, P, L, W);
   LAUNCH(KID_BO_CORR, k_bo_corr, grid, blk, 0, st, P, L, W);
   LAUNCH(KID_ATOM_STATE, k_atom_state, grid, blk, 0, st, P, L, W);
   LAUNCH(KID_ATOM_ENERGY, k_atom_energy, grid, blk, 0, st, P, L, W, energies);
-  LAUNCH(KID_ANGLES, k_angles, grid, blk, 0, st, P, L, W, energies);
-  LAUNCH(KID_TORSIONS, k_torsions, grid, blk, 0, st, P, L, W, energies);
-  LAUNCH(KID_HBONDS, k_hbonds, grid, blk, 0, st, P, g, L, W, energies);
+  // task lists: count, prefix sums, fill
+  LAUNCH(KID_TASKS, k_tasks<false>, grid, blk, 0, st, P, L, W);
+  (void)hipMemsetAsync(W.cnt_ang + n, 0, sizeof(int32_t), st);
+  (void)hipMemsetAsync(W.cnt_tor + n, 0, sizeof(int32_t), st);
+  (void)hipMemsetAsync(W.cnt_don + n, 0, sizeof(int32_t), st);
+  pf.begin(KID_SCAN, st);
+  scan_i32(W.cnt_ang, W.off_ang, n + 1, sc, st);
+  scan_i32(W.cnt_tor, W.off_tor, n + 1, sc, st);
+  scan_i32(W.cnt_don, W.off_don, n + 1, sc, st);
+  pf.end(st);
+  LAUNCH(KID_TASKS, k_tasks<true>, grid, blk, 0, st, P, L, W);
+  const dim3 ga(task_grid(L.bound_ang)), gt(task_grid(L.bound_tor)), gd(task_grid(L.bound_don));
+  LAUNCH(KID_ANGLES, k_angles, ga, blk, 0, st, P, L, W, energies);
+  LAUNCH(KID_TORSIONS, k_torsions, gt, blk, 0, st, P, L, W, energies);
+  LAUNCH(KID_HBONDS, k_hbonds, gd, blk, 0, st, P, g, L, W, energies);
+  (void)hipMemcpyAsync(W.counters, W.off_ang + n, sizeof(int32_t), hipMemcpyDeviceToDevice, st);
+  (void)hipMemcpyAsync(W.counters + 1, W.off_tor + n, sizeof(int32_t), hipMemcpyDeviceToDevice, st);
   LAUNCH(KID_BACK_S, k_back_s, grid, blk, 0, st, L, W);
   LAUNCH(KID_BACK_CORR, k_back_corr, grid, blk, 0, st, P, L, W);
   LAUNCH(KID_BACK_DP, k_back_dp, grid, blk, 0, st, L, W);

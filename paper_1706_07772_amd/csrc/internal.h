@@ -10,8 +10,8 @@ namespace rx {
 // kernels timed by the optional event profiler (reaxff_profile)
 enum KernelId {
   KID_BBOX, KID_CELL_HIST, KID_CELL_SCATTER, KID_CELL_SORT, KID_GATHER, KID_LIST_SWEEP, KID_SCAN,
-  KID_COMPACT, KID_MIRROR, KID_ZERO, KID_GATHER_Q, KID_BO_PRIME, KID_DELTA_PRIME, KID_BO_CORR,
-  KID_ATOM_STATE, KID_ATOM_ENERGY, KID_ANGLES, KID_TORSIONS, KID_HBONDS, KID_NONBONDED,
+  KID_BONDTEST, KID_COMPACT, KID_MIRROR, KID_ZERO, KID_GATHER_Q, KID_BO_PRIME, KID_DELTA_PRIME, KID_BO_CORR,
+  KID_ATOM_STATE, KID_ATOM_ENERGY, KID_TASKS, KID_ANGLES, KID_TORSIONS, KID_HBONDS, KID_NONBONDED,
   KID_BACK_S, KID_BACK_CORR, KID_BACK_DP, KID_FORCES, KID_COUNT
 };
 extern const char* const kKernelNames[KID_COUNT];
@@ -70,18 +70,16 @@ struct Scratch {
   int32_t* cell_cursor = nullptr; // [ncell + 1]
   int32_t* flag = nullptr;        // error flags written by kernels
   int32_t* cnt_bond = nullptr;    // [n + 1]
-  int32_t* cnt_hb = nullptr;      // [n + 1]
   int32_t* cnt_cand = nullptr;    // [n] bond candidates
-  // fixed-width wave-blocked staging of the sweep (see blk_index)
-  int32_t* cand_j = nullptr;      // bond candidates, width cand_w
-  int32_t* bond_t = nullptr;      // bonds, width bond_w
-  int32_t* hb_t = nullptr;        // H-list entries, width hb_w
-  int32_t cand_w = 0, bond_w = 0, hb_w = 0;
-  int64_t cap_cand = 0, cap_bondt = 0, cap_hbt = 0;
+  // fixed-width rows (one per atom) staging the sweep's bond candidates and bonds
+  int32_t* cand_j = nullptr;      // width cand_w
+  int32_t* bond_t = nullptr;      // width bond_w
+  int32_t cand_w = 0, bond_w = 0;
+  int64_t cap_cand = 0, cap_bondt = 0;
   int32_t* need = nullptr;        // device [4]: largest counts seen (far, cand, bond, hb)
   double* part = nullptr;         // bbox partials
-  int64_t* totals = nullptr;      // device [4]
-  int64_t* totals_host = nullptr; // pinned host [4]
+  int64_t* totals = nullptr;      // device [8]
+  int64_t* totals_host = nullptr; // pinned host [8]
   // scan temporaries
   int64_t* scan_tmp = nullptr;
   int64_t scan_cap = 0;
@@ -95,14 +93,14 @@ int launch_bbox(const double* pos, const int32_t* type, int64_t n, double* part,
                 int32_t* flag, Prof& pf, hipStream_t st);
 int launch_cell_sort(const double* pos, const int32_t* type, int64_t n, const Grid& g, int ncell,
                      Scratch& sc, Lists& L, Prof& pf, hipStream_t st);
-int launch_sweep(const DevParams* P, const Grid& g, int64_t n, Scratch& sc, Lists& L, Prof& pf,
-                 hipStream_t st);
+int launch_sweep(const DevParams* P, const Grid& g, int64_t n, int ncell, Scratch& sc, Lists& L,
+                 Prof& pf, hipStream_t st);
 int launch_compact(int64_t n, Scratch& sc, Lists& L, Prof& pf, hipStream_t st);
 int launch_export(const Lists& L, int32_t* far, int32_t* bonds, int32_t* hb, Scratch& sc,
                   hipStream_t st);
 
 int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, const double* q,
-                  double* forces, double* energies, Prof& pf, hipStream_t st);
+                  double* forces, double* energies, Scratch& sc, Prof& pf, hipStream_t st);
 int launch_kick(int64_t n, double* vel, const double* forces, const int32_t* type,
                 const DevParams* P, double half_dt, hipStream_t st);
 int launch_drift(int64_t n, double* pos, const double* vel, double dt, const Grid& g, hipStream_t st);

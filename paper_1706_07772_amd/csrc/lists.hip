@@ -124,14 +124,13 @@ __device__ __forceinline__ double bo_raw(const PairP& p, double r, double bo_cut
   return s + pi + pp;
 }
 
-// visit every atom slot in the cell stencil of cell (c0,c1,c2).  Cells are
-// numbered with z fastest, so the 5 cells of a stencil column (x, y, z-2..z+2)
-// are one contiguous range of sorted atoms (two when the column wraps).
-template <class F>
-__device__ __forceinline__ void for_stencil(const Grid& g, const int32_t* __restrict__ cstart,
-                                            int c0, int c1, int c2, F&& f) {
-  // z ranges of the column, as offsets within a row of cells
-  int za0, za1, zb0 = 0, zb1 = 0;   // [za0, za1) and [zb0, zb1) in cell units
+// z ranges of a stencil column around cell z = c2, in cell units within a
+// row: [za0, za1) and [zb0, zb1).  Cells are numbered with z fastest, so the
+// 5 cells of a column (x, y, c2-2..c2+2) are one contiguous range of sorted
+// atoms, or two when the column wraps around a periodic edge.
+__device__ __forceinline__ void column_ranges(const Grid& g, int c2, int& za0, int& za1, int& zb0,
+                                              int& zb1) {
+  zb0 = zb1 = 0;
   if (g.full[2]) {
     za0 = 0; za1 = g.nc[2];
   } else if (g.periodic) {
@@ -142,89 +141,177 @@ __device__ __forceinline__ void for_stencil(const Grid& g, const int32_t* __rest
     za0 = c2 - 2 < 0 ? 0 : c2 - 2;
     za1 = c2 + 3 > g.nc[2] ? g.nc[2] : c2 + 3;
   }
-  for (int a = 0; a < g.span[0]; ++a) {
-    int x = g.full[0] ? a : c0 + a - 2;
-    if (g.periodic) x = x < 0 ? x + g.nc[0] : (x >= g.nc[0] ? x - g.nc[0] : x);
-    else if (x < 0 || x >= g.nc[0]) continue;
-    for (int b = 0; b < g.span[1]; ++b) {
-      int y = g.full[1] ? b : c1 + b - 2;
-      if (g.periodic) y = y < 0 ? y + g.nc[1] : (y >= g.nc[1] ? y - g.nc[1] : y);
-      else if (y < 0 || y >= g.nc[1]) continue;
-      const int row = (x * g.nc[1] + y) * g.nc[2];
-      const int s0 = cstart[row + za0], s1 = cstart[row + za1];
-      for (int s = s0; s < s1; ++s) f(s);
-      if (zb1 > zb0) {
-        const int t0 = cstart[row + zb0], t1 = cstart[row + zb1];
-        for (int s = t0; s < t1; ++s) f(s);
+}
+
+// One wavefront per cell.  Every atom of a cell has the same 5x5x5 cell
+// stencil, so the wavefront loads each 64-candidate chunk of a stencil column
+// once (coalesced) and tests it against each atom of its cell in turn: the
+// cell's atoms live in the lanes and are broadcast one at a time.  Accepted
+// candidates of atom i are numbered with a ballot and written contiguously to
+// i's rows (far list, bond candidates inside the per-type bond reach, H list).
+// Entries beyond a row's width are counted but not written; the largest count
+// of each list is reported so the host can widen the rows and sweep again.
+constexpr int SWEEP_WAVES = 4;
+
+__global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
+    const DevParams* __restrict__ P, Grid g, int ncell, const double4* __restrict__ xs,
+    const int32_t* __restrict__ cstart, int32_t* __restrict__ far_cnt, int32_t* __restrict__ far_j,
+    int far_w, int32_t* __restrict__ cnt_cand, int32_t* __restrict__ cand_j, int cand_w,
+    int32_t* __restrict__ hb_cnt, int32_t* __restrict__ hb_j, int hb_w, int32_t* __restrict__ need,
+    unsigned long long* __restrict__ totals) {
+  __shared__ unsigned long long red[SWEEP_WAVES][2];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = blockIdx.x * SWEEP_WAVES + wv;
+  const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  unsigned long long tf = 0, th = 0;
+  int a0 = 0, m = 0;
+  if (c < ncell) {
+    a0 = cstart[c];
+    m = cstart[c + 1] - a0;
+  }
+  const double rn2 = P->rn2, rh2 = P->rh2;
+  const double rb2 = P->r_bond * P->r_bond;
+  int accmask = 0, donmask = 0;
+  for (int t = 0; t < NT; ++t) {
+    accmask |= (P->atom[t].hbond == 2) << t;
+    donmask |= (P->atom[t].hbond == 1) << t;
+  }
+  const int c2 = c % g.nc[2], c1 = (c / g.nc[2]) % g.nc[1], c0 = c / (g.nc[1] * g.nc[2]);
+  int za0, za1, zb0, zb1;
+  column_ranges(g, c2, za0, za1, zb0, zb1);
+  // image shift of the wrapped part of the z column
+  const double szb = c2 - 2 < 0 ? g.L[2] : -g.L[2];
+  for (int ig = 0; ig < m; ig += 64) {       // the cell's atoms, 64 at a time, one per lane
+    const int mi = m - ig < 64 ? m - ig : 64;
+    double4 xmine = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (lane < mi) xmine = xs[a0 + ig + lane];
+    int kf = 0, kc = 0, kh = 0;               // lane l: counts of the cell's atom l
+    auto chunk = [&](int s0, int s1, double sx, double sy, double sz) {
+      for (int base = s0; base < s1; base += 64) {
+        const int s = base + lane;
+        const bool valid = s < s1;
+        double4 xj = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (valid) xj = xs[s];
+        const int tj = (int)xj.w;
+        // bond reach of this candidate's type against each centre type
+        const double q0 = fmin(P->pair[0 * NT + tj].reach2, rb2), q1 = fmin(P->pair[1 * NT + tj].reach2, rb2),
+                     q2 = fmin(P->pair[2 * NT + tj].reach2, rb2), q3 = fmin(P->pair[3 * NT + tj].reach2, rb2);
+        const bool acc = (accmask >> tj) & 1;
+        for (int l = 0; l < mi; ++l) {
+          const int i = a0 + ig + l;
+          const double xix = readlane_d(xmine.x, l), xiy = readlane_d(xmine.y, l),
+                       xiz = readlane_d(xmine.z, l);
+          const int ti = (int)readlane_d(xmine.w, l);
+          double dx = xj.x - xix, dy = xj.y - xiy, dz = xj.z - xiz;
+          if (g.shift_ok) {
+            dx -= sx;
+            dy -= sy;
+            dz -= sz;
+          } else if (g.periodic) {
+            dx = min_image(dx, g.L[0], g.invL[0]);
+            dy = min_image(dy, g.L[1], g.invL[1]);
+            dz = min_image(dz, g.L[2], g.invL[2]);
+          }
+          const double r2 = r2_of(dx, dy, dz);
+          const bool f = valid && r2 <= rn2 && s != i;
+          const double qt = ti == 0 ? q0 : (ti == 1 ? q1 : (ti == 2 ? q2 : q3));
+          const bool b = f && r2 <= qt;
+          const bool h = f && acc && ((donmask >> ti) & 1) && r2 <= rh2;
+          const unsigned long long mf = __ballot(f);
+          if (mf) {
+            const unsigned long long mb = __ballot(b), mh = __ballot(h);
+            const int k0 = readlane_i(kf, l);
+            if (f) {
+              const int k = k0 + __popcll(mf & below);
+              if (k < far_w) far_j[(int64_t)i * far_w + k] = s;
+            }
+            kf = writelane_i(k0 + __popcll(mf), l, kf);
+            if (mb) {
+              const int k1 = readlane_i(kc, l);
+              if (b) {
+                const int k = k1 + __popcll(mb & below);
+                if (k < cand_w) cand_j[(int64_t)i * cand_w + k] = s;
+              }
+              kc = writelane_i(k1 + __popcll(mb), l, kc);
+            }
+            if (mh) {
+              const int k2 = readlane_i(kh, l);
+              if (h) {
+                const int k = k2 + __popcll(mh & below);
+                if (k < hb_w) hb_j[(int64_t)i * hb_w + k] = s;
+              }
+              kh = writelane_i(k2 + __popcll(mh), l, kh);
+            }
+          }
+        }
+      }
+    };
+    for (int a = 0; a < g.span[0]; ++a) {
+      int x = g.full[0] ? a : c0 + a - 2;
+      double sx = 0.0;
+      if (g.periodic) {
+        if (x < 0) { x += g.nc[0]; sx = g.L[0]; }
+        else if (x >= g.nc[0]) { x -= g.nc[0]; sx = -g.L[0]; }
+      } else if (x < 0 || x >= g.nc[0]) continue;
+      for (int bb = 0; bb < g.span[1]; ++bb) {
+        int y = g.full[1] ? bb : c1 + bb - 2;
+        double sy = 0.0;
+        if (g.periodic) {
+          if (y < 0) { y += g.nc[1]; sy = g.L[1]; }
+          else if (y >= g.nc[1]) { y -= g.nc[1]; sy = -g.L[1]; }
+        } else if (y < 0 || y >= g.nc[1]) continue;
+        const int row = (x * g.nc[1] + y) * g.nc[2];
+        chunk(cstart[row + za0], cstart[row + za1], sx, sy, 0.0);
+        if (zb1 > zb0) chunk(cstart[row + zb0], cstart[row + zb1], sx, sy, szb);
       }
     }
+    if (lane < mi) {
+      const int i = a0 + ig + lane;
+      far_cnt[i] = kf;
+      cnt_cand[i] = kc;
+      hb_cnt[i] = kh;
+      if (kf > far_w) atomicMax(&need[0], kf);
+      if (kc > cand_w) atomicMax(&need[1], kc);
+      if (kh > hb_w) atomicMax(&need[3], kh);
+      tf += (unsigned long long)kf;
+      th += (unsigned long long)kh;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    tf += __shfl_down(tf, off, 64);
+    th += __shfl_down(th, off, 64);
+  }
+  if (lane == 0) {
+    red[wv][0] = tf;
+    red[wv][1] = th;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    unsigned long long v = 0;
+    for (int w = 0; w < SWEEP_WAVES; ++w) v += red[w][threadIdx.x];
+    if (v) atomicAdd(&totals[threadIdx.x == 0 ? 0 : 4], v);
   }
 }
 
-// One thread per sorted atom, one sweep over its cell stencil.  The sweep
-// writes the far list directly (fixed-width blocked layout) and stages bond
-// candidates (pairs inside the per-type bond reach) and H-list entries; the
-// bond-order test of the candidates then runs as a dense loop per atom, so
-// the transcendental work is not paid by every lane of a wavefront whenever
-// one lane meets a candidate.  Counts beyond a width are still counted, and
-// the largest count of each list is reported so the host can grow the
-// buffers and sweep again.
-__global__ __launch_bounds__(256) void k_sweep(
+// bond-order test of each atom's staged candidates (one thread per atom):
+// a candidate is a bond iff its raw uncorrected bond order reaches bo_cut
+__global__ __launch_bounds__(256) void k_bondtest(
     const DevParams* __restrict__ P, Grid g, int64_t n, const double4* __restrict__ xs,
-    const int32_t* __restrict__ cell_s, const int32_t* __restrict__ cstart,
-    int32_t* __restrict__ far_cnt, int32_t* __restrict__ far_j, int far_w,
-    int32_t* __restrict__ cnt_cand, int32_t* __restrict__ cand_j, int cand_w,
+    const int32_t* __restrict__ cnt_cand, const int32_t* __restrict__ cand_j, int cand_w,
     int32_t* __restrict__ cnt_bond, int32_t* __restrict__ bond_t, int bond_w,
-    int32_t* __restrict__ cnt_hb, int32_t* __restrict__ hb_t, int hb_w,
-    int32_t* __restrict__ need, unsigned long long* __restrict__ far_total) {
+    int32_t* __restrict__ need, unsigned long long* __restrict__ totals) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  int nf = 0;
+  unsigned long long ba = 0, bt = 0, bd = 0;
   if (i < n) {
     const double4 xi = xs[i];
     const int ti = (int)xi.w;
-    const int c = cell_s[i];
-    const int c2 = c % g.nc[2], c1 = (c / g.nc[2]) % g.nc[1], c0 = c / (g.nc[1] * g.nc[2]);
-    const double rn2 = P->rn2, rh2 = P->rh2, bo_cut = P->bo_cut;
-    const double rb2 = P->r_bond * P->r_bond;
-    // bond prefilter of this atom's type against each partner type
-    const double q0 = fmin(P->pair[ti * NT + 0].reach2, rb2), q1 = fmin(P->pair[ti * NT + 1].reach2, rb2),
-                 q2 = fmin(P->pair[ti * NT + 2].reach2, rb2), q3 = fmin(P->pair[ti * NT + 3].reach2, rb2);
-    const double qmax = fmax(fmax(q0, q1), fmax(q2, q3));
-    int accmask = 0;
-    for (int t = 0; t < NT; ++t) accmask |= (P->atom[t].hbond == 2) << t;
-    const bool donor = P->atom[ti].hbond == 1;
-    int nc = 0, nh = 0;
-    for_stencil(g, cstart, c0, c1, c2, [&](int s) {
-      const double4 xj = xs[s];
-      double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
-      if (g.periodic) {
-        dx = min_image(dx, g.L[0], g.invL[0]);
-        dy = min_image(dy, g.L[1], g.invL[1]);
-        dz = min_image(dz, g.L[2], g.invL[2]);
-      }
-      const double r2 = r2_of(dx, dy, dz);
-      if (r2 <= rn2 && s != (int)i) {
-        if (nf < far_w) far_j[blk_index(i, nf, far_w)] = s;
-        ++nf;
-        const int tj = (int)xj.w;
-        if (r2 <= qmax) {
-          const double qt = tj == 0 ? q0 : (tj == 1 ? q1 : (tj == 2 ? q2 : q3));
-          if (r2 <= qt) {
-            if (nc < cand_w) cand_j[blk_index(i, nc, cand_w)] = s;
-            ++nc;
-          }
-        }
-        if (donor && r2 <= rh2 && ((accmask >> tj) & 1)) {
-          if (nh < hb_w) hb_t[blk_index(i, nh, hb_w)] = s;
-          ++nh;
-        }
-      }
-    });
-    // bond-order test of the staged candidates (kept in stencil order)
+    const double bo_cut = P->bo_cut;
+    const int nc = cnt_cand[i] < cand_w ? cnt_cand[i] : cand_w;
+    const int32_t* crow = cand_j + i * (int64_t)cand_w;
+    int32_t* brow = bond_t + i * (int64_t)bond_w;
     int nb = 0;
-    const int ncand = nc < cand_w ? nc : cand_w;
-    for (int k = 0; k < ncand; ++k) {
-      const int s = cand_j[blk_index(i, k, cand_w)];
+    for (int k = 0; k < nc; ++k) {
+      const int s = crow[k];
       const double4 xj = xs[s];
       double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
       if (g.periodic) {
@@ -234,37 +321,46 @@ __global__ __launch_bounds__(256) void k_sweep(
       }
       const double r2 = r2_of(dx, dy, dz);
       if (bo_raw(P->pair[ti * NT + (int)xj.w], sqrt(r2), bo_cut) >= bo_cut) {
-        if (nb < bond_w) bond_t[blk_index(i, nb, bond_w)] = s;
+        if (nb < bond_w) brow[nb] = s;
         ++nb;
       }
     }
-    far_cnt[i] = nf;
-    cnt_cand[i] = nc;
     cnt_bond[i] = nb;
-    cnt_hb[i] = nh;
-    if (nf > far_w) atomicMax(&need[0], nf);
-    if (nc > cand_w) atomicMax(&need[1], nc);
     if (nb > bond_w) atomicMax(&need[2], nb);
-    if (nh > hb_w) atomicMax(&need[3], nh);
+    // bounds of the interaction task lists built from this bond list:
+    // angles at i <= C(d,2); torsions about i's bonds <= ceil(d (d-1)^2 / 2)
+    // (the sum over bonds of (d_j-1)(d_k-1) is at most half the sum of
+    // squares); donor bonds <= d for an H atom
+    const unsigned long long d = (unsigned long long)nb;
+    ba = d * (d > 0 ? d - 1 : 0) / 2;
+    bt = (d * (d > 0 ? (d - 1) * (d - 1) : 0) + 1) / 2;
+    bd = P->atom[ti].hbond == 1 ? d : 0;
   }
-  // total far entries: wave sums, one atomic per wavefront
-  unsigned long long v = (unsigned long long)nf;
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  if ((threadIdx.x & 63) == 0 && v) atomicAdd(far_total, v);
+  for (int off = 32; off > 0; off >>= 1) {
+    ba += __shfl_down(ba, off, 64);
+    bt += __shfl_down(bt, off, 64);
+    bd += __shfl_down(bd, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (ba) atomicAdd(&totals[1], ba);
+    if (bt) atomicAdd(&totals[2], bt);
+    if (bd) atomicAdd(&totals[3], bd);
+  }
 }
 
-// staged (blocked) bond and H-list entries -> compressed rows
+// staged bond rows -> compressed rows, with the owner of each entry
 __global__ void k_compact(int64_t n, const int32_t* __restrict__ cnt_bond,
                           const int32_t* __restrict__ bond_t, int bond_w,
                           const int32_t* __restrict__ bond_off, int32_t* __restrict__ bond_j,
-                          const int32_t* __restrict__ cnt_hb, const int32_t* __restrict__ hb_t,
-                          int hb_w, const int32_t* __restrict__ hb_off, int32_t* __restrict__ hb_j) {
+                          int32_t* __restrict__ bond_i) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int ob = bond_off[i], nb = cnt_bond[i];
-  for (int k = 0; k < nb; ++k) bond_j[ob + k] = bond_t[blk_index(i, k, bond_w)];
-  const int oh = hb_off[i], nh = cnt_hb[i];
-  for (int k = 0; k < nh; ++k) hb_j[oh + k] = hb_t[blk_index(i, k, hb_w)];
+  const int32_t* row = bond_t + i * (int64_t)bond_w;
+  for (int k = 0; k < nb; ++k) {
+    bond_j[ob + k] = row[k];
+    bond_i[ob + k] = (int32_t)i;
+  }
 }
 
 // mirror entry: position of i in the bond list of j
@@ -288,7 +384,7 @@ __global__ void k_mirror(int64_t n, const int32_t* __restrict__ off, const int32
 }
 
 // export helpers: lists in caller indices
-// half far list from the full list: the entries with j > i, at per-atom
+// half far list from the full rows: the entries with j > i, at per-atom
 // offsets hoff (exclusive scan of the per-atom half counts)
 template <bool WRITE>
 __global__ void k_export_far(int64_t n, const int32_t* __restrict__ cnt, const int32_t* __restrict__ fj,
@@ -299,8 +395,9 @@ __global__ void k_export_far(int64_t n, const int32_t* __restrict__ cnt, const i
   int64_t o = WRITE ? hoff[i] : 0;
   int h = 0;
   const int pi = WRITE ? perm[i] : 0;
+  const int32_t* row = fj + i * (int64_t)far_w;
   for (int k = 0; k < cnt[i]; ++k) {
-    const int j = fj[blk_index(i, k, far_w)];
+    const int j = row[k];
     if (j > (int)i) {
       if (WRITE) {
         const int pj = perm[j];
@@ -322,6 +419,21 @@ __global__ void k_export_csr(int64_t n, const int32_t* __restrict__ off, const i
   for (int e = off[i]; e < off[i + 1]; ++e) {
     out[2 * (int64_t)e] = pi;
     out[2 * (int64_t)e + 1] = perm[bj[e]];
+  }
+}
+
+// H rows -> (h, z) pairs at offsets hoff
+__global__ void k_export_rows(int64_t n, const int32_t* __restrict__ cnt, const int32_t* __restrict__ rows,
+                              int w, const int64_t* __restrict__ off, const int32_t* __restrict__ perm,
+                              int32_t* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int pi = perm[i];
+  int64_t o = off[i];
+  for (int k = 0; k < cnt[i]; ++k) {
+    out[2 * o] = pi;
+    out[2 * o + 1] = perm[rows[i * (int64_t)w + k]];
+    ++o;
   }
 }
 
@@ -366,14 +478,19 @@ int launch_cell_sort(const double* pos, const int32_t* type, int64_t n, const Gr
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_sweep(const DevParams* P, const Grid& g, int64_t n, Scratch& sc, Lists& L, Prof& pf,
-                 hipStream_t st) {
+int launch_sweep(const DevParams* P, const Grid& g, int64_t n, int ncell, Scratch& sc, Lists& L,
+                 Prof& pf, hipStream_t st) {
   (void)hipMemsetAsync(sc.need, 0, sizeof(int32_t) * 4, st);
-  (void)hipMemsetAsync(sc.totals, 0, sizeof(int64_t) * 4, st);
+  (void)hipMemsetAsync(sc.totals, 0, sizeof(int64_t) * 8, st);
   pf.begin(KID_LIST_SWEEP, st);
-  hipLaunchKernelGGL(k_sweep, dim3(nblk(n, 256)), dim3(256), 0, st, P, g, n, L.xs, sc.cell_s,
-                     L.cell_start, L.far_cnt, L.far_j, L.far_w, sc.cnt_cand, sc.cand_j, sc.cand_w,
-                     sc.cnt_bond, sc.bond_t, sc.bond_w, sc.cnt_hb, sc.hb_t, sc.hb_w, sc.need,
+  hipLaunchKernelGGL(k_sweep, dim3(nblk(ncell, SWEEP_WAVES)), dim3(64 * SWEEP_WAVES), 0, st, P, g,
+                     ncell, L.xs, L.cell_start, L.far_cnt, L.far_j, L.far_w, sc.cnt_cand, sc.cand_j,
+                     sc.cand_w, L.hb_cnt, L.hb_j, L.hb_w, sc.need,
+                     reinterpret_cast<unsigned long long*>(sc.totals));
+  pf.end(st);
+  pf.begin(KID_BONDTEST, st);
+  hipLaunchKernelGGL(k_bondtest, dim3(nblk(n, 256)), dim3(256), 0, st, P, g, n, L.xs, sc.cnt_cand,
+                     sc.cand_j, sc.cand_w, sc.cnt_bond, sc.bond_t, sc.bond_w, sc.need,
                      reinterpret_cast<unsigned long long*>(sc.totals));
   pf.end(st);
   return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -382,7 +499,7 @@ int launch_sweep(const DevParams* P, const Grid& g, int64_t n, Scratch& sc, List
 int launch_compact(int64_t n, Scratch& sc, Lists& L, Prof& pf, hipStream_t st) {
   pf.begin(KID_COMPACT, st);
   hipLaunchKernelGGL(k_compact, dim3(nblk(n, 256)), dim3(256), 0, st, n, sc.cnt_bond, sc.bond_t,
-                     sc.bond_w, L.bond_off, L.bond_j, sc.cnt_hb, sc.hb_t, sc.hb_w, L.hb_off, L.hb_j);
+                     sc.bond_w, L.bond_off, L.bond_j, L.bond_i);
   pf.end(st);
   pf.begin(KID_MIRROR, st);
   hipLaunchKernelGGL(k_mirror, dim3(nblk(n, 256)), dim3(256), 0, st, n, L.bond_off, L.bond_j,
@@ -394,23 +511,32 @@ int launch_compact(int64_t n, Scratch& sc, Lists& L, Prof& pf, hipStream_t st) {
 int launch_export(const Lists& L, int32_t* far, int32_t* bonds, int32_t* hb, Scratch& sc,
                   hipStream_t st) {
   const int64_t n = L.n;
+  int32_t* hcnt = nullptr;
+  int64_t* hoff = nullptr;
+  if (hipMalloc(&hcnt, sizeof(int32_t) * (n + 1)) != hipSuccess) return -1;
+  if (hipMalloc(&hoff, sizeof(int64_t) * (n + 1)) != hipSuccess) return -1;
   if (far) {
-    int32_t* hcnt = nullptr;
-    int64_t* hoff = nullptr;
-    if (hipMalloc(&hcnt, sizeof(int32_t) * (n + 1)) != hipSuccess) return -1;
-    if (hipMalloc(&hoff, sizeof(int64_t) * (n + 1)) != hipSuccess) return -1;
     (void)hipMemsetAsync(hcnt + n, 0, sizeof(int32_t), st);
     hipLaunchKernelGGL(k_export_far<false>, dim3(nblk(n, 256)), dim3(256), 0, st, n, L.far_cnt,
                        L.far_j, L.far_w, L.perm, hcnt, nullptr, nullptr);
     scan_i32_to_i64(hcnt, hoff, n + 1, sc, st);
     hipLaunchKernelGGL(k_export_far<true>, dim3(nblk(n, 256)), dim3(256), 0, st, n, L.far_cnt,
                        L.far_j, L.far_w, L.perm, nullptr, hoff, far);
-    (void)hipStreamSynchronize(st);
-    (void)hipFree(hcnt);
-    (void)hipFree(hoff);
   }
-  if (bonds) hipLaunchKernelGGL(k_export_csr, dim3(nblk(n, 256)), dim3(256), 0, st, n, L.bond_off, L.bond_j, L.perm, bonds);
-  if (hb) hipLaunchKernelGGL(k_export_csr, dim3(nblk(n, 256)), dim3(256), 0, st, n, L.hb_off, L.hb_j, L.perm, hb);
+  if (bonds)
+    hipLaunchKernelGGL(k_export_csr, dim3(nblk(n, 256)), dim3(256), 0, st, n, L.bond_off, L.bond_j,
+                       L.perm, bonds);
+  if (hb) {
+    (void)hipStreamSynchronize(st);
+    (void)hipMemcpyAsync(hcnt, L.hb_cnt, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st);
+    (void)hipMemsetAsync(hcnt + n, 0, sizeof(int32_t), st);
+    scan_i32_to_i64(hcnt, hoff, n + 1, sc, st);
+    hipLaunchKernelGGL(k_export_rows, dim3(nblk(n, 256)), dim3(256), 0, st, n, L.hb_cnt, L.hb_j,
+                       L.hb_w, hoff, L.perm, hb);
+  }
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(hcnt);
+  (void)hipFree(hoff);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

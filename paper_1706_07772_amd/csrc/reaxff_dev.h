@@ -67,6 +67,11 @@ struct Grid {
   double lo[3];     // origin (0 for periodic)
   double L[3], invL[3];
   double invw[3];   // 1 / cell width
+  // 1 when every position lies in [0, L) and every dimension has at least 7
+  // cells: then any pair within r_nonb of a stencil column has the column's
+  // image shift as its minimum image, and d - shift is bit-identical to
+  // d - L rint(d / L)
+  int shift_ok;
 };
 
 // --- lists and work arrays (device pointers, owned by the context) -------
@@ -77,27 +82,26 @@ struct Lists {
   int32_t* type_s;      // sorted types
   double4* xs;          // sorted positions, w = type (as a double)
   int32_t* cell_start;  // [ncell + 1]
-  // far-neighbour list, full (both directions of every pair), wave-blocked
-  // with a fixed width far_w: entry k of atom i is stored at
-  // far_j[(i / 64) * 64 * far_w + 64 k + i % 64], so a wavefront reading its
-  // atoms' k-th entries touches one contiguous 256-byte segment
+  // far-neighbour list, full (both directions of every pair), one row of
+  // width far_w per atom: entry k of atom i is far_j[i * far_w + k].  A
+  // wavefront works on one atom, so it writes and reads a row contiguously.
   int32_t* far_cnt;     // [n]
   int32_t* far_j;
   int32_t far_w;
   // full bond list
   int32_t* bond_off;    // [n + 1]
   int32_t* bond_j;
+  int32_t* bond_i;      // owner atom of each entry
   int32_t* bond_mir;
-  // H list
-  int32_t* hb_off;      // [n + 1]
+  // H list, one row of width hb_w per atom (rows of non-H atoms are empty)
+  int32_t* hb_cnt;      // [n]
   int32_t* hb_j;
+  int32_t hb_w;
   int64_t nfar;         // unordered pairs (half the entries)
   int64_t nbond, nhb;
+  // upper bounds on the interaction task lists (from the bond degrees)
+  int64_t bound_ang, bound_tor, bound_don;
 };
-
-__device__ __forceinline__ int64_t blk_index(int64_t i, int64_t k, int w) {
-  return (i >> 6) * 64 * (int64_t)w + 64 * k + (i & 63);
-}
 
 // per-atom state of the bond-order stage
 struct AtomState {
@@ -105,7 +109,11 @@ struct AtomState {
   double dnlp;                  // d nlp / d S
   double SBO2, dSBO2;           // SBO2 and dSBO2/dSBO
   double prod, W, dW;           // prod_e exp(-BO^8), W = -Dang - p_val8 vlpadj, dW/dS
-  double pad[6];
+  // angle-centre factors: 1 - e^{-p_val10 (2 - SBO2)} and its SBO2 derivative,
+  // e^{p_val6 Dang}, penalty f9 and d f9/d Delta, coalition 1/(1+e^{p_coa2 Dang})
+  // and its Dang derivative
+  double th0f, dth0f, e6, f9, df9, fc, dfc;
+  double pad[3];
 };
 
 struct Work {
@@ -128,6 +136,17 @@ struct Work {
   double4* fnb;    // forces from nonbonded and hydrogen-bond Z terms (atomics)
   double4* xq;     // sorted positions with charge in w
   unsigned long long* counters;  // [0] angles [1] torsions [2] hbonds
+  // interaction task lists: per-owner counts, exclusive sums, flat tasks
+  int32_t* cnt_ang;  // [n + 1] valence angles centred on each atom
+  int32_t* cnt_tor;  // [n + 1] torsions whose central bond the atom owns (lower index)
+  int32_t* cnt_don;  // [n + 1] donor bonds H->X of each H atom
+  int32_t* off_ang;
+  int32_t* off_tor;
+  int32_t* off_don;
+  int2* ang;         // (entry j->i, entry j->k)
+  int4* tor;         // (entry j->k, entry j->i, entry k->l, unused)
+  int32_t* don;      // entry h->X
+  int64_t cap_ang, cap_tor, cap_don;
 };
 
 // ---------------------------------------------------------------------------
@@ -141,6 +160,19 @@ __device__ __forceinline__ double min_image(double d, double L, double invL) {
 #pragma clang fp contract(off)
   const double s = L * rint(d * invL);
   return d - s;
+}
+
+// broadcast lane l's value to the whole wavefront (l uniform)
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ int readlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+// lane l takes the (uniform) value v, the other lanes keep old
+__device__ __forceinline__ int writelane_i(int v, int l, int old) {
+  return (int)(threadIdx.x & 63) == l ? v : old;
 }
 
 __device__ __forceinline__ double r2_of(double dx, double dy, double dz) {
