@@ -25,25 +25,28 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_VALU_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
-# Kernel work models: FP64 floating-point operations per unit, counted from the
-# kernel's FP64 VALU instruction mix per unit of work (FMA = 2, add/mul/trans
-# and the rest = 1, per lane) -- see the design doc for how each figure was taken.
+# Kernel work models.  nonbonded: FP64 operations per pair evaluation of the
+# compiled inner loop (v_fma/v_fmac/v_div_fmas counted as 2, v_add, v_mul,
+# v_rcp, v_rsq as 1; compares, conversions and exponent manipulation not
+# counted), read from the gfx950 assembly of this library's own build.  Each
+# unordered far pair is evaluated from both of its atoms.
 WORK = {
-    "nonbonded": ("far_pairs", 276.0),
-    "torsions": ("torsions", 590.0),
-    "angles": ("angles", 420.0),
-    "hbonds": ("hbonds", 130.0),
-    "list_count": ("candidates", 12.0),
-    "list_fill": ("candidates", 12.0),
+    "nonbonded": ("pair_evaluations", 421.0),
 }
-# bytes per unit for HBM-bound kernels
-BYTES = {}
+
+# Measured HBM bytes per launch of a kernel (rocprofv3 FETCH_SIZE and
+# WRITE_SIZE, scaled by the same counters' reading for a 1 GiB device copy),
+# recorded in profiles/kernels_petn_1044000.md.  Valid only for the kernel
+# version they were taken on; set to None when the kernel changes.
+TRAFFIC = {
+    "nonbonded": 3.470e9,
+}
 
 PHASES = {
     "lists": ("bbox", "cell_hist", "scan", "cell_scatter", "cell_sort", "gather_sorted",
-              "list_sweep", "compact", "mirror"),
+              "list_sweep", "bondtest", "compact", "mirror"),
     "bonded": ("gather_q", "bo_prime", "delta_prime", "bo_corr", "atom_state", "atom_energy",
-               "angles", "torsions", "hbonds"),
+               "tasks", "angles", "torsions", "hbonds", "hb_acceptors"),
     "nonbonded": ("nonbonded",),
     "backward": ("back_s", "back_corr", "back_dp", "forces"),
 }
@@ -151,15 +154,14 @@ def main():
         avg_s = kernels[dom]["ms_avg"] * 1e-3
         if dom in WORK:
             unit, per = WORK[dom]
-            units = counts.get(unit)
-            if unit == "candidates":
-                units = None
+            units = 2 * counts["far_pairs"] if unit == "pair_evaluations" else counts.get(unit)
             if units:
                 flops = per * units / (kernels[dom]["launches"] / args.steps)
                 achieved = flops / avg_s / 1e12
                 roofline = {"kernel": dom, "bound": "alu", "achieved": achieved,
                             "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
-                            "frac": achieved / PEAK_FP64_VALU_TFLOPS, "traffic": None,
+                            "frac": achieved / PEAK_FP64_VALU_TFLOPS,
+                            "traffic": TRAFFIC.get(dom),
                             "units_per_launch": units, "unit_name": unit,
                             "flops_per_unit": per, "avg_ms": kernels[dom]["ms_avg"]}
         if roofline is None:

@@ -25,7 +25,7 @@ struct reaxff_ctx {
   bool built = false;
   double box[3] = {0, 0, 0};
   bool periodic = false;
-  int64_t cap_n = 0, cap_cell = 0, cap_far = 0, cap_bond = 0, cap_hb = 0, cap_part = 0;
+  int64_t cap_n = 0, cap_cell = 0, cap_far = 0, cap_bond = 0, cap_hb = 0, cap_ha = 0, cap_part = 0;
   std::string err;
 };
 
@@ -170,6 +170,7 @@ int alloc_atoms(reaxff_ctx* c, int64_t n) {
   int64_t tmp;
 #define G(ptr) do { tmp = c->cap_n; if (grow(c, ptr, tmp, need)) return REAXFF_ERR_HIP; cap = tmp; } while (0)
   G(c->L.perm); G(c->L.type_s); G(c->L.xs); G(c->L.far_cnt); G(c->L.bond_off); G(c->L.hb_cnt);
+  G(c->L.ha_cnt);
   G(c->sc.cid); G(c->sc.cell_s); G(c->sc.cnt_cand); G(c->sc.cnt_bond);
   G(c->W.dp); G(c->W.ast); G(c->W.gS); G(c->W.gSig); G(c->W.gSBO); G(c->W.gStot); G(c->W.gDp);
   G(c->W.fnb); G(c->W.xq); G(c->W.cnt_ang); G(c->W.cnt_tor); G(c->W.cnt_don); G(c->W.off_ang);
@@ -235,7 +236,7 @@ int reaxff_create(const reaxff_params* params, const reaxff_cutoffs* cutoffs, in
       hipMemcpy(c->dp, &c->hd, sizeof(DevParams), hipMemcpyHostToDevice) != hipSuccess ||
       hipMalloc(&c->sc.flag, sizeof(int32_t) * 4) != hipSuccess ||
       hipMalloc(&c->sc.totals, sizeof(int64_t) * 8) != hipSuccess ||
-      hipMalloc(&c->sc.need, sizeof(int32_t) * 4) != hipSuccess ||
+      hipMalloc(&c->sc.need, sizeof(int32_t) * 8) != hipSuccess ||
       hipHostMalloc(&c->sc.totals_host, sizeof(int64_t) * 8, hipHostMallocDefault) != hipSuccess ||
       hipMalloc(&c->W.counters, sizeof(unsigned long long) * 4) != hipSuccess) {
     reaxff_destroy(c);
@@ -251,6 +252,7 @@ void reaxff_destroy(reaxff_ctx* c) {
   (void)hipDeviceSynchronize();
   void* ptrs[] = {c->dp, c->L.perm, c->L.type_s, c->L.xs, c->L.cell_start, c->L.far_cnt,
                   c->L.far_j, c->L.bond_off, c->L.bond_j, c->L.bond_mir, c->L.hb_cnt, c->L.hb_j,
+                  c->L.ha_cnt, c->L.ha_j,
                   c->W.bd, c->W.bop, c->W.dbop, c->W.bo, c->W.gbo, c->W.gvec, c->W.gup, c->W.dp,
                   c->W.ast, c->W.gS, c->W.gSig, c->W.gSBO, c->W.gStot, c->W.gDp, c->W.fnb,
                   c->W.xq, c->W.counters, c->W.cnt_ang, c->W.cnt_tor, c->W.cnt_don,
@@ -339,11 +341,12 @@ int reaxff_build_lists(reaxff_ctx* c, int64_t n, const double* pos, const int32_
     };
     if (c->L.far_w == 0) c->L.far_w = est(c->cut.r_nonb);
     if (c->L.hb_w == 0) c->L.hb_w = est(c->cut.r_hb);
+    if (c->L.ha_w == 0) c->L.ha_w = est(c->cut.r_hb);
     if (c->sc.cand_w == 0) c->sc.cand_w = 32;
     if (c->sc.bond_w == 0) c->sc.bond_w = 16;
   }
   int64_t* th = c->sc.totals_host;
-  int32_t need[4] = {0, 0, 0, 0};
+  int32_t need[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int32_t t32[2] = {0, 0};
   for (int attempt = 0;; ++attempt) {
     const int64_t rows = std::max<int64_t>(n, 1);
@@ -360,6 +363,9 @@ int reaxff_build_lists(reaxff_ctx* c, int64_t n, const double* pos, const int32_
       t = c->cap_hb;
       if (grow(c, c->L.hb_j, t, rows * c->L.hb_w, 1.0)) return REAXFF_ERR_HIP;
       c->cap_hb = t;
+      t = c->cap_ha;
+      if (grow(c, c->L.ha_j, t, rows * c->L.ha_w, 1.0)) return REAXFF_ERR_HIP;
+      c->cap_ha = t;
     }
     if (n > 0 && launch_sweep(c->dp, c->grid, n, (int)ncell, c->sc, c->L, c->prof, st))
       return fail(c, REAXFF_ERR_HIP, "sweep launch failed");
@@ -387,6 +393,7 @@ int reaxff_build_lists(reaxff_ctx* c, int64_t n, const double* pos, const int32_
     widen(c->sc.cand_w, need[1]);
     widen(c->sc.bond_w, need[2]);
     widen(c->L.hb_w, need[3]);
+    widen(c->L.ha_w, need[4]);
     if (!again) break;
     if (attempt >= 3) return fail(c, REAXFF_ERR_CAPACITY, "list widths did not converge");
   }

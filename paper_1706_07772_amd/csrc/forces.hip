@@ -16,6 +16,8 @@
 // per entry and gathered through the mirror index.  Only the torsion terms
 // (which touch entries of both central atoms) and the hydrogen-bond acceptor
 // use atomic adds; the nonbonded pairs are evaluated from both sides instead.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace rx {
@@ -350,13 +352,41 @@ __global__ __launch_bounds__(BS) void k_atom_energy(const DevParams* __restrict_
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void atomic_add3(double4* p, double3 v) { atomic_add3(p, v.x, v.y, v.z); }
 
+// The tasks are ordered by centre atom and a centre's bond entries are
+// contiguous, so the 256 tasks of a block touch one contiguous range of
+// entries and centres.  Their adjoints are summed in LDS (FP64 LDS atomics),
+// then written once: plain stores for centres whose tasks all lie in this
+// block, global atomics for the first and last centre, which may share tasks
+// with the neighbouring blocks.  Entries or centres beyond the LDS capacity
+// go straight to global atomics.
+constexpr int ANG_CAPE = 512;   // bond entries per block held in LDS
+constexpr int ANG_CAPC = 256;   // centres per block held in LDS
+
 __global__ __launch_bounds__(BS) void k_angles(const DevParams* __restrict__ P, Lists L, Work W,
                                                double* __restrict__ energies) {
+  __shared__ double se[ANG_CAPE][5];   // gvec x, y, z, gbo.x, gbo.w per entry
+  __shared__ double sc[ANG_CAPC][2];   // gS, dE/dSBO2 per centre
+  __shared__ int range[4];
   const int64_t ntask = W.off_ang[L.n];
+  const int64_t T0 = (int64_t)blockIdx.x * BS;
+  if (T0 >= ntask) return;                          // uniform over the block
+  const int64_t T1 = T0 + BS < ntask ? T0 + BS : ntask;
+  if (threadIdx.x == 0) {
+    const int jf = L.bond_i[W.ang[T0].x], jl = L.bond_i[W.ang[T1 - 1].x];
+    range[0] = jf;
+    range[1] = jl;
+    range[2] = L.bond_off[jf];
+    range[3] = L.bond_off[jl + 1];
+  }
+  for (int k = threadIdx.x; k < ANG_CAPE; k += BS)
+    for (int c = 0; c < 5; ++c) se[k][c] = 0.0;
+  for (int k = threadIdx.x; k < ANG_CAPC; k += BS) sc[k][0] = sc[k][1] = 0.0;
+  __syncthreads();
+  const int jf = range[0], jl = range[1], E0 = range[2], E1 = range[3];
   const double thb = P->thb_cut;
   double eval = 0.0, epen = 0.0, ecoa = 0.0;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ntask;
-       t += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t t = T0 + threadIdx.x;
+  if (t < T1) {
     const int2 uv = W.ang[t];
     const int u = uv.x, v = uv.y;
     const int j = L.bond_i[u], i = L.bond_j[u], k = L.bond_j[v];
@@ -413,22 +443,69 @@ __global__ __launch_bounds__(BS) void k_angles(const DevParams* __restrict__ P, 
     const double gSk = Ec * (-2.0 * P->p_coa3 * (Sk - B2));
     gB1 += Ec * (2.0 * P->p_coa3 * (Si - B1) - 2.0 * P->p_coa4 * (B1 - 1.5));
     gB2 += Ec * (2.0 * P->p_coa3 * (Sk - B2) - 2.0 * P->p_coa4 * (B2 - 1.5));
-    eval += Ev;
-    epen += Ep;
-    ecoa += Ec;
+    eval = Ev;
+    epen = Ep;
+    ecoa = Ec;
     // geometry: dtheta/dc = -1/sin;  dE/dc = dE/dtheta * dtheta/dc = gdt / sin
     const double gc = gdt / sn;
     const double ca = c * il1 * il1, cb = c * il2 * il2, ab = il1 * il2;
-    atomic_add3(&W.gvec[u], gc * (rv.x * ab - ru.x * ca), gc * (rv.y * ab - ru.y * ca),
-                gc * (rv.z * ab - ru.z * ca));
-    atomic_add3(&W.gvec[v], gc * (ru.x * ab - rv.x * cb), gc * (ru.y * ab - rv.y * cb),
-                gc * (ru.z * ab - rv.z * cb));
-    atomicAdd(&W.gbo[u].x, gB1);
-    atomicAdd(&W.gbo[u].w, gSi);
-    atomicAdd(&W.gbo[v].x, gB2);
-    atomicAdd(&W.gbo[v].w, gSk);
-    atomicAdd(&W.gS[j], gS);
-    atomicAdd(&W.gSBO[j], gSBO2);
+    const double gu[5] = {gc * (rv.x * ab - ru.x * ca), gc * (rv.y * ab - ru.y * ca),
+                          gc * (rv.z * ab - ru.z * ca), gB1, gSi};
+    const double gv[5] = {gc * (ru.x * ab - rv.x * cb), gc * (ru.y * ab - rv.y * cb),
+                          gc * (ru.z * ab - rv.z * cb), gB2, gSk};
+    const int lu = u - E0, lv = v - E0, lj = j - jf;
+    if (lu < ANG_CAPE) {
+      for (int q = 0; q < 5; ++q) atomicAdd(&se[lu][q], gu[q]);
+    } else {
+      atomic_add3(&W.gvec[u], gu[0], gu[1], gu[2]);
+      atomicAdd(&W.gbo[u].x, gu[3]);
+      atomicAdd(&W.gbo[u].w, gu[4]);
+    }
+    if (lv < ANG_CAPE) {
+      for (int q = 0; q < 5; ++q) atomicAdd(&se[lv][q], gv[q]);
+    } else {
+      atomic_add3(&W.gvec[v], gv[0], gv[1], gv[2]);
+      atomicAdd(&W.gbo[v].x, gv[3]);
+      atomicAdd(&W.gbo[v].w, gv[4]);
+    }
+    if (lj < ANG_CAPC) {
+      atomicAdd(&sc[lj][0], gS);
+      atomicAdd(&sc[lj][1], gSBO2);
+    } else {
+      atomicAdd(&W.gS[j], gS);
+      atomicAdd(&W.gSBO[j], gSBO2);
+    }
+  }
+  __syncthreads();
+  // flush: entries of boundary centres with atomics, the rest with stores
+  const int Eb0 = L.bond_off[jf + 1];   // entries of jf end here
+  const int Eb1 = L.bond_off[jl];       // entries of jl start here
+  const int ne = E1 - E0 < ANG_CAPE ? E1 - E0 : ANG_CAPE;
+  for (int k = threadIdx.x; k < ne; k += BS) {
+    const int e = E0 + k;
+    const bool boundary = e < Eb0 || e >= Eb1;
+    double4* gv = &W.gvec[e];
+    if (boundary) {
+      if (se[k][0] != 0.0 || se[k][1] != 0.0 || se[k][2] != 0.0) atomic_add3(gv, se[k][0], se[k][1], se[k][2]);
+      if (se[k][3] != 0.0) atomicAdd(&W.gbo[e].x, se[k][3]);
+      if (se[k][4] != 0.0) atomicAdd(&W.gbo[e].w, se[k][4]);
+    } else {
+      // this block holds all of the entry's angle terms; the arrays were zeroed
+      *gv = make_double4(se[k][0], se[k][1], se[k][2], 0.0);
+      W.gbo[e].x += se[k][3];
+      W.gbo[e].w = se[k][4];
+    }
+  }
+  const int nc = jl - jf + 1 < ANG_CAPC ? jl - jf + 1 : ANG_CAPC;
+  for (int k = threadIdx.x; k < nc; k += BS) {
+    const int j = jf + k;
+    if (j == jf || j == jl) {
+      if (sc[k][0] != 0.0) atomicAdd(&W.gS[j], sc[k][0]);
+      if (sc[k][1] != 0.0) atomicAdd(&W.gSBO[j], sc[k][1]);
+    } else {
+      W.gS[j] += sc[k][0];
+      W.gSBO[j] = sc[k][1];
+    }
   }
   block_add<BS>(eval, energies + E_VAL);
   block_add<BS>(epen, energies + E_PEN);
@@ -543,8 +620,45 @@ __global__ __launch_bounds__(BS) void k_torsions(const DevParams* __restrict__ P
 }
 
 // ---------------------------------------------------------------------------
-// (8) hydrogen bonds: one thread per donor bond H-X, over the H's acceptors Z
+// (8) hydrogen bonds.  Each term X-H...Z moves three atoms.  The donor side
+//     (one thread per donor bond H-X, over H's acceptor row) sums the energy,
+//     the adjoints of the H-X bond entry and the force on H.  The acceptor
+//     side (one thread per acceptor Z, over the donors within r_hb found in
+//     Z's far row by the H list's own predicate) recomputes the term's
+//     gradient with respect to Z and keeps it in a register, so no force is
+//     scattered to acceptors.
 // ---------------------------------------------------------------------------
+struct HbTerm {
+  double E, dE_dbo;
+  double3 g_rx, g_rz;   // dE/d(x_X - x_h), dE/d(x_Z - x_h)
+};
+
+__device__ __forceinline__ HbTerm hb_term(const HbP& hp, double bo, double4 rx, double dx, double dy,
+                                          double dz) {
+  HbTerm o;
+  const double ilx = 1.0 / rx.w;
+  const double rz = sqrt(dx * dx + dy * dy + dz * dz);
+  const double ilz = 1.0 / rz;
+  const double c = (rx.x * dx + rx.y * dy + rx.z * dz) * ilx * ilz;
+  const double hc = 0.5 * (1.0 - c);
+  const double s4 = hc * hc;
+  const double ds4 = -hc;                 // d s4 / d c
+  const double eb = exp(-hp.p_hb2 * bo);
+  const double fbo = 1.0 - eb, dfbo = hp.p_hb2 * eb;
+  const double fr = exp(-hp.p_hb3 * (hp.r0hb * ilz + rz / hp.r0hb - 2.0));
+  const double dfr = fr * (-hp.p_hb3) * (-hp.r0hb * ilz * ilz + 1.0 / hp.r0hb);
+  o.E = hp.p_hb1 * fbo * fr * s4;
+  o.dE_dbo = hp.p_hb1 * dfbo * fr * s4;
+  const double gc = hp.p_hb1 * fbo * fr * ds4;
+  const double grz = hp.p_hb1 * fbo * dfr * s4;
+  o.g_rx = make_double3(gc * (dx * ilx * ilz - c * rx.x * ilx * ilx), gc * (dy * ilx * ilz - c * rx.y * ilx * ilx),
+                        gc * (dz * ilx * ilz - c * rx.z * ilx * ilx));
+  o.g_rz = make_double3(gc * (rx.x * ilx * ilz - c * dx * ilz * ilz) + grz * dx * ilz,
+                        gc * (rx.y * ilx * ilz - c * dy * ilz * ilz) + grz * dy * ilz,
+                        gc * (rx.z * ilx * ilz - c * dz * ilz * ilz) + grz * dz * ilz);
+  return o;
+}
+
 __global__ __launch_bounds__(BS) void k_hbonds(const DevParams* __restrict__ P, Grid g, Lists L, Work W,
                                                double* __restrict__ energies) {
   const int64_t ntask = W.off_don[L.n];
@@ -558,20 +672,14 @@ __global__ __launch_bounds__(BS) void k_hbonds(const DevParams* __restrict__ P, 
     const double4 xh = L.xs[h];
     const double bo = W.bo[ex].x;
     const double4 rx = W.bd[ex];     // x_X - x_h
-    const double ilx = 1.0 / rx.w;
     double gbo = 0.0;
     double3 gx = make_double3(0.0, 0.0, 0.0), fh = make_double3(0.0, 0.0, 0.0);
     const int nz = L.hb_cnt[h];
     const int32_t* __restrict__ zrow = L.hb_j + (int64_t)h * L.hb_w;
-    // 1 - e^{-p_hb2 BO} depends on the acceptor's type only through p_hb2:
-    // evaluate it once for the first acceptor type met
-    const int tz0 = nz > 0 ? L.type_s[zrow[0] == X && nz > 1 ? zrow[1] : zrow[0]] : 0;
-    const double eb0 = exp(-P->hb[(tx * NT + th) * NT + tz0].p_hb2 * bo);
     for (int s = 0; s < nz; ++s) {
       const int Z = zrow[s];
       if (Z == X) continue;
-      const int tz = L.type_s[Z];
-      const HbP& hp = P->hb[(tx * NT + th) * NT + tz];
+      const HbP& hp = P->hb[(tx * NT + th) * NT + L.type_s[Z]];
       ++nhb;
       const double4 xz = L.xs[Z];
       double dx = xz.x - xh.x, dy = xz.y - xh.y, dz = xz.z - xh.z;
@@ -580,32 +688,11 @@ __global__ __launch_bounds__(BS) void k_hbonds(const DevParams* __restrict__ P, 
         dy = min_image(dy, g.L[1], g.invL[1]);
         dz = min_image(dz, g.L[2], g.invL[2]);
       }
-      const double rz = sqrt(dx * dx + dy * dy + dz * dz);
-      const double ilz = 1.0 / rz;
-      const double c = (rx.x * dx + rx.y * dy + rx.z * dz) * ilx * ilz;
-      const double hc = 0.5 * (1.0 - c);
-      const double s4 = hc * hc;
-      const double ds4 = -hc;                 // d s4 / d c
-      const double eb = tz == tz0 ? eb0 : exp(-hp.p_hb2 * bo);
-      const double fbo = 1.0 - eb, dfbo = hp.p_hb2 * eb;
-      const double fr = exp(-hp.p_hb3 * (hp.r0hb * ilz + rz / hp.r0hb - 2.0));
-      const double dfr = fr * (-hp.p_hb3) * (-hp.r0hb * ilz * ilz + 1.0 / hp.r0hb);
-      ehb += hp.p_hb1 * fbo * fr * s4;
-      gbo += hp.p_hb1 * dfbo * fr * s4;
-      const double gc = hp.p_hb1 * fbo * fr * ds4;
-      const double grz = hp.p_hb1 * fbo * dfr * s4;
-      // dE/d r_hX
-      gx.x += gc * (dx * ilx * ilz - c * rx.x * ilx * ilx);
-      gx.y += gc * (dy * ilx * ilz - c * rx.y * ilx * ilx);
-      gx.z += gc * (dz * ilx * ilz - c * rx.z * ilx * ilx);
-      // dE/d r_hZ
-      const double gzx = gc * (rx.x * ilx * ilz - c * dx * ilz * ilz) + grz * dx * ilz;
-      const double gzy = gc * (rx.y * ilx * ilz - c * dy * ilz * ilz) + grz * dy * ilz;
-      const double gzz = gc * (rx.z * ilx * ilz - c * dz * ilz * ilz) + grz * dz * ilz;
-      fh.x += gzx;
-      fh.y += gzy;
-      fh.z += gzz;
-      atomic_add3(&W.fnb[Z], -gzx, -gzy, -gzz);
+      const HbTerm o = hb_term(hp, bo, rx, dx, dy, dz);
+      ehb += o.E;
+      gbo += o.dE_dbo;
+      gx = add3(gx, o.g_rx);
+      fh = add3(fh, o.g_rz);            // r_hZ = x_Z - x_h: F_h = +dE/dr_hZ
     }
     // the entry h->X belongs to this task alone
     double4 gv = W.gvec[ex];
@@ -619,6 +706,47 @@ __global__ __launch_bounds__(BS) void k_hbonds(const DevParams* __restrict__ P, 
   block_add<BS>(ehb, energies + E_HB);
   for (int off = 32; off > 0; off >>= 1) nhb += __shfl_down(nhb, off, 64);
   if ((threadIdx.x & 63) == 0 && nhb) atomicAdd(&W.counters[2], nhb);
+}
+
+// acceptor side: F_Z = -dE/dx_Z = -sum dE/d(x_Z - x_h), over Z's donor row
+__global__ __launch_bounds__(BS) void k_hb_acceptors(const DevParams* __restrict__ P, Grid g, Lists L,
+                                                     Work W) {
+  const int64_t z = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (z >= L.n) return;
+  const int cnt = L.ha_cnt[z];
+  if (cnt == 0) return;
+  const int tz = L.type_s[z];
+  const double4 xz = L.xs[z];
+  const int32_t* __restrict__ row = L.ha_j + z * (int64_t)L.ha_w;
+  double3 fz = make_double3(0.0, 0.0, 0.0);
+  for (int k = 0; k < cnt; ++k) {
+    const int h = row[k];
+    const int t0 = W.off_don[h], t1 = W.off_don[h + 1];
+    if (t0 == t1) continue;
+    const int th = L.type_s[h];
+    const double4 xh = L.xs[h];
+    double dx = xz.x - xh.x, dy = xz.y - xh.y, dz = xz.z - xh.z;   // x_Z - x_h
+    if (g.periodic) {
+      dx = min_image(dx, g.L[0], g.invL[0]);
+      dy = min_image(dy, g.L[1], g.invL[1]);
+      dz = min_image(dz, g.L[2], g.invL[2]);
+    }
+    for (int t = t0; t < t1; ++t) {
+      const int ex = W.don[t];
+      const int X = L.bond_j[ex];
+      if (X == (int)z) continue;
+      const HbP& hp = P->hb[(L.type_s[X] * NT + th) * NT + tz];
+      const HbTerm o = hb_term(hp, W.bo[ex].x, W.bd[ex], dx, dy, dz);
+      fz.x -= o.g_rz.x;
+      fz.y -= o.g_rz.y;
+      fz.z -= o.g_rz.z;
+    }
+  }
+  double4 f = W.fnb[z];
+  f.x += fz.x;
+  f.y += fz.y;
+  f.z += fz.z;
+  W.fnb[z] = f;
 }
 
 // ---------------------------------------------------------------------------
@@ -821,7 +949,7 @@ __global__ void k_gather_q(const double* __restrict__ q, const int32_t* __restri
 const char* const kKernelNames[KID_COUNT] = {
     "bbox", "cell_hist", "cell_scatter", "cell_sort", "gather_sorted", "list_sweep", "scan",
     "bondtest", "compact", "mirror", "zero", "gather_q", "bo_prime", "delta_prime", "bo_corr", "atom_state",
-    "atom_energy", "tasks", "angles", "torsions", "hbonds", "nonbonded", "back_s", "back_corr",
+    "atom_energy", "tasks", "angles", "torsions", "hbonds", "hb_acceptors", "nonbonded", "back_s", "back_corr",
     "back_dp", "forces"};
 
 // grid of a grid-stride task kernel: enough blocks to fill the chip, no more
@@ -871,10 +999,12 @@ int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, co
   scan_i32(W.cnt_don, W.off_don, n + 1, sc, st);
   pf.end(st);
   LAUNCH(KID_TASKS, k_tasks<true>, grid, blk, 0, st, P, L, W);
-  const dim3 ga(task_grid(L.bound_ang)), gt(task_grid(L.bound_tor)), gd(task_grid(L.bound_don));
-  LAUNCH(KID_ANGLES, k_angles, ga, blk, 0, st, P, L, W, energies);
+  const dim3 gt(task_grid(L.bound_tor)), gd(task_grid(L.bound_don));
+  LAUNCH(KID_ANGLES, k_angles, dim3((unsigned)std::max<int64_t>((L.bound_ang + BS - 1) / BS, 1)), blk, 0,
+         st, P, L, W, energies);
   LAUNCH(KID_TORSIONS, k_torsions, gt, blk, 0, st, P, L, W, energies);
   LAUNCH(KID_HBONDS, k_hbonds, gd, blk, 0, st, P, g, L, W, energies);
+  LAUNCH(KID_HB_ACC, k_hb_acceptors, grid, blk, 0, st, P, g, L, W);
   (void)hipMemcpyAsync(W.counters, W.off_ang + n, sizeof(int32_t), hipMemcpyDeviceToDevice, st);
   (void)hipMemcpyAsync(W.counters + 1, W.off_tor + n, sizeof(int32_t), hipMemcpyDeviceToDevice, st);
   LAUNCH(KID_BACK_S, k_back_s, grid, blk, 0, st, L, W);

@@ -157,7 +157,8 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
     const DevParams* __restrict__ P, Grid g, int ncell, const double4* __restrict__ xs,
     const int32_t* __restrict__ cstart, int32_t* __restrict__ far_cnt, int32_t* __restrict__ far_j,
     int far_w, int32_t* __restrict__ cnt_cand, int32_t* __restrict__ cand_j, int cand_w,
-    int32_t* __restrict__ hb_cnt, int32_t* __restrict__ hb_j, int hb_w, int32_t* __restrict__ need,
+    int32_t* __restrict__ hb_cnt, int32_t* __restrict__ hb_j, int hb_w,
+    int32_t* __restrict__ ha_cnt, int32_t* __restrict__ ha_j, int ha_w, int32_t* __restrict__ need,
     unsigned long long* __restrict__ totals) {
   __shared__ unsigned long long red[SWEEP_WAVES][2];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -185,7 +186,7 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
     const int mi = m - ig < 64 ? m - ig : 64;
     double4 xmine = make_double4(0.0, 0.0, 0.0, 0.0);
     if (lane < mi) xmine = xs[a0 + ig + lane];
-    int kf = 0, kc = 0, kh = 0;               // lane l: counts of the cell's atom l
+    int kf = 0, kc = 0, kh = 0, ka = 0;       // lane l: counts of the cell's atom l
     auto chunk = [&](int s0, int s1, double sx, double sy, double sz) {
       for (int base = s0; base < s1; base += 64) {
         const int s = base + lane;
@@ -196,7 +197,7 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
         // bond reach of this candidate's type against each centre type
         const double q0 = fmin(P->pair[0 * NT + tj].reach2, rb2), q1 = fmin(P->pair[1 * NT + tj].reach2, rb2),
                      q2 = fmin(P->pair[2 * NT + tj].reach2, rb2), q3 = fmin(P->pair[3 * NT + tj].reach2, rb2);
-        const bool acc = (accmask >> tj) & 1;
+        const bool acc = (accmask >> tj) & 1, don = (donmask >> tj) & 1;
         for (int l = 0; l < mi; ++l) {
           const int i = a0 + ig + l;
           const double xix = readlane_d(xmine.x, l), xiy = readlane_d(xmine.y, l),
@@ -217,9 +218,10 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
           const double qt = ti == 0 ? q0 : (ti == 1 ? q1 : (ti == 2 ? q2 : q3));
           const bool b = f && r2 <= qt;
           const bool h = f && acc && ((donmask >> ti) & 1) && r2 <= rh2;
+          const bool ha = f && don && ((accmask >> ti) & 1) && r2 <= rh2;
           const unsigned long long mf = __ballot(f);
           if (mf) {
-            const unsigned long long mb = __ballot(b), mh = __ballot(h);
+            const unsigned long long mb = __ballot(b), mh = __ballot(h), ma = __ballot(ha);
             const int k0 = readlane_i(kf, l);
             if (f) {
               const int k = k0 + __popcll(mf & below);
@@ -241,6 +243,14 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
                 if (k < hb_w) hb_j[(int64_t)i * hb_w + k] = s;
               }
               kh = writelane_i(k2 + __popcll(mh), l, kh);
+            }
+            if (ma) {
+              const int k3 = readlane_i(ka, l);
+              if (ha) {
+                const int k = k3 + __popcll(ma & below);
+                if (k < ha_w) ha_j[(int64_t)i * ha_w + k] = s;
+              }
+              ka = writelane_i(k3 + __popcll(ma), l, ka);
             }
           }
         }
@@ -270,6 +280,8 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
       far_cnt[i] = kf;
       cnt_cand[i] = kc;
       hb_cnt[i] = kh;
+      ha_cnt[i] = ka;
+      if (ka > ha_w) atomicMax(&need[4], ka);
       if (kf > far_w) atomicMax(&need[0], kf);
       if (kc > cand_w) atomicMax(&need[1], kc);
       if (kh > hb_w) atomicMax(&need[3], kh);
@@ -480,12 +492,12 @@ int launch_cell_sort(const double* pos, const int32_t* type, int64_t n, const Gr
 
 int launch_sweep(const DevParams* P, const Grid& g, int64_t n, int ncell, Scratch& sc, Lists& L,
                  Prof& pf, hipStream_t st) {
-  (void)hipMemsetAsync(sc.need, 0, sizeof(int32_t) * 4, st);
+  (void)hipMemsetAsync(sc.need, 0, sizeof(int32_t) * 8, st);
   (void)hipMemsetAsync(sc.totals, 0, sizeof(int64_t) * 8, st);
   pf.begin(KID_LIST_SWEEP, st);
   hipLaunchKernelGGL(k_sweep, dim3(nblk(ncell, SWEEP_WAVES)), dim3(64 * SWEEP_WAVES), 0, st, P, g,
                      ncell, L.xs, L.cell_start, L.far_cnt, L.far_j, L.far_w, sc.cnt_cand, sc.cand_j,
-                     sc.cand_w, L.hb_cnt, L.hb_j, L.hb_w, sc.need,
+                     sc.cand_w, L.hb_cnt, L.hb_j, L.hb_w, L.ha_cnt, L.ha_j, L.ha_w, sc.need,
                      reinterpret_cast<unsigned long long*>(sc.totals));
   pf.end(st);
   pf.begin(KID_BONDTEST, st);

@@ -97,6 +97,11 @@ struct Lists {
   int32_t* hb_cnt;      // [n]
   int32_t* hb_j;
   int32_t hb_w;
+  // the same relation seen from the acceptor: donors H within r_hb of each
+  // acceptor (rows of non-acceptors are empty)
+  int32_t* ha_cnt;      // [n]
+  int32_t* ha_j;
+  int32_t ha_w;
   int64_t nfar;         // unordered pairs (half the entries)
   int64_t nbond, nhb;
   // upper bounds on the interaction task lists (from the bond degrees)
