@@ -163,6 +163,89 @@ int reaxff_profile(reaxff_ctx* ctx, int32_t enable);
 int reaxff_profile_read(reaxff_ctx* ctx, int32_t max, double* ms, int64_t* launches,
                         const char** names);
 
+/* ---- Batched evaluation of many small non-periodic systems ---------------
+ *
+ * Force-field fitting and cluster screening evaluate thousands of small,
+ * independent, unevenly sized systems: the small-system regime that the
+ * paper's closing discussion leaves to a serial code.  A batch plan fixes the
+ * cluster sizes; each compute call then evaluates every cluster in ONE
+ * persistent kernel launch replayed from a HIP graph.  Every workgroup takes
+ * whole clusters, one at a time, and runs the complete force evaluation of a
+ * cluster (bond list, bond orders, every energy term of reaxff_compute_forces,
+ * forces) with the cluster's atoms and nonbonded/H-bond forces in LDS and its
+ * bond-entry arrays in a private slice of device scratch.  Clusters are
+ * non-periodic; the far-neighbour and H-bond relations are tested in place
+ * (all pairs within the cluster, same predicates as the lists of
+ * reaxff_build_lists) instead of being stored.
+ */
+#define REAXFF_BATCH_MAX_ATOMS 384   /* atoms per cluster (LDS-resident) */
+
+enum {
+  REAXFF_SCHED_STATIC = 0,   /* clusters dealt round-robin in the given order */
+  REAXFF_SCHED_LPT = 1,      /* longest-processing-time-first greedy assignment
+                                (cost model: n^2 per cluster) */
+  REAXFF_SCHED_DYNAMIC = 2   /* atomic work queue over clusters sorted by
+                                decreasing size */
+};
+
+typedef struct reaxff_batch_config {
+  int32_t block;      /* threads per workgroup: 64, 128, 256 or 512 */
+  int32_t schedule;   /* REAXFF_SCHED_* */
+  int32_t wg_per_cu;  /* persistent workgroups per compute unit, 1..16 */
+} reaxff_batch_config;
+
+typedef struct reaxff_batch reaxff_batch;
+
+/* Plan a batch of `nclusters` clusters; cluster c holds atoms
+ * offsets[c] .. offsets[c+1]-1 of the concatenated arrays.  offsets [host]
+ * (nclusters+1), offsets[0] = 0, non-decreasing, every cluster at most
+ * REAXFF_BATCH_MAX_ATOMS atoms (else REAXFF_ERR_ARG).  cfg NULL: the
+ * configuration autotuned earlier in this context for the same multiset of
+ * cluster sizes, else {256, LPT, 4}.  The plan allocates its device scratch
+ * here (one slice per persistent workgroup) and uses the context's
+ * parameters and cutoffs.  The context must outlive the plan. */
+int reaxff_batch_create(reaxff_ctx* ctx, int32_t nclusters, const int64_t* offsets,
+                        const reaxff_batch_config* cfg, reaxff_batch** out);
+void reaxff_batch_destroy(reaxff_batch* b);
+int reaxff_batch_set_config(reaxff_batch* b, const reaxff_batch_config* cfg);
+int reaxff_batch_get_config(const reaxff_batch* b, reaxff_batch_config* cfg);
+
+/* Evaluate every cluster: pos [dev] (N,3), type [dev] (N), q [dev] (N) over
+ * the N = offsets[nclusters] concatenated atoms; forces [dev] (N,3) and
+ * energies [dev] (nclusters, REAXFF_NTERMS) are overwritten.  One graph
+ * launch on `stream`, no host synchronisation; the graph is captured again
+ * only when a pointer or the configuration changes.  A cluster that fails
+ * (type outside 0..3, more bond entries than its scratch slice holds) gets
+ * NaN energies and forces; reaxff_batch_status reports it. */
+int reaxff_batch_compute(reaxff_batch* b, const double* pos, const int32_t* type,
+                         const double* q, double* forces, double* energies,
+                         hipStream_t stream);
+
+/* Wait for the last compute and report: REAXFF_OK, REAXFF_ERR_ARG (a bad
+ * type) or REAXFF_ERR_CAPACITY (bond entries beyond the scratch slice; the
+ * next compute grows the slices to fit and recaptures).  *first_bad (may be
+ * NULL) receives the lowest failing cluster index or -1. */
+int reaxff_batch_status(reaxff_batch* b, int32_t* first_bad);
+
+/* Per-cluster interaction counts of the last compute [host]
+ * (nclusters, 5): valence angles, torsions, hydrogen bonds, far pairs
+ * (unordered, r <= r_nonb), bonds (undirected).  Synchronises. */
+int reaxff_batch_counts(reaxff_batch* b, int64_t* counts);
+
+/* Autotuner: times every configuration of block {64,128,256,512} x
+ * schedule {STATIC, LPT, DYNAMIC} x wg_per_cu {1,2,4,8} (at most max_trials
+ * of them, in that order; max_trials <= 0: all 48) by `reps` graph replays
+ * each on `stream` (events around the replays, one untimed replay first),
+ * selects the fastest, makes it the plan's configuration and caches it in
+ * the context for reaxff_batch_create.  trials/trial_ms [host] (may be
+ * NULL) receive each configuration and its mean milliseconds per launch;
+ * *ntrials their number.  The buffers' contents after tuning are those of
+ * the last replay. */
+int reaxff_batch_tune(reaxff_batch* b, const double* pos, const int32_t* type,
+                      const double* q, double* forces, double* energies,
+                      hipStream_t stream, int32_t reps, int32_t max_trials,
+                      reaxff_batch_config* trials, double* trial_ms, int32_t* ntrials);
+
 const char* reaxff_strerror(int code);
 const char* reaxff_last_error(const reaxff_ctx* ctx);
 

@@ -4,4 +4,5 @@ The compute path is the HIP library libreaxff_hip.so behind the C ABI in
 include/reaxff.h; this package holds its sources (csrc/), its build script
 and a thin ctypes binding.
 """
-from .binding import NTERMS, TERM_NAMES, ReaxFF, ReaxFFError, load_library  # noqa: F401
+from .binding import (BATCH_MAX_ATOMS, NTERMS, SCHEDULES, TERM_NAMES, Batch, ReaxFF,  # noqa: F401
+                      ReaxFFError, load_library)

@@ -49,6 +49,18 @@ class CCutoffs(ctypes.Structure):
                                   "hb_bo_cut")]
 
 
+class BatchConfig(ctypes.Structure):
+    """reaxff_batch_config: threads per workgroup, schedule, workgroups per CU."""
+    _fields_ = [("block", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("wg_per_cu", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (int(self.block), int(self.schedule), int(self.wg_per_cu))
+
+
+SCHEDULES = {0: "static", 1: "lpt", 2: "dynamic"}
+BATCH_MAX_ATOMS = 384
+
 _lib = None
 
 
@@ -71,6 +83,17 @@ def load_library():
     lib.reaxff_list_sizes.argtypes = [vp, ctypes.POINTER(i64)]
     lib.reaxff_export_lists.argtypes = [vp, vp, vp, vp]
     lib.reaxff_interaction_counts.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.reaxff_batch_create.argtypes = [vp, i32, vp, vp, ctypes.POINTER(vp)]
+    lib.reaxff_batch_destroy.argtypes = [vp]
+    lib.reaxff_batch_set_config.argtypes = [vp, ctypes.POINTER(BatchConfig)]
+    lib.reaxff_batch_get_config.argtypes = [vp, ctypes.POINTER(BatchConfig)]
+    lib.reaxff_batch_compute.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.reaxff_batch_status.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.reaxff_batch_counts.argtypes = [vp, vp]
+    lib.reaxff_batch_tune.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, i32, vp, vp,
+                                      ctypes.POINTER(i32)]
+    lib.reaxff_profile.argtypes = [vp, i32]
+    lib.reaxff_profile_read.argtypes = [vp, i32, vp, vp, vp]
     lib.reaxff_last_error.restype = ctypes.c_char_p
     lib.reaxff_last_error.argtypes = [vp]
     lib.reaxff_strerror.restype = ctypes.c_char_p
@@ -210,3 +233,107 @@ class ReaxFF:
         c = (ctypes.c_int64 * 5)()
         self._check(self._lib.reaxff_interaction_counts(self._h, c))
         return dict(zip(("angles", "torsions", "hbonds", "far_pairs", "bonds"), (int(x) for x in c)))
+
+
+class Batch:
+    """A batch plan over many small non-periodic clusters (reaxff_batch_*).
+
+    offsets: int64 (nclusters+1,) host array; cluster c holds atoms
+    offsets[c]:offsets[c+1] of the concatenated position/type/charge arrays.
+    """
+
+    def __init__(self, ff: ReaxFF, offsets, config=None):
+        self._ff = ff
+        self._lib = ff._lib
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        self.offsets = off
+        self.nclusters = off.size - 1
+        self.natoms = int(off[-1])
+        h = ctypes.c_void_p()
+        cfg = None
+        if config is not None:
+            cfg = BatchConfig(*config)
+        rc = self._lib.reaxff_batch_create(ff._h, self.nclusters, off.ctypes.data,
+                                           ctypes.byref(cfg) if cfg is not None else None,
+                                           ctypes.byref(h))
+        ff._check(rc)
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.reaxff_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def config(self):
+        c = BatchConfig()
+        self._ff._check(self._lib.reaxff_batch_get_config(self._h, ctypes.byref(c)))
+        return c.as_tuple()
+
+    @config.setter
+    def config(self, value):
+        c = BatchConfig(*value)
+        self._ff._check(self._lib.reaxff_batch_set_config(self._h, ctypes.byref(c)))
+
+    def _bufs(self, pos, forces, energies):
+        n = self.natoms
+        if forces is None:
+            forces = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+        if energies is None:
+            energies = torch.empty((self.nclusters, NTERMS), dtype=torch.float64, device=pos.device)
+        return forces, energies
+
+    def _check_inputs(self, pos, type_, q, forces, energies):
+        n = self.natoms
+        assert pos.dtype == torch.float64 and pos.is_cuda and pos.is_contiguous() and pos.shape == (n, 3)
+        assert type_.dtype == torch.int32 and type_.is_cuda and type_.is_contiguous() and type_.shape == (n,)
+        assert q.dtype == torch.float64 and q.is_cuda and q.is_contiguous() and q.shape == (n,)
+        assert forces.dtype == torch.float64 and forces.is_contiguous() and forces.shape == (n, 3)
+        assert energies.dtype == torch.float64 and energies.is_contiguous()
+        assert energies.shape == (self.nclusters, NTERMS)
+
+    def compute(self, pos, type_, q, forces=None, energies=None):
+        """reaxff_batch_compute -> (forces (N,3), energies (nclusters,12)) float64 cuda."""
+        forces, energies = self._bufs(pos, forces, energies)
+        self._check_inputs(pos, type_, q, forces, energies)
+        self._ff._check(self._lib.reaxff_batch_compute(self._h, _ptr(pos), _ptr(type_), _ptr(q),
+                                                       _ptr(forces), _ptr(energies), _stream()))
+        return forces, energies
+
+    def status(self):
+        """(return code, first failing cluster or -1); waits for the last compute."""
+        fb = ctypes.c_int32(-1)
+        rc = self._lib.reaxff_batch_status(self._h, ctypes.byref(fb))
+        return int(rc), int(fb.value)
+
+    def check(self):
+        rc, fb = self.status()
+        if rc != 0:
+            raise ReaxFFError(rc, self._lib.reaxff_last_error(self._ff._h).decode())
+
+    def counts(self):
+        """(nclusters, 5) int64: angles, torsions, hbonds, far pairs, bonds per cluster."""
+        c = np.zeros((self.nclusters, 5), dtype=np.int64)
+        self._ff._check(self._lib.reaxff_batch_counts(self._h, c.ctypes.data))
+        return c
+
+    def tune(self, pos, type_, q, forces=None, energies=None, reps: int = 3, max_trials: int = 0):
+        """reaxff_batch_tune: returns [(config, ms per launch)] of every trial; the fastest
+        becomes the plan's configuration."""
+        forces, energies = self._bufs(pos, forces, energies)
+        self._check_inputs(pos, type_, q, forces, energies)
+        cap = 64
+        trials = (BatchConfig * cap)()
+        ms = (ctypes.c_double * cap)()
+        nt = ctypes.c_int32(0)
+        self._ff._check(self._lib.reaxff_batch_tune(self._h, _ptr(pos), _ptr(type_), _ptr(q),
+                                                    _ptr(forces), _ptr(energies), _stream(),
+                                                    int(reps), int(max_trials), trials, ms,
+                                                    ctypes.byref(nt)))
+        return [(trials[k].as_tuple(), float(ms[k])) for k in range(nt.value)]

@@ -13,7 +13,7 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-munsafe-fp-atomics",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wno-unused-result", "-Wno-unused-value",
+    "-Wno-unused-result", "-Wno-unused-value", "-Wno-pass-failed",
 ]
 
 

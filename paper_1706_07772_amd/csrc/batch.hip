@@ -1,0 +1,1074 @@
+// Batched ReaxFF: thousands of small non-periodic clusters in one persistent
+// launch replayed from a HIP graph.
+//
+// One workgroup evaluates one cluster at a time, stage by stage, with a
+// workgroup barrier between stages: the same stages and the same arithmetic
+// (terms.h) as the one-launch-per-stage path, with
+//   * the cluster's atoms (x, y, z, q), types, bond-row offsets and the
+//     nonbonded/H-bond force accumulators in LDS;
+//   * the bond list built as the paper builds its lists (Section 3.3): count
+//     per atom, prefix sum, fill, here inside the workgroup;
+//   * far-neighbour and H-bond relations tested in place over all pairs of
+//     the cluster (same predicates as the stored lists of the large path);
+//   * the per-entry and per-atom work arrays in a private slice of device
+//     scratch per persistent workgroup (L2-resident while it works).
+// Clusters come from a per-workgroup list (static or longest-processing-
+// time-first) or from an atomic queue, chosen by the autotuner.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <numeric>
+#include <queue>
+
+#include "internal.h"
+#include "terms.h"
+
+using namespace rx;
+
+namespace rx {
+
+constexpr int BNMAX = REAXFF_BATCH_MAX_ATOMS;
+constexpr int NCOUNT = 5;   // angles, torsions, hbonds, far pairs, bonds
+
+// status bits of a cluster
+constexpr int ST_CAPACITY = 1, ST_TYPE = 2;
+
+// byte offsets of the arrays inside one workgroup's scratch slice
+struct BatchLayout {
+  int64_t ast, dp, gS, gSig, gSBO, gStot, gDp;    // per atom (nmax)
+  int64_t bj, bi, bm;                             // per entry (ecap), int32
+  int64_t bd, bop, dbop, bo, gbo, gvec, gup;      // per entry, double4
+  int64_t stride;
+};
+
+static BatchLayout make_layout(int nmax, int ecap) {
+  BatchLayout y{};
+  int64_t o = 0;
+  auto take = [&](int64_t bytes) {
+    const int64_t at = o;
+    o += (bytes + 255) & ~int64_t(255);
+    return at;
+  };
+  y.ast = take(sizeof(AtomState) * (int64_t)nmax);
+  y.dp = take(sizeof(double2) * (int64_t)nmax);
+  y.gS = take(sizeof(double) * (int64_t)nmax);
+  y.gSig = take(sizeof(double) * (int64_t)nmax);
+  y.gSBO = take(sizeof(double) * (int64_t)nmax);
+  y.gStot = take(sizeof(double) * (int64_t)nmax);
+  y.gDp = take(sizeof(double) * (int64_t)nmax);
+  y.bj = take(sizeof(int32_t) * (int64_t)ecap);
+  y.bi = take(sizeof(int32_t) * (int64_t)ecap);
+  y.bm = take(sizeof(int32_t) * (int64_t)ecap);
+  y.bd = take(sizeof(double4) * (int64_t)ecap);
+  y.bop = take(sizeof(double4) * (int64_t)ecap);
+  y.dbop = take(sizeof(double4) * (int64_t)ecap);
+  y.bo = take(sizeof(double4) * (int64_t)ecap);
+  y.gbo = take(sizeof(double4) * (int64_t)ecap);
+  y.gvec = take(sizeof(double4) * (int64_t)ecap);
+  y.gup = take(sizeof(double4) * (int64_t)ecap);
+  y.stride = o;
+  return y;
+}
+
+struct BatchArgs {
+  const DevParams* P;
+  int32_t ncl;
+  int32_t dynamic;           // 1: clusters from the queue, in `order`
+  const int64_t* off;        // [ncl + 1] atom offsets
+  const int32_t* order;      // cluster order (grouped per workgroup for static schedules)
+  const int32_t* wg_first;   // [G + 1] static schedules: workgroup b takes order[wg_first[b] ..)
+  int32_t* queue;            // [1] next position in `order` (dynamic)
+  const double* pos;
+  const int32_t* type;
+  const double* q;
+  double* forces;
+  double* energies;          // [ncl][NTERMS]
+  long long* counts;         // [ncl][NCOUNT]
+  int32_t* status;           // [ncl]
+  int32_t* err;              // [0] OR of statuses, [1] largest entry count, [2] lowest bad cluster
+  char* scratch;
+  BatchLayout lay;
+  int32_t ecap;
+};
+
+__global__ void k_batch_reset(int32_t* queue, int32_t* err) {
+  if (threadIdx.x == 0) {
+    queue[0] = 0;
+    err[0] = 0;
+    err[1] = 0;
+    err[2] = INT_MAX;
+  }
+}
+
+// inclusive prefix sum of v[1..n] in place (v[0] = 0), by the first wavefront
+__device__ __forceinline__ void wave_scan_inplace(int32_t* v, int n) {
+  if (threadIdx.x >= 64) return;
+  const int lane = threadIdx.x;
+  int carry = 0;
+  for (int base = 1; base <= n; base += 64) {
+    const int k = base + lane;
+    int x = k <= n ? v[k] : 0;
+    for (int d = 1; d < 64; d <<= 1) {
+      const int y = __shfl_up(x, d, 64);
+      if (lane >= d) x += y;
+    }
+    x += carry;
+    if (k <= n) v[k] = x;
+    carry = __shfl(x, 63, 64);
+  }
+}
+
+// wavefront sum of v added to an LDS accumulator (one LDS atomic per wave)
+__device__ __forceinline__ void wave_acc(double v, double* acc) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((threadIdx.x & 63) == 0 && v != 0.0) atomicAdd(acc, v);
+}
+
+// LDS of the workgroup's current cluster
+constexpr int NRED = NTERMS + NCOUNT;
+__shared__ double4 b_x[BNMAX];        // x, y, z, q
+__shared__ int32_t b_ty[BNMAX];
+__shared__ int32_t b_off[BNMAX + 1];  // bond rows
+__shared__ double4 b_f[BNMAX];        // nonbonded + H-bond forces
+__shared__ NbP b_nb[NT * NT];
+__shared__ double b_acc[NRED];        // per-cluster energies and counts
+__shared__ int32_t b_next;
+
+// The kernel's argument block, copied to LDS once per workgroup.  A stage
+// function reads it back with readfirstlane, so its fields and every pointer
+// derived from them are wave-uniform (scalar registers) inside the stage.
+__shared__ BatchArgs b_args;
+
+template <class T>
+__device__ __forceinline__ T uni_copy(const T& src) {
+  static_assert(sizeof(T) % 4 == 0, "copied as 32-bit words");
+  T out;
+  const int* s = reinterpret_cast<const int*>(&src);
+  int* d = reinterpret_cast<int*>(&out);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) d[k] = __builtin_amdgcn_readfirstlane(s[k]);
+  return out;
+}
+
+// values the caller holds uniformly across the wavefront, made scalar again
+// after the call boundary (arguments of called functions arrive in vector
+// registers)
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)v);
+  const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+  return ((int64_t)hi << 32) | (uint32_t)lo;
+}
+
+// views of this workgroup's scratch slice, with atoms and forces in LDS
+__device__ __forceinline__ void views(const BatchArgs& A, Lists& L, Work& W) {
+  char* base = A.scratch + (int64_t)blockIdx.x * A.lay.stride;
+  L = Lists{};
+  W = Work{};
+  L.xs = b_x;
+  L.type_s = b_ty;
+  L.bond_off = b_off;
+  L.bond_j = reinterpret_cast<int32_t*>(base + A.lay.bj);
+  L.bond_i = reinterpret_cast<int32_t*>(base + A.lay.bi);
+  L.bond_mir = reinterpret_cast<int32_t*>(base + A.lay.bm);
+  W.ast = reinterpret_cast<AtomState*>(base + A.lay.ast);
+  W.dp = reinterpret_cast<double2*>(base + A.lay.dp);
+  W.gS = reinterpret_cast<double*>(base + A.lay.gS);
+  W.gSig = reinterpret_cast<double*>(base + A.lay.gSig);
+  W.gSBO = reinterpret_cast<double*>(base + A.lay.gSBO);
+  W.gStot = reinterpret_cast<double*>(base + A.lay.gStot);
+  W.gDp = reinterpret_cast<double*>(base + A.lay.gDp);
+  W.bd = reinterpret_cast<double4*>(base + A.lay.bd);
+  W.bop = reinterpret_cast<double4*>(base + A.lay.bop);
+  W.dbop = reinterpret_cast<double4*>(base + A.lay.dbop);
+  W.bo = reinterpret_cast<double4*>(base + A.lay.bo);
+  W.gbo = reinterpret_cast<double4*>(base + A.lay.gbo);
+  W.gvec = reinterpret_cast<double4*>(base + A.lay.gvec);
+  W.gup = reinterpret_cast<double4*>(base + A.lay.gup);
+  W.fnb = b_f;
+}
+
+// Each stage is a separate (not inlined) function so that it gets its own
+// register allocation: the kernel's register count is the largest stage's,
+// not the union over all stages.
+
+// load the cluster; returns nonzero on a bad type
+template <int BSZ>
+__device__ __noinline__ int st_load(int64_t a0, int n) {
+  const BatchArgs A = uni_copy(b_args);
+  a0 = uni64(a0);
+  n = uni(n);
+  Lists L;
+  Work W;
+  views(A, L, W);
+  const int tid = threadIdx.x;
+  if (tid < NRED) b_acc[tid] = 0.0;
+  int bad = 0;
+  for (int i = tid; i < n; i += BSZ) {
+    int t = A.type[a0 + i];
+    if (t < 0 || t >= NT) {
+      bad = 1;
+      t = 0;
+    }
+    b_x[i] = make_double4(A.pos[3 * (a0 + i)], A.pos[3 * (a0 + i) + 1], A.pos[3 * (a0 + i) + 2], A.q[a0 + i]);
+    b_ty[i] = t;
+    b_f[i] = make_double4(0.0, 0.0, 0.0, 0.0);
+    W.gSBO[i] = 0.0;
+  }
+  return bad;
+}
+
+// a failed cluster: NaN outputs and its status
+template <int BSZ>
+__device__ __noinline__ void st_fail(int c, int64_t a0, int n, int code, int nent) {
+  const BatchArgs A = uni_copy(b_args);
+  c = uni(c);
+  a0 = uni64(a0);
+  n = uni(n);
+  code = uni(code);
+  nent = uni(nent);
+  const int tid = threadIdx.x;
+  const double nan = __longlong_as_double(0x7ff8000000000000LL);
+  for (int i = tid; i < 3 * n; i += BSZ) A.forces[3 * a0 + i] = nan;
+  if (tid < NTERMS) A.energies[(int64_t)c * NTERMS + tid] = nan;
+  if (tid == 0) {
+    A.status[c] = code;
+    atomicOr(&A.err[0], code);
+    if (code == ST_CAPACITY) atomicMax(&A.err[1], nent);
+    atomicMin(&A.err[2], c);
+  }
+}
+
+// bond rows: count per atom (and far pairs, for the counts)
+template <int BSZ>
+__device__ __noinline__ void st_count(int n) {
+  const BatchArgs A = uni_copy(b_args);
+  n = uni(n);
+  const DevParams* __restrict__ P = A.P;
+  const double rn2 = P->rn2, rb2 = P->r_bond * P->r_bond, bo_cut = P->bo_cut;
+  const int tid = threadIdx.x;
+  double nfar = 0.0;
+  for (int i = tid; i < n; i += BSZ) {
+    const double4 xi = b_x[i];
+    const int ti = b_ty[i];
+    int nb = 0;
+    for (int j = 0; j < n; ++j) {
+      if (j == i) continue;
+      const double4 xj = b_x[j];
+      const double r2 = r2_of(xj.x - xi.x, xj.y - xi.y, xj.z - xi.z);
+      if (j > i && r2 <= rn2) nfar += 1.0;
+      const PairP& p = P->pair[ti * NT + b_ty[j]];
+      if (r2 <= fmin(p.reach2, rb2) && bo_raw(p, sqrt(r2), bo_cut) >= bo_cut) ++nb;
+    }
+    b_off[i + 1] = nb;
+  }
+  if (tid == 0) b_off[0] = 0;
+  wave_acc(nfar, &b_acc[NTERMS + 3]);
+}
+
+// bond rows: fill (same predicate, same order) and clear the entry adjoints
+template <int BSZ>
+__device__ __noinline__ void st_fill(int n) {
+  const BatchArgs A = uni_copy(b_args);
+  n = uni(n);
+  Lists L;
+  Work W;
+  views(A, L, W);
+  const DevParams* __restrict__ P = A.P;
+  const double rb2 = P->r_bond * P->r_bond, bo_cut = P->bo_cut;
+  for (int i = threadIdx.x; i < n; i += BSZ) {
+    const double4 xi = b_x[i];
+    const int ti = b_ty[i];
+    int e = b_off[i];
+    const int e1 = b_off[i + 1];
+    for (int j = 0; j < n && e < e1; ++j) {
+      if (j == i) continue;
+      const double4 xj = b_x[j];
+      const double r2 = r2_of(xj.x - xi.x, xj.y - xi.y, xj.z - xi.z);
+      const PairP& p = P->pair[ti * NT + b_ty[j]];
+      if (r2 <= fmin(p.reach2, rb2) && bo_raw(p, sqrt(r2), bo_cut) >= bo_cut) {
+        L.bond_j[e] = j;
+        L.bond_i[e] = i;
+        W.gbo[e] = make_double4(0.0, 0.0, 0.0, 0.0);
+        W.gvec[e] = make_double4(0.0, 0.0, 0.0, 0.0);
+        ++e;
+      }
+    }
+  }
+}
+
+// mirror entries and uncorrected bond orders
+template <int BSZ>
+__device__ __noinline__ void st_bo_prime(int n) {
+  const BatchArgs A = uni_copy(b_args);
+  n = uni(n);
+  Lists L;
+  Work W;
+  views(A, L, W);
+  Grid g{};
+  g.periodic = 0;
+  for (int i = threadIdx.x; i < n; i += BSZ) {
+    for (int e = b_off[i]; e < b_off[i + 1]; ++e) {
+      const int j = L.bond_j[e];
+      int m = e;
+      for (int f = b_off[j]; f < b_off[j + 1]; ++f)
+        if (L.bond_j[f] == i) m = f;
+      L.bond_mir[e] = m;
+    }
+    bo_prime_atom(A.P, g, L, W, i);
+  }
+}
+
+template <int BSZ>
+__device__ __noinline__ void st_delta_prime(int n) {
+  const BatchArgs A = uni_copy(b_args);
+  n = uni(n);
+  Lists L;
+  Work W;
+  views(A, L, W);
+  for (int i = threadIdx.x; i < n; i += BSZ) delta_prime_atom(A.P, L, W, i);
+}
+
+template <int BSZ>
+__device__ __noinline__ void st_bo_corr(int n) {
+  const BatchArgs A = uni_copy(b_args);
+  n = uni(n);
+  Lists L;
+  Work W;
+  views(A, L, W);
+  for (int i = threadIdx.x; i < n; i += BSZ) bo_corr_atom(A.P, L, W, i);
+}
+
+template <int BSZ>
+__device__ __noinline__ void st_atom_state(int n) {
+  const BatchArgs A = uni_copy(b_args);
+  n = uni(n);
+  Lists L;
+  Work W;
+  views(A, L, W);
+  for (int i = threadIdx.x; i < n; i += BSZ) atom_state_atom(A.P, L, W, i);
+}
+
+// per atom: bond, lone-pair, over- and under-coordination energies
+template <int BSZ>
+__device__ __noinline__ void st_atom_energy(int n) {
+  const BatchArgs A = uni_copy(b_args);
+  n = uni(n);
+  Lists L;
+  Work W;
+  views(A, L, W);
+  double e4[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int j = threadIdx.x; j < n; j += BSZ) atom_energy_atom(A.P, L, W, j, e4);
+  for (int k = 0; k < 4; ++k) wave_acc(e4[k], &b_acc[E_BOND + k]);
+}
+
+// valence angles centred on each atom (one thread owns all of the centre's
+// entries, so no atomics)
+template <int BSZ>
+__device__ __noinline__ void st_angles(int n) {
+  const BatchArgs A = uni_copy(b_args);
+  n = uni(n);
+  Lists L;
+  Work W;
+  views(A, L, W);
+  const DevParams* __restrict__ P = A.P;
+  const double thb = P->thb_cut, thb2 = P->thb_cutsq;
+  double ev = 0.0, ep = 0.0, ec = 0.0, nang = 0.0;
+  for (int j = threadIdx.x; j < n; j += BSZ) {
+    const int e0 = b_off[j], e1 = b_off[j + 1];
+    double gS = 0.0, gSBO2 = 0.0;
+    for (int u = e0; u < e1; ++u) {
+      const double bu = W.bo[u].x;
+      if (!(bu - thb > 0.0)) continue;
+      for (int v = u + 1; v < e1; ++v) {
+        const double bv = W.bo[v].x;
+        if (!(bv - thb > 0.0 && bu * bv > thb2)) continue;
+        const AngOut o = angle_eval(P, L, W, u, v);
+        ev += o.ev;
+        ep += o.ep;
+        ec += o.ec;
+        nang += 1.0;
+        double4 gu = W.gvec[u], gv = W.gvec[v];
+        gu.x += o.gu[0]; gu.y += o.gu[1]; gu.z += o.gu[2];
+        gv.x += o.gv[0]; gv.y += o.gv[1]; gv.z += o.gv[2];
+        W.gvec[u] = gu;
+        W.gvec[v] = gv;
+        W.gbo[u].x += o.gu[3];
+        W.gbo[u].w += o.gu[4];
+        W.gbo[v].x += o.gv[3];
+        W.gbo[v].w += o.gv[4];
+        gS += o.gS;
+        gSBO2 += o.gSBO2;
+      }
+    }
+    W.gS[j] += gS;
+    W.gSBO[j] = gSBO2;
+  }
+  wave_acc(ev, &b_acc[E_VAL]);
+  wave_acc(ep, &b_acc[E_PEN]);
+  wave_acc(ec, &b_acc[E_COA]);
+  wave_acc(nang, &b_acc[NTERMS + 0]);
+}
+
+// nonbonded: one wavefront per atom, one partner per lane, every pair from
+// both sides (no force scatter), half energy weight per visit
+template <int BSZ>
+__device__ __noinline__ void st_nonbonded(int n) {
+  const BatchArgs A = uni_copy(b_args);
+  n = uni(n);
+  const DevParams* __restrict__ P = A.P;
+  const double rn2 = P->rn2, iR = P->inv_r_nonb, pv = P->p_vdW1, ipv = P->inv_p_vdW1;
+  constexpr int NW = BSZ / 64;
+  const int lane = threadIdx.x & 63;
+  double ev = 0.0, eq = 0.0;
+  for (int i = threadIdx.x >> 6; i < n; i += NW) {
+    const double4 xi = b_x[i];
+    const double qi = xi.w * C_ELE;
+    const NbP* __restrict__ spi = b_nb + b_ty[i] * NT;
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    for (int j = lane; j < n; j += 64) {
+      if (j == i) continue;
+      const double4 xj = b_x[j];
+      const double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
+      const double r2 = r2_of(dx, dy, dz);
+      if (!(r2 <= rn2)) continue;
+      const NbOut o = nb_pair(spi[b_ty[j]], iR, pv, ipv, qi * xj.w, r2);
+      ev += o.ev;
+      eq += o.eq;
+      fx += o.f * dx;
+      fy += o.f * dy;
+      fz += o.f * dz;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      fx += __shfl_down(fx, off, 64);
+      fy += __shfl_down(fy, off, 64);
+      fz += __shfl_down(fz, off, 64);
+    }
+    if (lane == 0) b_f[i] = make_double4(fx, fy, fz, 0.0);
+  }
+  wave_acc(0.5 * ev, &b_acc[E_VDW]);
+  wave_acc(0.5 * eq, &b_acc[E_COUL]);
+}
+
+// torsions about the bonds each atom owns (lower index), with atomic adds
+template <int BSZ>
+__device__ __noinline__ void st_torsions(int n) {
+  const BatchArgs A = uni_copy(b_args);
+  n = uni(n);
+  Lists L;
+  Work W;
+  views(A, L, W);
+  const DevParams* __restrict__ P = A.P;
+  const double thb = P->thb_cut;
+  double etor = 0.0, econj = 0.0, ntor = 0.0;
+  for (int j = threadIdx.x; j < n; j += BSZ) {
+    const int e0 = b_off[j], e1 = b_off[j + 1];
+    for (int u = e0; u < e1; ++u) {
+      const int k = L.bond_j[u];
+      const double bu = W.bo[u].x;
+      if (!(k > j && bu > thb)) continue;
+      const int f0 = b_off[k], f1 = b_off[k + 1];
+      for (int a = e0; a < e1; ++a) {
+        if (a == u) continue;
+        const double ba = W.bo[a].x;
+        if (!(ba > thb)) continue;
+        const int i = L.bond_j[a];
+        for (int b = f0; b < f1; ++b) {
+          const int l = L.bond_j[b];
+          if (l == j || l == i) continue;
+          const double bb = W.bo[b].x;
+          if (!(bb > thb)) continue;
+          if (!(ba * bu * bb > thb)) continue;
+          torsion_eval(P, L, W, u, a, b, etor, econj);
+          ntor += 1.0;
+        }
+      }
+    }
+  }
+  wave_acc(etor, &b_acc[E_TOR]);
+  wave_acc(econj, &b_acc[E_CONJ]);
+  wave_acc(ntor, &b_acc[NTERMS + 1]);
+}
+
+// hydrogen bonds of each H atom over the acceptors of the cluster within
+// r_hb; acceptor forces and the donor entry's adjoints with atomic adds
+template <int BSZ>
+__device__ __noinline__ void st_hbonds(int n) {
+  const BatchArgs A = uni_copy(b_args);
+  n = uni(n);
+  Lists L;
+  Work W;
+  views(A, L, W);
+  const DevParams* __restrict__ P = A.P;
+  const double rh2 = P->rh2, hb_bo_cut = P->hb_bo_cut;
+  double ehb = 0.0, nhb = 0.0;
+  for (int h = threadIdx.x; h < n; h += BSZ) {
+    const int th = b_ty[h];
+    if (P->atom[th].hbond != 1) continue;
+    const double4 xh = b_x[h];
+    double3 fh = make_double3(0.0, 0.0, 0.0);
+    for (int u = b_off[h]; u < b_off[h + 1]; ++u) {
+      const int X = L.bond_j[u];
+      const int tx = b_ty[X];
+      const double bo = W.bo[u].x;
+      if (P->atom[tx].hbond != 2 || !(bo >= hb_bo_cut)) continue;
+      const double4 rx = W.bd[u];
+      double gbo = 0.0;
+      double3 gx = make_double3(0.0, 0.0, 0.0);
+      for (int Z = 0; Z < n; ++Z) {
+        if (Z == X) continue;
+        const int tz = b_ty[Z];
+        if (P->atom[tz].hbond != 2) continue;
+        const double4 xz = b_x[Z];
+        const double dx = xz.x - xh.x, dy = xz.y - xh.y, dz = xz.z - xh.z;
+        if (!(r2_of(dx, dy, dz) <= rh2)) continue;
+        const HbTerm o = hb_term(P->hb[(tx * NT + th) * NT + tz], bo, rx, dx, dy, dz);
+        ehb += o.E;
+        gbo += o.dE_dbo;
+        gx = add3(gx, o.g_rx);
+        fh = add3(fh, o.g_rz);
+        atomic_add3(&b_f[Z], -o.g_rz.x, -o.g_rz.y, -o.g_rz.z);
+        nhb += 1.0;
+      }
+      atomic_add3(&W.gvec[u], gx);
+      atomicAdd(&W.gbo[u].x, gbo);
+    }
+    atomic_add3(&b_f[h], fh);
+  }
+  wave_acc(ehb, &b_acc[E_HB]);
+  wave_acc(nhb, &b_acc[NTERMS + 2]);
+}
+
+template <int BSZ>
+__device__ __noinline__ void st_back_s(int n) {
+  const BatchArgs A = uni_copy(b_args);
+  n = uni(n);
+  Lists L;
+  Work W;
+  views(A, L, W);
+  for (int i = threadIdx.x; i < n; i += BSZ) back_s_atom(L, W, i);
+}
+
+template <int BSZ>
+__device__ __noinline__ void st_back_corr(int n) {
+  const BatchArgs A = uni_copy(b_args);
+  n = uni(n);
+  Lists L;
+  Work W;
+  views(A, L, W);
+  for (int i = threadIdx.x; i < n; i += BSZ) back_corr_atom(A.P, L, W, i);
+}
+
+template <int BSZ>
+__device__ __noinline__ void st_back_dp(int n) {
+  const BatchArgs A = uni_copy(b_args);
+  n = uni(n);
+  Lists L;
+  Work W;
+  views(A, L, W);
+  for (int i = threadIdx.x; i < n; i += BSZ) back_dp_atom(L, W, i);
+}
+
+// forces, energies and counts of the cluster
+template <int BSZ>
+__device__ __noinline__ void st_out(int c, int64_t a0, int n) {
+  const BatchArgs A = uni_copy(b_args);
+  c = uni(c);
+  a0 = uni64(a0);
+  n = uni(n);
+  Lists L;
+  Work W;
+  views(A, L, W);
+  for (int i = threadIdx.x; i < n; i += BSZ) {
+    const double3 f = force_atom(L, W, i);
+    A.forces[3 * (a0 + i)] = f.x;
+    A.forces[3 * (a0 + i) + 1] = f.y;
+    A.forces[3 * (a0 + i) + 2] = f.z;
+  }
+}
+
+template <int BSZ>
+// 3 waves per SIMD: the largest stages (torsions, angles) fit in 168 VGPRs
+__global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(3))) void k_batch(BatchArgs A) {
+  const int tid = threadIdx.x;
+  if (tid == 0) b_args = A;
+  for (int k = tid; k < NT * NT; k += BSZ) b_nb[k] = nb_params(A.P->pair[k]);
+  int pos_in_order = A.dynamic ? 0 : A.wg_first[blockIdx.x];
+  const int pos_end = A.dynamic ? 0 : A.wg_first[blockIdx.x + 1];
+  for (;;) {
+    if (tid == 0) {
+      int idx;
+      if (A.dynamic) idx = atomicAdd(A.queue, 1);
+      else idx = pos_in_order < pos_end ? pos_in_order : A.ncl;
+      b_next = idx < A.ncl ? A.order[idx] : -1;
+    }
+    ++pos_in_order;
+    __syncthreads();
+    const int c = b_next;
+    if (c < 0) break;
+    const int64_t a0 = A.off[c];
+    const int n = (int)(A.off[c + 1] - a0);
+    if (__syncthreads_or(st_load<BSZ>(a0, n))) {
+      st_fail<BSZ>(c, a0, n, ST_TYPE, 0);
+      __syncthreads();
+      continue;
+    }
+    st_count<BSZ>(n);
+    __syncthreads();
+    wave_scan_inplace(b_off, n);
+    __syncthreads();
+    const int nent = b_off[n];
+    if (nent > A.ecap) {
+      st_fail<BSZ>(c, a0, n, ST_CAPACITY, nent);
+      __syncthreads();
+      continue;
+    }
+    st_fill<BSZ>(n);
+    __syncthreads();
+    st_bo_prime<BSZ>(n);
+    __syncthreads();
+    st_delta_prime<BSZ>(n);
+    __syncthreads();
+    st_bo_corr<BSZ>(n);
+    __syncthreads();
+    st_atom_state<BSZ>(n);
+    __syncthreads();
+    st_atom_energy<BSZ>(n);
+    st_nonbonded<BSZ>(n);
+    __syncthreads();
+    st_angles<BSZ>(n);
+    __syncthreads();
+    st_torsions<BSZ>(n);
+    st_hbonds<BSZ>(n);
+    __syncthreads();
+    st_back_s<BSZ>(n);
+    __syncthreads();
+    st_back_corr<BSZ>(n);
+    __syncthreads();
+    st_back_dp<BSZ>(n);
+    __syncthreads();
+    st_out<BSZ>(c, a0, n);
+    __syncthreads();
+    if (tid < NTERMS) A.energies[(int64_t)c * NTERMS + tid] = b_acc[tid];
+    else if (tid < NTERMS + 4) A.counts[(int64_t)c * NCOUNT + (tid - NTERMS)] = (long long)b_acc[tid];
+    else if (tid == NTERMS + 4) A.counts[(int64_t)c * NCOUNT + 4] = nent / 2;
+    if (tid == 0) A.status[c] = 0;
+    __syncthreads();
+  }
+}
+
+}  // namespace rx
+
+// ---------------------------------------------------------------------------
+// host side: plan, schedule, graph, autotuner
+// ---------------------------------------------------------------------------
+struct reaxff_batch {
+  reaxff_ctx* ctx = nullptr;
+  int32_t ncl = 0;
+  std::vector<int64_t> off;
+  int nmax = 0;
+  int cus = 0;
+  uint64_t sig = 0;
+  reaxff_batch_config cfg{256, REAXFF_SCHED_LPT, 4};
+  // device
+  int64_t* d_off = nullptr;
+  int32_t* d_order = nullptr;
+  int32_t* d_wg_first = nullptr;
+  int32_t* d_queue = nullptr;
+  int32_t* d_err = nullptr;
+  int32_t* d_status = nullptr;
+  long long* d_counts = nullptr;
+  char* d_scratch = nullptr;
+  int64_t scratch_bytes = 0;
+  int ecap = 0;
+  int ecap_need = 0;
+  int grid = 0;
+  bool sched_valid = false;
+  // graph
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const void* key[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  reaxff_batch_config key_cfg{0, 0, 0};
+  hipStream_t last_stream = nullptr;
+};
+
+namespace {
+
+int bfail(reaxff_batch* b, int code, const std::string& msg) {
+  if (b && b->ctx) b->ctx->err = msg;
+  return code;
+}
+
+#define BHIP(b, expr)                                                                \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return bfail(b, REAXFF_ERR_HIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+bool valid_cfg(const reaxff_batch_config& c) {
+  return (c.block == 64 || c.block == 128 || c.block == 256 || c.block == 512) &&
+         (c.schedule >= REAXFF_SCHED_STATIC && c.schedule <= REAXFF_SCHED_DYNAMIC) &&
+         c.wg_per_cu >= 1 && c.wg_per_cu <= 16;
+}
+
+// order-independent signature of the multiset of cluster sizes
+uint64_t size_signature(const std::vector<int64_t>& off) {
+  std::vector<int64_t> s(off.size() - 1);
+  for (size_t c = 0; c + 1 < off.size(); ++c) s[c] = off[c + 1] - off[c];
+  std::sort(s.begin(), s.end());
+  uint64_t h = 1469598103934665603ull;
+  for (int64_t v : s) {
+    h ^= (uint64_t)v + 0x9e3779b97f4a7c15ull;
+    h *= 1099511628211ull;
+  }
+  return h ^ (uint64_t)s.size();
+}
+
+void drop_graph(reaxff_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+// per-workgroup cluster lists for the configuration's schedule
+int make_schedule(reaxff_batch* b) {
+  const int C = b->ncl;
+  const int G = std::max(1, std::min(b->cfg.wg_per_cu * b->cus, std::max(C, 1)));
+  std::vector<int64_t> cost(C);
+  for (int c = 0; c < C; ++c) {
+    const int64_t n = b->off[c + 1] - b->off[c];
+    cost[c] = n * n + 64;
+  }
+  std::vector<int32_t> order;
+  std::vector<int32_t> first(G + 1, 0);
+  if (b->cfg.schedule == REAXFF_SCHED_DYNAMIC) {
+    order.resize(C);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+  } else {
+    std::vector<std::vector<int32_t>> per(G);
+    if (b->cfg.schedule == REAXFF_SCHED_STATIC) {
+      for (int c = 0; c < C; ++c) per[c % G].push_back(c);
+    } else {
+      std::vector<int32_t> idx(C);
+      std::iota(idx.begin(), idx.end(), 0);
+      std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+      using Load = std::pair<int64_t, int>;
+      std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+      for (int w = 0; w < G; ++w) heap.push({0, w});
+      for (int c : idx) {
+        Load l = heap.top();
+        heap.pop();
+        per[l.second].push_back(c);
+        l.first += cost[c];
+        heap.push(l);
+      }
+    }
+    for (int w = 0; w < G; ++w) {
+      first[w] = (int32_t)order.size();
+      order.insert(order.end(), per[w].begin(), per[w].end());
+    }
+    first[G] = (int32_t)order.size();
+  }
+  b->grid = G;
+  if (b->d_order) (void)hipFree(b->d_order);
+  if (b->d_wg_first) (void)hipFree(b->d_wg_first);
+  b->d_order = nullptr;
+  b->d_wg_first = nullptr;
+  BHIP(b, hipMalloc(&b->d_order, sizeof(int32_t) * std::max<size_t>(order.size(), 1)));
+  BHIP(b, hipMalloc(&b->d_wg_first, sizeof(int32_t) * first.size()));
+  if (!order.empty())
+    BHIP(b, hipMemcpy(b->d_order, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice));
+  BHIP(b, hipMemcpy(b->d_wg_first, first.data(), sizeof(int32_t) * first.size(), hipMemcpyHostToDevice));
+  // scratch: one slice per workgroup
+  const BatchLayout lay = make_layout(std::max(b->nmax, 1), b->ecap);
+  const int64_t need = lay.stride * (int64_t)G;
+  if (need > b->scratch_bytes) {
+    if (b->d_scratch) (void)hipFree(b->d_scratch);
+    b->d_scratch = nullptr;
+    b->scratch_bytes = 0;
+    BHIP(b, hipMalloc(&b->d_scratch, need));
+    b->scratch_bytes = need;
+  }
+  b->sched_valid = true;
+  drop_graph(b);
+  return 0;
+}
+
+template <int BSZ>
+void launch_batch(const BatchArgs& a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch<BSZ>, dim3(grid), dim3(BSZ), 0, st, a);
+}
+
+int capture(reaxff_batch* b, const double* pos, const int32_t* type, const double* q, double* forces,
+            double* energies) {
+  drop_graph(b);
+  reaxff_ctx* c = b->ctx;
+  BatchArgs a{};
+  a.P = c->dp;
+  a.ncl = b->ncl;
+  a.dynamic = b->cfg.schedule == REAXFF_SCHED_DYNAMIC;
+  a.off = b->d_off;
+  a.order = b->d_order;
+  a.wg_first = b->d_wg_first;
+  a.queue = b->d_queue;
+  a.pos = pos;
+  a.type = type;
+  a.q = q;
+  a.forces = forces;
+  a.energies = energies;
+  a.counts = b->d_counts;
+  a.status = b->d_status;
+  a.err = b->d_err;
+  a.scratch = b->d_scratch;
+  a.lay = make_layout(std::max(b->nmax, 1), b->ecap);
+  a.ecap = b->ecap;
+  BHIP(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, b->cap_stream, b->d_queue, b->d_err);
+  if (b->ncl > 0) {
+    switch (b->cfg.block) {
+      case 64: launch_batch<64>(a, b->grid, b->cap_stream); break;
+      case 128: launch_batch<128>(a, b->grid, b->cap_stream); break;
+      case 256: launch_batch<256>(a, b->grid, b->cap_stream); break;
+      default: launch_batch<512>(a, b->grid, b->cap_stream); break;
+    }
+  }
+  const hipError_t le = hipGetLastError();
+  hipGraph_t gph = nullptr;
+  const hipError_t ee = hipStreamEndCapture(b->cap_stream, &gph);
+  if (le != hipSuccess) {
+    if (gph) (void)hipGraphDestroy(gph);
+    return bfail(b, REAXFF_ERR_HIP, std::string("batch launch: ") + hipGetErrorString(le));
+  }
+  if (ee != hipSuccess) return bfail(b, REAXFF_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
+  b->graph = gph;
+  BHIP(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  b->key[0] = pos;
+  b->key[1] = type;
+  b->key[2] = q;
+  b->key[3] = forces;
+  b->key[4] = energies;
+  b->key_cfg = b->cfg;
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int reaxff_batch_create(reaxff_ctx* ctx, int32_t nclusters, const int64_t* offsets,
+                        const reaxff_batch_config* cfg, reaxff_batch** out) {
+  if (!ctx || !out || nclusters < 0 || (!offsets && nclusters > 0)) {
+    if (ctx) ctx->err = "reaxff_batch_create: null argument or negative cluster count";
+    return REAXFF_ERR_ARG;
+  }
+  *out = nullptr;
+  std::vector<int64_t> off(offsets, offsets + nclusters + 1);
+  if (nclusters == 0) off.assign(1, 0);
+  if (off[0] != 0) {
+    ctx->err = "reaxff_batch_create: offsets[0] must be 0";
+    return REAXFF_ERR_ARG;
+  }
+  int nmax = 0;
+  for (int c = 0; c < nclusters; ++c) {
+    const int64_t n = off[c + 1] - off[c];
+    if (n < 0 || n > REAXFF_BATCH_MAX_ATOMS) {
+      ctx->err = "reaxff_batch_create: cluster " + std::to_string(c) + " has " + std::to_string(n) +
+                 " atoms (allowed 0.." + std::to_string(REAXFF_BATCH_MAX_ATOMS) + ")";
+      return REAXFF_ERR_ARG;
+    }
+    nmax = std::max<int>(nmax, (int)n);
+  }
+  if (cfg && !valid_cfg(*cfg)) {
+    ctx->err = "reaxff_batch_create: invalid configuration";
+    return REAXFF_ERR_ARG;
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) {
+    ctx->err = "hipSetDevice failed";
+    return REAXFF_ERR_HIP;
+  }
+  reaxff_batch* b = new reaxff_batch();
+  b->ctx = ctx;
+  b->ncl = nclusters;
+  b->off = off;
+  b->nmax = nmax;
+  b->sig = size_signature(off);
+  // directed bond entries per atom: dense molecular matter stays far below 8
+  // on average; a cluster beyond it is reported and the slices grow
+  b->ecap = std::max(64, 8 * nmax);
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus <= 0)
+    cus = 256;
+  b->cus = cus;
+  if (cfg) {
+    b->cfg = *cfg;
+  } else {
+    auto it = ctx->tuned.find(b->sig);
+    if (it != ctx->tuned.end()) b->cfg = it->second;
+  }
+  auto cleanup = [&](int code) {
+    reaxff_batch_destroy(b);
+    return code;
+  };
+  if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    return cleanup(bfail(b, REAXFF_ERR_HIP, "hipStreamCreate failed"));
+  const size_t C = (size_t)std::max(nclusters, 1);
+  if (hipMalloc(&b->d_off, sizeof(int64_t) * off.size()) != hipSuccess ||
+      hipMalloc(&b->d_queue, sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(&b->d_err, sizeof(int32_t) * 4) != hipSuccess ||
+      hipMalloc(&b->d_status, sizeof(int32_t) * C) != hipSuccess ||
+      hipMalloc(&b->d_counts, sizeof(long long) * C * rx::NCOUNT) != hipSuccess)
+    return cleanup(bfail(b, REAXFF_ERR_HIP, "hipMalloc failed (batch plan)"));
+  if (hipMemcpy(b->d_off, off.data(), sizeof(int64_t) * off.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(b->d_err, 0, sizeof(int32_t) * 4) != hipSuccess ||
+      hipMemset(b->d_status, 0, sizeof(int32_t) * C) != hipSuccess ||
+      hipMemset(b->d_counts, 0, sizeof(long long) * C * rx::NCOUNT) != hipSuccess)
+    return cleanup(bfail(b, REAXFF_ERR_HIP, "hipMemcpy failed (batch plan)"));
+  const int r = make_schedule(b);
+  if (r) return cleanup(r);
+  *out = b;
+  return REAXFF_OK;
+}
+
+void reaxff_batch_destroy(reaxff_batch* b) {
+  if (!b) return;
+  if (b->ctx) (void)hipSetDevice(b->ctx->device);
+  if (b->cap_stream) (void)hipStreamSynchronize(b->cap_stream);
+  if (b->last_stream) (void)hipStreamSynchronize(b->last_stream);
+  drop_graph(b);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  for (void* p : {(void*)b->d_off, (void*)b->d_order, (void*)b->d_wg_first, (void*)b->d_queue, (void*)b->d_err,
+                  (void*)b->d_status, (void*)b->d_counts, (void*)b->d_scratch})
+    if (p) (void)hipFree(p);
+  delete b;
+}
+
+int reaxff_batch_set_config(reaxff_batch* b, const reaxff_batch_config* cfg) {
+  if (!b || !cfg) return REAXFF_ERR_ARG;
+  if (!valid_cfg(*cfg)) return bfail(b, REAXFF_ERR_ARG, "reaxff_batch_set_config: invalid configuration");
+  if (b->last_stream) (void)hipStreamSynchronize(b->last_stream);
+  b->cfg = *cfg;
+  return make_schedule(b);
+}
+
+int reaxff_batch_get_config(const reaxff_batch* b, reaxff_batch_config* cfg) {
+  if (!b || !cfg) return REAXFF_ERR_ARG;
+  *cfg = b->cfg;
+  return REAXFF_OK;
+}
+
+int reaxff_batch_compute(reaxff_batch* b, const double* pos, const int32_t* type, const double* q,
+                         double* forces, double* energies, hipStream_t stream) {
+  if (!b) return REAXFF_ERR_ARG;
+  const bool any = b->off.back() > 0;
+  if (any && (!pos || !type || !q || !forces)) return bfail(b, REAXFF_ERR_ARG, "reaxff_batch_compute: null pointer");
+  if (b->ncl > 0 && !energies) return bfail(b, REAXFF_ERR_ARG, "reaxff_batch_compute: null energies");
+  BHIP(b, hipSetDevice(b->ctx->device));
+  if (b->ecap_need > b->ecap) {
+    if (b->last_stream) (void)hipStreamSynchronize(b->last_stream);
+    b->ecap = b->ecap_need + b->ecap_need / 4 + 16;
+    b->ecap_need = 0;
+    const int r = make_schedule(b);
+    if (r) return r;
+  }
+  const bool same = b->exec && b->key[0] == pos && b->key[1] == type && b->key[2] == q &&
+                    b->key[3] == forces && b->key[4] == energies && b->key_cfg.block == b->cfg.block &&
+                    b->key_cfg.schedule == b->cfg.schedule && b->key_cfg.wg_per_cu == b->cfg.wg_per_cu;
+  if (!same) {
+    const int r = capture(b, pos, type, q, forces, energies);
+    if (r) return r;
+  }
+  rx::Prof& pf = b->ctx->prof;
+  pf.begin(rx::KID_BATCH, stream);
+  BHIP(b, hipGraphLaunch(b->exec, stream));
+  pf.end(stream);
+  b->last_stream = stream;
+  return REAXFF_OK;
+}
+
+int reaxff_batch_status(reaxff_batch* b, int32_t* first_bad) {
+  if (!b) return REAXFF_ERR_ARG;
+  BHIP(b, hipSetDevice(b->ctx->device));
+  int32_t e[4] = {0, 0, INT_MAX, 0};
+  BHIP(b, hipStreamSynchronize(b->last_stream));
+  BHIP(b, hipMemcpy(e, b->d_err, sizeof(e), hipMemcpyDeviceToHost));
+  if (first_bad) *first_bad = e[0] ? e[2] : -1;
+  if (e[0] & rx::ST_TYPE)
+    return bfail(b, REAXFF_ERR_ARG, "batch: atom type outside 0..3 in cluster " + std::to_string(e[2]));
+  if (e[0] & rx::ST_CAPACITY) {
+    b->ecap_need = std::max(b->ecap_need, (int)e[1]);
+    return bfail(b, REAXFF_ERR_CAPACITY,
+                 "batch: " + std::to_string(e[1]) + " bond entries in one cluster exceed the scratch slice (" +
+                     std::to_string(b->ecap) + "); the next compute grows it");
+  }
+  return REAXFF_OK;
+}
+
+int reaxff_batch_counts(reaxff_batch* b, int64_t* counts) {
+  if (!b || (!counts && b->ncl > 0)) return REAXFF_ERR_ARG;
+  BHIP(b, hipSetDevice(b->ctx->device));
+  BHIP(b, hipStreamSynchronize(b->last_stream));
+  if (b->ncl > 0)
+    BHIP(b, hipMemcpy(counts, b->d_counts, sizeof(long long) * (size_t)b->ncl * rx::NCOUNT,
+                      hipMemcpyDeviceToHost));
+  return REAXFF_OK;
+}
+
+int reaxff_batch_tune(reaxff_batch* b, const double* pos, const int32_t* type, const double* q,
+                      double* forces, double* energies, hipStream_t stream, int32_t reps,
+                      int32_t max_trials, reaxff_batch_config* trials, double* trial_ms,
+                      int32_t* ntrials) {
+  if (!b) return REAXFF_ERR_ARG;
+  if (reps < 1) reps = 1;
+  static const int blocks[4] = {64, 128, 256, 512};
+  static const int scheds[3] = {REAXFF_SCHED_STATIC, REAXFF_SCHED_LPT, REAXFF_SCHED_DYNAMIC};
+  static const int wgs[4] = {1, 2, 4, 8};
+  std::vector<reaxff_batch_config> all;
+  for (int bl : blocks)
+    for (int s : scheds)
+      for (int w : wgs) all.push_back(reaxff_batch_config{bl, s, w});
+  if (max_trials > 0 && (size_t)max_trials < all.size()) all.resize(max_trials);
+  hipEvent_t e0, e1;
+  BHIP(b, hipSetDevice(b->ctx->device));
+  BHIP(b, hipEventCreate(&e0));
+  BHIP(b, hipEventCreate(&e1));
+  double best = 1e300;
+  reaxff_batch_config bestc = b->cfg;
+  int k = 0;
+  int rc = REAXFF_OK;
+  for (const auto& cf : all) {
+    if ((rc = reaxff_batch_set_config(b, &cf))) break;
+    if ((rc = reaxff_batch_compute(b, pos, type, q, forces, energies, stream))) break;   // untimed
+    (void)hipEventRecord(e0, stream);
+    for (int r = 0; r < reps && !rc; ++r) rc = reaxff_batch_compute(b, pos, type, q, forces, energies, stream);
+    (void)hipEventRecord(e1, stream);
+    if (rc) break;
+    if (hipEventSynchronize(e1) != hipSuccess) {
+      rc = bfail(b, REAXFF_ERR_HIP, "batch tune: event synchronise failed");
+      break;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    const double per = (double)ms / reps;
+    if (trials) trials[k] = cf;
+    if (trial_ms) trial_ms[k] = per;
+    ++k;
+    if (per < best) {
+      best = per;
+      bestc = cf;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (ntrials) *ntrials = k;
+  if (rc) return rc;
+  b->ctx->tuned[b->sig] = bestc;
+  rc = reaxff_batch_set_config(b, &bestc);
+  if (rc) return rc;
+  return reaxff_batch_compute(b, pos, type, q, forces, energies, stream);
+}
+
+}  // extern "C"

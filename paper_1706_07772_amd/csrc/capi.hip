@@ -11,23 +11,6 @@
 
 using namespace rx;
 
-struct reaxff_ctx {
-  int device = 0;
-  reaxff_params hp;
-  reaxff_cutoffs cut;
-  DevParams* dp = nullptr;    // device copy
-  DevParams hd;               // host copy
-  Grid grid{};
-  Lists L{};
-  Work W{};
-  Scratch sc{};
-  Prof prof;
-  bool built = false;
-  double box[3] = {0, 0, 0};
-  bool periodic = false;
-  int64_t cap_n = 0, cap_cell = 0, cap_far = 0, cap_bond = 0, cap_hb = 0, cap_ha = 0, cap_part = 0;
-  std::string err;
-};
 
 namespace {
 

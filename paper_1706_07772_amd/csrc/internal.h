@@ -1,6 +1,8 @@
 // Host-side internals shared by the library's translation units.
 #pragma once
 
+#include <map>
+#include <string>
 #include <vector>
 
 #include "reaxff_dev.h"
@@ -12,7 +14,7 @@ enum KernelId {
   KID_BBOX, KID_CELL_HIST, KID_CELL_SCATTER, KID_CELL_SORT, KID_GATHER, KID_LIST_SWEEP, KID_SCAN,
   KID_BONDTEST, KID_COMPACT, KID_MIRROR, KID_ZERO, KID_GATHER_Q, KID_BO_PRIME, KID_DELTA_PRIME, KID_BO_CORR,
   KID_ATOM_STATE, KID_ATOM_ENERGY, KID_TASKS, KID_ANGLES, KID_TORSIONS, KID_HBONDS, KID_HB_ACC, KID_NONBONDED,
-  KID_BACK_S, KID_BACK_CORR, KID_BACK_DP, KID_FORCES, KID_COUNT
+  KID_BACK_S, KID_BACK_CORR, KID_BACK_DP, KID_FORCES, KID_BATCH, KID_COUNT
 };
 extern const char* const kKernelNames[KID_COUNT];
 
@@ -108,3 +110,24 @@ int launch_kinetic(int64_t n, const double* vel, const int32_t* type, const DevP
                    double* out, hipStream_t st);
 
 }  // namespace rx
+
+// the library context (opaque to callers)
+struct reaxff_ctx {
+  int device = 0;
+  reaxff_params hp;
+  reaxff_cutoffs cut;
+  rx::DevParams* dp = nullptr;    // device copy
+  rx::DevParams hd;               // host copy
+  rx::Grid grid{};
+  rx::Lists L{};
+  rx::Work W{};
+  rx::Scratch sc{};
+  rx::Prof prof;
+  bool built = false;
+  double box[3] = {0, 0, 0};
+  bool periodic = false;
+  int64_t cap_n = 0, cap_cell = 0, cap_far = 0, cap_bond = 0, cap_hb = 0, cap_ha = 0, cap_part = 0;
+  std::string err;
+  // autotuned batch configurations, keyed by a signature of the cluster sizes
+  std::map<uint64_t, reaxff_batch_config> tuned;
+};

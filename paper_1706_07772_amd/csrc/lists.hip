@@ -12,6 +12,7 @@
 // of the three totals that size the buffers.
 #include "reaxff_dev.h"
 #include "internal.h"
+#include "terms.h"
 
 namespace rx {
 
@@ -111,17 +112,6 @@ __global__ void k_gather_sorted(const double* __restrict__ pos, const int32_t* _
   xs[s] = make_double4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], (double)type[i]);
   type_s[s] = type[i];
   cell_s[s] = cid[i];
-}
-
-// ---------------------------------------------------------------------------
-// raw uncorrected bond order of a pair (sigma scaled by 1 + bo_cut)
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double bo_raw(const PairP& p, double r, double bo_cut) {
-  double s = 0.0, pi = 0.0, pp = 0.0;
-  if (p.r_s > 0.0) s = (1.0 + bo_cut) * exp(p.p_bo1 * pow(r / p.r_s, p.p_bo2));
-  if (p.r_p > 0.0) pi = exp(p.p_bo3 * pow(r / p.r_p, p.p_bo4));
-  if (p.r_pp > 0.0) pp = exp(p.p_bo5 * pow(r / p.r_pp, p.p_bo6));
-  return s + pi + pp;
 }
 
 // z ranges of a stencil column around cell z = c2, in cell units within a

@@ -1,0 +1,636 @@
+// Per-atom and per-interaction ReaxFF arithmetic, shared by the kernels of
+// the large-system path (one launch per stage, forces.hip) and the batched
+// cluster kernel (all stages inside one workgroup, batch.hip).  Each function
+// works on the Lists/Work views of reaxff_dev.h; the batched kernel points
+// some of those views at LDS.
+#pragma once
+
+#include "reaxff_dev.h"
+
+namespace rx {
+
+__device__ __forceinline__ void atomic_add3(double4* p, double x, double y, double z) {
+  double* d = reinterpret_cast<double*>(p);
+  atomicAdd(d + 0, x);
+  atomicAdd(d + 1, y);
+  atomicAdd(d + 2, z);
+}
+__device__ __forceinline__ double3 cross(double3 a, double3 b) {
+  return make_double3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double dot(double3 a, double3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ double3 d3(double4 v) { return make_double3(v.x, v.y, v.z); }
+__device__ __forceinline__ double3 axpy(double a, double3 x, double3 y) {
+  return make_double3(a * x.x + y.x, a * x.y + y.y, a * x.z + y.z);
+}
+__device__ __forceinline__ double3 scale(double a, double3 x) { return make_double3(a * x.x, a * x.y, a * x.z); }
+__device__ __forceinline__ double3 add3(double3 a, double3 b) { return make_double3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ void atomic_add3(double4* p, double3 v) { atomic_add3(p, v.x, v.y, v.z); }
+
+// raw uncorrected bond order sum of sigma, pi and pi-pi (the bond-list test)
+__device__ __forceinline__ double bo_raw(const PairP& p, double r, double bo_cut) {
+  double s = 0.0, pi = 0.0, pp = 0.0;
+  if (p.r_s > 0.0) s = (1.0 + bo_cut) * exp(p.p_bo1 * pow(r / p.r_s, p.p_bo2));
+  if (p.r_p > 0.0) pi = exp(p.p_bo3 * pow(r / p.r_p, p.p_bo4));
+  if (p.r_pp > 0.0) pp = exp(p.p_bo5 * pow(r / p.r_pp, p.p_bo6));
+  return s + pi + pp;
+}
+
+// ---------------------------------------------------------------------------
+// (1) uncorrected bond orders of atom i's entries, computed in a canonical
+//     orientation (lower index first) so both entries of a bond hold
+//     identical bits
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void bo_prime_atom(const DevParams* __restrict__ P, const Grid& g,
+                                              const Lists& L, const Work& W, int i) {
+  const double4 xi = L.xs[i];
+  const int ti = L.type_s[i];
+  const double bo_cut = P->bo_cut;
+  for (int e = L.bond_off[i]; e < L.bond_off[i + 1]; ++e) {
+    const int j = L.bond_j[e];
+    const double4 xj = L.xs[j];
+    const bool lo = i < j;
+    // d = x_b - x_a with a the lower index
+    double dx = lo ? xj.x - xi.x : xi.x - xj.x;
+    double dy = lo ? xj.y - xi.y : xi.y - xj.y;
+    double dz = lo ? xj.z - xi.z : xi.z - xj.z;
+    if (g.periodic) {
+      dx = min_image(dx, g.L[0], g.invL[0]);
+      dy = min_image(dy, g.L[1], g.invL[1]);
+      dz = min_image(dz, g.L[2], g.invL[2]);
+    }
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    W.bd[e] = lo ? make_double4(dx, dy, dz, r) : make_double4(-dx, -dy, -dz, r);
+    const PairP& p = P->pair[ti * NT + L.type_s[j]];
+    double s = 0.0, ds = 0.0, pi = 0.0, dpi = 0.0, pp = 0.0, dpp = 0.0;
+    const double ir = 1.0 / r;
+    if (p.r_s > 0.0) {
+      const double x = pow(r / p.r_s, p.p_bo2);
+      s = (1.0 + bo_cut) * exp(p.p_bo1 * x);
+      ds = s * p.p_bo1 * p.p_bo2 * x * ir;
+    }
+    if (p.r_p > 0.0) {
+      const double x = pow(r / p.r_p, p.p_bo4);
+      pi = exp(p.p_bo3 * x);
+      dpi = pi * p.p_bo3 * p.p_bo4 * x * ir;
+    }
+    if (p.r_pp > 0.0) {
+      const double x = pow(r / p.r_pp, p.p_bo6);
+      pp = exp(p.p_bo5 * x);
+      dpp = pp * p.p_bo5 * p.p_bo6 * x * ir;
+    }
+    const double raw = s + pi + pp;
+    W.bop[e] = make_double4(s - bo_cut, pi, pp, raw - bo_cut);
+    W.dbop[e] = make_double4(ds, dpi, dpp, 0.0);
+  }
+}
+
+// (2) Delta'_i = sum BO' - Val_i,  Delta'boc_i = sum BO' - Val_boc_i
+__device__ __forceinline__ void delta_prime_atom(const DevParams* __restrict__ P, const Lists& L,
+                                                 const Work& W, int i) {
+  double s = 0.0;
+  for (int e = L.bond_off[i]; e < L.bond_off[i + 1]; ++e) s += W.bop[e].w;
+  const AtomP& a = P->atom[L.type_s[i]];
+  W.dp[i] = make_double2(s - a.val, s - a.val_boc);
+}
+
+// bond-order correction of one bond, canonical orientation (a lower index)
+struct Corr {
+  double f1, f4, f5;
+  double df1_da, df1_db;     // d f1 / d Delta'_a, d Delta'_b
+  double df4_dbo, df5_dbo;   // d f4 / d BO', d f5 / d BO'
+  double df4_da, df5_db;     // d f4 / d Delta'boc_a, d f5 / d Delta'boc_b
+};
+
+__device__ __forceinline__ Corr correction(const DevParams* __restrict__ P, double bop, double va,
+                                           double vb, double2 da, double2 db, const PairP& p) {
+  Corr c;
+  const double ea1 = exp(-P->p_boc1 * da.x), eb1 = exp(-P->p_boc1 * db.x);
+  const double ea2 = exp(-P->p_boc2 * da.x), eb2 = exp(-P->p_boc2 * db.x);
+  const double f2 = ea1 + eb1;
+  const double u = 0.5 * (ea2 + eb2);
+  const double f3 = -(1.0 / P->p_boc2) * log(u);
+  const double A = va + f2, Ad = va + f2 + f3;
+  const double B = vb + f2, Bd = vb + f2 + f3;
+  c.f1 = 0.5 * (A / Ad + B / Bd);
+  const double df1_df2 = 0.5 * (f3 / (Ad * Ad) + f3 / (Bd * Bd));
+  const double df1_df3 = -0.5 * (A / (Ad * Ad) + B / (Bd * Bd));
+  const double w2 = 1.0 / (ea2 + eb2);
+  c.df1_da = df1_df2 * (-P->p_boc1 * ea1) + df1_df3 * (ea2 * w2);
+  c.df1_db = df1_df2 * (-P->p_boc1 * eb1) + df1_df3 * (eb2 * w2);
+  const double bo2 = bop * bop;
+  const double e4 = exp(-p.p_boc3 * (p.p_boc4 * bo2 - da.y) + p.p_boc5);
+  const double e5 = exp(-p.p_boc3 * (p.p_boc4 * bo2 - db.y) + p.p_boc5);
+  c.f4 = 1.0 / (1.0 + e4);
+  c.f5 = 1.0 / (1.0 + e5);
+  const double s4 = c.f4 * (1.0 - c.f4), s5 = c.f5 * (1.0 - c.f5);
+  c.df4_dbo = s4 * 2.0 * p.p_boc3 * p.p_boc4 * bop;
+  c.df5_dbo = s5 * 2.0 * p.p_boc3 * p.p_boc4 * bop;
+  c.df4_da = -s4 * p.p_boc3;
+  c.df5_db = -s5 * p.p_boc3;
+  return c;
+}
+
+// (3) corrected bond orders of atom i's entries
+__device__ __forceinline__ void bo_corr_atom(const DevParams* __restrict__ P, const Lists& L,
+                                             const Work& W, int i) {
+  const int ti = L.type_s[i];
+  for (int e = L.bond_off[i]; e < L.bond_off[i + 1]; ++e) {
+    const int j = L.bond_j[e];
+    const int tj = L.type_s[j];
+    const bool lo = i < j;
+    const int a = lo ? i : j, b = lo ? j : i;
+    const int ta = lo ? ti : tj, tb = lo ? tj : ti;
+    const double4 bp = W.bop[e];
+    const Corr c = correction(P, bp.w, P->atom[ta].val, P->atom[tb].val, W.dp[a], W.dp[b],
+                              P->pair[ti * NT + tj]);
+    const double F = c.f1 * c.f4 * c.f5;
+    const double G = c.f1 * c.f1 * c.f4 * c.f5;
+    const double BO = bp.w * F, BOp = bp.y * G, BOpp = bp.z * G;
+    W.bo[e] = make_double4(BO, BOp, BOpp, BO - BOp - BOpp);
+  }
+}
+
+// (4) atom state
+__device__ __forceinline__ void atom_state_atom(const DevParams* __restrict__ P, const Lists& L,
+                                                const Work& W, int i) {
+  const AtomP& a = P->atom[L.type_s[i]];
+  double S = 0.0, sumpi = 0.0, sum8 = 0.0;
+  for (int e = L.bond_off[i]; e < L.bond_off[i + 1]; ++e) {
+    const double4 b = W.bo[e];
+    S += b.x;
+    sumpi += b.y + b.z;
+    const double b2 = b.x * b.x, b4 = b2 * b2;
+    sum8 += b4 * b4;
+  }
+  AtomState st;
+  st.S = S;
+  st.Delta = S - a.val;
+  st.Dang = S - a.val_ang;
+  const double De = S - a.val_e;
+  const double tr = trunc(De * 0.5);
+  const double vlpex = De - 2.0 * tr;
+  const double enlp = exp(-P->p_lp1 * sqr(2.0 + vlpex));
+  const double nlp = enlp - tr;
+  st.Dlp = a.nlp_opt - nlp;
+  st.dnlp = enlp * (-2.0 * P->p_lp1 * (2.0 + vlpex));
+  st.prod = exp(-sum8);
+  const bool neg = vlpex < 0.0;
+  st.W = -st.Dang - P->p_val8 * (neg ? nlp : 0.0);
+  st.dW = -1.0 - P->p_val8 * (neg ? st.dnlp : 0.0);
+  const double SBO = sumpi + (1.0 - st.prod) * st.W;
+  const double p9 = P->p_val9;
+  if (SBO <= 0.0) {
+    st.SBO2 = 0.0; st.dSBO2 = 0.0;
+  } else if (SBO <= 1.0) {
+    const double t = pow(SBO, p9);
+    st.SBO2 = t; st.dSBO2 = p9 * t / SBO;
+  } else if (SBO < 2.0) {
+    const double t = pow(2.0 - SBO, p9);
+    st.SBO2 = 2.0 - t; st.dSBO2 = p9 * t / (2.0 - SBO);
+  } else {
+    st.SBO2 = 2.0; st.dSBO2 = 0.0;
+  }
+  // centre factors of the valence-angle family
+  const double ex10 = exp(-P->p_val10 * (2.0 - st.SBO2));
+  st.th0f = 1.0 - ex10;
+  st.dth0f = -ex10 * P->p_val10;                 // d th0f / d SBO2
+  st.e6 = exp(P->p_val6 * st.Dang);
+  const double ep3 = exp(-P->p_pen3 * st.Delta), ep4 = exp(P->p_pen4 * st.Delta);
+  const double f9d = 1.0 + ep3 + ep4;
+  st.f9 = (2.0 + ep3) / f9d;
+  st.df9 = (-P->p_pen3 * ep3 * f9d - (2.0 + ep3) * (-P->p_pen3 * ep3 + P->p_pen4 * ep4)) / (f9d * f9d);
+  const double ec = exp(P->p_coa2 * st.Dang);
+  st.fc = 1.0 / (1.0 + ec);
+  st.dfc = -P->p_coa2 * ec * st.fc * st.fc;
+  W.ast[i] = st;
+}
+
+// (5) bond energy (once per bond, from its lower-index entry), lone pair,
+//     over- and under-coordination of atom i; adds the scalar adjoints to i's
+//     own entries and sets gS[i], gSig[i].  e[0..3] += bond, lp, over, under.
+__device__ __forceinline__ void atom_energy_atom(const DevParams* __restrict__ P, const Lists& L,
+                                                 const Work& W, int i, double e[4]) {
+  const int ti = L.type_s[i];
+  const AtomP& a = P->atom[ti];
+  const AtomState st = W.ast[i];
+  double sumpi = 0.0, sumov = 0.0, ebond = 0.0;
+  for (int e = L.bond_off[i]; e < L.bond_off[i + 1]; ++e) {
+    const int j = L.bond_j[e];
+    const int tj = L.type_s[j];
+    const PairP& p = P->pair[ti * NT + tj];
+    const double4 b = W.bo[e];
+    const AtomState sj = W.ast[j];
+    sumpi += (sj.Delta - sj.Dlp) * (b.y + b.z);
+    sumov += p.p_ovun1 * p.D_s * b.x;
+    if (i < j) {
+      const double sig = b.w;
+      const double pw = sig > 0.0 ? pow(sig, p.p_be2) : 0.0;
+      const double ex = exp(p.p_be1 * (1.0 - pw));
+      ebond += -p.D_s * sig * ex - p.D_p * b.y - p.D_pp * b.z;
+      const double dsig = -p.D_s * ex * (1.0 - p.p_be1 * p.p_be2 * pw);
+      double4 gb = W.gbo[e];
+      gb.x += dsig;
+      gb.y += -p.D_p - dsig;
+      gb.z += -p.D_pp - dsig;
+      W.gbo[e] = gb;
+    }
+  }
+  // lone pair
+  const double e75 = exp(-75.0 * st.Dlp);
+  const double den75 = 1.0 / (1.0 + e75);
+  const double elp = a.p_lp2 * st.Dlp * den75;
+  const double dElp_dDlp = a.p_lp2 * (den75 + st.Dlp * 75.0 * e75 * den75 * den75);
+  // over / under
+  const double ep4 = exp(P->p_ovun4 * sumpi);
+  const double DD = 1.0 + P->p_ovun3 * ep4;
+  const double Dlpc = st.Delta - st.Dlp / DD;
+  const double Vp = a.val + 1e-8;
+  const double R = Dlpc / (Dlpc + Vp);
+  const double dR = Vp / sqr(Dlpc + Vp);
+  const double so = 1.0 / (1.0 + exp(a.p_ovun2 * Dlpc));
+  const double dso = -a.p_ovun2 * so * (1.0 - so);
+  const double eover = sumov * R * so;
+  const double e6 = exp(P->p_ovun6 * Dlpc);
+  const double su = 1.0 / (1.0 + exp(-a.p_ovun2 * Dlpc));
+  const double dsu = a.p_ovun2 * su * (1.0 - su);
+  const double ep8 = exp(P->p_ovun8 * sumpi);
+  const double t8 = 1.0 / (1.0 + P->p_ovun7 * ep8);
+  const double eunder = -a.p_ovun5 * (1.0 - e6) * su * t8;
+  const double gL = sumov * (dR * so + R * dso) +
+                    (-a.p_ovun5 * t8) * (-P->p_ovun6 * e6 * su + (1.0 - e6) * dsu);
+  const double dt8 = -P->p_ovun7 * P->p_ovun8 * ep8 * t8 * t8;
+  const double dDlpc_dsig = st.Dlp * P->p_ovun3 * P->p_ovun4 * ep4 / (DD * DD);
+  const double gSig = -a.p_ovun5 * (1.0 - e6) * su * dt8 + gL * dDlpc_dsig;
+  const double gRso = R * so;
+  for (int e = L.bond_off[i]; e < L.bond_off[i + 1]; ++e) {
+    const int j = L.bond_j[e];
+    const PairP& p = P->pair[ti * NT + L.type_s[j]];
+    const AtomState sj = W.ast[j];
+    double4 gb = W.gbo[e];
+    gb.x += p.p_ovun1 * p.D_s * gRso;
+    const double w = gSig * (sj.Delta - sj.Dlp);
+    gb.y += w;
+    gb.z += w;
+    W.gbo[e] = gb;
+  }
+  W.gS[i] = dElp_dDlp * (-st.dnlp) + gL * (1.0 + st.dnlp / DD);
+  W.gSig[i] = gSig;
+  e[0] += ebond;
+  e[1] += elp;
+  e[2] += eover;
+  e[3] += eunder;
+}
+
+// ---------------------------------------------------------------------------
+// (6) one valence angle i-j-k given by the centre's entries u = j->i and
+//     v = j->k: energies and the adjoints to deposit
+// ---------------------------------------------------------------------------
+struct AngOut {
+  double gu[5], gv[5];   // gvec (x, y, z), gbo.x, gbo.w of entries u and v
+  double gS, gSBO2;      // centre adjoints: dE/dS (via Dang, Delta), dE/dSBO2
+  double ev, ep, ec;     // valence, penalty, coalition energies
+};
+
+__device__ __forceinline__ AngOut angle_eval(const DevParams* __restrict__ P, const Lists& L,
+                                             const Work& W, int u, int v) {
+  AngOut o;
+  const double thb = P->thb_cut;
+  const int j = L.bond_i[u], i = L.bond_j[u], k = L.bond_j[v];
+  const int ti = L.type_s[i], tj = L.type_s[j], tk = L.type_s[k];
+  const AtomP& aj = P->atom[tj];
+  const AngleP& ap = P->angle[(ti * NT + tj) * NT + tk];
+  const AtomState& st = W.ast[j];
+  const double4 ru = W.bd[u], rv = W.bd[v];
+  const double B1 = W.bo[u].x - thb, B2 = W.bo[v].x - thb;
+  const double Si = W.ast[i].S, Sk = W.ast[k].S;
+  // angle between r_ji (= bd[u]) and r_jk (= bd[v])
+  const double il1 = 1.0 / ru.w, il2 = 1.0 / rv.w;
+  double c = (ru.x * rv.x + ru.y * rv.y + ru.z * rv.z) * il1 * il2;
+  c = c > 1.0 ? 1.0 : (c < -1.0 ? -1.0 : c);
+  const double th = acos(c);
+  const double sn = fmax(sqrt(1.0 - c * c), 1e-5);
+  const double th0 = PI - ap.theta00_rad * st.th0f;
+  const double dth0 = -ap.theta00_rad * st.dth0f;     // d th0 / d SBO2
+  // f7
+  const double x1 = pow(B1, ap.p_val4), x2 = pow(B2, ap.p_val4);
+  const double g1 = exp(-aj.p_val3 * x1), g2 = exp(-aj.p_val3 * x2);
+  const double f7a = 1.0 - g1, f7b = 1.0 - g2;
+  const double df7a = aj.p_val3 * ap.p_val4 * x1 / B1 * g1;
+  const double df7b = aj.p_val3 * ap.p_val4 * x2 / B2 * g2;
+  // f8
+  const double e6 = st.e6;
+  const double e7 = exp(-ap.p_val7 * st.Dang);
+  const double f8d = 1.0 + e6 + e7;
+  const double f8 = aj.p_val5 - (aj.p_val5 - 1.0) * (2.0 + e6) / f8d;
+  const double df8 = -(aj.p_val5 - 1.0) *
+                     (P->p_val6 * e6 * f8d - (2.0 + e6) * (P->p_val6 * e6 - ap.p_val7 * e7)) /
+                     (f8d * f8d);
+  const double dt = th0 - th;
+  const double ev = exp(-ap.p_val2 * dt * dt);
+  const double Ea = f7a * f7b * f8 * ap.p_val1;
+  const double Ev = Ea * (1.0 - ev);
+  const double gdt = Ea * ev * 2.0 * ap.p_val2 * dt;   // dE/d(th0 - th)
+  double gB1 = df7a * f7b * f8 * ap.p_val1 * (1.0 - ev);
+  double gB2 = f7a * df7b * f8 * ap.p_val1 * (1.0 - ev);
+  double gS = f7a * f7b * df8 * ap.p_val1 * (1.0 - ev);      // via Dang
+  o.gSBO2 = gdt * dth0;
+  // penalty
+  const double pe1 = exp(-P->p_pen2 * sqr(B1 - 2.0)), pe2 = exp(-P->p_pen2 * sqr(B2 - 2.0));
+  const double Ep = ap.p_pen1 * st.f9 * pe1 * pe2;
+  gB1 += Ep * (-2.0 * P->p_pen2 * (B1 - 2.0));
+  gB2 += Ep * (-2.0 * P->p_pen2 * (B2 - 2.0));
+  gS += ap.p_pen1 * st.df9 * pe1 * pe2;                       // via Delta
+  // coalition
+  const double ci = exp(-P->p_coa3 * sqr(Si - B1)), ck = exp(-P->p_coa3 * sqr(Sk - B2));
+  const double cb1 = exp(-P->p_coa4 * sqr(B1 - 1.5)), cb2 = exp(-P->p_coa4 * sqr(B2 - 1.5));
+  const double Ec = ap.p_coa1 * st.fc * ci * ck * cb1 * cb2;
+  gS += ap.p_coa1 * st.dfc * ci * ck * cb1 * cb2;            // via Dang
+  const double gSi = Ec * (-2.0 * P->p_coa3 * (Si - B1));
+  const double gSk = Ec * (-2.0 * P->p_coa3 * (Sk - B2));
+  gB1 += Ec * (2.0 * P->p_coa3 * (Si - B1) - 2.0 * P->p_coa4 * (B1 - 1.5));
+  gB2 += Ec * (2.0 * P->p_coa3 * (Sk - B2) - 2.0 * P->p_coa4 * (B2 - 1.5));
+  o.ev = Ev;
+  o.ep = Ep;
+  o.ec = Ec;
+  o.gS = gS;
+  // geometry: dtheta/dc = -1/sin;  dE/dc = dE/dtheta * dtheta/dc = gdt / sin
+  const double gc = gdt / sn;
+  const double ca = c * il1 * il1, cb = c * il2 * il2, ab = il1 * il2;
+  o.gu[0] = gc * (rv.x * ab - ru.x * ca);
+  o.gu[1] = gc * (rv.y * ab - ru.y * ca);
+  o.gu[2] = gc * (rv.z * ab - ru.z * ca);
+  o.gu[3] = gB1;
+  o.gu[4] = gSi;
+  o.gv[0] = gc * (ru.x * ab - rv.x * cb);
+  o.gv[1] = gc * (ru.y * ab - rv.y * cb);
+  o.gv[2] = gc * (ru.z * ab - rv.z * cb);
+  o.gv[3] = gB2;
+  o.gv[4] = gSk;
+  return o;
+}
+
+// ---------------------------------------------------------------------------
+// (7) one torsion i-j-k-l (entries ejk = j->k, eji = j->i, ekl = k->l):
+//     energies into etor/econj, adjoints deposited with atomic adds
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void torsion_eval(const DevParams* __restrict__ P, const Lists& L,
+                                             const Work& W, int ejk, int eji, int ekl, double& etor,
+                                             double& econj) {
+  const double thb = P->thb_cut, pt2 = P->p_tor2, pc2 = P->p_cot2;
+  const int j = L.bond_i[ejk], k = L.bond_j[ejk], i = L.bond_j[eji], l = L.bond_j[ekl];
+  const int ti = L.type_s[i], tj = L.type_s[j], tk = L.type_s[k], tl = L.type_s[l];
+  const TorsP& tp = P->tors[((ti * NT + tj) * NT + tk) * NT + tl];
+  const double4 bjk = W.bo[ejk];
+  const double bij = W.bo[eji].x, bkl = W.bo[ekl].x;
+  // f11 of the central bond
+  const double Dsum = W.ast[j].Dang + W.ast[k].Dang;
+  const double et3 = exp(-P->p_tor3 * Dsum), et4 = exp(P->p_tor4 * Dsum);
+  const double f11d = 1.0 + et3 + et4;
+  const double f11 = (2.0 + et3) / f11d;
+  const double df11 = (-P->p_tor3 * et3 * f11d - (2.0 + et3) * (-P->p_tor3 * et3 + P->p_tor4 * et4)) /
+                      (f11d * f11d);
+  const double Bij = bij - thb, Bjk = bjk.x - thb, Bkl = bkl - thb;
+  const double xij = exp(-pt2 * Bij), xjk = exp(-pt2 * Bjk), xkl = exp(-pt2 * Bkl);
+  const double hij = 1.0 - xij, hjk = 1.0 - xjk, hkl = 1.0 - xkl;
+  const double dhij = pt2 * xij, dhjk = pt2 * xjk, dhkl = pt2 * xkl;
+  const double cij = exp(-pc2 * sqr(Bij - 1.5)), cjk = exp(-pc2 * sqr(Bjk - 1.5)),
+               ckl = exp(-pc2 * sqr(Bkl - 1.5));
+  const double pi2 = 2.0 - bjk.y - f11;
+  // geometry: b1 = x_j - x_i = -r_ji, b2 = x_k - x_j, b3 = x_l - x_k
+  const double4 r1v = W.bd[eji], r2v = W.bd[ejk], r3v = W.bd[ekl];
+  const double3 b1 = make_double3(-r1v.x, -r1v.y, -r1v.z), b2 = d3(r2v), b3 = d3(r3v);
+  const double l1 = r1v.w, l2 = r2v.w, l3 = r3v.w;
+  const double c1 = -dot(b1, b2) / (l1 * l2);   // cos of angle i-j-k
+  const double c2 = -dot(b2, b3) / (l2 * l3);   // cos of angle j-k-l
+  const double s1 = sqrt(fmax(1.0 - c1 * c1, 0.0)), s2 = sqrt(fmax(1.0 - c2 * c2, 0.0));
+  const double3 m = cross(b1, b2), nv = cross(b2, b3);
+  const double nm = fmax(sqrt(dot(m, m)), 1e-20), nn = fmax(sqrt(dot(nv, nv)), 1e-20);
+  const double cw = dot(m, nv) / (nm * nn);
+  const double ss = s1 * s2;
+  const double f10 = hij * hjk * hkl;
+  const double exv = exp(tp.p_tor1 * pi2 * pi2);
+  const double c2w = 2.0 * cw * cw - 1.0;
+  const double c3w = 4.0 * cw * cw * cw - 3.0 * cw;
+  const double Vt = 0.5 * (tp.V1 * (1.0 + cw) + tp.V2 * exv * (1.0 - c2w) + tp.V3 * (1.0 + c3w));
+  const double Et = f10 * ss * Vt;
+  const double f12 = cij * cjk * ckl;
+  const double Ec = tp.p_cot1 * f12 * (1.0 + (cw * cw - 1.0) * ss);
+  etor += Et;
+  econj += Ec;
+  // scalar adjoints
+  const double dVt_dcw = 0.5 * (tp.V1 - 4.0 * tp.V2 * exv * cw + tp.V3 * (12.0 * cw * cw - 3.0));
+  // d exv / d BOpi_jk = d exv / d f11 = -2 p_tor1 pi2 exv
+  const double dex = 0.5 * tp.V2 * (1.0 - c2w) * exv * tp.p_tor1 * 2.0 * pi2 * (-1.0);
+  const double gPjk = f10 * ss * dex;
+  const double gD = f10 * ss * dex * df11;
+  const double gss = f10 * Vt + tp.p_cot1 * f12 * (cw * cw - 1.0);
+  const double gcw = f10 * ss * dVt_dcw + tp.p_cot1 * f12 * 2.0 * cw * ss;
+  const double gBij = dhij * hjk * hkl * ss * Vt + Ec * (-2.0 * pc2 * (Bij - 1.5));
+  const double gBjk = hij * dhjk * hkl * ss * Vt + Ec * (-2.0 * pc2 * (Bjk - 1.5));
+  const double gBkl = hij * hjk * dhkl * ss * Vt + Ec * (-2.0 * pc2 * (Bkl - 1.5));
+  // cos w gradients
+  const double inm = 1.0 / (nm * nn);
+  const double3 Gm = axpy(-cw / (nm * nm), m, scale(inm, nv));
+  const double3 Gn = axpy(-cw / (nn * nn), nv, scale(inm, m));
+  const double3 dcw_b1 = cross(b2, Gm);
+  const double3 dcw_b2 = add3(cross(Gm, b1), cross(b3, Gn));
+  const double3 dcw_b3 = cross(Gn, b2);
+  // sin = sqrt(1 - c^2): d sin / d c = -c / sin
+  const double gc1 = s1 > 1e-10 ? gss * s2 * (-c1 / s1) : 0.0;
+  const double gc2 = s2 > 1e-10 ? gss * s1 * (-c2 / s2) : 0.0;
+  const double i12 = 1.0 / (l1 * l2), i23 = 1.0 / (l2 * l3);
+  const double3 dc1_b1 = axpy(-c1 / (l1 * l1), b1, scale(-i12, b2));
+  const double3 dc1_b2 = axpy(-c1 / (l2 * l2), b2, scale(-i12, b1));
+  const double3 dc2_b2 = axpy(-c2 / (l2 * l2), b2, scale(-i23, b3));
+  const double3 dc2_b3 = axpy(-c2 / (l3 * l3), b3, scale(-i23, b2));
+  const double3 gb1 = axpy(gc1, dc1_b1, scale(gcw, dcw_b1));
+  const double3 gb2 = axpy(gc2, dc2_b2, axpy(gc1, dc1_b2, scale(gcw, dcw_b2)));
+  const double3 gb3 = axpy(gc2, dc2_b3, scale(gcw, dcw_b3));
+  // entry j->i holds r_ji = -b1; j->k holds b2; k->l holds b3
+  atomic_add3(&W.gvec[eji], -gb1.x, -gb1.y, -gb1.z);
+  atomic_add3(&W.gvec[ejk], gb2);
+  atomic_add3(&W.gvec[ekl], gb3);
+  atomicAdd(&W.gbo[eji].x, gBij);
+  atomicAdd(&W.gbo[ejk].x, gBjk);
+  atomicAdd(&W.gbo[ejk].y, gPjk);
+  atomicAdd(&W.gbo[ekl].x, gBkl);
+  atomicAdd(&W.gS[j], gD);
+  atomicAdd(&W.gS[k], gD);
+}
+
+// ---------------------------------------------------------------------------
+// (8) one hydrogen-bond term X-H...Z from the H-X bond order, r_hX (with its
+//     length in w) and r_hZ = (dx, dy, dz)
+// ---------------------------------------------------------------------------
+struct HbTerm {
+  double E, dE_dbo;
+  double3 g_rx, g_rz;   // dE/d(x_X - x_h), dE/d(x_Z - x_h)
+};
+
+__device__ __forceinline__ HbTerm hb_term(const HbP& hp, double bo, double4 rx, double dx, double dy,
+                                          double dz) {
+  HbTerm o;
+  const double ilx = 1.0 / rx.w;
+  const double rz = sqrt(dx * dx + dy * dy + dz * dz);
+  const double ilz = 1.0 / rz;
+  const double c = (rx.x * dx + rx.y * dy + rx.z * dz) * ilx * ilz;
+  const double hc = 0.5 * (1.0 - c);
+  const double s4 = hc * hc;
+  const double ds4 = -hc;                 // d s4 / d c
+  const double eb = exp(-hp.p_hb2 * bo);
+  const double fbo = 1.0 - eb, dfbo = hp.p_hb2 * eb;
+  const double fr = exp(-hp.p_hb3 * (hp.r0hb * ilz + rz / hp.r0hb - 2.0));
+  const double dfr = fr * (-hp.p_hb3) * (-hp.r0hb * ilz * ilz + 1.0 / hp.r0hb);
+  o.E = hp.p_hb1 * fbo * fr * s4;
+  o.dE_dbo = hp.p_hb1 * dfbo * fr * s4;
+  const double gc = hp.p_hb1 * fbo * fr * ds4;
+  const double grz = hp.p_hb1 * fbo * dfr * s4;
+  o.g_rx = make_double3(gc * (dx * ilx * ilz - c * rx.x * ilx * ilx), gc * (dy * ilx * ilz - c * rx.y * ilx * ilx),
+                        gc * (dz * ilx * ilz - c * rx.z * ilx * ilx));
+  o.g_rz = make_double3(gc * (rx.x * ilx * ilz - c * dx * ilz * ilz) + grz * dx * ilz,
+                        gc * (rx.y * ilx * ilz - c * dy * ilz * ilz) + grz * dy * ilz,
+                        gc * (rx.z * ilx * ilz - c * dz * ilz * ilz) + grz * dz * ilz);
+  return o;
+}
+
+// ---------------------------------------------------------------------------
+// (9) one van der Waals + Coulomb pair at squared distance r2: tapered
+//     shielded Morse with inner wall, tapered shielded Coulomb.  qq = q_i q_j
+//     C_ele.  Returns the two energies and f = (dE/dr) / r.
+// ---------------------------------------------------------------------------
+struct NbP { double D, alpha, inv_rv, gw_pow, g3, e_core, a_core, inv_rc; };
+
+struct NbOut { double ev, eq, f; };
+
+__device__ __forceinline__ NbOut nb_pair(const NbP& p, double iR, double pv, double ipv, double qq,
+                                         double r2) {
+  const double ir = rsqrt(r2);
+  const double r = r2 * ir;
+  // taper
+  const double u = r * iR, u2 = u * u, u3 = u2 * u, u4 = u2 * u2;
+  const double tap = 20.0 * u4 * u3 - 70.0 * u4 * u2 + 84.0 * u4 * u - 35.0 * u4 + 1.0;
+  const double dtap = (140.0 * u3 * u3 - 420.0 * u4 * u + 420.0 * u4 - 140.0 * u3) * iR;
+  // shielded Morse with inner wall
+  const double pw = exp(pv * log(r));
+  const double sum = pw + p.gw_pow;
+  const double isum = 1.0 / sum;
+  const double f13 = exp(ipv * log(sum));
+  const double df13 = f13 * isum * pw * ir;
+  const double t = 1.0 - f13 * p.inv_rv;
+  const double e2 = exp(0.5 * p.alpha * t);
+  const double e1 = e2 * e2;
+  const double ev = p.D * (e1 - 2.0 * e2);
+  const double dev = -p.D * p.alpha * p.inv_rv * (e1 - e2) * df13;
+  const double ecr = p.e_core * exp(p.a_core * (1.0 - r * p.inv_rc));
+  const double decr = -ecr * p.a_core * p.inv_rc;
+  // shielded Coulomb: den = (r^3 + gamma^-3)^(1/3), 1/s3 = (1/den)^3
+  const double s3 = r2 * r + p.g3;
+  const double iden = 1.0 / cbrt(s3);
+  const double eq = qq * iden;
+  const double deq = -eq * r2 * (iden * iden * iden);
+  const double Ev = ev + ecr;
+  NbOut o;
+  o.ev = tap * Ev;
+  o.eq = tap * eq;
+  o.f = (dtap * (Ev + eq) + tap * (dev + decr + deq)) * ir;
+  return o;
+}
+
+__device__ __forceinline__ NbP nb_params(const PairP& p) {
+  return NbP{p.D_vdw, p.alpha, p.inv_r_vdw, p.gw_pow, p.g3, p.e_core, p.a_core, p.inv_r_core};
+}
+
+// ---------------------------------------------------------------------------
+// backward
+// ---------------------------------------------------------------------------
+// (10) total dE/dS of atom i: own terms, coalition terms of angles centred on
+//      neighbours (stored in the neighbour's entry), the Sigma_pi term of the
+//      neighbours' over/under-coordination, and SBO's valence term
+__device__ __forceinline__ void back_s_atom(const Lists& L, const Work& W, int i) {
+  const AtomState st = W.ast[i];
+  double g = W.gS[i];
+  double gsig = 0.0;
+  for (int e = L.bond_off[i]; e < L.bond_off[i + 1]; ++e) {
+    const int m = L.bond_mir[e];
+    const int j = L.bond_j[e];
+    g += W.gbo[m].w;
+    const double4 b = W.bo[e];
+    gsig += W.gSig[j] * (b.y + b.z);
+  }
+  g += (1.0 + st.dnlp) * gsig;
+  // the angle terms accumulated dE/dSBO2; convert to dE/dSBO for the next stage
+  const double gsbo = W.gSBO[i] * st.dSBO2;
+  W.gSBO[i] = gsbo;
+  g += gsbo * (1.0 - st.prod) * st.dW;
+  W.gStot[i] = g;
+}
+
+// (11) through the correction to the uncorrected orders and Delta'
+__device__ __forceinline__ void back_corr_atom(const DevParams* __restrict__ P, const Lists& L,
+                                               const Work& W, int i) {
+  const int ti = L.type_s[i];
+  for (int e = L.bond_off[i]; e < L.bond_off[i + 1]; ++e) {
+    const int j = L.bond_j[e];
+    const int m = L.bond_mir[e];
+    const int tj = L.type_s[j];
+    const bool lo = i < j;
+    const int a = lo ? i : j, b = lo ? j : i;
+    const int ea = lo ? e : m, eb = lo ? m : e;
+    const int ta = lo ? ti : tj, tb = lo ? tj : ti;
+    const double4 bp = W.bop[e];
+    const double4 bo = W.bo[e];
+    const AtomState sa = W.ast[a], sb = W.ast[b];
+    const double4 ga = W.gbo[ea], gb = W.gbo[eb];
+    const double gsa = W.gSBO[a], gsb = W.gSBO[b];
+    const double b2 = bo.x * bo.x, b7 = b2 * b2 * b2 * bo.x;
+    const double gBO = ga.x + gb.x + W.gStot[a] + W.gStot[b] +
+                       8.0 * b7 * (gsa * sa.prod * sa.W + gsb * sb.prod * sb.W);
+    const double gBOp = ga.y + gb.y + gsa + gsb;
+    const double gBOpp = ga.z + gb.z + gsa + gsb;
+    const Corr c = correction(P, bp.w, P->atom[ta].val, P->atom[tb].val, W.dp[a], W.dp[b],
+                              P->pair[ti * NT + tj]);
+    const double F = c.f1 * c.f4 * c.f5, G = c.f1 * c.f1 * c.f4 * c.f5;
+    const double gF = gBO * bp.w;
+    const double gG = gBOp * bp.y + gBOpp * bp.z;
+    const double gf1 = gF * c.f4 * c.f5 + gG * 2.0 * c.f1 * c.f4 * c.f5;
+    const double gf4 = gF * c.f1 * c.f5 + gG * c.f1 * c.f1 * c.f5;
+    const double gf5 = gF * c.f1 * c.f4 + gG * c.f1 * c.f1 * c.f4;
+    const double gBOt = gBO * F + gf4 * c.df4_dbo + gf5 * c.df5_dbo;   // uncorrected total
+    const double gPi = gBOp * G, gPp = gBOpp * G;                       // uncorrected pi parts
+    const double own = lo ? gf1 * c.df1_da + gf4 * c.df4_da : gf1 * c.df1_db + gf5 * c.df5_db;
+    W.gup[e] = make_double4(gBOt, gPi, gPp, own);
+  }
+}
+
+// (12) dE/dDelta' of atom i (Delta' and Delta'boc both are sums of BO')
+__device__ __forceinline__ void back_dp_atom(const Lists& L, const Work& W, int i) {
+  double g = 0.0;
+  for (int e = L.bond_off[i]; e < L.bond_off[i + 1]; ++e) g += W.gup[e].w;
+  W.gDp[i] = g;
+}
+
+// (13) force on atom i: nonbonded/H-bond part plus its bond entries
+__device__ __forceinline__ double3 force_atom(const Lists& L, const Work& W, int i) {
+  const double4 f0 = W.fnb[i];
+  double fx = f0.x, fy = f0.y, fz = f0.z;
+  const double gi = W.gDp[i];
+  for (int e = L.bond_off[i]; e < L.bond_off[i + 1]; ++e) {
+    const int j = L.bond_j[e];
+    const int m = L.bond_mir[e];
+    const double gj = W.gDp[j];
+    const double gsum = i < j ? gi + gj : gj + gi;
+    const double4 gu = W.gup[e];
+    const double4 db = W.dbop[e];
+    const double dEdr = (gu.x + gsum) * (db.x + db.y + db.z) + gu.y * db.y + gu.z * db.z;
+    const double4 d = W.bd[e];
+    const double s = dEdr / d.w;
+    const double4 ge = W.gvec[e], gm = W.gvec[m];
+    fx += s * d.x + ge.x - gm.x;
+    fy += s * d.y + ge.y - gm.y;
+    fz += s * d.z + ge.z - gm.z;
+  }
+  return make_double3(fx, fy, fz);
+}
+
+}  // namespace rx
