@@ -68,6 +68,107 @@ def cpu_baseline(params, seconds_cap=60.0):
                       f"of the same recipe (1,120 units, 69.2 A box): {t:.2f} s single-threaded"}
 
 
+def bench_batched(ff, steps: int, warmup: int):
+    """4,096 non-periodic clusters (sizes uniform in 10-300, seed 3) in one persistent
+    graph-replayed launch with the autotuned configuration, against the plain path on the
+    same clusters (a) packed 40 A apart in one non-periodic system, (b) one plain
+    build_lists + compute_forces call per cluster (timed on the first 256 clusters and
+    scaled by atom count)."""
+    import numpy as np
+    import torch
+
+    import reaxff_synth as rs
+    from paper_1706_07772_amd import SCHEDULES, Batch
+
+    dev = torch.device("cuda:0")
+    pos, typ, q, off = rs.cluster_batch(4096, seed=3)
+    natoms = int(off[-1])
+    P = torch.tensor(pos, dtype=torch.float64, device=dev)
+    T = torch.tensor(typ, dtype=torch.int32, device=dev)
+    Q = torch.tensor(q, dtype=torch.float64, device=dev)
+    b = Batch(ff, off)
+    t0 = time.perf_counter()
+    trials = b.tune(P, T, Q, reps=3)
+    tune_s = time.perf_counter() - t0
+    cfg = b.config
+    print(f"bench: batch tuner {len(trials)} trials in {tune_s:.2f} s, best {cfg}", file=sys.stderr, flush=True)
+    f, e = b.compute(P, T, Q)
+    for _ in range(warmup):
+        b.compute(P, T, Q, f, e)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(st)
+    for _ in range(steps):
+        b.compute(P, T, Q, f, e)
+    ev1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1) / steps
+    rc, bad = b.status()
+    counts = b.counts().sum(0)
+    b.close()
+
+    # (a) the plain path on the packed system
+    nc = off.size - 1
+    side = int(np.ceil(nc ** (1.0 / 3.0)))
+    g = np.stack(np.unravel_index(np.arange(nc), (side, side, side)), axis=1).astype(np.float64)
+    sizes = np.diff(off)
+    packed = pos + 40.0 * np.repeat(g, sizes, axis=0)
+    PP = torch.tensor(packed, dtype=torch.float64, device=dev)
+    fp = torch.empty_like(PP)
+    ep = torch.empty(12, dtype=torch.float64, device=dev)
+
+    def plain_step():
+        ff.build_lists(PP, T, None)
+        ff.compute_forces(PP, T, Q, None, fp, ep)
+
+    for _ in range(warmup):
+        plain_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plain_step()
+    torch.cuda.synchronize()
+    ms_packed = 1e3 * (time.perf_counter() - t0) / steps
+
+    # (b) one plain call pair per cluster, first 256 clusters
+    ns = 256
+    subs = [(P[off[c]:off[c + 1]].contiguous(), T[off[c]:off[c + 1]].contiguous(),
+             Q[off[c]:off[c + 1]].contiguous()) for c in range(ns)]
+    outs = [(torch.empty_like(x), torch.empty(12, dtype=torch.float64, device=dev)) for x, _, _ in subs]
+    for (x, t, qq), (fo, eo) in zip(subs, outs):
+        ff.build_lists(x, t, None)
+        ff.compute_forces(x, t, qq, None, fo, eo)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for (x, t, qq), (fo, eo) in zip(subs, outs):
+        ff.build_lists(x, t, None)
+        ff.compute_forces(x, t, qq, None, fo, eo)
+    torch.cuda.synchronize()
+    sub_atoms = int(off[ns])
+    loop_rate = sub_atoms / (time.perf_counter() - t0)
+
+    rate = natoms / (ms * 1e-3)
+    best_ms = min(t for _, t in trials)
+    worst_ms = max(t for _, t in trials)
+    return {
+        "workload": "4,096 clusters, 10-300 atoms (uniform), non-periodic, seed 3",
+        "atoms": natoms, "status": rc, "atom_steps_per_s": rate, "ms_per_launch": ms,
+        "wall_ms_per_launch": 1e3 * wall / steps,
+        "config": {"block": cfg[0], "schedule": SCHEDULES[cfg[1]], "wg_per_cu": cfg[2]},
+        "tuner": {"trials": len(trials), "seconds": tune_s, "best_ms": best_ms, "worst_ms": worst_ms},
+        "plain_packed": {"ms_per_step": ms_packed, "atom_steps_per_s": natoms / (ms_packed * 1e-3),
+                          "speedup_of_batched": ms_packed / ms},
+        "plain_loop": {"clusters_timed": ns, "atom_steps_per_s": loop_rate,
+                       "speedup_of_batched": rate / loop_rate},
+        "counts": {"angles": int(counts[0]), "torsions": int(counts[1]), "hbonds": int(counts[2]),
+                   "far_pairs": int(counts[3]), "bonds": int(counts[4])},
+        "kernel_stats": "profiles/batch_clusters_4096.md",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +178,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without per-kernel events (value only)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-clusters measurement")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the batched-clusters measurement (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -91,6 +196,11 @@ def main():
     from paper_1706_07772_amd.binding import load_library
 
     params = rs.draw_params(0)
+    if args.batched_only:
+        ff = ReaxFF(params)
+        out = bench_batched(ff, args.steps, args.warmup)
+        print(json.dumps({"batched": out}), flush=True)
+        return
     system = rs.workload(args.workload)
     n = system.n
     dev = torch.device("cuda:0")
@@ -169,6 +279,11 @@ def main():
                         "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s", "frac": None,
                         "traffic": None, "avg_ms": kernels[dom]["ms_avg"]}
 
+    batched = None
+    if not args.no_batched:
+        print("bench: batched clusters", file=sys.stderr, flush=True)
+        batched = bench_batched(ff, args.steps, args.warmup)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
@@ -192,6 +307,7 @@ def main():
                    "cutoffs_A": {"nonbonded": 10.0, "bond": 5.0, "hbond": 7.5}, "bo_cut": 0.01},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched": batched,
         "phases_ms": phases,
         "counts": counts,
         "kernels_ms_avg": {k: round(v["ms_avg"], 4) for k, v in kernels.items()},
