@@ -246,6 +246,79 @@ int reaxff_batch_tune(reaxff_batch* b, const double* pos, const int32_t* type,
                       hipStream_t stream, int32_t reps, int32_t max_trials,
                       reaxff_batch_config* trials, double* trial_ms, int32_t* ntrials);
 
+/* ---- Learned surrogate with the plain evaluation as fallback -------------
+ *
+ * An ensemble of per-element neural networks predicts per-atom energies
+ * from atom-centred descriptors of the neighbours within 5 A (Behler-
+ * Parrinello radial functions: 16 per neighbour element; angular power
+ * spectrum: 16 per unordered neighbour-element pair; 224 features), and
+ * forces as the exact negative gradient of that energy.  Each network maps
+ * x = (G - shift) * scale through 224 -> 128 -> 128 -> 1 with SiLU
+ * activations; products run on BF16 matrix cores with FP32 accumulation.
+ * Parameters are FP32, per member and element network, flattened as
+ * W1[224][128], b1[128], W2[128][128], b2[128], w3[128], b3
+ * (reaxff_surrogate_param_count() floats per network; networks ordered
+ * [member][element]).  The plain FP64 force evaluation of this library is
+ * the fallback wherever the members disagree (reaxff_surrogate_gated_forces).
+ * Energies in kcal/mol, forces in kcal/(mol A), as elsewhere.
+ */
+typedef struct reaxff_surrogate reaxff_surrogate;
+
+/* Floats per element network. */
+int64_t reaxff_surrogate_param_count(void);
+
+/* An ensemble of `members` (1..16) on the device of ctx; the neighbour lists
+ * come from an internal context with ctx's parameters and a 5 A cutoff.
+ * Parameters start at zero, shift at 0 and scale at 1. */
+int reaxff_surrogate_create(reaxff_ctx* ctx, int32_t members, reaxff_surrogate** out);
+void reaxff_surrogate_destroy(reaxff_surrogate* s);
+const char* reaxff_surrogate_last_error(const reaxff_surrogate* s);
+
+/* [host] theta (members*4*param_count), shift and scale (224 each); any may be
+ * NULL to leave it unchanged.  Setting theta resets the Adam state. */
+int reaxff_surrogate_set_params(reaxff_surrogate* s, const float* theta, const float* shift,
+                                const float* scale);
+int reaxff_surrogate_get_params(reaxff_surrogate* s, float* theta, float* shift, float* scale);
+
+/* Descriptors G [dev] (n, 224) FP32, caller order.  pos/type/box as in
+ * reaxff_build_lists.  Synchronises once (list sizes). */
+int reaxff_surrogate_descriptors(reaxff_surrogate* s, int64_t n, const double* pos,
+                                 const int32_t* type, const double* box, float* G,
+                                 hipStream_t stream);
+
+/* Every member on one configuration: energies [dev] (members) FP64 totals;
+ * optional [dev] outputs (NULL to skip): eatom (members, n) per-atom energies,
+ * forces (members, n, 3), fmean (n, 3) FP64 ensemble mean force, sigma (n)
+ * ensemble spread sqrt(mean_m |F_i^m - Fbar_i|^2).  Caller order. */
+int reaxff_surrogate_evaluate(reaxff_surrogate* s, int64_t n, const double* pos,
+                              const int32_t* type, const double* box, double* energies,
+                              float* eatom, float* forces, double* fmean, float* sigma,
+                              hipStream_t stream);
+
+/* One training step of every member on one reference frame (eref total
+ * energy, fref [dev] (n, 3) forces, caller order): loss [dev] (members)
+ * = wE ((E - eref)/n)^2 + wF/(3n) sum_i |F_i - fref_i|^2 before the step,
+ * its parameter gradient by forward-over-reverse differentiation, then one
+ * Adam step of size lr (none if lr <= 0; the gradient stays readable). */
+int reaxff_surrogate_train_step(reaxff_surrogate* s, int64_t n, const double* pos,
+                                const int32_t* type, const double* box, double eref,
+                                const double* fref, double wE, double wF, double lr,
+                                double* loss, hipStream_t stream);
+/* [host] (members*4*param_count) gradient of the last train_step. */
+int reaxff_surrogate_get_grad(reaxff_surrogate* s, float* grad);
+
+/* Gated forces: the ensemble mean force, except on atoms whose spread
+ * exceeds `threshold` (kcal/(mol A)), which take the plain FP64 ReaxFF force
+ * computed by `plain` (a context of this library, charges q [dev]).  The
+ * plain evaluation runs only when some atom is flagged.  forces [dev] (n,3)
+ * FP64, mask [dev] (n) 1 = fallback, energies [dev] (members) surrogate
+ * totals, *nflagged [host] number of flagged atoms.  Synchronises once. */
+int reaxff_surrogate_gated_forces(reaxff_surrogate* s, reaxff_ctx* plain, int64_t n,
+                                  const double* pos, const int32_t* type, const double* q,
+                                  const double* box, double threshold, double* forces,
+                                  uint8_t* mask, double* energies, int64_t* nflagged,
+                                  hipStream_t stream);
+
 const char* reaxff_strerror(int code);
 const char* reaxff_last_error(const reaxff_ctx* ctx);
 

@@ -50,6 +50,10 @@ MU_A = 1.0 + 0.5 * np.arange(NA)          # 1.0 .. 4.5 A
 ETA_A = 0.5 / 0.5 ** 2
 PAIRS = [(b, c) for b in range(4) for c in range(b, 4)]
 PAIR_INDEX = {bc: p for p, bc in enumerate(PAIRS)}
+# ordered element pair (b, c) -> unordered pair index when b <= c, else -1
+PAIR_OF = np.full((4, 4), -1, dtype=np.int64)
+for _p, (_b, _c) in enumerate(PAIRS):
+    PAIR_OF[_b, _c] = _p
 NDESC = 4 * NR + len(PAIRS) * 2 * NA      # 224
 H = 128
 NPAR = NDESC * H + H + H * H + H + H + 1  # one element network
@@ -120,16 +124,15 @@ def descriptors(pos, types, box, nb=None):
         An = np.exp(-ETA_A * (r[:, None] - MU_A[None, :]) ** 2) * fc[:, None]      # (m, 8)
         u = d / r[:, None]
         cos = u @ u.T                                                             # (m, m)
-        for j in range(sel.size):
-            for k in range(sel.size):
-                b, c = t[j], t[k]
-                if b > c:
-                    continue
-                p = PAIR_INDEX[(b, c)]
-                w = An[j] * An[k]
-                base = 4 * NR + 2 * NA * p
-                G[i, base:base + NA] += w * cos[j, k]
-                G[i, base + NA:base + 2 * NA] += w * cos[j, k] ** 2
+        pj = PAIR_OF[t[:, None], t[None, :]]                                      # (m, m)
+        for p in range(len(PAIRS)):
+            sel_p = (pj == p)                     # ordered pairs (j of b, k of c), b <= c
+            if not sel_p.any():
+                continue
+            base = 4 * NR + 2 * NA * p
+            for l in (1, 2):
+                wjk = np.where(sel_p, cos ** l, 0.0)
+                G[i, base + (l - 1) * NA:base + l * NA] = np.einsum("jk,jn,kn->n", wjk, An, An)
     return G
 
 
@@ -158,24 +161,23 @@ def descriptor_vjp(pos, types, box, g, nb=None):
         An = ea * fc[:, None]
         dAn = ea * (-2.0 * ETA_A * (r[:, None] - MU_A[None, :])) * fc[:, None] + ea * dfc[:, None]
         cos = u @ u.T
-        for j in range(sel.size):
-            for k in range(sel.size):
-                b, c = t[j], t[k]
-                if b > c:
-                    continue
-                p = PAIR_INDEX[(b, c)]
-                base = 4 * NR + 2 * NA * p
-                g1 = g[i, base:base + NA]
-                g2 = g[i, base + NA:base + 2 * NA]
-                cjk = cos[j, k]
-                # T = A_n(r_j) A_n(r_k) (g1 c + g2 c^2), summed over n
-                s_val = (g1 * cjk + g2 * cjk * cjk)
-                dT_drj = (dAn[j] * An[k] * s_val).sum()
-                dT_drk = (An[j] * dAn[k] * s_val).sum()
-                dT_dc = (An[j] * An[k] * (g1 + 2.0 * g2 * cjk)).sum()
-                # dc/dd_j = (u_k - c u_j) / r_j
-                gd[j] += dT_drj * u[j] + dT_dc * (u[k] - cjk * u[j]) / r[j]
-                gd[k] += dT_drk * u[k] + dT_dc * (u[j] - cjk * u[k]) / r[k]
+        pj = PAIR_OF[t[:, None], t[None, :]]
+        ok = pj >= 0
+        pjc = np.where(ok, pj, 0)
+        base = 4 * NR + 2 * NA * pjc                                  # (m, m)
+        idx = base[:, :, None] + np.arange(NA)[None, None, :]
+        g1 = np.where(ok[:, :, None], g[i][idx], 0.0)                 # (m, m, 8)
+        g2 = np.where(ok[:, :, None], g[i][idx + NA], 0.0)
+        # T_jk = sum_n A_n(r_j) A_n(r_k) (g1 c + g2 c^2)
+        s_val = g1 * cos[:, :, None] + g2 * (cos ** 2)[:, :, None]
+        dT_drj = np.einsum("jn,kn,jkn->jk", dAn, An, s_val)
+        dT_drk = np.einsum("jn,kn,jkn->jk", An, dAn, s_val)
+        dT_dc = np.einsum("jn,kn,jkn->jk", An, An, g1 + 2.0 * g2 * cos[:, :, None])
+        # dc/dd_j = (u_k - c u_j) / r_j, dc/dd_k = (u_j - c u_k) / r_k
+        gd += dT_drj.sum(1)[:, None] * u
+        gd += (dT_dc @ u - (dT_dc * cos).sum(1)[:, None] * u) / r[:, None]
+        gd += dT_drk.sum(0)[:, None] * u
+        gd += (dT_dc.T @ u - (dT_dc * cos).sum(0)[:, None] * u) / r[:, None]
         # d_j = x_j - x_i
         np.add.at(F, sel, -gd)
         F[i] += gd.sum(0)

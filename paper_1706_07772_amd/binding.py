@@ -92,6 +92,19 @@ def load_library():
     lib.reaxff_batch_counts.argtypes = [vp, vp]
     lib.reaxff_batch_tune.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, i32, vp, vp,
                                       ctypes.POINTER(i32)]
+    lib.reaxff_surrogate_param_count.restype = i64
+    lib.reaxff_surrogate_create.argtypes = [vp, i32, ctypes.POINTER(vp)]
+    lib.reaxff_surrogate_destroy.argtypes = [vp]
+    lib.reaxff_surrogate_last_error.restype = ctypes.c_char_p
+    lib.reaxff_surrogate_last_error.argtypes = [vp]
+    lib.reaxff_surrogate_set_params.argtypes = [vp, vp, vp, vp]
+    lib.reaxff_surrogate_get_params.argtypes = [vp, vp, vp, vp]
+    lib.reaxff_surrogate_descriptors.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+    lib.reaxff_surrogate_evaluate.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.reaxff_surrogate_train_step.argtypes = [vp, i64, vp, vp, vp, _d, vp, _d, _d, _d, vp, vp]
+    lib.reaxff_surrogate_get_grad.argtypes = [vp, vp]
+    lib.reaxff_surrogate_gated_forces.argtypes = [vp, vp, i64, vp, vp, vp, vp, _d, vp, vp, vp,
+                                                  ctypes.POINTER(i64), vp]
     lib.reaxff_profile.argtypes = [vp, i32]
     lib.reaxff_profile_read.argtypes = [vp, i32, vp, vp, vp]
     lib.reaxff_last_error.restype = ctypes.c_char_p
@@ -337,3 +350,118 @@ class Batch:
                                                     int(reps), int(max_trials), trials, ms,
                                                     ctypes.byref(nt)))
         return [(trials[k].as_tuple(), float(ms[k])) for k in range(nt.value)]
+
+
+NDESC = 224
+
+
+class Surrogate:
+    """An ensemble of per-element networks on the GPU (reaxff_surrogate_*).
+
+    Parameters are float32 arrays shaped (members, 4, param_count); shift and
+    scale (224,) float32.  Energies kcal/mol, forces kcal/(mol A).
+    """
+
+    def __init__(self, ff: ReaxFF, members: int = 4):
+        self._ff = ff
+        self._lib = ff._lib
+        self.members = int(members)
+        self.npar = int(self._lib.reaxff_surrogate_param_count())
+        h = ctypes.c_void_p()
+        ff._check(self._lib.reaxff_surrogate_create(ff._h, self.members, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.reaxff_surrogate_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != 0:
+            raise ReaxFFError(rc, self._lib.reaxff_surrogate_last_error(self._h).decode())
+
+    def set_params(self, theta=None, shift=None, scale=None):
+        def arr(x, shape):
+            if x is None:
+                return None
+            a = np.ascontiguousarray(x, dtype=np.float32)
+            assert a.size == int(np.prod(shape)), (a.shape, shape)
+            return a
+        t = arr(theta, (self.members, 4, self.npar))
+        sh = arr(shift, (NDESC,))
+        sc = arr(scale, (NDESC,))
+        self._check(self._lib.reaxff_surrogate_set_params(
+            self._h, t.ctypes.data if t is not None else None, sh.ctypes.data if sh is not None else None,
+            sc.ctypes.data if sc is not None else None))
+
+    def get_params(self):
+        t = np.zeros((self.members, 4, self.npar), dtype=np.float32)
+        sh = np.zeros(NDESC, dtype=np.float32)
+        sc = np.zeros(NDESC, dtype=np.float32)
+        self._check(self._lib.reaxff_surrogate_get_params(self._h, t.ctypes.data, sh.ctypes.data, sc.ctypes.data))
+        return t, sh, sc
+
+    def get_grad(self):
+        g = np.zeros((self.members, 4, self.npar), dtype=np.float32)
+        self._check(self._lib.reaxff_surrogate_get_grad(self._h, g.ctypes.data))
+        return g
+
+    @staticmethod
+    def _boxarg(box):
+        return ReaxFF._boxarg(box)
+
+    def descriptors(self, pos, type_, box=None):
+        n = pos.shape[0]
+        G = torch.empty((n, NDESC), dtype=torch.float32, device=pos.device)
+        b, bp = self._boxarg(box)
+        self._check(self._lib.reaxff_surrogate_descriptors(self._h, n, _ptr(pos), _ptr(type_), bp, _ptr(G),
+                                                           _stream()))
+        return G
+
+    def evaluate(self, pos, type_, box=None):
+        """dict: energies (M,) float64, eatom (M,n), forces (M,n,3) float32, fmean (n,3) float64,
+        sigma (n,) float32 -- cuda tensors, caller order."""
+        n = pos.shape[0]
+        M = self.members
+        d = pos.device
+        out = dict(energies=torch.empty(M, dtype=torch.float64, device=d),
+                   eatom=torch.empty((M, n), dtype=torch.float32, device=d),
+                   forces=torch.empty((M, n, 3), dtype=torch.float32, device=d),
+                   fmean=torch.empty((n, 3), dtype=torch.float64, device=d),
+                   sigma=torch.empty(n, dtype=torch.float32, device=d))
+        b, bp = self._boxarg(box)
+        self._check(self._lib.reaxff_surrogate_evaluate(
+            self._h, n, _ptr(pos), _ptr(type_), bp, _ptr(out["energies"]), _ptr(out["eatom"]),
+            _ptr(out["forces"]), _ptr(out["fmean"]), _ptr(out["sigma"]), _stream()))
+        return out
+
+    def train_step(self, pos, type_, box, eref: float, fref, wE: float = 1.0, wF: float = 1.0,
+                   lr: float = 1e-3):
+        """Loss of every member before the step (float64 cuda tensor (M,))."""
+        loss = torch.empty(self.members, dtype=torch.float64, device=pos.device)
+        assert fref.dtype == torch.float64 and fref.is_contiguous() and fref.shape == pos.shape
+        b, bp = self._boxarg(box)
+        self._check(self._lib.reaxff_surrogate_train_step(
+            self._h, pos.shape[0], _ptr(pos), _ptr(type_), bp, float(eref), _ptr(fref), float(wE), float(wF),
+            float(lr), _ptr(loss), _stream()))
+        return loss
+
+    def gated_forces(self, plain: ReaxFF, pos, type_, q, box, threshold: float):
+        """(forces (n,3) float64, mask (n,) uint8, energies (M,), nflagged int)."""
+        n = pos.shape[0]
+        d = pos.device
+        forces = torch.empty((n, 3), dtype=torch.float64, device=d)
+        mask = torch.empty(n, dtype=torch.uint8, device=d)
+        energies = torch.empty(self.members, dtype=torch.float64, device=d)
+        nf = ctypes.c_int64(0)
+        b, bp = self._boxarg(box)
+        self._check(self._lib.reaxff_surrogate_gated_forces(
+            self._h, plain._h, n, _ptr(pos), _ptr(type_), _ptr(q), bp, float(threshold), _ptr(forces),
+            _ptr(mask), _ptr(energies), ctypes.byref(nf), _stream()))
+        return forces, mask, energies, int(nf.value)
