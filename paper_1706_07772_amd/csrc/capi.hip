@@ -120,10 +120,13 @@ void fill_dev_params(const reaxff_params& p, const reaxff_cutoffs& c, DevParams&
 }
 
 // grid: cells at least r_nonb/2 wide, +-2 cell stencil
+// cells at least r_nonb / reach wide, so every pair within r_nonb lies within
+// +-reach cells in each dimension
 void make_grid(Grid& g, bool periodic, const double* box, const double lo[3], const double hi[3],
-               double r_nonb) {
+               double r_nonb, int reach) {
   g.periodic = periodic ? 1 : 0;
-  const double wmin = 0.5 * r_nonb;
+  g.reach = reach;
+  const double wmin = r_nonb / reach;
   for (int k = 0; k < 3; ++k) {
     double ext;
     if (periodic) {
@@ -141,8 +144,8 @@ void make_grid(Grid& g, bool periodic, const double* box, const double lo[3], co
     if (nc < 1) nc = 1;
     g.nc[k] = nc;
     g.invw[k] = nc / ext;
-    g.full[k] = nc < 5 ? 1 : 0;
-    g.span[k] = nc < 5 ? nc : 5;
+    g.full[k] = nc < 2 * reach + 1 ? 1 : 0;
+    g.span[k] = nc < 2 * reach + 1 ? nc : 2 * reach + 1;
   }
 }
 
@@ -291,12 +294,21 @@ int reaxff_build_lists(reaxff_ctx* c, int64_t n, const double* pos, const int32_
       if (!(lo[k] > -1e307) || !std::isfinite(hi[k]) || !std::isfinite(lo[k]))
         return fail(c, REAXFF_ERR_NONFINITE, "non-finite position");
   }
-  make_grid(c->grid, c->periodic, c->box, lo, hi, c->cut.r_nonb);
+  // stencil reach: +-2 cells of r_nonb/2 unless such cells would hold fewer than
+  // about 4 atoms (short cutoffs), then +-1 cell of r_nonb (fuller wavefronts)
+  int reach = 2;
+  {
+    double vol = 1.0;
+    for (int k = 0; k < 3; ++k) vol *= c->periodic ? c->box[k] : std::max(hi[k] - lo[k], 1.0);
+    const double per_cell = (double)n / vol * std::pow(0.5 * c->cut.r_nonb, 3.0);
+    if (per_cell < 4.0) reach = 1;
+  }
+  make_grid(c->grid, c->periodic, c->box, lo, hi, c->cut.r_nonb, reach);
   c->grid.shift_ok = 0;
   if (c->periodic && n > 0) {
     bool ok = true;
     for (int k = 0; k < 3; ++k)
-      ok = ok && lo[k] >= 0.0 && hi[k] < c->box[k] && c->grid.nc[k] >= 7;
+      ok = ok && lo[k] >= 0.0 && hi[k] < c->box[k] && c->grid.nc[k] >= 2 * reach + 3;
     c->grid.shift_ok = ok ? 1 : 0;
   }
   const int64_t ncell = (int64_t)c->grid.nc[0] * c->grid.nc[1] * c->grid.nc[2];

@@ -116,24 +116,25 @@ __global__ void k_gather_sorted(const double* __restrict__ pos, const int32_t* _
 
 // z ranges of a stencil column around cell z = c2, in cell units within a
 // row: [za0, za1) and [zb0, zb1).  Cells are numbered with z fastest, so the
-// 5 cells of a column (x, y, c2-2..c2+2) are one contiguous range of sorted
-// atoms, or two when the column wraps around a periodic edge.
+// 2R+1 cells of a column (x, y, c2-R..c2+R, R = g.reach) are one contiguous
+// range of sorted atoms, or two when the column wraps around a periodic edge.
 __device__ __forceinline__ void column_ranges(const Grid& g, int c2, int& za0, int& za1, int& zb0,
                                               int& zb1) {
+  const int R = g.reach;
   zb0 = zb1 = 0;
   if (g.full[2]) {
     za0 = 0; za1 = g.nc[2];
   } else if (g.periodic) {
-    if (c2 - 2 < 0) { za0 = 0; za1 = c2 + 3; zb0 = g.nc[2] + c2 - 2; zb1 = g.nc[2]; }
-    else if (c2 + 2 >= g.nc[2]) { za0 = c2 - 2; za1 = g.nc[2]; zb0 = 0; zb1 = c2 + 3 - g.nc[2]; }
-    else { za0 = c2 - 2; za1 = c2 + 3; }
+    if (c2 - R < 0) { za0 = 0; za1 = c2 + R + 1; zb0 = g.nc[2] + c2 - R; zb1 = g.nc[2]; }
+    else if (c2 + R >= g.nc[2]) { za0 = c2 - R; za1 = g.nc[2]; zb0 = 0; zb1 = c2 + R + 1 - g.nc[2]; }
+    else { za0 = c2 - R; za1 = c2 + R + 1; }
   } else {
-    za0 = c2 - 2 < 0 ? 0 : c2 - 2;
-    za1 = c2 + 3 > g.nc[2] ? g.nc[2] : c2 + 3;
+    za0 = c2 - R < 0 ? 0 : c2 - R;
+    za1 = c2 + R + 1 > g.nc[2] ? g.nc[2] : c2 + R + 1;
   }
 }
 
-// One wavefront per cell.  Every atom of a cell has the same 5x5x5 cell
+// One wavefront per cell.  Every atom of a cell has the same (2R+1)^3 cell
 // stencil, so the wavefront loads each 64-candidate chunk of a stencil column
 // once (coalesced) and tests it against each atom of its cell in turn: the
 // cell's atoms live in the lanes and are broadcast one at a time.  Accepted
@@ -171,7 +172,7 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
   int za0, za1, zb0, zb1;
   column_ranges(g, c2, za0, za1, zb0, zb1);
   // image shift of the wrapped part of the z column
-  const double szb = c2 - 2 < 0 ? g.L[2] : -g.L[2];
+  const double szb = c2 - g.reach < 0 ? g.L[2] : -g.L[2];
   for (int ig = 0; ig < m; ig += 64) {       // the cell's atoms, 64 at a time, one per lane
     const int mi = m - ig < 64 ? m - ig : 64;
     double4 xmine = make_double4(0.0, 0.0, 0.0, 0.0);
@@ -247,14 +248,14 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
       }
     };
     for (int a = 0; a < g.span[0]; ++a) {
-      int x = g.full[0] ? a : c0 + a - 2;
+      int x = g.full[0] ? a : c0 + a - g.reach;
       double sx = 0.0;
       if (g.periodic) {
         if (x < 0) { x += g.nc[0]; sx = g.L[0]; }
         else if (x >= g.nc[0]) { x -= g.nc[0]; sx = -g.L[0]; }
       } else if (x < 0 || x >= g.nc[0]) continue;
       for (int bb = 0; bb < g.span[1]; ++bb) {
-        int y = g.full[1] ? bb : c1 + bb - 2;
+        int y = g.full[1] ? bb : c1 + bb - g.reach;
         double sy = 0.0;
         if (g.periodic) {
           if (y < 0) { y += g.nc[1]; sy = g.L[1]; }

@@ -62,13 +62,14 @@ struct DevParams {
 struct Grid {
   int periodic;
   int nc[3];        // cells per dimension
-  int span[3];      // distinct stencil offsets per dimension (5, or nc when nc < 5)
+  int reach;        // stencil half-width in cells (1 or 2)
+  int span[3];      // distinct stencil offsets per dimension (2 reach + 1, or nc when fewer)
   int full[3];      // 1: iterate every cell in this dimension
   double lo[3];     // origin (0 for periodic)
   double L[3], invL[3];
   double invw[3];   // 1 / cell width
-  // 1 when every position lies in [0, L) and every dimension has at least 7
-  // cells: then any pair within r_nonb of a stencil column has the column's
+  // 1 when every position lies in [0, L) and every dimension has at least
+  // 2 reach + 3 cells: then any pair within r_nonb of a stencil column has the column's
   // image shift as its minimum image, and d - shift is bit-identical to
   // d - L rint(d / L)
   int shift_ok;

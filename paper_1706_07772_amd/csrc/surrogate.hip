@@ -222,6 +222,8 @@ struct DescArgs {
   const float* v;        // JVP field [n][3], sorted order
   uint16_t* xq;          // [rows][ND]
   float* G;              // optional [n][ND]
+  float* mom;            // optional [n][4][NM] moments (forward pass only)
+  const int32_t* seg;    // [n][4] element segment starts of the rows, or null (unsorted rows)
 };
 
 template <bool JVP>
@@ -247,7 +249,12 @@ __global__ __launch_bounds__(128) void k_desc(DescArgs a) {
     if (JVP) { vix = a.v[3 * i]; viy = a.v[3 * i + 1]; viz = a.v[3 * i + 2]; }
     const int cnt = a.far_cnt[i];
     const int32_t* __restrict__ rowp = a.far_j + i * (int64_t)a.far_w;
-    for (int k = 0; k < cnt; ++k) {
+    int k0 = 0, k1 = cnt;
+    if (a.seg) {
+      k0 = a.seg[i * 4 + b];
+      k1 = b < 3 ? a.seg[i * 4 + b + 1] : cnt;
+    }
+    for (int k = k0; k < k1; ++k) {
       const int j = rowp[k];
       const double4 xj = a.xs[j];
       if ((int)xj.w != b) continue;
@@ -308,6 +315,10 @@ __global__ __launch_bounds__(128) void k_desc(DescArgs a) {
   }
 #pragma unroll
   for (int k = 0; k < NM; ++k) sm[al][b][k] = m[k];
+  if (!JVP && a.mom && i < a.n) {
+#pragma unroll
+    for (int k = 0; k < NM; ++k) a.mom[(i * 4 + b) * NM + k] = m[k];
+  }
   if (JVP) {
 #pragma unroll
     for (int k = 0; k < NM; ++k) sd[al][b][k] = dm[k];
@@ -484,15 +495,16 @@ __global__ __launch_bounds__(256) void k_net_infer(NetArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// forces of every member: one thread per (atom i, neighbour element b).
-// dE/dd_ij for the neighbours j of element b follows from the adjoints of
-// atom i's features (radial block of b; angular moments of b through their
-// contractions with all elements' moments); F_i += dE/dd_ij, F_j -= dE/dd_ij
-// (atomic adds).  F [M][n][3] sorted order, zeroed beforehand.
+// forces of every member, without atomics.  Pass 1, one thread per (atom i,
+// neighbour element b): the adjoints of atom i's features give dE_i/dd_ij
+// for each neighbour j of element b, written to j's slot of i's neighbour
+// row (w[m][i * far_w + k]).  Pass 2, one thread per atom: with the mirror
+// slot of each pair, F_i = sum_k (w_ik - w_{j_k, i}) (d_ij = x_j - x_i, so
+// dE/dx_i = -sum_k w_ik + sum_k w_{j_k, i}).
 // ---------------------------------------------------------------------------
 struct ForceArgs {
   Grid g;
-  int64_t n, rows;
+  int64_t n, rows, slots;
   int32_t members;
   const double4* xs;
   const int32_t* far_cnt;
@@ -500,90 +512,170 @@ struct ForceArgs {
   int32_t far_w;
   const int32_t* rowof;
   const float* gG;   // [M][rows][ND]
-  float* F;          // [M][n][3]
+  const float* mom;  // [n][4][NM] moments of the descriptor pass
+  const int32_t* mir;  // [n * far_w] mirror slots
+  float4* w;         // [M][slots]: w[m][j, slot of i] = dE_i/dd_ij (received by j)
+  float* Fown;       // [M][n][3]: sum over i's own pairs
 };
 
-__global__ __launch_bounds__(128) void k_sur_forces(ForceArgs a) {
-  __shared__ float sm[32][4][NM];
-  const int al = threadIdx.x >> 2, b = threadIdx.x & 3;
-  const int64_t i = (int64_t)blockIdx.x * 32 + al;
-  const bool live = i < a.n;
-  double4 xi = make_double4(0, 0, 0, 0);
-  int cnt = 0;
-  const int32_t* rowp = nullptr;
-  {
-    float m[NM];
-#pragma unroll
-    for (int k = 0; k < NM; ++k) m[k] = 0.f;
-    if (live) {
-      xi = a.xs[i];
-      cnt = a.far_cnt[i];
-      rowp = a.far_j + i * (int64_t)a.far_w;
-      for (int k = 0; k < cnt; ++k) {
-        const int j = rowp[k];
-        const double4 xj = a.xs[j];
-        if ((int)xj.w != b) continue;
-        double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
-        if (a.g.periodic) {
-          dx = min_image(dx, a.g.L[0], a.g.invL[0]);
-          dy = min_image(dy, a.g.L[1], a.g.invL[1]);
-          dz = min_image(dz, a.g.L[2], a.g.invL[2]);
-        }
-        const double r2d = dx * dx + dy * dy + dz * dz;
-        if (!(r2d < (double)(RC * RC))) continue;
-        const float r = (float)sqrt(r2d), ir = 1.0f / r;
-        const float ux = (float)dx * ir, uy = (float)dy * ir, uz = (float)dz * ir;
-        const float fc = 0.5f * (__cosf(PIF * r / RC) + 1.0f);
-        const float uu[6] = {ux * ux, uy * uy, uz * uz, ux * uy, ux * uz, uy * uz};
-#pragma unroll
-        for (int nn = 0; nn < NA; ++nn) {
-          const float t = r - mu_a(nn);
-          const float A = __expf(-ETA_A * t * t) * fc;
-          m[nn * 3 + 0] += A * ux;
-          m[nn * 3 + 1] += A * uy;
-          m[nn * 3 + 2] += A * uz;
-#pragma unroll
-          for (int q = 0; q < 6; ++q) m[24 + nn * 6 + q] += A * uu[q];
-        }
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < NM; ++k) sm[al][b][k] = m[k];
+// Neighbour rows in increasing index order (rank sort in LDS, one wavefront
+// per row of at most SORT_MAX entries), so that mirror slots can be found by
+// binary search.  The order of a row is free: every kernel reading it indexes
+// its per-pair data by slot.
+constexpr int SORT_MAX = 256;
+constexpr int KEY_SHIFT = 27;   // sort key (element << 27) | index; atoms < 2^27
+
+__global__ __launch_bounds__(256) void k_far_sort(int64_t n, const int32_t* __restrict__ far_cnt,
+                                                  int32_t* __restrict__ far_j, int32_t far_w,
+                                                  const int32_t* __restrict__ type_s, int32_t* __restrict__ seg) {
+  __shared__ int32_t buf[4][SORT_MAX];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + wv;
+  if (i >= n) return;
+  const int cnt = far_cnt[i];
+  int32_t* __restrict__ row = far_j + i * (int64_t)far_w;
+  int c0 = 0, c1 = 0, c2 = 0;
+  for (int k = lane; k < cnt; k += 64) {
+    const int j = row[k];
+    const int t = type_s[j];
+    buf[wv][k] = (t << KEY_SHIFT) | j;
+    c0 += t < 1;
+    c1 += t < 2;
+    c2 += t < 3;
   }
-  __syncthreads();
-  if (!live) return;
+  for (int off = 32; off > 0; off >>= 1) {
+    c0 += __shfl_down(c0, off, 64);
+    c1 += __shfl_down(c1, off, 64);
+    c2 += __shfl_down(c2, off, 64);
+  }
+  if (lane == 0) {
+    seg[i * 4 + 0] = 0;
+    seg[i * 4 + 1] = c0;
+    seg[i * 4 + 2] = c1;
+    seg[i * 4 + 3] = c2;
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  for (int k = lane; k < cnt; k += 64) {
+    const int key = buf[wv][k];
+    int rank = 0;
+    for (int t = 0; t < cnt; ++t) rank += buf[wv][t] < key;
+    row[rank] = key & ((1 << KEY_SHIFT) - 1);
+  }
+}
+
+// mirror slot of every neighbour-row entry: mir[i * far_w + k] = slot of i in
+// row j_k (sorted by element, then index), by binary search; -1 if absent
+__global__ __launch_bounds__(256) void k_far_mirror(int64_t n, const int32_t* __restrict__ far_cnt,
+                                                    const int32_t* __restrict__ far_j, int32_t far_w,
+                                                    const int32_t* __restrict__ type_s,
+                                                    const int32_t* __restrict__ seg, int32_t* __restrict__ mir) {
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;
+  const int cnt = far_cnt[i];
+  const int ti = type_s[i];
+  const int32_t* __restrict__ row = far_j + i * (int64_t)far_w;
+  for (int k = lane; k < cnt; k += 64) {
+    const int j = row[k];
+    const int32_t* __restrict__ rj = far_j + (int64_t)j * far_w;
+    const int cj = far_cnt[j];
+    int lo = seg[(int64_t)j * 4 + ti];
+    int hi = ti < 3 ? seg[(int64_t)j * 4 + ti + 1] : cj;
+    const int end = hi;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (rj[mid] < (int)i) lo = mid + 1;
+      else hi = mid;
+    }
+    mir[i * (int64_t)far_w + k] = (lo < end && rj[lo] == (int)i) ? lo : -1;
+  }
+}
+
+// linear-search variant for rows longer than SORT_MAX (unsorted rows)
+__global__ __launch_bounds__(256) void k_far_mirror_scan(int64_t n, const int32_t* __restrict__ far_cnt,
+                                                         const int32_t* __restrict__ far_j, int32_t far_w,
+                                                         int32_t* __restrict__ mir) {
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;
+  const int cnt = far_cnt[i];
+  const int32_t* __restrict__ row = far_j + i * (int64_t)far_w;
+  for (int k = 0; k < cnt; ++k) {
+    const int j = row[k];
+    const int cj = far_cnt[j];
+    const int32_t* __restrict__ rj = far_j + (int64_t)j * far_w;
+    int m = -1;
+    for (int t0 = 0; t0 < cj && m < 0; t0 += 64) {
+      const int t = t0 + lane;
+      const unsigned long long hit = __ballot(t < cj && rj[t] == (int)i);
+      if (hit) m = t0 + __ffsll((long long)hit) - 1;
+    }
+    if (lane == 0) mir[i * (int64_t)far_w + k] = m;
+  }
+}
+
+// Pair contributions, one wavefront per atom i, one neighbour slot per lane.
+// The wavefront first builds, for a chunk of up to 4 members, the adjoints of
+// atom i's features seen from each neighbour element b (in LDS):
+//   radial  gR_b,k = dE_i/dG[16 b + k]
+//   M1      g1_b,n = sum_c (2 if c = b else 1) dE_i/dA1_(bc),n  M1_c,n
+//   M2      g2_b,n = sum_c (2 if c = b else 1) dE_i/dA2_(bc),n  M2_c,n
+// (M from the descriptor pass); then each lane forms dE_i/dd_ij for its
+// neighbour j from the radial and angular basis of r_ij.
+constexpr int GAM = NR + NA * 3 + NA * 6;   // 88 adjoint floats per element
+constexpr int MCH = 4;                      // members per chunk
+
+__global__ __launch_bounds__(256) void k_sur_pairw(ForceArgs a) {
+  __shared__ float sg[4][MCH][4][GAM];
+  __shared__ float smm[4][4][NM];
+  __shared__ float sgg[4][ND];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + wv;
+  if (i >= a.n) return;                       // wave-uniform; no block barriers below
+  for (int k = lane; k < 4 * NM; k += 64) smm[wv][k / NM][k % NM] = a.mom[i * 4 * NM + k];
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  const double4 xi = a.xs[i];
+  const int cnt = a.far_cnt[i];
+  const int32_t* __restrict__ rowp = a.far_j + i * (int64_t)a.far_w;
   const int row = a.rowof[i];
-  for (int mem = 0; mem < a.members; ++mem) {
-    const float* __restrict__ g = a.gG + ((int64_t)mem * a.rows + row) * ND;
-    float gR[NR], g1[NA][3], g2[NA][6];
+  for (int m0 = 0; m0 < a.members; m0 += MCH) {
+    const int mc = a.members - m0 < MCH ? a.members - m0 : MCH;
+    for (int mm = 0; mm < mc; ++mm) {
+      // this member's dE/dG of atom i, then its adjoints in three uniform passes:
+      // radial copies, M1 contractions, M2 contractions
+      for (int k = lane; k < ND; k += 64) sgg[wv][k] = a.gG[((int64_t)(m0 + mm) * a.rows + row) * ND + k];
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      const float* __restrict__ g = sgg[wv];
+      for (int k = lane; k < 4 * NR; k += 64) sg[wv][mm][k / NR][k % NR] = g[k];
+      for (int k = lane; k < 4 * NA * 3; k += 64) {
+        const int b = k / (NA * 3), o = k % (NA * 3), nn = o / 3, comp = o % 3;
+        float v = 0.f;
 #pragma unroll
-    for (int k = 0; k < NR; ++k) gR[k] = g[b * NR + k];
-#pragma unroll
-    for (int nn = 0; nn < NA; ++nn) {
-#pragma unroll
-      for (int q = 0; q < 3; ++q) g1[nn][q] = 0.f;
-#pragma unroll
-      for (int q = 0; q < 6; ++q) g2[nn][q] = 0.f;
-    }
-    for (int c = 0; c < 4; ++c) {
-      const int p = pidx(b, c);
-      const float coef = c == b ? 2.0f : 1.0f;
-#pragma unroll
-      for (int nn = 0; nn < NA; ++nn) {
-        const float a1 = coef * g[4 * NR + p * 16 + nn];
-        const float a2 = coef * g[4 * NR + p * 16 + 8 + nn];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) g1[nn][q] += a1 * sm[al][c][nn * 3 + q];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) g2[nn][q] += a2 * sm[al][c][24 + nn * 6 + q];
+        for (int c = 0; c < 4; ++c)
+          v += (c == b ? 2.0f : 1.0f) * g[4 * NR + pidx(b, c) * 16 + nn] * smm[wv][c][nn * 3 + comp];
+        sg[wv][mm][b][NR + o] = v;
       }
+      for (int k = lane; k < 4 * NA * 6; k += 64) {
+        const int b = k / (NA * 6), o = k % (NA * 6), nn = o / 6, comp = o % 6;
+        float v = 0.f;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          v += (c == b ? 2.0f : 1.0f) * g[4 * NR + pidx(b, c) * 16 + 8 + nn] * smm[wv][c][24 + nn * 6 + comp];
+        sg[wv][mm][b][NR + NA * 3 + o] = v;
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     }
-    float fx = 0.f, fy = 0.f, fz = 0.f;
-    float* __restrict__ Fm = a.F + (int64_t)mem * a.n * 3;
-    for (int k = 0; k < cnt; ++k) {
+    float fo[MCH][3];
+#pragma unroll
+    for (int mm = 0; mm < MCH; ++mm) fo[mm][0] = fo[mm][1] = fo[mm][2] = 0.f;
+    for (int k = lane; k < cnt; k += 64) {
       const int j = rowp[k];
       const double4 xj = a.xs[j];
-      if ((int)xj.w != b) continue;
+      const int b = (int)xj.w;
       double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
       if (a.g.periodic) {
         dx = min_image(dx, a.g.L[0], a.g.invL[0]);
@@ -591,47 +683,106 @@ __global__ __launch_bounds__(128) void k_sur_forces(ForceArgs a) {
         dz = min_image(dz, a.g.L[2], a.g.invL[2]);
       }
       const double r2d = dx * dx + dy * dy + dz * dz;
-      if (!(r2d < (double)(RC * RC))) continue;
-      const float r = (float)sqrt(r2d), ir = 1.0f / r;
+      const bool in = r2d < (double)(RC * RC);
+      const float r = in ? (float)sqrt(r2d) : RC, ir = 1.0f / r;
       const float ux = (float)dx * ir, uy = (float)dy * ir, uz = (float)dz * ir;
       const float fc = 0.5f * (__cosf(PIF * r / RC) + 1.0f);
       const float dfc = -0.5f * (PIF / RC) * __sinf(PIF * r / RC);
-      // radial: sum_k gR_k R_k'(r) u
-      float sr = 0.f;
+      float dR[NR], A[NA], dA[NA];
 #pragma unroll
-      for (int k = 0; k < NR; ++k) {
-        const float t = r - mu_r(k);
+      for (int k2 = 0; k2 < NR; ++k2) {
+        const float t = r - mu_r(k2);
         const float e = __expf(-ETA_R * t * t);
-        sr += gR[k] * (e * (-2.0f * ETA_R * t) * fc + e * dfc);
+        dR[k2] = e * (-2.0f * ETA_R * t) * fc + e * dfc;
       }
-      float wx = sr * ux, wy = sr * uy, wz = sr * uz;
 #pragma unroll
       for (int nn = 0; nn < NA; ++nn) {
         const float t = r - mu_a(nn);
         const float e = __expf(-ETA_A * t * t);
-        const float A = e * fc, dA = e * (-2.0f * ETA_A * t) * fc + e * dfc;
-        // M1: d/dd of A(r) (g1 . u) = dA (g1.u) u + (A / r)(g1 - (g1.u) u)
-        const float gu = g1[nn][0] * ux + g1[nn][1] * uy + g1[nn][2] * uz;
-        // M2: with symmetric Gamma (xx yy zz xy xz yz): u^T Gamma u and Gamma u
-        const float Gx = g2[nn][0] * ux + g2[nn][3] * uy + g2[nn][4] * uz;
-        const float Gy = g2[nn][3] * ux + g2[nn][1] * uy + g2[nn][5] * uz;
-        const float Gz = g2[nn][4] * ux + g2[nn][5] * uy + g2[nn][2] * uz;
-        const float uGu = ux * Gx + uy * Gy + uz * Gz;
-        const float cu = dA * (gu + uGu) - A * ir * (gu + 2.0f * uGu);
-        wx += cu * ux + A * ir * (g1[nn][0] + 2.0f * Gx);
-        wy += cu * uy + A * ir * (g1[nn][1] + 2.0f * Gy);
-        wz += cu * uz + A * ir * (g1[nn][2] + 2.0f * Gz);
+        A[nn] = e * fc;
+        dA[nn] = e * (-2.0f * ETA_A * t) * fc + e * dfc;
       }
-      fx += wx;
-      fy += wy;
-      fz += wz;
-      atomicAdd(&Fm[3 * j], -wx);
-      atomicAdd(&Fm[3 * j + 1], -wy);
-      atomicAdd(&Fm[3 * j + 2], -wz);
+      for (int mm = 0; mm < mc; ++mm) {
+        const float* __restrict__ G = sg[wv][mm][b];
+        float sr = 0.f;
+#pragma unroll
+        for (int k2 = 0; k2 < NR; ++k2) sr += G[k2] * dR[k2];
+        float wx = sr * ux, wy = sr * uy, wz = sr * uz;
+#pragma unroll
+        for (int nn = 0; nn < NA; ++nn) {
+          const float* g1 = G + NR + nn * 3;
+          const float* g2 = G + NR + NA * 3 + nn * 6;
+          // M1: d/dd of A(r) (g1 . u) = dA (g1.u) u + (A / r)(g1 - (g1.u) u)
+          const float gu = g1[0] * ux + g1[1] * uy + g1[2] * uz;
+          // M2: symmetric Gamma (xx yy zz xy xz yz): u^T Gamma u and Gamma u
+          const float Gx = g2[0] * ux + g2[3] * uy + g2[4] * uz;
+          const float Gy = g2[3] * ux + g2[1] * uy + g2[5] * uz;
+          const float Gz = g2[4] * ux + g2[5] * uy + g2[2] * uz;
+          const float uGu = ux * Gx + uy * Gy + uz * Gz;
+          const float cu = dA[nn] * (gu + uGu) - A[nn] * ir * (gu + 2.0f * uGu);
+          wx += cu * ux + A[nn] * ir * (g1[0] + 2.0f * Gx);
+          wy += cu * uy + A[nn] * ir * (g1[1] + 2.0f * Gy);
+          wz += cu * uz + A[nn] * ir * (g1[2] + 2.0f * Gz);
+        }
+        if (!in) { wx = 0.f; wy = 0.f; wz = 0.f; }
+        // own side: F_i += w; the neighbour's side goes to the slot of i in row j
+#pragma unroll
+        for (int q = 0; q < MCH; ++q)
+          if (q == mm) { fo[q][0] += wx; fo[q][1] += wy; fo[q][2] += wz; }
+        const int mk = a.mir[i * (int64_t)a.far_w + k];
+        if (mk >= 0) a.w[(int64_t)(m0 + mm) * a.slots + (int64_t)j * a.far_w + mk] = make_float4(wx, wy, wz, 0.f);
+      }
     }
-    atomicAdd(&Fm[3 * i], fx);
-    atomicAdd(&Fm[3 * i + 1], fy);
-    atomicAdd(&Fm[3 * i + 2], fz);
+    for (int mm = 0; mm < mc; ++mm) {
+      float fx = fo[mm][0], fy = fo[mm][1], fz = fo[mm][2];
+      for (int off = 32; off > 0; off >>= 1) {
+        fx += __shfl_down(fx, off, 64);
+        fy += __shfl_down(fy, off, 64);
+        fz += __shfl_down(fz, off, 64);
+      }
+      if (lane == 0) {
+        float* f = a.Fown + ((int64_t)(m0 + mm) * a.n + i) * 3;
+        f[0] = fx;
+        f[1] = fy;
+        f[2] = fz;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  }
+}
+
+// F[m][i] = Fown[m][i] - sum_k w[m][i, k] (contributions received from the
+// neighbours), sorted order; one wavefront per atom, one slot per lane
+__global__ __launch_bounds__(256) void k_sur_gather(int64_t n, int32_t members, int64_t slots,
+                                                    const int32_t* __restrict__ far_cnt, int32_t far_w,
+                                                    const float4* __restrict__ w, const float* __restrict__ Fown,
+                                                    float* __restrict__ F) {
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;
+  const int cnt = far_cnt[i];
+  const int64_t base = i * (int64_t)far_w;
+  for (int m = 0; m < members; ++m) {
+    const float4* __restrict__ wm = w + (int64_t)m * slots;
+    float fx = 0.f, fy = 0.f, fz = 0.f;
+    for (int k = lane; k < cnt; k += 64) {
+      const float4 p = wm[base + k];
+      fx += p.x;
+      fy += p.y;
+      fz += p.z;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      fx += __shfl_down(fx, off, 64);
+      fy += __shfl_down(fy, off, 64);
+      fz += __shfl_down(fz, off, 64);
+    }
+    if (lane == 0) {
+      const int64_t o = ((int64_t)m * n + i) * 3;
+      F[o] = Fown[o] - fx;
+      F[o + 1] = Fown[o + 1] - fy;
+      F[o + 2] = Fown[o + 2] - fz;
+    }
   }
 }
 
@@ -960,6 +1111,13 @@ struct reaxff_surrogate {
   float* Erow = nullptr;         // [M][rows]
   float* gG = nullptr;           // [M][rows][ND]
   float* F = nullptr;            // [M][n][3]
+  float4* w = nullptr;           // [M][n * far_w] per-pair force contributions received
+  float* Fown = nullptr;         // [M][n][3]
+  int32_t* mir = nullptr;        // [n * far_w] mirror slots of the neighbour rows
+  float* mom = nullptr;          // [n][4][NM] descriptor moments
+  int32_t* seg = nullptr;        // [n][4] element segment starts of the sorted rows
+  bool sorted_rows = false;
+  int64_t cap_slots = 0;
   float* res = nullptr;          // [n][3]
   float* G = nullptr;            // [n][ND] (descriptor output for callers)
   double* Etot = nullptr;        // [M]
@@ -1014,7 +1172,9 @@ int prepare(reaxff_surrogate* s, int64_t n, const double* pos, const int32_t* ty
         (rc = salloc(s, s->xq, cr * ND)) || (rc = salloc(s, s->uq, cr * ND)) ||
         (rc = salloc(s, s->Erow, (int64_t)M * cr)) || (rc = salloc(s, s->gG, (int64_t)M * cr * ND)) ||
         (rc = salloc(s, s->F, (int64_t)M * cn * 3)) || (rc = salloc(s, s->res, cn * 3)) ||
-        (rc = salloc(s, s->Fbar, cn * 3)) || (rc = salloc(s, s->Freax, cn * 3)))
+        (rc = salloc(s, s->Fbar, cn * 3)) || (rc = salloc(s, s->Freax, cn * 3)) ||
+        (rc = salloc(s, s->mom, cn * 4 * NM)) || (rc = salloc(s, s->seg, cn * 4)) ||
+        (rc = salloc(s, s->Fown, (int64_t)M * cn * 3)))
       return rc;
     s->cap_n = cn;
     s->cap_rows = cr;
@@ -1023,6 +1183,22 @@ int prepare(reaxff_surrogate* s, int64_t n, const double* pos, const int32_t* ty
   s->rows = rows;
   if (n == 0) return 0;
   const rx::Lists& L = s->nb->L;
+  const int64_t slots = n * (int64_t)L.far_w;
+  if (slots > s->cap_slots) {
+    const int64_t cs = slots + slots / 8;
+    if ((rc = salloc(s, s->w, (int64_t)s->members * cs)) || (rc = salloc(s, s->mir, cs))) return rc;
+    s->cap_slots = cs;
+  }
+  s->sorted_rows = L.far_w <= SORT_MAX && n < (1 << KEY_SHIFT);
+  if (s->sorted_rows) {
+    hipLaunchKernelGGL(k_far_sort, dim3(nb(n, 4)), dim3(256), 0, st, n, L.far_cnt, L.far_j, L.far_w, L.type_s,
+                       s->seg);
+    hipLaunchKernelGGL(k_far_mirror, dim3(nb(n, 4)), dim3(256), 0, st, n, L.far_cnt, L.far_j, L.far_w, L.type_s,
+                       s->seg, s->mir);
+  } else {
+    hipLaunchKernelGGL(k_far_mirror_scan, dim3(nb(n, 4)), dim3(256), 0, st, n, L.far_cnt, L.far_j, L.far_w,
+                       s->mir);
+  }
   // rows: stable partition of the sorted atoms by element, groups padded to 64
   for (int e = 0; e < 4; ++e) {
     hipLaunchKernelGGL(k_elem_flag, dim3(nb(n + 1, 256)), dim3(256), 0, st, n, L.type_s, e, s->R.flag);
@@ -1055,6 +1231,7 @@ DescArgs desc_args(reaxff_surrogate* s, const float* v, uint16_t* out, float* G)
   a.v = v;
   a.xq = out;
   a.G = G;
+  a.seg = s->sorted_rows ? s->seg : nullptr;
   return a;
 }
 
@@ -1064,7 +1241,11 @@ int evaluate_frame(reaxff_surrogate* s, hipStream_t st) {
   const int M = s->members;
   SHIP(s, hipMemsetAsync(s->Etot, 0, sizeof(double) * M, st));
   if (n == 0) return 0;
-  hipLaunchKernelGGL(k_desc<false>, dim3(nb(n, 32)), dim3(128), 0, st, desc_args(s, nullptr, s->xq, nullptr));
+  {
+    DescArgs da = desc_args(s, nullptr, s->xq, nullptr);
+    da.mom = s->mom;
+    hipLaunchKernelGGL(k_desc<false>, dim3(nb(n, 32)), dim3(128), 0, st, da);
+  }
   NetArgs na{};
   na.theta = s->theta;
   na.W1 = s->W1;
@@ -1080,12 +1261,12 @@ int evaluate_frame(reaxff_surrogate* s, hipStream_t st) {
   na.gG = s->gG;
   hipLaunchKernelGGL(k_net_infer, dim3((unsigned)(rows / TILE), M), dim3(256), 0, st, na);
   hipLaunchKernelGGL(k_sur_energy, dim3(nb(rows, 256)), dim3(256), 0, st, rows, M, s->R.rowatom, s->Erow, s->Etot);
-  SHIP(s, hipMemsetAsync(s->F, 0, sizeof(float) * M * n * 3, st));
   const rx::Lists& L = s->nb->L;
   ForceArgs fa{};
   fa.g = s->nb->grid;
   fa.n = n;
   fa.rows = rows;
+  fa.slots = s->cap_slots;
   fa.members = M;
   fa.xs = L.xs;
   fa.far_cnt = L.far_cnt;
@@ -1093,8 +1274,13 @@ int evaluate_frame(reaxff_surrogate* s, hipStream_t st) {
   fa.far_w = L.far_w;
   fa.rowof = s->R.rowof;
   fa.gG = s->gG;
-  fa.F = s->F;
-  hipLaunchKernelGGL(k_sur_forces, dim3(nb(n, 32)), dim3(128), 0, st, fa);
+  fa.mom = s->mom;
+  fa.mir = s->mir;
+  fa.w = s->w;
+  fa.Fown = s->Fown;
+  hipLaunchKernelGGL(k_sur_pairw, dim3(nb(n, 4)), dim3(256), 0, st, fa);
+  hipLaunchKernelGGL(k_sur_gather, dim3(nb(n, 4)), dim3(256), 0, st, n, M, s->cap_slots, L.far_cnt, L.far_w,
+                     s->w, s->Fown, s->F);
   return hipGetLastError() == hipSuccess ? 0 : sfail(s, REAXFF_ERR_HIP, "surrogate kernels");
 }
 
@@ -1125,9 +1311,11 @@ int reaxff_surrogate_create(reaxff_ctx* ctx, int32_t members, reaxff_surrogate**
   s->members = members;
   s->nparams = (int64_t)members * 4 * NPAR;
   reaxff_cutoffs c = ctx->cut;
+  // only the 5 A neighbour rows of this context are used: bond and H-bond
+  // lists are kept empty (sub-bond-length cutoffs)
   c.r_nonb = 5.0;
-  c.r_bond = std::min(c.r_bond, 5.0);
-  c.r_hb = std::min(c.r_hb, 5.0);
+  c.r_bond = 0.1;
+  c.r_hb = 0.1;
   int rc = reaxff_create(&ctx->hp, &c, ctx->device, &s->nb);
   auto bail = [&](int code) {
     if (ctx) ctx->err = s->err.empty() ? (s->nb ? reaxff_last_error(s->nb) : "reaxff_surrogate_create") : s->err;
@@ -1164,7 +1352,7 @@ void reaxff_surrogate_destroy(reaxff_surrogate* s) {
                   (void*)s->W2, (void*)s->Wt2, (void*)s->shift, (void*)s->scale, (void*)s->R.flag,
                   (void*)s->R.pre, (void*)s->R.base, (void*)s->R.rowof, (void*)s->R.rowatom,
                   (void*)s->R.tile_elem, (void*)s->xq, (void*)s->uq, (void*)s->Erow, (void*)s->gG, (void*)s->F,
-                  (void*)s->res, (void*)s->G, (void*)s->Etot, (void*)s->ss, (void*)s->nflag, (void*)s->Fbar,
+                  (void*)s->res, (void*)s->G, (void*)s->w, (void*)s->mir, (void*)s->mom, (void*)s->seg, (void*)s->Fown, (void*)s->Etot, (void*)s->ss, (void*)s->nflag, (void*)s->Fbar,
                   (void*)s->Freax, (void*)s->Ereax})
     if (p) (void)hipFree(p);
   if (s->nflag_host) (void)hipHostFree(s->nflag_host);

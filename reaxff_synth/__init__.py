@@ -346,6 +346,19 @@ def workload(name: str) -> System:
     return petn_lattice(w["n_units"], w["box"], w["seed"])
 
 
+def thermal_frame(n_units: int, box: float, seed: int, temp: float, k_eff: float = 100.0) -> System:
+    """A training frame at temperature temp (K): the lattice recipe (its 0.3 A jitter),
+    then every atom displaced by an isotropic Gaussian of standard deviation
+    sqrt(k_B T / k_eff) per component (a harmonic-well stand-in for thermal motion;
+    k_eff in kcal/(mol A^2)), wrapped into the box."""
+    s = petn_lattice(n_units, box, seed)
+    rng = np.random.default_rng(np.random.PCG64(seed + 7919))
+    sigma = math.sqrt(0.0019872043 * temp / k_eff)
+    pos = s.pos + rng.normal(scale=sigma, size=s.pos.shape)
+    pos -= box * np.floor(pos / box)
+    return System(pos=pos, type=s.type, q=s.q, box=s.box, meta=dict(s.meta, temp=temp))
+
+
 def small_periodic(n_units: int, seed: int, box: float | None = None) -> System:
     """A periodic PETN-stoichiometry box at the crystal density (edge >= 20 A)."""
     natoms = n_units * PETN_UNIT_ATOMS
