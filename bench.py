@@ -25,13 +25,15 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_VALU_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
-# Kernel work models.  nonbonded: FP64 operations per pair evaluation of the
-# compiled inner loop (v_fma/v_fmac/v_div_fmas counted as 2, v_add, v_mul,
-# v_rcp, v_rsq as 1; compares, conversions and exponent manipulation not
-# counted), read from the gfx950 assembly of this library's own build.  Each
-# unordered far pair is evaluated from both of its atoms.
+# Kernel work models (algorithmic work: what the method requires).
+# nonbonded: FP64 operations of one pair evaluation of the compiled inner loop
+# (v_fma/v_fmac/v_div_fmas counted as 2, v_add, v_mul, v_rcp, v_rsq as 1;
+# compares, conversions and exponent manipulation not counted), read from the
+# gfx950 assembly of this library's own build, per UNORDERED far pair (the
+# energy and both atoms' forces of a pair follow from one evaluation; a kernel
+# that evaluates each pair from both of its atoms does twice this work).
 WORK = {
-    "nonbonded": ("pair_evaluations", 421.0),
+    "nonbonded": ("far_pairs", 421.0),
 }
 
 # Measured HBM bytes per launch of a kernel (rocprofv3 FETCH_SIZE and
@@ -169,6 +171,76 @@ def bench_batched(ff, steps: int, warmup: int):
     }
 
 
+def bench_surrogate(ff, params, steps: int, warmup: int, train_steps: int = 200, nframes: int = 32):
+    """Learned surrogate: an ensemble of 4 networks trained here by the library's own
+    kernels on frames of 1,856 atoms (the workload recipe at 300-3000 K, labelled by the
+    plain GPU path); force errors on 3 held-out frames against the CPU oracle; throughput
+    at 1,044,000 atoms of the ensemble alone and of the gated evaluation (plain FP64
+    fallback where the members disagree by more than 0.1 eV/A)."""
+    import numpy as np
+    import torch
+
+    import reaxff_synth as rs
+    from oracle import Oracle
+    from paper_1706_07772_amd import Surrogate
+    from paper_1706_07772_amd import training as T
+
+    sur = Surrogate(ff, 4)
+    info = T.train(sur, ff, T.FrameSource(64, seed=1000), steps=train_steps, nframes=nframes, lr=2e-3)
+    print(f"bench: surrogate trained {train_steps} steps on {nframes} frames in {info['train_s']:.2f} s",
+          file=sys.stderr, flush=True)
+    held = T.FrameSource(64, seed=99)
+    errs = []
+    kcal = T.KCAL_PER_EV
+    thr = 0.1 * kcal
+    for _ in range(3):
+        fr, temp = held.next()
+        _, f_ref = Oracle(fr, params).forces()
+        pos, typ, q, box = T.to_device(fr)
+        ev = sur.evaluate(pos, typ, box)
+        fg, mask, _, nf = sur.gated_forces(ff, pos, typ, q, box, thr)
+        torch.cuda.synchronize()
+        fm = ev["fmean"].cpu().numpy()
+        fgn = fg.cpu().numpy()
+
+        def rmse(a):
+            return float(np.sqrt(((a - f_ref) ** 2).sum(1).mean())) / kcal
+
+        errs.append({"temp_K": round(temp), "rmse_ensemble_ev": rmse(fm), "rmse_gated_ev": rmse(fgn),
+                     "rmse_zero_ev": rmse(np.zeros_like(f_ref)), "fallback_fraction": nf / fr.n})
+    # throughput at 1.04M atoms
+    big = rs.workload("petn_1044000")
+    pos, typ, q, box = T.to_device(big)
+    n = big.n
+    for _ in range(warmup):
+        sur.evaluate(pos, typ, box)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sur.evaluate(pos, typ, box)
+    torch.cuda.synchronize()
+    ms_sur = 1e3 * (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    nfl = 0
+    gsteps = max(1, steps // 2)
+    for _ in range(gsteps):
+        _, _, _, nfl = sur.gated_forces(ff, pos, typ, q, box, thr)
+    torch.cuda.synchronize()
+    ms_gated = 1e3 * (time.perf_counter() - t0) / gsteps
+    sur.close()
+    return {
+        "ensemble": "4 members, 224 -> 128 -> 128 -> 1 SiLU per element, BF16 MFMA, FP32 accumulation",
+        "training": {"frames": nframes, "atoms_per_frame": info["atoms_per_frame"], "steps": train_steps,
+                     "seconds": info["train_s"], "ms_per_step": info["ms_per_step"],
+                     "final_loss": info["losses"][-1][1]},
+        "heldout_vs_oracle": errs,
+        "atoms": n,
+        "ensemble_ms_per_step": ms_sur, "ensemble_atom_steps_per_s": n / (ms_sur * 1e-3),
+        "gated_ms_per_step": ms_gated, "gated_atom_steps_per_s": n / (ms_gated * 1e-3),
+        "gated_fallback_fraction": nfl / n, "threshold_ev_per_A": 0.1,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,6 +254,9 @@ def main():
                     help="skip the batched-clusters measurement")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched-clusters measurement (for profiling)")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate measurement")
+    ap.add_argument("--surrogate-only", action="store_true",
+                    help="only the surrogate measurement (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -200,6 +275,11 @@ def main():
         ff = ReaxFF(params)
         out = bench_batched(ff, args.steps, args.warmup)
         print(json.dumps({"batched": out}), flush=True)
+        return
+    if args.surrogate_only:
+        ff = ReaxFF(params)
+        out = bench_surrogate(ff, params, args.steps, args.warmup)
+        print(json.dumps({"surrogate": out}), flush=True)
         return
     system = rs.workload(args.workload)
     n = system.n
@@ -264,7 +344,7 @@ def main():
         avg_s = kernels[dom]["ms_avg"] * 1e-3
         if dom in WORK:
             unit, per = WORK[dom]
-            units = 2 * counts["far_pairs"] if unit == "pair_evaluations" else counts.get(unit)
+            units = counts.get(unit)
             if units:
                 flops = per * units / (kernels[dom]["launches"] / args.steps)
                 achieved = flops / avg_s / 1e12
@@ -283,6 +363,11 @@ def main():
     if not args.no_batched:
         print("bench: batched clusters", file=sys.stderr, flush=True)
         batched = bench_batched(ff, args.steps, args.warmup)
+
+    surrogate = None
+    if not args.no_surrogate:
+        print("bench: surrogate", file=sys.stderr, flush=True)
+        surrogate = bench_surrogate(ff, params, args.steps, args.warmup)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -308,6 +393,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched": batched,
+        "surrogate": surrogate,
         "phases_ms": phases,
         "counts": counts,
         "kernels_ms_avg": {k: round(v["ms_avg"], 4) for k, v in kernels.items()},

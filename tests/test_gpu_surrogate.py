@@ -244,3 +244,37 @@ def test_empty_frame(sur4):
     out = sur4.evaluate(pos, typ, None)
     torch.cuda.synchronize()
     assert np.all(out["energies"].cpu().numpy() == 0)
+
+
+def test_training_gains_over_untrained(ff, params):
+    """What training buys: on held-out frames the trained ensemble's mean force is closer
+    to the oracle's FP64 ReaxFF forces than the untrained ensemble's and than zero."""
+    import torch
+    from oracle import Oracle
+    from paper_1706_07772_amd import Surrogate
+    from paper_1706_07772_amd import training as T
+    sur = Surrogate(ff, 2)
+    T.train(sur, ff, T.FrameSource(64, seed=1000), steps=150, nframes=24, lr=2e-3, seed=3)
+    th_trained = sur.get_params()
+    held = T.FrameSource(64, seed=99)
+    frames = [held.next()[0] for _ in range(2)]
+    refs = [Oracle(f, params).forces()[1] for f in frames]
+
+    def rmse_all():
+        out = []
+        for f, fr in zip(frames, refs):
+            pos, typ, q, box = T.to_device(f)
+            fm = sur.evaluate(pos, typ, box)["fmean"]
+            torch.cuda.synchronize()
+            out.append(np.sqrt(((fm.cpu().numpy() - fr) ** 2).sum(1).mean()))
+        return np.array(out)
+
+    trained = rmse_all()
+    theta, shift, scale = th_trained
+    sur.set_params(T.init_params(2, sur.npar, 3, float(theta[0, 0, -1])), shift, scale)
+    untrained = rmse_all()
+    sur.close()
+    zero = np.array([np.sqrt((fr ** 2).sum(1).mean()) for fr in refs])
+    print("rmse kcal/mol/A trained", trained, "untrained", untrained, "zero", zero)
+    assert np.all(trained < 0.7 * zero)
+    assert np.all(trained < 0.7 * untrained)
