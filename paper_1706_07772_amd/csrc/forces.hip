@@ -251,11 +251,13 @@ __global__ __launch_bounds__(BS) void k_torsions(const DevParams* __restrict__ P
 // (8) hydrogen bonds.  Each term X-H...Z moves three atoms.  The donor side
 //     (one thread per donor bond H-X, over H's acceptor row) sums the energy,
 //     the adjoints of the H-X bond entry and the force on H.  The acceptor
-//     side (one thread per acceptor Z, over the donors within r_hb found in
-//     Z's far row by the H list's own predicate) recomputes the term's
-//     gradient with respect to Z and keeps it in a register, so no force is
-//     scattered to acceptors.
+//     side (one wavefront per acceptor Z, over Z's acceptor row: the donors
+//     H within r_hb, found by the sweep with the H list's own predicate)
+//     recomputes the term's gradient with respect to Z and reduces it over
+//     the wavefront, so no force is scattered to acceptors.
 // ---------------------------------------------------------------------------
+constexpr int HB_WAVES = BS / 64;
+
 __global__ __launch_bounds__(BS) void k_hbonds(const DevParams* __restrict__ P, Grid g, Lists L, Work W,
                                                double* __restrict__ energies) {
   const int64_t ntask = W.off_don[L.n];
@@ -305,10 +307,13 @@ __global__ __launch_bounds__(BS) void k_hbonds(const DevParams* __restrict__ P, 
   if ((threadIdx.x & 63) == 0 && nhb) atomicAdd(&W.counters[2], nhb);
 }
 
-// acceptor side: F_Z = -dE/dx_Z = -sum dE/d(x_Z - x_h), over Z's donor row
+// Acceptor side: F_Z = -dE/dx_Z = -sum dE/d(x_Z - x_h) over the donors H of
+// Z's acceptor row; one wavefront per acceptor, one H per lane, reduced over
+// the wavefront (no atomics: the acceptor's force is written once).
 __global__ __launch_bounds__(BS) void k_hb_acceptors(const DevParams* __restrict__ P, Grid g, Lists L,
                                                      Work W) {
-  const int64_t z = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t z = (int64_t)blockIdx.x * HB_WAVES + (threadIdx.x >> 6);
   if (z >= L.n) return;
   const int cnt = L.ha_cnt[z];
   if (cnt == 0) return;
@@ -316,7 +321,7 @@ __global__ __launch_bounds__(BS) void k_hb_acceptors(const DevParams* __restrict
   const double4 xz = L.xs[z];
   const int32_t* __restrict__ row = L.ha_j + z * (int64_t)L.ha_w;
   double3 fz = make_double3(0.0, 0.0, 0.0);
-  for (int k = 0; k < cnt; ++k) {
+  for (int k = lane; k < cnt; k += 64) {
     const int h = row[k];
     const int t0 = W.off_don[h], t1 = W.off_don[h + 1];
     if (t0 == t1) continue;
@@ -339,11 +344,18 @@ __global__ __launch_bounds__(BS) void k_hb_acceptors(const DevParams* __restrict
       fz.z -= o.g_rz.z;
     }
   }
-  double4 f = W.fnb[z];
-  f.x += fz.x;
-  f.y += fz.y;
-  f.z += fz.z;
-  W.fnb[z] = f;
+  for (int off = 32; off > 0; off >>= 1) {
+    fz.x += __shfl_down(fz.x, off, 64);
+    fz.y += __shfl_down(fz.y, off, 64);
+    fz.z += __shfl_down(fz.z, off, 64);
+  }
+  if (lane == 0) {
+    double4 f = W.fnb[z];
+    f.x += fz.x;
+    f.y += fz.y;
+    f.z += fz.z;
+    W.fnb[z] = f;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -497,12 +509,12 @@ int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, co
   scan_i32(W.cnt_don, W.off_don, n + 1, sc, st);
   pf.end(st);
   LAUNCH(KID_TASKS, k_tasks<true>, grid, blk, 0, st, P, L, W);
-  const dim3 gt(task_grid(L.bound_tor)), gd(task_grid(L.bound_don));
+  const dim3 gt(task_grid(L.bound_tor));
   LAUNCH(KID_ANGLES, k_angles, dim3((unsigned)std::max<int64_t>((L.bound_ang + BS - 1) / BS, 1)), blk, 0,
          st, P, L, W, energies);
   LAUNCH(KID_TORSIONS, k_torsions, gt, blk, 0, st, P, L, W, energies);
-  LAUNCH(KID_HBONDS, k_hbonds, gd, blk, 0, st, P, g, L, W, energies);
-  LAUNCH(KID_HB_ACC, k_hb_acceptors, grid, blk, 0, st, P, g, L, W);
+  LAUNCH(KID_HBONDS, k_hbonds, dim3(task_grid(L.bound_don)), blk, 0, st, P, g, L, W, energies);
+  LAUNCH(KID_HB_ACC, k_hb_acceptors, dim3(nblk(n, HB_WAVES)), blk, 0, st, P, g, L, W);
   (void)hipMemcpyAsync(W.counters, W.off_ang + n, sizeof(int32_t), hipMemcpyDeviceToDevice, st);
   (void)hipMemcpyAsync(W.counters + 1, W.off_tor + n, sizeof(int32_t), hipMemcpyDeviceToDevice, st);
   LAUNCH(KID_BACK_S, k_back_s, grid, blk, 0, st, L, W);
