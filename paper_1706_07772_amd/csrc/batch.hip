@@ -410,8 +410,9 @@ __device__ __noinline__ void st_angles(int n) {
   wave_acc(nang, &b_acc[NTERMS + 0]);
 }
 
-// nonbonded: one wavefront per atom, one partner per lane, every pair from
-// both sides (no force scatter), half energy weight per visit
+// nonbonded: one wavefront per atom i, one partner j > i per lane, so every
+// unordered pair is evaluated once; the partner's force goes to the LDS force
+// array with atomic adds, the atom's own sum is reduced over the wavefront
 template <int BSZ>
 __device__ __noinline__ void st_nonbonded(int n) {
   const BatchArgs A = uni_copy(b_args);
@@ -426,8 +427,7 @@ __device__ __noinline__ void st_nonbonded(int n) {
     const double qi = xi.w * C_ELE;
     const NbP* __restrict__ spi = b_nb + b_ty[i] * NT;
     double fx = 0.0, fy = 0.0, fz = 0.0;
-    for (int j = lane; j < n; j += 64) {
-      if (j == i) continue;
+    for (int j = i + 1 + lane; j < n; j += 64) {
       const double4 xj = b_x[j];
       const double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
       const double r2 = r2_of(dx, dy, dz);
@@ -438,16 +438,17 @@ __device__ __noinline__ void st_nonbonded(int n) {
       fx += o.f * dx;
       fy += o.f * dy;
       fz += o.f * dz;
+      atomic_add3(&b_f[j], -o.f * dx, -o.f * dy, -o.f * dz);
     }
     for (int off = 32; off > 0; off >>= 1) {
       fx += __shfl_down(fx, off, 64);
       fy += __shfl_down(fy, off, 64);
       fz += __shfl_down(fz, off, 64);
     }
-    if (lane == 0) b_f[i] = make_double4(fx, fy, fz, 0.0);
+    if (lane == 0) atomic_add3(&b_f[i], fx, fy, fz);
   }
-  wave_acc(0.5 * ev, &b_acc[E_VDW]);
-  wave_acc(0.5 * eq, &b_acc[E_COUL]);
+  wave_acc(ev, &b_acc[E_VDW]);
+  wave_acc(eq, &b_acc[E_COUL]);
 }
 
 // torsions about the bonds each atom owns (lower index), with atomic adds
