@@ -207,6 +207,7 @@ int reaxff_create(const reaxff_params* params, const reaxff_cutoffs* cutoffs, in
   c->hp = *params;
   if (cutoffs) c->cut = *cutoffs;
   else c->cut = reaxff_cutoffs{10.0, 5.0, 7.5, 0.01, 0.001, 1e-5, 0.01};
+  c->L.far_slots = 1;
   const reaxff_cutoffs& cc = c->cut;
   if (!(cc.r_nonb > 0 && cc.r_bond > 0 && cc.r_hb > 0 && cc.r_bond <= cc.r_nonb &&
         cc.r_hb <= cc.r_nonb && cc.bo_cut >= 0)) {
@@ -477,7 +478,7 @@ int reaxff_export_lists(reaxff_ctx* c, int32_t* far, int32_t* bonds, int32_t* hb
   if (far && c->L.nfar) HIPCHK(c, hipMalloc(&df, sizeof(int32_t) * 2 * c->L.nfar));
   if (bonds && c->L.nbond) HIPCHK(c, hipMalloc(&db, sizeof(int32_t) * 2 * c->L.nbond));
   if (hb && c->L.nhb) HIPCHK(c, hipMalloc(&dh, sizeof(int32_t) * 2 * c->L.nhb));
-  if (launch_export(c->L, df, db, dh, c->sc, 0)) return fail(c, REAXFF_ERR_HIP, "export failed");
+  if (launch_export(c->grid, c->L, df, db, dh, c->sc, 0)) return fail(c, REAXFF_ERR_HIP, "export failed");
   HIPCHK(c, hipDeviceSynchronize());
   if (df) HIPCHK(c, hipMemcpy(far, df, sizeof(int32_t) * 2 * c->L.nfar, hipMemcpyDeviceToHost));
   if (db) HIPCHK(c, hipMemcpy(bonds, db, sizeof(int32_t) * 2 * c->L.nbond, hipMemcpyDeviceToHost));

@@ -16,6 +16,7 @@
 // per entry and gathered through the mirror index.  Only the torsion terms
 // (which touch entries of both central atoms) and the hydrogen-bond acceptor
 // use atomic adds; the nonbonded pairs are evaluated from both sides instead.
+#include <type_traits>
 #include <algorithm>
 
 #include "internal.h"
@@ -359,62 +360,238 @@ __global__ __launch_bounds__(BS) void k_hb_acceptors(const DevParams* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// (9) van der Waals and Coulomb.  One wavefront per atom walks the atom's
-//     full neighbour row, one neighbour per lane, and reduces the atom's
-//     force across the wavefront.  Every pair is evaluated twice (once from
-//     each side) and no force is scattered: the redundant-computation choice
-//     the paper cites as the better one for pairwise terms on massively
-//     parallel processors (Section 3.1).  Energies weigh each visit by 1/2.
+// (9) van der Waals and Coulomb.  One workgroup per cell.  All atoms of a
+//     cell share one stencil, so the workgroup first copies the stencil's
+//     atoms (position, charge, type) into LDS with coalesced loads; far rows
+//     hold stencil slots, so each neighbour is then read from LDS rather than
+//     gathered from memory.  The cell's rows are cut into units of 64
+//     entries that never cross a row, and the units are split evenly over
+//     the workgroup's wavefronts, one entry per lane: the centre atom is the
+//     same for the whole wavefront, and its force is reduced across the
+//     wavefront and added to the atom's LDS accumulator whenever the
+//     wavefront moves on to the next atom.  Every pair is evaluated from both
+//     sides and no force is scattered (the redundant-computation choice for
+//     pairwise terms, Section 3.1); energies weigh each visit by 1/2.  A
+//     stencil too large for the LDS copy reads its neighbours from memory
+//     through the chunk table instead.  Cells go to the XCDs in contiguous
+//     ranges, so the cells running together on an XCD share stencils in its L2.
 // ---------------------------------------------------------------------------
-constexpr int NB_WAVES = BS / 64;
+constexpr int NBC_BS = 512, NBC_WAVES = NBC_BS / 64;
+constexpr int NBC_CAP = 2048;  // stencil atoms held in LDS
+constexpr int NBC_MG = 64;     // atoms of a cell per pass
+constexpr int NBC_MAXQ = 64;   // chunks of a stencil: 2 (2 reach + 1)^2 <= 50
 
-__global__ __launch_bounds__(BS) void k_nonbonded(const DevParams* __restrict__ P, Grid g, Lists L,
-                                                  Work W, double* __restrict__ energies) {
+// largest k in [0, n) with b[k] <= t, for non-decreasing b with b[0] <= t
+__device__ __forceinline__ int last_le(const int* b, int n, int t) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (b[mid] <= t) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// inclusive prefix sum over the 64 lanes
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  const int lane = threadIdx.x & 63;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int t = __shfl_up(v, off, 64);
+    if (lane >= off) v += t;
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(NBC_BS) void k_nonbonded(const DevParams* __restrict__ P, Grid g, Lists L,
+                                                      Work W, int ncell, int per_xcd,
+                                                      double* __restrict__ energies) {
   __shared__ NbP sp[NT * NT];
-  if (threadIdx.x < NT * NT) {
-    const PairP& p = P->pair[threadIdx.x];
-    sp[threadIdx.x] = nb_params(p);
+  __shared__ double sxx[NBC_CAP], sxy[NBC_CAP], sxz[NBC_CAP], sxq[NBC_CAP];
+  __shared__ unsigned char sty[NBC_CAP];
+  __shared__ int q_s0[NBC_MAXQ], q_base[NBC_MAXQ + 1];
+  __shared__ int upre[NBC_MG + 1];
+  __shared__ double facc[3][NBC_MG];
+  // the pass's centre atoms: position, charge times the Coulomb constant,
+  // type and row length
+  __shared__ double ixx[NBC_MG], ixy[NBC_MG], ixz[NBC_MG], iqq[NBC_MG];
+  __shared__ int ity[NBC_MG], icnt[NBC_MG];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int c = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+  if (c >= ncell) return;
+  const int a0 = L.cell_start[c], m = L.cell_start[c + 1] - a0;
+  if (m == 0) return;
+  if (tid < NT * NT) sp[tid] = nb_params(P->pair[tid]);
+  // chunk table of the stencil: start atom and first slot of each chunk
+  const int nq = stencil_chunks(g);
+  if (tid < nq) {
+    int s0, s1;
+    double sx, sy, sz;
+    stencil_chunk(g, L.cell_start, c, tid, s0, s1, sx, sy, sz);
+    q_s0[tid] = s0;
+    q_base[tid + 1] = s1 - s0;
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * NB_WAVES + (threadIdx.x >> 6);
-  double evdw = 0.0, ecoul = 0.0;
-  if (i < L.n) {
-    const double4 xi = W.xq[i];
-    const int ti = L.type_s[i];
-    const double qi = xi.w * C_ELE;
-    const double iR = P->inv_r_nonb, pv = P->p_vdW1, ipv = P->inv_p_vdW1;
-    double fx = 0.0, fy = 0.0, fz = 0.0;
-    const int cnt = L.far_cnt[i];
-    const int32_t* __restrict__ row = L.far_j + i * (int64_t)L.far_w;
-    const NbP* __restrict__ spi = sp + ti * NT;
-    for (int k = lane; k < cnt; k += 64) {
-      const int j = row[k];
-      const double4 xj = W.xq[j];
-      double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
-      if (g.periodic) {
-        dx = min_image(dx, g.L[0], g.invL[0]);
-        dy = min_image(dy, g.L[1], g.invL[1]);
-        dz = min_image(dz, g.L[2], g.invL[2]);
-      }
-      const double r2 = dx * dx + dy * dy + dz * dz;
-      const NbOut o = nb_pair(spi[L.type_s[j]], iR, pv, ipv, qi * xj.w, r2);
-      evdw += o.ev;
-      ecoul += o.eq;
-      const double f = o.f;
-      fx += f * dx;
-      fy += f * dy;
-      fz += f * dz;
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-      fx += __shfl_down(fx, off, 64);
-      fy += __shfl_down(fy, off, 64);
-      fz += __shfl_down(fz, off, 64);
-    }
-    if (lane == 0) W.fnb[i] = make_double4(fx, fy, fz, 0.0);
+  if (wv == 0) {
+    const int v = wave_incl_scan(lane < nq ? q_base[lane + 1] : 0);
+    if (lane < nq) q_base[lane + 1] = v;
+    if (lane == 0) q_base[0] = 0;
   }
-  block_add<BS>(0.5 * evdw, energies + E_VDW);
-  block_add<BS>(0.5 * ecoul, energies + E_COUL);
+  __syncthreads();
+  const int nst = q_base[nq];
+  const bool staged = nst <= NBC_CAP;
+  if (staged) {
+    for (int t0 = 0; t0 < nst; t0 += 4 * NBC_BS) {
+      int idx[4];
+      double4 v[4];
+      int ty[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int t = t0 + u * NBC_BS + tid;
+        idx[u] = -1;
+        if (t < nst) {
+          const int q = last_le(q_base, nq, t);
+          idx[u] = q_s0[q] + (t - q_base[q]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (idx[u] >= 0) {
+          v[u] = W.xq[idx[u]];
+          ty[u] = L.type_s[idx[u]];
+        }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (idx[u] >= 0) {
+          const int t = t0 + u * NBC_BS + tid;
+          sxx[t] = v[u].x;
+          sxy[t] = v[u].y;
+          sxz[t] = v[u].z;
+          sxq[t] = v[u].w;
+          sty[t] = (unsigned char)ty[u];
+        }
+    }
+  }
+  const double iR = P->inv_r_nonb, pv = P->p_vdW1, ipv = P->inv_p_vdW1;
+  double evdw = 0.0, ecoul = 0.0;
+  for (int g0 = 0; g0 < m; g0 += NBC_MG) {
+    const int mg = m - g0 < NBC_MG ? m - g0 : NBC_MG;
+    // units of 64 row entries per atom, prefix-summed
+    if (wv == 0) {
+      int cnt = 0;
+      if (lane < mg) {
+        const int i = a0 + g0 + lane;
+        cnt = L.far_cnt[i];
+        const double4 xi = W.xq[i];
+        ixx[lane] = xi.x;
+        ixy[lane] = xi.y;
+        ixz[lane] = xi.z;
+        iqq[lane] = xi.w * C_ELE;
+        ity[lane] = L.type_s[i];
+        icnt[lane] = cnt;
+      }
+      const int v = wave_incl_scan((cnt + 63) >> 6);
+      if (lane < mg) upre[lane + 1] = v;
+      if (lane == 0) upre[0] = 0;
+    }
+    for (int t = tid; t < 3 * NBC_MG; t += NBC_BS) facc[t / NBC_MG][t % NBC_MG] = 0.0;
+    __syncthreads();
+    const int U = __builtin_amdgcn_readfirstlane(upre[mg]);
+    const int wu = __builtin_amdgcn_readfirstlane(wv);
+    const int u0 = U * wu / NBC_WAVES, u1 = U * (wu + 1) / NBC_WAVES;
+    // one copy of the unit loop per neighbour source, so that each keeps its
+    // own address space (LDS reads, or global reads through the chunk table)
+    auto units = [&](auto from_lds) {
+      constexpr bool LDS = decltype(from_lds)::value;
+      // the row entry of unit u + 1 is loaded while unit u is computed
+      auto locate = [&](int u, int& a) {
+        while (__builtin_amdgcn_readfirstlane(upre[a + 1]) <= u) ++a;
+      };
+      auto fetch = [&](int u, int a) {
+        const int k = ((u - __builtin_amdgcn_readfirstlane(upre[a])) << 6) + lane;
+        const int32_t* __restrict__ row = L.far_j + (int64_t)(a0 + g0 + a) * L.far_w;
+        return k < __builtin_amdgcn_readfirstlane(icnt[a]) ? row[k] : -1;
+      };
+      int a = __builtin_amdgcn_readfirstlane(last_le(upre, mg, u0));
+      locate(u0, a);
+      int slot = fetch(u0, a);
+      int cur = a;
+      double xix = ixx[cur], xiy = ixy[cur], xiz = ixz[cur], qi = iqq[cur];
+      const NbP* __restrict__ spi = sp + ity[cur] * NT;
+      double fx = 0.0, fy = 0.0, fz = 0.0;
+      auto flush = [&]() {
+        for (int off = 32; off > 0; off >>= 1) {
+          fx += __shfl_down(fx, off, 64);
+          fy += __shfl_down(fy, off, 64);
+          fz += __shfl_down(fz, off, 64);
+        }
+        if (lane == 0) {
+          atomicAdd(&facc[0][cur], fx);
+          atomicAdd(&facc[1][cur], fy);
+          atomicAdd(&facc[2][cur], fz);
+        }
+        fx = fy = fz = 0.0;
+      };
+      for (int u = u0; u < u1; ++u) {
+        const int snow = slot, anow = a;
+        if (u + 1 < u1) {
+          locate(u + 1, a);
+          slot = fetch(u + 1, a);
+        }
+        if (anow != cur) {
+          flush();
+          cur = anow;
+          xix = ixx[cur];
+          xiy = ixy[cur];
+          xiz = ixz[cur];
+          qi = iqq[cur];
+          spi = sp + ity[cur] * NT;
+        }
+        if (snow >= 0) {
+          double xjx, xjy, xjz, qj;
+          int tj;
+          if constexpr (LDS) {
+            xjx = sxx[snow];
+            xjy = sxy[snow];
+            xjz = sxz[snow];
+            qj = sxq[snow];
+            tj = sty[snow];
+          } else {
+            const int q = last_le(q_base, nq, snow);
+            const int j = q_s0[q] + (snow - q_base[q]);
+            const double4 xj = W.xq[j];
+            xjx = xj.x;
+            xjy = xj.y;
+            xjz = xj.z;
+            qj = xj.w;
+            tj = L.type_s[j];
+          }
+          double dx = xjx - xix, dy = xjy - xiy, dz = xjz - xiz;
+          if (g.periodic) {
+            dx = min_image(dx, g.L[0], g.invL[0]);
+            dy = min_image(dy, g.L[1], g.invL[1]);
+            dz = min_image(dz, g.L[2], g.invL[2]);
+          }
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          const NbOut o = nb_pair(spi[tj], iR, pv, ipv, qi * qj, r2);
+          evdw += o.ev;
+          ecoul += o.eq;
+          fx += o.f * dx;
+          fy += o.f * dy;
+          fz += o.f * dz;
+        }
+      }
+      flush();
+    };
+    if (u0 < u1) {
+      if (staged) units(std::true_type{});
+      else units(std::false_type{});
+    }
+    __syncthreads();
+    if (tid < mg) W.fnb[a0 + g0 + tid] = make_double4(facc[0][tid], facc[1][tid], facc[2][tid], 0.0);
+    __syncthreads();
+  }
+  block_add<NBC_BS>(0.5 * evdw, energies + E_VDW);
+  block_add<NBC_BS>(0.5 * ecoul, energies + E_COUL);
 }
 
 // ---------------------------------------------------------------------------
@@ -492,7 +669,13 @@ int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, co
   LAUNCH(KID_GATHER_Q, k_gather_q, grid, blk, 0, st, q, L.perm, L.xs, n, W.xq);
   // nonbonded first: it initialises the per-atom force accumulator that the
   // hydrogen-bond kernel adds to
-  LAUNCH(KID_NONBONDED, k_nonbonded, dim3(nblk(n, NB_WAVES)), blk, 0, st, P, g, L, W, energies);
+  {
+    // the kernel reads neighbours by stencil slot through a chunk table
+    if (!L.far_slots || stencil_chunks(g) > NBC_MAXQ) return -1;
+    const int ncell = g.nc[0] * g.nc[1] * g.nc[2], per_xcd = (ncell + 7) / 8;
+    LAUNCH(KID_NONBONDED, k_nonbonded, dim3(8u * (unsigned)per_xcd), dim3(NBC_BS), 0, st, P, g, L, W,
+           ncell, per_xcd, energies);
+  }
   LAUNCH(KID_BO_PRIME, k_bo_prime, grid, blk, 0, st, P, g, L, W);
   LAUNCH(KID_DELTA_PRIME, k_delta_prime, grid, blk, 0, st, P, L, W);
   LAUNCH(KID_BO_CORR, k_bo_corr, grid, blk, 0, st, P, L, W);

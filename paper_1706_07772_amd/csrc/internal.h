@@ -98,7 +98,7 @@ int launch_cell_sort(const double* pos, const int32_t* type, int64_t n, const Gr
 int launch_sweep(const DevParams* P, const Grid& g, int64_t n, int ncell, Scratch& sc, Lists& L,
                  Prof& pf, hipStream_t st);
 int launch_compact(int64_t n, Scratch& sc, Lists& L, Prof& pf, hipStream_t st);
-int launch_export(const Lists& L, int32_t* far, int32_t* bonds, int32_t* hb, Scratch& sc,
+int launch_export(const Grid& g, const Lists& L, int32_t* far, int32_t* bonds, int32_t* hb, Scratch& sc,
                   hipStream_t st);
 
 int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, const double* q,

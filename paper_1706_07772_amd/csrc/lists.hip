@@ -114,26 +114,6 @@ __global__ void k_gather_sorted(const double* __restrict__ pos, const int32_t* _
   cell_s[s] = cid[i];
 }
 
-// z ranges of a stencil column around cell z = c2, in cell units within a
-// row: [za0, za1) and [zb0, zb1).  Cells are numbered with z fastest, so the
-// 2R+1 cells of a column (x, y, c2-R..c2+R, R = g.reach) are one contiguous
-// range of sorted atoms, or two when the column wraps around a periodic edge.
-__device__ __forceinline__ void column_ranges(const Grid& g, int c2, int& za0, int& za1, int& zb0,
-                                              int& zb1) {
-  const int R = g.reach;
-  zb0 = zb1 = 0;
-  if (g.full[2]) {
-    za0 = 0; za1 = g.nc[2];
-  } else if (g.periodic) {
-    if (c2 - R < 0) { za0 = 0; za1 = c2 + R + 1; zb0 = g.nc[2] + c2 - R; zb1 = g.nc[2]; }
-    else if (c2 + R >= g.nc[2]) { za0 = c2 - R; za1 = g.nc[2]; zb0 = 0; zb1 = c2 + R + 1 - g.nc[2]; }
-    else { za0 = c2 - R; za1 = c2 + R + 1; }
-  } else {
-    za0 = c2 - R < 0 ? 0 : c2 - R;
-    za1 = c2 + R + 1 > g.nc[2] ? g.nc[2] : c2 + R + 1;
-  }
-}
-
 // One wavefront per cell.  Every atom of a cell has the same (2R+1)^3 cell
 // stencil, so the wavefront loads each 64-candidate chunk of a stencil column
 // once (coalesced) and tests it against each atom of its cell in turn: the
@@ -142,6 +122,9 @@ __device__ __forceinline__ void column_ranges(const Grid& g, int c2, int& za0, i
 // i's rows (far list, bond candidates inside the per-type bond reach, H list).
 // Entries beyond a row's width are counted but not written; the largest count
 // of each list is reported so the host can widen the rows and sweep again.
+// Far entries are stencil slots (the neighbour's position in the cell's chunk
+// sequence, see stencil_chunk) when slots is set, sorted atom indices
+// otherwise.
 constexpr int SWEEP_WAVES = 4;
 
 __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
@@ -149,8 +132,8 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
     const int32_t* __restrict__ cstart, int32_t* __restrict__ far_cnt, int32_t* __restrict__ far_j,
     int far_w, int32_t* __restrict__ cnt_cand, int32_t* __restrict__ cand_j, int cand_w,
     int32_t* __restrict__ hb_cnt, int32_t* __restrict__ hb_j, int hb_w,
-    int32_t* __restrict__ ha_cnt, int32_t* __restrict__ ha_j, int ha_w, int32_t* __restrict__ need,
-    unsigned long long* __restrict__ totals) {
+    int32_t* __restrict__ ha_cnt, int32_t* __restrict__ ha_j, int ha_w, int slots,
+    int32_t* __restrict__ need, unsigned long long* __restrict__ totals) {
   __shared__ unsigned long long red[SWEEP_WAVES][2];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int c = blockIdx.x * SWEEP_WAVES + wv;
@@ -178,7 +161,8 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
     double4 xmine = make_double4(0.0, 0.0, 0.0, 0.0);
     if (lane < mi) xmine = xs[a0 + ig + lane];
     int kf = 0, kc = 0, kh = 0, ka = 0;       // lane l: counts of the cell's atom l
-    auto chunk = [&](int s0, int s1, double sx, double sy, double sz) {
+    // slot0: stencil slot of candidate s0
+    auto chunk = [&](int s0, int s1, double sx, double sy, double sz, int slot0) {
       for (int base = s0; base < s1; base += 64) {
         const int s = base + lane;
         const bool valid = s < s1;
@@ -216,7 +200,7 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
             const int k0 = readlane_i(kf, l);
             if (f) {
               const int k = k0 + __popcll(mf & below);
-              if (k < far_w) far_j[(int64_t)i * far_w + k] = s;
+              if (k < far_w) far_j[(int64_t)i * far_w + k] = slots ? slot0 + (s - s0) : s;
             }
             kf = writelane_i(k0 + __popcll(mf), l, kf);
             if (mb) {
@@ -247,6 +231,10 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
         }
       }
     };
+    // the chunks in stencil_chunk's order (x offset, y offset, unwrapped
+    // then wrapped z range), slots counted along; the two z ranges keep their
+    // own call sites so the unwrapped one folds its zero shift
+    int slot = 0;
     for (int a = 0; a < g.span[0]; ++a) {
       int x = g.full[0] ? a : c0 + a - g.reach;
       double sx = 0.0;
@@ -262,8 +250,14 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
           else if (y >= g.nc[1]) { y -= g.nc[1]; sy = -g.L[1]; }
         } else if (y < 0 || y >= g.nc[1]) continue;
         const int row = (x * g.nc[1] + y) * g.nc[2];
-        chunk(cstart[row + za0], cstart[row + za1], sx, sy, 0.0);
-        if (zb1 > zb0) chunk(cstart[row + zb0], cstart[row + zb1], sx, sy, szb);
+        const int sa0 = cstart[row + za0], sa1 = cstart[row + za1];
+        chunk(sa0, sa1, sx, sy, 0.0, slot);
+        slot += sa1 - sa0;
+        if (zb1 > zb0) {
+          const int sb0 = cstart[row + zb0], sb1 = cstart[row + zb1];
+          chunk(sb0, sb1, sx, sy, szb, slot);
+          slot += sb1 - sb0;
+        }
       }
     }
     if (lane < mi) {
@@ -388,10 +382,14 @@ __global__ void k_mirror(int64_t n, const int32_t* __restrict__ off, const int32
 
 // export helpers: lists in caller indices
 // half far list from the full rows: the entries with j > i, at per-atom
-// offsets hoff (exclusive scan of the per-atom half counts)
+// offsets hoff (exclusive scan of the per-atom half counts).  Slot entries are
+// mapped back to sorted indices by walking the cell's chunk sequence along
+// the (increasing) row.
 template <bool WRITE>
-__global__ void k_export_far(int64_t n, const int32_t* __restrict__ cnt, const int32_t* __restrict__ fj,
-                             int far_w, const int32_t* __restrict__ perm, int32_t* __restrict__ hcnt,
+__global__ void k_export_far(int64_t n, Grid g, const int32_t* __restrict__ cstart,
+                             const int32_t* __restrict__ cell_s, const int32_t* __restrict__ cnt,
+                             const int32_t* __restrict__ fj, int far_w, int slots,
+                             const int32_t* __restrict__ perm, int32_t* __restrict__ hcnt,
                              const int64_t* __restrict__ hoff, int32_t* __restrict__ out) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -399,8 +397,19 @@ __global__ void k_export_far(int64_t n, const int32_t* __restrict__ cnt, const i
   int h = 0;
   const int pi = WRITE ? perm[i] : 0;
   const int32_t* row = fj + i * (int64_t)far_w;
+  const int c = slots ? cell_s[i] : 0, nq = stencil_chunks(g);
+  int q = 0, s0 = 0, s1 = 0, base = 0;
+  double sx, sy, sz;
+  if (slots) stencil_chunk(g, cstart, c, 0, s0, s1, sx, sy, sz);
   for (int k = 0; k < cnt[i]; ++k) {
-    const int j = row[k];
+    int j = row[k];
+    if (slots) {
+      while (j >= base + (s1 - s0) && q + 1 < nq) {
+        base += s1 - s0;
+        stencil_chunk(g, cstart, c, ++q, s0, s1, sx, sy, sz);
+      }
+      j = s0 + (j - base);
+    }
     if (j > (int)i) {
       if (WRITE) {
         const int pj = perm[j];
@@ -488,7 +497,7 @@ int launch_sweep(const DevParams* P, const Grid& g, int64_t n, int ncell, Scratc
   pf.begin(KID_LIST_SWEEP, st);
   hipLaunchKernelGGL(k_sweep, dim3(nblk(ncell, SWEEP_WAVES)), dim3(64 * SWEEP_WAVES), 0, st, P, g,
                      ncell, L.xs, L.cell_start, L.far_cnt, L.far_j, L.far_w, sc.cnt_cand, sc.cand_j,
-                     sc.cand_w, L.hb_cnt, L.hb_j, L.hb_w, L.ha_cnt, L.ha_j, L.ha_w, sc.need,
+                     sc.cand_w, L.hb_cnt, L.hb_j, L.hb_w, L.ha_cnt, L.ha_j, L.ha_w, L.far_slots, sc.need,
                      reinterpret_cast<unsigned long long*>(sc.totals));
   pf.end(st);
   pf.begin(KID_BONDTEST, st);
@@ -511,7 +520,7 @@ int launch_compact(int64_t n, Scratch& sc, Lists& L, Prof& pf, hipStream_t st) {
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_export(const Lists& L, int32_t* far, int32_t* bonds, int32_t* hb, Scratch& sc,
+int launch_export(const Grid& g, const Lists& L, int32_t* far, int32_t* bonds, int32_t* hb, Scratch& sc,
                   hipStream_t st) {
   const int64_t n = L.n;
   int32_t* hcnt = nullptr;
@@ -520,11 +529,12 @@ int launch_export(const Lists& L, int32_t* far, int32_t* bonds, int32_t* hb, Scr
   if (hipMalloc(&hoff, sizeof(int64_t) * (n + 1)) != hipSuccess) return -1;
   if (far) {
     (void)hipMemsetAsync(hcnt + n, 0, sizeof(int32_t), st);
-    hipLaunchKernelGGL(k_export_far<false>, dim3(nblk(n, 256)), dim3(256), 0, st, n, L.far_cnt,
-                       L.far_j, L.far_w, L.perm, hcnt, nullptr, nullptr);
+    hipLaunchKernelGGL(k_export_far<false>, dim3(nblk(n, 256)), dim3(256), 0, st, n, g, L.cell_start,
+                       sc.cell_s, L.far_cnt, L.far_j, L.far_w, L.far_slots, L.perm, hcnt, nullptr,
+                       nullptr);
     scan_i32_to_i64(hcnt, hoff, n + 1, sc, st);
-    hipLaunchKernelGGL(k_export_far<true>, dim3(nblk(n, 256)), dim3(256), 0, st, n, L.far_cnt,
-                       L.far_j, L.far_w, L.perm, nullptr, hoff, far);
+    hipLaunchKernelGGL(k_export_far<true>, dim3(nblk(n, 256)), dim3(256), 0, st, n, g, L.cell_start,
+                       sc.cell_s, L.far_cnt, L.far_j, L.far_w, L.far_slots, L.perm, nullptr, hoff, far);
   }
   if (bonds)
     hipLaunchKernelGGL(k_export_csr, dim3(nblk(n, 256)), dim3(256), 0, st, n, L.bond_off, L.bond_j,

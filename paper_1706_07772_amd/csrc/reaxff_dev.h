@@ -84,11 +84,15 @@ struct Lists {
   double4* xs;          // sorted positions, w = type (as a double)
   int32_t* cell_start;  // [ncell + 1]
   // far-neighbour list, full (both directions of every pair), one row of
-  // width far_w per atom: entry k of atom i is far_j[i * far_w + k].  A
-  // wavefront works on one atom, so it writes and reads a row contiguously.
+  // width far_w per atom: entry k of atom i is far_j[i * far_w + k], in
+  // increasing order.  With far_slots set an entry is the neighbour's stencil
+  // slot: its position in the chunk sequence of i's cell (stencil_chunk),
+  // which is also its place in the staged copy of that stencil; otherwise it
+  // is the neighbour's sorted index.
   int32_t* far_cnt;     // [n]
   int32_t* far_j;
   int32_t far_w;
+  int32_t far_slots;
   // full bond list
   int32_t* bond_off;    // [n + 1]
   int32_t* bond_j;
@@ -183,6 +187,64 @@ __device__ __forceinline__ int writelane_i(int v, int l, int old) {
 
 __device__ __forceinline__ double r2_of(double dx, double dy, double dz) {
   return fma(dz, dz, fma(dy, dy, dx * dx));
+}
+
+// z ranges of a stencil column around cell z = c2, in cell units within a
+// row: [za0, za1) and [zb0, zb1).  Cells are numbered with z fastest, so the
+// 2R+1 cells of a column (x, y, c2-R..c2+R, R = g.reach) are one contiguous
+// range of sorted atoms, or two when the column wraps around a periodic edge.
+__device__ __forceinline__ void column_ranges(const Grid& g, int c2, int& za0, int& za1, int& zb0,
+                                              int& zb1) {
+  const int R = g.reach;
+  zb0 = zb1 = 0;
+  if (g.full[2]) {
+    za0 = 0; za1 = g.nc[2];
+  } else if (g.periodic) {
+    if (c2 - R < 0) { za0 = 0; za1 = c2 + R + 1; zb0 = g.nc[2] + c2 - R; zb1 = g.nc[2]; }
+    else if (c2 + R >= g.nc[2]) { za0 = c2 - R; za1 = g.nc[2]; zb0 = 0; zb1 = c2 + R + 1 - g.nc[2]; }
+    else { za0 = c2 - R; za1 = c2 + R + 1; }
+  } else {
+    za0 = c2 - R < 0 ? 0 : c2 - R;
+    za1 = c2 + R + 1 > g.nc[2] ? g.nc[2] : c2 + R + 1;
+  }
+}
+
+// The stencil of cell c as a fixed sequence of chunks of contiguous sorted
+// atoms: chunk q (0 <= q < stencil_chunks) is column (a, b) = ((q/2) / span1,
+// (q/2) % span1) of the (x, y) stencil, its unwrapped z range for even q and
+// its wrapped z range for odd q.  A chunk is empty when its column lies
+// outside a non-periodic grid or has no wrapped part.  (sx, sy, sz) is the
+// chunk's image shift.  Far-list entries number a neighbour by its position
+// in this sequence, so the order is part of the list format.
+__host__ __device__ __forceinline__ int stencil_chunks(const Grid& g) { return 2 * g.span[0] * g.span[1]; }
+
+__device__ __forceinline__ void stencil_chunk(const Grid& g, const int32_t* __restrict__ cstart, int c, int q,
+                                              int& s0, int& s1, double& sx, double& sy, double& sz) {
+  const int c2 = c % g.nc[2], c1 = (c / g.nc[2]) % g.nc[1], c0 = c / (g.nc[1] * g.nc[2]);
+  const int col = q >> 1, a = col / g.span[1], bb = col % g.span[1];
+  s0 = s1 = 0;
+  sx = sy = sz = 0.0;
+  int x = g.full[0] ? a : c0 + a - g.reach;
+  if (g.periodic) {
+    if (x < 0) { x += g.nc[0]; sx = g.L[0]; }
+    else if (x >= g.nc[0]) { x -= g.nc[0]; sx = -g.L[0]; }
+  } else if (x < 0 || x >= g.nc[0]) return;
+  int y = g.full[1] ? bb : c1 + bb - g.reach;
+  if (g.periodic) {
+    if (y < 0) { y += g.nc[1]; sy = g.L[1]; }
+    else if (y >= g.nc[1]) { y -= g.nc[1]; sy = -g.L[1]; }
+  } else if (y < 0 || y >= g.nc[1]) return;
+  int za0, za1, zb0, zb1;
+  column_ranges(g, c2, za0, za1, zb0, zb1);
+  const int row = (x * g.nc[1] + y) * g.nc[2];
+  if ((q & 1) == 0) {
+    s0 = cstart[row + za0];
+    s1 = cstart[row + za1];
+  } else if (zb1 > zb0) {
+    s0 = cstart[row + zb0];
+    s1 = cstart[row + zb1];
+    sz = c2 - g.reach < 0 ? g.L[2] : -g.L[2];
+  }
 }
 
 // wave64 + block reduction of one double into *dst (one atomic per block)

@@ -1323,6 +1323,8 @@ int reaxff_surrogate_create(reaxff_ctx* ctx, int32_t members, reaxff_surrogate**
     return code;
   };
   if (rc) return bail(rc);
+  // the descriptor kernels address neighbours by sorted index
+  s->nb->L.far_slots = 0;
   const int64_t wsz = (int64_t)members * 4 * ND * HID, w2sz = (int64_t)members * 4 * HID * HID;
   if ((rc = salloc(s, s->theta, s->nparams)) || (rc = salloc(s, s->grad, s->nparams)) ||
       (rc = salloc(s, s->adam_m, s->nparams)) || (rc = salloc(s, s->adam_v, s->nparams)) ||

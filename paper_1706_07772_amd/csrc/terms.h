@@ -495,6 +495,89 @@ __device__ __forceinline__ HbTerm hb_term(const HbP& hp, double bo, double4 rx, 
 }
 
 // ---------------------------------------------------------------------------
+// FP64 elementary functions for the pair term, for the finite positive
+// arguments it produces (no NaN, infinity or subnormal handling; an argument
+// outside the double range still ends in 0 or infinity through ldexp):
+//   exp_f:   Cody-Waite reduction x = k ln2 + r, |r| <= ln2/2, with ln 2
+//            split into a head of 29 significant bits (k * head exact for
+//            |k| < 2^24) and a tail; exp(r) from its Taylor series to degree
+//            13 (truncation below 1e-17 relative), scaled by 2^k.
+//   log_f:   x = 2^e m with m in [1/sqrt2, sqrt2); log m = 2 atanh(s) with
+//            s = (m - 1)/(m + 1), |s| < 0.172, odd series to s^19
+//            (truncation below 1e-17).
+//   rcbrt_f: x^(-1/3) from a single-precision seed 2^(-log2(x)/3) and two
+//            Newton steps y <- y (4 - x y^3) / 3, each squaring the relative
+//            error (about 1e-7, then 1e-14, then rounding level).
+//   rcp_f:   1/x from the hardware reciprocal estimate and two Newton steps
+//            y <- y (2 - x y).
+// Each is within a few units in the last place, far inside the 1e-9
+// relative agreement asked of energies and forces.
+// ---------------------------------------------------------------------------
+constexpr double LN2_HEAD = 0x1.62e42ff000000p-1;
+constexpr double LN2_TAIL = -0x1.718432a1b0e26p-35;
+constexpr double LOG2_E = 1.4426950408889634;
+
+__device__ __forceinline__ double exp_f(double x) {
+  const double k = rint(x * LOG2_E);
+  double r = fma(-k, LN2_HEAD, x);
+  r = fma(-k, LN2_TAIL, r);
+  double p = 1.0 / 6227020800.0;
+  p = fma(p, r, 1.0 / 479001600.0);
+  p = fma(p, r, 1.0 / 39916800.0);
+  p = fma(p, r, 1.0 / 3628800.0);
+  p = fma(p, r, 1.0 / 362880.0);
+  p = fma(p, r, 1.0 / 40320.0);
+  p = fma(p, r, 1.0 / 5040.0);
+  p = fma(p, r, 1.0 / 720.0);
+  p = fma(p, r, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return ldexp(p, (int)k);
+}
+
+__device__ __forceinline__ double rcp_f(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = y * fma(-x, y, 2.0);
+  y = y * fma(-x, y, 2.0);
+  return y;
+}
+
+__device__ __forceinline__ double log_f(double x) {
+  int e;
+  double m = frexp(x, &e);
+  if (m < 0.7071067811865476) {
+    m *= 2.0;
+    e -= 1;
+  }
+  const double f = m - 1.0;
+  const double s = f * rcp_f(2.0 + f);
+  const double z = s * s;
+  double p = 1.0 / 19.0;
+  p = fma(p, z, 1.0 / 17.0);
+  p = fma(p, z, 1.0 / 15.0);
+  p = fma(p, z, 1.0 / 13.0);
+  p = fma(p, z, 1.0 / 11.0);
+  p = fma(p, z, 1.0 / 9.0);
+  p = fma(p, z, 1.0 / 7.0);
+  p = fma(p, z, 1.0 / 5.0);
+  p = fma(p, z, 1.0 / 3.0);
+  const double lm = fma(2.0 * s * z, p, 2.0 * s);
+  const double de = (double)e;
+  return fma(de, LN2_HEAD, fma(de, LN2_TAIL, lm));
+}
+
+__device__ __forceinline__ double rcbrt_f(double x) {
+  const float xf = (float)x;
+  double y = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf(xf) * (-1.0f / 3.0f));
+  y = y * fma(-x, y * y * y, 4.0) * (1.0 / 3.0);
+  y = y * fma(-x, y * y * y, 4.0) * (1.0 / 3.0);
+  return y;
+}
+
+// ---------------------------------------------------------------------------
 // (9) one van der Waals + Coulomb pair at squared distance r2: tapered
 //     shielded Morse with inner wall, tapered shielded Coulomb.  qq = q_i q_j
 //     C_ele.  Returns the two energies and f = (dE/dr) / r.
@@ -512,21 +595,21 @@ __device__ __forceinline__ NbOut nb_pair(const NbP& p, double iR, double pv, dou
   const double tap = 20.0 * u4 * u3 - 70.0 * u4 * u2 + 84.0 * u4 * u - 35.0 * u4 + 1.0;
   const double dtap = (140.0 * u3 * u3 - 420.0 * u4 * u + 420.0 * u4 - 140.0 * u3) * iR;
   // shielded Morse with inner wall
-  const double pw = exp(pv * log(r));
+  const double pw = exp_f(pv * log_f(r));
   const double sum = pw + p.gw_pow;
-  const double isum = 1.0 / sum;
-  const double f13 = exp(ipv * log(sum));
+  const double isum = rcp_f(sum);
+  const double f13 = exp_f(ipv * log_f(sum));
   const double df13 = f13 * isum * pw * ir;
   const double t = 1.0 - f13 * p.inv_rv;
-  const double e2 = exp(0.5 * p.alpha * t);
+  const double e2 = exp_f(0.5 * p.alpha * t);
   const double e1 = e2 * e2;
   const double ev = p.D * (e1 - 2.0 * e2);
   const double dev = -p.D * p.alpha * p.inv_rv * (e1 - e2) * df13;
-  const double ecr = p.e_core * exp(p.a_core * (1.0 - r * p.inv_rc));
+  const double ecr = p.e_core * exp_f(p.a_core * (1.0 - r * p.inv_rc));
   const double decr = -ecr * p.a_core * p.inv_rc;
   // shielded Coulomb: den = (r^3 + gamma^-3)^(1/3), 1/s3 = (1/den)^3
   const double s3 = r2 * r + p.g3;
-  const double iden = 1.0 / cbrt(s3);
+  const double iden = rcbrt_f(s3);
   const double eq = qq * iden;
   const double deq = -eq * r2 * (iden * iden * iden);
   const double Ev = ev + ecr;
