@@ -125,8 +125,11 @@ __global__ void k_gather_sorted(const double* __restrict__ pos, const int32_t* _
 // Far entries are stencil slots (the neighbour's position in the cell's chunk
 // sequence, see stencil_chunk) when slots is set, sorted atom indices
 // otherwise.
+// MINIMG: periodic box without stencil image shifts (minimum image per pair);
+// otherwise each chunk carries its image shift (zero in open boundaries).
 constexpr int SWEEP_WAVES = 4;
 
+template <bool MINIMG>
 __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
     const DevParams* __restrict__ P, Grid g, int ncell, const double4* __restrict__ xs,
     const int32_t* __restrict__ cstart, int32_t* __restrict__ far_cnt, int32_t* __restrict__ far_j,
@@ -135,7 +138,7 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
     int32_t* __restrict__ ha_cnt, int32_t* __restrict__ ha_j, int ha_w, int slots,
     int32_t* __restrict__ need, unsigned long long* __restrict__ totals) {
   __shared__ unsigned long long red[SWEEP_WAVES][2];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int c = blockIdx.x * SWEEP_WAVES + wv;
   const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   unsigned long long tf = 0, th = 0;
@@ -160,6 +163,7 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
     const int mi = m - ig < 64 ? m - ig : 64;
     double4 xmine = make_double4(0.0, 0.0, 0.0, 0.0);
     if (lane < mi) xmine = xs[a0 + ig + lane];
+    const int tmine = (int)xmine.w;
     int kf = 0, kc = 0, kh = 0, ka = 0;       // lane l: counts of the cell's atom l
     // slot0: stencil slot of candidate s0
     auto chunk = [&](int s0, int s1, double sx, double sy, double sz, int slot0) {
@@ -177,25 +181,28 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
           const int i = a0 + ig + l;
           const double xix = readlane_d(xmine.x, l), xiy = readlane_d(xmine.y, l),
                        xiz = readlane_d(xmine.z, l);
-          const int ti = (int)readlane_d(xmine.w, l);
           double dx = xj.x - xix, dy = xj.y - xiy, dz = xj.z - xiz;
-          if (g.shift_ok) {
-            dx -= sx;
-            dy -= sy;
-            dz -= sz;
-          } else if (g.periodic) {
+          if constexpr (MINIMG) {
             dx = min_image(dx, g.L[0], g.invL[0]);
             dy = min_image(dy, g.L[1], g.invL[1]);
             dz = min_image(dz, g.L[2], g.invL[2]);
+          } else {
+            dx -= sx;
+            dy -= sy;
+            dz -= sz;
           }
           const double r2 = r2_of(dx, dy, dz);
           const bool f = valid && r2 <= rn2 && s != i;
-          const double qt = ti == 0 ? q0 : (ti == 1 ? q1 : (ti == 2 ? q2 : q3));
-          const bool b = f && r2 <= qt;
-          const bool h = f && acc && ((donmask >> ti) & 1) && r2 <= rh2;
-          const bool ha = f && don && ((accmask >> ti) & 1) && r2 <= rh2;
           const unsigned long long mf = __ballot(f);
           if (mf) {
+            // centre type and the bond reach against it, selected without branches
+            const int ti = readlane_i(tmine, l);
+            const double qa = (ti & 1) ? q1 : q0, qb = (ti & 1) ? q3 : q2;
+            const double qt = (ti & 2) ? qb : qa;
+            const bool b = f && r2 <= qt;
+            const bool hr = f && r2 <= rh2;
+            const bool h = hr && acc && ((donmask >> ti) & 1);
+            const bool ha = hr && don && ((accmask >> ti) & 1);
             const unsigned long long mb = __ballot(b), mh = __ballot(h), ma = __ballot(ha);
             const int k0 = readlane_i(kf, l);
             if (f) {
@@ -495,10 +502,16 @@ int launch_sweep(const DevParams* P, const Grid& g, int64_t n, int ncell, Scratc
   (void)hipMemsetAsync(sc.need, 0, sizeof(int32_t) * 8, st);
   (void)hipMemsetAsync(sc.totals, 0, sizeof(int64_t) * 8, st);
   pf.begin(KID_LIST_SWEEP, st);
-  hipLaunchKernelGGL(k_sweep, dim3(nblk(ncell, SWEEP_WAVES)), dim3(64 * SWEEP_WAVES), 0, st, P, g,
-                     ncell, L.xs, L.cell_start, L.far_cnt, L.far_j, L.far_w, sc.cnt_cand, sc.cand_j,
-                     sc.cand_w, L.hb_cnt, L.hb_j, L.hb_w, L.ha_cnt, L.ha_j, L.ha_w, L.far_slots, sc.need,
-                     reinterpret_cast<unsigned long long*>(sc.totals));
+  if (g.periodic && !g.shift_ok)
+    hipLaunchKernelGGL(k_sweep<true>, dim3(nblk(ncell, SWEEP_WAVES)), dim3(64 * SWEEP_WAVES), 0, st, P, g,
+                       ncell, L.xs, L.cell_start, L.far_cnt, L.far_j, L.far_w, sc.cnt_cand, sc.cand_j,
+                       sc.cand_w, L.hb_cnt, L.hb_j, L.hb_w, L.ha_cnt, L.ha_j, L.ha_w, L.far_slots, sc.need,
+                       reinterpret_cast<unsigned long long*>(sc.totals));
+  else
+    hipLaunchKernelGGL(k_sweep<false>, dim3(nblk(ncell, SWEEP_WAVES)), dim3(64 * SWEEP_WAVES), 0, st, P, g,
+                       ncell, L.xs, L.cell_start, L.far_cnt, L.far_j, L.far_w, sc.cnt_cand, sc.cand_j,
+                       sc.cand_w, L.hb_cnt, L.hb_j, L.hb_w, L.ha_cnt, L.ha_j, L.ha_w, L.far_slots, sc.need,
+                       reinterpret_cast<unsigned long long*>(sc.totals));
   pf.end(st);
   pf.begin(KID_BONDTEST, st);
   hipLaunchKernelGGL(k_bondtest, dim3(nblk(n, 256)), dim3(256), 0, st, P, g, n, L.xs, sc.cnt_cand,
