@@ -243,7 +243,7 @@ void reaxff_destroy(reaxff_ctx* c) {
                   c->W.bd, c->W.bop, c->W.dbop, c->W.bo, c->W.gbo, c->W.gvec, c->W.gup, c->W.dp,
                   c->W.ast, c->W.gS, c->W.gSig, c->W.gSBO, c->W.gStot, c->W.gDp, c->W.fnb,
                   c->W.xq, c->W.counters, c->W.cnt_ang, c->W.cnt_tor, c->W.cnt_don,
-                  c->W.off_ang, c->W.off_tor, c->W.off_don, c->W.ang, c->W.tor, c->W.don,
+                  c->W.off_ang, c->W.off_tor, c->W.off_don, c->W.ang, c->W.tor, c->W.don, c->W.donrec,
                   c->L.bond_i, c->sc.cid, c->sc.cell_s, c->sc.cell_count,
                   c->sc.cell_cursor, c->sc.flag, c->sc.cnt_cand, c->sc.cnt_bond,
                   c->sc.cand_j, c->sc.bond_t, c->sc.need,
@@ -408,6 +408,8 @@ int reaxff_build_lists(reaxff_ctx* c, int64_t n, const double* pos, const int32_
     c->W.cap_tor = t;
     t = c->W.cap_don;
     if (grow(c, c->W.don, t, std::max<int64_t>(c->L.bound_don, 1))) return REAXFF_ERR_HIP;
+    int64_t t2 = c->W.cap_don;
+    if (grow(c, c->W.donrec, t2, std::max<int64_t>(c->L.bound_don, 1))) return REAXFF_ERR_HIP;
     c->W.cap_don = t;
   }
   if (alloc_bonds(c, std::max<int64_t>(c->L.nbond, 1))) return REAXFF_ERR_HIP;

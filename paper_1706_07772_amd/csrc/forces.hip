@@ -33,22 +33,22 @@ static inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(BS) void k_bo_prime(const DevParams* __restrict__ P, Grid g, Lists L,
                                                  Work W) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
   if (i < L.n) bo_prime_atom(P, g, L, W, (int)i);
 }
 
 __global__ __launch_bounds__(BS) void k_delta_prime(const DevParams* __restrict__ P, Lists L, Work W) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
   if (i < L.n) delta_prime_atom(P, L, W, (int)i);
 }
 
 __global__ __launch_bounds__(BS) void k_bo_corr(const DevParams* __restrict__ P, Lists L, Work W) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
   if (i < L.n) bo_corr_atom(P, L, W, (int)i);
 }
 
 __global__ __launch_bounds__(BS) void k_atom_state(const DevParams* __restrict__ P, Lists L, Work W) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
   if (i < L.n) atom_state_atom(P, L, W, (int)i);
 }
 
@@ -61,7 +61,7 @@ __global__ __launch_bounds__(BS) void k_atom_state(const DevParams* __restrict__
 // ---------------------------------------------------------------------------
 template <bool FILL>
 __global__ __launch_bounds__(BS) void k_tasks(const DevParams* __restrict__ P, Lists L, Work W) {
-  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t j = xcd_block() * blockDim.x + threadIdx.x;
   if (j >= L.n) return;
   const double thb = P->thb_cut, thb2 = P->thb_cutsq;
   const int e0 = L.bond_off[j], e1 = L.bond_off[j + 1];
@@ -102,7 +102,10 @@ __global__ __launch_bounds__(BS) void k_tasks(const DevParams* __restrict__ P, L
     }
     // donor bonds
     if (hyd && P->atom[L.type_s[k]].hbond == 2 && bu >= P->hb_bo_cut && L.hb_cnt[j] > 0) {
-      if (FILL) W.don[od + nd] = u;
+      if (FILL) {
+        W.don[od + nd] = u;
+        W.donrec[od + nd] = DonRec{W.bd[u], bu, k, L.type_s[k]};
+      }
       ++nd;
     }
   }
@@ -116,7 +119,7 @@ __global__ __launch_bounds__(BS) void k_tasks(const DevParams* __restrict__ P, L
 // (5) bond energy, lone pair, over- and under-coordination (per atom)
 __global__ __launch_bounds__(BS) void k_atom_energy(const DevParams* __restrict__ P, Lists L, Work W,
                                                     double* __restrict__ energies) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
   double e[4] = {0.0, 0.0, 0.0, 0.0};
   if (i < L.n) atom_energy_atom(P, L, W, (int)i, e);
   block_add<BS>(e[0], energies + E_BOND);
@@ -252,12 +255,11 @@ __global__ __launch_bounds__(BS) void k_torsions(const DevParams* __restrict__ P
 // (8) hydrogen bonds.  Each term X-H...Z moves three atoms.  The donor side
 //     (one thread per donor bond H-X, over H's acceptor row) sums the energy,
 //     the adjoints of the H-X bond entry and the force on H.  The acceptor
-//     side (one wavefront per acceptor Z, over Z's acceptor row: the donors
-//     H within r_hb, found by the sweep with the H list's own predicate)
+//     side (16 lanes per acceptor Z, over Z's acceptor row: the donors H
+//     within r_hb, found by the sweep with the H list's own predicate)
 //     recomputes the term's gradient with respect to Z and reduces it over
-//     the wavefront, so no force is scattered to acceptors.
+//     the lanes, so no force is scattered to acceptors.
 // ---------------------------------------------------------------------------
-constexpr int HB_WAVES = BS / 64;
 
 __global__ __launch_bounds__(BS) void k_hbonds(const DevParams* __restrict__ P, Grid g, Lists L, Work W,
                                                double* __restrict__ energies) {
@@ -309,48 +311,50 @@ __global__ __launch_bounds__(BS) void k_hbonds(const DevParams* __restrict__ P, 
 }
 
 // Acceptor side: F_Z = -dE/dx_Z = -sum dE/d(x_Z - x_h) over the donors H of
-// Z's acceptor row; one wavefront per acceptor, one H per lane, reduced over
-// the wavefront (no atomics: the acceptor's force is written once).
+// Z's acceptor row.  Four acceptors per wavefront, 16 lanes each, one H per
+// lane; each donor bond H-X is read from its packed record; the 16-lane sums
+// are written once per acceptor (no atomics).
+constexpr int HB_GROUP = 16;
+
 __global__ __launch_bounds__(BS) void k_hb_acceptors(const DevParams* __restrict__ P, Grid g, Lists L,
                                                      Work W) {
-  const int lane = threadIdx.x & 63;
-  const int64_t z = (int64_t)blockIdx.x * HB_WAVES + (threadIdx.x >> 6);
-  if (z >= L.n) return;
-  const int cnt = L.ha_cnt[z];
-  if (cnt == 0) return;
-  const int tz = L.type_s[z];
-  const double4 xz = L.xs[z];
-  const int32_t* __restrict__ row = L.ha_j + z * (int64_t)L.ha_w;
+  const int lane = threadIdx.x & 63, sub = lane & (HB_GROUP - 1);
+  const int64_t z = (xcd_block() * BS + threadIdx.x) / HB_GROUP;
+  const int cnt = z < L.n ? L.ha_cnt[z] : 0;
   double3 fz = make_double3(0.0, 0.0, 0.0);
-  for (int k = lane; k < cnt; k += 64) {
-    const int h = row[k];
-    const int t0 = W.off_don[h], t1 = W.off_don[h + 1];
-    if (t0 == t1) continue;
-    const int th = L.type_s[h];
-    const double4 xh = L.xs[h];
-    double dx = xz.x - xh.x, dy = xz.y - xh.y, dz = xz.z - xh.z;   // x_Z - x_h
-    if (g.periodic) {
-      dx = min_image(dx, g.L[0], g.invL[0]);
-      dy = min_image(dy, g.L[1], g.invL[1]);
-      dz = min_image(dz, g.L[2], g.invL[2]);
-    }
-    for (int t = t0; t < t1; ++t) {
-      const int ex = W.don[t];
-      const int X = L.bond_j[ex];
-      if (X == (int)z) continue;
-      const HbP& hp = P->hb[(L.type_s[X] * NT + th) * NT + tz];
-      const HbTerm o = hb_term(hp, W.bo[ex].x, W.bd[ex], dx, dy, dz);
-      fz.x -= o.g_rz.x;
-      fz.y -= o.g_rz.y;
-      fz.z -= o.g_rz.z;
+  if (cnt > 0) {
+    const int tz = L.type_s[z];
+    const double4 xz = L.xs[z];
+    const int32_t* __restrict__ row = L.ha_j + z * (int64_t)L.ha_w;
+    for (int k = sub; k < cnt; k += HB_GROUP) {
+      const int h = row[k];
+      const int t0 = W.off_don[h], t1 = W.off_don[h + 1];
+      if (t0 == t1) continue;
+      const int th = L.type_s[h];
+      const double4 xh = L.xs[h];
+      double dx = xz.x - xh.x, dy = xz.y - xh.y, dz = xz.z - xh.z;   // x_Z - x_h
+      if (g.periodic) {
+        dx = min_image(dx, g.L[0], g.invL[0]);
+        dy = min_image(dy, g.L[1], g.invL[1]);
+        dz = min_image(dz, g.L[2], g.invL[2]);
+      }
+      for (int t = t0; t < t1; ++t) {
+        const DonRec d = W.donrec[t];
+        if (d.X == (int)z) continue;
+        const HbP& hp = P->hb[(d.tX * NT + th) * NT + tz];
+        const HbTerm o = hb_term(hp, d.bo, d.bd, dx, dy, dz);
+        fz.x -= o.g_rz.x;
+        fz.y -= o.g_rz.y;
+        fz.z -= o.g_rz.z;
+      }
     }
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    fz.x += __shfl_down(fz.x, off, 64);
-    fz.y += __shfl_down(fz.y, off, 64);
-    fz.z += __shfl_down(fz.z, off, 64);
+  for (int off = HB_GROUP / 2; off > 0; off >>= 1) {
+    fz.x += __shfl_down(fz.x, off, HB_GROUP);
+    fz.y += __shfl_down(fz.y, off, HB_GROUP);
+    fz.z += __shfl_down(fz.z, off, HB_GROUP);
   }
-  if (lane == 0) {
+  if (sub == 0 && cnt > 0) {
     double4 f = W.fnb[z];
     f.x += fz.x;
     f.y += fz.y;
@@ -599,23 +603,23 @@ __global__ __launch_bounds__(NBC_BS) void k_nonbonded(const DevParams* __restric
 // ---------------------------------------------------------------------------
 // (10)-(13) backward, one thread per atom
 __global__ __launch_bounds__(BS) void k_back_s(Lists L, Work W) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
   if (i < L.n) back_s_atom(L, W, (int)i);
 }
 
 __global__ __launch_bounds__(BS) void k_back_corr(const DevParams* __restrict__ P, Lists L, Work W) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
   if (i < L.n) back_corr_atom(P, L, W, (int)i);
 }
 
 __global__ __launch_bounds__(BS) void k_back_dp(Lists L, Work W) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
   if (i < L.n) back_dp_atom(L, W, (int)i);
 }
 
 // per-atom force gather, written in the caller's order
 __global__ __launch_bounds__(BS) void k_forces(Lists L, Work W, double* __restrict__ forces) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
   if (i >= L.n) return;
   const double3 f = force_atom(L, W, (int)i);
   const int o = L.perm[i];
@@ -626,7 +630,7 @@ __global__ __launch_bounds__(BS) void k_forces(Lists L, Work W, double* __restri
 
 __global__ void k_gather_q(const double* __restrict__ q, const int32_t* __restrict__ perm,
                            const double4* __restrict__ xs, int64_t n, double4* __restrict__ xq) {
-  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
   if (s < n) {
     const double4 x = xs[s];
     xq[s] = make_double4(x.x, x.y, x.z, q[perm[s]]);
@@ -659,7 +663,7 @@ int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, co
   if (n > 0) (void)hipMemsetAsync(W.gSBO, 0, sizeof(double) * n, st);
   pf.end(st);
   if (n == 0) return hipGetLastError() == hipSuccess ? 0 : -1;
-  const dim3 grid(nblk(n, BS)), blk(BS);
+  const dim3 grid(xcd_grid(nblk(n, BS))), blk(BS);
 #define LAUNCH(id, ...)                                  \
   do {                                                   \
     pf.begin(id, st);                                    \
@@ -697,7 +701,7 @@ int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, co
          st, P, L, W, energies);
   LAUNCH(KID_TORSIONS, k_torsions, gt, blk, 0, st, P, L, W, energies);
   LAUNCH(KID_HBONDS, k_hbonds, dim3(task_grid(L.bound_don)), blk, 0, st, P, g, L, W, energies);
-  LAUNCH(KID_HB_ACC, k_hb_acceptors, dim3(nblk(n, HB_WAVES)), blk, 0, st, P, g, L, W);
+  LAUNCH(KID_HB_ACC, k_hb_acceptors, dim3(xcd_grid(nblk(n, BS / HB_GROUP))), blk, 0, st, P, g, L, W);
   (void)hipMemcpyAsync(W.counters, W.off_ang + n, sizeof(int32_t), hipMemcpyDeviceToDevice, st);
   (void)hipMemcpyAsync(W.counters + 1, W.off_tor + n, sizeof(int32_t), hipMemcpyDeviceToDevice, st);
   LAUNCH(KID_BACK_S, k_back_s, grid, blk, 0, st, L, W);

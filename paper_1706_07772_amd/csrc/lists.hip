@@ -304,7 +304,7 @@ __global__ __launch_bounds__(256) void k_bondtest(
     const int32_t* __restrict__ cnt_cand, const int32_t* __restrict__ cand_j, int cand_w,
     int32_t* __restrict__ cnt_bond, int32_t* __restrict__ bond_t, int bond_w,
     int32_t* __restrict__ need, unsigned long long* __restrict__ totals) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
   unsigned long long ba = 0, bt = 0, bd = 0;
   if (i < n) {
     const double4 xi = xs[i];
@@ -514,7 +514,7 @@ int launch_sweep(const DevParams* P, const Grid& g, int64_t n, int ncell, Scratc
                        reinterpret_cast<unsigned long long*>(sc.totals));
   pf.end(st);
   pf.begin(KID_BONDTEST, st);
-  hipLaunchKernelGGL(k_bondtest, dim3(nblk(n, 256)), dim3(256), 0, st, P, g, n, L.xs, sc.cnt_cand,
+  hipLaunchKernelGGL(k_bondtest, dim3(xcd_grid(nblk(n, 256))), dim3(256), 0, st, P, g, n, L.xs, sc.cnt_cand,
                      sc.cand_j, sc.cand_w, sc.cnt_bond, sc.bond_t, sc.bond_w, sc.need,
                      reinterpret_cast<unsigned long long*>(sc.totals));
   pf.end(st);

@@ -126,6 +126,13 @@ struct AtomState {
   double pad[3];
 };
 
+// a donor bond h->X as the acceptor side of the hydrogen-bond term reads it
+struct DonRec {
+  double4 bd;        // x_X - x_h and its length
+  double bo;         // corrected bond order
+  int32_t X, tX;     // donor atom and its type
+};
+
 struct Work {
   // per directed bond entry
   double4* bd;     // (dx, dy, dz, r): x_j - x_i
@@ -156,6 +163,7 @@ struct Work {
   int2* ang;         // (entry j->i, entry j->k)
   int4* tor;         // (entry j->k, entry j->i, entry k->l, unused)
   int32_t* don;      // entry h->X
+  DonRec* donrec;    // per donor task: what the acceptor side reads of h->X
   int64_t cap_ang, cap_tor, cap_don;
 };
 
@@ -183,6 +191,20 @@ __device__ __forceinline__ int readlane_i(int v, int l) { return __builtin_amdgc
 // lane l takes the (uniform) value v, the other lanes keep old
 __device__ __forceinline__ int writelane_i(int v, int l, int old) {
   return (int)(threadIdx.x & 63) == l ? v : old;
+}
+
+// Work-group order for kernels over cell-sorted data.  The hardware deals
+// work-groups to the 8 XCDs round-robin; giving work-group b the logical index
+// (b mod 8) * (grid / 8) + b / 8, on a grid padded to a multiple of 8, lets
+// each XCD walk one contiguous range of atoms (a slab of the box), so the
+// neighbour data its work-groups gather stays in that XCD's L2.
+constexpr int NXCD = 8;
+__host__ __device__ __forceinline__ unsigned xcd_grid(int64_t nblocks) {
+  const int64_t b = nblocks < 1 ? 1 : nblocks;
+  return (unsigned)(NXCD * ((b + NXCD - 1) / NXCD));
+}
+__device__ __forceinline__ int64_t xcd_block() {
+  return (int64_t)(blockIdx.x % NXCD) * (gridDim.x / NXCD) + blockIdx.x / NXCD;
 }
 
 __device__ __forceinline__ double r2_of(double dx, double dy, double dz) {
