@@ -514,7 +514,8 @@ struct ForceArgs {
   const float* gG;   // [M][rows][ND]
   const float* mom;  // [n][4][NM] moments of the descriptor pass
   const int32_t* mir;  // [n * far_w] mirror slots
-  float4* w;         // [M][slots]: w[m][j, slot of i] = dE_i/dd_ij (received by j)
+  float4* w;         // [M/4][slots][3]: for j = row_i[k], dE_i/dd_ij of the 4 members
+                     // of a chunk packed in 12 floats (read by j)
   float* Fown;       // [M][n][3]: sum over i's own pairs
 };
 
@@ -625,6 +626,7 @@ __global__ __launch_bounds__(256) void k_far_mirror_scan(int64_t n, const int32_
 // neighbour j from the radial and angular basis of r_ij.
 constexpr int GAM = NR + NA * 3 + NA * 6;   // 88 adjoint floats per element
 constexpr int MCH = 4;                      // members per chunk
+static_assert(MCH == 4, "pair records pack exactly four members");
 
 __global__ __launch_bounds__(256) void k_sur_pairw(ForceArgs a) {
   __shared__ float sg[4][MCH][4][GAM];
@@ -642,10 +644,24 @@ __global__ __launch_bounds__(256) void k_sur_pairw(ForceArgs a) {
   const int row = a.rowof[i];
   for (int m0 = 0; m0 < a.members; m0 += MCH) {
     const int mc = a.members - m0 < MCH ? a.members - m0 : MCH;
+    // every member's dE/dG of atom i, loaded at once (4 values per lane each)
+    constexpr int GPL = (ND + 63) / 64;
+    float gl[MCH][GPL];
+#pragma unroll
+    for (int mm = 0; mm < MCH; ++mm)
+#pragma unroll
+      for (int t = 0; t < GPL; ++t) {
+        const int k = lane + 64 * t;
+        gl[mm][t] = (mm < mc && k < ND) ? a.gG[((int64_t)(m0 + mm) * a.rows + row) * ND + k] : 0.f;
+      }
     for (int mm = 0; mm < mc; ++mm) {
-      // this member's dE/dG of atom i, then its adjoints in three uniform passes:
-      // radial copies, M1 contractions, M2 contractions
-      for (int k = lane; k < ND; k += 64) sgg[wv][k] = a.gG[((int64_t)(m0 + mm) * a.rows + row) * ND + k];
+      // this member's adjoints in three uniform passes: radial copies, M1
+      // contractions, M2 contractions
+#pragma unroll
+      for (int t = 0; t < GPL; ++t) {
+        const int k = lane + 64 * t;
+        if (k < ND) sgg[wv][k] = gl[mm][t];
+      }
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       const float* __restrict__ g = sgg[wv];
@@ -702,7 +718,11 @@ __global__ __launch_bounds__(256) void k_sur_pairw(ForceArgs a) {
         A[nn] = e * fc;
         dA[nn] = e * (-2.0f * ETA_A * t) * fc + e * dfc;
       }
-      for (int mm = 0; mm < mc; ++mm) {
+      float ww[MCH][3];
+#pragma unroll
+      for (int mm = 0; mm < MCH; ++mm) {
+        ww[mm][0] = ww[mm][1] = ww[mm][2] = 0.f;
+        if (mm >= mc) continue;
         const float* __restrict__ G = sg[wv][mm][b];
         float sr = 0.f;
 #pragma unroll
@@ -725,13 +745,20 @@ __global__ __launch_bounds__(256) void k_sur_pairw(ForceArgs a) {
           wz += cu * uz + A[nn] * ir * (g1[2] + 2.0f * Gz);
         }
         if (!in) { wx = 0.f; wy = 0.f; wz = 0.f; }
-        // own side: F_i += w; the neighbour's side goes to the slot of i in row j
-#pragma unroll
-        for (int q = 0; q < MCH; ++q)
-          if (q == mm) { fo[q][0] += wx; fo[q][1] += wy; fo[q][2] += wz; }
-        const int mk = a.mir[i * (int64_t)a.far_w + k];
-        if (mk >= 0) a.w[(int64_t)(m0 + mm) * a.slots + (int64_t)j * a.far_w + mk] = make_float4(wx, wy, wz, 0.f);
+        fo[mm][0] += wx;
+        fo[mm][1] += wy;
+        fo[mm][2] += wz;
+        ww[mm][0] = wx;
+        ww[mm][1] = wy;
+        ww[mm][2] = wz;
       }
+      // own side: F_i += w; the neighbour's side, all members of the chunk in
+      // one 48-byte record, stays in i's own slot k (coalesced) and is pulled
+      // by j through the mirror index
+      float4* __restrict__ wp = a.w + ((int64_t)(m0 / MCH) * a.slots + i * (int64_t)a.far_w + k) * 3;
+      wp[0] = make_float4(ww[0][0], ww[0][1], ww[0][2], ww[1][0]);
+      wp[1] = make_float4(ww[1][1], ww[1][2], ww[2][0], ww[2][1]);
+      wp[2] = make_float4(ww[2][2], ww[3][0], ww[3][1], ww[3][2]);
     }
     for (int mm = 0; mm < mc; ++mm) {
       float fx = fo[mm][0], fy = fo[mm][1], fz = fo[mm][2];
@@ -752,10 +779,14 @@ __global__ __launch_bounds__(256) void k_sur_pairw(ForceArgs a) {
   }
 }
 
-// F[m][i] = Fown[m][i] - sum_k w[m][i, k] (contributions received from the
-// neighbours), sorted order; one wavefront per atom, one slot per lane
+// F[m][j] = Fown[m][j] - sum_k w[m][i, slot of j in row i] over the neighbours
+// i = row_j[k] (the slot is mir[j, k]), sorted order; one wavefront per atom,
+// one neighbour per lane, one 48-byte record per neighbour for each chunk of
+// 4 members
 __global__ __launch_bounds__(256) void k_sur_gather(int64_t n, int32_t members, int64_t slots,
-                                                    const int32_t* __restrict__ far_cnt, int32_t far_w,
+                                                    const int32_t* __restrict__ far_cnt,
+                                                    const int32_t* __restrict__ far_j, int32_t far_w,
+                                                    const int32_t* __restrict__ mir,
                                                     const float4* __restrict__ w, const float* __restrict__ Fown,
                                                     float* __restrict__ F) {
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -763,25 +794,30 @@ __global__ __launch_bounds__(256) void k_sur_gather(int64_t n, int32_t members, 
   if (i >= n) return;
   const int cnt = far_cnt[i];
   const int64_t base = i * (int64_t)far_w;
-  for (int m = 0; m < members; ++m) {
-    const float4* __restrict__ wm = w + (int64_t)m * slots;
-    float fx = 0.f, fy = 0.f, fz = 0.f;
+  for (int m0 = 0; m0 < members; m0 += 4) {
+    const float4* __restrict__ wc = w + (int64_t)(m0 / 4) * slots * 3;
+    float f[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) f[q] = 0.f;
     for (int k = lane; k < cnt; k += 64) {
-      const float4 p = wm[base + k];
-      fx += p.x;
-      fy += p.y;
-      fz += p.z;
+      const int mk = mir[base + k];
+      if (mk < 0) continue;
+      const float4* __restrict__ p = wc + ((int64_t)far_j[base + k] * far_w + mk) * 3;
+      const float4 p0 = p[0], p1 = p[1], p2 = p[2];
+      f[0] += p0.x; f[1] += p0.y; f[2] += p0.z; f[3] += p0.w;
+      f[4] += p1.x; f[5] += p1.y; f[6] += p1.z; f[7] += p1.w;
+      f[8] += p2.x; f[9] += p2.y; f[10] += p2.z; f[11] += p2.w;
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      fx += __shfl_down(fx, off, 64);
-      fy += __shfl_down(fy, off, 64);
-      fz += __shfl_down(fz, off, 64);
-    }
+#pragma unroll
+    for (int q = 0; q < 12; ++q)
+      for (int off = 32; off > 0; off >>= 1) f[q] += __shfl_down(f[q], off, 64);
     if (lane == 0) {
-      const int64_t o = ((int64_t)m * n + i) * 3;
-      F[o] = Fown[o] - fx;
-      F[o + 1] = Fown[o + 1] - fy;
-      F[o + 2] = Fown[o + 2] - fz;
+      for (int mm = 0; mm < 4 && m0 + mm < members; ++mm) {
+        const int64_t o = ((int64_t)(m0 + mm) * n + i) * 3;
+        F[o] = Fown[o] - f[3 * mm];
+        F[o + 1] = Fown[o + 1] - f[3 * mm + 1];
+        F[o + 2] = Fown[o + 2] - f[3 * mm + 2];
+      }
     }
   }
 }
@@ -1186,7 +1222,7 @@ int prepare(reaxff_surrogate* s, int64_t n, const double* pos, const int32_t* ty
   const int64_t slots = n * (int64_t)L.far_w;
   if (slots > s->cap_slots) {
     const int64_t cs = slots + slots / 8;
-    if ((rc = salloc(s, s->w, (int64_t)s->members * cs)) || (rc = salloc(s, s->mir, cs))) return rc;
+    if ((rc = salloc(s, s->w, (int64_t)3 * ((s->members + 3) / 4) * cs)) || (rc = salloc(s, s->mir, cs))) return rc;
     s->cap_slots = cs;
   }
   s->sorted_rows = L.far_w <= SORT_MAX && n < (1 << KEY_SHIFT);
@@ -1279,8 +1315,8 @@ int evaluate_frame(reaxff_surrogate* s, hipStream_t st) {
   fa.w = s->w;
   fa.Fown = s->Fown;
   hipLaunchKernelGGL(k_sur_pairw, dim3(nb(n, 4)), dim3(256), 0, st, fa);
-  hipLaunchKernelGGL(k_sur_gather, dim3(nb(n, 4)), dim3(256), 0, st, n, M, s->cap_slots, L.far_cnt, L.far_w,
-                     s->w, s->Fown, s->F);
+  hipLaunchKernelGGL(k_sur_gather, dim3(nb(n, 4)), dim3(256), 0, st, n, M, s->cap_slots, L.far_cnt, L.far_j,
+                     L.far_w, s->mir, s->w, s->Fown, s->F);
   return hipGetLastError() == hipSuccess ? 0 : sfail(s, REAXFF_ERR_HIP, "surrogate kernels");
 }
 
