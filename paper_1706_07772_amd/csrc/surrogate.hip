@@ -91,27 +91,39 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
 // dimension lda, K contiguous), B given transposed in global memory as
 // Bt[N][K].  Wave w owns column tiles w, w + 4, ...; acc[rt][c] holds the
 // 16 x 16 block (row tile rt, column tile w + 4 c).  Lane l holds rows
-// 16 rt + 4 (l >> 4) + i, column 16 ct + (l & 15).
+// 16 rt + 4 (l >> 4) + i, column 16 ct + (l & 15).  All of the wave's B
+// fragments are loaded before the first product, so the weights cost one
+// memory round trip per product rather than one per 32-wide K step.
 template <int N, int K, int CT>
 __device__ __forceinline__ void gemm_tile(const uint16_t* __restrict__ A, int lda,
                                           const uint16_t* __restrict__ Bt, f32x4 (&acc)[4][CT]) {
+  static_assert(K % 32 == 0, "K in steps of 32");
+  constexpr int KB = K / 32;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
     for (int c = 0; c < CT; ++c) acc[rt][c] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int kl = (lane >> 4) * 8, rl = lane & 15;
-  for (int kb = 0; kb < K; kb += 32) {
+  bf16x8 bf[KB][CT];
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      const int ct = w + 4 * c;
+      bf[kb][c] = ct * 16 < N ? ld8(Bt + (int64_t)(ct * 16 + rl) * K + kb * 32 + kl) : bf16x8{};
+    }
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
     bf16x8 a[4];
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt) a[rt] = ld8(A + (rt * 16 + rl) * lda + kb + kl);
+    for (int rt = 0; rt < 4; ++rt) a[rt] = ld8(A + (rt * 16 + rl) * lda + kb * 32 + kl);
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
       const int ct = w + 4 * c;
       if (ct * 16 < N) {
-        const bf16x8 b = ld8(Bt + (int64_t)(ct * 16 + rl) * K + kb + kl);
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt) acc[rt][c] = mfma(a[rt], b, acc[rt][c]);
+        for (int rt = 0; rt < 4; ++rt) acc[rt][c] = mfma(a[rt], bf[kb][c], acc[rt][c]);
       }
     }
   }
