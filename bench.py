@@ -44,7 +44,7 @@ WORK = {
 # recorded in profiles/kernels_petn_1044000.md.  Valid only for the kernel
 # version they were taken on; set to None when the kernel changes.
 TRAFFIC = {
-    "nonbonded": 2.117e9,
+    "nonbonded": None,
 }
 
 PHASES = {
@@ -52,7 +52,7 @@ PHASES = {
               "list_sweep", "bondtest", "compact", "mirror"),
     "bonded": ("gather_q", "bo_prime", "delta_prime", "bo_corr", "atom_state", "atom_energy",
                "tasks", "angles", "torsions", "hbonds", "hb_acceptors"),
-    "nonbonded": ("nonbonded",),
+    "nonbonded": ("nonbonded", "nb_reduce"),
     "backward": ("back_s", "back_corr", "back_dp", "forces"),
 }
 
@@ -357,6 +357,13 @@ def main():
                             "traffic": TRAFFIC.get(dom),
                             "units_per_launch": units, "unit_name": unit,
                             "flops_per_unit": per, "avg_ms": kernels[dom]["ms_avg"]}
+                # the whole nonbonded term: the pair kernel and, in the half
+                # evaluation, the per-atom sum of the cells' partial forces
+                extra = kernels.get("nb_reduce")
+                if dom == "nonbonded" and extra:
+                    term_ms = kernels[dom]["ms_avg"] + extra["ms_avg"]
+                    roofline["term_ms"] = term_ms
+                    roofline["term_frac"] = flops / (term_ms * 1e-3) / 1e12 / PEAK_FP64_VALU_TFLOPS
         if roofline is None:
             roofline = {"kernel": dom, "bound": "alu", "achieved": None,
                         "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s", "frac": None,

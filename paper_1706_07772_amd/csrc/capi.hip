@@ -155,7 +155,7 @@ int alloc_atoms(reaxff_ctx* c, int64_t n) {
   const int64_t need = n + 1;
   int64_t tmp;
 #define G(ptr) do { tmp = c->cap_n; if (grow(c, ptr, tmp, need)) return REAXFF_ERR_HIP; cap = tmp; } while (0)
-  G(c->L.perm); G(c->L.type_s); G(c->L.xs); G(c->L.far_cnt); G(c->L.bond_off); G(c->L.hb_cnt);
+  G(c->L.perm); G(c->L.type_s); G(c->L.xs); G(c->L.far_cnt); G(c->L.far_lo); G(c->L.bond_off); G(c->L.hb_cnt);
   G(c->L.ha_cnt);
   G(c->sc.cid); G(c->sc.cell_s); G(c->sc.cnt_cand); G(c->sc.cnt_bond);
   G(c->W.dp); G(c->W.ast); G(c->W.gS); G(c->W.gSig); G(c->W.gSBO); G(c->W.gStot); G(c->W.gDp);
@@ -243,7 +243,7 @@ void reaxff_destroy(reaxff_ctx* c) {
                   c->W.bd, c->W.bop, c->W.dbop, c->W.bo, c->W.gbo, c->W.gvec, c->W.gup, c->W.dp,
                   c->W.ast, c->W.gS, c->W.gSig, c->W.gSBO, c->W.gStot, c->W.gDp, c->W.fnb,
                   c->W.xq, c->W.counters, c->W.cnt_ang, c->W.cnt_tor, c->W.cnt_don,
-                  c->W.off_ang, c->W.off_tor, c->W.off_don, c->W.ang, c->W.tor, c->W.don, c->W.donrec,
+                  c->W.off_ang, c->W.off_tor, c->W.off_don, c->W.ang, c->W.tor, c->W.don, c->W.donrec, c->L.far_lo, c->W.nbpart, c->W.nbtab,
                   c->L.bond_i, c->sc.cid, c->sc.cell_s, c->sc.cell_count,
                   c->sc.cell_cursor, c->sc.flag, c->sc.cnt_cand, c->sc.cnt_bond,
                   c->sc.cand_j, c->sc.bond_t, c->sc.need,
@@ -394,6 +394,18 @@ int reaxff_build_lists(reaxff_ctx* c, int64_t n, const double* pos, const int32_
     if (attempt >= 3) return fail(c, REAXFF_ERR_CAPACITY, "list widths did not converge");
   }
   c->L.nfar = th[0] / 2;
+  // half nonbonded evaluation when every cell's upper stencil fits in LDS
+  // (need[5], reported by the sweep; zero when a dimension is covered whole)
+  c->L.cell_of = c->sc.cell_s;
+  c->L.nb_half = c->L.far_slots && n > 0 && need[5] > 0 && need[5] <= NB_HALF_CAP;
+  if (c->L.nb_half) {
+    int64_t t = c->W.cap_nbpart;
+    if (grow(c, c->W.nbpart, t, ncell * 3 * (int64_t)NB_HALF_CAP, 1.0)) return REAXFF_ERR_HIP;
+    c->W.cap_nbpart = t;
+    t = c->W.cap_nbtab;
+    if (grow(c, c->W.nbtab, t, ncell * (int64_t)NB_QMAX, 1.0)) return REAXFF_ERR_HIP;
+    c->W.cap_nbtab = t;
+  }
   c->L.nbond = t32[0];
   c->L.nhb = th[4];
   c->L.bound_ang = th[1];

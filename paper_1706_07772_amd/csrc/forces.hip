@@ -599,6 +599,261 @@ __global__ __launch_bounds__(NBC_BS) void k_nonbonded(const DevParams* __restric
 }
 
 // ---------------------------------------------------------------------------
+// (9) half evaluation.  With the chunk order of stencil_chunk and no
+//     dimension covered whole, the neighbours of atom i at a larger slot than
+//     i's own are exactly those at a lexicographically positive cell offset
+//     (or after i in its own cell); of every pair, exactly one atom sees the
+//     other there.  The workgroup of cell c evaluates each such pair once,
+//     for the row suffix [far_lo[i], cnt_i) of each of its atoms, with only
+//     the upper stencil (from the cell's first atom on) in LDS.  Both atoms'
+//     forces are added to LDS accumulators on the staged slots (the centre's
+//     through a wavefront sum when the wavefront moves on, the partner's per
+//     pair); the accumulators are stored, not added, to the cell's partial
+//     array, and k_nb_reduce sums the partial arrays of the 63 cells whose
+//     upper stencil holds an atom.  Energies take each pair once.
+// ---------------------------------------------------------------------------
+constexpr int NBH_BS = 512, NBH_WAVES = NBH_BS / 64;
+
+__global__ __launch_bounds__(NBH_BS) void k_nonbonded_half(const DevParams* __restrict__ P, Grid g, Lists L,
+                                                           Work W, int ncell, int per_xcd,
+                                                           double* __restrict__ energies) {
+  __shared__ NbP sp[NT * NT];
+  __shared__ double sxx[NB_HALF_CAP], sxy[NB_HALF_CAP], sxz[NB_HALF_CAP], sxq[NB_HALF_CAP];
+  __shared__ double fax[NB_HALF_CAP], fay[NB_HALF_CAP], faz[NB_HALF_CAP];
+  __shared__ unsigned char sty[NB_HALF_CAP];
+  __shared__ int q_s0[NBC_MAXQ], q_base[NBC_MAXQ + 1];
+  __shared__ int upre[NBC_MG + 1];
+  __shared__ double ixx[NBC_MG], ixy[NBC_MG], ixz[NBC_MG], iqq[NBC_MG];
+  __shared__ int ity[NBC_MG], icnt[NBC_MG], ilo[NBC_MG];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int c = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+  if (c >= ncell) return;
+  const int a0 = L.cell_start[c], m = L.cell_start[c + 1] - a0;
+  if (m == 0) return;   // no pairs; the reduce skips empty cells
+  if (tid < NT * NT) sp[tid] = nb_params(P->pair[tid]);
+  const int nq = stencil_chunks(g);
+  if (tid < nq) {
+    int s0, s1;
+    double sx, sy, sz;
+    stencil_chunk(g, L.cell_start, c, tid, s0, s1, sx, sy, sz);
+    q_s0[tid] = s0;
+    q_base[tid + 1] = s1 - s0;
+  }
+  __syncthreads();
+  if (wv == 0) {
+    const int v = wave_incl_scan(lane < nq ? q_base[lane + 1] : 0);
+    if (lane < nq) q_base[lane + 1] = v;
+    if (lane == 0) q_base[0] = 0;
+  }
+  __syncthreads();
+  const int nst = q_base[nq];
+  // the centre cell's own chunk: its column is the middle one, and its
+  // unwrapped z range comes second when the column wraps below the cell
+  const int c2 = c % g.nc[2];
+  const int col_own = g.reach * g.span[1] + g.reach;
+  const bool wrap_first = g.periodic && c2 - g.reach < 0;
+  const int q_own = 2 * col_own + (wrap_first ? 1 : 0);
+  const int S0 = q_base[q_own] + (a0 - q_s0[q_own]);   // slot of the cell's first atom
+  const int nup = nst - S0;                            // <= NB_HALF_CAP (checked by the sweep)
+  // chunk bases relative to S0, for the reduce
+  if (tid <= nq) W.nbtab[(int64_t)c * NB_QMAX + tid] = q_base[tid] - S0;
+  for (int t0 = 0; t0 < nup; t0 += 2 * NBH_BS) {
+    int idx[2];
+    double4 v[2];
+    int ty[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int t = t0 + u * NBH_BS + tid;
+      idx[u] = -1;
+      if (t < nup) {
+        const int slot = S0 + t;
+        const int q = last_le(q_base, nq, slot);
+        idx[u] = q_s0[q] + (slot - q_base[q]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+      if (idx[u] >= 0) {
+        v[u] = W.xq[idx[u]];
+        ty[u] = L.type_s[idx[u]];
+      }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int t = t0 + u * NBH_BS + tid;
+      if (idx[u] >= 0) {
+        sxx[t] = v[u].x;
+        sxy[t] = v[u].y;
+        sxz[t] = v[u].z;
+        sxq[t] = v[u].w;
+        sty[t] = (unsigned char)ty[u];
+      }
+      if (t < nup) fax[t] = fay[t] = faz[t] = 0.0;
+    }
+  }
+  const double iR = P->inv_r_nonb, pv = P->p_vdW1, ipv = P->inv_p_vdW1;
+  double evdw = 0.0, ecoul = 0.0;
+  for (int g0 = 0; g0 < m; g0 += NBC_MG) {
+    const int mg = m - g0 < NBC_MG ? m - g0 : NBC_MG;
+    __syncthreads();   // staging done / previous pass's units done
+    if (wv == 0) {
+      int nu = 0;
+      if (lane < mg) {
+        const int i = a0 + g0 + lane;
+        const int cnt = L.far_cnt[i], lo = L.far_lo[i];
+        const double4 xi = W.xq[i];
+        ixx[lane] = xi.x;
+        ixy[lane] = xi.y;
+        ixz[lane] = xi.z;
+        iqq[lane] = xi.w * C_ELE;
+        ity[lane] = L.type_s[i];
+        icnt[lane] = cnt;
+        ilo[lane] = lo;
+        nu = (cnt - lo + 63) >> 6;
+      }
+      const int v = wave_incl_scan(nu);
+      if (lane < mg) upre[lane + 1] = v;
+      if (lane == 0) upre[0] = 0;
+    }
+    __syncthreads();
+    const int U = __builtin_amdgcn_readfirstlane(upre[mg]);
+    const int wu = __builtin_amdgcn_readfirstlane(wv);
+    const int u0 = U * wu / NBH_WAVES, u1 = U * (wu + 1) / NBH_WAVES;
+    if (u0 < u1) {
+      auto locate = [&](int u, int& a) {
+        while (__builtin_amdgcn_readfirstlane(upre[a + 1]) <= u) ++a;
+      };
+      auto fetch = [&](int u, int a) {
+        const int k = __builtin_amdgcn_readfirstlane(ilo[a]) +
+                      ((u - __builtin_amdgcn_readfirstlane(upre[a])) << 6) + lane;
+        const int32_t* __restrict__ row = L.far_j + (int64_t)(a0 + g0 + a) * L.far_w;
+        const int t = k < __builtin_amdgcn_readfirstlane(icnt[a]) ? row[k] - S0 : -1;
+        return (unsigned)t < (unsigned)nup ? t : -1;   // always in range for a consistent list
+      };
+      int a = __builtin_amdgcn_readfirstlane(last_le(upre, mg, u0));
+      locate(u0, a);
+      int slot = fetch(u0, a);
+      int cur = a;
+      double xix = ixx[cur], xiy = ixy[cur], xiz = ixz[cur], qi = iqq[cur];
+      const NbP* __restrict__ spi = sp + ity[cur] * NT;
+      double fx = 0.0, fy = 0.0, fz = 0.0;
+      auto flush = [&]() {
+        for (int off = 32; off > 0; off >>= 1) {
+          fx += __shfl_down(fx, off, 64);
+          fy += __shfl_down(fy, off, 64);
+          fz += __shfl_down(fz, off, 64);
+        }
+        if (lane == 0) {
+          const int t = g0 + cur;   // the centre's staged index: slot - S0 = i - a0
+          atomicAdd(&fax[t], fx);
+          atomicAdd(&fay[t], fy);
+          atomicAdd(&faz[t], fz);
+        }
+        fx = fy = fz = 0.0;
+      };
+      for (int u = u0; u < u1; ++u) {
+        const int tnow = slot, anow = a;
+        if (u + 1 < u1) {
+          locate(u + 1, a);
+          slot = fetch(u + 1, a);
+        }
+        if (anow != cur) {
+          flush();
+          cur = anow;
+          xix = ixx[cur];
+          xiy = ixy[cur];
+          xiz = ixz[cur];
+          qi = iqq[cur];
+          spi = sp + ity[cur] * NT;
+        }
+        if (tnow >= 0) {
+          double dx = sxx[tnow] - xix, dy = sxy[tnow] - xiy, dz = sxz[tnow] - xiz;
+          if (g.periodic) {
+            dx = min_image(dx, g.L[0], g.invL[0]);
+            dy = min_image(dy, g.L[1], g.invL[1]);
+            dz = min_image(dz, g.L[2], g.invL[2]);
+          }
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          const NbOut o = nb_pair(spi[sty[tnow]], iR, pv, ipv, qi * sxq[tnow], r2);
+          evdw += o.ev;
+          ecoul += o.eq;
+          const double px = o.f * dx, py = o.f * dy, pz = o.f * dz;
+          fx += px;
+          fy += py;
+          fz += pz;
+          atomicAdd(&fax[tnow], -px);
+          atomicAdd(&fay[tnow], -py);
+          atomicAdd(&faz[tnow], -pz);
+        }
+      }
+      flush();
+    }
+  }
+  __syncthreads();
+  double* __restrict__ part = W.nbpart + (int64_t)c * 3 * NB_HALF_CAP;
+  for (int t = tid; t < nup; t += NBH_BS) {
+    part[t] = fax[t];
+    part[NB_HALF_CAP + t] = fay[t];
+    part[2 * NB_HALF_CAP + t] = faz[t];
+  }
+  block_add<NBH_BS>(evdw, energies + E_VDW);
+  block_add<NBH_BS>(ecoul, energies + E_COUL);
+}
+
+// Nonbonded force of each atom j from the partial arrays of the cells whose
+// upper stencil holds it: cells c = cell(j) - o for the offsets o with
+// (o_x, o_y) lexicographically positive, or o_x = o_y = 0 and o_z >= 0.  In
+// c's chunk sequence j lies in column (o_x, o_y) and in that column's
+// unwrapped or wrapped z range; its staged index is the chunk's base
+// (relative to c's first atom) plus its place in the chunk.  Writes the
+// per-atom accumulator the hydrogen-bond kernels then add to.
+__global__ __launch_bounds__(BS) void k_nb_reduce(Grid g, Lists L, Work W) {
+  const int64_t j = xcd_block() * blockDim.x + threadIdx.x;
+  if (j >= L.n) return;
+  const int R = g.reach;
+  const int cj = L.cell_of[j];
+  const int jz = cj % g.nc[2], jy = (cj / g.nc[2]) % g.nc[1], jx = cj / (g.nc[1] * g.nc[2]);
+  const int jrow = (jx * g.nc[1] + jy) * g.nc[2];
+  double fx = 0.0, fy = 0.0, fz = 0.0;
+  for (int ox = 0; ox <= R; ++ox) {
+    int cx = jx - ox;
+    if (cx < 0) {
+      if (!g.periodic) continue;
+      cx += g.nc[0];
+    }
+    for (int oy = ox == 0 ? 0 : -R; oy <= R; ++oy) {
+      int cy = jy - oy;
+      if (cy < 0 || cy >= g.nc[1]) {
+        if (!g.periodic) continue;
+        cy += cy < 0 ? g.nc[1] : -g.nc[1];
+      }
+      const int col = (ox + R) * g.span[1] + (oy + R);
+      for (int oz = (ox == 0 && oy == 0) ? 0 : -R; oz <= R; ++oz) {
+        int cz = jz - oz;
+        if (cz < 0 || cz >= g.nc[2]) {
+          if (!g.periodic) continue;
+          cz += cz < 0 ? g.nc[2] : -g.nc[2];
+        }
+        const int c = (cx * g.nc[1] + cy) * g.nc[2] + cz;
+        if (L.cell_start[c + 1] == L.cell_start[c]) continue;   // empty: no partial array
+        int za0, za1, zb0, zb1;
+        column_ranges(g, cz, za0, za1, zb0, zb1);
+        const bool in_a = jz >= za0 && jz < za1;
+        const bool wrap_first = zb1 > zb0 && cz - R < 0;
+        const int q = 2 * col + ((in_a != wrap_first) ? 0 : 1);
+        const int s0 = L.cell_start[jrow + (in_a ? za0 : zb0)];
+        const int t = W.nbtab[(int64_t)c * NB_QMAX + q] + ((int)j - s0);
+        if ((unsigned)t >= (unsigned)NB_HALF_CAP) continue;   // never taken for a consistent list
+        const double* __restrict__ part = W.nbpart + (int64_t)c * 3 * NB_HALF_CAP;
+        fx += part[t];
+        fy += part[NB_HALF_CAP + t];
+        fz += part[2 * NB_HALF_CAP + t];
+      }
+    }
+  }
+  W.fnb[j] = make_double4(fx, fy, fz, 0.0);
+}
+
+// ---------------------------------------------------------------------------
 // backward
 // ---------------------------------------------------------------------------
 // (10)-(13) backward, one thread per atom
@@ -641,7 +896,7 @@ const char* const kKernelNames[KID_COUNT] = {
     "bbox", "cell_hist", "cell_scatter", "cell_sort", "gather_sorted", "list_sweep", "scan",
     "bondtest", "compact", "mirror", "zero", "gather_q", "bo_prime", "delta_prime", "bo_corr", "atom_state",
     "atom_energy", "tasks", "angles", "torsions", "hbonds", "hb_acceptors", "nonbonded", "back_s", "back_corr",
-    "back_dp", "forces", "batch"};
+    "back_dp", "forces", "batch", "nb_reduce"};
 
 // grid of a grid-stride task kernel: enough blocks to fill the chip, no more
 // than the task bound needs
@@ -677,8 +932,14 @@ int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, co
     // the kernel reads neighbours by stencil slot through a chunk table
     if (!L.far_slots || stencil_chunks(g) > NBC_MAXQ) return -1;
     const int ncell = g.nc[0] * g.nc[1] * g.nc[2], per_xcd = (ncell + 7) / 8;
-    LAUNCH(KID_NONBONDED, k_nonbonded, dim3(8u * (unsigned)per_xcd), dim3(NBC_BS), 0, st, P, g, L, W,
-           ncell, per_xcd, energies);
+    if (L.nb_half) {
+      LAUNCH(KID_NONBONDED, k_nonbonded_half, dim3(8u * (unsigned)per_xcd), dim3(NBH_BS), 0, st, P, g, L, W,
+             ncell, per_xcd, energies);
+      LAUNCH(KID_NB_REDUCE, k_nb_reduce, grid, blk, 0, st, g, L, W);
+    } else {
+      LAUNCH(KID_NONBONDED, k_nonbonded, dim3(8u * (unsigned)per_xcd), dim3(NBC_BS), 0, st, P, g, L, W,
+             ncell, per_xcd, energies);
+    }
   }
   LAUNCH(KID_BO_PRIME, k_bo_prime, grid, blk, 0, st, P, g, L, W);
   LAUNCH(KID_DELTA_PRIME, k_delta_prime, grid, blk, 0, st, P, L, W);

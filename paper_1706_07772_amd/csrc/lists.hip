@@ -10,6 +10,7 @@
 // each entry at its atom's offset.  No slot is ever contended, the order of
 // entries is deterministic, and the only host synchronisation is the readback
 // of the three totals that size the buffers.
+#include <type_traits>
 #include "reaxff_dev.h"
 #include "internal.h"
 #include "terms.h"
@@ -136,7 +137,7 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
     int far_w, int32_t* __restrict__ cnt_cand, int32_t* __restrict__ cand_j, int cand_w,
     int32_t* __restrict__ hb_cnt, int32_t* __restrict__ hb_j, int hb_w,
     int32_t* __restrict__ ha_cnt, int32_t* __restrict__ ha_j, int ha_w, int slots,
-    int32_t* __restrict__ need, unsigned long long* __restrict__ totals) {
+    int32_t* __restrict__ far_lo, int32_t* __restrict__ need, unsigned long long* __restrict__ totals) {
   __shared__ unsigned long long red[SWEEP_WAVES][2];
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int c = blockIdx.x * SWEEP_WAVES + wv;
@@ -165,8 +166,12 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
     if (lane < mi) xmine = xs[a0 + ig + lane];
     const int tmine = (int)xmine.w;
     int kf = 0, kc = 0, kh = 0, ka = 0;       // lane l: counts of the cell's atom l
-    // slot0: stencil slot of candidate s0
-    auto chunk = [&](int s0, int s1, double sx, double sy, double sz, int slot0) {
+    int klo = 0;                              // lane l: far entries before atom l's own slot
+    // slot0: stencil slot of candidate s0; own_split (compile-time): the
+    // centre cell's own chunk, whose entries before the atom itself are added
+    // to klo
+    auto chunk = [&](int s0, int s1, double sx, double sy, double sz, int slot0, auto own_split) {
+      constexpr bool OWN = decltype(own_split)::value;
       for (int base = s0; base < s1; base += 64) {
         const int s = base + lane;
         const bool valid = s < s1;
@@ -210,6 +215,10 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
               if (k < far_w) far_j[(int64_t)i * far_w + k] = slots ? slot0 + (s - s0) : s;
             }
             kf = writelane_i(k0 + __popcll(mf), l, kf);
+            if constexpr (OWN) {
+              const unsigned long long ml = __ballot(f && s < i);
+              klo = writelane_i(readlane_i(klo, l) + __popcll(ml), l, klo);
+            }
             if (mb) {
               const int k1 = readlane_i(kc, l);
               if (b) {
@@ -238,10 +247,15 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
         }
       }
     };
-    // the chunks in stencil_chunk's order (x offset, y offset, unwrapped
-    // then wrapped z range), slots counted along; the two z ranges keep their
-    // own call sites so the unwrapped one folds its zero shift
-    int slot = 0;
+    // the chunks in stencil_chunk's order (x offset, y offset, then the z
+    // range at negative offsets first), slots counted along; the two z ranges
+    // keep their own call sites so the unwrapped one folds its zero shift.
+    // With far_lo set and no dimension covered whole, klo counts the entries
+    // that precede the atom's own slot and own0 is the slot of the cell's
+    // first atom.
+    const bool halfable = far_lo != nullptr && !g.full[0] && !g.full[1] && !g.full[2];
+    const bool wrap_first = zb1 > zb0 && c2 - g.reach < 0;
+    int slot = 0, own0 = 0;
     for (int a = 0; a < g.span[0]; ++a) {
       int x = g.full[0] ? a : c0 + a - g.reach;
       double sx = 0.0;
@@ -257,19 +271,33 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
           else if (y >= g.nc[1]) { y -= g.nc[1]; sy = -g.L[1]; }
         } else if (y < 0 || y >= g.nc[1]) continue;
         const int row = (x * g.nc[1] + y) * g.nc[2];
+        const bool own = a == g.reach && bb == g.reach;
         const int sa0 = cstart[row + za0], sa1 = cstart[row + za1];
-        chunk(sa0, sa1, sx, sy, 0.0, slot);
+        const int sb0 = zb1 > zb0 ? cstart[row + zb0] : 0, sb1 = zb1 > zb0 ? cstart[row + zb1] : 0;
+        if (wrap_first && sb1 > sb0) {
+          chunk(sb0, sb1, sx, sy, szb, slot, std::false_type{});
+          slot += sb1 - sb0;
+        }
+        if (own && halfable) {
+          // every entry so far lies before the cell's atoms in slot order
+          own0 = slot + (a0 - sa0);
+          klo = kf;
+          chunk(sa0, sa1, sx, sy, 0.0, slot, std::true_type{});
+        } else {
+          chunk(sa0, sa1, sx, sy, 0.0, slot, std::false_type{});
+        }
         slot += sa1 - sa0;
-        if (zb1 > zb0) {
-          const int sb0 = cstart[row + zb0], sb1 = cstart[row + zb1];
-          chunk(sb0, sb1, sx, sy, szb, slot);
+        if (!wrap_first && sb1 > sb0) {
+          chunk(sb0, sb1, sx, sy, szb, slot, std::false_type{});
           slot += sb1 - sb0;
         }
       }
     }
+    if (halfable && ig == 0 && lane == 0 && m > 0) atomicMax(&need[5], slot - own0);
     if (lane < mi) {
       const int i = a0 + ig + lane;
       far_cnt[i] = kf;
+      if (far_lo) far_lo[i] = klo;
       cnt_cand[i] = kc;
       hb_cnt[i] = kh;
       ha_cnt[i] = ka;
@@ -505,12 +533,14 @@ int launch_sweep(const DevParams* P, const Grid& g, int64_t n, int ncell, Scratc
   if (g.periodic && !g.shift_ok)
     hipLaunchKernelGGL(k_sweep<true>, dim3(nblk(ncell, SWEEP_WAVES)), dim3(64 * SWEEP_WAVES), 0, st, P, g,
                        ncell, L.xs, L.cell_start, L.far_cnt, L.far_j, L.far_w, sc.cnt_cand, sc.cand_j,
-                       sc.cand_w, L.hb_cnt, L.hb_j, L.hb_w, L.ha_cnt, L.ha_j, L.ha_w, L.far_slots, sc.need,
+                       sc.cand_w, L.hb_cnt, L.hb_j, L.hb_w, L.ha_cnt, L.ha_j, L.ha_w, L.far_slots,
+                     L.far_slots ? L.far_lo : nullptr, sc.need,
                        reinterpret_cast<unsigned long long*>(sc.totals));
   else
     hipLaunchKernelGGL(k_sweep<false>, dim3(nblk(ncell, SWEEP_WAVES)), dim3(64 * SWEEP_WAVES), 0, st, P, g,
                        ncell, L.xs, L.cell_start, L.far_cnt, L.far_j, L.far_w, sc.cnt_cand, sc.cand_j,
-                       sc.cand_w, L.hb_cnt, L.hb_j, L.hb_w, L.ha_cnt, L.ha_j, L.ha_w, L.far_slots, sc.need,
+                       sc.cand_w, L.hb_cnt, L.hb_j, L.hb_w, L.ha_cnt, L.ha_j, L.ha_w, L.far_slots,
+                     L.far_slots ? L.far_lo : nullptr, sc.need,
                        reinterpret_cast<unsigned long long*>(sc.totals));
   pf.end(st);
   pf.begin(KID_BONDTEST, st);

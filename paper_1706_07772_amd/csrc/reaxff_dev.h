@@ -93,6 +93,13 @@ struct Lists {
   int32_t* far_j;
   int32_t far_w;
   int32_t far_slots;
+  // half evaluation of the nonbonded term (slot form, no dimension covered
+  // whole, every cell's upper stencil within NB_HALF_CAP atoms): far_lo[i]
+  // entries of row i precede i's own slot; the pairs of the rest of the row
+  // are evaluated by i's cell, the others by the partner's cell
+  int32_t* far_lo;      // [n]
+  int32_t nb_half;
+  int32_t* cell_of;     // [n] cell of each sorted atom
   // full bond list
   int32_t* bond_off;    // [n + 1]
   int32_t* bond_j;
@@ -133,6 +140,12 @@ struct DonRec {
   int32_t X, tX;     // donor atom and its type
 };
 
+// atoms of a cell's upper stencil (the centre cell from its first atom on,
+// and every later chunk) that the half nonbonded kernel holds in LDS
+constexpr int NB_HALF_CAP = 1024;
+// chunk-table entries per cell: 2 (2 reach + 1)^2 <= 50 chunks and the total
+constexpr int NB_QMAX = 64;
+
 struct Work {
   // per directed bond entry
   double4* bd;     // (dx, dy, dz, r): x_j - x_i
@@ -165,6 +178,12 @@ struct Work {
   int32_t* don;      // entry h->X
   DonRec* donrec;    // per donor task: what the acceptor side reads of h->X
   int64_t cap_ang, cap_tor, cap_don;
+  // half nonbonded evaluation: per-cell partial forces on the upper stencil
+  // ([cell][3][NB_HALF_CAP]) and per-cell chunk bases relative to the cell's
+  // first atom ([cell][NB_QMAX])
+  double* nbpart;
+  int32_t* nbtab;
+  int64_t cap_nbpart, cap_nbtab;
 };
 
 // ---------------------------------------------------------------------------
@@ -233,11 +252,17 @@ __device__ __forceinline__ void column_ranges(const Grid& g, int c2, int& za0, i
 
 // The stencil of cell c as a fixed sequence of chunks of contiguous sorted
 // atoms: chunk q (0 <= q < stencil_chunks) is column (a, b) = ((q/2) / span1,
-// (q/2) % span1) of the (x, y) stencil, its unwrapped z range for even q and
-// its wrapped z range for odd q.  A chunk is empty when its column lies
+// (q/2) % span1) of the (x, y) stencil; within a column the z range at
+// negative offsets comes first: the wrapped range, then the unwrapped one,
+// when the column wraps below the cell (c2 < reach), otherwise the unwrapped
+// range, then the wrapped one.  A chunk is empty when its column lies
 // outside a non-periodic grid or has no wrapped part.  (sx, sy, sz) is the
 // chunk's image shift.  Far-list entries number a neighbour by its position
-// in this sequence, so the order is part of the list format.
+// in this sequence, so the order is part of the list format.  When no
+// dimension is covered whole, the sequence runs through the stencil in
+// increasing (x, y, z) offset order except inside z ranges, so a neighbour
+// at a lexicographically positive offset, or in the centre's own cell after
+// it, has a larger slot than the centre itself.
 __host__ __device__ __forceinline__ int stencil_chunks(const Grid& g) { return 2 * g.span[0] * g.span[1]; }
 
 __device__ __forceinline__ void stencil_chunk(const Grid& g, const int32_t* __restrict__ cstart, int c, int q,
@@ -259,7 +284,8 @@ __device__ __forceinline__ void stencil_chunk(const Grid& g, const int32_t* __re
   int za0, za1, zb0, zb1;
   column_ranges(g, c2, za0, za1, zb0, zb1);
   const int row = (x * g.nc[1] + y) * g.nc[2];
-  if ((q & 1) == 0) {
+  const bool wrap_first = zb1 > zb0 && c2 - g.reach < 0;
+  if (((q & 1) == 0) != wrap_first) {
     s0 = cstart[row + za0];
     s1 = cstart[row + za1];
   } else if (zb1 > zb0) {

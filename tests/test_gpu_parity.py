@@ -3,6 +3,7 @@
 Every test calls the HIP library through its C ABI (ctypes binding) and the
 oracle through its own library; the two share no code.
 """
+import ctypes
 import math
 
 import numpy as np
@@ -42,6 +43,57 @@ def _parity(ff, params, system, cutoffs=None):
     assert_energy_parity(e, e_ref, e_abs, names=TERM_NAMES)
     assert_force_parity(f, f_ref)
     return e, f, nborder
+
+
+def _launches(ff):
+    """Kernel launch counts since profiling was switched on (name -> launches)."""
+    K = 32
+    ms = (ctypes.c_double * K)()
+    calls = (ctypes.c_int64 * K)()
+    names = (ctypes.c_char_p * K)()
+    k = ff._lib.reaxff_profile_read(ff._h, K, ms, calls, names)
+    return {names[i].decode(): int(calls[i]) for i in range(k)}
+
+
+def _parity_path(ff, params, system, half):
+    """Parity, and that the nonbonded term took the expected path: the half
+    evaluation (pairs once, partial arrays summed per atom) needs at least
+    2 reach + 1 cells per edge; smaller grids evaluate every pair from both
+    atoms."""
+    ff._lib.reaxff_profile(ff._h, 1)
+    try:
+        out = _parity(ff, params, system)
+        used = _launches(ff)
+    finally:
+        ff._lib.reaxff_profile(ff._h, 0)
+    print("nonbonded launches", used.get("nonbonded", 0), "reduce", used.get("nb_reduce", 0), flush=True)
+    assert used.get("nonbonded", 0) > 0
+    assert (used.get("nb_reduce", 0) > 0) == half
+    return out
+
+
+def test_half_nonbonded_periodic_shifted(ff, params):
+    """6,264 atoms in a 40.05 A periodic box: 8 cells per edge, image shifts per
+    stencil column, every pair evaluated once."""
+    _parity_path(ff, params, rs.petn_lattice(216, 40.05, seed=11), half=True)
+
+
+def test_half_nonbonded_open_cluster(ff, params):
+    """A 3,000-atom open cluster (about 31 A across, 6 cells per edge): half
+    evaluation with stencils clipped at the grid faces."""
+    _parity_path(ff, params, rs.cluster(3000, seed=5), half=True)
+
+
+def test_half_nonbonded_wrapping_both_sides(ff, params):
+    """The 1,856-atom box has 5 cells per edge: every stencil column wraps,
+    below the cell for some cells and above it for others."""
+    _parity_path(ff, params, rs.petn_lattice(64, 26.7, seed=0), half=True)
+
+
+def test_full_nonbonded_small_grid(ff, params):
+    """870 atoms in a 20.7 A box (4 cells per edge): the stencil covers every
+    cell, so pairs are evaluated from both atoms."""
+    _parity_path(ff, params, rs.petn_lattice(30, 20.7, seed=4), half=False)
 
 
 def test_petn_1856_parity(ff, params):
