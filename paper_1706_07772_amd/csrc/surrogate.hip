@@ -643,7 +643,6 @@ static_assert(MCH == 4, "pair records pack exactly four members");
 __global__ __launch_bounds__(256) void k_sur_pairw(ForceArgs a) {
   __shared__ float sg[4][MCH][4][GAM];
   __shared__ float smm[4][4][NM];
-  __shared__ float sgg[4][ND];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * 4 + wv;
   if (i >= a.n) return;                       // wave-uniform; no block barriers below
@@ -656,47 +655,41 @@ __global__ __launch_bounds__(256) void k_sur_pairw(ForceArgs a) {
   const int row = a.rowof[i];
   for (int m0 = 0; m0 < a.members; m0 += MCH) {
     const int mc = a.members - m0 < MCH ? a.members - m0 : MCH;
-    // every member's dE/dG of atom i, loaded at once (4 values per lane each)
-    constexpr int GPL = (ND + 63) / 64;
-    float gl[MCH][GPL];
+    // adjoints of each member of the chunk: lane l takes member half l / 32
+    // of a member pair, neighbour element b = (l / 8) mod 4 and angular
+    // channel n = l mod 8, and forms all nine (M1, M2) components of that
+    // (b, n) from dE/dG read straight from memory; the radial part is a copy.
+    const int hb = (lane >> 3) & 3, hn = lane & 7;
 #pragma unroll
     for (int mm = 0; mm < MCH; ++mm)
-#pragma unroll
-      for (int t = 0; t < GPL; ++t) {
-        const int k = lane + 64 * t;
-        gl[mm][t] = (mm < mc && k < ND) ? a.gG[((int64_t)(m0 + mm) * a.rows + row) * ND + k] : 0.f;
+      if (mm < mc) {
+        const float* __restrict__ g = a.gG + ((int64_t)(m0 + mm) * a.rows + row) * ND;
+        sg[wv][mm][lane / NR][lane % NR] = g[lane];     // 4 NR = 64 radial values
       }
-    for (int mm = 0; mm < mc; ++mm) {
-      // this member's adjoints in three uniform passes: radial copies, M1
-      // contractions, M2 contractions
 #pragma unroll
-      for (int t = 0; t < GPL; ++t) {
-        const int k = lane + 64 * t;
-        if (k < ND) sgg[wv][k] = gl[mm][t];
-      }
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      const float* __restrict__ g = sgg[wv];
-      for (int k = lane; k < 4 * NR; k += 64) sg[wv][mm][k / NR][k % NR] = g[k];
-      for (int k = lane; k < 4 * NA * 3; k += 64) {
-        const int b = k / (NA * 3), o = k % (NA * 3), nn = o / 3, comp = o % 3;
-        float v = 0.f;
+    for (int mp = 0; mp < MCH; mp += 2) {
+      const int mm = mp + (lane >> 5);
+      if (mm < mc) {
+        const float* __restrict__ g = a.gG + ((int64_t)(m0 + mm) * a.rows + row) * ND;
+        float g1[3] = {0.f, 0.f, 0.f}, g2[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-          v += (c == b ? 2.0f : 1.0f) * g[4 * NR + pidx(b, c) * 16 + nn] * smm[wv][c][nn * 3 + comp];
-        sg[wv][mm][b][NR + o] = v;
-      }
-      for (int k = lane; k < 4 * NA * 6; k += 64) {
-        const int b = k / (NA * 6), o = k % (NA * 6), nn = o / 6, comp = o % 6;
-        float v = 0.f;
+        for (int c = 0; c < 4; ++c) {
+          const float w = c == hb ? 2.0f : 1.0f;
+          const float a1 = w * g[4 * NR + pidx(hb, c) * 16 + hn];
+          const float a2 = w * g[4 * NR + pidx(hb, c) * 16 + 8 + hn];
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-          v += (c == b ? 2.0f : 1.0f) * g[4 * NR + pidx(b, c) * 16 + 8 + nn] * smm[wv][c][24 + nn * 6 + comp];
-        sg[wv][mm][b][NR + NA * 3 + o] = v;
+          for (int comp = 0; comp < 3; ++comp) g1[comp] += a1 * smm[wv][c][hn * 3 + comp];
+#pragma unroll
+          for (int comp = 0; comp < 6; ++comp) g2[comp] += a2 * smm[wv][c][24 + hn * 6 + comp];
+        }
+#pragma unroll
+        for (int comp = 0; comp < 3; ++comp) sg[wv][mm][hb][NR + hn * 3 + comp] = g1[comp];
+#pragma unroll
+        for (int comp = 0; comp < 6; ++comp) sg[wv][mm][hb][NR + NA * 3 + hn * 6 + comp] = g2[comp];
       }
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     float fo[MCH][3];
 #pragma unroll
     for (int mm = 0; mm < MCH; ++mm) fo[mm][0] = fo[mm][1] = fo[mm][2] = 0.f;
