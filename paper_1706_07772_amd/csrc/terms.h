@@ -9,6 +9,103 @@
 
 namespace rx {
 
+// ---------------------------------------------------------------------------
+// FP64 elementary functions written for the arguments of the force terms
+// (exp_f, log_f for finite positive x; exp_c and pow_c for any argument):
+//   exp_f:   Cody-Waite reduction x = k ln2 + r, |r| <= ln2/2, with ln 2
+//            split into a head of 29 significant bits (k * head exact for
+//            |k| < 2^24) and a tail; exp(r) from its Taylor series to degree
+//            13 (truncation below 1e-17 relative), scaled by 2^k.
+//   log_f:   x = 2^e m with m in [1/sqrt2, sqrt2); log m = 2 atanh(s) with
+//            s = (m - 1)/(m + 1), |s| < 0.172, odd series to s^19
+//            (truncation below 1e-17).
+//   rcbrt_f: x^(-1/3) from a single-precision seed 2^(-log2(x)/3) and two
+//            Newton steps y <- y (4 - x y^3) / 3, each squaring the relative
+//            error (about 1e-7, then 1e-14, then rounding level).
+//   rcp_f:   1/x from the hardware reciprocal estimate and two Newton steps
+//            y <- y (2 - x y).
+//   exp_c:   exp_f after clamping the argument to [-1000, 1000] (exp is 0 or
+//            infinity beyond; the reduction then stays exact); NaN passes.
+//   pow_c:   x^y = exp_c(y log x) for x > 0, with 0^y spelled out.
+// Each is within a few units in the last place, far inside the 1e-9
+// relative agreement asked of energies and forces.
+// ---------------------------------------------------------------------------
+constexpr double LN2_HEAD = 0x1.62e42ff000000p-1;
+constexpr double LN2_TAIL = -0x1.718432a1b0e26p-35;
+constexpr double LOG2_E = 1.4426950408889634;
+
+__device__ __forceinline__ double exp_f(double x) {
+  const double k = rint(x * LOG2_E);
+  double r = fma(-k, LN2_HEAD, x);
+  r = fma(-k, LN2_TAIL, r);
+  double p = 1.0 / 6227020800.0;
+  p = fma(p, r, 1.0 / 479001600.0);
+  p = fma(p, r, 1.0 / 39916800.0);
+  p = fma(p, r, 1.0 / 3628800.0);
+  p = fma(p, r, 1.0 / 362880.0);
+  p = fma(p, r, 1.0 / 40320.0);
+  p = fma(p, r, 1.0 / 5040.0);
+  p = fma(p, r, 1.0 / 720.0);
+  p = fma(p, r, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return ldexp(p, (int)k);
+}
+
+__device__ __forceinline__ double rcp_f(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = y * fma(-x, y, 2.0);
+  y = y * fma(-x, y, 2.0);
+  return y;
+}
+
+__device__ __forceinline__ double log_f(double x) {
+  int e;
+  double m = frexp(x, &e);
+  if (m < 0.7071067811865476) {
+    m *= 2.0;
+    e -= 1;
+  }
+  const double f = m - 1.0;
+  const double s = f * rcp_f(2.0 + f);
+  const double z = s * s;
+  double p = 1.0 / 19.0;
+  p = fma(p, z, 1.0 / 17.0);
+  p = fma(p, z, 1.0 / 15.0);
+  p = fma(p, z, 1.0 / 13.0);
+  p = fma(p, z, 1.0 / 11.0);
+  p = fma(p, z, 1.0 / 9.0);
+  p = fma(p, z, 1.0 / 7.0);
+  p = fma(p, z, 1.0 / 5.0);
+  p = fma(p, z, 1.0 / 3.0);
+  const double lm = fma(2.0 * s * z, p, 2.0 * s);
+  const double de = (double)e;
+  return fma(de, LN2_HEAD, fma(de, LN2_TAIL, lm));
+}
+
+__device__ __forceinline__ double rcbrt_f(double x) {
+  const float xf = (float)x;
+  double y = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf(xf) * (-1.0f / 3.0f));
+  y = y * fma(-x, y * y * y, 4.0) * (1.0 / 3.0);
+  y = y * fma(-x, y * y * y, 4.0) * (1.0 / 3.0);
+  return y;
+}
+
+__device__ __forceinline__ double exp_c(double x) {
+  x = x < -1000.0 ? -1000.0 : (x > 1000.0 ? 1000.0 : x);
+  return exp_f(x);
+}
+
+__device__ __forceinline__ double pow_c(double x, double y) {
+  if (x > 0.0) return exp_c(y * log_f(x));
+  if (x == 0.0) return y > 0.0 ? 0.0 : (y == 0.0 ? 1.0 : __builtin_inf());
+  return __builtin_nan("");
+}
+
+
 __device__ __forceinline__ void atomic_add3(double4* p, double x, double y, double z) {
   double* d = reinterpret_cast<double*>(p);
   atomicAdd(d + 0, x);
@@ -30,9 +127,9 @@ __device__ __forceinline__ void atomic_add3(double4* p, double3 v) { atomic_add3
 // raw uncorrected bond order sum of sigma, pi and pi-pi (the bond-list test)
 __device__ __forceinline__ double bo_raw(const PairP& p, double r, double bo_cut) {
   double s = 0.0, pi = 0.0, pp = 0.0;
-  if (p.r_s > 0.0) s = (1.0 + bo_cut) * exp(p.p_bo1 * pow(r / p.r_s, p.p_bo2));
-  if (p.r_p > 0.0) pi = exp(p.p_bo3 * pow(r / p.r_p, p.p_bo4));
-  if (p.r_pp > 0.0) pp = exp(p.p_bo5 * pow(r / p.r_pp, p.p_bo6));
+  if (p.r_s > 0.0) s = (1.0 + bo_cut) * exp_c(p.p_bo1 * pow_c(r / p.r_s, p.p_bo2));
+  if (p.r_p > 0.0) pi = exp_c(p.p_bo3 * pow_c(r / p.r_p, p.p_bo4));
+  if (p.r_pp > 0.0) pp = exp_c(p.p_bo5 * pow_c(r / p.r_pp, p.p_bo6));
   return s + pi + pp;
 }
 
@@ -65,18 +162,18 @@ __device__ __forceinline__ void bo_prime_atom(const DevParams* __restrict__ P, c
     double s = 0.0, ds = 0.0, pi = 0.0, dpi = 0.0, pp = 0.0, dpp = 0.0;
     const double ir = 1.0 / r;
     if (p.r_s > 0.0) {
-      const double x = pow(r / p.r_s, p.p_bo2);
-      s = (1.0 + bo_cut) * exp(p.p_bo1 * x);
+      const double x = pow_c(r / p.r_s, p.p_bo2);
+      s = (1.0 + bo_cut) * exp_c(p.p_bo1 * x);
       ds = s * p.p_bo1 * p.p_bo2 * x * ir;
     }
     if (p.r_p > 0.0) {
-      const double x = pow(r / p.r_p, p.p_bo4);
-      pi = exp(p.p_bo3 * x);
+      const double x = pow_c(r / p.r_p, p.p_bo4);
+      pi = exp_c(p.p_bo3 * x);
       dpi = pi * p.p_bo3 * p.p_bo4 * x * ir;
     }
     if (p.r_pp > 0.0) {
-      const double x = pow(r / p.r_pp, p.p_bo6);
-      pp = exp(p.p_bo5 * x);
+      const double x = pow_c(r / p.r_pp, p.p_bo6);
+      pp = exp_c(p.p_bo5 * x);
       dpp = pp * p.p_bo5 * p.p_bo6 * x * ir;
     }
     const double raw = s + pi + pp;
@@ -105,11 +202,11 @@ struct Corr {
 __device__ __forceinline__ Corr correction(const DevParams* __restrict__ P, double bop, double va,
                                            double vb, double2 da, double2 db, const PairP& p) {
   Corr c;
-  const double ea1 = exp(-P->p_boc1 * da.x), eb1 = exp(-P->p_boc1 * db.x);
-  const double ea2 = exp(-P->p_boc2 * da.x), eb2 = exp(-P->p_boc2 * db.x);
+  const double ea1 = exp_c(-P->p_boc1 * da.x), eb1 = exp_c(-P->p_boc1 * db.x);
+  const double ea2 = exp_c(-P->p_boc2 * da.x), eb2 = exp_c(-P->p_boc2 * db.x);
   const double f2 = ea1 + eb1;
   const double u = 0.5 * (ea2 + eb2);
-  const double f3 = -(1.0 / P->p_boc2) * log(u);
+  const double f3 = -(1.0 / P->p_boc2) * log_f(u);
   const double A = va + f2, Ad = va + f2 + f3;
   const double B = vb + f2, Bd = vb + f2 + f3;
   c.f1 = 0.5 * (A / Ad + B / Bd);
@@ -119,8 +216,8 @@ __device__ __forceinline__ Corr correction(const DevParams* __restrict__ P, doub
   c.df1_da = df1_df2 * (-P->p_boc1 * ea1) + df1_df3 * (ea2 * w2);
   c.df1_db = df1_df2 * (-P->p_boc1 * eb1) + df1_df3 * (eb2 * w2);
   const double bo2 = bop * bop;
-  const double e4 = exp(-p.p_boc3 * (p.p_boc4 * bo2 - da.y) + p.p_boc5);
-  const double e5 = exp(-p.p_boc3 * (p.p_boc4 * bo2 - db.y) + p.p_boc5);
+  const double e4 = exp_c(-p.p_boc3 * (p.p_boc4 * bo2 - da.y) + p.p_boc5);
+  const double e5 = exp_c(-p.p_boc3 * (p.p_boc4 * bo2 - db.y) + p.p_boc5);
   c.f4 = 1.0 / (1.0 + e4);
   c.f5 = 1.0 / (1.0 + e5);
   const double s4 = c.f4 * (1.0 - c.f4), s5 = c.f5 * (1.0 - c.f5);
@@ -170,11 +267,11 @@ __device__ __forceinline__ void atom_state_atom(const DevParams* __restrict__ P,
   const double De = S - a.val_e;
   const double tr = trunc(De * 0.5);
   const double vlpex = De - 2.0 * tr;
-  const double enlp = exp(-P->p_lp1 * sqr(2.0 + vlpex));
+  const double enlp = exp_c(-P->p_lp1 * sqr(2.0 + vlpex));
   const double nlp = enlp - tr;
   st.Dlp = a.nlp_opt - nlp;
   st.dnlp = enlp * (-2.0 * P->p_lp1 * (2.0 + vlpex));
-  st.prod = exp(-sum8);
+  st.prod = exp_c(-sum8);
   const bool neg = vlpex < 0.0;
   st.W = -st.Dang - P->p_val8 * (neg ? nlp : 0.0);
   st.dW = -1.0 - P->p_val8 * (neg ? st.dnlp : 0.0);
@@ -183,24 +280,24 @@ __device__ __forceinline__ void atom_state_atom(const DevParams* __restrict__ P,
   if (SBO <= 0.0) {
     st.SBO2 = 0.0; st.dSBO2 = 0.0;
   } else if (SBO <= 1.0) {
-    const double t = pow(SBO, p9);
+    const double t = pow_c(SBO, p9);
     st.SBO2 = t; st.dSBO2 = p9 * t / SBO;
   } else if (SBO < 2.0) {
-    const double t = pow(2.0 - SBO, p9);
+    const double t = pow_c(2.0 - SBO, p9);
     st.SBO2 = 2.0 - t; st.dSBO2 = p9 * t / (2.0 - SBO);
   } else {
     st.SBO2 = 2.0; st.dSBO2 = 0.0;
   }
   // centre factors of the valence-angle family
-  const double ex10 = exp(-P->p_val10 * (2.0 - st.SBO2));
+  const double ex10 = exp_c(-P->p_val10 * (2.0 - st.SBO2));
   st.th0f = 1.0 - ex10;
   st.dth0f = -ex10 * P->p_val10;                 // d th0f / d SBO2
-  st.e6 = exp(P->p_val6 * st.Dang);
-  const double ep3 = exp(-P->p_pen3 * st.Delta), ep4 = exp(P->p_pen4 * st.Delta);
+  st.e6 = exp_c(P->p_val6 * st.Dang);
+  const double ep3 = exp_c(-P->p_pen3 * st.Delta), ep4 = exp_c(P->p_pen4 * st.Delta);
   const double f9d = 1.0 + ep3 + ep4;
   st.f9 = (2.0 + ep3) / f9d;
   st.df9 = (-P->p_pen3 * ep3 * f9d - (2.0 + ep3) * (-P->p_pen3 * ep3 + P->p_pen4 * ep4)) / (f9d * f9d);
-  const double ec = exp(P->p_coa2 * st.Dang);
+  const double ec = exp_c(P->p_coa2 * st.Dang);
   st.fc = 1.0 / (1.0 + ec);
   st.dfc = -P->p_coa2 * ec * st.fc * st.fc;
   W.ast[i] = st;
@@ -225,8 +322,8 @@ __device__ __forceinline__ void atom_energy_atom(const DevParams* __restrict__ P
     sumov += p.p_ovun1 * p.D_s * b.x;
     if (i < j) {
       const double sig = b.w;
-      const double pw = sig > 0.0 ? pow(sig, p.p_be2) : 0.0;
-      const double ex = exp(p.p_be1 * (1.0 - pw));
+      const double pw = sig > 0.0 ? pow_c(sig, p.p_be2) : 0.0;
+      const double ex = exp_c(p.p_be1 * (1.0 - pw));
       ebond += -p.D_s * sig * ex - p.D_p * b.y - p.D_pp * b.z;
       const double dsig = -p.D_s * ex * (1.0 - p.p_be1 * p.p_be2 * pw);
       double4 gb = W.gbo[e];
@@ -237,24 +334,24 @@ __device__ __forceinline__ void atom_energy_atom(const DevParams* __restrict__ P
     }
   }
   // lone pair
-  const double e75 = exp(-75.0 * st.Dlp);
+  const double e75 = exp_c(-75.0 * st.Dlp);
   const double den75 = 1.0 / (1.0 + e75);
   const double elp = a.p_lp2 * st.Dlp * den75;
   const double dElp_dDlp = a.p_lp2 * (den75 + st.Dlp * 75.0 * e75 * den75 * den75);
   // over / under
-  const double ep4 = exp(P->p_ovun4 * sumpi);
+  const double ep4 = exp_c(P->p_ovun4 * sumpi);
   const double DD = 1.0 + P->p_ovun3 * ep4;
   const double Dlpc = st.Delta - st.Dlp / DD;
   const double Vp = a.val + 1e-8;
   const double R = Dlpc / (Dlpc + Vp);
   const double dR = Vp / sqr(Dlpc + Vp);
-  const double so = 1.0 / (1.0 + exp(a.p_ovun2 * Dlpc));
+  const double so = 1.0 / (1.0 + exp_c(a.p_ovun2 * Dlpc));
   const double dso = -a.p_ovun2 * so * (1.0 - so);
   const double eover = sumov * R * so;
-  const double e6 = exp(P->p_ovun6 * Dlpc);
-  const double su = 1.0 / (1.0 + exp(-a.p_ovun2 * Dlpc));
+  const double e6 = exp_c(P->p_ovun6 * Dlpc);
+  const double su = 1.0 / (1.0 + exp_c(-a.p_ovun2 * Dlpc));
   const double dsu = a.p_ovun2 * su * (1.0 - su);
-  const double ep8 = exp(P->p_ovun8 * sumpi);
+  const double ep8 = exp_c(P->p_ovun8 * sumpi);
   const double t8 = 1.0 / (1.0 + P->p_ovun7 * ep8);
   const double eunder = -a.p_ovun5 * (1.0 - e6) * su * t8;
   const double gL = sumov * (dR * so + R * dso) +
@@ -313,21 +410,21 @@ __device__ __forceinline__ AngOut angle_eval(const DevParams* __restrict__ P, co
   const double th0 = PI - ap.theta00_rad * st.th0f;
   const double dth0 = -ap.theta00_rad * st.dth0f;     // d th0 / d SBO2
   // f7
-  const double x1 = pow(B1, ap.p_val4), x2 = pow(B2, ap.p_val4);
-  const double g1 = exp(-aj.p_val3 * x1), g2 = exp(-aj.p_val3 * x2);
+  const double x1 = pow_c(B1, ap.p_val4), x2 = pow_c(B2, ap.p_val4);
+  const double g1 = exp_c(-aj.p_val3 * x1), g2 = exp_c(-aj.p_val3 * x2);
   const double f7a = 1.0 - g1, f7b = 1.0 - g2;
   const double df7a = aj.p_val3 * ap.p_val4 * x1 / B1 * g1;
   const double df7b = aj.p_val3 * ap.p_val4 * x2 / B2 * g2;
   // f8
   const double e6 = st.e6;
-  const double e7 = exp(-ap.p_val7 * st.Dang);
+  const double e7 = exp_c(-ap.p_val7 * st.Dang);
   const double f8d = 1.0 + e6 + e7;
   const double f8 = aj.p_val5 - (aj.p_val5 - 1.0) * (2.0 + e6) / f8d;
   const double df8 = -(aj.p_val5 - 1.0) *
                      (P->p_val6 * e6 * f8d - (2.0 + e6) * (P->p_val6 * e6 - ap.p_val7 * e7)) /
                      (f8d * f8d);
   const double dt = th0 - th;
-  const double ev = exp(-ap.p_val2 * dt * dt);
+  const double ev = exp_c(-ap.p_val2 * dt * dt);
   const double Ea = f7a * f7b * f8 * ap.p_val1;
   const double Ev = Ea * (1.0 - ev);
   const double gdt = Ea * ev * 2.0 * ap.p_val2 * dt;   // dE/d(th0 - th)
@@ -336,14 +433,14 @@ __device__ __forceinline__ AngOut angle_eval(const DevParams* __restrict__ P, co
   double gS = f7a * f7b * df8 * ap.p_val1 * (1.0 - ev);      // via Dang
   o.gSBO2 = gdt * dth0;
   // penalty
-  const double pe1 = exp(-P->p_pen2 * sqr(B1 - 2.0)), pe2 = exp(-P->p_pen2 * sqr(B2 - 2.0));
+  const double pe1 = exp_c(-P->p_pen2 * sqr(B1 - 2.0)), pe2 = exp_c(-P->p_pen2 * sqr(B2 - 2.0));
   const double Ep = ap.p_pen1 * st.f9 * pe1 * pe2;
   gB1 += Ep * (-2.0 * P->p_pen2 * (B1 - 2.0));
   gB2 += Ep * (-2.0 * P->p_pen2 * (B2 - 2.0));
   gS += ap.p_pen1 * st.df9 * pe1 * pe2;                       // via Delta
   // coalition
-  const double ci = exp(-P->p_coa3 * sqr(Si - B1)), ck = exp(-P->p_coa3 * sqr(Sk - B2));
-  const double cb1 = exp(-P->p_coa4 * sqr(B1 - 1.5)), cb2 = exp(-P->p_coa4 * sqr(B2 - 1.5));
+  const double ci = exp_c(-P->p_coa3 * sqr(Si - B1)), ck = exp_c(-P->p_coa3 * sqr(Sk - B2));
+  const double cb1 = exp_c(-P->p_coa4 * sqr(B1 - 1.5)), cb2 = exp_c(-P->p_coa4 * sqr(B2 - 1.5));
   const double Ec = ap.p_coa1 * st.fc * ci * ck * cb1 * cb2;
   gS += ap.p_coa1 * st.dfc * ci * ck * cb1 * cb2;            // via Dang
   const double gSi = Ec * (-2.0 * P->p_coa3 * (Si - B1));
@@ -385,17 +482,17 @@ __device__ __forceinline__ void torsion_eval(const DevParams* __restrict__ P, co
   const double bij = W.bo[eji].x, bkl = W.bo[ekl].x;
   // f11 of the central bond
   const double Dsum = W.ast[j].Dang + W.ast[k].Dang;
-  const double et3 = exp(-P->p_tor3 * Dsum), et4 = exp(P->p_tor4 * Dsum);
+  const double et3 = exp_c(-P->p_tor3 * Dsum), et4 = exp_c(P->p_tor4 * Dsum);
   const double f11d = 1.0 + et3 + et4;
   const double f11 = (2.0 + et3) / f11d;
   const double df11 = (-P->p_tor3 * et3 * f11d - (2.0 + et3) * (-P->p_tor3 * et3 + P->p_tor4 * et4)) /
                       (f11d * f11d);
   const double Bij = bij - thb, Bjk = bjk.x - thb, Bkl = bkl - thb;
-  const double xij = exp(-pt2 * Bij), xjk = exp(-pt2 * Bjk), xkl = exp(-pt2 * Bkl);
+  const double xij = exp_c(-pt2 * Bij), xjk = exp_c(-pt2 * Bjk), xkl = exp_c(-pt2 * Bkl);
   const double hij = 1.0 - xij, hjk = 1.0 - xjk, hkl = 1.0 - xkl;
   const double dhij = pt2 * xij, dhjk = pt2 * xjk, dhkl = pt2 * xkl;
-  const double cij = exp(-pc2 * sqr(Bij - 1.5)), cjk = exp(-pc2 * sqr(Bjk - 1.5)),
-               ckl = exp(-pc2 * sqr(Bkl - 1.5));
+  const double cij = exp_c(-pc2 * sqr(Bij - 1.5)), cjk = exp_c(-pc2 * sqr(Bjk - 1.5)),
+               ckl = exp_c(-pc2 * sqr(Bkl - 1.5));
   const double pi2 = 2.0 - bjk.y - f11;
   // geometry: b1 = x_j - x_i = -r_ji, b2 = x_k - x_j, b3 = x_l - x_k
   const double4 r1v = W.bd[eji], r2v = W.bd[ejk], r3v = W.bd[ekl];
@@ -409,7 +506,7 @@ __device__ __forceinline__ void torsion_eval(const DevParams* __restrict__ P, co
   const double cw = dot(m, nv) / (nm * nn);
   const double ss = s1 * s2;
   const double f10 = hij * hjk * hkl;
-  const double exv = exp(tp.p_tor1 * pi2 * pi2);
+  const double exv = exp_c(tp.p_tor1 * pi2 * pi2);
   const double c2w = 2.0 * cw * cw - 1.0;
   const double c3w = 4.0 * cw * cw * cw - 3.0 * cw;
   const double Vt = 0.5 * (tp.V1 * (1.0 + cw) + tp.V2 * exv * (1.0 - c2w) + tp.V3 * (1.0 + c3w));
@@ -478,9 +575,9 @@ __device__ __forceinline__ HbTerm hb_term(const HbP& hp, double bo, double4 rx, 
   const double hc = 0.5 * (1.0 - c);
   const double s4 = hc * hc;
   const double ds4 = -hc;                 // d s4 / d c
-  const double eb = exp(-hp.p_hb2 * bo);
+  const double eb = exp_c(-hp.p_hb2 * bo);
   const double fbo = 1.0 - eb, dfbo = hp.p_hb2 * eb;
-  const double fr = exp(-hp.p_hb3 * (hp.r0hb * ilz + rz / hp.r0hb - 2.0));
+  const double fr = exp_c(-hp.p_hb3 * (hp.r0hb * ilz + rz / hp.r0hb - 2.0));
   const double dfr = fr * (-hp.p_hb3) * (-hp.r0hb * ilz * ilz + 1.0 / hp.r0hb);
   o.E = hp.p_hb1 * fbo * fr * s4;
   o.dE_dbo = hp.p_hb1 * dfbo * fr * s4;
@@ -494,88 +591,6 @@ __device__ __forceinline__ HbTerm hb_term(const HbP& hp, double bo, double4 rx, 
   return o;
 }
 
-// ---------------------------------------------------------------------------
-// FP64 elementary functions for the pair term, for the finite positive
-// arguments it produces (no NaN, infinity or subnormal handling; an argument
-// outside the double range still ends in 0 or infinity through ldexp):
-//   exp_f:   Cody-Waite reduction x = k ln2 + r, |r| <= ln2/2, with ln 2
-//            split into a head of 29 significant bits (k * head exact for
-//            |k| < 2^24) and a tail; exp(r) from its Taylor series to degree
-//            13 (truncation below 1e-17 relative), scaled by 2^k.
-//   log_f:   x = 2^e m with m in [1/sqrt2, sqrt2); log m = 2 atanh(s) with
-//            s = (m - 1)/(m + 1), |s| < 0.172, odd series to s^19
-//            (truncation below 1e-17).
-//   rcbrt_f: x^(-1/3) from a single-precision seed 2^(-log2(x)/3) and two
-//            Newton steps y <- y (4 - x y^3) / 3, each squaring the relative
-//            error (about 1e-7, then 1e-14, then rounding level).
-//   rcp_f:   1/x from the hardware reciprocal estimate and two Newton steps
-//            y <- y (2 - x y).
-// Each is within a few units in the last place, far inside the 1e-9
-// relative agreement asked of energies and forces.
-// ---------------------------------------------------------------------------
-constexpr double LN2_HEAD = 0x1.62e42ff000000p-1;
-constexpr double LN2_TAIL = -0x1.718432a1b0e26p-35;
-constexpr double LOG2_E = 1.4426950408889634;
-
-__device__ __forceinline__ double exp_f(double x) {
-  const double k = rint(x * LOG2_E);
-  double r = fma(-k, LN2_HEAD, x);
-  r = fma(-k, LN2_TAIL, r);
-  double p = 1.0 / 6227020800.0;
-  p = fma(p, r, 1.0 / 479001600.0);
-  p = fma(p, r, 1.0 / 39916800.0);
-  p = fma(p, r, 1.0 / 3628800.0);
-  p = fma(p, r, 1.0 / 362880.0);
-  p = fma(p, r, 1.0 / 40320.0);
-  p = fma(p, r, 1.0 / 5040.0);
-  p = fma(p, r, 1.0 / 720.0);
-  p = fma(p, r, 1.0 / 120.0);
-  p = fma(p, r, 1.0 / 24.0);
-  p = fma(p, r, 1.0 / 6.0);
-  p = fma(p, r, 0.5);
-  p = fma(p, r, 1.0);
-  p = fma(p, r, 1.0);
-  return ldexp(p, (int)k);
-}
-
-__device__ __forceinline__ double rcp_f(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  y = y * fma(-x, y, 2.0);
-  y = y * fma(-x, y, 2.0);
-  return y;
-}
-
-__device__ __forceinline__ double log_f(double x) {
-  int e;
-  double m = frexp(x, &e);
-  if (m < 0.7071067811865476) {
-    m *= 2.0;
-    e -= 1;
-  }
-  const double f = m - 1.0;
-  const double s = f * rcp_f(2.0 + f);
-  const double z = s * s;
-  double p = 1.0 / 19.0;
-  p = fma(p, z, 1.0 / 17.0);
-  p = fma(p, z, 1.0 / 15.0);
-  p = fma(p, z, 1.0 / 13.0);
-  p = fma(p, z, 1.0 / 11.0);
-  p = fma(p, z, 1.0 / 9.0);
-  p = fma(p, z, 1.0 / 7.0);
-  p = fma(p, z, 1.0 / 5.0);
-  p = fma(p, z, 1.0 / 3.0);
-  const double lm = fma(2.0 * s * z, p, 2.0 * s);
-  const double de = (double)e;
-  return fma(de, LN2_HEAD, fma(de, LN2_TAIL, lm));
-}
-
-__device__ __forceinline__ double rcbrt_f(double x) {
-  const float xf = (float)x;
-  double y = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf(xf) * (-1.0f / 3.0f));
-  y = y * fma(-x, y * y * y, 4.0) * (1.0 / 3.0);
-  y = y * fma(-x, y * y * y, 4.0) * (1.0 / 3.0);
-  return y;
-}
 
 // ---------------------------------------------------------------------------
 // (9) one van der Waals + Coulomb pair at squared distance r2: tapered
