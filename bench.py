@@ -251,6 +251,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="petn_1044000")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="run the nonbonded and bonded terms in order in the throughput pass too")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without per-kernel events (value only)")
     ap.add_argument("--no-batched", action="store_true",
@@ -299,6 +301,7 @@ def main():
         ff.build_lists(pos, typ, box)
         ff.compute_forces(pos, typ, q, box, forces, energies)
 
+    ff.set_overlap(not args.no_overlap)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -306,9 +309,8 @@ def main():
 
     lib = load_library()
     import ctypes
-    if not args.no_profile:
-        lib.reaxff_profile.argtypes = [ctypes.c_void_p, ctypes.c_int32]
-        lib.reaxff_profile(ff._h, 1)
+    # throughput pass: the steps as a user runs them (nonbonded term concurrent
+    # with the bonded terms unless --no-overlap), no per-kernel events
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -322,7 +324,23 @@ def main():
 
     counts = ff.interaction_counts()
     kernels = {}
+    kernel_pass_ms = None
     if not args.no_profile:
+        # kernel pass: the same number of steps with every kernel in order on
+        # one stream, each bracketed by HIP events on that stream, so each
+        # kernel's time is its own (under overlap a kernel's interval would
+        # include the concurrent terms' share of the chip)
+        ff.set_overlap(False)
+        lib.reaxff_profile.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+        lib.reaxff_profile(ff._h, 1)
+        torch.cuda.synchronize()
+        tk0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        kernel_pass_ms = 1e3 * (time.perf_counter() - tk0) / args.steps
+        ff.set_overlap(not args.no_overlap)
+        print(f"bench: kernel pass {kernel_pass_ms:.3f} ms/step (terms in order)", file=sys.stderr, flush=True)
         K = 32
         ms = (ctypes.c_double * K)()
         calls = (ctypes.c_int64 * K)()
@@ -356,7 +374,8 @@ def main():
                             "frac": achieved / PEAK_FP64_VALU_TFLOPS,
                             "traffic": TRAFFIC.get(dom),
                             "units_per_launch": units, "unit_name": unit,
-                            "flops_per_unit": per, "avg_ms": kernels[dom]["ms_avg"]}
+                            "flops_per_unit": per, "avg_ms": kernels[dom]["ms_avg"],
+                            "measured": "kernel pass: same steps, terms in order on one stream"}
                 # the whole nonbonded term: the pair kernel and, in the half
                 # evaluation, the per-atom sum of the cells' partial forces
                 extra = kernels.get("nb_reduce")
@@ -399,12 +418,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "atoms": n, "box_A": box[0],
                    "path": "plain FP64 ReaxFF: build_lists + compute_forces",
+                   "overlap": not args.no_overlap,
                    "cutoffs_A": {"nonbonded": 10.0, "bond": 5.0, "hbond": 7.5}, "bo_cut": 0.01},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched": batched,
         "surrogate": surrogate,
         "phases_ms": phases,
+        "kernel_pass_ms_per_step": kernel_pass_ms,
         "counts": counts,
         "kernels_ms_avg": {k: round(v["ms_avg"], 4) for k, v in kernels.items()},
     }

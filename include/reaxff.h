@@ -163,6 +163,17 @@ int reaxff_profile(reaxff_ctx* ctx, int32_t enable);
 int reaxff_profile_read(reaxff_ctx* ctx, int32_t max, double* ms, int64_t* launches,
                         const char** names);
 
+/* Concurrent terms [host]: with enable != 0 (the default) the nonbonded term
+ * of reaxff_compute_forces runs on a stream of the context's own,
+ * concurrently with the bonded terms, joined back to the caller's stream
+ * before the per-atom force gather (Section 3.2 schedules the paper's terms
+ * one after another; they are independent until forces are summed).  With
+ * enable == 0 every kernel runs on the caller's stream in order, so that
+ * per-kernel timings measure each kernel alone.  Results are the same up to
+ * the order of floating-point additions.  Returns REAXFF_OK or
+ * REAXFF_ERR_ARG for a null context. */
+int reaxff_set_overlap(reaxff_ctx* ctx, int32_t enable);
+
 /* ---- Batched evaluation of many small non-periodic systems ---------------
  *
  * Force-field fitting and cluster screening evaluate thousands of small,

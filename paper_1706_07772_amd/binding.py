@@ -106,6 +106,7 @@ def load_library():
     lib.reaxff_surrogate_gated_forces.argtypes = [vp, vp, i64, vp, vp, vp, vp, _d, vp, vp, vp,
                                                   ctypes.POINTER(i64), vp]
     lib.reaxff_profile.argtypes = [vp, i32]
+    lib.reaxff_set_overlap.argtypes = [vp, i32]
     lib.reaxff_profile_read.argtypes = [vp, i32, vp, vp, vp]
     lib.reaxff_last_error.restype = ctypes.c_char_p
     lib.reaxff_last_error.argtypes = [vp]
@@ -241,6 +242,10 @@ class ReaxFF:
         self._check(self._lib.reaxff_export_lists(self._h, far.ctypes.data, bonds.ctypes.data,
                                                   hb.ctypes.data))
         return far, bonds, hb
+
+    def set_overlap(self, enable: bool):
+        """Run the nonbonded term concurrently with the bonded terms (default) or in order."""
+        self._check(self._lib.reaxff_set_overlap(self._h, 1 if enable else 0))
 
     def interaction_counts(self):
         c = (ctypes.c_int64 * 5)()

@@ -159,7 +159,7 @@ int alloc_atoms(reaxff_ctx* c, int64_t n) {
   G(c->L.ha_cnt);
   G(c->sc.cid); G(c->sc.cell_s); G(c->sc.cnt_cand); G(c->sc.cnt_bond);
   G(c->W.dp); G(c->W.ast); G(c->W.gS); G(c->W.gSig); G(c->W.gSBO); G(c->W.gStot); G(c->W.gDp);
-  G(c->W.fnb); G(c->W.xq); G(c->W.cnt_ang); G(c->W.cnt_tor); G(c->W.cnt_don); G(c->W.off_ang);
+  G(c->W.fnb); G(c->W.fhb); G(c->W.xq); G(c->W.cnt_ang); G(c->W.cnt_tor); G(c->W.cnt_don); G(c->W.off_ang);
   G(c->W.off_tor); G(c->W.off_don);
 #undef G
   c->cap_n = cap;
@@ -225,7 +225,10 @@ int reaxff_create(const reaxff_params* params, const reaxff_cutoffs* cutoffs, in
       hipMalloc(&c->sc.totals, sizeof(int64_t) * 8) != hipSuccess ||
       hipMalloc(&c->sc.need, sizeof(int32_t) * 8) != hipSuccess ||
       hipHostMalloc(&c->sc.totals_host, sizeof(int64_t) * 8, hipHostMallocDefault) != hipSuccess ||
-      hipMalloc(&c->W.counters, sizeof(unsigned long long) * 4) != hipSuccess) {
+      hipMalloc(&c->W.counters, sizeof(unsigned long long) * 4) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
     reaxff_destroy(c);
     return REAXFF_ERR_HIP;
   }
@@ -241,7 +244,7 @@ void reaxff_destroy(reaxff_ctx* c) {
                   c->L.far_j, c->L.bond_off, c->L.bond_j, c->L.bond_mir, c->L.hb_cnt, c->L.hb_j,
                   c->L.ha_cnt, c->L.ha_j,
                   c->W.bd, c->W.bop, c->W.dbop, c->W.bo, c->W.gbo, c->W.gvec, c->W.gup, c->W.dp,
-                  c->W.ast, c->W.gS, c->W.gSig, c->W.gSBO, c->W.gStot, c->W.gDp, c->W.fnb,
+                  c->W.ast, c->W.gS, c->W.gSig, c->W.gSBO, c->W.gStot, c->W.gDp, c->W.fnb, c->W.fhb,
                   c->W.xq, c->W.counters, c->W.cnt_ang, c->W.cnt_tor, c->W.cnt_don,
                   c->W.off_ang, c->W.off_tor, c->W.off_don, c->W.ang, c->W.tor, c->W.don, c->W.donrec, c->L.far_lo, c->W.nbpart, c->W.nbtab,
                   c->L.bond_i, c->sc.cid, c->sc.cell_s, c->sc.cell_count,
@@ -251,6 +254,9 @@ void reaxff_destroy(reaxff_ctx* c) {
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->sc.totals_host) (void)hipHostFree(c->sc.totals_host);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  if (c->side) (void)hipStreamDestroy(c->side);
   delete c;
 }
 
@@ -444,7 +450,8 @@ int reaxff_compute_forces(reaxff_ctx* c, int64_t n, const double* pos, const int
     return fail(c, REAXFF_ERR_ARG, "null pointer");
   (void)pos; (void)type;   // the sorted copies made by the list build are used
   HIPCHK(c, hipSetDevice(c->device));
-  if (launch_forces(c->dp, c->grid, c->L, c->W, q, forces, energies, c->sc, c->prof, st))
+  if (launch_forces(c->dp, c->grid, c->L, c->W, q, c->overlap ? c->side : st, c->ev_fork, c->ev_join, forces,
+                    energies, c->sc, c->prof, st))
     return fail(c, REAXFF_ERR_HIP, "force launch failed");
   return REAXFF_OK;
 }
@@ -500,6 +507,12 @@ int reaxff_export_lists(reaxff_ctx* c, int32_t* far, int32_t* bonds, int32_t* hb
   if (df) (void)hipFree(df);
   if (db) (void)hipFree(db);
   if (dh) (void)hipFree(dh);
+  return REAXFF_OK;
+}
+
+int reaxff_set_overlap(reaxff_ctx* c, int32_t enable) {
+  if (!c) return REAXFF_ERR_ARG;
+  c->overlap = enable != 0;
   return REAXFF_OK;
 }
 

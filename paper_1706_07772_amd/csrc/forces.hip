@@ -303,7 +303,7 @@ __global__ __launch_bounds__(BS) void k_hbonds(const DevParams* __restrict__ P, 
     gv.z += gx.z;
     W.gvec[ex] = gv;
     W.gbo[ex].x += gbo;
-    atomic_add3(&W.fnb[h], fh);
+    atomic_add3(&W.fhb[h], fh);
   }
   block_add<BS>(ehb, energies + E_HB);
   for (int off = 32; off > 0; off >>= 1) nhb += __shfl_down(nhb, off, 64);
@@ -355,11 +355,11 @@ __global__ __launch_bounds__(BS) void k_hb_acceptors(const DevParams* __restrict
     fz.z += __shfl_down(fz.z, off, HB_GROUP);
   }
   if (sub == 0 && cnt > 0) {
-    double4 f = W.fnb[z];
+    double4 f = W.fhb[z];
     f.x += fz.x;
     f.y += fz.y;
     f.z += fz.z;
-    W.fnb[z] = f;
+    W.fhb[z] = f;
   }
 }
 
@@ -877,10 +877,11 @@ __global__ __launch_bounds__(BS) void k_forces(Lists L, Work W, double* __restri
   const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
   if (i >= L.n) return;
   const double3 f = force_atom(L, W, (int)i);
+  const double4 h = W.fhb[i];
   const int o = L.perm[i];
-  forces[3 * (int64_t)o] = f.x;
-  forces[3 * (int64_t)o + 1] = f.y;
-  forces[3 * (int64_t)o + 2] = f.z;
+  forces[3 * (int64_t)o] = f.x + h.x;
+  forces[3 * (int64_t)o + 1] = f.y + h.y;
+  forces[3 * (int64_t)o + 2] = f.z + h.z;
 }
 
 __global__ void k_gather_q(const double* __restrict__ q, const int32_t* __restrict__ perm,
@@ -906,7 +907,8 @@ static unsigned task_grid(int64_t bound) {
 }
 
 int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, const double* q,
-                  double* forces, double* energies, Scratch& sc, Prof& pf, hipStream_t st) {
+                  hipStream_t side, hipEvent_t ev_fork, hipEvent_t ev_join, double* forces,
+                  double* energies, Scratch& sc, Prof& pf, hipStream_t st) {
   const int64_t n = L.n, nb = L.nbond;
   pf.begin(KID_ZERO, st);
   (void)hipMemsetAsync(energies, 0, sizeof(double) * NTERMS, st);
@@ -916,6 +918,7 @@ int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, co
     (void)hipMemsetAsync(W.gvec, 0, sizeof(double4) * nb, st);
   }
   if (n > 0) (void)hipMemsetAsync(W.gSBO, 0, sizeof(double) * n, st);
+  if (n > 0) (void)hipMemsetAsync(W.fhb, 0, sizeof(double4) * n, st);
   pf.end(st);
   if (n == 0) return hipGetLastError() == hipSuccess ? 0 : -1;
   const dim3 grid(xcd_grid(nblk(n, BS))), blk(BS);
@@ -925,22 +928,37 @@ int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, co
     hipLaunchKernelGGL(__VA_ARGS__);                     \
     pf.end(st);                                          \
   } while (0)
+  // the nonbonded kernels read neighbours by stencil slot through a chunk table
+  if (!L.far_slots || stencil_chunks(g) > NBC_MAXQ) return -1;
   LAUNCH(KID_GATHER_Q, k_gather_q, grid, blk, 0, st, q, L.perm, L.xs, n, W.xq);
-  // nonbonded first: it initialises the per-atom force accumulator that the
-  // hydrogen-bond kernel adds to
-  {
-    // the kernel reads neighbours by stencil slot through a chunk table
-    if (!L.far_slots || stencil_chunks(g) > NBC_MAXQ) return -1;
-    const int ncell = g.nc[0] * g.nc[1] * g.nc[2], per_xcd = (ncell + 7) / 8;
-    if (L.nb_half) {
-      LAUNCH(KID_NONBONDED, k_nonbonded_half, dim3(8u * (unsigned)per_xcd), dim3(NBH_BS), 0, st, P, g, L, W,
-             ncell, per_xcd, energies);
-      LAUNCH(KID_NB_REDUCE, k_nb_reduce, grid, blk, 0, st, g, L, W);
-    } else {
-      LAUNCH(KID_NONBONDED, k_nonbonded, dim3(8u * (unsigned)per_xcd), dim3(NBC_BS), 0, st, P, g, L, W,
-             ncell, per_xcd, energies);
-    }
+  // fork: the nonbonded term (writing fnb) runs on the side stream while the
+  // bonded terms run on the caller's stream; they share only the energy
+  // accumulators (atomic adds) until the join before the force gather.  With
+  // side == st everything runs in order on the caller's stream.
+  const bool fork = side != st;
+  if (fork) {
+    (void)hipEventRecord(ev_fork, st);
+    (void)hipStreamWaitEvent(side, ev_fork, 0);
   }
+  {
+    const int ncell = g.nc[0] * g.nc[1] * g.nc[2], per_xcd = (ncell + 7) / 8;
+#define LAUNCH_SIDE(id, ...)                             \
+  do {                                                   \
+    pf.begin(id, side);                                  \
+    hipLaunchKernelGGL(__VA_ARGS__);                     \
+    pf.end(side);                                        \
+  } while (0)
+    if (L.nb_half) {
+      LAUNCH_SIDE(KID_NONBONDED, k_nonbonded_half, dim3(8u * (unsigned)per_xcd), dim3(NBH_BS), 0, side, P, g,
+                  L, W, ncell, per_xcd, energies);
+      LAUNCH_SIDE(KID_NB_REDUCE, k_nb_reduce, grid, blk, 0, side, g, L, W);
+    } else {
+      LAUNCH_SIDE(KID_NONBONDED, k_nonbonded, dim3(8u * (unsigned)per_xcd), dim3(NBC_BS), 0, side, P, g, L,
+                  W, ncell, per_xcd, energies);
+    }
+#undef LAUNCH_SIDE
+  }
+  if (fork) (void)hipEventRecord(ev_join, side);
   LAUNCH(KID_BO_PRIME, k_bo_prime, grid, blk, 0, st, P, g, L, W);
   LAUNCH(KID_DELTA_PRIME, k_delta_prime, grid, blk, 0, st, P, L, W);
   LAUNCH(KID_BO_CORR, k_bo_corr, grid, blk, 0, st, P, L, W);
@@ -968,6 +986,8 @@ int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, co
   LAUNCH(KID_BACK_S, k_back_s, grid, blk, 0, st, L, W);
   LAUNCH(KID_BACK_CORR, k_back_corr, grid, blk, 0, st, P, L, W);
   LAUNCH(KID_BACK_DP, k_back_dp, grid, blk, 0, st, L, W);
+  // join: the force gather reads the nonbonded forces
+  if (fork) (void)hipStreamWaitEvent(st, ev_join, 0);
   LAUNCH(KID_FORCES, k_forces, grid, blk, 0, st, L, W, forces);
 #undef LAUNCH
   return hipGetLastError() == hipSuccess ? 0 : -1;

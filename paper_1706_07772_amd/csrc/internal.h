@@ -102,6 +102,7 @@ int launch_export(const Grid& g, const Lists& L, int32_t* far, int32_t* bonds, i
                   hipStream_t st);
 
 int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, const double* q,
+                  hipStream_t side, hipEvent_t ev_fork, hipEvent_t ev_join,
                   double* forces, double* energies, Scratch& sc, Prof& pf, hipStream_t st);
 int launch_kick(int64_t n, double* vel, const double* forces, const int32_t* type,
                 const DevParams* P, double half_dt, hipStream_t st);
@@ -123,6 +124,11 @@ struct reaxff_ctx {
   rx::Work W{};
   rx::Scratch sc{};
   rx::Prof prof;
+  // the nonbonded term runs on a stream of its own, concurrent with the
+  // bonded terms, between a fork and a join event on the caller's stream
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool overlap = true;
   bool built = false;
   double box[3] = {0, 0, 0};
   bool periodic = false;

@@ -163,7 +163,8 @@ struct Work {
   double* gSBO;    // dE/dSBO
   double* gStot;   // dE/dS including gathered cross-atom terms
   double* gDp;     // dE/dDelta' (sum over own bonds)
-  double4* fnb;    // forces from nonbonded and hydrogen-bond Z terms (atomics)
+  double4* fnb;    // nonbonded forces
+  double4* fhb;    // hydrogen-bond forces on H (atomics) and on acceptors
   double4* xq;     // sorted positions with charge in w
   unsigned long long* counters;  // [0] angles [1] torsions [2] hbonds
   // interaction task lists: per-owner counts, exclusive sums, flat tasks

@@ -203,3 +203,21 @@ def test_error_paths(ff, params):
     # the context still works afterwards
     e, f = gpu_eval(ff, s)
     assert np.isfinite(e).all() and np.isfinite(f).all()
+
+
+@pytest.mark.parametrize("system", ["box", "cluster"])
+def test_overlap_matches_in_order(ff, params, system):
+    """The nonbonded term on the context's second stream, concurrent with the
+    bonded terms, gives the energies and forces of the in-order run (the two
+    differ only in the order of floating-point additions)."""
+    s = rs.petn_lattice(216, 40.05, seed=11) if system == "box" else rs.cluster(3000, seed=5)
+    try:
+        ff.set_overlap(False)
+        e0, f0 = gpu_eval(ff, s)
+        ff.set_overlap(True)
+        e1, f1 = gpu_eval(ff, s)
+    finally:
+        ff.set_overlap(True)
+    scale = np.abs(e0).max()
+    assert np.abs(e1 - e0).max() <= 1e-12 * scale
+    assert np.abs(f1 - f0).max() <= 1e-11 * np.abs(f0).max()
