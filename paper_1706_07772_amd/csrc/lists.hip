@@ -325,58 +325,86 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
   }
 }
 
-// bond-order test of each atom's staged candidates (one thread per atom):
-// a candidate is a bond iff its raw uncorrected bond order reaches bo_cut
-__global__ __launch_bounds__(256) void k_bondtest(
+// bond-order test of each atom's staged candidates, 16 lanes per atom, one
+// candidate per lane: a candidate is a bond iff its raw uncorrected bond order
+// reaches bo_cut.  Accepted candidates keep their candidate order (numbered
+// with the group's ballot).  Workgroups stride over tiles of 16 atoms and
+// add their task-list bounds to the three totals once per workgroup.
+constexpr int BT_GROUP = 16, BT_BS = 256, BT_TILE = BT_BS / BT_GROUP;
+
+__global__ __launch_bounds__(BT_BS) void k_bondtest(
     const DevParams* __restrict__ P, Grid g, int64_t n, const double4* __restrict__ xs,
     const int32_t* __restrict__ cnt_cand, const int32_t* __restrict__ cand_j, int cand_w,
     int32_t* __restrict__ cnt_bond, int32_t* __restrict__ bond_t, int bond_w,
     int32_t* __restrict__ need, unsigned long long* __restrict__ totals) {
-  const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
+  __shared__ unsigned long long red[BT_BS / 64][3];
+  const int lane = threadIdx.x & 63, sub = lane & (BT_GROUP - 1), gsh = lane & ~(BT_GROUP - 1);
+  const double bo_cut = P->bo_cut;
   unsigned long long ba = 0, bt = 0, bd = 0;
-  if (i < n) {
-    const double4 xi = xs[i];
+  const int64_t ntile = (n + BT_TILE - 1) / BT_TILE;
+  for (int64_t tile = xcd_block(); tile < ntile; tile += gridDim.x) {
+    const int64_t i = tile * BT_TILE + threadIdx.x / BT_GROUP;
+    const bool live = i < n;
+    const double4 xi = live ? xs[i] : make_double4(0.0, 0.0, 0.0, 0.0);
     const int ti = (int)xi.w;
-    const double bo_cut = P->bo_cut;
-    const int nc = cnt_cand[i] < cand_w ? cnt_cand[i] : cand_w;
-    const int32_t* crow = cand_j + i * (int64_t)cand_w;
-    int32_t* brow = bond_t + i * (int64_t)bond_w;
+    const int nc = live ? (cnt_cand[i] < cand_w ? cnt_cand[i] : cand_w) : 0;
+    const int32_t* crow = cand_j + (live ? i : 0) * (int64_t)cand_w;
+    int32_t* brow = bond_t + (live ? i : 0) * (int64_t)bond_w;
+    // the longest candidate row of the wavefront bounds its (uniform) loop
+    int ncmax = nc;
+    for (int off = BT_GROUP; off < 64; off <<= 1) ncmax = max(ncmax, __shfl_xor(ncmax, off, 64));
     int nb = 0;
-    for (int k = 0; k < nc; ++k) {
-      const int s = crow[k];
-      const double4 xj = xs[s];
-      double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
-      if (g.periodic) {
-        dx = min_image(dx, g.L[0], g.invL[0]);
-        dy = min_image(dy, g.L[1], g.invL[1]);
-        dz = min_image(dz, g.L[2], g.invL[2]);
+    for (int k0 = 0; k0 < ncmax; k0 += BT_GROUP) {
+      const int k = k0 + sub;
+      bool ok = false;
+      int s = 0;
+      if (k < nc) {
+        s = crow[k];
+        const double4 xj = xs[s];
+        double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
+        if (g.periodic) {
+          dx = min_image(dx, g.L[0], g.invL[0]);
+          dy = min_image(dy, g.L[1], g.invL[1]);
+          dz = min_image(dz, g.L[2], g.invL[2]);
+        }
+        const double r2 = r2_of(dx, dy, dz);
+        ok = bo_raw(P->pair[ti * NT + (int)xj.w], sqrt(r2), bo_cut) >= bo_cut;
       }
-      const double r2 = r2_of(dx, dy, dz);
-      if (bo_raw(P->pair[ti * NT + (int)xj.w], sqrt(r2), bo_cut) >= bo_cut) {
-        if (nb < bond_w) brow[nb] = s;
-        ++nb;
+      const unsigned mask = (unsigned)(__ballot(ok) >> gsh) & ((1u << BT_GROUP) - 1u);
+      if (ok) {
+        const int pos = nb + __popc(mask & ((1u << sub) - 1u));
+        if (pos < bond_w) brow[pos] = s;
       }
+      nb += __popc(mask);
     }
-    cnt_bond[i] = nb;
-    if (nb > bond_w) atomicMax(&need[2], nb);
-    // bounds of the interaction task lists built from this bond list:
-    // angles at i <= C(d,2); torsions about i's bonds <= ceil(d (d-1)^2 / 2)
-    // (the sum over bonds of (d_j-1)(d_k-1) is at most half the sum of
-    // squares); donor bonds <= d for an H atom
-    const unsigned long long d = (unsigned long long)nb;
-    ba = d * (d > 0 ? d - 1 : 0) / 2;
-    bt = (d * (d > 0 ? (d - 1) * (d - 1) : 0) + 1) / 2;
-    bd = P->atom[ti].hbond == 1 ? d : 0;
+    if (live && sub == 0) {
+      cnt_bond[i] = nb;
+      if (nb > bond_w) atomicMax(&need[2], nb);
+      // bounds of the interaction task lists built from this bond list:
+      // angles at i <= C(d,2); torsions about i's bonds <= ceil(d (d-1)^2 / 2)
+      // (the sum over bonds of (d_j-1)(d_k-1) is at most half the sum of
+      // squares); donor bonds <= d for an H atom
+      const unsigned long long d = (unsigned long long)nb;
+      ba += d * (d > 0 ? d - 1 : 0) / 2;
+      bt += (d * (d > 0 ? (d - 1) * (d - 1) : 0) + 1) / 2;
+      bd += P->atom[ti].hbond == 1 ? d : 0;
+    }
   }
   for (int off = 32; off > 0; off >>= 1) {
     ba += __shfl_down(ba, off, 64);
     bt += __shfl_down(bt, off, 64);
     bd += __shfl_down(bd, off, 64);
   }
-  if ((threadIdx.x & 63) == 0) {
-    if (ba) atomicAdd(&totals[1], ba);
-    if (bt) atomicAdd(&totals[2], bt);
-    if (bd) atomicAdd(&totals[3], bd);
+  if (lane == 0) {
+    red[threadIdx.x >> 6][0] = ba;
+    red[threadIdx.x >> 6][1] = bt;
+    red[threadIdx.x >> 6][2] = bd;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    unsigned long long v = 0;
+    for (int w = 0; w < BT_BS / 64; ++w) v += red[w][threadIdx.x];
+    if (v) atomicAdd(&totals[threadIdx.x + 1], v);
   }
 }
 
@@ -544,7 +572,8 @@ int launch_sweep(const DevParams* P, const Grid& g, int64_t n, int ncell, Scratc
                        reinterpret_cast<unsigned long long*>(sc.totals));
   pf.end(st);
   pf.begin(KID_BONDTEST, st);
-  hipLaunchKernelGGL(k_bondtest, dim3(xcd_grid(nblk(n, 256))), dim3(256), 0, st, P, g, n, L.xs, sc.cnt_cand,
+  hipLaunchKernelGGL(k_bondtest, dim3(xcd_grid(std::min<int64_t>(nblk(n, BT_TILE), 4096))), dim3(BT_BS), 0, st,
+                     P, g, n, L.xs, sc.cnt_cand,
                      sc.cand_j, sc.cand_w, sc.cnt_bond, sc.bond_t, sc.bond_w, sc.need,
                      reinterpret_cast<unsigned long long*>(sc.totals));
   pf.end(st);
