@@ -52,7 +52,7 @@ PHASES = {
               "list_sweep", "bondtest", "compact", "mirror"),
     "bonded": ("gather_q", "bo_prime", "delta_prime", "bo_corr", "atom_state", "atom_energy",
                "tasks", "angles", "torsions", "hbonds", "hb_acceptors"),
-    "nonbonded": ("nonbonded", "nb_reduce"),
+    "nonbonded": ("nonbonded", "nb_reduce", "nb_energy"),
     "backward": ("back_s", "back_corr", "back_dp", "forces"),
 }
 
@@ -378,9 +378,9 @@ def main():
                             "measured": "kernel pass: same steps, terms in order on one stream"}
                 # the whole nonbonded term: the pair kernel and, in the half
                 # evaluation, the per-atom sum of the cells' partial forces
-                extra = kernels.get("nb_reduce")
+                extra = [kernels[k]["ms_avg"] for k in ("nb_reduce", "nb_energy") if k in kernels]
                 if dom == "nonbonded" and extra:
-                    term_ms = kernels[dom]["ms_avg"] + extra["ms_avg"]
+                    term_ms = kernels[dom]["ms_avg"] + sum(extra)
                     roofline["term_ms"] = term_ms
                     roofline["term_frac"] = flops / (term_ms * 1e-3) / 1e12 / PEAK_FP64_VALU_TFLOPS
         if roofline is None:

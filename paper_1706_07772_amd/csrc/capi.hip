@@ -246,7 +246,7 @@ void reaxff_destroy(reaxff_ctx* c) {
                   c->W.bd, c->W.bop, c->W.dbop, c->W.bo, c->W.gbo, c->W.gvec, c->W.gup, c->W.dp,
                   c->W.ast, c->W.gS, c->W.gSig, c->W.gSBO, c->W.gStot, c->W.gDp, c->W.fnb, c->W.fhb,
                   c->W.xq, c->W.counters, c->W.cnt_ang, c->W.cnt_tor, c->W.cnt_don,
-                  c->W.off_ang, c->W.off_tor, c->W.off_don, c->W.ang, c->W.tor, c->W.don, c->W.donrec, c->L.far_lo, c->W.nbpart, c->W.nbtab,
+                  c->W.off_ang, c->W.off_tor, c->W.off_don, c->W.ang, c->W.tor, c->W.don, c->W.donrec, c->L.far_lo, c->W.nbpart, c->W.nbtab, c->W.nbe,
                   c->L.bond_i, c->sc.cid, c->sc.cell_s, c->sc.cell_count,
                   c->sc.cell_cursor, c->sc.flag, c->sc.cnt_cand, c->sc.cnt_bond,
                   c->sc.cand_j, c->sc.bond_t, c->sc.need,
@@ -403,6 +403,11 @@ int reaxff_build_lists(reaxff_ctx* c, int64_t n, const double* pos, const int32_
   // half nonbonded evaluation when every cell's upper stencil fits in LDS
   // (need[5], reported by the sweep; zero when a dimension is covered whole)
   c->L.cell_of = c->sc.cell_s;
+  {
+    int64_t t = c->W.cap_nbe;
+    if (grow(c, c->W.nbe, t, std::max<int64_t>(ncell, 1))) return REAXFF_ERR_HIP;
+    c->W.cap_nbe = t;
+  }
   c->L.nb_half = c->L.far_slots && n > 0 && need[5] > 0 && need[5] <= NB_HALF_CAP;
   if (c->L.nb_half) {
     int64_t t = c->W.cap_nbpart;

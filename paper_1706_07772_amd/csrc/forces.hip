@@ -423,7 +423,10 @@ __global__ __launch_bounds__(NBC_BS) void k_nonbonded(const DevParams* __restric
   const int c = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
   if (c >= ncell) return;
   const int a0 = L.cell_start[c], m = L.cell_start[c + 1] - a0;
-  if (m == 0) return;
+  if (m == 0) {
+    if (tid == 0) W.nbe[c] = make_double2(0.0, 0.0);
+    return;
+  }
   if (tid < NT * NT) sp[tid] = nb_params(P->pair[tid]);
   // chunk table of the stencil: start atom and first slot of each chunk
   const int nq = stencil_chunks(g);
@@ -594,8 +597,8 @@ __global__ __launch_bounds__(NBC_BS) void k_nonbonded(const DevParams* __restric
     if (tid < mg) W.fnb[a0 + g0 + tid] = make_double4(facc[0][tid], facc[1][tid], facc[2][tid], 0.0);
     __syncthreads();
   }
-  block_add<NBC_BS>(0.5 * evdw, energies + E_VDW);
-  block_add<NBC_BS>(0.5 * ecoul, energies + E_COUL);
+  const double sv = block_sum<NBC_BS>(0.5 * evdw), sq = block_sum<NBC_BS>(0.5 * ecoul);
+  if (tid == 0) W.nbe[c] = make_double2(sv, sq);
 }
 
 // ---------------------------------------------------------------------------
@@ -629,7 +632,10 @@ __global__ __launch_bounds__(NBH_BS) void k_nonbonded_half(const DevParams* __re
   const int c = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
   if (c >= ncell) return;
   const int a0 = L.cell_start[c], m = L.cell_start[c + 1] - a0;
-  if (m == 0) return;   // no pairs; the reduce skips empty cells
+  if (m == 0) {   // no pairs; the reduce skips empty cells
+    if (tid == 0) W.nbe[c] = make_double2(0.0, 0.0);
+    return;
+  }
   if (tid < NT * NT) sp[tid] = nb_params(P->pair[tid]);
   const int nq = stencil_chunks(g);
   if (tid < nq) {
@@ -795,8 +801,21 @@ __global__ __launch_bounds__(NBH_BS) void k_nonbonded_half(const DevParams* __re
     part[NB_HALF_CAP + t] = fay[t];
     part[2 * NB_HALF_CAP + t] = faz[t];
   }
-  block_add<NBH_BS>(evdw, energies + E_VDW);
-  block_add<NBH_BS>(ecoul, energies + E_COUL);
+  const double sv = block_sum<NBH_BS>(evdw), sq = block_sum<NBH_BS>(ecoul);
+  if (tid == 0) W.nbe[c] = make_double2(sv, sq);
+}
+
+// the cells' nonbonded energies, summed into the two energy terms
+__global__ __launch_bounds__(BS) void k_nb_energy(int ncell, const double2* __restrict__ nbe,
+                                                  double* __restrict__ energies) {
+  double ev = 0.0, eq = 0.0;
+  for (int c = blockIdx.x * BS + threadIdx.x; c < ncell; c += gridDim.x * BS) {
+    const double2 e = nbe[c];
+    ev += e.x;
+    eq += e.y;
+  }
+  block_add<BS>(ev, energies + E_VDW);
+  block_add<BS>(eq, energies + E_COUL);
 }
 
 // Nonbonded force of each atom j from the partial arrays of the cells whose
@@ -897,7 +916,7 @@ const char* const kKernelNames[KID_COUNT] = {
     "bbox", "cell_hist", "cell_scatter", "cell_sort", "gather_sorted", "list_sweep", "scan",
     "bondtest", "compact", "mirror", "zero", "gather_q", "bo_prime", "delta_prime", "bo_corr", "atom_state",
     "atom_energy", "tasks", "angles", "torsions", "hbonds", "hb_acceptors", "nonbonded", "back_s", "back_corr",
-    "back_dp", "forces", "batch", "nb_reduce"};
+    "back_dp", "forces", "batch", "nb_reduce", "nb_energy"};
 
 // grid of a grid-stride task kernel: enough blocks to fill the chip, no more
 // than the task bound needs
@@ -956,6 +975,8 @@ int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, co
       LAUNCH_SIDE(KID_NONBONDED, k_nonbonded, dim3(8u * (unsigned)per_xcd), dim3(NBC_BS), 0, side, P, g, L,
                   W, ncell, per_xcd, energies);
     }
+    LAUNCH_SIDE(KID_NB_ENERGY, k_nb_energy, dim3((unsigned)std::min<int64_t>(nblk(ncell, BS), 64)), blk, 0, side,
+                ncell, W.nbe, energies);
 #undef LAUNCH_SIDE
   }
   if (fork) (void)hipEventRecord(ev_join, side);

@@ -185,6 +185,10 @@ struct Work {
   double* nbpart;
   int32_t* nbtab;
   int64_t cap_nbpart, cap_nbtab;
+  // per-cell nonbonded energies (van der Waals, Coulomb), summed by a small
+  // reduction instead of one pair of same-address atomics per cell
+  double2* nbe;
+  int64_t cap_nbe;
 };
 
 // ---------------------------------------------------------------------------
@@ -310,6 +314,21 @@ __device__ __forceinline__ void block_add(double v, double* dst) {
     for (int k = 0; k < BS / 64; ++k) s += red[k];
     if (s != 0.0) atomicAdd(dst, s);
   }
+}
+
+// wave64 + block reduction of one double; the sum is valid in thread 0
+template <int BS>
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double red[BS / 64];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < BS / 64; ++k) s += red[k];
+  return s;
 }
 
 }  // namespace rx
