@@ -714,41 +714,49 @@ __global__ __launch_bounds__(NBH_BS) void k_nonbonded_half(const DevParams* __re
         ity[lane] = L.type_s[i];
         icnt[lane] = cnt;
         ilo[lane] = lo;
-        nu = (cnt - lo + 63) >> 6;
+        nu = (cnt - lo + 31) >> 5;   // units of 32 entries
       }
       const int v = wave_incl_scan(nu);
       if (lane < mg) upre[lane + 1] = v;
       if (lane == 0) upre[0] = 0;
     }
     __syncthreads();
+    // units of 32 row entries: each wavefront takes a contiguous share of the
+    // units and works on two at a time, one per half (lanes 0-31, 32-63), so a
+    // row's last unit wastes at most 31 lanes of a half; the centre atom is
+    // uniform over each half
     const int U = __builtin_amdgcn_readfirstlane(upre[mg]);
     const int wu = __builtin_amdgcn_readfirstlane(wv);
     const int u0 = U * wu / NBH_WAVES, u1 = U * (wu + 1) / NBH_WAVES;
     if (u0 < u1) {
+      const int hh = lane >> 5, sl = lane & 31;
       auto locate = [&](int u, int& a) {
-        while (__builtin_amdgcn_readfirstlane(upre[a + 1]) <= u) ++a;
+        while (upre[a + 1] <= u) ++a;
       };
       auto fetch = [&](int u, int a) {
-        const int k = __builtin_amdgcn_readfirstlane(ilo[a]) +
-                      ((u - __builtin_amdgcn_readfirstlane(upre[a])) << 6) + lane;
+        const int k = ilo[a] + ((u - upre[a]) << 5) + sl;
         const int32_t* __restrict__ row = L.far_j + (int64_t)(a0 + g0 + a) * L.far_w;
-        const int t = k < __builtin_amdgcn_readfirstlane(icnt[a]) ? row[k] - S0 : -1;
+        const int t = k < icnt[a] ? row[k] - S0 : -1;
         return (unsigned)t < (unsigned)nup ? t : -1;   // always in range for a consistent list
       };
-      int a = __builtin_amdgcn_readfirstlane(last_le(upre, mg, u0));
-      locate(u0, a);
-      int slot = fetch(u0, a);
+      int uh = u0 + hh;   // this half's unit
+      int a = last_le(upre, mg, uh < u1 ? uh : u1 - 1);
+      int slot = -1;
+      if (uh < u1) {
+        locate(uh, a);
+        slot = fetch(uh, a);
+      }
       int cur = a;
       double xix = ixx[cur], xiy = ixy[cur], xiz = ixz[cur], qi = iqq[cur];
       const NbP* __restrict__ spi = sp + ity[cur] * NT;
       double fx = 0.0, fy = 0.0, fz = 0.0;
-      auto flush = [&]() {
-        for (int off = 32; off > 0; off >>= 1) {
-          fx += __shfl_down(fx, off, 64);
-          fy += __shfl_down(fy, off, 64);
-          fz += __shfl_down(fz, off, 64);
+      auto flush = [&]() {   // over the 32 lanes of this half
+        for (int off = 16; off > 0; off >>= 1) {
+          fx += __shfl_down(fx, off, 32);
+          fy += __shfl_down(fy, off, 32);
+          fz += __shfl_down(fz, off, 32);
         }
-        if (lane == 0) {
+        if (sl == 0) {
           const int t = g0 + cur;   // the centre's staged index: slot - S0 = i - a0
           atomicAdd(&fax[t], fx);
           atomicAdd(&fay[t], fy);
@@ -756,11 +764,13 @@ __global__ __launch_bounds__(NBH_BS) void k_nonbonded_half(const DevParams* __re
         }
         fx = fy = fz = 0.0;
       };
-      for (int u = u0; u < u1; ++u) {
+      for (int ub = u0; ub < u1; ub += 2) {
         const int tnow = slot, anow = a;
-        if (u + 1 < u1) {
-          locate(u + 1, a);
-          slot = fetch(u + 1, a);
+        const int unext = ub + 2 + hh;
+        slot = -1;
+        if (unext < u1) {
+          locate(unext, a);
+          slot = fetch(unext, a);
         }
         if (anow != cur) {
           flush();
