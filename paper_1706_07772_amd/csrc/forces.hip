@@ -612,8 +612,8 @@ __global__ __launch_bounds__(NBC_BS) void k_nonbonded(const DevParams* __restric
 //     forces are added to LDS accumulators on the staged slots (the centre's
 //     through a wavefront sum when the wavefront moves on, the partner's per
 //     pair); the accumulators are stored, not added, to the cell's partial
-//     array, and k_nb_reduce sums the partial arrays of the 63 cells whose
-//     upper stencil holds an atom.  Energies take each pair once.
+//     array (x, y, z of a slot contiguous), and k_nb_reduce sums the partial
+//     arrays of the 63 cells whose upper stencil holds an atom.  Energies take each pair once.
 // ---------------------------------------------------------------------------
 constexpr int NBH_BS = 512, NBH_WAVES = NBH_BS / 64;
 
@@ -807,9 +807,9 @@ __global__ __launch_bounds__(NBH_BS) void k_nonbonded_half(const DevParams* __re
   __syncthreads();
   double* __restrict__ part = W.nbpart + (int64_t)c * 3 * NB_HALF_CAP;
   for (int t = tid; t < nup; t += NBH_BS) {
-    part[t] = fax[t];
-    part[NB_HALF_CAP + t] = fay[t];
-    part[2 * NB_HALF_CAP + t] = faz[t];
+    part[3 * t] = fax[t];
+    part[3 * t + 1] = fay[t];
+    part[3 * t + 2] = faz[t];
   }
   const double sv = block_sum<NBH_BS>(evdw), sq = block_sum<NBH_BS>(ecoul);
   if (tid == 0) W.nbe[c] = make_double2(sv, sq);
@@ -873,9 +873,9 @@ __global__ __launch_bounds__(BS) void k_nb_reduce(Grid g, Lists L, Work W) {
         const int t = W.nbtab[(int64_t)c * NB_QMAX + q] + ((int)j - s0);
         if ((unsigned)t >= (unsigned)NB_HALF_CAP) continue;   // never taken for a consistent list
         const double* __restrict__ part = W.nbpart + (int64_t)c * 3 * NB_HALF_CAP;
-        fx += part[t];
-        fy += part[NB_HALF_CAP + t];
-        fz += part[2 * NB_HALF_CAP + t];
+        fx += part[3 * t];
+        fy += part[3 * t + 1];
+        fz += part[3 * t + 2];
       }
     }
   }

@@ -180,7 +180,7 @@ struct Work {
   DonRec* donrec;    // per donor task: what the acceptor side reads of h->X
   int64_t cap_ang, cap_tor, cap_don;
   // half nonbonded evaluation: per-cell partial forces on the upper stencil
-  // ([cell][3][NB_HALF_CAP]) and per-cell chunk bases relative to the cell's
+  // ([cell][NB_HALF_CAP][3]) and per-cell chunk bases relative to the cell's
   // first atom ([cell][NB_QMAX])
   double* nbpart;
   int32_t* nbtab;
