@@ -385,27 +385,6 @@ constexpr int NBC_CAP = 2048;  // stencil atoms held in LDS
 constexpr int NBC_MG = 64;     // atoms of a cell per pass
 constexpr int NBC_MAXQ = 64;   // chunks of a stencil: 2 (2 reach + 1)^2 <= 50
 
-// largest k in [0, n) with b[k] <= t, for non-decreasing b with b[0] <= t
-__device__ __forceinline__ int last_le(const int* b, int n, int t) {
-  int lo = 0, hi = n;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (b[mid] <= t) lo = mid;
-    else hi = mid;
-  }
-  return lo;
-}
-
-// inclusive prefix sum over the 64 lanes
-__device__ __forceinline__ int wave_incl_scan(int v) {
-  const int lane = threadIdx.x & 63;
-  for (int off = 1; off < 64; off <<= 1) {
-    const int t = __shfl_up(v, off, 64);
-    if (lane >= off) v += t;
-  }
-  return v;
-}
-
 __global__ __launch_bounds__(NBC_BS) void k_nonbonded(const DevParams* __restrict__ P, Grid g, Lists L,
                                                       Work W, int ncell, int per_xcd,
                                                       double* __restrict__ energies) {

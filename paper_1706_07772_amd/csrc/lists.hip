@@ -116,19 +116,24 @@ __global__ void k_gather_sorted(const double* __restrict__ pos, const int32_t* _
 }
 
 // One wavefront per cell.  Every atom of a cell has the same (2R+1)^3 cell
-// stencil, so the wavefront loads each 64-candidate chunk of a stencil column
-// once (coalesced) and tests it against each atom of its cell in turn: the
-// cell's atoms live in the lanes and are broadcast one at a time.  Accepted
-// candidates of atom i are numbered with a ballot and written contiguously to
-// i's rows (far list, bond candidates inside the per-type bond reach, H list).
-// Entries beyond a row's width are counted but not written; the largest count
-// of each list is reported so the host can widen the rows and sweep again.
-// Far entries are stencil slots (the neighbour's position in the cell's chunk
-// sequence, see stencil_chunk) when slots is set, sorted atom indices
-// otherwise.
+// stencil.  The wavefront lays the stencil's chunks (stencil_chunk) end to end
+// and walks the resulting slot sequence in full batches of 64 candidates, one
+// per lane (each lane advances through a table of the chunks' first atoms,
+// first slots and image shifts in LDS), loading each batch once and testing
+// it against each atom of its cell in turn: the cell's atoms live in the
+// lanes and are broadcast one at a time.  Accepted candidates of atom i are
+// numbered with a ballot and written contiguously to i's rows (far list, bond
+// candidates inside the per-type bond reach, H lists), in slot order.  Entries
+// beyond a row's width are counted but not written; the largest count of each
+// list is reported so the host can widen the rows and sweep again.  Far
+// entries are stencil slots when slots is set, sorted atom indices otherwise.
+// With far_lo set and no dimension covered whole, far_lo[i] counts the far
+// entries before i's own slot (the pairs the partner's cell owns) and need[5]
+// reports the largest upper stencil (the cell's first atom to the end).
 // MINIMG: periodic box without stencil image shifts (minimum image per pair);
 // otherwise each chunk carries its image shift (zero in open boundaries).
 constexpr int SWEEP_WAVES = 4;
+constexpr int SWEEP_MAXQ = 64;   // chunks of a stencil: 2 (2 reach + 1)^2 <= 50
 
 template <bool MINIMG>
 __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
@@ -139,6 +144,8 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
     int32_t* __restrict__ ha_cnt, int32_t* __restrict__ ha_j, int ha_w, int slots,
     int32_t* __restrict__ far_lo, int32_t* __restrict__ need, unsigned long long* __restrict__ totals) {
   __shared__ unsigned long long red[SWEEP_WAVES][2];
+  __shared__ int q_s0[SWEEP_WAVES][SWEEP_MAXQ], q_base[SWEEP_WAVES][SWEEP_MAXQ + 1];
+  __shared__ double q_sh[SWEEP_WAVES][SWEEP_MAXQ][3];
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int c = blockIdx.x * SWEEP_WAVES + wv;
   const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -155,11 +162,39 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
     accmask |= (P->atom[t].hbond == 2) << t;
     donmask |= (P->atom[t].hbond == 1) << t;
   }
-  const int c2 = c % g.nc[2], c1 = (c / g.nc[2]) % g.nc[1], c0 = c / (g.nc[1] * g.nc[2]);
-  int za0, za1, zb0, zb1;
-  column_ranges(g, c2, za0, za1, zb0, zb1);
-  // image shift of the wrapped part of the z column
-  const double szb = c2 - g.reach < 0 ? g.L[2] : -g.L[2];
+  // the stencil's chunk table: first atom, first slot and image shift
+  int* __restrict__ qs0 = q_s0[wv];
+  int* __restrict__ qb = q_base[wv];
+  const int nq = stencil_chunks(g);
+  {
+    int len = 0;
+    if (m > 0 && lane < nq) {
+      int s0, s1;
+      double sx, sy, sz;
+      stencil_chunk(g, cstart, c, lane, s0, s1, sx, sy, sz);
+      qs0[lane] = s0;
+      len = s1 - s0;
+      q_sh[wv][lane][0] = sx;
+      q_sh[wv][lane][1] = sy;
+      q_sh[wv][lane][2] = sz;
+    }
+    const int v = wave_incl_scan(len);
+    if (lane < nq) qb[lane + 1] = v;
+    if (lane == 0) qb[0] = 0;
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  const int nst = m > 0 ? __builtin_amdgcn_readfirstlane(qb[nq]) : 0;
+  // slot of the cell's first atom: in the centre column's unwrapped z range,
+  // which comes second when the column wraps below the cell
+  const bool halfable = far_lo != nullptr && !g.full[0] && !g.full[1] && !g.full[2];
+  int own0 = 0;
+  if (halfable && m > 0) {
+    const int c2 = c % g.nc[2];
+    const int q_own = 2 * (g.reach * g.span[1] + g.reach) + (g.periodic && c2 - g.reach < 0 ? 1 : 0);
+    own0 = __builtin_amdgcn_readfirstlane(qb[q_own] + (a0 - qs0[q_own]));
+    if (lane == 0) atomicMax(&need[5], nst - own0);
+  }
   for (int ig = 0; ig < m; ig += 64) {       // the cell's atoms, 64 at a time, one per lane
     const int mi = m - ig < 64 ? m - ig : 64;
     double4 xmine = make_double4(0.0, 0.0, 0.0, 0.0);
@@ -167,133 +202,92 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
     const int tmine = (int)xmine.w;
     int kf = 0, kc = 0, kh = 0, ka = 0;       // lane l: counts of the cell's atom l
     int klo = 0;                              // lane l: far entries before atom l's own slot
-    // slot0: stencil slot of candidate s0; own_split (compile-time): the
-    // centre cell's own chunk, whose entries before the atom itself are added
-    // to klo
-    auto chunk = [&](int s0, int s1, double sx, double sy, double sz, int slot0, auto own_split) {
-      constexpr bool OWN = decltype(own_split)::value;
-      for (int base = s0; base < s1; base += 64) {
-        const int s = base + lane;
-        const bool valid = s < s1;
-        double4 xj = make_double4(0.0, 0.0, 0.0, 0.0);
-        if (valid) xj = xs[s];
-        const int tj = (int)xj.w;
-        // bond reach of this candidate's type against each centre type
-        const double q0 = fmin(P->pair[0 * NT + tj].reach2, rb2), q1 = fmin(P->pair[1 * NT + tj].reach2, rb2),
-                     q2 = fmin(P->pair[2 * NT + tj].reach2, rb2), q3 = fmin(P->pair[3 * NT + tj].reach2, rb2);
-        const bool acc = (accmask >> tj) & 1, don = (donmask >> tj) & 1;
-        for (int l = 0; l < mi; ++l) {
-          const int i = a0 + ig + l;
-          const double xix = readlane_d(xmine.x, l), xiy = readlane_d(xmine.y, l),
-                       xiz = readlane_d(xmine.z, l);
-          double dx = xj.x - xix, dy = xj.y - xiy, dz = xj.z - xiz;
-          if constexpr (MINIMG) {
-            dx = min_image(dx, g.L[0], g.invL[0]);
-            dy = min_image(dy, g.L[1], g.invL[1]);
-            dz = min_image(dz, g.L[2], g.invL[2]);
-          } else {
-            dx -= sx;
-            dy -= sy;
-            dz -= sz;
-          }
-          const double r2 = r2_of(dx, dy, dz);
-          const bool f = valid && r2 <= rn2 && s != i;
-          const unsigned long long mf = __ballot(f);
-          if (mf) {
-            // centre type and the bond reach against it, selected without branches
-            const int ti = readlane_i(tmine, l);
-            const double qa = (ti & 1) ? q1 : q0, qb = (ti & 1) ? q3 : q2;
-            const double qt = (ti & 2) ? qb : qa;
-            const bool b = f && r2 <= qt;
-            const bool hr = f && r2 <= rh2;
-            const bool h = hr && acc && ((donmask >> ti) & 1);
-            const bool ha = hr && don && ((accmask >> ti) & 1);
-            const unsigned long long mb = __ballot(b), mh = __ballot(h), ma = __ballot(ha);
-            const int k0 = readlane_i(kf, l);
-            if (f) {
-              const int k = k0 + __popcll(mf & below);
-              if (k < far_w) far_j[(int64_t)i * far_w + k] = slots ? slot0 + (s - s0) : s;
-            }
-            kf = writelane_i(k0 + __popcll(mf), l, kf);
-            if constexpr (OWN) {
-              const unsigned long long ml = __ballot(f && s < i);
-              klo = writelane_i(readlane_i(klo, l) + __popcll(ml), l, klo);
-            }
-            if (mb) {
-              const int k1 = readlane_i(kc, l);
-              if (b) {
-                const int k = k1 + __popcll(mb & below);
-                if (k < cand_w) cand_j[(int64_t)i * cand_w + k] = s;
-              }
-              kc = writelane_i(k1 + __popcll(mb), l, kc);
-            }
-            if (mh) {
-              const int k2 = readlane_i(kh, l);
-              if (h) {
-                const int k = k2 + __popcll(mh & below);
-                if (k < hb_w) hb_j[(int64_t)i * hb_w + k] = s;
-              }
-              kh = writelane_i(k2 + __popcll(mh), l, kh);
-            }
-            if (ma) {
-              const int k3 = readlane_i(ka, l);
-              if (ha) {
-                const int k = k3 + __popcll(ma & below);
-                if (k < ha_w) ha_j[(int64_t)i * ha_w + k] = s;
-              }
-              ka = writelane_i(k3 + __popcll(ma), l, ka);
-            }
-          }
+    int q = 0;                                // this lane's chunk
+    for (int b0 = 0; b0 < nst; b0 += 64) {
+      const int slot = b0 + lane;
+      const bool valid = slot < nst;
+      int s = 0;
+      double sx = 0.0, sy = 0.0, sz = 0.0;
+      if (valid) {
+        while (qb[q + 1] <= slot) ++q;
+        s = qs0[q] + (slot - qb[q]);
+        if constexpr (!MINIMG) {
+          sx = q_sh[wv][q][0];
+          sy = q_sh[wv][q][1];
+          sz = q_sh[wv][q][2];
         }
       }
-    };
-    // the chunks in stencil_chunk's order (x offset, y offset, then the z
-    // range at negative offsets first), slots counted along; the two z ranges
-    // keep their own call sites so the unwrapped one folds its zero shift.
-    // With far_lo set and no dimension covered whole, klo counts the entries
-    // that precede the atom's own slot and own0 is the slot of the cell's
-    // first atom.
-    const bool halfable = far_lo != nullptr && !g.full[0] && !g.full[1] && !g.full[2];
-    const bool wrap_first = zb1 > zb0 && c2 - g.reach < 0;
-    int slot = 0, own0 = 0;
-    for (int a = 0; a < g.span[0]; ++a) {
-      int x = g.full[0] ? a : c0 + a - g.reach;
-      double sx = 0.0;
-      if (g.periodic) {
-        if (x < 0) { x += g.nc[0]; sx = g.L[0]; }
-        else if (x >= g.nc[0]) { x -= g.nc[0]; sx = -g.L[0]; }
-      } else if (x < 0 || x >= g.nc[0]) continue;
-      for (int bb = 0; bb < g.span[1]; ++bb) {
-        int y = g.full[1] ? bb : c1 + bb - g.reach;
-        double sy = 0.0;
-        if (g.periodic) {
-          if (y < 0) { y += g.nc[1]; sy = g.L[1]; }
-          else if (y >= g.nc[1]) { y -= g.nc[1]; sy = -g.L[1]; }
-        } else if (y < 0 || y >= g.nc[1]) continue;
-        const int row = (x * g.nc[1] + y) * g.nc[2];
-        const bool own = a == g.reach && bb == g.reach;
-        const int sa0 = cstart[row + za0], sa1 = cstart[row + za1];
-        const int sb0 = zb1 > zb0 ? cstart[row + zb0] : 0, sb1 = zb1 > zb0 ? cstart[row + zb1] : 0;
-        if (wrap_first && sb1 > sb0) {
-          chunk(sb0, sb1, sx, sy, szb, slot, std::false_type{});
-          slot += sb1 - sb0;
-        }
-        if (own && halfable) {
-          // every entry so far lies before the cell's atoms in slot order
-          own0 = slot + (a0 - sa0);
-          klo = kf;
-          chunk(sa0, sa1, sx, sy, 0.0, slot, std::true_type{});
+      double4 xj = make_double4(0.0, 0.0, 0.0, 0.0);
+      if (valid) xj = xs[s];
+      const int tj = (int)xj.w;
+      // bond reach of this candidate's type against each centre type
+      const double q0 = fmin(P->pair[0 * NT + tj].reach2, rb2), q1 = fmin(P->pair[1 * NT + tj].reach2, rb2),
+                   q2 = fmin(P->pair[2 * NT + tj].reach2, rb2), q3 = fmin(P->pair[3 * NT + tj].reach2, rb2);
+      const bool acc = (accmask >> tj) & 1, don = (donmask >> tj) & 1;
+      for (int l = 0; l < mi; ++l) {
+        const int i = a0 + ig + l;
+        const double xix = readlane_d(xmine.x, l), xiy = readlane_d(xmine.y, l),
+                     xiz = readlane_d(xmine.z, l);
+        double dx = xj.x - xix, dy = xj.y - xiy, dz = xj.z - xiz;
+        if constexpr (MINIMG) {
+          dx = min_image(dx, g.L[0], g.invL[0]);
+          dy = min_image(dy, g.L[1], g.invL[1]);
+          dz = min_image(dz, g.L[2], g.invL[2]);
         } else {
-          chunk(sa0, sa1, sx, sy, 0.0, slot, std::false_type{});
+          dx -= sx;
+          dy -= sy;
+          dz -= sz;
         }
-        slot += sa1 - sa0;
-        if (!wrap_first && sb1 > sb0) {
-          chunk(sb0, sb1, sx, sy, szb, slot, std::false_type{});
-          slot += sb1 - sb0;
+        const double r2 = r2_of(dx, dy, dz);
+        const bool f = valid && r2 <= rn2 && s != i;
+        const unsigned long long mf = __ballot(f);
+        if (mf) {
+          // centre type and the bond reach against it, selected without branches
+          const int ti = readlane_i(tmine, l);
+          const double qa = (ti & 1) ? q1 : q0, qbr = (ti & 1) ? q3 : q2;
+          const double qt = (ti & 2) ? qbr : qa;
+          const bool b = f && r2 <= qt;
+          const bool hr = f && r2 <= rh2;
+          const bool h = hr && acc && ((donmask >> ti) & 1);
+          const bool ha = hr && don && ((accmask >> ti) & 1);
+          const unsigned long long mb = __ballot(b), mh = __ballot(h), ma = __ballot(ha);
+          const int k0 = readlane_i(kf, l);
+          if (f) {
+            const int k = k0 + __popcll(mf & below);
+            if (k < far_w) far_j[(int64_t)i * far_w + k] = slots ? slot : s;
+          }
+          kf = writelane_i(k0 + __popcll(mf), l, kf);
+          if (halfable) {
+            const unsigned long long ml = __ballot(f && slot < own0 + ig + l);
+            klo = writelane_i(readlane_i(klo, l) + __popcll(ml), l, klo);
+          }
+          if (mb) {
+            const int k1 = readlane_i(kc, l);
+            if (b) {
+              const int k = k1 + __popcll(mb & below);
+              if (k < cand_w) cand_j[(int64_t)i * cand_w + k] = s;
+            }
+            kc = writelane_i(k1 + __popcll(mb), l, kc);
+          }
+          if (mh) {
+            const int k2 = readlane_i(kh, l);
+            if (h) {
+              const int k = k2 + __popcll(mh & below);
+              if (k < hb_w) hb_j[(int64_t)i * hb_w + k] = s;
+            }
+            kh = writelane_i(k2 + __popcll(mh), l, kh);
+          }
+          if (ma) {
+            const int k3 = readlane_i(ka, l);
+            if (ha) {
+              const int k = k3 + __popcll(ma & below);
+              if (k < ha_w) ha_j[(int64_t)i * ha_w + k] = s;
+            }
+            ka = writelane_i(k3 + __popcll(ma), l, ka);
+          }
         }
       }
     }
-    if (halfable && ig == 0 && lane == 0 && m > 0) atomicMax(&need[5], slot - own0);
     if (lane < mi) {
       const int i = a0 + ig + lane;
       far_cnt[i] = kf;
@@ -555,6 +549,7 @@ int launch_cell_sort(const double* pos, const int32_t* type, int64_t n, const Gr
 
 int launch_sweep(const DevParams* P, const Grid& g, int64_t n, int ncell, Scratch& sc, Lists& L,
                  Prof& pf, hipStream_t st) {
+  if (stencil_chunks(g) > SWEEP_MAXQ) return -1;   // the sweep's chunk table
   (void)hipMemsetAsync(sc.need, 0, sizeof(int32_t) * 8, st);
   (void)hipMemsetAsync(sc.totals, 0, sizeof(int64_t) * 8, st);
   pf.begin(KID_LIST_SWEEP, st);

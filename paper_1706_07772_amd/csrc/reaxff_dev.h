@@ -300,6 +300,27 @@ __device__ __forceinline__ void stencil_chunk(const Grid& g, const int32_t* __re
   }
 }
 
+// largest k in [0, n) with b[k] <= t, for non-decreasing b with b[0] <= t
+__device__ __forceinline__ int last_le(const int* b, int n, int t) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (b[mid] <= t) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// inclusive prefix sum over the 64 lanes
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  const int lane = threadIdx.x & 63;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int t = __shfl_up(v, off, 64);
+    if (lane >= off) v += t;
+  }
+  return v;
+}
+
 // wave64 + block reduction of one double into *dst (one atomic per block)
 template <int BS>
 __device__ __forceinline__ void block_add(double v, double* dst) {
