@@ -159,19 +159,19 @@ int alloc_atoms(reaxff_ctx* c, int64_t n) {
   G(c->L.ha_cnt);
   G(c->sc.cid); G(c->sc.cell_s); G(c->sc.cnt_cand); G(c->sc.cnt_bond);
   G(c->W.dp); G(c->W.ast); G(c->W.gS); G(c->W.gSig); G(c->W.gSBO); G(c->W.gStot); G(c->W.gDp);
-  G(c->W.fnb); G(c->W.fhb); G(c->W.xq); G(c->W.cnt_ang); G(c->W.cnt_tor); G(c->W.cnt_don); G(c->W.off_ang);
-  G(c->W.off_tor); G(c->W.off_don);
+  G(c->W.fnb); G(c->W.fhb); G(c->W.xq);
 #undef G
   c->cap_n = cap;
   return 0;
 }
 
 int alloc_bonds(reaxff_ctx* c, int64_t nb) {
-  if (nb <= c->cap_bond && c->L.bond_j) return 0;
+  if (nb + 1 <= c->cap_bond && c->L.bond_j) return 0;
   int64_t cap = 0, tmp;
-#define G(ptr) do { tmp = c->cap_bond; if (grow(c, ptr, tmp, nb)) return REAXFF_ERR_HIP; cap = tmp; } while (0)
+#define G(ptr) do { tmp = c->cap_bond; if (grow(c, ptr, tmp, nb + 1)) return REAXFF_ERR_HIP; cap = tmp; } while (0)
   G(c->L.bond_j); G(c->L.bond_i); G(c->L.bond_mir); G(c->W.bd); G(c->W.bop); G(c->W.dbop); G(c->W.bo);
   G(c->W.gbo); G(c->W.gvec); G(c->W.gup);
+  G(c->W.cnt_ang); G(c->W.cnt_tor); G(c->W.cnt_don); G(c->W.off_ang); G(c->W.off_tor); G(c->W.off_don);
 #undef G
   c->cap_bond = cap;
   return 0;

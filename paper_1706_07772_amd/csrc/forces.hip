@@ -61,58 +61,62 @@ __global__ __launch_bounds__(BS) void k_atom_state(const DevParams* __restrict__
 // ---------------------------------------------------------------------------
 template <bool FILL>
 __global__ __launch_bounds__(BS) void k_tasks(const DevParams* __restrict__ P, Lists L, Work W) {
-  const int64_t j = xcd_block() * blockDim.x + threadIdx.x;
-  if (j >= L.n) return;
+  // one thread per bond entry u = j->k; the entries of an atom are
+  // consecutive, so the tasks come out in the order of the atom-major
+  // enumeration: angles (u, v > u) centred on j, torsions about u when k > j,
+  // and the donor bond u when j is a hydrogen
+  const int64_t u = xcd_block() * blockDim.x + threadIdx.x;
+  if (u >= L.nbond) return;
   const double thb = P->thb_cut, thb2 = P->thb_cutsq;
-  const int e0 = L.bond_off[j], e1 = L.bond_off[j + 1];
+  const int j = L.bond_i[u];
+  const int e1 = L.bond_off[j + 1];
+  const int k = L.bond_j[u];
+  const double bu = W.bo[u].x;
   int na = 0, nt = 0, nd = 0;
-  int oa = FILL ? W.off_ang[j] : 0, ot = FILL ? W.off_tor[j] : 0, od = FILL ? W.off_don[j] : 0;
-  const bool hyd = P->atom[L.type_s[j]].hbond == 1;
-  for (int u = e0; u < e1; ++u) {
-    const double bu = W.bo[u].x;
-    // angles (u, v), u < v
-    if (bu - thb > 0.0) {
-      for (int v = u + 1; v < e1; ++v) {
-        const double bv = W.bo[v].x;
-        if (bv - thb > 0.0 && bu * bv > thb2) {
-          if (FILL) W.ang[oa + na] = make_int2(u, v);
-          ++na;
-        }
+  const int oa = FILL ? W.off_ang[u] : 0, ot = FILL ? W.off_tor[u] : 0, od = FILL ? W.off_don[u] : 0;
+  // angles (u, v), u < v
+  if (bu - thb > 0.0) {
+    for (int v = (int)u + 1; v < e1; ++v) {
+      const double bv = W.bo[v].x;
+      if (bv - thb > 0.0 && bu * bv > thb2) {
+        if (FILL) W.ang[oa + na] = make_int2((int)u, v);
+        ++na;
       }
-    }
-    // torsions about the central bond u = j->k, k > j
-    const int k = L.bond_j[u];
-    if (k > (int)j && bu > thb) {
-      const int f0 = L.bond_off[k], f1 = L.bond_off[k + 1];
-      for (int a = e0; a < e1; ++a) {
-        if (a == u) continue;
-        const double ba = W.bo[a].x;
-        if (!(ba > thb)) continue;
-        const int i = L.bond_j[a];
-        for (int b = f0; b < f1; ++b) {
-          const int l = L.bond_j[b];
-          if (l == (int)j || l == i) continue;
-          const double bb = W.bo[b].x;
-          if (!(bb > thb)) continue;
-          if (!(ba * bu * bb > thb)) continue;
-          if (FILL) W.tor[ot + nt] = make_int4(u, a, b, 0);
-          ++nt;
-        }
-      }
-    }
-    // donor bonds
-    if (hyd && P->atom[L.type_s[k]].hbond == 2 && bu >= P->hb_bo_cut && L.hb_cnt[j] > 0) {
-      if (FILL) {
-        W.don[od + nd] = u;
-        W.donrec[od + nd] = DonRec{W.bd[u], bu, k, L.type_s[k]};
-      }
-      ++nd;
     }
   }
+  // torsions about the central bond u = j->k, k > j
+  if (k > j && bu > thb) {
+    const int e0 = L.bond_off[j];
+    const int f0 = L.bond_off[k], f1 = L.bond_off[k + 1];
+    for (int a = e0; a < e1; ++a) {
+      if (a == (int)u) continue;
+      const double ba = W.bo[a].x;
+      if (!(ba > thb)) continue;
+      const int i = L.bond_j[a];
+      for (int b = f0; b < f1; ++b) {
+        const int l = L.bond_j[b];
+        if (l == j || l == i) continue;
+        const double bb = W.bo[b].x;
+        if (!(bb > thb)) continue;
+        if (!(ba * bu * bb > thb)) continue;
+        if (FILL) W.tor[ot + nt] = make_int4((int)u, a, b, 0);
+        ++nt;
+      }
+    }
+  }
+  // donor bond
+  if (P->atom[L.type_s[j]].hbond == 1 && P->atom[L.type_s[k]].hbond == 2 && bu >= P->hb_bo_cut &&
+      L.hb_cnt[j] > 0) {
+    if (FILL) {
+      W.don[od] = (int)u;
+      W.donrec[od] = DonRec{W.bd[u], bu, k, L.type_s[k]};
+    }
+    nd = 1;
+  }
   if (!FILL) {
-    W.cnt_ang[j] = na;
-    W.cnt_tor[j] = nt;
-    W.cnt_don[j] = nd;
+    W.cnt_ang[u] = na;
+    W.cnt_tor[u] = nt;
+    W.cnt_don[u] = nd;
   }
 }
 
@@ -147,7 +151,7 @@ __global__ __launch_bounds__(BS) void k_angles(const DevParams* __restrict__ P, 
   __shared__ double se[ANG_CAPE][5];   // gvec x, y, z, gbo.x, gbo.w per entry
   __shared__ double sc[ANG_CAPC][2];   // gS, dE/dSBO2 per centre
   __shared__ int range[4];
-  const int64_t ntask = W.off_ang[L.n];
+  const int64_t ntask = W.off_ang[L.nbond];
   const int64_t T0 = (int64_t)blockIdx.x * BS;
   if (T0 >= ntask) return;                          // uniform over the block
   const int64_t T1 = T0 + BS < ntask ? T0 + BS : ntask;
@@ -240,7 +244,7 @@ __global__ __launch_bounds__(BS) void k_angles(const DevParams* __restrict__ P, 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(BS) void k_torsions(const DevParams* __restrict__ P, Lists L, Work W,
                                                  double* __restrict__ energies) {
-  const int64_t ntask = W.off_tor[L.n];
+  const int64_t ntask = W.off_tor[L.nbond];
   double etor = 0.0, econj = 0.0;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ntask;
        t += (int64_t)gridDim.x * blockDim.x) {
@@ -263,7 +267,7 @@ __global__ __launch_bounds__(BS) void k_torsions(const DevParams* __restrict__ P
 
 __global__ __launch_bounds__(BS) void k_hbonds(const DevParams* __restrict__ P, Grid g, Lists L, Work W,
                                                double* __restrict__ energies) {
-  const int64_t ntask = W.off_don[L.n];
+  const int64_t ntask = W.off_don[L.nbond];
   double ehb = 0.0;
   unsigned long long nhb = 0;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ntask;
@@ -328,7 +332,7 @@ __global__ __launch_bounds__(BS) void k_hb_acceptors(const DevParams* __restrict
     const int32_t* __restrict__ row = L.ha_j + z * (int64_t)L.ha_w;
     for (int k = sub; k < cnt; k += HB_GROUP) {
       const int h = row[k];
-      const int t0 = W.off_don[h], t1 = W.off_don[h + 1];
+      const int t0 = W.off_don[L.bond_off[h]], t1 = W.off_don[L.bond_off[h + 1]];
       if (t0 == t1) continue;
       const int th = L.type_s[h];
       const double4 xh = L.xs[h];
@@ -975,24 +979,25 @@ int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, co
   LAUNCH(KID_ATOM_STATE, k_atom_state, grid, blk, 0, st, P, L, W);
   LAUNCH(KID_ATOM_ENERGY, k_atom_energy, grid, blk, 0, st, P, L, W, energies);
   // task lists: count, prefix sums, fill
-  LAUNCH(KID_TASKS, k_tasks<false>, grid, blk, 0, st, P, L, W);
-  (void)hipMemsetAsync(W.cnt_ang + n, 0, sizeof(int32_t), st);
-  (void)hipMemsetAsync(W.cnt_tor + n, 0, sizeof(int32_t), st);
-  (void)hipMemsetAsync(W.cnt_don + n, 0, sizeof(int32_t), st);
+  const dim3 gridb(xcd_grid(nblk(std::max<int64_t>(nb, 1), BS)));
+  LAUNCH(KID_TASKS, k_tasks<false>, gridb, blk, 0, st, P, L, W);
+  (void)hipMemsetAsync(W.cnt_ang + nb, 0, sizeof(int32_t), st);
+  (void)hipMemsetAsync(W.cnt_tor + nb, 0, sizeof(int32_t), st);
+  (void)hipMemsetAsync(W.cnt_don + nb, 0, sizeof(int32_t), st);
   pf.begin(KID_SCAN, st);
-  scan_i32(W.cnt_ang, W.off_ang, n + 1, sc, st);
-  scan_i32(W.cnt_tor, W.off_tor, n + 1, sc, st);
-  scan_i32(W.cnt_don, W.off_don, n + 1, sc, st);
+  scan_i32(W.cnt_ang, W.off_ang, nb + 1, sc, st);
+  scan_i32(W.cnt_tor, W.off_tor, nb + 1, sc, st);
+  scan_i32(W.cnt_don, W.off_don, nb + 1, sc, st);
   pf.end(st);
-  LAUNCH(KID_TASKS, k_tasks<true>, grid, blk, 0, st, P, L, W);
+  LAUNCH(KID_TASKS, k_tasks<true>, gridb, blk, 0, st, P, L, W);
   const dim3 gt(task_grid(L.bound_tor));
   LAUNCH(KID_ANGLES, k_angles, dim3((unsigned)std::max<int64_t>((L.bound_ang + BS - 1) / BS, 1)), blk, 0,
          st, P, L, W, energies);
   LAUNCH(KID_TORSIONS, k_torsions, gt, blk, 0, st, P, L, W, energies);
   LAUNCH(KID_HBONDS, k_hbonds, dim3(task_grid(L.bound_don)), blk, 0, st, P, g, L, W, energies);
   LAUNCH(KID_HB_ACC, k_hb_acceptors, dim3(xcd_grid(nblk(n, BS / HB_GROUP))), blk, 0, st, P, g, L, W);
-  (void)hipMemcpyAsync(W.counters, W.off_ang + n, sizeof(int32_t), hipMemcpyDeviceToDevice, st);
-  (void)hipMemcpyAsync(W.counters + 1, W.off_tor + n, sizeof(int32_t), hipMemcpyDeviceToDevice, st);
+  (void)hipMemcpyAsync(W.counters, W.off_ang + nb, sizeof(int32_t), hipMemcpyDeviceToDevice, st);
+  (void)hipMemcpyAsync(W.counters + 1, W.off_tor + nb, sizeof(int32_t), hipMemcpyDeviceToDevice, st);
   LAUNCH(KID_BACK_S, k_back_s, grid, blk, 0, st, L, W);
   LAUNCH(KID_BACK_CORR, k_back_corr, grid, blk, 0, st, P, L, W);
   LAUNCH(KID_BACK_DP, k_back_dp, grid, blk, 0, st, L, W);

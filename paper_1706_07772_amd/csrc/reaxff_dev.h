@@ -168,9 +168,11 @@ struct Work {
   double4* xq;     // sorted positions with charge in w
   unsigned long long* counters;  // [0] angles [1] torsions [2] hbonds
   // interaction task lists: per-owner counts, exclusive sums, flat tasks
-  int32_t* cnt_ang;  // [n + 1] valence angles centred on each atom
-  int32_t* cnt_tor;  // [n + 1] torsions whose central bond the atom owns (lower index)
-  int32_t* cnt_don;  // [n + 1] donor bonds H->X of each H atom
+  // per bond entry u (owner j = bond_i[u]); an atom's tasks start at the
+  // offset of its first entry, off[bond_off[j]]
+  int32_t* cnt_ang;  // [nbond + 1] valence angles (u, v > u) centred on j
+  int32_t* cnt_tor;  // [nbond + 1] torsions about the central bond u = j->k, k > j
+  int32_t* cnt_don;  // [nbond + 1] donor bond u = H->X (0 or 1)
   int32_t* off_ang;
   int32_t* off_tor;
   int32_t* off_don;
