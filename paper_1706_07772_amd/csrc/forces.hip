@@ -66,6 +66,7 @@ __global__ __launch_bounds__(BS) void k_tasks(const DevParams* __restrict__ P, L
   // enumeration: angles (u, v > u) centred on j, torsions about u when k > j,
   // and the donor bond u when j is a hydrogen
   const int64_t u = xcd_block() * blockDim.x + threadIdx.x;
+  if (FILL && u < L.n) W.don_rng[u] = make_int2(W.off_don[L.bond_off[u]], W.off_don[L.bond_off[u + 1]]);
   if (u >= L.nbond) return;
   const double thb = P->thb_cut, thb2 = P->thb_cutsq;
   const int j = L.bond_i[u];
@@ -332,7 +333,8 @@ __global__ __launch_bounds__(BS) void k_hb_acceptors(const DevParams* __restrict
     const int32_t* __restrict__ row = L.ha_j + z * (int64_t)L.ha_w;
     for (int k = sub; k < cnt; k += HB_GROUP) {
       const int h = row[k];
-      const int t0 = W.off_don[L.bond_off[h]], t1 = W.off_don[L.bond_off[h + 1]];
+      const int2 tr = W.don_rng[h];
+      const int t0 = tr.x, t1 = tr.y;
       if (t0 == t1) continue;
       const int th = L.type_s[h];
       const double4 xh = L.xs[h];
@@ -597,6 +599,9 @@ __global__ __launch_bounds__(NBC_BS) void k_nonbonded(const DevParams* __restric
 //     pair); the accumulators are stored, not added, to the cell's partial
 //     array (x, y, z of a slot contiguous), and k_nb_reduce sums the partial
 //     arrays of the 63 cells whose upper stencil holds an atom.  Energies take each pair once.
+//     In a periodic box whose chunk shifts are the minimum images, the
+//     staged positions carry their chunk's shift, so a displacement is a
+//     plain difference; the centre sums use DPP row moves, not LDS.
 // ---------------------------------------------------------------------------
 constexpr int NBH_BS = 512, NBH_WAVES = NBH_BS / 64;
 
@@ -608,6 +613,7 @@ __global__ __launch_bounds__(NBH_BS) void k_nonbonded_half(const DevParams* __re
   __shared__ double fax[NB_HALF_CAP], fay[NB_HALF_CAP], faz[NB_HALF_CAP];
   __shared__ unsigned char sty[NB_HALF_CAP];
   __shared__ int q_s0[NBC_MAXQ], q_base[NBC_MAXQ + 1];
+  __shared__ double q_sh[NBC_MAXQ][3];
   __shared__ int upre[NBC_MG + 1];
   __shared__ double ixx[NBC_MG], ixy[NBC_MG], ixz[NBC_MG], iqq[NBC_MG];
   __shared__ int ity[NBC_MG], icnt[NBC_MG], ilo[NBC_MG];
@@ -621,12 +627,19 @@ __global__ __launch_bounds__(NBH_BS) void k_nonbonded_half(const DevParams* __re
   }
   if (tid < NT * NT) sp[tid] = nb_params(P->pair[tid]);
   const int nq = stencil_chunks(g);
+  // staged positions carry their chunk's image shift when it is the minimum
+  // image of every listed pair; otherwise each pair takes the minimum image
+  const bool shifted = g.periodic && g.shift_ok;
+  const bool minimg = g.periodic && !g.shift_ok;
   if (tid < nq) {
     int s0, s1;
     double sx, sy, sz;
     stencil_chunk(g, L.cell_start, c, tid, s0, s1, sx, sy, sz);
     q_s0[tid] = s0;
     q_base[tid + 1] = s1 - s0;
+    q_sh[tid][0] = shifted ? sx : 0.0;
+    q_sh[tid][1] = shifted ? sy : 0.0;
+    q_sh[tid][2] = shifted ? sz : 0.0;
   }
   __syncthreads();
   if (wv == 0) {
@@ -647,7 +660,7 @@ __global__ __launch_bounds__(NBH_BS) void k_nonbonded_half(const DevParams* __re
   // chunk bases relative to S0, for the reduce
   if (tid <= nq) W.nbtab[(int64_t)c * NB_QMAX + tid] = q_base[tid] - S0;
   for (int t0 = 0; t0 < nup; t0 += 2 * NBH_BS) {
-    int idx[2];
+    int idx[2], qq[2];
     double4 v[2];
     int ty[2];
 #pragma unroll
@@ -657,6 +670,7 @@ __global__ __launch_bounds__(NBH_BS) void k_nonbonded_half(const DevParams* __re
       if (t < nup) {
         const int slot = S0 + t;
         const int q = last_le(q_base, nq, slot);
+        qq[u] = q;
         idx[u] = q_s0[q] + (slot - q_base[q]);
       }
     }
@@ -670,9 +684,9 @@ __global__ __launch_bounds__(NBH_BS) void k_nonbonded_half(const DevParams* __re
     for (int u = 0; u < 2; ++u) {
       const int t = t0 + u * NBH_BS + tid;
       if (idx[u] >= 0) {
-        sxx[t] = v[u].x;
-        sxy[t] = v[u].y;
-        sxz[t] = v[u].z;
+        sxx[t] = v[u].x - q_sh[qq[u]][0];
+        sxy[t] = v[u].y - q_sh[qq[u]][1];
+        sxz[t] = v[u].z - q_sh[qq[u]][2];
         sxq[t] = v[u].w;
         sty[t] = (unsigned char)ty[u];
       }
@@ -733,13 +747,11 @@ __global__ __launch_bounds__(NBH_BS) void k_nonbonded_half(const DevParams* __re
       double xix = ixx[cur], xiy = ixy[cur], xiz = ixz[cur], qi = iqq[cur];
       const NbP* __restrict__ spi = sp + ity[cur] * NT;
       double fx = 0.0, fy = 0.0, fz = 0.0;
-      auto flush = [&]() {   // over the 32 lanes of this half
-        for (int off = 16; off > 0; off >>= 1) {
-          fx += __shfl_down(fx, off, 32);
-          fy += __shfl_down(fy, off, 32);
-          fz += __shfl_down(fz, off, 32);
-        }
-        if (sl == 0) {
+      auto flush = [&]() {   // over the 32 lanes of this half, into its last lane
+        fx = half_sum_last(fx);
+        fy = half_sum_last(fy);
+        fz = half_sum_last(fz);
+        if (sl == 31) {
           const int t = g0 + cur;   // the centre's staged index: slot - S0 = i - a0
           atomicAdd(&fax[t], fx);
           atomicAdd(&fay[t], fy);
@@ -766,7 +778,7 @@ __global__ __launch_bounds__(NBH_BS) void k_nonbonded_half(const DevParams* __re
         }
         if (tnow >= 0) {
           double dx = sxx[tnow] - xix, dy = sxy[tnow] - xiy, dz = sxz[tnow] - xiz;
-          if (g.periodic) {
+          if (minimg) {
             dx = min_image(dx, g.L[0], g.invL[0]);
             dy = min_image(dy, g.L[1], g.invL[1]);
             dz = min_image(dz, g.L[2], g.invL[2]);
@@ -979,7 +991,7 @@ int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, co
   LAUNCH(KID_ATOM_STATE, k_atom_state, grid, blk, 0, st, P, L, W);
   LAUNCH(KID_ATOM_ENERGY, k_atom_energy, grid, blk, 0, st, P, L, W, energies);
   // task lists: count, prefix sums, fill
-  const dim3 gridb(xcd_grid(nblk(std::max<int64_t>(nb, 1), BS)));
+  const dim3 gridb(xcd_grid(nblk(std::max<int64_t>(std::max(nb, n), 1), BS)));
   LAUNCH(KID_TASKS, k_tasks<false>, gridb, blk, 0, st, P, L, W);
   (void)hipMemsetAsync(W.cnt_ang + nb, 0, sizeof(int32_t), st);
   (void)hipMemsetAsync(W.cnt_tor + nb, 0, sizeof(int32_t), st);

@@ -226,8 +226,8 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
       const bool acc = (accmask >> tj) & 1, don = (donmask >> tj) & 1;
       for (int l = 0; l < mi; ++l) {
         const int i = a0 + ig + l;
-        const double xix = readlane_d(xmine.x, l), xiy = readlane_d(xmine.y, l),
-                     xiz = readlane_d(xmine.z, l);
+        const double4 xi4 = xs[i];   // uniform: a scalar load
+        const double xix = xi4.x, xiy = xi4.y, xiz = xi4.z;
         double dx = xj.x - xix, dy = xj.y - xiy, dz = xj.z - xiz;
         if constexpr (MINIMG) {
           dx = min_image(dx, g.L[0], g.invL[0]);

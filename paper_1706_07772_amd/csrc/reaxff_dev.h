@@ -180,6 +180,7 @@ struct Work {
   int4* tor;         // (entry j->k, entry j->i, entry k->l, unused)
   int32_t* don;      // entry h->X
   DonRec* donrec;    // per donor task: what the acceptor side reads of h->X
+  int2* don_rng;     // [n] each atom's donor tasks [x, y)
   int64_t cap_ang, cap_tor, cap_don;
   // half nonbonded evaluation: per-cell partial forces on the upper stencil
   // ([cell][NB_HALF_CAP][3]) and per-cell chunk bases relative to the cell's
@@ -214,9 +215,34 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 __device__ __forceinline__ int readlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+// DPP move of a double (both 32-bit halves): lanes whose source lies outside
+// the row, and rows outside ROWMASK, read 0
+template <int CTRL, int ROWMASK = 0xF>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWMASK, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over each half wavefront (lanes 0-31, 32-63), left in the half's last
+// lane (31, 63); other lanes hold partial sums.  Row shifts by 1, 2, 4, 8
+// make lane 15 of each 16-lane row the row's sum; the broadcast of lane 15 of
+// rows 0 and 2 into rows 1 and 3 adds the half's first row.  Every lane of a
+// half must be active.
+__device__ __forceinline__ double half_sum_last(double v) {
+  v += dpp_d<0x111>(v);          // row_shr:1
+  v += dpp_d<0x112>(v);          // row_shr:2
+  v += dpp_d<0x114>(v);          // row_shr:4
+  v += dpp_d<0x118>(v);          // row_shr:8
+  v += dpp_d<0x142, 0xA>(v);     // row_bcast:15 into rows 1 and 3
+  return v;
+}
 // lane l takes the (uniform) value v, the other lanes keep old
 __device__ __forceinline__ int writelane_i(int v, int l, int old) {
-  return (int)(threadIdx.x & 63) == l ? v : old;
+  asm("v_writelane_b32 %0, %1, m0" : "+v"(old) : "s"(v), "{m0}"(l));
+  return old;
 }
 
 // Work-group order for kernels over cell-sorted data.  The hardware deals
