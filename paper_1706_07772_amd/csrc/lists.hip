@@ -224,6 +224,9 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
       const double q0 = fmin(P->pair[0 * NT + tj].reach2, rb2), q1 = fmin(P->pair[1 * NT + tj].reach2, rb2),
                    q2 = fmin(P->pair[2 * NT + tj].reach2, rb2), q3 = fmin(P->pair[3 * NT + tj].reach2, rb2);
       const bool acc = (accmask >> tj) & 1, don = (donmask >> tj) & 1;
+      // lane masks of the batch: the count masks below are ANDs of plain
+      // compares with these, so no predicate is rebuilt for its ballot
+      const unsigned long long vmask = ballot(valid), accl = ballot(valid && acc), donl = ballot(valid && don);
       for (int l = 0; l < mi; ++l) {
         const int i = a0 + ig + l;
         const double4 xi4 = xs[i];   // uniform: a scalar load
@@ -240,17 +243,26 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
         }
         const double r2 = r2_of(dx, dy, dz);
         const bool f = valid && r2 <= rn2 && s != i;
-        const unsigned long long mf = __ballot(f);
+        const unsigned long long mf = ballot(r2 <= rn2) & ballot(s != i) & vmask;
         if (mf) {
-          // centre type and the bond reach against it, selected without branches
+          // centre type (uniform) and the bond reach against it
           const int ti = readlane_i(tmine, l);
-          const double qa = (ti & 1) ? q1 : q0, qbr = (ti & 1) ? q3 : q2;
-          const double qt = (ti & 2) ? qbr : qa;
-          const bool b = f && r2 <= qt;
+          const bool hdon = (donmask >> ti) & 1, hacc = (accmask >> ti) & 1;
           const bool hr = f && r2 <= rh2;
-          const bool h = hr && acc && ((donmask >> ti) & 1);
-          const bool ha = hr && don && ((accmask >> ti) & 1);
-          const unsigned long long mb = __ballot(b), mh = __ballot(h), ma = __ballot(ha);
+          const bool h = hr && acc && hdon;
+          const bool ha = hr && don && hacc;
+          const unsigned long long mhr = mf & ballot(r2 <= rh2);
+          const unsigned long long mh = hdon ? (mhr & accl) : 0ull, ma = hacc ? (mhr & donl) : 0ull;
+          // bond candidates: the pair reach is only selected when some lane
+          // lies within the largest one
+          unsigned long long mb = 0;
+          bool b = false;
+          if (mf & ballot(r2 <= rb2)) {
+            const double qa = (ti & 1) ? q1 : q0, qbr = (ti & 1) ? q3 : q2;
+            const double qt = (ti & 2) ? qbr : qa;
+            b = f && r2 <= qt;
+            mb = mf & ballot(r2 <= qt);
+          }
           const int k0 = readlane_i(kf, l);
           if (f) {
             const int k = k0 + __popcll(mf & below);
@@ -258,7 +270,7 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
           }
           kf = writelane_i(k0 + __popcll(mf), l, kf);
           if (halfable) {
-            const unsigned long long ml = __ballot(f && slot < own0 + ig + l);
+            const unsigned long long ml = mf & ballot(slot < own0 + ig + l);
             klo = writelane_i(readlane_i(klo, l) + __popcll(ml), l, klo);
           }
           if (mb) {
@@ -364,7 +376,7 @@ __global__ __launch_bounds__(BT_BS) void k_bondtest(
         const double r2 = r2_of(dx, dy, dz);
         ok = bo_raw(P->pair[ti * NT + (int)xj.w], sqrt(r2), bo_cut) >= bo_cut;
       }
-      const unsigned mask = (unsigned)(__ballot(ok) >> gsh) & ((1u << BT_GROUP) - 1u);
+      const unsigned mask = (unsigned)(ballot(ok) >> gsh) & ((1u << BT_GROUP) - 1u);
       if (ok) {
         const int pos = nb + __popc(mask & ((1u << sub) - 1u));
         if (pos < bond_w) brow[pos] = s;

@@ -216,6 +216,10 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
 }
 __device__ __forceinline__ int readlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
+// lanes of the wavefront whose predicate holds (taken straight from the
+// compare's lane mask)
+__device__ __forceinline__ unsigned long long ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
 // DPP move of a double (both 32-bit halves): lanes whose source lies outside
 // the row, and rows outside ROWMASK, read 0
 template <int CTRL, int ROWMASK = 0xF>

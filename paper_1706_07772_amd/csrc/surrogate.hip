@@ -621,7 +621,7 @@ __global__ __launch_bounds__(256) void k_far_mirror_scan(int64_t n, const int32_
     int m = -1;
     for (int t0 = 0; t0 < cj && m < 0; t0 += 64) {
       const int t = t0 + lane;
-      const unsigned long long hit = __ballot(t < cj && rj[t] == (int)i);
+      const unsigned long long hit = ballot(t < cj && rj[t] == (int)i);
       if (hit) m = t0 + __ffsll((long long)hit) - 1;
     }
     if (lane == 0) mir[i * (int64_t)far_w + k] = m;
