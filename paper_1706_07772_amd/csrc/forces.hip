@@ -29,12 +29,13 @@ constexpr int BS = 256;
 static inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 // ---------------------------------------------------------------------------
-// per-atom stage kernels: one thread per atom
+// stage kernels: one thread per atom, or per bond entry where the entries
+// of an atom are independent (no serial loop over the entries)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(BS) void k_bo_prime(const DevParams* __restrict__ P, Grid g, Lists L,
                                                  Work W) {
-  const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
-  if (i < L.n) bo_prime_atom(P, g, L, W, (int)i);
+  const int64_t e = xcd_block() * blockDim.x + threadIdx.x;
+  if (e < L.nbond) bo_prime_entry(P, g, L, W, L.bond_i[e], (int)e);
 }
 
 __global__ __launch_bounds__(BS) void k_delta_prime(const DevParams* __restrict__ P, Lists L, Work W) {
@@ -43,8 +44,8 @@ __global__ __launch_bounds__(BS) void k_delta_prime(const DevParams* __restrict_
 }
 
 __global__ __launch_bounds__(BS) void k_bo_corr(const DevParams* __restrict__ P, Lists L, Work W) {
-  const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
-  if (i < L.n) bo_corr_atom(P, L, W, (int)i);
+  const int64_t e = xcd_block() * blockDim.x + threadIdx.x;
+  if (e < L.nbond) bo_corr_entry(P, L, W, L.bond_i[e], (int)e);
 }
 
 __global__ __launch_bounds__(BS) void k_atom_state(const DevParams* __restrict__ P, Lists L, Work W) {
@@ -887,8 +888,8 @@ __global__ __launch_bounds__(BS) void k_back_s(Lists L, Work W) {
 }
 
 __global__ __launch_bounds__(BS) void k_back_corr(const DevParams* __restrict__ P, Lists L, Work W) {
-  const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
-  if (i < L.n) back_corr_atom(P, L, W, (int)i);
+  const int64_t e = xcd_block() * blockDim.x + threadIdx.x;
+  if (e < L.nbond) back_corr_entry(P, L, W, L.bond_i[e], (int)e);
 }
 
 __global__ __launch_bounds__(BS) void k_back_dp(Lists L, Work W) {
@@ -896,16 +897,24 @@ __global__ __launch_bounds__(BS) void k_back_dp(Lists L, Work W) {
   if (i < L.n) back_dp_atom(L, W, (int)i);
 }
 
-// per-atom force gather, written in the caller's order
+// per-atom force gather, four lanes per atom over its entries, written in
+// the caller's order
 __global__ __launch_bounds__(BS) void k_forces(Lists L, Work W, double* __restrict__ forces) {
-  const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
-  if (i >= L.n) return;
-  const double3 f = force_atom(L, W, (int)i);
-  const double4 h = W.fhb[i];
-  const int o = L.perm[i];
-  forces[3 * (int64_t)o] = f.x + h.x;
-  forces[3 * (int64_t)o + 1] = f.y + h.y;
-  forces[3 * (int64_t)o + 2] = f.z + h.z;
+  const int64_t t = xcd_block() * blockDim.x + threadIdx.x;
+  const int64_t i = t >> 2;
+  const int sub = (int)(t & 3);
+  if (i >= L.n) return;   // uniform over the four lanes of an atom
+  double3 f = force_atom(L, W, (int)i, sub, 4);
+  f.x = quad_sum(f.x);
+  f.y = quad_sum(f.y);
+  f.z = quad_sum(f.z);
+  if (sub == 0) {
+    const double4 h = W.fhb[i];
+    const int o = L.perm[i];
+    forces[3 * (int64_t)o] = f.x + h.x;
+    forces[3 * (int64_t)o + 1] = f.y + h.y;
+    forces[3 * (int64_t)o + 2] = f.z + h.z;
+  }
 }
 
 __global__ void k_gather_q(const double* __restrict__ q, const int32_t* __restrict__ perm,
@@ -985,9 +994,10 @@ int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, co
 #undef LAUNCH_SIDE
   }
   if (fork) (void)hipEventRecord(ev_join, side);
-  LAUNCH(KID_BO_PRIME, k_bo_prime, grid, blk, 0, st, P, g, L, W);
+  const dim3 grid_e(xcd_grid(nblk(std::max<int64_t>(nb, 1), BS)));   // one thread per bond entry
+  LAUNCH(KID_BO_PRIME, k_bo_prime, grid_e, blk, 0, st, P, g, L, W);
   LAUNCH(KID_DELTA_PRIME, k_delta_prime, grid, blk, 0, st, P, L, W);
-  LAUNCH(KID_BO_CORR, k_bo_corr, grid, blk, 0, st, P, L, W);
+  LAUNCH(KID_BO_CORR, k_bo_corr, grid_e, blk, 0, st, P, L, W);
   LAUNCH(KID_ATOM_STATE, k_atom_state, grid, blk, 0, st, P, L, W);
   LAUNCH(KID_ATOM_ENERGY, k_atom_energy, grid, blk, 0, st, P, L, W, energies);
   // task lists: count, prefix sums, fill
@@ -1011,11 +1021,11 @@ int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, co
   (void)hipMemcpyAsync(W.counters, W.off_ang + nb, sizeof(int32_t), hipMemcpyDeviceToDevice, st);
   (void)hipMemcpyAsync(W.counters + 1, W.off_tor + nb, sizeof(int32_t), hipMemcpyDeviceToDevice, st);
   LAUNCH(KID_BACK_S, k_back_s, grid, blk, 0, st, L, W);
-  LAUNCH(KID_BACK_CORR, k_back_corr, grid, blk, 0, st, P, L, W);
+  LAUNCH(KID_BACK_CORR, k_back_corr, grid_e, blk, 0, st, P, L, W);
   LAUNCH(KID_BACK_DP, k_back_dp, grid, blk, 0, st, L, W);
   // join: the force gather reads the nonbonded forces
   if (fork) (void)hipStreamWaitEvent(st, ev_join, 0);
-  LAUNCH(KID_FORCES, k_forces, grid, blk, 0, st, L, W, forces);
+  LAUNCH(KID_FORCES, k_forces, dim3(xcd_grid(nblk(4 * n, BS))), blk, 0, st, L, W, forces);
 #undef LAUNCH
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

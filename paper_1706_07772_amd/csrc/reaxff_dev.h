@@ -230,6 +230,14 @@ __device__ __forceinline__ double dpp_d(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Sum over each aligned group of four lanes, in every lane of the group
+// (quad permutations [1,0,3,2] and [2,3,0,1]); all four lanes must be active.
+__device__ __forceinline__ double quad_sum(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  return v;
+}
+
 // Sum over each half wavefront (lanes 0-31, 32-63), left in the half's last
 // lane (31, 63); other lanes hold partial sums.  Row shifts by 1, 2, 4, 8
 // make lane 15 of each 16-lane row the row's sum; the broadcast of lane 15 of

@@ -138,12 +138,12 @@ __device__ __forceinline__ double bo_raw(const PairP& p, double r, double bo_cut
 //     orientation (lower index first) so both entries of a bond hold
 //     identical bits
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void bo_prime_atom(const DevParams* __restrict__ P, const Grid& g,
-                                              const Lists& L, const Work& W, int i) {
+__device__ __forceinline__ void bo_prime_entry(const DevParams* __restrict__ P, const Grid& g,
+                                               const Lists& L, const Work& W, int i, int e) {
   const double4 xi = L.xs[i];
   const int ti = L.type_s[i];
   const double bo_cut = P->bo_cut;
-  for (int e = L.bond_off[i]; e < L.bond_off[i + 1]; ++e) {
+  {
     const int j = L.bond_j[e];
     const double4 xj = L.xs[j];
     const bool lo = i < j;
@@ -180,6 +180,10 @@ __device__ __forceinline__ void bo_prime_atom(const DevParams* __restrict__ P, c
     W.bop[e] = make_double4(s - bo_cut, pi, pp, raw - bo_cut);
     W.dbop[e] = make_double4(ds, dpi, dpp, 0.0);
   }
+}
+__device__ __forceinline__ void bo_prime_atom(const DevParams* __restrict__ P, const Grid& g,
+                                              const Lists& L, const Work& W, int i) {
+  for (int e = L.bond_off[i]; e < L.bond_off[i + 1]; ++e) bo_prime_entry(P, g, L, W, i, e);
 }
 
 // (2) Delta'_i = sum BO' - Val_i,  Delta'boc_i = sum BO' - Val_boc_i
@@ -229,10 +233,10 @@ __device__ __forceinline__ Corr correction(const DevParams* __restrict__ P, doub
 }
 
 // (3) corrected bond orders of atom i's entries
-__device__ __forceinline__ void bo_corr_atom(const DevParams* __restrict__ P, const Lists& L,
-                                             const Work& W, int i) {
+__device__ __forceinline__ void bo_corr_entry(const DevParams* __restrict__ P, const Lists& L,
+                                              const Work& W, int i, int e) {
   const int ti = L.type_s[i];
-  for (int e = L.bond_off[i]; e < L.bond_off[i + 1]; ++e) {
+  {
     const int j = L.bond_j[e];
     const int tj = L.type_s[j];
     const bool lo = i < j;
@@ -246,6 +250,10 @@ __device__ __forceinline__ void bo_corr_atom(const DevParams* __restrict__ P, co
     const double BO = bp.w * F, BOp = bp.y * G, BOpp = bp.z * G;
     W.bo[e] = make_double4(BO, BOp, BOpp, BO - BOp - BOpp);
   }
+}
+__device__ __forceinline__ void bo_corr_atom(const DevParams* __restrict__ P, const Lists& L,
+                                             const Work& W, int i) {
+  for (int e = L.bond_off[i]; e < L.bond_off[i + 1]; ++e) bo_corr_entry(P, L, W, i, e);
 }
 
 // (4) atom state
@@ -665,10 +673,10 @@ __device__ __forceinline__ void back_s_atom(const Lists& L, const Work& W, int i
 }
 
 // (11) through the correction to the uncorrected orders and Delta'
-__device__ __forceinline__ void back_corr_atom(const DevParams* __restrict__ P, const Lists& L,
-                                               const Work& W, int i) {
+__device__ __forceinline__ void back_corr_entry(const DevParams* __restrict__ P, const Lists& L,
+                                                const Work& W, int i, int e) {
   const int ti = L.type_s[i];
-  for (int e = L.bond_off[i]; e < L.bond_off[i + 1]; ++e) {
+  {
     const int j = L.bond_j[e];
     const int m = L.bond_mir[e];
     const int tj = L.type_s[j];
@@ -700,6 +708,10 @@ __device__ __forceinline__ void back_corr_atom(const DevParams* __restrict__ P, 
     W.gup[e] = make_double4(gBOt, gPi, gPp, own);
   }
 }
+__device__ __forceinline__ void back_corr_atom(const DevParams* __restrict__ P, const Lists& L,
+                                               const Work& W, int i) {
+  for (int e = L.bond_off[i]; e < L.bond_off[i + 1]; ++e) back_corr_entry(P, L, W, i, e);
+}
 
 // (12) dE/dDelta' of atom i (Delta' and Delta'boc both are sums of BO')
 __device__ __forceinline__ void back_dp_atom(const Lists& L, const Work& W, int i) {
@@ -709,11 +721,19 @@ __device__ __forceinline__ void back_dp_atom(const Lists& L, const Work& W, int 
 }
 
 // (13) force on atom i: nonbonded/H-bond part plus its bond entries
-__device__ __forceinline__ double3 force_atom(const Lists& L, const Work& W, int i) {
-  const double4 f0 = W.fnb[i];
-  double fx = f0.x, fy = f0.y, fz = f0.z;
+// (entries first + sub, first + sub + stride, ...; sub = 0 adds the
+// nonbonded part)
+__device__ __forceinline__ double3 force_atom(const Lists& L, const Work& W, int i, int sub = 0,
+                                             int stride = 1) {
+  double fx = 0.0, fy = 0.0, fz = 0.0;
+  if (sub == 0) {
+    const double4 f0 = W.fnb[i];
+    fx = f0.x;
+    fy = f0.y;
+    fz = f0.z;
+  }
   const double gi = W.gDp[i];
-  for (int e = L.bond_off[i]; e < L.bond_off[i + 1]; ++e) {
+  for (int e = L.bond_off[i] + sub; e < L.bond_off[i + 1]; e += stride) {
     const int j = L.bond_j[e];
     const int m = L.bond_mir[e];
     const double gj = W.gDp[j];
