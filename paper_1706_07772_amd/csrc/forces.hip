@@ -122,7 +122,8 @@ __global__ __launch_bounds__(BS) void k_tasks(const DevParams* __restrict__ P, L
   }
 }
 
-// (5) bond energy, lone pair, over- and under-coordination (per atom)
+// (5) bond energy, lone pair, over- and under-coordination (per atom; the
+//     atom's own terms are arithmetic-heavy, so one lane per atom)
 __global__ __launch_bounds__(BS) void k_atom_energy(const DevParams* __restrict__ P, Lists L, Work W,
                                                     double* __restrict__ energies) {
   const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
@@ -154,8 +155,9 @@ __global__ __launch_bounds__(BS) void k_angles(const DevParams* __restrict__ P, 
   __shared__ double sc[ANG_CAPC][2];   // gS, dE/dSBO2 per centre
   __shared__ int range[4];
   const int64_t ntask = W.off_ang[L.nbond];
-  const int64_t T0 = (int64_t)blockIdx.x * BS;
-  if (T0 >= ntask) return;                          // uniform over the block
+  const int64_t ab = xcd_active_block((ntask + BS - 1) / BS);
+  if (ab < 0) return;                               // uniform over the block
+  const int64_t T0 = ab * BS;
   const int64_t T1 = T0 + BS < ntask ? T0 + BS : ntask;
   if (threadIdx.x == 0) {
     const int jf = L.bond_i[W.ang[T0].x], jl = L.bond_i[W.ang[T1 - 1].x];
@@ -248,6 +250,8 @@ __global__ __launch_bounds__(BS) void k_torsions(const DevParams* __restrict__ P
                                                  double* __restrict__ energies) {
   const int64_t ntask = W.off_tor[L.nbond];
   double etor = 0.0, econj = 0.0;
+  // grid-stride in plain block order: tasks running together are spread over
+  // the system, so their atomic adds rarely meet on one address
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ntask;
        t += (int64_t)gridDim.x * blockDim.x) {
     const int4 q = W.tor[t];
@@ -272,8 +276,10 @@ __global__ __launch_bounds__(BS) void k_hbonds(const DevParams* __restrict__ P, 
   const int64_t ntask = W.off_don[L.nbond];
   double ehb = 0.0;
   unsigned long long nhb = 0;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ntask;
-       t += (int64_t)gridDim.x * blockDim.x) {
+  // one task per thread; XCD k takes the k-th eighth of the blocks with work
+  const int64_t ab = xcd_active_block((ntask + BS - 1) / BS);
+  const int64_t t = ab * BS + threadIdx.x;
+  if (ab >= 0 && t < ntask) {
     const int ex = W.don[t];
     const int h = L.bond_i[ex], X = L.bond_j[ex];
     const int th = L.type_s[h], tx = L.type_s[X];
@@ -883,8 +889,9 @@ __global__ __launch_bounds__(BS) void k_nb_reduce(Grid g, Lists L, Work W) {
 // ---------------------------------------------------------------------------
 // (10)-(13) backward, one thread per atom
 __global__ __launch_bounds__(BS) void k_back_s(Lists L, Work W) {
-  const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
-  if (i < L.n) back_s_atom(L, W, (int)i);
+  const int64_t t = xcd_block() * blockDim.x + threadIdx.x;
+  const int64_t i = t >> 2;
+  if (i < L.n) back_s_atom<4>(L, W, (int)i, (int)(t & 3));
 }
 
 __global__ __launch_bounds__(BS) void k_back_corr(const DevParams* __restrict__ P, Lists L, Work W) {
@@ -931,13 +938,6 @@ const char* const kKernelNames[KID_COUNT] = {
     "bondtest", "compact", "mirror", "zero", "gather_q", "bo_prime", "delta_prime", "bo_corr", "atom_state",
     "atom_energy", "tasks", "angles", "torsions", "hbonds", "hb_acceptors", "nonbonded", "back_s", "back_corr",
     "back_dp", "forces", "batch", "nb_reduce", "nb_energy"};
-
-// grid of a grid-stride task kernel: enough blocks to fill the chip, no more
-// than the task bound needs
-static unsigned task_grid(int64_t bound) {
-  const int64_t b = (bound + BS - 1) / BS;
-  return (unsigned)(b < 1 ? 1 : (b > 8192 ? 8192 : b));
-}
 
 int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, const double* q,
                   hipStream_t side, hipEvent_t ev_fork, hipEvent_t ev_join, double* forces,
@@ -1012,15 +1012,16 @@ int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, co
   scan_i32(W.cnt_don, W.off_don, nb + 1, sc, st);
   pf.end(st);
   LAUNCH(KID_TASKS, k_tasks<true>, gridb, blk, 0, st, P, L, W);
-  const dim3 gt(task_grid(L.bound_tor));
-  LAUNCH(KID_ANGLES, k_angles, dim3((unsigned)std::max<int64_t>((L.bound_ang + BS - 1) / BS, 1)), blk, 0,
+  const int64_t bt = (L.bound_tor + BS - 1) / BS;
+  const dim3 gt((unsigned)(bt < 1 ? 1 : (bt > 8192 ? 8192 : bt)));
+  LAUNCH(KID_ANGLES, k_angles, dim3(xcd_grid((L.bound_ang + BS - 1) / BS)), blk, 0,
          st, P, L, W, energies);
   LAUNCH(KID_TORSIONS, k_torsions, gt, blk, 0, st, P, L, W, energies);
-  LAUNCH(KID_HBONDS, k_hbonds, dim3(task_grid(L.bound_don)), blk, 0, st, P, g, L, W, energies);
+  LAUNCH(KID_HBONDS, k_hbonds, dim3(xcd_grid((L.bound_don + BS - 1) / BS)), blk, 0, st, P, g, L, W, energies);
   LAUNCH(KID_HB_ACC, k_hb_acceptors, dim3(xcd_grid(nblk(n, BS / HB_GROUP))), blk, 0, st, P, g, L, W);
   (void)hipMemcpyAsync(W.counters, W.off_ang + nb, sizeof(int32_t), hipMemcpyDeviceToDevice, st);
   (void)hipMemcpyAsync(W.counters + 1, W.off_tor + nb, sizeof(int32_t), hipMemcpyDeviceToDevice, st);
-  LAUNCH(KID_BACK_S, k_back_s, grid, blk, 0, st, L, W);
+  LAUNCH(KID_BACK_S, k_back_s, dim3(xcd_grid(nblk(4 * n, BS))), blk, 0, st, L, W);
   LAUNCH(KID_BACK_CORR, k_back_corr, grid_e, blk, 0, st, P, L, W);
   LAUNCH(KID_BACK_DP, k_back_dp, grid, blk, 0, st, L, W);
   // join: the force gather reads the nonbonded forces

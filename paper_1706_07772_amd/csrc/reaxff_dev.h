@@ -181,6 +181,9 @@ struct Work {
   int32_t* don;      // entry h->X
   DonRec* donrec;    // per donor task: what the acceptor side reads of h->X
   int2* don_rng;     // [n] each atom's donor tasks [x, y)
+  // [n] what other atoms' terms read of atom j, in one 32-byte record:
+  // (S, Delta - Dlp, Dang, prod W); null: read from ast
+  double4* nv;
   int64_t cap_ang, cap_tor, cap_don;
   // half nonbonded evaluation: per-cell partial forces on the upper stencil
   // ([cell][NB_HALF_CAP][3]) and per-cell chunk bases relative to the cell's
@@ -269,6 +272,18 @@ __host__ __device__ __forceinline__ unsigned xcd_grid(int64_t nblocks) {
 }
 __device__ __forceinline__ int64_t xcd_block() {
   return (int64_t)(blockIdx.x % NXCD) * (gridDim.x / NXCD) + blockIdx.x / NXCD;
+}
+
+// Blocks over work whose size A is known only on the device, on a grid sized
+// by an upper bound (a multiple of NXCD blocks, at least A): XCD k takes the
+// contiguous active blocks [k ceil(A/NXCD), (k+1) ceil(A/NXCD)), so each
+// XCD's L2 sees one region of the cell-sorted data and every XCD gets an
+// equal share.  -1: no work for this block.
+__device__ __forceinline__ int64_t xcd_active_block(int64_t A) {
+  const int64_t per = (A + NXCD - 1) / NXCD;
+  const int64_t j = blockIdx.x / NXCD;
+  const int64_t a = (int64_t)(blockIdx.x % NXCD) * per + j;
+  return j < per && a < A ? a : -1;
 }
 
 __device__ __forceinline__ double r2_of(double dx, double dy, double dz) {

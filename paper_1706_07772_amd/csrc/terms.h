@@ -309,24 +309,38 @@ __device__ __forceinline__ void atom_state_atom(const DevParams* __restrict__ P,
   st.fc = 1.0 / (1.0 + ec);
   st.dfc = -P->p_coa2 * ec * st.fc * st.fc;
   W.ast[i] = st;
+  if (W.nv) W.nv[i] = make_double4(st.S, st.Delta - st.Dlp, st.Dang, st.prod * st.W);
+}
+
+// what a term centred elsewhere reads of atom j (S, Delta - Dlp, Dang,
+// prod W): the compact record when there is one
+__device__ __forceinline__ double4 nview(const Work& W, int j) {
+  if (W.nv) return W.nv[j];
+  const AtomState& s = W.ast[j];
+  return make_double4(s.S, s.Delta - s.Dlp, s.Dang, s.prod * s.W);
 }
 
 // (5) bond energy (once per bond, from its lower-index entry), lone pair,
 //     over- and under-coordination of atom i; adds the scalar adjoints to i's
 //     own entries and sets gS[i], gSig[i].  e[0..3] += bond, lp, over, under.
+//     G = 4: the four lanes of an aligned group share atom i, lane sub taking
+//     entries sub, sub + 4, ...; the sums are combined across the group and
+//     the atom's own terms are added by lane 0 only.
+template <int G = 1>
 __device__ __forceinline__ void atom_energy_atom(const DevParams* __restrict__ P, const Lists& L,
-                                                 const Work& W, int i, double e[4]) {
+                                                 const Work& W, int i, double e[4], int sub = 0) {
+  static_assert(G == 1 || G == 4, "one lane or a quad per atom");
   const int ti = L.type_s[i];
   const AtomP& a = P->atom[ti];
   const AtomState st = W.ast[i];
   double sumpi = 0.0, sumov = 0.0, ebond = 0.0;
-  for (int e = L.bond_off[i]; e < L.bond_off[i + 1]; ++e) {
+#pragma unroll 4
+  for (int e = L.bond_off[i] + sub; e < L.bond_off[i + 1]; e += G) {
     const int j = L.bond_j[e];
     const int tj = L.type_s[j];
     const PairP& p = P->pair[ti * NT + tj];
     const double4 b = W.bo[e];
-    const AtomState sj = W.ast[j];
-    sumpi += (sj.Delta - sj.Dlp) * (b.y + b.z);
+    sumpi += nview(W, j).y * (b.y + b.z);
     sumov += p.p_ovun1 * p.D_s * b.x;
     if (i < j) {
       const double sig = b.w;
@@ -340,6 +354,10 @@ __device__ __forceinline__ void atom_energy_atom(const DevParams* __restrict__ P
       gb.z += -p.D_pp - dsig;
       W.gbo[e] = gb;
     }
+  }
+  if constexpr (G == 4) {
+    sumpi = quad_sum(sumpi);
+    sumov = quad_sum(sumov);
   }
   // lone pair
   const double e75 = exp_c(-75.0 * st.Dlp);
@@ -368,20 +386,21 @@ __device__ __forceinline__ void atom_energy_atom(const DevParams* __restrict__ P
   const double dDlpc_dsig = st.Dlp * P->p_ovun3 * P->p_ovun4 * ep4 / (DD * DD);
   const double gSig = -a.p_ovun5 * (1.0 - e6) * su * dt8 + gL * dDlpc_dsig;
   const double gRso = R * so;
-  for (int e = L.bond_off[i]; e < L.bond_off[i + 1]; ++e) {
+#pragma unroll 4
+  for (int e = L.bond_off[i] + sub; e < L.bond_off[i + 1]; e += G) {
     const int j = L.bond_j[e];
     const PairP& p = P->pair[ti * NT + L.type_s[j]];
-    const AtomState sj = W.ast[j];
     double4 gb = W.gbo[e];
     gb.x += p.p_ovun1 * p.D_s * gRso;
-    const double w = gSig * (sj.Delta - sj.Dlp);
+    const double w = gSig * nview(W, j).y;
     gb.y += w;
     gb.z += w;
     W.gbo[e] = gb;
   }
+  e[0] += ebond;
+  if (sub != 0) return;
   W.gS[i] = dElp_dDlp * (-st.dnlp) + gL * (1.0 + st.dnlp / DD);
   W.gSig[i] = gSig;
-  e[0] += ebond;
   e[1] += elp;
   e[2] += eover;
   e[3] += eunder;
@@ -408,7 +427,7 @@ __device__ __forceinline__ AngOut angle_eval(const DevParams* __restrict__ P, co
   const AtomState& st = W.ast[j];
   const double4 ru = W.bd[u], rv = W.bd[v];
   const double B1 = W.bo[u].x - thb, B2 = W.bo[v].x - thb;
-  const double Si = W.ast[i].S, Sk = W.ast[k].S;
+  const double Si = nview(W, i).x, Sk = nview(W, k).x;
   // angle between r_ji (= bd[u]) and r_jk (= bd[v])
   const double il1 = 1.0 / ru.w, il2 = 1.0 / rv.w;
   double c = (ru.x * rv.x + ru.y * rv.y + ru.z * rv.z) * il1 * il2;
@@ -489,7 +508,7 @@ __device__ __forceinline__ void torsion_eval(const DevParams* __restrict__ P, co
   const double4 bjk = W.bo[ejk];
   const double bij = W.bo[eji].x, bkl = W.bo[ekl].x;
   // f11 of the central bond
-  const double Dsum = W.ast[j].Dang + W.ast[k].Dang;
+  const double Dsum = nview(W, j).z + nview(W, k).z;
   const double et3 = exp_c(-P->p_tor3 * Dsum), et4 = exp_c(P->p_tor4 * Dsum);
   const double f11d = 1.0 + et3 + et4;
   const double f11 = (2.0 + et3) / f11d;
@@ -576,17 +595,20 @@ struct HbTerm {
 __device__ __forceinline__ HbTerm hb_term(const HbP& hp, double bo, double4 rx, double dx, double dy,
                                           double dz) {
   HbTerm o;
-  const double ilx = 1.0 / rx.w;
-  const double rz = sqrt(dx * dx + dy * dy + dz * dz);
-  const double ilz = 1.0 / rz;
+  // reciprocals and the length from rcp_f / rsqrt (a few ulp), not IEEE
+  // division and square root
+  const double ilx = rcp_f(rx.w);
+  const double ilz = rsqrt(dx * dx + dy * dy + dz * dz);
+  const double rz = (dx * dx + dy * dy + dz * dz) * ilz;
+  const double ir0 = rcp_f(hp.r0hb);
   const double c = (rx.x * dx + rx.y * dy + rx.z * dz) * ilx * ilz;
   const double hc = 0.5 * (1.0 - c);
   const double s4 = hc * hc;
   const double ds4 = -hc;                 // d s4 / d c
   const double eb = exp_c(-hp.p_hb2 * bo);
   const double fbo = 1.0 - eb, dfbo = hp.p_hb2 * eb;
-  const double fr = exp_c(-hp.p_hb3 * (hp.r0hb * ilz + rz / hp.r0hb - 2.0));
-  const double dfr = fr * (-hp.p_hb3) * (-hp.r0hb * ilz * ilz + 1.0 / hp.r0hb);
+  const double fr = exp_c(-hp.p_hb3 * (hp.r0hb * ilz + rz * ir0 - 2.0));
+  const double dfr = fr * (-hp.p_hb3) * (-hp.r0hb * ilz * ilz + ir0);
   o.E = hp.p_hb1 * fbo * fr * s4;
   o.dE_dbo = hp.p_hb1 * dfbo * fr * s4;
   const double gc = hp.p_hb1 * fbo * fr * ds4;
@@ -653,17 +675,26 @@ __device__ __forceinline__ NbP nb_params(const PairP& p) {
 // (10) total dE/dS of atom i: own terms, coalition terms of angles centred on
 //      neighbours (stored in the neighbour's entry), the Sigma_pi term of the
 //      neighbours' over/under-coordination, and SBO's valence term
-__device__ __forceinline__ void back_s_atom(const Lists& L, const Work& W, int i) {
-  const AtomState st = W.ast[i];
-  double g = W.gS[i];
+//      (G = 4: a quad of lanes per atom, as in atom_energy_atom)
+template <int G = 1>
+__device__ __forceinline__ void back_s_atom(const Lists& L, const Work& W, int i, int sub = 0) {
+  static_assert(G == 1 || G == 4, "one lane or a quad per atom");
+  double g = 0.0;
   double gsig = 0.0;
-  for (int e = L.bond_off[i]; e < L.bond_off[i + 1]; ++e) {
+  for (int e = L.bond_off[i] + sub; e < L.bond_off[i + 1]; e += G) {
     const int m = L.bond_mir[e];
     const int j = L.bond_j[e];
     g += W.gbo[m].w;
     const double4 b = W.bo[e];
     gsig += W.gSig[j] * (b.y + b.z);
   }
+  if constexpr (G == 4) {
+    g = quad_sum(g);
+    gsig = quad_sum(gsig);
+  }
+  if (sub != 0) return;
+  const AtomState st = W.ast[i];
+  g += W.gS[i];
   g += (1.0 + st.dnlp) * gsig;
   // the angle terms accumulated dE/dSBO2; convert to dE/dSBO for the next stage
   const double gsbo = W.gSBO[i] * st.dSBO2;
@@ -686,12 +717,11 @@ __device__ __forceinline__ void back_corr_entry(const DevParams* __restrict__ P,
     const int ta = lo ? ti : tj, tb = lo ? tj : ti;
     const double4 bp = W.bop[e];
     const double4 bo = W.bo[e];
-    const AtomState sa = W.ast[a], sb = W.ast[b];
+    const double pwa = nview(W, a).w, pwb = nview(W, b).w;   // prod W of a and b
     const double4 ga = W.gbo[ea], gb = W.gbo[eb];
     const double gsa = W.gSBO[a], gsb = W.gSBO[b];
     const double b2 = bo.x * bo.x, b7 = b2 * b2 * b2 * bo.x;
-    const double gBO = ga.x + gb.x + W.gStot[a] + W.gStot[b] +
-                       8.0 * b7 * (gsa * sa.prod * sa.W + gsb * sb.prod * sb.W);
+    const double gBO = ga.x + gb.x + W.gStot[a] + W.gStot[b] + 8.0 * b7 * (gsa * pwa + gsb * pwb);
     const double gBOp = ga.y + gb.y + gsa + gsb;
     const double gBOpp = ga.z + gb.z + gsa + gsb;
     const Corr c = correction(P, bp.w, P->atom[ta].val, P->atom[tb].val, W.dp[a], W.dp[b],
