@@ -246,16 +246,83 @@ __global__ __launch_bounds__(BS) void k_angles(const DevParams* __restrict__ P, 
 // ---------------------------------------------------------------------------
 // (7) torsion and 4-body conjugation: one thread per torsion task
 // ---------------------------------------------------------------------------
+// The tasks are ordered by the central bond's lower atom j, so the BS tasks
+// of a block touch one contiguous range of j's entries (j->i and j->k) and
+// of j atoms.  Those adjoints are summed in LDS and added to memory once per
+// block, with atomics (other blocks reach the same entries as the far atom k
+// of their central bond); the k side (entry k->l, Delta_k) goes straight to
+// global atomics.  Blocks run in plain order, so the global atomics of
+// blocks running together fall on separate parts of the system.
+constexpr int TOR_CAPE = 1024;   // j-side entries per block held in LDS
+constexpr int TOR_CAPC = 512;    // j atoms per block held in LDS
+
 __global__ __launch_bounds__(BS) void k_torsions(const DevParams* __restrict__ P, Lists L, Work W,
                                                  double* __restrict__ energies) {
+  __shared__ double se[TOR_CAPE][5];   // gvec x, y, z, gbo.x, gbo.y per entry
+  __shared__ double sj[TOR_CAPC];      // gS per j atom
+  __shared__ int range[3];
   const int64_t ntask = W.off_tor[L.nbond];
   double etor = 0.0, econj = 0.0;
-  // grid-stride in plain block order: tasks running together are spread over
-  // the system, so their atomic adds rarely meet on one address
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ntask;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    const int4 q = W.tor[t];
-    torsion_eval(P, L, W, q.x, q.y, q.z, etor, econj);
+  for (int64_t T0 = (int64_t)blockIdx.x * BS; T0 < ntask; T0 += (int64_t)gridDim.x * BS) {
+    const int64_t T1 = T0 + BS < ntask ? T0 + BS : ntask;
+    __syncthreads();   // the previous pass's flush is done
+    if (threadIdx.x == 0) {
+      const int jf = L.bond_i[W.tor[T0].x], jl = L.bond_i[W.tor[T1 - 1].x];
+      range[0] = jf;
+      range[1] = L.bond_off[jf];
+      range[2] = L.bond_off[jl + 1];
+    }
+    for (int k = threadIdx.x; k < TOR_CAPE; k += BS)
+      for (int c = 0; c < 5; ++c) se[k][c] = 0.0;
+    for (int k = threadIdx.x; k < TOR_CAPC; k += BS) sj[k] = 0.0;
+    __syncthreads();
+    const int jf = range[0], E0 = range[1], E1 = range[2];
+    const int64_t t = T0 + threadIdx.x;
+    if (t < T1) {
+      const int4 q = W.tor[t];
+      const int ejk = q.x, eji = q.y, ekl = q.z;
+      const TorOut o = torsion_terms(P, L, W, ejk, eji, ekl, etor, econj);
+      const int j = L.bond_i[ejk], k = L.bond_j[ejk];
+      const int lji = eji - E0, ljk = ejk - E0, lj = j - jf;
+      if (lji < TOR_CAPE) {
+        atomicAdd(&se[lji][0], o.gji.x);
+        atomicAdd(&se[lji][1], o.gji.y);
+        atomicAdd(&se[lji][2], o.gji.z);
+        atomicAdd(&se[lji][3], o.gBij);
+      } else {
+        atomic_add3(&W.gvec[eji], o.gji);
+        atomicAdd(&W.gbo[eji].x, o.gBij);
+      }
+      if (ljk < TOR_CAPE) {
+        atomicAdd(&se[ljk][0], o.gjk.x);
+        atomicAdd(&se[ljk][1], o.gjk.y);
+        atomicAdd(&se[ljk][2], o.gjk.z);
+        atomicAdd(&se[ljk][3], o.gBjk);
+        atomicAdd(&se[ljk][4], o.gPjk);
+      } else {
+        atomic_add3(&W.gvec[ejk], o.gjk);
+        atomicAdd(&W.gbo[ejk].x, o.gBjk);
+        atomicAdd(&W.gbo[ejk].y, o.gPjk);
+      }
+      if (lj < TOR_CAPC) atomicAdd(&sj[lj], o.gD);
+      else atomicAdd(&W.gS[j], o.gD);
+      atomic_add3(&W.gvec[ekl], o.gkl);
+      atomicAdd(&W.gbo[ekl].x, o.gBkl);
+      atomicAdd(&W.gS[k], o.gD);
+    }
+    __syncthreads();
+    const int ne = E1 - E0 < TOR_CAPE ? E1 - E0 : TOR_CAPE;
+    for (int k = threadIdx.x; k < ne; k += BS) {
+      const int e = E0 + k;
+      if (se[k][0] != 0.0 || se[k][1] != 0.0 || se[k][2] != 0.0)
+        atomic_add3(&W.gvec[e], se[k][0], se[k][1], se[k][2]);
+      if (se[k][3] != 0.0) atomicAdd(&W.gbo[e].x, se[k][3]);
+      if (se[k][4] != 0.0) atomicAdd(&W.gbo[e].y, se[k][4]);
+    }
+    const int jl = L.bond_i[W.tor[T1 - 1].x];
+    const int nc = jl - jf + 1 < TOR_CAPC ? jl - jf + 1 : TOR_CAPC;
+    for (int k = threadIdx.x; k < nc; k += BS)
+      if (sj[k] != 0.0) atomicAdd(&W.gS[jf + k], sj[k]);
   }
   block_add<BS>(etor, energies + E_TOR);
   block_add<BS>(econj, energies + E_CONJ);

@@ -498,9 +498,16 @@ __device__ __forceinline__ AngOut angle_eval(const DevParams* __restrict__ P, co
 // (7) one torsion i-j-k-l (entries ejk = j->k, eji = j->i, ekl = k->l):
 //     energies into etor/econj, adjoints deposited with atomic adds
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void torsion_eval(const DevParams* __restrict__ P, const Lists& L,
-                                             const Work& W, int ejk, int eji, int ekl, double& etor,
-                                             double& econj) {
+// adjoints of one torsion term: gradients of the three entries' vectors
+// (entry j->i, j->k, k->l), of their bond orders, and of Delta_j, Delta_k
+struct TorOut {
+  double3 gji, gjk, gkl;
+  double gBij, gBjk, gPjk, gBkl, gD;
+};
+
+__device__ __forceinline__ TorOut torsion_terms(const DevParams* __restrict__ P, const Lists& L,
+                                                const Work& W, int ejk, int eji, int ekl, double& etor,
+                                                double& econj) {
   const double thb = P->thb_cut, pt2 = P->p_tor2, pc2 = P->p_cot2;
   const int j = L.bond_i[ejk], k = L.bond_j[ejk], i = L.bond_j[eji], l = L.bond_j[ekl];
   const int ti = L.type_s[i], tj = L.type_s[j], tk = L.type_s[k], tl = L.type_s[l];
@@ -572,15 +579,33 @@ __device__ __forceinline__ void torsion_eval(const DevParams* __restrict__ P, co
   const double3 gb2 = axpy(gc2, dc2_b2, axpy(gc1, dc1_b2, scale(gcw, dcw_b2)));
   const double3 gb3 = axpy(gc2, dc2_b3, scale(gcw, dcw_b3));
   // entry j->i holds r_ji = -b1; j->k holds b2; k->l holds b3
-  atomic_add3(&W.gvec[eji], -gb1.x, -gb1.y, -gb1.z);
-  atomic_add3(&W.gvec[ejk], gb2);
-  atomic_add3(&W.gvec[ekl], gb3);
-  atomicAdd(&W.gbo[eji].x, gBij);
-  atomicAdd(&W.gbo[ejk].x, gBjk);
-  atomicAdd(&W.gbo[ejk].y, gPjk);
-  atomicAdd(&W.gbo[ekl].x, gBkl);
-  atomicAdd(&W.gS[j], gD);
-  atomicAdd(&W.gS[k], gD);
+  TorOut o;
+  o.gji = make_double3(-gb1.x, -gb1.y, -gb1.z);
+  o.gjk = gb2;
+  o.gkl = gb3;
+  o.gBij = gBij;
+  o.gBjk = gBjk;
+  o.gPjk = gPjk;
+  o.gBkl = gBkl;
+  o.gD = gD;
+  return o;
+}
+
+// one torsion, its adjoints added with global atomics
+__device__ __forceinline__ void torsion_eval(const DevParams* __restrict__ P, const Lists& L,
+                                             const Work& W, int ejk, int eji, int ekl, double& etor,
+                                             double& econj) {
+  const TorOut o = torsion_terms(P, L, W, ejk, eji, ekl, etor, econj);
+  const int j = L.bond_i[ejk], k = L.bond_j[ejk];
+  atomic_add3(&W.gvec[eji], o.gji);
+  atomic_add3(&W.gvec[ejk], o.gjk);
+  atomic_add3(&W.gvec[ekl], o.gkl);
+  atomicAdd(&W.gbo[eji].x, o.gBij);
+  atomicAdd(&W.gbo[ejk].x, o.gBjk);
+  atomicAdd(&W.gbo[ejk].y, o.gPjk);
+  atomicAdd(&W.gbo[ekl].x, o.gBkl);
+  atomicAdd(&W.gS[j], o.gD);
+  atomicAdd(&W.gS[k], o.gD);
 }
 
 // ---------------------------------------------------------------------------
