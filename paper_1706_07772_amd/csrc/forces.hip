@@ -390,51 +390,82 @@ __global__ __launch_bounds__(BS) void k_hbonds(const DevParams* __restrict__ P, 
 }
 
 // Acceptor side: F_Z = -dE/dx_Z = -sum dE/d(x_Z - x_h) over the donors H of
-// Z's acceptor row.  Four acceptors per wavefront, 16 lanes each, one H per
-// lane; each donor bond H-X is read from its packed record; the 16-lane sums
-// are written once per acceptor (no atomics).
+// Z's acceptor row.  Four acceptors per wavefront, one 16-lane row each.  The
+// row's lanes first list the (H, donor task) pairs of Z's acceptor row in LDS
+// (most H atoms have no donor bond), then share the list evenly, so the
+// lanes evaluate terms instead of idling; a list longer than the LDS slot is
+// walked directly.  Each donor bond H-X is read from its packed record; the
+// row sums are written once per acceptor (no atomics).
 constexpr int HB_GROUP = 16;
+constexpr int HB_PACK = 128;   // listed (H, task) pairs per acceptor
 
 __global__ __launch_bounds__(BS) void k_hb_acceptors(const DevParams* __restrict__ P, Grid g, Lists L,
                                                      Work W) {
+  __shared__ int2 pk[BS / HB_GROUP][HB_PACK];
   const int lane = threadIdx.x & 63, sub = lane & (HB_GROUP - 1);
+  int2* __restrict__ mylist = pk[threadIdx.x / HB_GROUP];
   const int64_t z = (xcd_block() * BS + threadIdx.x) / HB_GROUP;
-  const int cnt = z < L.n ? L.ha_cnt[z] : 0;
+  const int cnt = z < L.n ? L.ha_cnt[z] : 0;   // uniform over the row
   double3 fz = make_double3(0.0, 0.0, 0.0);
-  if (cnt > 0) {
+  const int32_t* __restrict__ row = L.ha_j + z * (int64_t)L.ha_w;
+  // this lane's pairs, and their offset in the row's list
+  int mine = 0;
+  for (int k = sub; k < cnt; k += HB_GROUP) {
+    const int2 tr = W.don_rng[row[k]];
+    mine += tr.y - tr.x;
+  }
+  int incl = mine;
+  for (int off = 1; off < HB_GROUP; off <<= 1) {
+    const int v = __shfl_up(incl, off, HB_GROUP);
+    if (sub >= off) incl += v;
+  }
+  const int total = __shfl(incl, HB_GROUP - 1, HB_GROUP);
+  auto term = [&](int h, int t, double4 xz, int tz) {
+    const DonRec d = W.donrec[t];
+    if (d.X == (int)z) return;
+    const int th = L.type_s[h];
+    const double4 xh = L.xs[h];
+    double dx = xz.x - xh.x, dy = xz.y - xh.y, dz = xz.z - xh.z;   // x_Z - x_h
+    if (g.periodic) {
+      dx = min_image(dx, g.L[0], g.invL[0]);
+      dy = min_image(dy, g.L[1], g.invL[1]);
+      dz = min_image(dz, g.L[2], g.invL[2]);
+    }
+    const HbP& hp = P->hb[(d.tX * NT + th) * NT + tz];
+    const HbTerm o = hb_term(hp, d.bo, d.bd, dx, dy, dz);
+    fz.x -= o.g_rz.x;
+    fz.y -= o.g_rz.y;
+    fz.z -= o.g_rz.z;
+  };
+  if (total > 0) {
     const int tz = L.type_s[z];
     const double4 xz = L.xs[z];
-    const int32_t* __restrict__ row = L.ha_j + z * (int64_t)L.ha_w;
-    for (int k = sub; k < cnt; k += HB_GROUP) {
-      const int h = row[k];
-      const int2 tr = W.don_rng[h];
-      const int t0 = tr.x, t1 = tr.y;
-      if (t0 == t1) continue;
-      const int th = L.type_s[h];
-      const double4 xh = L.xs[h];
-      double dx = xz.x - xh.x, dy = xz.y - xh.y, dz = xz.z - xh.z;   // x_Z - x_h
-      if (g.periodic) {
-        dx = min_image(dx, g.L[0], g.invL[0]);
-        dy = min_image(dy, g.L[1], g.invL[1]);
-        dz = min_image(dz, g.L[2], g.invL[2]);
+    if (total <= HB_PACK) {
+      int pos = incl - mine;
+      for (int k = sub; k < cnt; k += HB_GROUP) {
+        const int h = row[k];
+        const int2 tr = W.don_rng[h];
+        for (int t = tr.x; t < tr.y; ++t) mylist[pos++] = make_int2(h, t);
       }
-      for (int t = t0; t < t1; ++t) {
-        const DonRec d = W.donrec[t];
-        if (d.X == (int)z) continue;
-        const HbP& hp = P->hb[(d.tX * NT + th) * NT + tz];
-        const HbTerm o = hb_term(hp, d.bo, d.bd, dx, dy, dz);
-        fz.x -= o.g_rz.x;
-        fz.y -= o.g_rz.y;
-        fz.z -= o.g_rz.z;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int q = sub; q < total; q += HB_GROUP) {
+        const int2 ht = mylist[q];
+        term(ht.x, ht.y, xz, tz);
+      }
+    } else {
+      for (int k = sub; k < cnt; k += HB_GROUP) {
+        const int h = row[k];
+        const int2 tr = W.don_rng[h];
+        for (int t = tr.x; t < tr.y; ++t) term(h, t, xz, tz);
       }
     }
   }
-  for (int off = HB_GROUP / 2; off > 0; off >>= 1) {
-    fz.x += __shfl_down(fz.x, off, HB_GROUP);
-    fz.y += __shfl_down(fz.y, off, HB_GROUP);
-    fz.z += __shfl_down(fz.z, off, HB_GROUP);
-  }
-  if (sub == 0 && cnt > 0) {
+  fz.x = row_sum_last(fz.x);
+  fz.y = row_sum_last(fz.y);
+  fz.z = row_sum_last(fz.z);
+  if (sub == HB_GROUP - 1 && total > 0) {
     double4 f = W.fhb[z];
     f.x += fz.x;
     f.y += fz.y;

@@ -241,6 +241,16 @@ __device__ __forceinline__ double quad_sum(double v) {
   return v;
 }
 
+// Sum over each 16-lane row, left in the row's last lane (15, 31, 47, 63);
+// every lane of a row must be active.
+__device__ __forceinline__ double row_sum_last(double v) {
+  v += dpp_d<0x111>(v);          // row_shr:1
+  v += dpp_d<0x112>(v);          // row_shr:2
+  v += dpp_d<0x114>(v);          // row_shr:4
+  v += dpp_d<0x118>(v);          // row_shr:8
+  return v;
+}
+
 // Sum over each half wavefront (lanes 0-31, 32-63), left in the half's last
 // lane (31, 63); other lanes hold partial sums.  Row shifts by 1, 2, 4, 8
 // make lane 15 of each 16-lane row the row's sum; the broadcast of lane 15 of
