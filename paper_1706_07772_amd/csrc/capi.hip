@@ -89,6 +89,9 @@ void fill_dev_params(const reaxff_params& p, const reaxff_cutoffs& c, DevParams&
     for (int j = 0; j < NT; ++j) {
       PairP& q = d.pair[i * NT + j];
       q.r_s = p.r_s[i][j]; q.r_p = p.r_p[i][j]; q.r_pp = p.r_pp[i][j];
+      q.ln_r_s = q.r_s > 0 ? std::log(q.r_s) : 0.0;
+      q.ln_r_p = q.r_p > 0 ? std::log(q.r_p) : 0.0;
+      q.ln_r_pp = q.r_pp > 0 ? std::log(q.r_pp) : 0.0;
       q.p_bo1 = p.p_bo1[i][j]; q.p_bo2 = p.p_bo2[i][j]; q.p_bo3 = p.p_bo3[i][j];
       q.p_bo4 = p.p_bo4[i][j]; q.p_bo5 = p.p_bo5[i][j]; q.p_bo6 = p.p_bo6[i][j];
       q.D_s = p.D_s[i][j]; q.D_p = p.D_p[i][j]; q.D_pp = p.D_pp[i][j];

@@ -31,7 +31,8 @@ struct PairP {
   double g3;                                // gamma^(-3)
   double e_core, a_core, inv_r_core;
   double reach2;                            // bond prefilter: raw BO' < bo_cut beyond it
-  double pad;
+  double ln_r_s, ln_r_p, ln_r_pp;           // logs of the bond radii (0 when off)
+  double pad[2];
 };
 
 struct AtomP {

@@ -125,11 +125,13 @@ __device__ __forceinline__ double3 add3(double3 a, double3 b) { return make_doub
 __device__ __forceinline__ void atomic_add3(double4* p, double3 v) { atomic_add3(p, v.x, v.y, v.z); }
 
 // raw uncorrected bond order sum of sigma, pi and pi-pi (the bond-list test)
+// ((r / r_x)^p as exp(p (log r - log r_x)): one log for the three terms)
 __device__ __forceinline__ double bo_raw(const PairP& p, double r, double bo_cut) {
   double s = 0.0, pi = 0.0, pp = 0.0;
-  if (p.r_s > 0.0) s = (1.0 + bo_cut) * exp_c(p.p_bo1 * pow_c(r / p.r_s, p.p_bo2));
-  if (p.r_p > 0.0) pi = exp_c(p.p_bo3 * pow_c(r / p.r_p, p.p_bo4));
-  if (p.r_pp > 0.0) pp = exp_c(p.p_bo5 * pow_c(r / p.r_pp, p.p_bo6));
+  const double lr = log_f(r);
+  if (p.r_s > 0.0) s = (1.0 + bo_cut) * exp_c(p.p_bo1 * exp_c(p.p_bo2 * (lr - p.ln_r_s)));
+  if (p.r_p > 0.0) pi = exp_c(p.p_bo3 * exp_c(p.p_bo4 * (lr - p.ln_r_p)));
+  if (p.r_pp > 0.0) pp = exp_c(p.p_bo5 * exp_c(p.p_bo6 * (lr - p.ln_r_pp)));
   return s + pi + pp;
 }
 
@@ -160,19 +162,20 @@ __device__ __forceinline__ void bo_prime_entry(const DevParams* __restrict__ P, 
     W.bd[e] = lo ? make_double4(dx, dy, dz, r) : make_double4(-dx, -dy, -dz, r);
     const PairP& p = P->pair[ti * NT + L.type_s[j]];
     double s = 0.0, ds = 0.0, pi = 0.0, dpi = 0.0, pp = 0.0, dpp = 0.0;
-    const double ir = 1.0 / r;
+    const double ir = rcp_f(r);
+    const double lr = log_f(r);   // (r / r_x)^p = exp(p (log r - log r_x))
     if (p.r_s > 0.0) {
-      const double x = pow_c(r / p.r_s, p.p_bo2);
+      const double x = exp_c(p.p_bo2 * (lr - p.ln_r_s));
       s = (1.0 + bo_cut) * exp_c(p.p_bo1 * x);
       ds = s * p.p_bo1 * p.p_bo2 * x * ir;
     }
     if (p.r_p > 0.0) {
-      const double x = pow_c(r / p.r_p, p.p_bo4);
+      const double x = exp_c(p.p_bo4 * (lr - p.ln_r_p));
       pi = exp_c(p.p_bo3 * x);
       dpi = pi * p.p_bo3 * p.p_bo4 * x * ir;
     }
     if (p.r_pp > 0.0) {
-      const double x = pow_c(r / p.r_pp, p.p_bo6);
+      const double x = exp_c(p.p_bo6 * (lr - p.ln_r_pp));
       pp = exp_c(p.p_bo5 * x);
       dpp = pp * p.p_bo5 * p.p_bo6 * x * ir;
     }
