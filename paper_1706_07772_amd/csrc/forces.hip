@@ -360,9 +360,9 @@ __global__ __launch_bounds__(BS) void k_hbonds(const DevParams* __restrict__ P, 
     for (int s = 0; s < nz; ++s) {
       const int Z = zrow[s];
       if (Z == X) continue;
-      const HbP& hp = P->hb[(tx * NT + th) * NT + L.type_s[Z]];
+      const double4 xz = L.xs[Z];   // position and type
+      const HbP& hp = P->hb[(tx * NT + th) * NT + (int)xz.w];
       ++nhb;
-      const double4 xz = L.xs[Z];
       double dx = xz.x - xh.x, dy = xz.y - xh.y, dz = xz.z - xh.z;
       if (g.periodic) {
         dx = min_image(dx, g.L[0], g.invL[0]);
@@ -423,8 +423,8 @@ __global__ __launch_bounds__(BS) void k_hb_acceptors(const DevParams* __restrict
   auto term = [&](int h, int t, double4 xz, int tz) {
     const DonRec d = W.donrec[t];
     if (d.X == (int)z) return;
-    const int th = L.type_s[h];
-    const double4 xh = L.xs[h];
+    const double4 xh = L.xs[h];   // position and type
+    const int th = (int)xh.w;
     double dx = xz.x - xh.x, dy = xz.y - xh.y, dz = xz.z - xh.z;   // x_Z - x_h
     if (g.periodic) {
       dx = min_image(dx, g.L[0], g.invL[0]);
@@ -907,9 +907,9 @@ __global__ __launch_bounds__(NBH_BS) void k_nonbonded_half(const DevParams* __re
   __syncthreads();
   double* __restrict__ part = W.nbpart + (int64_t)c * 3 * NB_HALF_CAP;
   for (int t = tid; t < nup; t += NBH_BS) {
-    part[3 * t] = fax[t];
-    part[3 * t + 1] = fay[t];
-    part[3 * t + 2] = faz[t];
+    __builtin_nontemporal_store(fax[t], &part[3 * t]);   // streamed to the reduce
+    __builtin_nontemporal_store(fay[t], &part[3 * t + 1]);
+    __builtin_nontemporal_store(faz[t], &part[3 * t + 2]);
   }
   const double sv = block_sum<NBH_BS>(evdw), sq = block_sum<NBH_BS>(ecoul);
   if (tid == 0) W.nbe[c] = make_double2(sv, sq);

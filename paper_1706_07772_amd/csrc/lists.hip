@@ -266,7 +266,9 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
           const int k0 = readlane_i(kf, l);
           if (f) {
             const int k = k0 + __popcll(mf & below);
-            if (k < far_w) far_j[(int64_t)i * far_w + k] = slots ? slot : s;
+            // list rows are streamed out (non-temporal), keeping the
+            // stencil's positions in L2
+            if (k < far_w) __builtin_nontemporal_store(slots ? slot : s, &far_j[(int64_t)i * far_w + k]);
           }
           kf = writelane_i(k0 + __popcll(mf), l, kf);
           if (halfable) {
@@ -277,7 +279,7 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
             const int k1 = readlane_i(kc, l);
             if (b) {
               const int k = k1 + __popcll(mb & below);
-              if (k < cand_w) cand_j[(int64_t)i * cand_w + k] = s;
+              if (k < cand_w) __builtin_nontemporal_store(s, &cand_j[(int64_t)i * cand_w + k]);
             }
             kc = writelane_i(k1 + __popcll(mb), l, kc);
           }
@@ -285,7 +287,7 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
             const int k2 = readlane_i(kh, l);
             if (h) {
               const int k = k2 + __popcll(mh & below);
-              if (k < hb_w) hb_j[(int64_t)i * hb_w + k] = s;
+              if (k < hb_w) __builtin_nontemporal_store(s, &hb_j[(int64_t)i * hb_w + k]);
             }
             kh = writelane_i(k2 + __popcll(mh), l, kh);
           }
@@ -293,7 +295,7 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
             const int k3 = readlane_i(ka, l);
             if (ha) {
               const int k = k3 + __popcll(ma & below);
-              if (k < ha_w) ha_j[(int64_t)i * ha_w + k] = s;
+              if (k < ha_w) __builtin_nontemporal_store(s, &ha_j[(int64_t)i * ha_w + k]);
             }
             ka = writelane_i(k3 + __popcll(ma), l, ka);
           }
