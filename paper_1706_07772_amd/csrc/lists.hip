@@ -244,6 +244,14 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
         const double r2 = r2_of(dx, dy, dz);
         const bool f = valid && r2 <= rn2 && s != i;
         const unsigned long long mf = ballot(r2 <= rn2) & ballot(s != i) & vmask;
+        // far entries before the centre's own slot: every entry of the
+        // batches below it, plus the lanes below it in the batch holding it
+        // (rows fill in slot order), so the count is set once per centre
+        const int ol = own0 + ig + l - b0;   // the own slot's lane (uniform)
+        if (halfable && (unsigned)ol < 64u) {
+          const unsigned long long low = ol == 0 ? 0ull : (~0ull >> (64 - ol));
+          klo = writelane_i(readlane_i(kf, l) + __popcll(mf & low), l, klo);
+        }
         if (mf) {
           // centre type (uniform) and the bond reach against it
           const int ti = readlane_i(tmine, l);
@@ -271,10 +279,6 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
             if (k < far_w) __builtin_nontemporal_store(slots ? slot : s, &far_j[(int64_t)i * far_w + k]);
           }
           kf = writelane_i(k0 + __popcll(mf), l, kf);
-          if (halfable) {
-            const unsigned long long ml = mf & ballot(slot < own0 + ig + l);
-            klo = writelane_i(readlane_i(klo, l) + __popcll(ml), l, klo);
-          }
           if (mb) {
             const int k1 = readlane_i(kc, l);
             if (b) {
