@@ -110,6 +110,27 @@ def test_cluster_parity(ff, params, n, seed):
     _parity(ff, params, rs.cluster(n, seed=seed))
 
 
+def test_hydrogen_rich_cluster_parity(ff, params):
+    """An H/O-rich cluster (55% H, 35% O) with every bond order above 1e-6
+    a bond and every H-acceptor bond a donor bond: hundreds of acceptor rows
+    hold more (H, donor bond) pairs than the 128 the acceptor kernel lists in
+    LDS, so its direct walk runs beside the listed one; torsions are sparse
+    among many bonded atoms, so blocks of torsion tasks span many entries."""
+    s = rs.cluster(1500, seed=11, probs=(0.05, 0.55, 0.05, 0.35))
+    cut = dict(rs.DEFAULT_CUTOFFS, bo_cut=1e-6, hb_bo_cut=0.0)
+    _parity(ff, params, s, cut)
+    # (H, donor bond) pairs of each acceptor's row, from the oracle's lists
+    _, bonds, hb = Oracle(s, params, cut).lists()
+    typ = s.type
+    don = np.zeros(len(typ), np.int64)
+    m = (typ[bonds[:, 0]] == 1) & np.isin(typ[bonds[:, 1]], (2, 3))
+    np.add.at(don, bonds[m, 0], 1)
+    per = np.zeros(len(typ), np.int64)
+    np.add.at(per, hb[:, 1], don[hb[:, 0]])
+    print("acceptor rows over 128 pairs:", int((per > 128).sum()), "max", int(per.max()), flush=True)
+    assert (per > 128).sum() > 0
+
+
 def test_small_periodic_parity(ff, params):
     """870 atoms in a 20.7 A box: the cell grid has 4 cells per edge, so every cell is
     visited once (the stencil's wrap-around degenerate case)."""
