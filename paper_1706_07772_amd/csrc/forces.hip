@@ -907,9 +907,9 @@ __global__ __launch_bounds__(NBH_BS) void k_nonbonded_half(const DevParams* __re
   __syncthreads();
   double* __restrict__ part = W.nbpart + (int64_t)c * 3 * NB_HALF_CAP;
   for (int t = tid; t < nup; t += NBH_BS) {
-    __builtin_nontemporal_store(fax[t], &part[3 * t]);   // streamed to the reduce
-    __builtin_nontemporal_store(fay[t], &part[3 * t + 1]);
-    __builtin_nontemporal_store(faz[t], &part[3 * t + 2]);
+    part[3 * t] = fax[t];
+    part[3 * t + 1] = fay[t];
+    part[3 * t + 2] = faz[t];
   }
   const double sv = block_sum<NBH_BS>(evdw), sq = block_sum<NBH_BS>(ecoul);
   if (tid == 0) W.nbe[c] = make_double2(sv, sq);
