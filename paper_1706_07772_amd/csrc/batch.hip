@@ -307,15 +307,15 @@ __device__ __noinline__ void st_bo_prime(int n) {
   views(A, L, W);
   Grid g{};
   g.periodic = 0;
-  for (int i = threadIdx.x; i < n; i += BSZ) {
-    for (int e = b_off[i]; e < b_off[i + 1]; ++e) {
-      const int j = L.bond_j[e];
-      int m = e;
-      for (int f = b_off[j]; f < b_off[j + 1]; ++f)
-        if (L.bond_j[f] == i) m = f;
-      L.bond_mir[e] = m;
-    }
-    bo_prime_atom(A.P, g, L, W, i);
+  // one bond entry per thread: an atom's entries are independent here
+  const int ne = b_off[n];
+  for (int e = threadIdx.x; e < ne; e += BSZ) {
+    const int i = L.bond_i[e], j = L.bond_j[e];
+    int m = e;
+    for (int f = b_off[j]; f < b_off[j + 1]; ++f)
+      if (L.bond_j[f] == i) m = f;
+    L.bond_mir[e] = m;
+    bo_prime_entry(A.P, g, L, W, i, e);
   }
 }
 
@@ -336,7 +336,8 @@ __device__ __noinline__ void st_bo_corr(int n) {
   Lists L;
   Work W;
   views(A, L, W);
-  for (int i = threadIdx.x; i < n; i += BSZ) bo_corr_atom(A.P, L, W, i);
+  const int ne = b_off[n];
+  for (int e = threadIdx.x; e < ne; e += BSZ) bo_corr_entry(A.P, L, W, L.bond_i[e], e);
 }
 
 template <int BSZ>
@@ -557,7 +558,8 @@ __device__ __noinline__ void st_back_corr(int n) {
   Lists L;
   Work W;
   views(A, L, W);
-  for (int i = threadIdx.x; i < n; i += BSZ) back_corr_atom(A.P, L, W, i);
+  const int ne = b_off[n];
+  for (int e = threadIdx.x; e < ne; e += BSZ) back_corr_entry(A.P, L, W, L.bond_i[e], e);
 }
 
 template <int BSZ>
