@@ -35,7 +35,7 @@ constexpr int ST_CAPACITY = 1, ST_TYPE = 2;
 
 // byte offsets of the arrays inside one workgroup's scratch slice
 struct BatchLayout {
-  int64_t ast, dp, gS, gSig, gSBO, gStot, gDp;    // per atom (nmax)
+  int64_t ast, dp, gS, gSig, gRso, gSBO, gStot, gDp;    // per atom (nmax)
   int64_t bj, bi, bm;                             // per entry (ecap), int32
   int64_t bd, bop, dbop, bo, gbo, gvec, gup;      // per entry, double4
   int64_t stride;
@@ -53,6 +53,7 @@ static BatchLayout make_layout(int nmax, int ecap) {
   y.dp = take(sizeof(double2) * (int64_t)nmax);
   y.gS = take(sizeof(double) * (int64_t)nmax);
   y.gSig = take(sizeof(double) * (int64_t)nmax);
+  y.gRso = take(sizeof(double) * (int64_t)nmax);
   y.gSBO = take(sizeof(double) * (int64_t)nmax);
   y.gStot = take(sizeof(double) * (int64_t)nmax);
   y.gDp = take(sizeof(double) * (int64_t)nmax);
@@ -175,6 +176,7 @@ __device__ __forceinline__ void views(const BatchArgs& A, Lists& L, Work& W) {
   W.dp = reinterpret_cast<double2*>(base + A.lay.dp);
   W.gS = reinterpret_cast<double*>(base + A.lay.gS);
   W.gSig = reinterpret_cast<double*>(base + A.lay.gSig);
+  W.gRso = reinterpret_cast<double*>(base + A.lay.gRso);
   W.gSBO = reinterpret_cast<double*>(base + A.lay.gSBO);
   W.gStot = reinterpret_cast<double*>(base + A.lay.gStot);
   W.gDp = reinterpret_cast<double*>(base + A.lay.gDp);

@@ -162,6 +162,7 @@ int alloc_atoms(reaxff_ctx* c, int64_t n) {
   G(c->L.ha_cnt);
   G(c->sc.cid); G(c->sc.cell_s); G(c->sc.cnt_cand); G(c->sc.cnt_bond);
   G(c->W.dp); G(c->W.ast); G(c->W.gS); G(c->W.gSig); G(c->W.gSBO); G(c->W.gStot); G(c->W.gDp);
+  G(c->W.gRso);
   G(c->W.fnb); G(c->W.fhb); G(c->W.xq); G(c->W.don_rng); G(c->W.nv);
 #undef G
   c->cap_n = cap;
@@ -247,7 +248,7 @@ void reaxff_destroy(reaxff_ctx* c) {
                   c->L.far_j, c->L.bond_off, c->L.bond_j, c->L.bond_mir, c->L.hb_cnt, c->L.hb_j,
                   c->L.ha_cnt, c->L.ha_j,
                   c->W.bd, c->W.bop, c->W.dbop, c->W.bo, c->W.gbo, c->W.gvec, c->W.gup, c->W.dp,
-                  c->W.ast, c->W.gS, c->W.gSig, c->W.gSBO, c->W.gStot, c->W.gDp, c->W.fnb, c->W.fhb, c->W.don_rng, c->W.nv,
+                  c->W.ast, c->W.gS, c->W.gSig, c->W.gRso, c->W.gSBO, c->W.gStot, c->W.gDp, c->W.fnb, c->W.fhb, c->W.don_rng, c->W.nv,
                   c->W.xq, c->W.counters, c->W.cnt_ang, c->W.cnt_tor, c->W.cnt_don,
                   c->W.off_ang, c->W.off_tor, c->W.off_don, c->W.ang, c->W.tor, c->W.don, c->W.donrec, c->L.far_lo, c->W.nbpart, c->W.nbtab, c->W.nbe,
                   c->L.bond_i, c->sc.cid, c->sc.cell_s, c->sc.cell_count,

@@ -161,6 +161,7 @@ struct Work {
   AtomState* ast;
   double* gS;      // dE/dS (direct terms)
   double* gSig;    // dE/dSigma_pi of the over/under term
+  double* gRso;    // R so of the over-coordination term (its bond-order factor)
   double* gSBO;    // dE/dSBO
   double* gStot;   // dE/dS including gathered cross-atom terms
   double* gDp;     // dE/dDelta' (sum over own bonds)

@@ -390,22 +390,14 @@ __device__ __forceinline__ void atom_energy_atom(const DevParams* __restrict__ P
   const double dt8 = -P->p_ovun7 * P->p_ovun8 * ep8 * t8 * t8;
   const double dDlpc_dsig = st.Dlp * P->p_ovun3 * P->p_ovun4 * ep4 / (DD * DD);
   const double gSig = -a.p_ovun5 * (1.0 - e6) * su * dt8 + gL * dDlpc_dsig;
-  const double gRso = R * so;
-#pragma unroll 4
-  for (int e = L.bond_off[i] + sub; e < L.bond_off[i + 1]; e += G) {
-    const int j = L.bond_j[e];
-    const PairP& p = P->pair[ti * NT + L.type_s[j]];
-    double4 gb = W.gbo[e];
-    gb.x += p.p_ovun1 * p.D_s * gRso;
-    const double w = gSig * nview(W, j).y;
-    gb.y += w;
-    gb.z += w;
-    W.gbo[e] = gb;
-  }
+  // the over/under terms' adjoints of i's entries, p_ovun1 D_s R so on BO
+  // and gSig (Delta_j - Dlp_j) on BOpi and BOpipi, are added where the
+  // entries' adjoints are read (back_corr_entry), from gRso and gSig
   e[0] += ebond;
   if (sub != 0) return;
   W.gS[i] = dElp_dDlp * (-st.dnlp) + gL * (1.0 + st.dnlp / DD);
   W.gSig[i] = gSig;
+  W.gRso[i] = R * so;
   e[1] += elp;
   e[2] += eover;
   e[3] += eunder;
@@ -747,8 +739,21 @@ __device__ __forceinline__ void back_corr_entry(const DevParams* __restrict__ P,
     const int ta = lo ? ti : tj, tb = lo ? tj : ti;
     const double4 bp = W.bop[e];
     const double4 bo = W.bo[e];
-    const double pwa = nview(W, a).w, pwb = nview(W, b).w;   // prod W of a and b
-    const double4 ga = W.gbo[ea], gb = W.gbo[eb];
+    const double4 na = nview(W, a), nb = nview(W, b);
+    const double pwa = na.w, pwb = nb.w;   // prod W of a and b
+    double4 ga = W.gbo[ea], gb = W.gbo[eb];
+    {
+      // over/under-coordination adjoints of the two entries (atom_energy_atom)
+      const PairP& pa = P->pair[ta * NT + tb];
+      const PairP& pb = P->pair[tb * NT + ta];
+      ga.x += pa.p_ovun1 * pa.D_s * W.gRso[a];
+      gb.x += pb.p_ovun1 * pb.D_s * W.gRso[b];
+      const double wa = W.gSig[a] * nb.y, wb = W.gSig[b] * na.y;
+      ga.y += wa;
+      ga.z += wa;
+      gb.y += wb;
+      gb.z += wb;
+    }
     const double gsa = W.gSBO[a], gsb = W.gSBO[b];
     const double b2 = bo.x * bo.x, b7 = b2 * b2 * b2 * bo.x;
     const double gBO = ga.x + gb.x + W.gStot[a] + W.gStot[b] + 8.0 * b7 * (gsa * pwa + gsb * pwb);
