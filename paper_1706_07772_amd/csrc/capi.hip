@@ -176,6 +176,7 @@ int alloc_bonds(reaxff_ctx* c, int64_t nb) {
   G(c->L.bond_j); G(c->L.bond_i); G(c->L.bond_mir); G(c->W.bd); G(c->W.bop); G(c->W.dbop); G(c->W.bo);
   G(c->W.gbo); G(c->W.gvec); G(c->W.gup);
   G(c->W.cnt_ang); G(c->W.cnt_tor); G(c->W.cnt_don); G(c->W.off_ang); G(c->W.off_tor); G(c->W.off_don);
+  G(c->W.bo1);
 #undef G
   c->cap_bond = cap;
   return 0;
@@ -248,7 +249,7 @@ void reaxff_destroy(reaxff_ctx* c) {
                   c->L.far_j, c->L.bond_off, c->L.bond_j, c->L.bond_mir, c->L.hb_cnt, c->L.hb_j,
                   c->L.ha_cnt, c->L.ha_j,
                   c->W.bd, c->W.bop, c->W.dbop, c->W.bo, c->W.gbo, c->W.gvec, c->W.gup, c->W.dp,
-                  c->W.ast, c->W.gS, c->W.gSig, c->W.gRso, c->W.gSBO, c->W.gStot, c->W.gDp, c->W.fnb, c->W.fhb, c->W.don_rng, c->W.nv,
+                  c->W.ast, c->W.gS, c->W.gSig, c->W.gRso, c->W.gSBO, c->W.gStot, c->W.gDp, c->W.fnb, c->W.fhb, c->W.don_rng, c->W.nv, c->W.bo1,
                   c->W.xq, c->W.counters, c->W.cnt_ang, c->W.cnt_tor, c->W.cnt_don,
                   c->W.off_ang, c->W.off_tor, c->W.off_don, c->W.ang, c->W.tor, c->W.don, c->W.donrec, c->L.far_lo, c->W.nbpart, c->W.nbtab, c->W.nbe,
                   c->L.bond_i, c->sc.cid, c->sc.cell_s, c->sc.cell_count,

@@ -73,13 +73,13 @@ __global__ __launch_bounds__(BS) void k_tasks(const DevParams* __restrict__ P, L
   const int j = L.bond_i[u];
   const int e1 = L.bond_off[j + 1];
   const int k = L.bond_j[u];
-  const double bu = W.bo[u].x;
+  const double bu = W.bo1[u];
   int na = 0, nt = 0, nd = 0;
   const int oa = FILL ? W.off_ang[u] : 0, ot = FILL ? W.off_tor[u] : 0, od = FILL ? W.off_don[u] : 0;
   // angles (u, v), u < v
   if (bu - thb > 0.0) {
     for (int v = (int)u + 1; v < e1; ++v) {
-      const double bv = W.bo[v].x;
+      const double bv = W.bo1[v];
       if (bv - thb > 0.0 && bu * bv > thb2) {
         if (FILL) W.ang[oa + na] = make_int2((int)u, v);
         ++na;
@@ -92,13 +92,13 @@ __global__ __launch_bounds__(BS) void k_tasks(const DevParams* __restrict__ P, L
     const int f0 = L.bond_off[k], f1 = L.bond_off[k + 1];
     for (int a = e0; a < e1; ++a) {
       if (a == (int)u) continue;
-      const double ba = W.bo[a].x;
+      const double ba = W.bo1[a];
       if (!(ba > thb)) continue;
       const int i = L.bond_j[a];
       for (int b = f0; b < f1; ++b) {
         const int l = L.bond_j[b];
         if (l == j || l == i) continue;
-        const double bb = W.bo[b].x;
+        const double bb = W.bo1[b];
         if (!(bb > thb)) continue;
         if (!(ba * bu * bb > thb)) continue;
         if (FILL) W.tor[ot + nt] = make_int4((int)u, a, b, 0);
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(BS) void k_hbonds(const DevParams* __restrict__ P, 
     const int h = L.bond_i[ex], X = L.bond_j[ex];
     const int th = L.type_s[h], tx = L.type_s[X];
     const double4 xh = L.xs[h];
-    const double bo = W.bo[ex].x;
+    const double bo = W.bo1[ex];
     const double4 rx = W.bd[ex];     // x_X - x_h
     double gbo = 0.0;
     double3 gx = make_double3(0.0, 0.0, 0.0), fh = make_double3(0.0, 0.0, 0.0);

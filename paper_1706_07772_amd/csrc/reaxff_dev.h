@@ -183,6 +183,9 @@ struct Work {
   int32_t* don;      // entry h->X
   DonRec* donrec;    // per donor task: what the acceptor side reads of h->X
   int2* don_rng;     // [n] each atom's donor tasks [x, y)
+  // [nbond] corrected total bond order BO alone (the .x of bo), for the
+  // kernels that only test or scale by it; null: read bo[e].x
+  double* bo1;
   // [n] what other atoms' terms read of atom j, in one 32-byte record:
   // (S, Delta - Dlp, Dang, prod W); null: read from ast
   double4* nv;

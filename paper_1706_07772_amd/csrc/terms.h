@@ -254,6 +254,7 @@ __device__ __forceinline__ void bo_corr_entry(const DevParams* __restrict__ P, c
     const double G = c.f1 * c.f1 * c.f4 * c.f5;
     const double BO = bp.w * F, BOp = bp.y * G, BOpp = bp.z * G;
     W.bo[e] = make_double4(BO, BOp, BOpp, BO - BOp - BOpp);
+    if (W.bo1) W.bo1[e] = BO;
   }
 }
 __device__ __forceinline__ void bo_corr_atom(const DevParams* __restrict__ P, const Lists& L,
@@ -316,6 +317,9 @@ __device__ __forceinline__ void atom_state_atom(const DevParams* __restrict__ P,
   W.ast[i] = st;
   if (W.nv) W.nv[i] = make_double4(st.S, st.Delta - st.Dlp, st.Dang, st.prod * st.W);
 }
+
+// corrected total bond order of entry e (the compact copy when there is one)
+__device__ __forceinline__ double bo_tot(const Work& W, int e) { return W.bo1 ? W.bo1[e] : W.bo[e].x; }
 
 // what a term centred elsewhere reads of atom j (S, Delta - Dlp, Dang,
 // prod W): the compact record when there is one
@@ -423,7 +427,7 @@ __device__ __forceinline__ AngOut angle_eval(const DevParams* __restrict__ P, co
   const AngleP& ap = P->angle[(ti * NT + tj) * NT + tk];
   const AtomState& st = W.ast[j];
   const double4 ru = W.bd[u], rv = W.bd[v];
-  const double B1 = W.bo[u].x - thb, B2 = W.bo[v].x - thb;
+  const double B1 = bo_tot(W, u) - thb, B2 = bo_tot(W, v) - thb;
   const double Si = nview(W, i).x, Sk = nview(W, k).x;
   // angle between r_ji (= bd[u]) and r_jk (= bd[v])
   const double il1 = 1.0 / ru.w, il2 = 1.0 / rv.w;
@@ -510,7 +514,7 @@ __device__ __forceinline__ TorOut torsion_terms(const DevParams* __restrict__ P,
   const int ti = L.type_s[i], tj = L.type_s[j], tk = L.type_s[k], tl = L.type_s[l];
   const TorsP& tp = P->tors[((ti * NT + tj) * NT + tk) * NT + tl];
   const double4 bjk = W.bo[ejk];
-  const double bij = W.bo[eji].x, bkl = W.bo[ekl].x;
+  const double bij = bo_tot(W, eji), bkl = bo_tot(W, ekl);
   // f11 of the central bond
   const double Dsum = nview(W, j).z + nview(W, k).z;
   const double et3 = exp_c(-P->p_tor3 * Dsum), et4 = exp_c(P->p_tor4 * Dsum);
