@@ -653,7 +653,8 @@ __device__ __forceinline__ HbTerm hb_term(const HbP& hp, double bo, double4 rx, 
 //     shielded Morse with inner wall, tapered shielded Coulomb.  qq = q_i q_j
 //     C_ele.  Returns the two energies and f = (dE/dr) / r.
 // ---------------------------------------------------------------------------
-struct NbP { double D, alpha, inv_rv, gw_pow, g3, e_core, a_core, inv_rc; };
+// (halpha = alpha / 2; Dar = D alpha / r_vdw; acr = a_core / r_core)
+struct NbP { double D, halpha, inv_rv, gw_pow, g3, e_core, a_core, acr, Dar; };
 
 struct NbOut { double ev, eq, f; };
 
@@ -661,10 +662,12 @@ __device__ __forceinline__ NbOut nb_pair(const NbP& p, double iR, double pv, dou
                                          double r2) {
   const double ir = rsqrt(r2);
   const double r = r2 * ir;
-  // taper
-  const double u = r * iR, u2 = u * u, u3 = u2 * u, u4 = u2 * u2;
-  const double tap = 20.0 * u4 * u3 - 70.0 * u4 * u2 + 84.0 * u4 * u - 35.0 * u4 + 1.0;
-  const double dtap = (140.0 * u3 * u3 - 420.0 * u4 * u + 420.0 * u4 - 140.0 * u3) * iR;
+  // taper 1 - 35u^4 + 84u^5 - 70u^6 + 20u^7 in Horner form, and its
+  // derivative 140 u^3 (u - 1)^3 / R
+  const double u = r * iR, u2 = u * u, u4 = u2 * u2;
+  const double tap = fma(u4, fma(u, fma(u, fma(20.0, u, -70.0), 84.0), -35.0), 1.0);
+  const double um = u - 1.0;
+  const double dtap = (140.0 * iR) * (u2 * u) * (um * um * um);
   // shielded Morse with inner wall
   const double pw = exp_f(pv * log_f(r));
   const double sum = pw + p.gw_pow;
@@ -672,12 +675,12 @@ __device__ __forceinline__ NbOut nb_pair(const NbP& p, double iR, double pv, dou
   const double f13 = exp_f(ipv * log_f(sum));
   const double df13 = f13 * isum * pw * ir;
   const double t = 1.0 - f13 * p.inv_rv;
-  const double e2 = exp_f(0.5 * p.alpha * t);
+  const double e2 = exp_f(p.halpha * t);
   const double e1 = e2 * e2;
   const double ev = p.D * (e1 - 2.0 * e2);
-  const double dev = -p.D * p.alpha * p.inv_rv * (e1 - e2) * df13;
-  const double ecr = p.e_core * exp_f(p.a_core * (1.0 - r * p.inv_rc));
-  const double decr = -ecr * p.a_core * p.inv_rc;
+  const double dev = -p.Dar * (e1 - e2) * df13;
+  const double ecr = p.e_core * exp_f(fma(-p.acr, r, p.a_core));   // a_core (1 - r / r_core)
+  const double decr = -ecr * p.acr;
   // shielded Coulomb: den = (r^3 + gamma^-3)^(1/3), 1/s3 = (1/den)^3
   const double s3 = r2 * r + p.g3;
   const double iden = rcbrt_f(s3);
@@ -692,7 +695,8 @@ __device__ __forceinline__ NbOut nb_pair(const NbP& p, double iR, double pv, dou
 }
 
 __device__ __forceinline__ NbP nb_params(const PairP& p) {
-  return NbP{p.D_vdw, p.alpha, p.inv_r_vdw, p.gw_pow, p.g3, p.e_core, p.a_core, p.inv_r_core};
+  return NbP{p.D_vdw, 0.5 * p.alpha, p.inv_r_vdw, p.gw_pow, p.g3, p.e_core, p.a_core, p.a_core * p.inv_r_core,
+             p.D_vdw * p.alpha * p.inv_r_vdw};
 }
 
 // ---------------------------------------------------------------------------
