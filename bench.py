@@ -53,7 +53,7 @@ PHASES = {
     "bonded": ("gather_q", "bo_prime", "delta_prime", "bo_corr", "atom_state", "atom_energy",
                "tasks", "angles", "torsions", "hbonds", "hb_acceptors"),
     "nonbonded": ("nonbonded", "nb_reduce", "nb_energy"),
-    "backward": ("back_s", "back_corr", "back_dp", "forces"),
+    "backward": ("back_s", "back_corr", "back_dp", "forces", "energy_fold"),
 }
 
 

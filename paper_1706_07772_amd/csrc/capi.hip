@@ -231,6 +231,7 @@ int reaxff_create(const reaxff_params* params, const reaxff_cutoffs* cutoffs, in
       hipMalloc(&c->sc.need, sizeof(int32_t) * 8) != hipSuccess ||
       hipHostMalloc(&c->sc.totals_host, sizeof(int64_t) * 8, hipHostMallocDefault) != hipSuccess ||
       hipMalloc(&c->W.counters, sizeof(unsigned long long) * 4) != hipSuccess ||
+      hipMalloc(&c->W.epart, sizeof(double) * ESLOT * NTERMS) != hipSuccess ||
       hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
@@ -250,7 +251,7 @@ void reaxff_destroy(reaxff_ctx* c) {
                   c->L.ha_cnt, c->L.ha_j,
                   c->W.bd, c->W.bop, c->W.dbop, c->W.bo, c->W.gbo, c->W.gvec, c->W.gup, c->W.dp,
                   c->W.ast, c->W.gS, c->W.gSig, c->W.gRso, c->W.gSBO, c->W.gStot, c->W.gDp, c->W.fnb, c->W.fhb, c->W.don_rng, c->W.nv, c->W.bo1,
-                  c->W.xq, c->W.counters, c->W.cnt_ang, c->W.cnt_tor, c->W.cnt_don,
+                  c->W.xq, c->W.counters, c->W.epart, c->W.cnt_ang, c->W.cnt_tor, c->W.cnt_don,
                   c->W.off_ang, c->W.off_tor, c->W.off_don, c->W.ang, c->W.tor, c->W.don, c->W.donrec, c->L.far_lo, c->W.nbpart, c->W.nbtab, c->W.nbe,
                   c->L.bond_i, c->sc.cid, c->sc.cell_s, c->sc.cell_count,
                   c->sc.cell_cursor, c->sc.flag, c->sc.cnt_cand, c->sc.cnt_bond,

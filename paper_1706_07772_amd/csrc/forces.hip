@@ -129,10 +129,10 @@ __global__ __launch_bounds__(BS) void k_atom_energy(const DevParams* __restrict_
   const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
   double e[4] = {0.0, 0.0, 0.0, 0.0};
   if (i < L.n) atom_energy_atom(P, L, W, (int)i, e);
-  block_add<BS>(e[0], energies + E_BOND);
-  block_add<BS>(e[1], energies + E_LP);
-  block_add<BS>(e[2], energies + E_OVER);
-  block_add<BS>(e[3], energies + E_UNDER);
+  block_add<BS>(e[0], eslot(W.epart) + E_BOND);
+  block_add<BS>(e[1], eslot(W.epart) + E_LP);
+  block_add<BS>(e[2], eslot(W.epart) + E_OVER);
+  block_add<BS>(e[3], eslot(W.epart) + E_UNDER);
 }
 
 // ---------------------------------------------------------------------------
@@ -238,9 +238,9 @@ __global__ __launch_bounds__(BS) void k_angles(const DevParams* __restrict__ P, 
       W.gSBO[j] = sc[k][1];
     }
   }
-  block_add<BS>(eval, energies + E_VAL);
-  block_add<BS>(epen, energies + E_PEN);
-  block_add<BS>(ecoa, energies + E_COA);
+  block_add<BS>(eval, eslot(W.epart) + E_VAL);
+  block_add<BS>(epen, eslot(W.epart) + E_PEN);
+  block_add<BS>(ecoa, eslot(W.epart) + E_COA);
 }
 
 // ---------------------------------------------------------------------------
@@ -324,8 +324,8 @@ __global__ __launch_bounds__(BS) void k_torsions(const DevParams* __restrict__ P
     for (int k = threadIdx.x; k < nc; k += BS)
       if (sj[k] != 0.0) atomicAdd(&W.gS[jf + k], sj[k]);
   }
-  block_add<BS>(etor, energies + E_TOR);
-  block_add<BS>(econj, energies + E_CONJ);
+  block_add<BS>(etor, eslot(W.epart) + E_TOR);
+  block_add<BS>(econj, eslot(W.epart) + E_CONJ);
 }
 
 // ---------------------------------------------------------------------------
@@ -384,9 +384,18 @@ __global__ __launch_bounds__(BS) void k_hbonds(const DevParams* __restrict__ P, 
     W.gbo[ex].x += gbo;
     atomic_add3(&W.fhb[h], fh);
   }
-  block_add<BS>(ehb, energies + E_HB);
-  for (int off = 32; off > 0; off >>= 1) nhb += __shfl_down(nhb, off, 64);
-  if ((threadIdx.x & 63) == 0 && nhb) atomicAdd(&W.counters[2], nhb);
+  block_add<BS>(ehb, eslot(W.epart) + E_HB);
+  {
+    __shared__ unsigned long long rn[BS / 64];
+    for (int off = 32; off > 0; off >>= 1) nhb += __shfl_down(nhb, off, 64);
+    if ((threadIdx.x & 63) == 0) rn[threadIdx.x >> 6] = nhb;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long t = 0;
+      for (int w = 0; w < BS / 64; ++w) t += rn[w];
+      if (t) atomicAdd(&W.counters[2], t);
+    }
+  }
 }
 
 // Acceptor side: F_Z = -dE/dx_Z = -sum dE/d(x_Z - x_h) over the donors H of
@@ -1031,11 +1040,20 @@ __global__ void k_gather_q(const double* __restrict__ q, const int32_t* __restri
   }
 }
 
+// the energy partial-sum slots, summed into the energies
+__global__ void k_energy_fold(const double* __restrict__ epart, double* __restrict__ energies) {
+  const int t = threadIdx.x;
+  if (t >= NTERMS) return;
+  double v = 0.0;
+  for (int k = 0; k < ESLOT; ++k) v += epart[k * NTERMS + t];
+  if (v != 0.0) atomicAdd(&energies[t], v);
+}
+
 const char* const kKernelNames[KID_COUNT] = {
     "bbox", "cell_hist", "cell_scatter", "cell_sort", "gather_sorted", "list_sweep", "scan",
     "bondtest", "compact", "mirror", "zero", "gather_q", "bo_prime", "delta_prime", "bo_corr", "atom_state",
     "atom_energy", "tasks", "angles", "torsions", "hbonds", "hb_acceptors", "nonbonded", "back_s", "back_corr",
-    "back_dp", "forces", "batch", "nb_reduce", "nb_energy"};
+    "back_dp", "forces", "batch", "nb_reduce", "nb_energy", "energy_fold"};
 
 int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, const double* q,
                   hipStream_t side, hipEvent_t ev_fork, hipEvent_t ev_join, double* forces,
@@ -1043,6 +1061,7 @@ int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, co
   const int64_t n = L.n, nb = L.nbond;
   pf.begin(KID_ZERO, st);
   (void)hipMemsetAsync(energies, 0, sizeof(double) * NTERMS, st);
+  (void)hipMemsetAsync(W.epart, 0, sizeof(double) * ESLOT * NTERMS, st);
   (void)hipMemsetAsync(W.counters, 0, sizeof(unsigned long long) * 4, st);
   if (nb > 0) {
     (void)hipMemsetAsync(W.gbo, 0, sizeof(double4) * nb, st);
@@ -1125,6 +1144,7 @@ int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, co
   // join: the force gather reads the nonbonded forces
   if (fork) (void)hipStreamWaitEvent(st, ev_join, 0);
   LAUNCH(KID_FORCES, k_forces, dim3(xcd_grid(nblk(4 * n, BS))), blk, 0, st, L, W, forces);
+  LAUNCH(KID_ENERGY_FOLD, k_energy_fold, dim3(1), dim3(64), 0, st, W.epart, energies);
 #undef LAUNCH
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

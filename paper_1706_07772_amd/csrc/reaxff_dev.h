@@ -183,6 +183,10 @@ struct Work {
   int32_t* don;      // entry h->X
   DonRec* donrec;    // per donor task: what the acceptor side reads of h->X
   int2* don_rng;     // [n] each atom's donor tasks [x, y)
+  // [ESLOT][NTERMS] energy partial sums: each workgroup adds its per-term
+  // sums to slot (block mod ESLOT), so no single address takes one atomic
+  // per workgroup of a large grid; folded into the energies at the end
+  double* epart;
   // [nbond] corrected total bond order BO alone (the .x of bo), for the
   // kernels that only test or scale by it; null: read bo[e].x
   double* bo1;
@@ -392,6 +396,13 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
 }
 
 // wave64 + block reduction of one double into *dst (one atomic per block)
+constexpr int ESLOT = 64;   // energy partial-sum slots
+
+// this workgroup's row of the energy partial sums
+__device__ __forceinline__ double* eslot(double* epart) {
+  return epart + (int64_t)(blockIdx.x & (ESLOT - 1)) * NTERMS;
+}
+
 template <int BS>
 __device__ __forceinline__ void block_add(double v, double* dst) {
   __shared__ double red[BS / 64];
