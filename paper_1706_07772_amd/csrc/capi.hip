@@ -228,6 +228,8 @@ int reaxff_create(const reaxff_params* params, const reaxff_cutoffs* cutoffs, in
       hipMemcpy(c->dp, &c->hd, sizeof(DevParams), hipMemcpyHostToDevice) != hipSuccess ||
       hipMalloc(&c->sc.flag, sizeof(int32_t) * 4) != hipSuccess ||
       hipMalloc(&c->sc.totals, sizeof(int64_t) * 8) != hipSuccess ||
+      hipMalloc(&c->sc.tslot, sizeof(int64_t) * 8 * ESLOT) != hipSuccess ||
+      hipMalloc(&c->sc.nslot, sizeof(int32_t) * ESLOT) != hipSuccess ||
       hipMalloc(&c->sc.need, sizeof(int32_t) * 8) != hipSuccess ||
       hipHostMalloc(&c->sc.totals_host, sizeof(int64_t) * 8, hipHostMallocDefault) != hipSuccess ||
       hipMalloc(&c->W.counters, sizeof(unsigned long long) * 4) != hipSuccess ||
@@ -255,7 +257,7 @@ void reaxff_destroy(reaxff_ctx* c) {
                   c->W.off_ang, c->W.off_tor, c->W.off_don, c->W.ang, c->W.tor, c->W.don, c->W.donrec, c->L.far_lo, c->W.nbpart, c->W.nbtab, c->W.nbe,
                   c->L.bond_i, c->sc.cid, c->sc.cell_s, c->sc.cell_count,
                   c->sc.cell_cursor, c->sc.flag, c->sc.cnt_cand, c->sc.cnt_bond,
-                  c->sc.cand_j, c->sc.bond_t, c->sc.need,
+                  c->sc.cand_j, c->sc.bond_t, c->sc.need, c->sc.tslot, c->sc.nslot,
                   c->sc.part, c->sc.totals, c->sc.scan_tmp};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);

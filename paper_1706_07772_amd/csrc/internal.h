@@ -81,6 +81,10 @@ struct Scratch {
   int32_t* need = nullptr;        // device [4]: largest counts seen (far, cand, bond, hb)
   double* part = nullptr;         // bbox partials
   int64_t* totals = nullptr;      // device [8]
+  // device [ESLOT][8] partial totals and [ESLOT] partial need[5] maxima of
+  // the sweep and bond test (workgroup mod ESLOT), folded into totals, need
+  int64_t* tslot = nullptr;
+  int32_t* nslot = nullptr;
   int64_t* totals_host = nullptr; // pinned host [8]
   // scan temporaries
   int64_t* scan_tmp = nullptr;

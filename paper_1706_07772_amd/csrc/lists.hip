@@ -142,7 +142,8 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
     int far_w, int32_t* __restrict__ cnt_cand, int32_t* __restrict__ cand_j, int cand_w,
     int32_t* __restrict__ hb_cnt, int32_t* __restrict__ hb_j, int hb_w,
     int32_t* __restrict__ ha_cnt, int32_t* __restrict__ ha_j, int ha_w, int slots,
-    int32_t* __restrict__ far_lo, int32_t* __restrict__ need, unsigned long long* __restrict__ totals) {
+    int32_t* __restrict__ far_lo, int32_t* __restrict__ need, unsigned long long* __restrict__ tslot,
+    int32_t* __restrict__ nslot) {
   __shared__ unsigned long long red[SWEEP_WAVES][2];
   __shared__ int q_s0[SWEEP_WAVES][SWEEP_MAXQ], q_base[SWEEP_WAVES][SWEEP_MAXQ + 1];
   __shared__ double q_sh[SWEEP_WAVES][SWEEP_MAXQ][3];
@@ -193,7 +194,7 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
     const int c2 = c % g.nc[2];
     const int q_own = 2 * (g.reach * g.span[1] + g.reach) + (g.periodic && c2 - g.reach < 0 ? 1 : 0);
     own0 = __builtin_amdgcn_readfirstlane(qb[q_own] + (a0 - qs0[q_own]));
-    if (lane == 0) atomicMax(&need[5], nst - own0);
+    if (lane == 0) atomicMax(&nslot[(blockIdx.x * SWEEP_WAVES + wv) & (ESLOT - 1)], nst - own0);
   }
   for (int ig = 0; ig < m; ig += 64) {       // the cell's atoms, 64 at a time, one per lane
     const int mi = m - ig < 64 ? m - ig : 64;
@@ -333,7 +334,7 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
   if (threadIdx.x < 2) {
     unsigned long long v = 0;
     for (int w = 0; w < SWEEP_WAVES; ++w) v += red[w][threadIdx.x];
-    if (v) atomicAdd(&totals[threadIdx.x == 0 ? 0 : 4], v);
+    if (v) atomicAdd(&tslot[(blockIdx.x & (ESLOT - 1)) * 8 + (threadIdx.x == 0 ? 0 : 4)], v);
   }
 }
 
@@ -348,7 +349,7 @@ __global__ __launch_bounds__(BT_BS) void k_bondtest(
     const DevParams* __restrict__ P, Grid g, int64_t n, const double4* __restrict__ xs,
     const int32_t* __restrict__ cnt_cand, const int32_t* __restrict__ cand_j, int cand_w,
     int32_t* __restrict__ cnt_bond, int32_t* __restrict__ bond_t, int bond_w,
-    int32_t* __restrict__ need, unsigned long long* __restrict__ totals) {
+    int32_t* __restrict__ need, unsigned long long* __restrict__ tslot) {
   __shared__ unsigned long long red[BT_BS / 64][3];
   const int lane = threadIdx.x & 63, sub = lane & (BT_GROUP - 1), gsh = lane & ~(BT_GROUP - 1);
   const double bo_cut = P->bo_cut;
@@ -416,7 +417,7 @@ __global__ __launch_bounds__(BT_BS) void k_bondtest(
   if (threadIdx.x < 3) {
     unsigned long long v = 0;
     for (int w = 0; w < BT_BS / 64; ++w) v += red[w][threadIdx.x];
-    if (v) atomicAdd(&totals[threadIdx.x + 1], v);
+    if (v) atomicAdd(&tslot[(blockIdx.x & (ESLOT - 1)) * 8 + threadIdx.x + 1], v);
   }
 }
 
@@ -565,30 +566,49 @@ int launch_cell_sort(const double* pos, const int32_t* type, int64_t n, const Gr
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// the sweep's and bond test's partial totals and need[5] maxima, folded
+__global__ void k_fold_totals(const unsigned long long* __restrict__ tslot, const int32_t* __restrict__ nslot,
+                              unsigned long long* __restrict__ totals, int32_t* __restrict__ need) {
+  const int t = threadIdx.x;
+  if (t < 8) {
+    unsigned long long v = 0;
+    for (int k = 0; k < ESLOT; ++k) v += tslot[k * 8 + t];
+    totals[t] += v;
+  } else if (t == 8) {
+    int m = need[5];
+    for (int k = 0; k < ESLOT; ++k) m = nslot[k] > m ? nslot[k] : m;
+    need[5] = m;
+  }
+}
+
 int launch_sweep(const DevParams* P, const Grid& g, int64_t n, int ncell, Scratch& sc, Lists& L,
                  Prof& pf, hipStream_t st) {
   if (stencil_chunks(g) > SWEEP_MAXQ) return -1;   // the sweep's chunk table
   (void)hipMemsetAsync(sc.need, 0, sizeof(int32_t) * 8, st);
   (void)hipMemsetAsync(sc.totals, 0, sizeof(int64_t) * 8, st);
+  (void)hipMemsetAsync(sc.tslot, 0, sizeof(int64_t) * 8 * ESLOT, st);
+  (void)hipMemsetAsync(sc.nslot, 0, sizeof(int32_t) * ESLOT, st);
   pf.begin(KID_LIST_SWEEP, st);
   if (g.periodic && !g.shift_ok)
     hipLaunchKernelGGL(k_sweep<true>, dim3(nblk(ncell, SWEEP_WAVES)), dim3(64 * SWEEP_WAVES), 0, st, P, g,
                        ncell, L.xs, L.cell_start, L.far_cnt, L.far_j, L.far_w, sc.cnt_cand, sc.cand_j,
                        sc.cand_w, L.hb_cnt, L.hb_j, L.hb_w, L.ha_cnt, L.ha_j, L.ha_w, L.far_slots,
                      L.far_slots ? L.far_lo : nullptr, sc.need,
-                       reinterpret_cast<unsigned long long*>(sc.totals));
+                       reinterpret_cast<unsigned long long*>(sc.tslot), sc.nslot);
   else
     hipLaunchKernelGGL(k_sweep<false>, dim3(nblk(ncell, SWEEP_WAVES)), dim3(64 * SWEEP_WAVES), 0, st, P, g,
                        ncell, L.xs, L.cell_start, L.far_cnt, L.far_j, L.far_w, sc.cnt_cand, sc.cand_j,
                        sc.cand_w, L.hb_cnt, L.hb_j, L.hb_w, L.ha_cnt, L.ha_j, L.ha_w, L.far_slots,
                      L.far_slots ? L.far_lo : nullptr, sc.need,
-                       reinterpret_cast<unsigned long long*>(sc.totals));
+                       reinterpret_cast<unsigned long long*>(sc.tslot), sc.nslot);
   pf.end(st);
   pf.begin(KID_BONDTEST, st);
   hipLaunchKernelGGL(k_bondtest, dim3(xcd_grid(std::min<int64_t>(nblk(n, BT_TILE), 4096))), dim3(BT_BS), 0, st,
                      P, g, n, L.xs, sc.cnt_cand,
                      sc.cand_j, sc.cand_w, sc.cnt_bond, sc.bond_t, sc.bond_w, sc.need,
-                     reinterpret_cast<unsigned long long*>(sc.totals));
+                     reinterpret_cast<unsigned long long*>(sc.tslot));
+  hipLaunchKernelGGL(k_fold_totals, dim3(1), dim3(64), 0, st, reinterpret_cast<const unsigned long long*>(sc.tslot), sc.nslot,
+                     reinterpret_cast<unsigned long long*>(sc.totals), sc.need);
   pf.end(st);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
