@@ -836,13 +836,15 @@ __global__ void k_unsort_rows(int64_t n, const int32_t* __restrict__ perm, const
   G[(int64_t)perm[s] * ND + k % ND] = Gs[k];
 }
 
-// sum of valid per-row energies of every member (FP64)
+// sum of valid per-row energies of every member (FP64); a small grid strides
+// over the rows, so each member's total takes one atomic add per workgroup
 __global__ void k_sur_energy(int64_t rows, int32_t members, const int32_t* __restrict__ rowatom,
                              const float* __restrict__ Erow, double* __restrict__ E) {
-  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   for (int m = 0; m < members; ++m) {
     double v = 0.0;
-    if (r < rows && rowatom[r] >= 0) v = (double)Erow[(int64_t)m * rows + r];
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < rows;
+         r += (int64_t)gridDim.x * blockDim.x)
+      if (rowatom[r] >= 0) v += (double)Erow[(int64_t)m * rows + r];
     block_add<256>(v, E + m);
   }
 }
@@ -888,8 +890,15 @@ __global__ void k_sur_ensemble(int64_t n, int32_t members, const int32_t* __rest
     if (mask) mask[o] = f;
     c = f;
   }
+  // one count per workgroup (256 threads)
+  __shared__ int rc[4];
   for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
-  if ((threadIdx.x & 63) == 0 && c && nflag) atomicAdd(nflag, c);
+  if ((threadIdx.x & 63) == 0) rc[threadIdx.x >> 6] = (int)c;
+  __syncthreads();
+  if (threadIdx.x == 0 && nflag) {
+    const int t = rc[0] + rc[1] + rc[2] + rc[3];
+    if (t) atomicAdd(nflag, (unsigned long long)t);
+  }
 }
 
 // gated forces: exact ReaxFF where the mask is set, the ensemble mean elsewhere
@@ -1301,7 +1310,8 @@ int evaluate_frame(reaxff_surrogate* s, hipStream_t st) {
   na.Erow = s->Erow;
   na.gG = s->gG;
   hipLaunchKernelGGL(k_net_infer, dim3((unsigned)(rows / TILE), M), dim3(256), 0, st, na);
-  hipLaunchKernelGGL(k_sur_energy, dim3(nb(rows, 256)), dim3(256), 0, st, rows, M, s->R.rowatom, s->Erow, s->Etot);
+  hipLaunchKernelGGL(k_sur_energy, dim3(std::min<int64_t>(std::max<int64_t>(nb(rows, 256), 1), 128)), dim3(256), 0,
+                     st, rows, M, s->R.rowatom, s->Erow, s->Etot);
   const rx::Lists& L = s->nb->L;
   ForceArgs fa{};
   fa.g = s->nb->grid;
