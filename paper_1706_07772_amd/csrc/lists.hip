@@ -201,6 +201,9 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
     double4 xmine = make_double4(0.0, 0.0, 0.0, 0.0);
     if (lane < mi) xmine = xs[a0 + ig + lane];
     const int tmine = (int)xmine.w;
+    // bit l: the group's centre l is a donor H / an acceptor
+    const unsigned long long donc = ballot(lane < mi && ((donmask >> tmine) & 1));
+    const unsigned long long accc = ballot(lane < mi && ((accmask >> tmine) & 1));
     int kf = 0, kc = 0, kh = 0, ka = 0;       // lane l: counts of the cell's atom l
     int klo = 0;                              // lane l: far entries before atom l's own slot
     int q = 0;                                // this lane's chunk
@@ -228,84 +231,99 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
       // lane masks of the batch: the count masks below are ANDs of plain
       // compares with these, so no predicate is rebuilt for its ballot
       const unsigned long long vmask = ballot(valid), accl = ballot(valid && acc), donl = ballot(valid && don);
-      for (int l = 0; l < mi; ++l) {
-        const int i = a0 + ig + l;
-        const double4 xi4 = xs[i];   // uniform: a scalar load
-        const double xix = xi4.x, xiy = xi4.y, xiz = xi4.z;
-        double dx = xj.x - xix, dy = xj.y - xiy, dz = xj.z - xiz;
-        if constexpr (MINIMG) {
-          dx = min_image(dx, g.L[0], g.invL[0]);
-          dy = min_image(dy, g.L[1], g.invL[1]);
-          dz = min_image(dz, g.L[2], g.invL[2]);
-        } else {
-          dx -= sx;
-          dy -= sy;
-          dz -= sz;
-        }
-        const double r2 = r2_of(dx, dy, dz);
-        const bool f = valid && r2 <= rn2 && s != i;
-        const unsigned long long mf = ballot(r2 <= rn2) & ballot(s != i) & vmask;
-        // far entries before the centre's own slot: every entry of the
-        // batches below it, plus the lanes below it in the batch holding it
-        // (rows fill in slot order), so the count is set once per centre
-        const int ol = own0 + ig + l - b0;   // the own slot's lane (uniform)
-        if (halfable && (unsigned)ol < 64u) {
-          const unsigned long long low = ol == 0 ? 0ull : (~0ull >> (64 - ol));
-          klo = writelane_i(readlane_i(kf, l) + __popcll(mf & low), l, klo);
-        }
-        if (mf) {
-          // centre type (uniform) and the bond reach against it
-          const int ti = readlane_i(tmine, l);
-          const bool hdon = (donmask >> ti) & 1, hacc = (accmask >> ti) & 1;
-          const bool hr = f && r2 <= rh2;
-          const bool h = hr && acc && hdon;
-          const bool ha = hr && don && hacc;
-          const unsigned long long mhr = mf & ballot(r2 <= rh2);
-          const unsigned long long mh = hdon ? (mhr & accl) : 0ull, ma = hacc ? (mhr & donl) : 0ull;
-          // bond candidates: the pair reach is only selected when some lane
-          // lies within the largest one
-          unsigned long long mb = 0;
-          bool b = false;
-          if (mf & ballot(r2 <= rb2)) {
-            const double qa = (ti & 1) ? q1 : q0, qbr = (ti & 1) ? q3 : q2;
-            const double qt = (ti & 2) ? qbr : qa;
-            b = f && r2 <= qt;
-            mb = mf & ballot(r2 <= qt);
+      // batches holding some centre's own slot set that centre's count of
+      // entries before it; the others run the loop without that code
+      const bool hasown = halfable && b0 < own0 + ig + mi && b0 + 64 > own0 + ig;
+      auto centres = [&](auto own_t) {
+        constexpr bool OWN = decltype(own_t)::value;
+        // the centre's position and far row, advanced with the centre
+        const double4* __restrict__ xcen = xs + (a0 + ig);
+        int32_t* __restrict__ frow = far_j + (int64_t)(a0 + ig) * far_w;
+        for (int l = 0; l < mi; ++l, ++xcen, frow += far_w) {
+          const int i = a0 + ig + l;
+          const double4 xi4 = *xcen;   // uniform: a scalar load
+          const double xix = xi4.x, xiy = xi4.y, xiz = xi4.z;
+          double dx = xj.x - xix, dy = xj.y - xiy, dz = xj.z - xiz;
+          if constexpr (MINIMG) {
+            dx = min_image(dx, g.L[0], g.invL[0]);
+            dy = min_image(dy, g.L[1], g.invL[1]);
+            dz = min_image(dz, g.L[2], g.invL[2]);
+          } else {
+            dx -= sx;
+            dy -= sy;
+            dz -= sz;
           }
-          const int k0 = readlane_i(kf, l);
-          if (f) {
-            const int k = k0 + __popcll(mf & below);
-            // list rows are streamed out (non-temporal), keeping the
-            // stencil's positions in L2
-            if (k < far_w) __builtin_nontemporal_store(slots ? slot : s, &far_j[(int64_t)i * far_w + k]);
-          }
-          kf = writelane_i(k0 + __popcll(mf), l, kf);
-          if (mb) {
-            const int k1 = readlane_i(kc, l);
-            if (b) {
-              const int k = k1 + __popcll(mb & below);
-              if (k < cand_w) __builtin_nontemporal_store(s, &cand_j[(int64_t)i * cand_w + k]);
+          const double r2 = r2_of(dx, dy, dz);
+          const bool f = valid && r2 <= rn2 && s != i;
+          const unsigned long long mf = ballot(r2 <= rn2) & ballot(s != i) & vmask;
+          if constexpr (OWN) {
+            // far entries before the centre's own slot: every entry of the
+            // batches below it, plus the lanes below it in the batch holding
+            // it (rows fill in slot order), so the count is set once
+            const int ol = own0 + ig + l - b0;   // the own slot's lane (uniform)
+            if ((unsigned)ol < 64u) {
+              const unsigned long long low = ol == 0 ? 0ull : (~0ull >> (64 - ol));
+              klo = writelane_i(readlane_i(kf, l) + __popcll(mf & low), l, klo);
             }
-            kc = writelane_i(k1 + __popcll(mb), l, kc);
           }
-          if (mh) {
-            const int k2 = readlane_i(kh, l);
-            if (h) {
-              const int k = k2 + __popcll(mh & below);
-              if (k < hb_w) __builtin_nontemporal_store(s, &hb_j[(int64_t)i * hb_w + k]);
+          if (mf) {
+            const int k0 = readlane_i(kf, l);
+            if (f) {
+              const int k = k0 + __popcll(mf & below);
+              // list rows are streamed out (non-temporal), keeping the
+              // stencil's positions in L2
+              if (k < far_w) __builtin_nontemporal_store(slots ? slot : s, &frow[k]);
             }
-            kh = writelane_i(k2 + __popcll(mh), l, kh);
-          }
-          if (ma) {
-            const int k3 = readlane_i(ka, l);
-            if (ha) {
-              const int k = k3 + __popcll(ma & below);
-              if (k < ha_w) __builtin_nontemporal_store(s, &ha_j[(int64_t)i * ha_w + k]);
+            kf = writelane_i(k0 + __popcll(mf), l, kf);
+            // bond candidates: the pair reach (by the centre's type) is only
+            // selected when some lane lies within the largest one
+            if (mf & ballot(r2 <= rb2)) {
+              const int ti = readlane_i(tmine, l);
+              const double qa = (ti & 1) ? q1 : q0, qbr = (ti & 1) ? q3 : q2;
+              const double qt = (ti & 2) ? qbr : qa;
+              const unsigned long long mb = mf & ballot(r2 <= qt);
+              if (mb) {
+                const int k1 = readlane_i(kc, l);
+                if (f && r2 <= qt) {
+                  const int k = k1 + __popcll(mb & below);
+                  if (k < cand_w) __builtin_nontemporal_store(s, &cand_j[(int64_t)i * cand_w + k]);
+                }
+                kc = writelane_i(k1 + __popcll(mb), l, kc);
+              }
             }
-            ka = writelane_i(k3 + __popcll(ma), l, ka);
+            // H-bond rows: only for a donor H or an acceptor centre
+            const bool hdon = (donc >> l) & 1, hacc = (accc >> l) & 1;
+            if (hdon || hacc) {
+              const bool hr = f && r2 <= rh2;
+              const unsigned long long mhr = mf & ballot(r2 <= rh2);
+              if (hdon) {
+                const unsigned long long mh = mhr & accl;
+                if (mh) {
+                  const int k2 = readlane_i(kh, l);
+                  if (hr && acc) {
+                    const int k = k2 + __popcll(mh & below);
+                    if (k < hb_w) __builtin_nontemporal_store(s, &hb_j[(int64_t)i * hb_w + k]);
+                  }
+                  kh = writelane_i(k2 + __popcll(mh), l, kh);
+                }
+              }
+              if (hacc) {
+                const unsigned long long ma = mhr & donl;
+                if (ma) {
+                  const int k3 = readlane_i(ka, l);
+                  if (hr && don) {
+                    const int k = k3 + __popcll(ma & below);
+                    if (k < ha_w) __builtin_nontemporal_store(s, &ha_j[(int64_t)i * ha_w + k]);
+                  }
+                  ka = writelane_i(k3 + __popcll(ma), l, ka);
+                }
+              }
+            }
           }
         }
-      }
+      };
+      if (hasown) centres(std::true_type{});
+      else centres(std::false_type{});
     }
     if (lane < mi) {
       const int i = a0 + ig + lane;
