@@ -417,9 +417,24 @@ __global__ __launch_bounds__(BS) void k_hb_acceptors(const DevParams* __restrict
   const int cnt = z < L.n ? L.ha_cnt[z] : 0;   // uniform over the row
   double3 fz = make_double3(0.0, 0.0, 0.0);
   const int32_t* __restrict__ row = L.ha_j + z * (int64_t)L.ha_w;
-  // this lane's pairs, and their offset in the row's list
+  // this lane's pairs, and their offset in the row's list; the first
+  // HB_KMAX row entries of the lane are read in one go and kept
+  constexpr int HB_KMAX = 8;
+  int hh[HB_KMAX];
+  int2 rr[HB_KMAX];
   int mine = 0;
-  for (int k = sub; k < cnt; k += HB_GROUP) {
+#pragma unroll
+  for (int j = 0; j < HB_KMAX; ++j) {
+    const int k = sub + j * HB_GROUP;
+    hh[j] = k < cnt ? row[k] : 0;
+  }
+#pragma unroll
+  for (int j = 0; j < HB_KMAX; ++j) {
+    const int k = sub + j * HB_GROUP;
+    rr[j] = k < cnt ? W.don_rng[hh[j]] : make_int2(0, 0);
+    mine += rr[j].y - rr[j].x;
+  }
+  for (int k = sub + HB_KMAX * HB_GROUP; k < cnt; k += HB_GROUP) {
     const int2 tr = W.don_rng[row[k]];
     mine += tr.y - tr.x;
   }
@@ -451,7 +466,10 @@ __global__ __launch_bounds__(BS) void k_hb_acceptors(const DevParams* __restrict
     const double4 xz = L.xs[z];
     if (total <= HB_PACK) {
       int pos = incl - mine;
-      for (int k = sub; k < cnt; k += HB_GROUP) {
+#pragma unroll
+      for (int j = 0; j < HB_KMAX; ++j)
+        for (int t = rr[j].x; t < rr[j].y; ++t) mylist[pos++] = make_int2(hh[j], t);
+      for (int k = sub + HB_KMAX * HB_GROUP; k < cnt; k += HB_GROUP) {
         const int h = row[k];
         const int2 tr = W.don_rng[h];
         for (int t = tr.x; t < tr.y; ++t) mylist[pos++] = make_int2(h, t);
