@@ -76,9 +76,12 @@ __global__ __launch_bounds__(BS) void k_tasks(const DevParams* __restrict__ P, L
   const double bu = W.bo1[u];
   int na = 0, nt = 0, nd = 0;
   const int oa = FILL ? W.off_ang[u] : 0, ot = FILL ? W.off_tor[u] : 0, od = FILL ? W.off_don[u] : 0;
+  // the fill pass knows the counts: it skips empty kinds and stops at the
+  // last task of a kind
+  const int ca = FILL ? W.cnt_ang[u] : 0, ct = FILL ? W.cnt_tor[u] : 0, cd = FILL ? W.cnt_don[u] : 0;
   // angles (u, v), u < v
-  if (bu - thb > 0.0) {
-    for (int v = (int)u + 1; v < e1; ++v) {
+  if (FILL ? ca > 0 : bu - thb > 0.0) {
+    for (int v = (int)u + 1; v < e1 && (!FILL || na < ca); ++v) {
       const double bv = W.bo1[v];
       if (bv - thb > 0.0 && bu * bv > thb2) {
         if (FILL) W.ang[oa + na] = make_int2((int)u, v);
@@ -87,10 +90,10 @@ __global__ __launch_bounds__(BS) void k_tasks(const DevParams* __restrict__ P, L
     }
   }
   // torsions about the central bond u = j->k, k > j
-  if (k > j && bu > thb) {
+  if (FILL ? ct > 0 : (k > j && bu > thb)) {
     const int e0 = L.bond_off[j];
     const int f0 = L.bond_off[k], f1 = L.bond_off[k + 1];
-    for (int a = e0; a < e1; ++a) {
+    for (int a = e0; a < e1 && (!FILL || nt < ct); ++a) {
       if (a == (int)u) continue;
       const double ba = W.bo1[a];
       if (!(ba > thb)) continue;
@@ -107,8 +110,9 @@ __global__ __launch_bounds__(BS) void k_tasks(const DevParams* __restrict__ P, L
     }
   }
   // donor bond
-  if (P->atom[L.type_s[j]].hbond == 1 && P->atom[L.type_s[k]].hbond == 2 && bu >= P->hb_bo_cut &&
-      L.hb_cnt[j] > 0) {
+  if (FILL ? cd > 0
+           : (P->atom[L.type_s[j]].hbond == 1 && P->atom[L.type_s[k]].hbond == 2 && bu >= P->hb_bo_cut &&
+              L.hb_cnt[j] > 0)) {
     if (FILL) {
       W.don[od] = (int)u;
       W.donrec[od] = DonRec{W.bd[u], bu, k, L.type_s[k]};
