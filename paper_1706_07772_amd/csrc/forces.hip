@@ -39,8 +39,9 @@ __global__ __launch_bounds__(BS) void k_bo_prime(const DevParams* __restrict__ P
 }
 
 __global__ __launch_bounds__(BS) void k_delta_prime(const DevParams* __restrict__ P, Lists L, Work W) {
-  const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
-  if (i < L.n) delta_prime_atom(P, L, W, (int)i);
+  const int64_t t = xcd_block() * blockDim.x + threadIdx.x;
+  const int64_t i = t >> 2;   // four lanes per atom
+  if (i < L.n) delta_prime_atom<4>(P, L, W, (int)i, (int)(t & 3));
 }
 
 __global__ __launch_bounds__(BS) void k_bo_corr(const DevParams* __restrict__ P, Lists L, Work W) {
@@ -1029,8 +1030,9 @@ __global__ __launch_bounds__(BS) void k_back_corr(const DevParams* __restrict__ 
 }
 
 __global__ __launch_bounds__(BS) void k_back_dp(Lists L, Work W) {
-  const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
-  if (i < L.n) back_dp_atom(L, W, (int)i);
+  const int64_t t = xcd_block() * blockDim.x + threadIdx.x;
+  const int64_t i = t >> 2;   // four lanes per atom
+  if (i < L.n) back_dp_atom<4>(L, W, (int)i, (int)(t & 3));
 }
 
 // per-atom force gather, four lanes per atom over its entries, written in
@@ -1135,7 +1137,7 @@ int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, co
   if (fork) (void)hipEventRecord(ev_join, side);
   const dim3 grid_e(xcd_grid(nblk(std::max<int64_t>(nb, 1), BS)));   // one thread per bond entry
   LAUNCH(KID_BO_PRIME, k_bo_prime, grid_e, blk, 0, st, P, g, L, W);
-  LAUNCH(KID_DELTA_PRIME, k_delta_prime, grid, blk, 0, st, P, L, W);
+  LAUNCH(KID_DELTA_PRIME, k_delta_prime, dim3(xcd_grid(nblk(4 * n, BS))), blk, 0, st, P, L, W);
   LAUNCH(KID_BO_CORR, k_bo_corr, grid_e, blk, 0, st, P, L, W);
   LAUNCH(KID_ATOM_STATE, k_atom_state, grid, blk, 0, st, P, L, W);
   LAUNCH(KID_ATOM_ENERGY, k_atom_energy, grid, blk, 0, st, P, L, W, energies);
@@ -1162,7 +1164,7 @@ int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, co
   (void)hipMemcpyAsync(W.counters + 1, W.off_tor + nb, sizeof(int32_t), hipMemcpyDeviceToDevice, st);
   LAUNCH(KID_BACK_S, k_back_s, dim3(xcd_grid(nblk(4 * n, BS))), blk, 0, st, L, W);
   LAUNCH(KID_BACK_CORR, k_back_corr, grid_e, blk, 0, st, P, L, W);
-  LAUNCH(KID_BACK_DP, k_back_dp, grid, blk, 0, st, L, W);
+  LAUNCH(KID_BACK_DP, k_back_dp, dim3(xcd_grid(nblk(4 * n, BS))), blk, 0, st, L, W);
   // join: the force gather reads the nonbonded forces
   if (fork) (void)hipStreamWaitEvent(st, ev_join, 0);
   LAUNCH(KID_FORCES, k_forces, dim3(xcd_grid(nblk(4 * n, BS))), blk, 0, st, L, W, forces);

@@ -192,10 +192,14 @@ __device__ __forceinline__ void bo_prime_atom(const DevParams* __restrict__ P, c
 }
 
 // (2) Delta'_i = sum BO' - Val_i,  Delta'boc_i = sum BO' - Val_boc_i
+//     (G = 4: a quad of lanes per atom, lane sub over entries sub, sub + 4, ...)
+template <int G = 1>
 __device__ __forceinline__ void delta_prime_atom(const DevParams* __restrict__ P, const Lists& L,
-                                                 const Work& W, int i) {
+                                                 const Work& W, int i, int sub = 0) {
   double s = 0.0;
-  for (int e = L.bond_off[i]; e < L.bond_off[i + 1]; ++e) s += W.bop[e].w;
+  for (int e = L.bond_off[i] + sub; e < L.bond_off[i + 1]; e += G) s += W.bop[e].w;
+  if constexpr (G == 4) s = quad_sum(s);
+  if (sub != 0) return;
   const AtomP& a = P->atom[L.type_s[i]];
   W.dp[i] = make_double2(s - a.val, s - a.val_boc);
 }
@@ -787,10 +791,12 @@ __device__ __forceinline__ void back_corr_atom(const DevParams* __restrict__ P, 
 }
 
 // (12) dE/dDelta' of atom i (Delta' and Delta'boc both are sums of BO')
-__device__ __forceinline__ void back_dp_atom(const Lists& L, const Work& W, int i) {
+template <int G = 1>
+__device__ __forceinline__ void back_dp_atom(const Lists& L, const Work& W, int i, int sub = 0) {
   double g = 0.0;
-  for (int e = L.bond_off[i]; e < L.bond_off[i + 1]; ++e) g += W.gup[e].w;
-  W.gDp[i] = g;
+  for (int e = L.bond_off[i] + sub; e < L.bond_off[i + 1]; e += G) g += W.gup[e].w;
+  if constexpr (G == 4) g = quad_sum(g);
+  if (sub == 0) W.gDp[i] = g;
 }
 
 // (13) force on atom i: nonbonded/H-bond part plus its bond entries
