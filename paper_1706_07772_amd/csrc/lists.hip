@@ -454,24 +454,22 @@ __global__ void k_compact(int64_t n, const int32_t* __restrict__ cnt_bond,
   }
 }
 
-// mirror entry: position of i in the bond list of j
-__global__ void k_mirror(int64_t n, const int32_t* __restrict__ off, const int32_t* __restrict__ bj,
-                         int32_t* __restrict__ mir, int32_t* __restrict__ flag) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  for (int e = off[i]; e < off[i + 1]; ++e) {
-    const int j = bj[e];
-    int m = -1;
-    for (int f = off[j]; f < off[j + 1]; ++f)
-      if (bj[f] == (int)i) { m = f; break; }
-    // the bond predicate is symmetric, so the partner entry exists; should it
-    // not, point at the entry itself and raise the flag rather than index -1
-    if (m < 0) {
-      atomicOr(flag, 2);
-      m = e;
-    }
-    mir[e] = m;
+// mirror entry: position of i in the bond list of j (one thread per entry)
+__global__ void k_mirror(int64_t nbond, const int32_t* __restrict__ off, const int32_t* __restrict__ bj,
+                         const int32_t* __restrict__ bi, int32_t* __restrict__ mir, int32_t* __restrict__ flag) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= nbond) return;
+  const int i = bi[e], j = bj[e];
+  int m = -1;
+  for (int f = off[j]; f < off[j + 1]; ++f)
+    if (bj[f] == i) { m = f; break; }
+  // the bond predicate is symmetric, so the partner entry exists; should it
+  // not, point at the entry itself and raise the flag rather than index -1
+  if (m < 0) {
+    atomicOr(flag, 2);
+    m = (int)e;
   }
+  mir[e] = m;
 }
 
 // export helpers: lists in caller indices
@@ -637,8 +635,8 @@ int launch_compact(int64_t n, Scratch& sc, Lists& L, Prof& pf, hipStream_t st) {
                      sc.bond_w, L.bond_off, L.bond_j, L.bond_i);
   pf.end(st);
   pf.begin(KID_MIRROR, st);
-  hipLaunchKernelGGL(k_mirror, dim3(nblk(n, 256)), dim3(256), 0, st, n, L.bond_off, L.bond_j,
-                     L.bond_mir, sc.flag);
+  hipLaunchKernelGGL(k_mirror, dim3(nblk(std::max<int64_t>(L.nbond, 1), 256)), dim3(256), 0, st, L.nbond,
+                     L.bond_off, L.bond_j, L.bond_i, L.bond_mir, sc.flag);
   pf.end(st);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
