@@ -30,6 +30,8 @@ namespace rx {
 //            error (about 1e-7, then 1e-14, then rounding level).
 //   rcp_f:   1/x from the hardware reciprocal estimate and two Newton steps
 //            y <- y (2 - x y).
+//   rsq_f:   x^(-1/2) for finite x > 0 from the hardware estimate y and one
+//            third-order step y + y e (1/2 + 3/8 e), e = 1 - x y^2.
 //   exp_c:   exp_f after clamping the argument to [-1000, 1000] (exp is 0 or
 //            infinity beyond; the reduction then stays exact); NaN passes.
 //   pow_c:   x^y = exp_c(y log x) for x > 0, with 0^y spelled out.
@@ -64,6 +66,12 @@ __device__ __forceinline__ double rcp_f(double x) {
   y = y * fma(-x, y, 2.0);
   y = y * fma(-x, y, 2.0);
   return y;
+}
+
+__device__ __forceinline__ double rsq_f(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y, y, 1.0);
+  return fma(y * e, fma(0.375, e, 0.5), y);
 }
 
 __device__ __forceinline__ double log_f(double x) {
@@ -628,7 +636,7 @@ __device__ __forceinline__ HbTerm hb_term(const HbP& hp, double bo, double4 rx, 
   // reciprocals and the length from rcp_f / rsqrt (a few ulp), not IEEE
   // division and square root
   const double ilx = rcp_f(rx.w);
-  const double ilz = rsqrt(dx * dx + dy * dy + dz * dz);
+  const double ilz = rsq_f(dx * dx + dy * dy + dz * dz);
   const double rz = (dx * dx + dy * dy + dz * dz) * ilz;
   const double ir0 = rcp_f(hp.r0hb);
   const double c = (rx.x * dx + rx.y * dy + rx.z * dz) * ilx * ilz;
@@ -664,7 +672,7 @@ struct NbOut { double ev, eq, f; };
 
 __device__ __forceinline__ NbOut nb_pair(const NbP& p, double iR, double pv, double ipv, double qq,
                                          double r2) {
-  const double ir = rsqrt(r2);
+  const double ir = rsq_f(r2);
   const double r = r2 * ir;
   // taper 1 - 35u^4 + 84u^5 - 70u^6 + 20u^7 in Horner form, and its
   // derivative 140 u^3 (u - 1)^3 / R
