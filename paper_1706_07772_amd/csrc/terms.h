@@ -25,9 +25,11 @@ namespace rx {
 //            below 1e-17) economized to degree 6 by shifted Chebyshev
 //            polynomials on z in [0, 0.02944]: |p error| < 1.6e-16, so the
 //            relative error it adds to log m is below z * 1.6e-16 < 5e-18.
-//   rcbrt_f: x^(-1/3) from a single-precision seed 2^(-log2(x)/3) and two
-//            Newton steps y <- y (4 - x y^3) / 3, each squaring the relative
-//            error (about 1e-7, then 1e-14, then rounding level).
+//   rcbrt_f: x^(-1/3) from a single-precision seed y = 2^(-log2(x)/3)
+//            (relative error about 1e-7) and one step of the series
+//            (1 - e)^(-1/3) = 1 + e/3 + 2e^2/9 + ..., e = 1 - x y^3, taken to
+//            second order: y <- y (1 + e (1/3 + 2e/9)); the error left is
+//            about e^3 / 6, far below rounding.
 //   rcp_f:   1/x from the hardware reciprocal estimate and two Newton steps
 //            y <- y (2 - x y).
 //   rsq_f:   x^(-1/2) for finite x > 0 from the hardware estimate y and one
@@ -98,10 +100,9 @@ __device__ __forceinline__ double log_f(double x) {
 
 __device__ __forceinline__ double rcbrt_f(double x) {
   const float xf = (float)x;
-  double y = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf(xf) * (-1.0f / 3.0f));
-  y = y * fma(-x, y * y * y, 4.0) * (1.0 / 3.0);
-  y = y * fma(-x, y * y * y, 4.0) * (1.0 / 3.0);
-  return y;
+  const double y = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf(xf) * (-1.0f / 3.0f));
+  const double e = fma(-x, y * y * y, 1.0);
+  return fma(y, e * fma(e, 2.0 / 9.0, 1.0 / 3.0), y);
 }
 
 __device__ __forceinline__ double exp_c(double x) {
