@@ -349,7 +349,9 @@ int reaxff_build_lists(reaxff_ctx* c, int64_t n, const double* pos, const int32_
       const double m = rho * 4.18879 * r * r * r;
       return (int32_t)std::min<double>((double)std::max<int64_t>(n, 1), 1.3 * m + 32.0);
     };
-    if (c->L.far_w == 0) c->L.far_w = est(c->cut.r_nonb);
+    c->L.far_upper = c->L.far_slots && !c->upper_off && !c->grid.full[0] && !c->grid.full[1] &&
+                     !c->grid.full[2];
+    if (c->L.far_w == 0) c->L.far_w = c->L.far_upper ? est(c->cut.r_nonb) / 2 + 32 : est(c->cut.r_nonb);
     if (c->L.hb_w == 0) c->L.hb_w = est(c->cut.r_hb);
     if (c->L.ha_w == 0) c->L.ha_w = est(c->cut.r_hb);
     if (c->sc.cand_w == 0) c->sc.cand_w = 32;
@@ -404,10 +406,17 @@ int reaxff_build_lists(reaxff_ctx* c, int64_t n, const double* pos, const int32_
     widen(c->sc.bond_w, need[2]);
     widen(c->L.hb_w, need[3]);
     widen(c->L.ha_w, need[4]);
+    // upper-only rows serve the half evaluation alone; without it, sweep
+    // again with full rows (and keep them for later builds)
+    if (c->L.far_upper && n > 0 && !(need[5] > 0 && need[5] <= NB_HALF_CAP)) {
+      c->upper_off = true;
+      c->L.far_upper = 0;
+      again = true;
+    }
     if (!again) break;
     if (attempt >= 3) return fail(c, REAXFF_ERR_CAPACITY, "list widths did not converge");
   }
-  c->L.nfar = th[0] / 2;
+  c->L.nfar = c->L.far_upper ? th[0] : th[0] / 2;
   // half nonbonded evaluation when every cell's upper stencil fits in LDS
   // (need[5], reported by the sweep; zero when a dimension is covered whole)
   c->L.cell_of = c->sc.cell_s;

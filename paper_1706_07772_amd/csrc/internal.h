@@ -133,6 +133,7 @@ struct reaxff_ctx {
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool overlap = true;
+  bool upper_off = false;   // a build found the half evaluation impossible: full far rows from then on
   bool built = false;
   double box[3] = {0, 0, 0};
   bool periodic = false;

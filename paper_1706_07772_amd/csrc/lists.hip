@@ -135,7 +135,8 @@ __global__ void k_gather_sorted(const double* __restrict__ pos, const int32_t* _
 constexpr int SWEEP_WAVES = 4;
 constexpr int SWEEP_MAXQ = 64;   // chunks of a stencil: 2 (2 reach + 1)^2 <= 50
 
-template <bool MINIMG>
+// UPPER: far rows keep only the entries after the centre's own slot.
+template <bool MINIMG, bool UPPER>
 __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
     const DevParams* __restrict__ P, Grid g, int ncell, const double4* __restrict__ xs,
     const int32_t* __restrict__ cstart, int32_t* __restrict__ far_cnt, int32_t* __restrict__ far_j,
@@ -233,7 +234,7 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
       const unsigned long long vmask = ballot(valid), accl = ballot(valid && acc), donl = ballot(valid && don);
       // batches holding some centre's own slot set that centre's count of
       // entries before it; the others run the loop without that code
-      const bool hasown = halfable && b0 < own0 + ig + mi && b0 + 64 > own0 + ig;
+      const bool hasown = !UPPER && halfable && b0 < own0 + ig + mi && b0 + 64 > own0 + ig;
       auto centres = [&](auto own_t) {
         constexpr bool OWN = decltype(own_t)::value;
         // the centre's position and far row, advanced with the centre
@@ -267,14 +268,21 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
             }
           }
           if (mf) {
-            const int k0 = readlane_i(kf, l);
-            if (f) {
-              const int k = k0 + __popcll(mf & below);
-              // list rows are streamed out (non-temporal), keeping the
-              // stencil's positions in L2
-              if (k < far_w) __builtin_nontemporal_store(slots ? slot : s, &frow[k]);
+            // far entries: all, or (UPPER) those after the own slot, whose
+            // lane in this batch is d
+            unsigned long long mfu = mf;
+            const int d = own0 + ig + l - b0;
+            if constexpr (UPPER) mfu = d < 0 ? mf : (d >= 63 ? 0ull : (mf & (~0ull << (d + 1))));
+            if (mfu) {
+              const int k0 = readlane_i(kf, l);
+              if (f && (!UPPER || lane > d)) {
+                const int k = k0 + __popcll(mfu & below);
+                // list rows are streamed out (non-temporal), keeping the
+                // stencil's positions in L2
+                if (k < far_w) __builtin_nontemporal_store(slots ? slot : s, &frow[k]);
+              }
+              kf = writelane_i(k0 + __popcll(mfu), l, kf);
             }
-            kf = writelane_i(k0 + __popcll(mf), l, kf);
             // bond candidates: the pair reach (by the centre's type) is only
             // selected when some lane lies within the largest one
             if (mf & ballot(r2 <= rb2)) {
@@ -480,7 +488,7 @@ __global__ void k_mirror(int64_t nbond, const int32_t* __restrict__ off, const i
 template <bool WRITE>
 __global__ void k_export_far(int64_t n, Grid g, const int32_t* __restrict__ cstart,
                              const int32_t* __restrict__ cell_s, const int32_t* __restrict__ cnt,
-                             const int32_t* __restrict__ fj, int far_w, int slots,
+                             const int32_t* __restrict__ fj, int far_w, int slots, int upper,
                              const int32_t* __restrict__ perm, int32_t* __restrict__ hcnt,
                              const int64_t* __restrict__ hoff, int32_t* __restrict__ out) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -502,7 +510,7 @@ __global__ void k_export_far(int64_t n, Grid g, const int32_t* __restrict__ csta
       }
       j = s0 + (j - base);
     }
-    if (j > (int)i) {
+    if (upper || j > (int)i) {   // upper rows hold each pair once
       if (WRITE) {
         const int pj = perm[j];
         out[2 * o] = pi < pj ? pi : pj;
@@ -605,18 +613,21 @@ int launch_sweep(const DevParams* P, const Grid& g, int64_t n, int ncell, Scratc
   (void)hipMemsetAsync(sc.tslot, 0, sizeof(int64_t) * 8 * ESLOT, st);
   (void)hipMemsetAsync(sc.nslot, 0, sizeof(int32_t) * ESLOT, st);
   pf.begin(KID_LIST_SWEEP, st);
-  if (g.periodic && !g.shift_ok)
-    hipLaunchKernelGGL(k_sweep<true>, dim3(nblk(ncell, SWEEP_WAVES)), dim3(64 * SWEEP_WAVES), 0, st, P, g,
-                       ncell, L.xs, L.cell_start, L.far_cnt, L.far_j, L.far_w, sc.cnt_cand, sc.cand_j,
-                       sc.cand_w, L.hb_cnt, L.hb_j, L.hb_w, L.ha_cnt, L.ha_j, L.ha_w, L.far_slots,
-                     L.far_slots ? L.far_lo : nullptr, sc.need,
+  auto sweep = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(nblk(ncell, SWEEP_WAVES)), dim3(64 * SWEEP_WAVES), 0, st, P, g, ncell, L.xs,
+                       L.cell_start, L.far_cnt, L.far_j, L.far_w, sc.cnt_cand, sc.cand_j, sc.cand_w, L.hb_cnt,
+                       L.hb_j, L.hb_w, L.ha_cnt, L.ha_j, L.ha_w, L.far_slots,
+                       L.far_slots ? L.far_lo : nullptr, sc.need,
                        reinterpret_cast<unsigned long long*>(sc.tslot), sc.nslot);
-  else
-    hipLaunchKernelGGL(k_sweep<false>, dim3(nblk(ncell, SWEEP_WAVES)), dim3(64 * SWEEP_WAVES), 0, st, P, g,
-                       ncell, L.xs, L.cell_start, L.far_cnt, L.far_j, L.far_w, sc.cnt_cand, sc.cand_j,
-                       sc.cand_w, L.hb_cnt, L.hb_j, L.hb_w, L.ha_cnt, L.ha_j, L.ha_w, L.far_slots,
-                     L.far_slots ? L.far_lo : nullptr, sc.need,
-                       reinterpret_cast<unsigned long long*>(sc.tslot), sc.nslot);
+  };
+  const bool minimg = g.periodic && !g.shift_ok;
+  if (minimg) {
+    if (L.far_upper) sweep(k_sweep<true, true>);
+    else sweep(k_sweep<true, false>);
+  } else {
+    if (L.far_upper) sweep(k_sweep<false, true>);
+    else sweep(k_sweep<false, false>);
+  }
   pf.end(st);
   pf.begin(KID_BONDTEST, st);
   hipLaunchKernelGGL(k_bondtest, dim3(xcd_grid(std::min<int64_t>(nblk(n, BT_TILE), 4096))), dim3(BT_BS), 0, st,
@@ -651,11 +662,11 @@ int launch_export(const Grid& g, const Lists& L, int32_t* far, int32_t* bonds, i
   if (far) {
     (void)hipMemsetAsync(hcnt + n, 0, sizeof(int32_t), st);
     hipLaunchKernelGGL(k_export_far<false>, dim3(nblk(n, 256)), dim3(256), 0, st, n, g, L.cell_start,
-                       sc.cell_s, L.far_cnt, L.far_j, L.far_w, L.far_slots, L.perm, hcnt, nullptr,
+                       sc.cell_s, L.far_cnt, L.far_j, L.far_w, L.far_slots, L.far_upper, L.perm, hcnt, nullptr,
                        nullptr);
     scan_i32_to_i64(hcnt, hoff, n + 1, sc, st);
     hipLaunchKernelGGL(k_export_far<true>, dim3(nblk(n, 256)), dim3(256), 0, st, n, g, L.cell_start,
-                       sc.cell_s, L.far_cnt, L.far_j, L.far_w, L.far_slots, L.perm, nullptr, hoff, far);
+                       sc.cell_s, L.far_cnt, L.far_j, L.far_w, L.far_slots, L.far_upper, L.perm, nullptr, hoff, far);
   }
   if (bonds)
     hipLaunchKernelGGL(k_export_csr, dim3(nblk(n, 256)), dim3(256), 0, st, n, L.bond_off, L.bond_j,

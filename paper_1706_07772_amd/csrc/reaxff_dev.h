@@ -99,6 +99,11 @@ struct Lists {
   // entries of row i precede i's own slot; the pairs of the rest of the row
   // are evaluated by i's cell, the others by the partner's cell
   int32_t* far_lo;      // [n]
+  // far_upper: rows hold only the entries after the centre's own slot, so
+  // each pair appears once, in the row of the atom whose cell evaluates it
+  // (far_lo is then 0).  Set when the half evaluation is expected; a build
+  // that finds it impossible sweeps again with full rows.
+  int32_t far_upper;
   int32_t nb_half;
   int32_t* cell_of;     // [n] cell of each sorted atom
   // full bond list
