@@ -368,8 +368,16 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
 // candidate per lane: a candidate is a bond iff its raw uncorrected bond order
 // reaches bo_cut.  Accepted candidates keep their candidate order (numbered
 // with the group's ballot).  Workgroups stride over tiles of 16 atoms and
-// add their task-list bounds to the three totals once per workgroup.
+// add their task-list bounds to the three totals once per workgroup.  The
+// pair parameters the test reads sit in LDS, and the next tile's atoms,
+// counts and first 16 candidates are loaded while this tile is tested, so a
+// tile waits on one global load (the candidates' positions) instead of four
+// dependent ones.
 constexpr int BT_GROUP = 16, BT_BS = 256, BT_TILE = BT_BS / BT_GROUP;
+
+struct BondTestP {
+  double r_s, r_p, r_pp, p_bo1, p_bo2, p_bo3, p_bo4, p_bo5, p_bo6, ln_r_s, ln_r_p, ln_r_pp;
+};
 
 __global__ __launch_bounds__(BT_BS) void k_bondtest(
     const DevParams* __restrict__ P, Grid g, int64_t n, const double4* __restrict__ xs,
@@ -377,16 +385,40 @@ __global__ __launch_bounds__(BT_BS) void k_bondtest(
     int32_t* __restrict__ cnt_bond, int32_t* __restrict__ bond_t, int bond_w,
     int32_t* __restrict__ need, unsigned long long* __restrict__ tslot) {
   __shared__ unsigned long long red[BT_BS / 64][3];
+  __shared__ BondTestP bp[NT * NT];
+  for (int t = threadIdx.x; t < NT * NT; t += BT_BS) {
+    const PairP& q = P->pair[t];
+    bp[t] = BondTestP{q.r_s, q.r_p, q.r_pp, q.p_bo1, q.p_bo2, q.p_bo3, q.p_bo4, q.p_bo5, q.p_bo6,
+                      q.ln_r_s, q.ln_r_p, q.ln_r_pp};
+  }
+  __syncthreads();
   const int lane = threadIdx.x & 63, sub = lane & (BT_GROUP - 1), gsh = lane & ~(BT_GROUP - 1);
   const double bo_cut = P->bo_cut;
   unsigned long long ba = 0, bt = 0, bd = 0;
   const int64_t ntile = (n + BT_TILE - 1) / BT_TILE;
-  for (int64_t tile = xcd_block(); tile < ntile; tile += gridDim.x) {
+  if (n <= 0) return;
+  // the loads of a tile that do not depend on its candidates, made for every
+  // lane (atoms past the end read the last atom; rows are cand_w wide, so
+  // the first entries exist whatever the count) so that no wait follows them
+  double4 xi_n;
+  int cnt_n;
+  int32_t s_n;
+  auto fetch = [&](int64_t tile) {
+    int64_t i = tile * BT_TILE + threadIdx.x / BT_GROUP;
+    i = i < n ? i : n - 1;
+    xi_n = xs[i];
+    cnt_n = cnt_cand[i];
+    s_n = cand_j[i * (int64_t)cand_w + (sub < cand_w ? sub : 0)];
+  };
+  int64_t tile = xcd_block();
+  fetch(tile);
+  for (; tile < ntile; tile += gridDim.x) {
     const int64_t i = tile * BT_TILE + threadIdx.x / BT_GROUP;
     const bool live = i < n;
-    const double4 xi = live ? xs[i] : make_double4(0.0, 0.0, 0.0, 0.0);
+    const double4 xi = xi_n;
     const int ti = (int)xi.w;
-    const int nc = live ? (cnt_cand[i] < cand_w ? cnt_cand[i] : cand_w) : 0;
+    const int nc = live ? (cnt_n < cand_w ? cnt_n : cand_w) : 0;
+    const int32_t s_first = s_n;
     const int32_t* crow = cand_j + (live ? i : 0) * (int64_t)cand_w;
     int32_t* brow = bond_t + (live ? i : 0) * (int64_t)bond_w;
     // the longest candidate row of the wavefront bounds its (uniform) loop
@@ -395,11 +427,12 @@ __global__ __launch_bounds__(BT_BS) void k_bondtest(
     int nb = 0;
     for (int k0 = 0; k0 < ncmax; k0 += BT_GROUP) {
       const int k = k0 + sub;
+      const bool in = k < nc;
+      const int s = in ? (k0 == 0 ? s_first : crow[k]) : 0;
+      const double4 xj = xs[s];
+      if (k0 == 0) fetch(tile + gridDim.x);
       bool ok = false;
-      int s = 0;
-      if (k < nc) {
-        s = crow[k];
-        const double4 xj = xs[s];
+      if (in) {
         double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
         if (g.periodic) {
           dx = min_image(dx, g.L[0], g.invL[0]);
@@ -407,7 +440,7 @@ __global__ __launch_bounds__(BT_BS) void k_bondtest(
           dz = min_image(dz, g.L[2], g.invL[2]);
         }
         const double r2 = r2_of(dx, dy, dz);
-        ok = bo_raw(P->pair[ti * NT + (int)xj.w], sqrt(r2), bo_cut) >= bo_cut;
+        ok = bo_raw(bp[ti * NT + (int)xj.w], sqrt(r2), bo_cut) >= bo_cut;
       }
       const unsigned mask = (unsigned)(ballot(ok) >> gsh) & ((1u << BT_GROUP) - 1u);
       if (ok) {
@@ -416,6 +449,7 @@ __global__ __launch_bounds__(BT_BS) void k_bondtest(
       }
       nb += __popc(mask);
     }
+    if (ncmax == 0) fetch(tile + gridDim.x);
     if (live && sub == 0) {
       cnt_bond[i] = nb;
       if (nb > bond_w) atomicMax(&need[2], nb);

@@ -137,7 +137,10 @@ __device__ __forceinline__ void atomic_add3(double4* p, double3 v) { atomic_add3
 
 // raw uncorrected bond order sum of sigma, pi and pi-pi (the bond-list test)
 // ((r / r_x)^p as exp(p (log r - log r_x)): one log for the three terms)
-__device__ __forceinline__ double bo_raw(const PairP& p, double r, double bo_cut) {
+// (PP: PairP, or any record with the same bond-order members, such as a
+// workgroup's LDS copy of them)
+template <class PP>
+__device__ __forceinline__ double bo_raw(const PP& p, double r, double bo_cut) {
   double s = 0.0, pi = 0.0, pp = 0.0;
   const double lr = log_f(r);
   if (p.r_s > 0.0) s = (1.0 + bo_cut) * exp_c(p.p_bo1 * exp_c(p.p_bo2 * (lr - p.ln_r_s)));
