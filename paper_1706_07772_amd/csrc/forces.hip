@@ -345,6 +345,11 @@ __global__ __launch_bounds__(BS) void k_torsions(const DevParams* __restrict__ P
 
 __global__ __launch_bounds__(BS) void k_hbonds(const DevParams* __restrict__ P, Grid g, Lists L, Work W,
                                                double* __restrict__ energies) {
+  // the H-bond parameters in LDS: a neighbour's record is then one LDS read
+  // after its position arrives
+  __shared__ HbP hbt[NT * NT * NT];
+  for (int q = threadIdx.x; q < NT * NT * NT; q += BS) hbt[q] = P->hb[q];
+  __syncthreads();
   const int64_t ntask = W.off_don[L.nbond];
   double ehb = 0.0;
   unsigned long long nhb = 0;
@@ -362,11 +367,21 @@ __global__ __launch_bounds__(BS) void k_hbonds(const DevParams* __restrict__ P, 
     double3 gx = make_double3(0.0, 0.0, 0.0), fh = make_double3(0.0, 0.0, 0.0);
     const int nz = L.hb_cnt[h];
     const int32_t* __restrict__ zrow = L.hb_j + (int64_t)h * L.hb_w;
+    // software pipeline over the row: entry s+1's position and entry s+2's
+    // index are loaded while entry s is evaluated (indices clamped to the
+    // row's last entry; an empty row reads X)
+    const int zl = nz - 1;
+    int zc = nz > 0 ? zrow[0] : X;
+    double4 xzc = L.xs[zc];
+    int zn = nz > 1 ? zrow[1] : zc;
     for (int s = 0; s < nz; ++s) {
-      const int Z = zrow[s];
+      const int Z = zc;
+      const double4 xz = xzc;   // position and type
+      zc = zn;
+      xzc = L.xs[zn];
+      zn = zrow[s + 2 < zl ? s + 2 : zl];
       if (Z == X) continue;
-      const double4 xz = L.xs[Z];   // position and type
-      const HbP& hp = P->hb[(tx * NT + th) * NT + (int)xz.w];
+      const HbP& hp = hbt[(tx * NT + th) * NT + (int)xz.w];
       ++nhb;
       double dx = xz.x - xh.x, dy = xz.y - xh.y, dz = xz.z - xh.z;
       if (g.periodic) {
@@ -416,6 +431,9 @@ constexpr int HB_PACK = 128;   // listed (H, task) pairs per acceptor
 __global__ __launch_bounds__(BS) void k_hb_acceptors(const DevParams* __restrict__ P, Grid g, Lists L,
                                                      Work W) {
   __shared__ int2 pk[BS / HB_GROUP][HB_PACK];
+  __shared__ HbP hbt[NT * NT * NT];
+  for (int q = threadIdx.x; q < NT * NT * NT; q += BS) hbt[q] = P->hb[q];
+  __syncthreads();
   const int lane = threadIdx.x & 63, sub = lane & (HB_GROUP - 1);
   int2* __restrict__ mylist = pk[threadIdx.x / HB_GROUP];
   const int64_t z = (xcd_block() * BS + threadIdx.x) / HB_GROUP;
@@ -460,7 +478,7 @@ __global__ __launch_bounds__(BS) void k_hb_acceptors(const DevParams* __restrict
       dy = min_image(dy, g.L[1], g.invL[1]);
       dz = min_image(dz, g.L[2], g.invL[2]);
     }
-    const HbP& hp = P->hb[(d.tX * NT + th) * NT + tz];
+    const HbP& hp = hbt[(d.tX * NT + th) * NT + tz];
     const HbTerm o = hb_term(hp, d.bo, d.bd, dx, dy, dz);
     fz.x -= o.g_rz.x;
     fz.y -= o.g_rz.y;
