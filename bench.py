@@ -44,7 +44,7 @@ WORK = {
 # recorded in profiles/kernels_petn_1044000.md.  Valid only for the kernel
 # version they were taken on; set to None when the kernel changes.
 TRAFFIC = {
-    "nonbonded": 2.732e9,
+    "nonbonded": 2.725e9,
 }
 
 PHASES = {
