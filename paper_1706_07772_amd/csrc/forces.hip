@@ -66,53 +66,77 @@ __global__ __launch_bounds__(BS) void k_tasks(const DevParams* __restrict__ P, L
   // one thread per bond entry u = j->k; the entries of an atom are
   // consecutive, so the tasks come out in the order of the atom-major
   // enumeration: angles (u, v > u) centred on j, torsions about u when k > j,
-  // and the donor bond u when j is a hydrogen
+  // and the donor bond u when j is a hydrogen.  The first TK_C entries of j
+  // and of k (bond order, partner) are read into registers in one batch of
+  // loads, since the angle and torsion loops both walk them; entries past
+  // TK_C are read from memory.
+  constexpr int TK_C = 8;
   const int64_t u = xcd_block() * blockDim.x + threadIdx.x;
   if (FILL && u < L.n) W.don_rng[u] = make_int2(W.off_don[L.bond_off[u]], W.off_don[L.bond_off[u + 1]]);
   if (u >= L.nbond) return;
   const double thb = P->thb_cut, thb2 = P->thb_cutsq;
+  // H-bond roles of the types as bit masks (uniform loads)
+  unsigned hmask = 0, amask = 0;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    hmask |= (P->atom[t].hbond == 1 ? 1u : 0u) << t;
+    amask |= (P->atom[t].hbond == 2 ? 1u : 0u) << t;
+  }
   const int j = L.bond_i[u];
-  const int e1 = L.bond_off[j + 1];
   const int k = L.bond_j[u];
   const double bu = W.bo1[u];
+  const int e0 = L.bond_off[j], e1 = L.bond_off[j + 1];
+  const int f0 = L.bond_off[k], f1 = L.bond_off[k + 1];
+  const int dj = e1 - e0, dk = f1 - f0, qu = (int)u - e0;
+  double boj[TK_C], bok[TK_C];
+  int nj[TK_C], nk[TK_C];
+#pragma unroll
+  for (int q = 0; q < TK_C; ++q) {
+    boj[q] = q < dj ? W.bo1[e0 + q] : 0.0;
+    nj[q] = q < dj ? L.bond_j[e0 + q] : -1;
+    bok[q] = q < dk ? W.bo1[f0 + q] : 0.0;
+    nk[q] = q < dk ? L.bond_j[f0 + q] : -1;
+  }
   int na = 0, nt = 0, nd = 0;
   const int oa = FILL ? W.off_ang[u] : 0, ot = FILL ? W.off_tor[u] : 0, od = FILL ? W.off_don[u] : 0;
-  // the fill pass knows the counts: it skips empty kinds and stops at the
-  // last task of a kind
+  // the fill pass knows the counts: it skips empty kinds
   const int ca = FILL ? W.cnt_ang[u] : 0, ct = FILL ? W.cnt_tor[u] : 0, cd = FILL ? W.cnt_don[u] : 0;
   // angles (u, v), u < v
   if (FILL ? ca > 0 : bu - thb > 0.0) {
-    for (int v = (int)u + 1; v < e1 && (!FILL || na < ca); ++v) {
-      const double bv = W.bo1[v];
+    auto ang = [&](int v, double bv) {
       if (bv - thb > 0.0 && bu * bv > thb2) {
         if (FILL) W.ang[oa + na] = make_int2((int)u, v);
         ++na;
       }
-    }
+    };
+#pragma unroll
+    for (int q = 0; q < TK_C; ++q)
+      if (q > qu && q < dj) ang(e0 + q, boj[q]);
+    for (int v = e0 + (qu + 1 > TK_C ? qu + 1 : TK_C); v < e1; ++v) ang(v, W.bo1[v]);
   }
-  // torsions about the central bond u = j->k, k > j
+  // torsions about the central bond u = j->k, k > j: entries a of j (a != u)
+  // and b of k, in that nesting
   if (FILL ? ct > 0 : (k > j && bu > thb)) {
-    const int e0 = L.bond_off[j];
-    const int f0 = L.bond_off[k], f1 = L.bond_off[k + 1];
-    for (int a = e0; a < e1 && (!FILL || nt < ct); ++a) {
-      if (a == (int)u) continue;
-      const double ba = W.bo1[a];
-      if (!(ba > thb)) continue;
-      const int i = L.bond_j[a];
-      for (int b = f0; b < f1; ++b) {
-        const int l = L.bond_j[b];
-        if (l == j || l == i) continue;
-        const double bb = W.bo1[b];
-        if (!(bb > thb)) continue;
-        if (!(ba * bu * bb > thb)) continue;
+    auto tor = [&](int a, double ba, int i) {
+      if (a == (int)u || !(ba > thb)) return;
+      auto one = [&](int b, double bb, int l) {
+        if (l == j || l == i || !(bb > thb) || !(ba * bu * bb > thb)) return;
         if (FILL) W.tor[ot + nt] = make_int4((int)u, a, b, 0);
         ++nt;
-      }
-    }
+      };
+#pragma unroll
+      for (int r = 0; r < TK_C; ++r)
+        if (r < dk) one(f0 + r, bok[r], nk[r]);
+      for (int b = f0 + TK_C; b < f1; ++b) one(b, W.bo1[b], L.bond_j[b]);
+    };
+#pragma unroll
+    for (int q = 0; q < TK_C; ++q)
+      if (q < dj) tor(e0 + q, boj[q], nj[q]);
+    for (int a = e0 + TK_C; a < e1; ++a) tor(a, W.bo1[a], L.bond_j[a]);
   }
   // donor bond
   if (FILL ? cd > 0
-           : (P->atom[L.type_s[j]].hbond == 1 && P->atom[L.type_s[k]].hbond == 2 && bu >= P->hb_bo_cut &&
+           : (((hmask >> L.type_s[j]) & 1u) && ((amask >> L.type_s[k]) & 1u) && bu >= P->hb_bo_cut &&
               L.hb_cnt[j] > 0)) {
     if (FILL) {
       W.don[od] = (int)u;
