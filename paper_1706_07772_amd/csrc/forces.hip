@@ -357,9 +357,11 @@ __global__ __launch_bounds__(BS) void k_torsions(const DevParams* __restrict__ P
   block_add<BS>(econj, eslot(W.epart) + E_CONJ);
 }
 
+constexpr int HB_DROW = 16;   // lanes per donor task
+
 // ---------------------------------------------------------------------------
 // (8) hydrogen bonds.  Each term X-H...Z moves three atoms.  The donor side
-//     (one thread per donor bond H-X, over H's acceptor row) sums the energy,
+//     (16 lanes per donor bond H-X, striding over H's acceptor row) sums the energy,
 //     the adjoints of the H-X bond entry and the force on H.  The acceptor
 //     side (16 lanes per acceptor Z, over Z's acceptor row: the donors H
 //     within r_hb, found by the sweep with the H list's own predicate)
@@ -377,34 +379,30 @@ __global__ __launch_bounds__(BS) void k_hbonds(const DevParams* __restrict__ P, 
   const int64_t ntask = W.off_don[L.nbond];
   double ehb = 0.0;
   unsigned long long nhb = 0;
-  // one task per thread; XCD k takes the k-th eighth of the blocks with work
-  const int64_t ab = xcd_active_block((ntask + BS - 1) / BS);
-  const int64_t t = ab * BS + threadIdx.x;
-  if (ab >= 0 && t < ntask) {
-    const int ex = W.don[t];
-    const int h = L.bond_i[ex], X = L.bond_j[ex];
+  // one 16-lane row per task, the lanes striding over H's row of acceptor
+  // candidates; XCD k takes the k-th eighth of the blocks with work
+  constexpr int TPB = BS / HB_DROW;
+  const int sub = threadIdx.x & (HB_DROW - 1);
+  const int64_t ab = xcd_active_block((ntask + TPB - 1) / TPB);
+  const int64_t t = ab * TPB + threadIdx.x / HB_DROW;
+  const bool live = ab >= 0 && t < ntask;
+  double gbo = 0.0;
+  double3 gx = make_double3(0.0, 0.0, 0.0), fh = make_double3(0.0, 0.0, 0.0);
+  int ex = 0, h = 0;
+  if (live) {
+    ex = W.don[t];
+    h = L.bond_i[ex];
+    const int X = L.bond_j[ex];
     const int th = L.type_s[h], tx = L.type_s[X];
     const double4 xh = L.xs[h];
     const double bo = W.bo1[ex];
     const double4 rx = W.bd[ex];     // x_X - x_h
-    double gbo = 0.0;
-    double3 gx = make_double3(0.0, 0.0, 0.0), fh = make_double3(0.0, 0.0, 0.0);
     const int nz = L.hb_cnt[h];
     const int32_t* __restrict__ zrow = L.hb_j + (int64_t)h * L.hb_w;
-    // software pipeline over the row: entry s+1's position and entry s+2's
-    // index are loaded while entry s is evaluated (indices clamped to the
-    // row's last entry; an empty row reads X)
-    const int zl = nz - 1;
-    int zc = nz > 0 ? zrow[0] : X;
-    double4 xzc = L.xs[zc];
-    int zn = nz > 1 ? zrow[1] : zc;
-    for (int s = 0; s < nz; ++s) {
-      const int Z = zc;
-      const double4 xz = xzc;   // position and type
-      zc = zn;
-      xzc = L.xs[zn];
-      zn = zrow[s + 2 < zl ? s + 2 : zl];
+    for (int s = sub; s < nz; s += HB_DROW) {
+      const int Z = zrow[s];
       if (Z == X) continue;
+      const double4 xz = L.xs[Z];   // position and type
       const HbP& hp = hbt[(tx * NT + th) * NT + (int)xz.w];
       ++nhb;
       double dx = xz.x - xh.x, dy = xz.y - xh.y, dz = xz.z - xh.z;
@@ -419,7 +417,17 @@ __global__ __launch_bounds__(BS) void k_hbonds(const DevParams* __restrict__ P, 
       gx = add3(gx, o.g_rx);
       fh = add3(fh, o.g_rz);            // r_hZ = x_Z - x_h: F_h = +dE/dr_hZ
     }
-    // the entry h->X belongs to this task alone
+  }
+  // row sums (every lane takes part), written by the row's last lane: the
+  // entry h->X belongs to this task alone
+  gbo = row_sum_last(gbo);
+  gx.x = row_sum_last(gx.x);
+  gx.y = row_sum_last(gx.y);
+  gx.z = row_sum_last(gx.z);
+  fh.x = row_sum_last(fh.x);
+  fh.y = row_sum_last(fh.y);
+  fh.z = row_sum_last(fh.z);
+  if (live && sub == HB_DROW - 1) {
     double4 gv = W.gvec[ex];
     gv.x += gx.x;
     gv.y += gx.y;
@@ -1200,7 +1208,8 @@ int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, co
   LAUNCH(KID_ANGLES, k_angles, dim3(xcd_grid((L.bound_ang + BS - 1) / BS)), blk, 0,
          st, P, L, W, energies);
   LAUNCH(KID_TORSIONS, k_torsions, gt, blk, 0, st, P, L, W, energies);
-  LAUNCH(KID_HBONDS, k_hbonds, dim3(xcd_grid((L.bound_don + BS - 1) / BS)), blk, 0, st, P, g, L, W, energies);
+  LAUNCH(KID_HBONDS, k_hbonds, dim3(xcd_grid((L.bound_don + BS / HB_DROW - 1) / (BS / HB_DROW))), blk, 0, st, P, g,
+         L, W, energies);
   LAUNCH(KID_HB_ACC, k_hb_acceptors, dim3(xcd_grid(nblk(n, BS / HB_GROUP))), blk, 0, st, P, g, L, W);
   (void)hipMemcpyAsync(W.counters, W.off_ang + nb, sizeof(int32_t), hipMemcpyDeviceToDevice, st);
   (void)hipMemcpyAsync(W.counters + 1, W.off_tor + nb, sizeof(int32_t), hipMemcpyDeviceToDevice, st);
