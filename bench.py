@@ -25,18 +25,24 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_VALU_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
-# Kernel work models (algorithmic work: what the method requires).
-# nonbonded: FP64 operations of one pair evaluation (v_fma/v_fmac/v_div_fmas
-# counted as 2, v_add, v_mul, v_rcp, v_rsq as 1; compares, conversions and
-# exponent manipulation not counted), read once from the gfx950 assembly of
-# the pair term built on the ROCm device library's exp, log, cbrt and
-# division, per UNORDERED far pair (the energy and both atoms' forces of a
-# pair follow from one evaluation; a kernel that evaluates each pair from both
-# of its atoms does twice this work).  The figure is kept fixed as the unit of
-# work: the kernel's own elementary functions now take fewer operations
-# (about 320 per evaluation), which shows up as time, not as a smaller unit.
+# Algorithmic work per unit, in FP64 operation equivalents (add/mul = 1,
+# fma = 2, exp 20, log 25, pow 60, div/sqrt 10, acos 40): fixed per-unit
+# figures of the method's arithmetic, independent of how a kernel is built.
+# Each unit is counted once per interaction (an unordered pair, a bond, an
+# angle), with the interaction's energy and every force it contributes.
+UNIT_FLOPS = {
+    "far_candidates": 15.0,     # distance test of one candidate pair of the half stencil
+    "far_pairs": 300.0,         # tapered vdW + shielded Coulomb pair, energy and force
+    "bond_candidates": 260.0,   # uncorrected bond orders (3 pow + 3 exp) and derivatives
+    "bonds": 500.0,             # bond-order correction, bond energy and its adjoint
+    "atoms": 300.0,             # lone pair, over- and under-coordination
+    "angles": 600.0,            # valence angle, penalty, coalition and adjoints
+    "torsions": 500.0,          # torsion and conjugation and adjoints
+    "hbonds": 150.0,            # hydrogen-bond triplet
+}
+# the dominant kernel's unit
 WORK = {
-    "nonbonded": ("far_pairs", 421.0),
+    "nonbonded": ("far_pairs", UNIT_FLOPS["far_pairs"]),
 }
 
 # Measured HBM bytes per launch of a kernel (rocprofv3 FETCH_SIZE and
@@ -57,20 +63,116 @@ PHASES = {
 }
 
 
-def cpu_baseline(params, seconds_cap=60.0):
-    """The oracle (single-threaded FP64, lists + forces) on a bounded sample of the
-    workload: the same generator recipe and density at 32,480 atoms (1,120 units,
-    69.2 A periodic box)."""
+def host_info():
+    """Host cores and CPU model of the machine the oracle is timed on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "cpu_model": model}
+
+
+def cpu_baseline(params, reps=3):
+    """The oracle (single-threaded FP64: lists, energies and forces) on a bounded
+    sample of the workload: the same generator recipe, density and cutoffs at
+    32,480 atoms (1,120 units, 69.2 A periodic box), median of `reps` runs, with
+    the calling thread pinned to one core for the duration.  The oracle's work is
+    linear in the atom count at fixed density, so its atom-steps/s carries over
+    to the 1,044,000-atom workload (an extrapolation, labelled as such)."""
+    import statistics
+
     import reaxff_synth as rs
     from oracle import Oracle
     s = rs.workload("petn_32480")
-    t0 = time.perf_counter()
-    o = Oracle(s, params)
-    o.forces()
-    t = time.perf_counter() - t0
+    info = host_info()
+    old = os.sched_getaffinity(0)
+    core = min(old)
+    os.sched_setaffinity(0, {core})
+    try:
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            o = Oracle(s, params)
+            o.forces()
+            times.append(time.perf_counter() - t0)
+    finally:
+        os.sched_setaffinity(0, old)
+    t = statistics.median(times)
     return {"value": s.n / t, "unit": "atom-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"one oracle force evaluation (lists + energies + forces) on {s.n} atoms "
-                      f"of the same recipe (1,120 units, 69.2 A box): {t:.2f} s single-threaded"}
+            "pinned_core": core, "host": info,
+            "sample": f"oracle force evaluation (lists + energies + forces, one thread pinned to core "
+                      f"{core}) on {s.n} atoms of the same recipe (1,120 units, 69.2 A box), median of "
+                      f"{reps}: {t:.2f} s; rate per atom applied to 1,044,000 atoms is an extrapolation "
+                      f"(work linear in atoms at fixed density)",
+            "seconds": times}
+
+
+def geometric_counts(system, r_bond=5.0, r_nonb=10.0):
+    """Candidate counts the method's list construction must test, from the
+    positions alone: unordered pairs within r_bond (bond candidates), and the
+    unordered candidate pairs of a half stencil of +-2 cells of r_nonb/2."""
+    import numpy as np
+    from scipy.spatial import cKDTree
+    box = np.asarray(system.box, dtype=np.float64)
+    pos = np.mod(system.pos, box)
+    n = system.n
+    tree = cKDTree(pos, boxsize=box)
+    bond_cand = (int(tree.count_neighbors(tree, r_bond)) - n) // 2
+    nc = np.floor(box / (0.5 * r_nonb)).astype(int)
+    idx = np.floor(pos / box * nc).astype(int) % nc
+    m = np.zeros(nc)
+    np.add.at(m, (idx[:, 0], idx[:, 1], idx[:, 2]), 1.0)
+    S = np.zeros_like(m)
+    for a in range(-2, 3):
+        for b in range(-2, 3):
+            for c in range(-2, 3):
+                S += np.roll(m, (a, b, c), axis=(0, 1, 2))
+    far_cand = int(((m * S).sum() - n) // 2)
+    return {"bond_candidates": bond_cand, "far_candidates": far_cand}
+
+
+def whole_step_work(counts, n):
+    """Sum over the method's units of (FP64 ops per unit) x (units per step)."""
+    units = dict(counts)
+    units["atoms"] = n
+    per = {k: UNIT_FLOPS[k] * units[k] for k in UNIT_FLOPS if k in units}
+    return sum(per.values()), per
+
+
+def bench_md(ff, params, steps=100, warmup_steps=5):
+    """reaxff_step: velocity-Verlet NVE, dt 0.1 fs, lists rebuilt every step, on
+    32,480 atoms (1,120 C5H8N4O12 units in a 69.2 A periodic box, Maxwell-Boltzmann
+    velocities at 300 K); atom-steps/s over `steps` steps in one call."""
+    import torch
+
+    import reaxff_synth as rs
+    s = rs.workload("petn_32480")
+    v0 = rs.maxwell_boltzmann(s.type, params.atom["mass"], 300.0, seed=101)
+    dev = torch.device("cuda:0")
+    P = torch.tensor(s.pos, dtype=torch.float64, device=dev)
+    V = torch.tensor(v0, dtype=torch.float64, device=dev)
+    T = torch.tensor(s.type, dtype=torch.int32, device=dev)
+    Q = torch.tensor(s.q, dtype=torch.float64, device=dev)
+    box = [float(x) for x in s.box]
+    ff.step(P.clone(), V.clone(), T, Q, box, 0.1, warmup_steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, en = ff.step(P, V, T, Q, box, 0.1, steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    e = en.cpu().numpy()
+    etot = e[:, :12].sum(1) + e[:, 12]
+    return {"workload": "petn_32480: 32,480 atoms, 69.2 A periodic box, MB 300 K, dt 0.1 fs, "
+                        "lists rebuilt every step",
+            "steps": steps, "seconds": dt, "ms_per_step": 1e3 * dt / steps,
+            "atom_steps_per_s": s.n * steps / dt,
+            "energy_span_kcal": float(etot.max() - etot.min()),
+            "kinetic_mean_kcal": float(e[:, 12].mean())}
 
 
 def bench_batched(ff, steps: int, warmup: int):
@@ -260,6 +362,7 @@ def main():
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched-clusters measurement (for profiling)")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate measurement")
+    ap.add_argument("--no-md", action="store_true", help="skip the 32,480-atom MD measurement")
     ap.add_argument("--surrogate-only", action="store_true",
                     help="only the surrogate measurement (for profiling)")
     args = ap.parse_args()
@@ -388,6 +491,20 @@ def main():
                         "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s", "frac": None,
                         "traffic": None, "avg_ms": kernels[dom]["ms_avg"]}
 
+    # whole step against the FP64 vector peak: the method's per-unit work
+    # (UNIT_FLOPS) times the units of one step, over the measured step time
+    geo = geometric_counts(system)
+    work, per_unit = whole_step_work({**counts, **geo}, n)
+    whole = {"gflop_eq": work / 1e9, "achieved_tflops": work / (ms_per_step * 1e-3) / 1e12,
+             "peak": PEAK_FP64_VALU_TFLOPS, "frac": work / (ms_per_step * 1e-3) / 1e12 / PEAK_FP64_VALU_TFLOPS,
+             "units": {k: {"count": int(v / UNIT_FLOPS[k]), "flops_per_unit": UNIT_FLOPS[k]}
+                       for k, v in per_unit.items()}}
+
+    md = None
+    if not args.no_md:
+        print("bench: MD steps on 32,480 atoms", file=sys.stderr, flush=True)
+        md = bench_md(ff, params)
+
     batched = None
     if not args.no_batched:
         print("bench: batched clusters", file=sys.stderr, flush=True)
@@ -421,7 +538,9 @@ def main():
                    "overlap": not args.no_overlap,
                    "cutoffs_A": {"nonbonded": 10.0, "bond": 5.0, "hbond": 7.5}, "bo_cut": 0.01},
         "roofline": roofline,
+        "whole_step_roofline": whole,
         "cpu_baseline": cpu,
+        "md_32480": md,
         "batched": batched,
         "surrogate": surrogate,
         "phases_ms": phases,
