@@ -257,6 +257,38 @@ int reaxff_batch_tune(reaxff_batch* b, const double* pos, const int32_t* type,
                       hipStream_t stream, int32_t reps, int32_t max_trials,
                       reaxff_batch_config* trials, double* trial_ms, int32_t* ntrials);
 
+/* ---- Batched evaluation that allocates nothing -----------------------------
+ *
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * per-cluster evaluation as reaxff_batch_compute (one persistent launch,
+ * every cluster in one workgroup), without a plan: cluster offsets stay on
+ * the device, clusters are taken from a work queue in index order, and all
+ * scratch (queue, status words, one slice per persistent workgroup) lives in
+ * one fixed device array of REAXFF_BATCHED_SCRATCH_BYTES that each GPU the
+ * library runs on holds until the process ends.  The call allocates nothing,
+ * synchronises nothing and may be captured into a graph.
+ *
+ * nsys clusters; sys_off [dev] (nsys+1) int64 atom offsets (sys_off[0] = 0,
+ * non-decreasing); max_atoms [host] an upper bound on the atoms of any
+ * cluster, 1..REAXFF_BATCH_MAX_ATOMS (else REAXFF_ERR_ARG; it sizes the
+ * workgroup slices, and the number of workgroups is what fits in the array).
+ * pos [dev] (N,3), type [dev] (N), q [dev] (N) over N = sys_off[nsys] atoms;
+ * forces [dev] (N,3) and energies [dev] (nsys, REAXFF_NTERMS) overwritten.
+ * status [dev] (3) int32 or NULL: [0] the OR of the failures (1: bond entries
+ * beyond REAXFF_BATCHED_ENTRIES_PER_ATOM * max_atoms, 2: a type outside 0..3,
+ * 4: a cluster longer than max_atoms or offsets out of order), [1] the largest
+ * entry count of a failing cluster, [2] the lowest failing cluster (INT32_MAX
+ * if none); a failing cluster gets NaN energies (and NaN forces when its
+ * atom range is valid).  Calls that overlap on one GPU share the array and
+ * race: serialise them (one stream, or events). */
+#define REAXFF_BATCHED_SCRATCH_BYTES (256ll << 20)
+#define REAXFF_BATCHED_ENTRIES_PER_ATOM 6
+int reaxff_compute_forces_batched(reaxff_ctx* ctx, int32_t nsys, const int64_t* sys_off,
+                                  int32_t max_atoms, const double* pos, const int32_t* type,
+                                  const double* q, double* forces, double* energies,
+                                  int32_t* status, hipStream_t stream);
+
 /* ---- Learned surrogate with the plain evaluation as fallback -------------
  *
  * An ensemble of per-element neural networks predicts per-atom energies

@@ -92,6 +92,7 @@ def load_library():
     lib.reaxff_batch_counts.argtypes = [vp, vp]
     lib.reaxff_batch_tune.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, i32, vp, vp,
                                       ctypes.POINTER(i32)]
+    lib.reaxff_compute_forces_batched.argtypes = [vp, i32, vp, i32, vp, vp, vp, vp, vp, vp, vp]
     lib.reaxff_surrogate_param_count.restype = i64
     lib.reaxff_surrogate_create.argtypes = [vp, i32, ctypes.POINTER(vp)]
     lib.reaxff_surrogate_destroy.argtypes = [vp]
@@ -246,6 +247,29 @@ class ReaxFF:
     def set_overlap(self, enable: bool):
         """Run the nonbonded term concurrently with the bonded terms (default) or in order."""
         self._check(self._lib.reaxff_set_overlap(self._h, 1 if enable else 0))
+
+    def compute_forces_batched(self, sys_off, max_atoms: int, pos, type_, q, forces=None, energies=None,
+                               status=None):
+        """reaxff_compute_forces_batched (no allocation inside the library): sys_off (nsys+1,)
+        int64 cuda offsets, max_atoms an upper bound on any cluster's atoms.  Returns
+        (forces (N,3), energies (nsys,12), status (3,) int32) cuda tensors."""
+        assert sys_off.dtype == torch.int64 and sys_off.is_cuda and sys_off.is_contiguous()
+        nsys = sys_off.shape[0] - 1
+        n = pos.shape[0]
+        if forces is None:
+            forces = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+        if energies is None:
+            energies = torch.empty((nsys, NTERMS), dtype=torch.float64, device=pos.device)
+        if status is None:
+            status = torch.empty(3, dtype=torch.int32, device=pos.device)
+        for t, dt in ((pos, torch.float64), (type_, torch.int32), (q, torch.float64), (forces, torch.float64),
+                      (energies, torch.float64), (status, torch.int32)):
+            assert t.dtype == dt and t.is_cuda and t.is_contiguous()
+        assert energies.shape == (nsys, NTERMS) and forces.shape == (n, 3) and status.numel() >= 3
+        self._check(self._lib.reaxff_compute_forces_batched(
+            self._h, nsys, _ptr(sys_off), int(max_atoms), _ptr(pos), _ptr(type_), _ptr(q), _ptr(forces),
+            _ptr(energies), _ptr(status), _stream()))
+        return forces, energies, status
 
     def interaction_counts(self):
         c = (ctypes.c_int64 * 5)()

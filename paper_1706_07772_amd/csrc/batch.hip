@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <mutex>
 #include <numeric>
 #include <queue>
 
@@ -30,8 +31,10 @@ namespace rx {
 constexpr int BNMAX = REAXFF_BATCH_MAX_ATOMS;
 constexpr int NCOUNT = 5;   // angles, torsions, hbonds, far pairs, bonds
 
-// status bits of a cluster
-constexpr int ST_CAPACITY = 1, ST_TYPE = 2;
+// status bits of a cluster: bond entries beyond the scratch slice, an atom
+// type outside 0..3, offsets that do not describe a cluster of at most the
+// slice's atom count (only the device-offset entry point can pass those)
+constexpr int ST_CAPACITY = 1, ST_TYPE = 2, ST_SIZE = 4;
 
 // byte offsets of the arrays inside one workgroup's scratch slice
 struct BatchLayout {
@@ -76,7 +79,8 @@ struct BatchArgs {
   int32_t ncl;
   int32_t dynamic;           // 1: clusters from the queue, in `order`
   const int64_t* off;        // [ncl + 1] atom offsets
-  const int32_t* order;      // cluster order (grouped per workgroup for static schedules)
+  const int32_t* order;      // cluster order (grouped per workgroup for static schedules);
+                             // null: the queue hands out clusters in index order
   const int32_t* wg_first;   // [G + 1] static schedules: workgroup b takes order[wg_first[b] ..)
   int32_t* queue;            // [1] next position in `order` (dynamic)
   const double* pos;
@@ -84,12 +88,13 @@ struct BatchArgs {
   const double* q;
   double* forces;
   double* energies;          // [ncl][NTERMS]
-  long long* counts;         // [ncl][NCOUNT]
-  int32_t* status;           // [ncl]
+  long long* counts;         // [ncl][NCOUNT], or null
+  int32_t* status;           // [ncl], or null
   int32_t* err;              // [0] OR of statuses, [1] largest entry count, [2] lowest bad cluster
   char* scratch;
   BatchLayout lay;
   int32_t ecap;
+  int32_t nmax;              // atoms per cluster the slice holds
 };
 
 __global__ void k_batch_reset(int32_t* queue, int32_t* err) {
@@ -234,7 +239,7 @@ __device__ __noinline__ void st_fail(int c, int64_t a0, int n, int code, int nen
   for (int i = tid; i < 3 * n; i += BSZ) A.forces[3 * a0 + i] = nan;
   if (tid < NTERMS) A.energies[(int64_t)c * NTERMS + tid] = nan;
   if (tid == 0) {
-    A.status[c] = code;
+    if (A.status) A.status[c] = code;
     atomicOr(&A.err[0], code);
     if (code == ST_CAPACITY) atomicMax(&A.err[1], nent);
     atomicMin(&A.err[2], c);
@@ -605,14 +610,20 @@ __global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(3))) void k
       int idx;
       if (A.dynamic) idx = atomicAdd(A.queue, 1);
       else idx = pos_in_order < pos_end ? pos_in_order : A.ncl;
-      b_next = idx < A.ncl ? A.order[idx] : -1;
+      b_next = idx < A.ncl ? (A.order ? A.order[idx] : idx) : -1;
     }
     ++pos_in_order;
     __syncthreads();
     const int c = b_next;
     if (c < 0) break;
     const int64_t a0 = A.off[c];
-    const int n = (int)(A.off[c + 1] - a0);
+    const int64_t len = A.off[c + 1] - a0;
+    if (len < 0 || len > A.nmax || a0 < 0 || a0 + len > A.off[A.ncl]) {
+      st_fail<BSZ>(c, a0, 0, ST_SIZE, 0);   // no atom range to write: energies and status only
+      __syncthreads();
+      continue;
+    }
+    const int n = (int)len;
     if (__syncthreads_or(st_load<BSZ>(a0, n))) {
       st_fail<BSZ>(c, a0, n, ST_TYPE, 0);
       __syncthreads();
@@ -655,13 +666,51 @@ __global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(3))) void k
     st_out<BSZ>(c, a0, n);
     __syncthreads();
     if (tid < NTERMS) A.energies[(int64_t)c * NTERMS + tid] = b_acc[tid];
-    else if (tid < NTERMS + 4) A.counts[(int64_t)c * NCOUNT + (tid - NTERMS)] = (long long)b_acc[tid];
-    else if (tid == NTERMS + 4) A.counts[(int64_t)c * NCOUNT + 4] = nent / 2;
-    if (tid == 0) A.status[c] = 0;
+    else if (A.counts && tid < NTERMS + 4) A.counts[(int64_t)c * NCOUNT + (tid - NTERMS)] = (long long)b_acc[tid];
+    else if (A.counts && tid == NTERMS + 4) A.counts[(int64_t)c * NCOUNT + 4] = nent / 2;
+    if (tid == 0 && A.status) A.status[c] = 0;
     __syncthreads();
   }
 }
 
+}  // namespace rx
+
+// ---------------------------------------------------------------------------
+// Scratch of reaxff_compute_forces_batched, the batched evaluation that
+// allocates nothing: one fixed array per device (every device the library
+// runs on holds its own copy until the process ends).  Bytes [0, 256) hold the
+// work queue and the internal status words; persistent workgroup slices
+// follow.  In host code `scratch` names a host-side stand-in, never a device
+// address: the host takes the array's address on each device once, with
+// hipGetSymbolAddress, and only ever passes that address to kernels.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[REAXFF_BATCHED_SCRATCH_BYTES];
+
+namespace rx {
+namespace {
+constexpr int MAXDEV = 64;
+constexpr int64_t SCRATCH_HEAD = 256;
+std::mutex g_scratch_mu;
+char* g_scratch_dev[MAXDEV] = {};   // device address of `scratch`, per device
+int g_scratch_cus[MAXDEV] = {};     // compute units of that device
+}  // namespace
+
+// Look up the address of `scratch` on `device`, which must be current; once per
+// device (reaxff_create calls this).  Returns a HIP error code.
+int batched_scratch_init(int device) {
+  if (device < 0 || device >= MAXDEV) return (int)hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[device]) return (int)hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || ptr == nullptr) return (int)(e != hipSuccess ? e : hipErrorInvalidSymbol);
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
+    cus = 256;
+  g_scratch_cus[device] = cus;
+  g_scratch_dev[device] = static_cast<char*>(ptr);
+  return (int)hipSuccess;
+}
 }  // namespace rx
 
 // ---------------------------------------------------------------------------
@@ -831,6 +880,7 @@ int capture(reaxff_batch* b, const double* pos, const int32_t* type, const doubl
   a.scratch = b->d_scratch;
   a.lay = make_layout(std::max(b->nmax, 1), b->ecap);
   a.ecap = b->ecap;
+  a.nmax = std::max(b->nmax, 1);
   BHIP(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, b->cap_stream, b->d_queue, b->d_err);
   if (b->ncl > 0) {
@@ -1074,6 +1124,83 @@ int reaxff_batch_tune(reaxff_batch* b, const double* pos, const int32_t* type, c
   rc = reaxff_batch_set_config(b, &bestc);
   if (rc) return rc;
   return reaxff_batch_compute(b, pos, type, q, forces, energies, stream);
+}
+
+int reaxff_compute_forces_batched(reaxff_ctx* ctx, int32_t nsys, const int64_t* sys_off, int32_t max_atoms,
+                                  const double* pos, const int32_t* type, const double* q, double* forces,
+                                  double* energies, int32_t* status, hipStream_t stream) {
+  using namespace rx;
+  if (!ctx) return REAXFF_ERR_ARG;
+  if (nsys < 0) {
+    ctx->err = "reaxff_compute_forces_batched: nsys < 0";
+    return REAXFF_ERR_ARG;
+  }
+  if (nsys > 0 && (!sys_off || !pos || !type || !q || !forces || !energies)) {
+    ctx->err = "reaxff_compute_forces_batched: null pointer";
+    return REAXFF_ERR_ARG;
+  }
+  if (nsys > 0 && (max_atoms < 1 || max_atoms > REAXFF_BATCH_MAX_ATOMS)) {
+    ctx->err = "reaxff_compute_forces_batched: max_atoms " + std::to_string(max_atoms) + " outside 1.." +
+               std::to_string(REAXFF_BATCH_MAX_ATOMS);
+    return REAXFF_ERR_ARG;
+  }
+  const int dev = ctx->device;
+  char* base = (dev >= 0 && dev < MAXDEV) ? g_scratch_dev[dev] : nullptr;
+  if (!base) {
+    ctx->err = "reaxff_compute_forces_batched: scratch address of this device not set up";
+    return REAXFF_ERR_STATE;
+  }
+  const hipError_t se = hipSetDevice(dev);
+  if (se != hipSuccess) {
+    ctx->err = std::string("hipSetDevice: ") + hipGetErrorString(se);
+    return REAXFF_ERR_HIP;
+  }
+  const int nmax = std::max(max_atoms, 1);
+  const int ecap = REAXFF_BATCHED_ENTRIES_PER_ATOM * nmax;
+  const BatchLayout lay = make_layout(nmax, ecap);
+  const int64_t slices = (REAXFF_BATCHED_SCRATCH_BYTES - SCRATCH_HEAD) / lay.stride;
+  if (slices < 1) {
+    ctx->err = "reaxff_compute_forces_batched: one workgroup slice exceeds the scratch array";
+    return REAXFF_ERR_CAPACITY;
+  }
+  constexpr int BSZ = 256, WG_PER_CU = 4;
+  const int grid = (int)std::min<int64_t>(std::min<int64_t>(slices, (int64_t)g_scratch_cus[dev] * WG_PER_CU),
+                                          std::max(nsys, 1));
+  int32_t* queue = reinterpret_cast<int32_t*>(base);
+  int32_t* err = status ? status : reinterpret_cast<int32_t*>(base + 64);
+  // the array keeps the previous call's contents: the queue and status words
+  // start again from zero (a kernel, not a memset, so that the call can be
+  // captured into a graph)
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, stream, queue, err);
+  if (nsys > 0) {
+    BatchArgs a{};
+    a.P = ctx->dp;
+    a.ncl = nsys;
+    a.dynamic = 1;
+    a.off = sys_off;
+    a.order = nullptr;
+    a.wg_first = nullptr;
+    a.queue = queue;
+    a.pos = pos;
+    a.type = type;
+    a.q = q;
+    a.forces = forces;
+    a.energies = energies;
+    a.counts = nullptr;
+    a.status = nullptr;
+    a.err = err;
+    a.scratch = base + SCRATCH_HEAD;
+    a.lay = lay;
+    a.ecap = ecap;
+    a.nmax = nmax;
+    hipLaunchKernelGGL(k_batch<BSZ>, dim3(grid), dim3(BSZ), 0, stream, a);
+  }
+  const hipError_t le = hipGetLastError();
+  if (le != hipSuccess) {
+    ctx->err = std::string("reaxff_compute_forces_batched launch: ") + hipGetErrorString(le);
+    return REAXFF_ERR_HIP;
+  }
+  return REAXFF_OK;
 }
 
 }  // extern "C"

@@ -224,6 +224,10 @@ int reaxff_create(const reaxff_params* params, const reaxff_cutoffs* cutoffs, in
     return REAXFF_ERR_HIP;
   }
   fill_dev_params(c->hp, c->cut, c->hd);
+  if (batched_scratch_init(device) != (int)hipSuccess) {
+    delete c;
+    return REAXFF_ERR_HIP;
+  }
   if (hipMalloc(&c->dp, sizeof(DevParams)) != hipSuccess ||
       hipMemcpy(c->dp, &c->hd, sizeof(DevParams), hipMemcpyHostToDevice) != hipSuccess ||
       hipMalloc(&c->sc.flag, sizeof(int32_t) * 4) != hipSuccess ||

@@ -114,6 +114,10 @@ int launch_drift(int64_t n, double* pos, const double* vel, double dt, const Gri
 int launch_kinetic(int64_t n, const double* vel, const int32_t* type, const DevParams* P,
                    double* out, hipStream_t st);
 
+// address of the fixed scratch array of reaxff_compute_forces_batched on a
+// device (which must be current), looked up once per device; a HIP error code
+int batched_scratch_init(int device);
+
 }  // namespace rx
 
 // the library context (opaque to callers)
