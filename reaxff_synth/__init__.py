@@ -212,6 +212,24 @@ def draw_params(seed: int = 0) -> Params:
     return Params(general=g, atom=a, pair=p, angle=ang, tors=tor, hb=hb, seed=seed)
 
 
+def draw_qeq_params(seed: int = 0) -> dict:
+    """Charge-equilibration parameters per element (C, H, N, O), from their own
+    seeded stream (the force-field draw above is unchanged by them).
+
+    chi: electronegativity, kcal/(mol e), in element ranges around 5-9 eV;
+    J:   self-Coulomb (twice the hardness), kcal/(mol e^2), 330-420 (14-18 eV),
+         which keeps the charge-equilibration matrix of the PETN-density
+         lattices positive definite (its off-diagonal part has eigenvalues down
+         to about -250 there).
+    The shielding gamma of each pair is the force field's Coulomb gamma.
+    """
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 7]))
+    chi_ranges = ((115, 145), (75, 105), (135, 165), (180, 210))
+    chi = np.array([float(_u(rng, lo, hi)) for lo, hi in chi_ranges])
+    J = np.array([float(_u(rng, 330, 420)) for _ in range(4)])
+    return {"chi": chi, "J": J}
+
+
 @dataclass
 class System:
     """One atom configuration.
