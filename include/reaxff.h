@@ -50,7 +50,8 @@ enum {
   REAXFF_ERR_BOX = -3,       /* periodic box edge below 2 r_nonb */
   REAXFF_ERR_HIP = -4,       /* HIP runtime failure (allocation, launch) */
   REAXFF_ERR_NONFINITE = -5, /* non-finite position */
-  REAXFF_ERR_STATE = -6      /* call out of order (forces before lists, n changed) */
+  REAXFF_ERR_STATE = -6,     /* call out of order (forces before lists, n changed) */
+  REAXFF_ERR_CONVERGENCE = -7 /* an iterative solver stopped at its iteration limit */
 };
 
 /* Force-field parameters, flattened per element (C,H,N,O).  Pair tables are
@@ -173,6 +174,44 @@ int reaxff_profile_read(reaxff_ctx* ctx, int32_t max, double* ms, int64_t* launc
  * the order of floating-point additions.  Returns REAXFF_OK or
  * REAXFF_ERR_ARG for a null context. */
 int reaxff_set_overlap(reaxff_ctx* ctx, int32_t enable);
+
+/* ---- Charge equilibration (Section 3.3, QEq) ------------------------------
+ *
+ * The charges that minimise the electrostatic energy
+ *   E(q) = sum_i (chi_i q_i + J_i q_i^2 / 2) + sum_{i<j} H_ij q_i q_j
+ * subject to sum_i q_i = 0, where H_ij is the force field's tapered shielded
+ * Coulomb coupling Tap(r) C_ele / (r^3 + gamma_ij^-3)^(1/3) over the pairs
+ * within r_nonb (minimum image in a periodic box) and H_ii = J_i.  As the
+ * paper describes, the minimum follows from two linear systems with the
+ * common matrix H, H s = -chi and H t = -1, as q = s - (sum s / sum t) t; H
+ * is computed once per call from the neighbours and stored, and both
+ * systems are solved together by diagonally preconditioned conjugate
+ * gradients (one product of H with both search directions per iteration),
+ * from a start extrapolated from earlier calls.  The paper's benchmarks stop
+ * at a relative residual of 1e-6 (Section 4). */
+typedef struct reaxff_qeq_params {
+  double chi[REAXFF_NTYPES];  /* electronegativity per element, kcal/(mol e) */
+  double J[REAXFF_NTYPES];    /* self-Coulomb (twice the hardness) per element,
+                                 kcal/(mol e^2); must be > 0, and H positive
+                                 definite for the iteration to converge */
+} reaxff_qeq_params;
+#define REAXFF_QEQ_MAXIT 10000
+
+/* Charges for the atoms of the last reaxff_build_lists call (same n; its
+ * positions, types and box).  qp [host].  Stops when both relative residuals
+ * |b - H x| / |b| are at most tol (> 0), or after maxit (0..REAXFF_QEQ_MAXIT)
+ * iterations, then returns REAXFF_ERR_CONVERGENCE with the charges of the
+ * last iterate.  guess != 0: start from the polynomial extrapolation through
+ * the solutions of up to four earlier calls for the same n (cubic with four:
+ * 4x1 - 6x2 + 4x3 - x4, newest first), else from zero (and forget them).
+ * q [dev] (n) the charges, s_out/t_out [dev] (n) or NULL the two solutions,
+ * all in the caller's order; iters [host] or NULL the iterations taken;
+ * resid [host] (2) or NULL the final relative residuals.  The context owns
+ * H (n x row width entries of 12 bytes) and the solver vectors.  One host
+ * synchronisation per iteration (the residual norms). */
+int reaxff_qeq(reaxff_ctx* ctx, int64_t n, const reaxff_qeq_params* qp, double tol,
+               int32_t maxit, int32_t guess, double* q, double* s_out, double* t_out,
+               int32_t* iters, double* resid, hipStream_t stream);
 
 /* ---- Batched evaluation of many small non-periodic systems ---------------
  *

@@ -20,7 +20,8 @@ TERM_NAMES = ("bond", "lp", "over", "under", "val", "pen", "coa", "tor", "conj",
               "hb", "vdw", "coul")
 
 ERRORS = {0: "ok", -1: "REAXFF_ERR_ARG", -2: "REAXFF_ERR_CAPACITY", -3: "REAXFF_ERR_BOX",
-          -4: "REAXFF_ERR_HIP", -5: "REAXFF_ERR_NONFINITE", -6: "REAXFF_ERR_STATE"}
+          -4: "REAXFF_ERR_HIP", -5: "REAXFF_ERR_NONFINITE", -6: "REAXFF_ERR_STATE",
+          -7: "REAXFF_ERR_CONVERGENCE"}
 
 _GENERAL = ("p_boc1", "p_boc2", "p_coa2", "p_coa3", "p_coa4", "p_ovun3", "p_ovun4", "p_ovun6",
             "p_ovun7", "p_ovun8", "p_val6", "p_val8", "p_val9", "p_val10", "p_pen2", "p_pen3",
@@ -47,6 +48,11 @@ class CParams(ctypes.Structure):
 class CCutoffs(ctypes.Structure):
     _fields_ = [(k, _d) for k in ("r_nonb", "r_bond", "r_hb", "bo_cut", "thb_cut", "thb_cutsq",
                                   "hb_bo_cut")]
+
+
+class QeqParams(ctypes.Structure):
+    """reaxff_qeq_params: electronegativity chi and self-Coulomb J per element."""
+    _fields_ = [("chi", _d * 4), ("J", _d * 4)]
 
 
 class BatchConfig(ctypes.Structure):
@@ -92,6 +98,8 @@ def load_library():
     lib.reaxff_batch_counts.argtypes = [vp, vp]
     lib.reaxff_batch_tune.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, i32, vp, vp,
                                       ctypes.POINTER(i32)]
+    lib.reaxff_qeq.argtypes = [vp, i64, ctypes.POINTER(QeqParams), _d, i32, i32, vp, vp, vp,
+                               ctypes.POINTER(i32), ctypes.POINTER(_d), vp]
     lib.reaxff_compute_forces_batched.argtypes = [vp, i32, vp, i32, vp, vp, vp, vp, vp, vp, vp]
     lib.reaxff_surrogate_param_count.restype = i64
     lib.reaxff_surrogate_create.argtypes = [vp, i32, ctypes.POINTER(vp)]
@@ -247,6 +255,32 @@ class ReaxFF:
     def set_overlap(self, enable: bool):
         """Run the nonbonded term concurrently with the bonded terms (default) or in order."""
         self._check(self._lib.reaxff_set_overlap(self._h, 1 if enable else 0))
+
+    def qeq(self, n: int, qparams, tol: float = 1e-6, maxit: int = 500, guess: bool = True,
+            q=None, want_st: bool = False, device=None, check: bool = True):
+        """reaxff_qeq over the atoms of the last build_lists: returns
+        (q (n,) float64 cuda, iterations, (relative residual s, t)[, s, t])."""
+        dev = device if device is not None else torch.device("cuda", self.device)
+        if q is None:
+            q = torch.empty(n, dtype=torch.float64, device=dev)
+        s = t = None
+        if want_st:
+            s = torch.empty(n, dtype=torch.float64, device=dev)
+            t = torch.empty(n, dtype=torch.float64, device=dev)
+        qp = QeqParams()
+        for k in range(4):
+            qp.chi[k] = float(qparams["chi"][k])
+            qp.J[k] = float(qparams["J"][k])
+        it = ctypes.c_int32(0)
+        res = (ctypes.c_double * 2)()
+        rc = self._lib.reaxff_qeq(self._h, int(n), ctypes.byref(qp), float(tol), int(maxit), 1 if guess else 0,
+                                  _ptr(q), _ptr(s), _ptr(t), ctypes.byref(it), res, _stream())
+        if check:
+            self._check(rc)
+        out = (q, int(it.value), (float(res[0]), float(res[1])))
+        if want_st:
+            out = out + (s, t)
+        return out if check else out + (rc,)
 
     def compute_forces_batched(self, sys_off, max_atoms: int, pos, type_, q, forces=None, energies=None,
                                status=None):

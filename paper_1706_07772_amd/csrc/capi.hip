@@ -197,6 +197,7 @@ const char* reaxff_strerror(int code) {
     case REAXFF_ERR_HIP: return "HIP runtime error";
     case REAXFF_ERR_NONFINITE: return "non-finite input";
     case REAXFF_ERR_STATE: return "call out of order";
+    case REAXFF_ERR_CONVERGENCE: return "iterative solver did not converge";
     default: return "unknown error";
   }
 }
@@ -266,6 +267,13 @@ void reaxff_destroy(reaxff_ctx* c) {
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->sc.totals_host) (void)hipHostFree(c->sc.totals_host);
+  {
+    rx::Qeq& Q = c->qeq;
+    void* qp[] = {Q.hj, Q.hv, Q.hcnt, Q.x, Q.r, Q.p, Q.ap, Q.red, Q.need, Q.hist[0], Q.hist[1], Q.hist[2], Q.hist[3]};
+    for (void* p : qp)
+      if (p) (void)hipFree(p);
+    if (Q.red_host) (void)hipHostFree(Q.red_host);
+  }
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   if (c->side) (void)hipStreamDestroy(c->side);

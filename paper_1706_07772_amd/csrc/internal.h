@@ -14,7 +14,8 @@ enum KernelId {
   KID_BBOX, KID_CELL_HIST, KID_CELL_SCATTER, KID_CELL_SORT, KID_GATHER, KID_LIST_SWEEP, KID_SCAN,
   KID_BONDTEST, KID_COMPACT, KID_MIRROR, KID_ZERO, KID_GATHER_Q, KID_BO_PRIME, KID_DELTA_PRIME, KID_BO_CORR,
   KID_ATOM_STATE, KID_ATOM_ENERGY, KID_TASKS, KID_ANGLES, KID_TORSIONS, KID_HBONDS, KID_HB_ACC, KID_NONBONDED,
-  KID_BACK_S, KID_BACK_CORR, KID_BACK_DP, KID_FORCES, KID_BATCH, KID_NB_REDUCE, KID_NB_ENERGY, KID_ENERGY_FOLD, KID_COUNT
+  KID_BACK_S, KID_BACK_CORR, KID_BACK_DP, KID_FORCES, KID_BATCH, KID_NB_REDUCE, KID_NB_ENERGY, KID_ENERGY_FOLD,
+  KID_QEQ_ROWS, KID_QEQ_SPMV, KID_QEQ_VEC, KID_COUNT
 };
 extern const char* const kKernelNames[KID_COUNT];
 
@@ -91,6 +92,26 @@ struct Scratch {
   int64_t scan_cap = 0;
 };
 
+// charge-equilibration state (device pointers): the rows of H, the CG
+// vectors of the two systems as (s, t) pairs in sorted order, per-iteration
+// partial-sum sets, and a ring of the last four solutions in caller order
+struct Qeq {
+  int32_t* hj = nullptr;     // [n][w] sorted neighbour index
+  double* hv = nullptr;      // [n][w] H_ij
+  int32_t* hcnt = nullptr;   // [n] row lengths
+  int32_t w = 0;
+  int64_t cap_rows = 0, cap_rowsv = 0, cap_cnt = 0;
+  double2 *x = nullptr, *r = nullptr, *p = nullptr, *ap = nullptr;
+  int64_t cap_n = 0, cap_vec = 0;
+  double* red = nullptr;     // [maxit + 2][ESLOT][8]
+  int64_t cap_red = 0;
+  double* red_host = nullptr;  // pinned [ESLOT][8]
+  int32_t* need = nullptr;   // device: longest row beyond w
+  double2* hist[4] = {nullptr, nullptr, nullptr, nullptr};
+  int head = 0, nhist = 0;
+  int64_t hist_n = -1;
+};
+
 // exclusive prefix sums; out[n-1] holds the total when in[n-1] == 0
 int scan_i32(const int32_t* in, int32_t* out, int64_t n, Scratch& sc, hipStream_t st);
 int scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, Scratch& sc, hipStream_t st);
@@ -132,6 +153,7 @@ struct reaxff_ctx {
   rx::Work W{};
   rx::Scratch sc{};
   rx::Prof prof;
+  rx::Qeq qeq;
   // the nonbonded term runs on a stream of its own, concurrent with the
   // bonded terms, between a fork and a join event on the caller's stream
   hipStream_t side = nullptr;

@@ -1,0 +1,516 @@
+// Charge equilibration (Section 3.3, QEq): the charges that minimise
+//   E(q) = sum_i (chi_i q_i + J_i q_i^2 / 2) + sum_{i<j} H_ij q_i q_j,
+//   H_ij = Tap(r_ij) C_ele / (r_ij^3 + gamma_ij^-3)^(1/3)  (r_ij <= r_nonb),
+// under sum_i q_i = 0, from the two systems H s = -chi and H t = -1 with the
+// common matrix H (diagonal J): q = s - (sum s / sum t) t.
+//
+// As in the paper: the matrix is computed once per call from the neighbours
+// within r_nonb and stored; the two systems are solved together by
+// conjugate gradients with a diagonal preconditioner, one product of H with
+// both search directions per iteration; the start is extrapolated from
+// earlier solutions.  On this GPU:
+//   * H rows: one wavefront per atom walks its cell stencil (contiguous
+//     ranges of cell-sorted atoms, coalesced) and appends the neighbours
+//     within r_nonb, with H_ij, to a fixed-width row (ballot + popcount
+//     numbering, stencil order, so the row order is deterministic).  Each row
+//     holds both halves of the symmetric matrix: a product then gathers and
+//     never scatters, so no partial result vectors and no atomics are needed
+//     (the paper keeps unique entries and pays for thread-private result
+//     arrays, Section 4's QEq discussion).
+//   * the product is HBM-bound: one wavefront per row reads the row's
+//     (index, value) entries once and gathers the two search directions as
+//     one 16-byte record per neighbour (L2-resident: neighbours are near in
+//     the cell-sorted order).
+//   * the scalar recurrences stay on the device: each kernel folds the
+//     64 partial-sum slots of the previous stage itself; the host reads only
+//     the residual norms, once per iteration, to stop.
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "terms.h"
+
+namespace rx {
+
+constexpr int QB = 256, QWAVES = QB / 64;
+// fields of one partial-sum slot: p.Ap (s, t), r.z (s, t), r.r (s, t), b.b (s, t)
+constexpr int QF = 8;
+
+struct QeqPar {
+  double chi[NT], J[NT], Jinv[NT];
+};
+
+__device__ __forceinline__ unsigned long long lanes_below() {
+  const int lane = threadIdx.x & 63;
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// sum of a slot field over the ESLOT slots (every thread of the block may call)
+__device__ __forceinline__ double fold(const double* __restrict__ set, int f) {
+  double s = 0.0;
+  for (int k = 0; k < ESLOT; ++k) s += set[k * QF + f];
+  return s;
+}
+
+// add per-block sums of NF fields to this block's slot
+template <int NF>
+__device__ __forceinline__ void slot_add(double* __restrict__ set, const int* fields, const double* v) {
+  __shared__ double red[NF][QWAVES];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double x[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    x[f] = v[f];
+    for (int off = 32; off > 0; off >>= 1) x[f] += __shfl_down(x[f], off, 64);
+  }
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int f = 0; f < NF; ++f) red[f][w] = x[f];
+  __syncthreads();
+  if (threadIdx.x < NF) {
+    double s = 0.0;
+    for (int k = 0; k < QWAVES; ++k) s += red[threadIdx.x][k];
+    if (s != 0.0) atomicAdd(&set[(blockIdx.x & (ESLOT - 1)) * QF + fields[threadIdx.x]], s);
+  }
+}
+
+// H rows, one wavefront per sorted atom i: every j != i of i's cell stencil
+// with r_ij^2 <= r_nonb^2 (minimum image, the far list's predicate)
+__global__ __launch_bounds__(QB) void k_qeq_rows(const DevParams* __restrict__ P, Grid g, Lists L,
+                                                 int32_t* __restrict__ hj, double* __restrict__ hv,
+                                                 int32_t* __restrict__ hcnt, int32_t w,
+                                                 int32_t* __restrict__ need) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = xcd_block() * QWAVES + (threadIdx.x >> 6);
+  if (i >= L.n) return;
+  const double4 xi = L.xs[i];
+  const int ti = (int)xi.w;
+  const int c = L.cell_of[i];
+  const int nq = stencil_chunks(g);
+  const double rn2 = P->rn2, iR = P->inv_r_nonb;
+  int32_t* __restrict__ rj = hj + i * (int64_t)w;
+  double* __restrict__ rv = hv + i * (int64_t)w;
+  int cnt = 0;
+  for (int q = 0; q < nq; ++q) {
+    int s0, s1;
+    double sx, sy, sz;
+    stencil_chunk(g, L.cell_start, c, q, s0, s1, sx, sy, sz);
+    for (int j0 = s0; j0 < s1; j0 += 64) {
+      const int j = j0 + lane;
+      bool ok = j < s1 && j != (int)i;
+      double r2 = 0.0;
+      int tj = 0;
+      if (ok) {
+        const double4 xj = L.xs[j];
+        double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
+        if (g.periodic) {
+          dx = min_image(dx, g.L[0], g.invL[0]);
+          dy = min_image(dy, g.L[1], g.invL[1]);
+          dz = min_image(dz, g.L[2], g.invL[2]);
+        }
+        r2 = r2_of(dx, dy, dz);
+        tj = (int)xj.w;
+        ok = r2 <= rn2;
+      }
+      const unsigned long long m = ballot(ok);
+      if (ok) {
+        const int k = cnt + __popcll(m & lanes_below());
+        if (k < w) {
+          const double r = sqrt(r2);
+          const double u = r * iR;
+          const double u4 = (u * u) * (u * u);
+          const double tap = fma(u4, fma(u, fma(u, fma(u, 20.0, -70.0), 84.0), -35.0), 1.0);
+          const double h = tap * C_ELE * rcbrt_f(fma(r2, r, P->pair[ti * NT + tj].g3));
+          rj[k] = j;
+          rv[k] = h;
+        }
+      }
+      cnt += __popcll(m);
+    }
+  }
+  if (lane == 0) {
+    hcnt[i] = cnt;
+    if (cnt > w) atomicMax(need, cnt);
+  }
+}
+
+// y = H x for the pair of vectors (s, t), one wavefront per row; with `set`,
+// the block's sums of x_i . y_i per system go to the slot fields 0 and 1
+__global__ __launch_bounds__(QB) void k_qeq_spmv(Lists L, const int32_t* __restrict__ hj,
+                                                 const double* __restrict__ hv,
+                                                 const int32_t* __restrict__ hcnt, int32_t w, QeqPar qp,
+                                                 const double2* __restrict__ x, double2* __restrict__ y,
+                                                 double* __restrict__ set) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = xcd_block() * QWAVES + (threadIdx.x >> 6);
+  double ds = 0.0, dt = 0.0;
+  if (i < L.n) {
+    const int cnt = min(hcnt[i], w);
+    const int32_t* __restrict__ rj = hj + i * (int64_t)w;
+    const double* __restrict__ rv = hv + i * (int64_t)w;
+    double as = 0.0, at = 0.0;
+    for (int k = lane; k < cnt; k += 64) {
+      const double h = rv[k];
+      const double2 xj = x[rj[k]];
+      as = fma(h, xj.x, as);
+      at = fma(h, xj.y, at);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      as += __shfl_down(as, off, 64);
+      at += __shfl_down(at, off, 64);
+    }
+    if (lane == 0) {
+      const double2 xi = x[i];
+      const double Ji = qp.J[L.type_s[i]];
+      const double2 yi = make_double2(fma(Ji, xi.x, as), fma(Ji, xi.y, at));
+      y[i] = yi;
+      ds = xi.x * yi.x;
+      dt = xi.y * yi.y;
+    }
+  }
+  if (set) {
+    const int f[2] = {0, 1};
+    const double v[2] = {ds, dt};
+    slot_add<2>(set, f, v);
+  }
+}
+
+// start: r = b - y (y = H x0, or x0 = 0 when y is null), p = M^-1 r; slot
+// fields 2..7 of the start set: r.z, r.r, b.b per system
+__global__ __launch_bounds__(QB) void k_qeq_start(Lists L, QeqPar qp, const double2* __restrict__ y,
+                                                  double2* __restrict__ x, double2* __restrict__ r,
+                                                  double2* __restrict__ p, double* __restrict__ set) {
+  const int64_t i = xcd_block() * QB + threadIdx.x;
+  double v[6] = {0, 0, 0, 0, 0, 0};
+  if (i < L.n) {
+    const int t = L.type_s[i];
+    const double2 b = make_double2(-qp.chi[t], -1.0);
+    double2 ri = b;
+    if (y) {
+      const double2 yi = y[i];
+      ri = make_double2(b.x - yi.x, b.y - yi.y);
+    } else {
+      x[i] = make_double2(0.0, 0.0);
+    }
+    const double mi = qp.Jinv[t];
+    const double2 zi = make_double2(mi * ri.x, mi * ri.y);
+    r[i] = ri;
+    p[i] = zi;
+    v[0] = ri.x * zi.x;
+    v[1] = ri.y * zi.y;
+    v[2] = ri.x * ri.x;
+    v[3] = ri.y * ri.y;
+    v[4] = b.x * b.x;
+    v[5] = b.y * b.y;
+  }
+  const int f[6] = {2, 3, 4, 5, 6, 7};
+  slot_add<6>(set, f, v);
+}
+
+// step lengths alpha = (r.z)_old / (p.Ap) per system (zero once a system's
+// residual or curvature is exactly zero); x += alpha p, r -= alpha Ap; slot
+// fields 2..5 of this iteration's set: new r.z and r.r
+__global__ __launch_bounds__(QB) void k_qeq_update(Lists L, QeqPar qp, const double* __restrict__ prev,
+                                                   double* __restrict__ cur, double2* __restrict__ x,
+                                                   double2* __restrict__ r, const double2* __restrict__ p,
+                                                   const double2* __restrict__ ap) {
+  __shared__ double alpha[2];
+  if (threadIdx.x < 2) {
+    const double pap = fold(cur, threadIdx.x), rz = fold(prev, 2 + threadIdx.x);
+    alpha[threadIdx.x] = (pap > 0.0 && rz > 0.0) ? rz / pap : 0.0;
+  }
+  __syncthreads();
+  const double as = alpha[0], at = alpha[1];
+  const int64_t i = xcd_block() * QB + threadIdx.x;
+  double v[4] = {0, 0, 0, 0};
+  if (i < L.n) {
+    const double2 pi = p[i], api = ap[i];
+    double2 xi = x[i], ri = r[i];
+    xi.x = fma(as, pi.x, xi.x);
+    xi.y = fma(at, pi.y, xi.y);
+    ri.x = fma(-as, api.x, ri.x);
+    ri.y = fma(-at, api.y, ri.y);
+    x[i] = xi;
+    r[i] = ri;
+    const double mi = qp.Jinv[L.type_s[i]];
+    v[0] = mi * ri.x * ri.x;
+    v[1] = mi * ri.y * ri.y;
+    v[2] = ri.x * ri.x;
+    v[3] = ri.y * ri.y;
+  }
+  const int f[4] = {2, 3, 4, 5};
+  slot_add<4>(cur, f, v);
+}
+
+// p = M^-1 r + beta p, beta = (r.z)_new / (r.z)_old per system
+__global__ __launch_bounds__(QB) void k_qeq_direction(Lists L, QeqPar qp, const double* __restrict__ prev,
+                                                      const double* __restrict__ cur,
+                                                      const double2* __restrict__ r, double2* __restrict__ p) {
+  __shared__ double beta[2];
+  if (threadIdx.x < 2) {
+    const double rzo = fold(prev, 2 + threadIdx.x), rzn = fold(cur, 2 + threadIdx.x);
+    beta[threadIdx.x] = rzo > 0.0 ? rzn / rzo : 0.0;
+  }
+  __syncthreads();
+  const int64_t i = xcd_block() * QB + threadIdx.x;
+  if (i < L.n) {
+    const double mi = qp.Jinv[L.type_s[i]];
+    const double2 ri = r[i], pi = p[i];
+    p[i] = make_double2(fma(beta[0], pi.x, mi * ri.x), fma(beta[1], pi.y, mi * ri.y));
+  }
+}
+
+// sums of s and t (slot fields 0, 1 of the final set)
+__global__ __launch_bounds__(QB) void k_qeq_sums(Lists L, const double2* __restrict__ x, double* __restrict__ set) {
+  const int64_t i = xcd_block() * QB + threadIdx.x;
+  double v[2] = {0, 0};
+  if (i < L.n) {
+    const double2 xi = x[i];
+    v[0] = xi.x;
+    v[1] = xi.y;
+  }
+  const int f[2] = {0, 1};
+  slot_add<2>(set, f, v);
+}
+
+// q = s - (sum s / sum t) t, written in the caller's order with s and t
+// (history ring slot `hist`, optional outputs)
+__global__ __launch_bounds__(QB) void k_qeq_charges(Lists L, const double2* __restrict__ x,
+                                                    const double* __restrict__ set, double* __restrict__ q,
+                                                    double2* __restrict__ hist, double* __restrict__ s_out,
+                                                    double* __restrict__ t_out) {
+  __shared__ double ratio;
+  if (threadIdx.x == 0) ratio = fold(set, 0) / fold(set, 1);
+  __syncthreads();
+  const int64_t i = xcd_block() * QB + threadIdx.x;
+  if (i < L.n) {
+    const double2 xi = x[i];
+    const int o = L.perm[i];
+    q[o] = fma(-ratio, xi.y, xi.x);
+    hist[o] = xi;
+    if (s_out) s_out[o] = xi.x;
+    if (t_out) t_out[o] = xi.y;
+  }
+}
+
+// initial guess from the history ring (caller order, newest first):
+// x_i = sum_k c_k hist_k[perm i]
+__global__ __launch_bounds__(QB) void k_qeq_guess(Lists L, const double2* __restrict__ h0,
+                                                  const double2* __restrict__ h1, const double2* __restrict__ h2,
+                                                  const double2* __restrict__ h3, double4 c, double2* __restrict__ x) {
+  const int64_t i = xcd_block() * QB + threadIdx.x;
+  if (i >= L.n) return;
+  const int o = L.perm[i];
+  double2 v = h0[o];
+  v.x *= c.x;
+  v.y *= c.x;
+  if (h1) {
+    const double2 a = h1[o];
+    v.x = fma(c.y, a.x, v.x);
+    v.y = fma(c.y, a.y, v.y);
+  }
+  if (h2) {
+    const double2 a = h2[o];
+    v.x = fma(c.z, a.x, v.x);
+    v.y = fma(c.z, a.y, v.y);
+  }
+  if (h3) {
+    const double2 a = h3[o];
+    v.x = fma(c.w, a.x, v.x);
+    v.y = fma(c.w, a.y, v.y);
+  }
+  x[i] = v;
+}
+
+}  // namespace rx
+
+using namespace rx;
+
+namespace {
+
+int qfail(reaxff_ctx* c, int code, const std::string& msg) {
+  c->err = msg;
+  return code;
+}
+
+#define QHIP(ctx, expr)                                                                  \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return qfail(ctx, REAXFF_ERR_HIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+template <class T>
+int qgrow(reaxff_ctx* c, T*& p, int64_t& cap, int64_t need) {
+  if (need <= cap && p) return 0;
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  const int64_t n = std::max<int64_t>(need + need / 8 + 64, 64);
+  const hipError_t e = hipMalloc(&p, sizeof(T) * n);
+  if (e != hipSuccess) {
+    cap = 0;
+    return qfail(c, REAXFF_ERR_HIP, std::string("hipMalloc (QEq): ") + hipGetErrorString(e));
+  }
+  cap = n;
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int reaxff_qeq(reaxff_ctx* c, int64_t n, const reaxff_qeq_params* qpar, double tol, int32_t maxit,
+               int32_t guess, double* q, double* s_out, double* t_out, int32_t* iters, double* resid,
+               hipStream_t st) {
+  if (!c) return REAXFF_ERR_ARG;
+  if (!qpar || (n > 0 && !q)) return qfail(c, REAXFF_ERR_ARG, "reaxff_qeq: null pointer");
+  if (!(tol > 0.0) || maxit < 0 || maxit > REAXFF_QEQ_MAXIT)
+    return qfail(c, REAXFF_ERR_ARG, "reaxff_qeq: tol must be > 0 and maxit within 0..REAXFF_QEQ_MAXIT");
+  for (int t = 0; t < NT; ++t)
+    if (!(qpar->J[t] > 0.0) || !std::isfinite(qpar->J[t]) || !std::isfinite(qpar->chi[t]))
+      return qfail(c, REAXFF_ERR_ARG, "reaxff_qeq: J must be positive and finite, chi finite");
+  if (!c->built || n != c->L.n) return qfail(c, REAXFF_ERR_STATE, "reaxff_qeq: lists not built for this n");
+  QHIP(c, hipSetDevice(c->device));
+  if (iters) *iters = 0;
+  if (resid) resid[0] = resid[1] = 0.0;
+  if (n == 0) return REAXFF_OK;
+  Qeq& Q = c->qeq;
+  QeqPar qp{};
+  for (int t = 0; t < NT; ++t) {
+    qp.chi[t] = qpar->chi[t];
+    qp.J[t] = qpar->J[t];
+    qp.Jinv[t] = 1.0 / qpar->J[t];
+  }
+  // per-atom vectors, reduction sets (one per iteration, plus start and final)
+  if (qgrow(c, Q.x, Q.cap_n, n)) return REAXFF_ERR_HIP;
+  if (n > Q.cap_vec) {
+    for (double2** v : {&Q.r, &Q.p, &Q.ap}) {
+      if (*v) (void)hipFree(*v);
+      *v = nullptr;
+      QHIP(c, hipMalloc(v, sizeof(double2) * Q.cap_n));
+    }
+    for (int k = 0; k < 4; ++k) {
+      if (Q.hist[k]) (void)hipFree(Q.hist[k]);
+      Q.hist[k] = nullptr;
+      QHIP(c, hipMalloc(&Q.hist[k], sizeof(double2) * Q.cap_n));
+    }
+    Q.cap_vec = Q.cap_n;
+    Q.nhist = 0;
+  }
+  const int64_t nsets = (int64_t)maxit + 2;
+  if (qgrow(c, Q.red, Q.cap_red, nsets * ESLOT * QF)) return REAXFF_ERR_HIP;
+  if (!Q.red_host) QHIP(c, hipHostMalloc(&Q.red_host, sizeof(double) * ESLOT * QF, hipHostMallocDefault));
+  if (!Q.need) QHIP(c, hipMalloc(&Q.need, sizeof(int32_t)));
+  // H rows: width from the density estimate, grown once if a row overflows
+  const Lists& L = c->L;
+  const Grid& g = c->grid;
+  if (Q.w == 0) {
+    double vol = 1.0;
+    for (int k = 0; k < 3; ++k) vol *= g.periodic ? g.L[k] : std::max(g.nc[k] / g.invw[k], 1.0);
+    const double rho = (double)n / vol;
+    const double r = c->cut.r_nonb;
+    Q.w = (int32_t)std::min<double>((double)std::max<int64_t>(n, 1), 1.3 * rho * 4.18879 * r * r * r + 64.0);
+  }
+  const unsigned gw = xcd_grid((n + QWAVES - 1) / QWAVES), ga = xcd_grid((n + QB - 1) / QB);
+  for (int attempt = 0;; ++attempt) {
+    if (qgrow(c, Q.hj, Q.cap_rows, n * (int64_t)Q.w)) return REAXFF_ERR_HIP;
+    int64_t capv = Q.cap_rowsv;
+    if (qgrow(c, Q.hv, capv, n * (int64_t)Q.w)) return REAXFF_ERR_HIP;
+    Q.cap_rowsv = capv;
+    if (!Q.hcnt || Q.cap_cnt < n) {
+      if (qgrow(c, Q.hcnt, Q.cap_cnt, n)) return REAXFF_ERR_HIP;
+    }
+    QHIP(c, hipMemsetAsync(Q.need, 0, sizeof(int32_t), st));
+    c->prof.begin(KID_QEQ_ROWS, st);
+    hipLaunchKernelGGL(k_qeq_rows, dim3(gw), dim3(QB), 0, st, c->dp, g, L, Q.hj, Q.hv, Q.hcnt, Q.w, Q.need);
+    c->prof.end(st);
+    int32_t need = 0;
+    QHIP(c, hipMemcpyAsync(&need, Q.need, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    QHIP(c, hipStreamSynchronize(st));
+    if (need <= Q.w) break;
+    if (attempt >= 2) return qfail(c, REAXFF_ERR_CAPACITY, "reaxff_qeq: row width did not converge");
+    Q.w = need + need / 8 + 16;
+  }
+  QHIP(c, hipMemsetAsync(Q.red, 0, sizeof(double) * nsets * ESLOT * QF, st));
+  double* const start = Q.red;                       // set -1
+  auto set_of = [&](int k) { return Q.red + (int64_t)(k + 1) * ESLOT * QF; };
+  // initial guess
+  const bool use_guess = guess != 0 && Q.nhist > 0 && Q.hist_n == n;
+  if (!use_guess) Q.nhist = 0;
+  if (use_guess) {
+    static const double coef[4][4] = {{1, 0, 0, 0}, {2, -1, 0, 0}, {3, -3, 1, 0}, {4, -6, 4, -1}};
+    const int k = std::min(Q.nhist, 4);
+    const double* cf = coef[k - 1];
+    auto h = [&](int a) -> const double2* { return a < k ? Q.hist[(Q.head - a + 4) % 4] : nullptr; };
+    hipLaunchKernelGGL(k_qeq_guess, dim3(ga), dim3(QB), 0, st, L, h(0), h(1), h(2), h(3),
+                       make_double4(cf[0], cf[1], cf[2], cf[3]), Q.x);
+    c->prof.begin(KID_QEQ_SPMV, st);
+    hipLaunchKernelGGL(k_qeq_spmv, dim3(gw), dim3(QB), 0, st, L, Q.hj, Q.hv, Q.hcnt, Q.w, qp, Q.x, Q.ap,
+                       (double*)nullptr);
+    c->prof.end(st);
+    hipLaunchKernelGGL(k_qeq_start, dim3(ga), dim3(QB), 0, st, L, qp, Q.ap, Q.x, Q.r, Q.p, start);
+  } else {
+    hipLaunchKernelGGL(k_qeq_start, dim3(ga), dim3(QB), 0, st, L, qp, (const double2*)nullptr, Q.x, Q.r, Q.p,
+                       start);
+  }
+  // relative residuals of a set, read on the host
+  double bb[2] = {0, 0};
+  auto residuals = [&](const double* set, double out[2], bool first) -> int {
+    QHIP(c, hipMemcpyAsync(Q.red_host, set, sizeof(double) * ESLOT * QF, hipMemcpyDeviceToHost, st));
+    QHIP(c, hipStreamSynchronize(st));
+    double rr[2] = {0, 0};
+    for (int k = 0; k < ESLOT; ++k) {
+      rr[0] += Q.red_host[k * QF + 4];
+      rr[1] += Q.red_host[k * QF + 5];
+      if (first) {
+        bb[0] += Q.red_host[k * QF + 6];
+        bb[1] += Q.red_host[k * QF + 7];
+      }
+    }
+    for (int s = 0; s < 2; ++s) out[s] = bb[s] > 0.0 ? std::sqrt(rr[s] / bb[s]) : std::sqrt(rr[s]);
+    return 0;
+  };
+  double res[2];
+  if (residuals(start, res, true)) return REAXFF_ERR_HIP;
+  int it = 0;
+  const double* last = start;
+  while ((res[0] > tol || res[1] > tol) && it < maxit) {
+    double* cur = set_of(it);
+    c->prof.begin(KID_QEQ_SPMV, st);
+    hipLaunchKernelGGL(k_qeq_spmv, dim3(gw), dim3(QB), 0, st, L, Q.hj, Q.hv, Q.hcnt, Q.w, qp, Q.p, Q.ap, cur);
+    c->prof.end(st);
+    c->prof.begin(KID_QEQ_VEC, st);
+    hipLaunchKernelGGL(k_qeq_update, dim3(ga), dim3(QB), 0, st, L, qp, last, cur, Q.x, Q.r, Q.p, Q.ap);
+    c->prof.end(st);
+    ++it;
+    if (residuals(cur, res, false)) return REAXFF_ERR_HIP;
+    if (res[0] > tol || res[1] > tol) {
+      c->prof.begin(KID_QEQ_VEC, st);
+      hipLaunchKernelGGL(k_qeq_direction, dim3(ga), dim3(QB), 0, st, L, qp, last, cur, Q.r, Q.p);
+      c->prof.end(st);
+    }
+    last = cur;
+  }
+  // charges, and the solutions into the history ring
+  double* fin = set_of(maxit);
+  QHIP(c, hipMemsetAsync(fin, 0, sizeof(double) * ESLOT * QF, st));
+  hipLaunchKernelGGL(k_qeq_sums, dim3(ga), dim3(QB), 0, st, L, Q.x, fin);
+  Q.head = (Q.head + 1) % 4;
+  hipLaunchKernelGGL(k_qeq_charges, dim3(ga), dim3(QB), 0, st, L, Q.x, fin, q, Q.hist[Q.head], s_out, t_out);
+  Q.nhist = std::min(Q.nhist + 1, 4);
+  Q.hist_n = n;
+  QHIP(c, hipGetLastError());
+  if (iters) *iters = it;
+  if (resid) {
+    resid[0] = res[0];
+    resid[1] = res[1];
+  }
+  if (res[0] > tol || res[1] > tol)
+    return qfail(c, REAXFF_ERR_CONVERGENCE, "reaxff_qeq: not converged within maxit iterations");
+  return REAXFF_OK;
+}
+
+}  // extern "C"
