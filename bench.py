@@ -144,6 +144,60 @@ def whole_step_work(counts, n):
     return sum(per.values()), per
 
 
+def read_profile(ff, lib):
+    import ctypes
+    K = 40
+    ms = (ctypes.c_double * K)()
+    calls = (ctypes.c_int64 * K)()
+    names = (ctypes.c_char_p * K)()
+    lib.reaxff_profile_read.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p]
+    k = lib.reaxff_profile_read(ff._h, K, ms, calls, names)
+    return {names[i].decode(): {"ms_total": ms[i], "launches": int(calls[i]), "ms_avg": ms[i] / calls[i]}
+            for i in range(k) if calls[i]}
+
+
+def bench_qeq(ff, n, far_pairs, reps=3, tol=1e-6):
+    """Charge equilibration over the lists of the last build (the 1,044,000-atom
+    workload): H rows, then both systems by preconditioned CG from a zero start to
+    the paper's relative residual of 1e-6; per-kernel times from a profiled pass.
+    The matrix-vector product is HBM-bound: algorithmic bytes per product =
+    stored entries x 12 B (index + value) + n x 40 B (both directions read, the
+    product written, row length and type read)."""
+    import torch
+
+    import reaxff_synth as rs
+    from paper_1706_07772_amd.binding import load_library
+    qp = rs.draw_qeq_params(0)
+    lib = load_library()
+    q, it, res = ff.qeq(n, qp, tol=tol, guess=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        q, it, res = ff.qeq(n, qp, tol=tol, guess=False, q=q)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / reps
+    lib.reaxff_profile(ff._h, 1)
+    for _ in range(reps):
+        ff.qeq(n, qp, tol=tol, guess=False, q=q)
+    torch.cuda.synchronize()
+    kern = read_profile(ff, lib)
+    lib.reaxff_profile(ff._h, 0)
+    nnz = 2 * far_pairs
+    spmv = kern.get("qeq_spmv", {})
+    out = {"workload": "petn_1044000 positions of the force benchmark; chi, J from seed 0",
+           "tol": tol, "iterations": it, "residuals": list(res), "ms_per_qeq": ms,
+           "kernels_ms_avg": {k: round(v["ms_avg"], 4) for k, v in kern.items() if k.startswith("qeq")},
+           "stored_entries": nnz}
+    if spmv:
+        byts = nnz * 12.0 + n * 40.0
+        ach = byts / (spmv["ms_avg"] * 1e-3) / 1e9
+        out["spmv_roofline"] = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                "frac": ach / PEAK_HBM_GBS, "bytes_per_launch": byts,
+                                "avg_ms": spmv["ms_avg"]}
+    return out
+
+
 def bench_md(ff, params, steps=100, warmup_steps=5):
     """reaxff_step: velocity-Verlet NVE, dt 0.1 fs, lists rebuilt every step, on
     32,480 atoms (1,120 C5H8N4O12 units in a 69.2 A periodic box, Maxwell-Boltzmann
@@ -363,6 +417,7 @@ def main():
                     help="only the batched-clusters measurement (for profiling)")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate measurement")
     ap.add_argument("--no-md", action="store_true", help="skip the 32,480-atom MD measurement")
+    ap.add_argument("--no-qeq", action="store_true", help="skip the charge-equilibration measurement")
     ap.add_argument("--surrogate-only", action="store_true",
                     help="only the surrogate measurement (for profiling)")
     args = ap.parse_args()
@@ -500,6 +555,13 @@ def main():
              "units": {k: {"count": int(v / UNIT_FLOPS[k]), "flops_per_unit": UNIT_FLOPS[k]}
                        for k, v in per_unit.items()}}
 
+    qeq = None
+    if not args.no_qeq:
+        print("bench: charge equilibration", file=sys.stderr, flush=True)
+        ff.set_overlap(not args.no_overlap)
+        step()
+        qeq = bench_qeq(ff, n, counts["far_pairs"])
+
     md = None
     if not args.no_md:
         print("bench: MD steps on 32,480 atoms", file=sys.stderr, flush=True)
@@ -541,6 +603,7 @@ def main():
         "whole_step_roofline": whole,
         "cpu_baseline": cpu,
         "md_32480": md,
+        "qeq": qeq,
         "batched": batched,
         "surrogate": surrogate,
         "phases_ms": phases,

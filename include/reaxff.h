@@ -213,6 +213,24 @@ int reaxff_qeq(reaxff_ctx* ctx, int64_t n, const reaxff_qeq_params* qp, double t
                int32_t maxit, int32_t guess, double* q, double* s_out, double* t_out,
                int32_t* iters, double* resid, hipStream_t stream);
 
+/* ---- In-situ molecular species analysis (Section 3.4) ---------------------
+ *
+ * Over the corrected bond orders of the last reaxff_compute_forces: two atoms
+ * are bonded when their bond order is larger than bo_threshold (the paper's
+ * default is 0.3); bonded atoms share a molecule whose ID is the smallest
+ * caller index among its atoms; the IDs are renumbered 1..M in increasing
+ * order; a species is a molecule's count of atoms per element, molecules
+ * with equal counts being the same species (isomers are not told apart).
+ * mol [dev] (n) int32: each atom's molecule number 1..M (caller order).
+ * mol_counts [dev] (n, 4) int32 or NULL: rows 0..M-1 hold molecule m+1's C,
+ * H, N, O counts.  table [dev] (n, 5) int32 or NULL: rows 0..S-1 hold each
+ * species' C, H, N, O counts and its number of molecules, in increasing
+ * lexicographic order of the counts.  *nmol = M, *nspecies = S [host].
+ * REAXFF_ERR_STATE before any force evaluation on the current lists.
+ * Synchronises the device twice. */
+int reaxff_species(reaxff_ctx* ctx, double bo_threshold, int32_t* mol, int32_t* mol_counts,
+                   int32_t* table, int64_t* nmol, int64_t* nspecies, hipStream_t stream);
+
 /* ---- Batched evaluation of many small non-periodic systems ---------------
  *
  * Force-field fitting and cluster screening evaluate thousands of small,

@@ -100,6 +100,7 @@ def load_library():
                                       ctypes.POINTER(i32)]
     lib.reaxff_qeq.argtypes = [vp, i64, ctypes.POINTER(QeqParams), _d, i32, i32, vp, vp, vp,
                                ctypes.POINTER(i32), ctypes.POINTER(_d), vp]
+    lib.reaxff_species.argtypes = [vp, _d, vp, vp, vp, ctypes.POINTER(i64), ctypes.POINTER(i64), vp]
     lib.reaxff_compute_forces_batched.argtypes = [vp, i32, vp, i32, vp, vp, vp, vp, vp, vp, vp]
     lib.reaxff_surrogate_param_count.restype = i64
     lib.reaxff_surrogate_create.argtypes = [vp, i32, ctypes.POINTER(vp)]
@@ -281,6 +282,20 @@ class ReaxFF:
         if want_st:
             out = out + (s, t)
         return out if check else out + (rc,)
+
+    def species(self, n: int, bo_threshold: float = 0.3, device=None):
+        """reaxff_species over the bond orders of the last compute_forces: returns
+        (molecule number per atom (n,) int32, element counts per molecule (M,4) int32,
+        species table (S,5) int32: C, H, N, O counts and number of molecules) cuda tensors."""
+        dev = device if device is not None else torch.device("cuda", self.device)
+        mol = torch.empty(n, dtype=torch.int32, device=dev)
+        counts = torch.empty((max(n, 1), 4), dtype=torch.int32, device=dev)
+        table = torch.empty((max(n, 1), 5), dtype=torch.int32, device=dev)
+        nm = ctypes.c_int64(0)
+        ns = ctypes.c_int64(0)
+        self._check(self._lib.reaxff_species(self._h, float(bo_threshold), _ptr(mol), _ptr(counts), _ptr(table),
+                                             ctypes.byref(nm), ctypes.byref(ns), _stream()))
+        return mol, counts[:nm.value], table[:ns.value]
 
     def compute_forces_batched(self, sys_off, max_atoms: int, pos, type_, q, forces=None, energies=None,
                                status=None):

@@ -273,6 +273,10 @@ void reaxff_destroy(reaxff_ctx* c) {
     for (void* p : qp)
       if (p) (void)hipFree(p);
     if (Q.red_host) (void)hipHostFree(Q.red_host);
+    rx::Species& S = c->species;
+    void* sp[] = {S.parent, S.flag, S.rank, S.counts, S.order, S.order2, S.sid, S.key, S.key2, S.tmp};
+    for (void* p : sp)
+      if (p) (void)hipFree(p);
   }
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);
@@ -287,6 +291,7 @@ int reaxff_build_lists(reaxff_ctx* c, int64_t n, const double* pos, const int32_
   if (n >= (int64_t)INT32_MAX / 2) return fail(c, REAXFF_ERR_ARG, "n too large for 32-bit indices");
   HIPCHK(c, hipSetDevice(c->device));
   c->built = false;
+  c->forces_done = false;
   c->periodic = box != nullptr;
   if (box) {
     for (int k = 0; k < 3; ++k) {
@@ -487,6 +492,7 @@ int reaxff_compute_forces(reaxff_ctx* c, int64_t n, const double* pos, const int
   if (launch_forces(c->dp, c->grid, c->L, c->W, q, c->overlap ? c->side : st, c->ev_fork, c->ev_join, forces,
                     energies, c->sc, c->prof, st))
     return fail(c, REAXFF_ERR_HIP, "force launch failed");
+  c->forces_done = true;
   return REAXFF_OK;
 }
 

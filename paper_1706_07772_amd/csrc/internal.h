@@ -112,6 +112,17 @@ struct Qeq {
   int64_t hist_n = -1;
 };
 
+// species-analysis work arrays (device): union-find parents over caller
+// indices, root flags and ranks, per-molecule element counts, sort buffers
+struct Species {
+  int32_t *parent = nullptr, *flag = nullptr, *rank = nullptr, *counts = nullptr;
+  int32_t *order = nullptr, *order2 = nullptr, *sid = nullptr;
+  uint32_t *key = nullptr, *key2 = nullptr;
+  void* tmp = nullptr;
+  size_t tmp_bytes = 0;
+  int64_t cap = 0;
+};
+
 // exclusive prefix sums; out[n-1] holds the total when in[n-1] == 0
 int scan_i32(const int32_t* in, int32_t* out, int64_t n, Scratch& sc, hipStream_t st);
 int scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, Scratch& sc, hipStream_t st);
@@ -154,6 +165,7 @@ struct reaxff_ctx {
   rx::Scratch sc{};
   rx::Prof prof;
   rx::Qeq qeq;
+  rx::Species species;
   // the nonbonded term runs on a stream of its own, concurrent with the
   // bonded terms, between a fork and a join event on the caller's stream
   hipStream_t side = nullptr;
@@ -161,6 +173,7 @@ struct reaxff_ctx {
   bool overlap = true;
   bool upper_off = false;   // a build found the half evaluation impossible: full far rows from then on
   bool built = false;
+  bool forces_done = false;  // bond orders of the current lists are computed
   double box[3] = {0, 0, 0};
   bool periodic = false;
   int64_t cap_n = 0, cap_cell = 0, cap_far = 0, cap_bond = 0, cap_hb = 0, cap_ha = 0, cap_part = 0;
