@@ -126,10 +126,12 @@ int reaxff_compute_forces(reaxff_ctx* ctx, int64_t n, const double* pos,
                           const int32_t* type, const double* q, const double* box,
                           double* forces, double* energies, hipStream_t stream);
 
-/* nsteps steps of velocity-Verlet NVE (dt in fs, Section 4's MD step), lists
- * rebuilt every step: lists and forces at the initial positions, then per
- * step half kick, drift (positions wrapped into a periodic box), lists,
- * forces, half kick.  pos, vel [dev] (n,3) in/out; forces [dev] (n,3) out:
+/* nsteps steps of velocity-Verlet NVE (dt in fs, Section 4's MD step): lists
+ * and forces at the initial positions, then per step half kick, drift
+ * (positions wrapped into a periodic box), lists, forces, half kick.  Lists
+ * are built every step, or with skin lists (reaxff_set_skin) refreshed as
+ * reaxff_refresh_lists does, positions then being wrapped only when the
+ * lists are built again.  pos, vel [dev] (n,3) in/out; forces [dev] (n,3) out:
  * the forces at the final positions.  energies [dev]
  * ((nsteps+1), REAXFF_NTERMS+1): potential terms and kinetic energy at every
  * step, step 0 first.  One host synchronisation per step (list sizes). */
@@ -137,6 +139,33 @@ int reaxff_step(reaxff_ctx* ctx, int64_t n, double* pos, double* vel,
                 const int32_t* type, const double* q, const double* box,
                 double dt, int32_t nsteps, double* forces, double* energies,
                 hipStream_t stream);
+
+/* Verlet-skin lists (the paper's runs check the neighbour lists every 10
+ * steps, Section 4): with skin > 0 the far list, the H-bond list and the bond
+ * candidates are built with every distance cutoff enlarged by `skin` (A), and
+ * kept by reaxff_refresh_lists while no atom has moved more than skin / 2
+ * since the build, for at most `every` (>= 1) calls; each call still remakes
+ * the bond list (bond orders change every step) and the force kernels apply
+ * the exact cutoffs to the kept far and H lists, so energies and forces are
+ * those of exact lists.  Periodic box edges must then be at least
+ * 2 (r_nonb + skin).  skin = 0 (the default): exact lists, built by every
+ * call.  Takes effect at the next build; 0 <= skin <= r_nonb, else
+ * REAXFF_ERR_ARG. */
+int reaxff_set_skin(reaxff_ctx* ctx, double skin, int32_t every);
+
+/* Lists for new positions of the same atoms (same n, types and box): a full
+ * reaxff_build_lists when skin lists are off, when the kept lists are `every`
+ * calls old, when some atom moved more than skin / 2 since the build (pos
+ * compared without wrapping: positions must move continuously between
+ * builds), or when n or the box changed; otherwise the kept far and H lists
+ * with the current positions and a new bond list.  *rebuilt [host] (may be
+ * NULL): 1 for a full build, 0 otherwise.  One host synchronisation. */
+int reaxff_refresh_lists(reaxff_ctx* ctx, int64_t n, const double* pos, const int32_t* type,
+                         const double* box, int32_t* rebuilt, hipStream_t stream);
+
+/* stats[0] full list builds, stats[1] refreshes that kept the lists, since
+ * the context was created [host]. */
+int reaxff_list_stats(const reaxff_ctx* ctx, int64_t stats[2]);
 
 /* Sizes of the last built lists: sizes[0] far pairs (unordered),
  * sizes[1] bond-list entries (directed), sizes[2] H-list entries. [host] */

@@ -87,6 +87,9 @@ def load_library():
     lib.reaxff_compute_forces.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
     lib.reaxff_step.argtypes = [vp, i64, vp, vp, vp, vp, vp, _d, i32, vp, vp, vp]
     lib.reaxff_list_sizes.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.reaxff_set_skin.argtypes = [vp, _d, i32]
+    lib.reaxff_refresh_lists.argtypes = [vp, i64, vp, vp, vp, ctypes.POINTER(i32), vp]
+    lib.reaxff_list_stats.argtypes = [vp, ctypes.POINTER(i64)]
     lib.reaxff_export_lists.argtypes = [vp, vp, vp, vp]
     lib.reaxff_interaction_counts.argtypes = [vp, ctypes.POINTER(i64)]
     lib.reaxff_batch_create.argtypes = [vp, i32, vp, vp, ctypes.POINTER(vp)]
@@ -210,6 +213,25 @@ class ReaxFF:
         b, bp = self._boxarg(box)
         self._check(self._lib.reaxff_build_lists(self._h, pos.shape[0], _ptr(pos), _ptr(type_), bp,
                                                  _stream()))
+
+    def set_skin(self, skin: float, every: int = 10):
+        """reaxff_set_skin: Verlet-skin lists (skin in A, kept for at most `every` refreshes)."""
+        self._check(self._lib.reaxff_set_skin(self._h, float(skin), int(every)))
+
+    def refresh_lists(self, pos: torch.Tensor, type_: torch.Tensor, box=None) -> bool:
+        """reaxff_refresh_lists; returns True when the lists were built from scratch."""
+        assert pos.dtype == torch.float64 and pos.is_cuda and pos.is_contiguous()
+        b, bp = self._boxarg(box)
+        rb = ctypes.c_int32(0)
+        self._check(self._lib.reaxff_refresh_lists(self._h, pos.shape[0], _ptr(pos), _ptr(type_), bp,
+                                                   ctypes.byref(rb), _stream()))
+        return bool(rb.value)
+
+    def list_stats(self):
+        """(full builds, refreshes that kept the lists) since creation."""
+        s = (ctypes.c_int64 * 2)()
+        self._check(self._lib.reaxff_list_stats(self._h, s))
+        return int(s[0]), int(s[1])
 
     def compute_forces(self, pos, type_, q, box=None, forces=None, energies=None):
         """reaxff_compute_forces -> (forces (n,3), energies (12,)) float64 cuda tensors."""

@@ -182,6 +182,106 @@ int alloc_bonds(reaxff_ctx* c, int64_t nb) {
   return 0;
 }
 
+int set_task_bounds(reaxff_ctx* c, const int64_t* th) {
+  c->L.bound_ang = th[1];
+  c->L.bound_tor = th[2];
+  c->L.bound_don = th[3];
+  int64_t t = c->W.cap_ang;
+  if (grow(c, c->W.ang, t, std::max<int64_t>(c->L.bound_ang, 1))) return REAXFF_ERR_HIP;
+  c->W.cap_ang = t;
+  t = c->W.cap_tor;
+  if (grow(c, c->W.tor, t, std::max<int64_t>(c->L.bound_tor, 1))) return REAXFF_ERR_HIP;
+  c->W.cap_tor = t;
+  t = c->W.cap_don;
+  if (grow(c, c->W.don, t, std::max<int64_t>(c->L.bound_don, 1))) return REAXFF_ERR_HIP;
+  int64_t t2 = c->W.cap_don;
+  if (grow(c, c->W.donrec, t2, std::max<int64_t>(c->L.bound_don, 1))) return REAXFF_ERR_HIP;
+  c->W.cap_don = t;
+  return 0;
+}
+
+// Lists for the current positions with the sorted order, cells, far and H
+// rows of the last build kept: when skin lists are on, the build is recent
+// enough (fewer than `every` refreshes) and no atom has moved more than
+// skin / 2 since it, only the sorted positions and the bond list (bond test
+// over the stored candidates, compressed rows, mirror index, task bounds) are
+// made again.  Otherwise a full build, after wrapping pos_mut into a
+// periodic box when it is given.  *rebuilt tells which happened.
+int refresh_lists(reaxff_ctx* c, int64_t n, const double* pos, double* pos_mut, const int32_t* type,
+                  const double* box, int32_t* rebuilt, hipStream_t st) {
+  bool full = !(c->skin > 0.0) || !c->built || n != c->L.n || n == 0 || (box != nullptr) != c->periodic ||
+              c->since + 1 >= c->every;
+  if (!full && box)
+    for (int k = 0; k < 3; ++k) full = full || box[k] != c->box[k];
+  if (!full) {
+    HIPCHK(c, hipSetDevice(c->device));
+    c->built = false;
+    c->forces_done = false;
+    Scratch& sc = c->sc;
+    HIPCHK(c, hipMemsetAsync(c->dmax, 0, sizeof(unsigned long long), st));
+    if (launch_refresh_gather(pos, n, c->xref, c->L, c->dmax, c->prof, st))
+      return fail(c, REAXFF_ERR_HIP, "refresh gather failed");
+    int32_t need[8];
+    int32_t nb = 0;
+    unsigned long long dm = 0;
+    int64_t* th = sc.totals_host;
+    for (int attempt = 0;; ++attempt) {
+      HIPCHK(c, hipMemsetAsync(sc.need, 0, sizeof(int32_t) * 8, st));
+      HIPCHK(c, hipMemsetAsync(sc.totals, 0, sizeof(int64_t) * 8, st));
+      HIPCHK(c, hipMemsetAsync(sc.tslot, 0, sizeof(int64_t) * 8 * ESLOT, st));
+      HIPCHK(c, hipMemsetAsync(sc.nslot, 0, sizeof(int32_t) * ESLOT, st));
+      if (launch_bondtest(c->dp, c->grid, n, c->cut.r_bond * c->cut.r_bond, sc, c->L, c->prof, st))
+        return fail(c, REAXFF_ERR_HIP, "bond test launch failed");
+      HIPCHK(c, hipMemsetAsync(sc.cnt_bond + n, 0, sizeof(int32_t), st));
+      c->prof.begin(KID_SCAN, st);
+      const int src = scan_i32(sc.cnt_bond, c->L.bond_off, n + 1, sc, st);
+      c->prof.end(st);
+      if (src) return fail(c, REAXFF_ERR_HIP, "scan failed");
+      HIPCHK(c, hipMemcpyAsync(th, sc.totals, sizeof(int64_t) * 8, hipMemcpyDeviceToHost, st));
+      HIPCHK(c, hipMemcpyAsync(&nb, c->L.bond_off + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      HIPCHK(c, hipMemcpyAsync(need, sc.need, sizeof(need), hipMemcpyDeviceToHost, st));
+      HIPCHK(c, hipMemcpyAsync(&dm, c->dmax, sizeof(dm), hipMemcpyDeviceToHost, st));
+      HIPCHK(c, hipStreamSynchronize(st));
+      double d2;
+      std::memcpy(&d2, &dm, sizeof(d2));
+      if (!(std::sqrt(d2) <= 0.5 * c->skin)) {   // moved too far (or non-finite): build again
+        full = true;
+        break;
+      }
+      if (need[2] <= sc.bond_w) break;
+      if (attempt >= 3) return fail(c, REAXFF_ERR_CAPACITY, "bond staging width did not converge");
+      sc.bond_w = (int32_t)(need[2] * 1.15) + 16;
+      int64_t t = sc.cap_bondt;
+      if (grow(c, sc.bond_t, t, n * (int64_t)sc.bond_w, 1.0)) return REAXFF_ERR_HIP;
+      sc.cap_bondt = t;
+    }
+    if (!full) {
+      c->L.nbond = nb;
+      if (set_task_bounds(c, th)) return REAXFF_ERR_HIP;
+      if (alloc_bonds(c, std::max<int64_t>(c->L.nbond, 1))) return REAXFF_ERR_HIP;
+      if (launch_compact(n, sc, c->L, c->prof, st)) return fail(c, REAXFF_ERR_HIP, "compact launch failed");
+      ++c->since;
+      ++c->nrefresh;
+      c->built = true;
+      if (rebuilt) *rebuilt = 0;
+      return REAXFF_OK;
+    }
+  }
+  if (pos_mut && box) {
+    // wrap into the box before building (the grid of the last build is only
+    // used for its box edges here)
+    Grid g{};
+    g.periodic = 1;
+    for (int k = 0; k < 3; ++k) {
+      g.L[k] = box[k];
+      g.invL[k] = 1.0 / box[k];
+    }
+    if (launch_wrap(n, pos_mut, g, st)) return fail(c, REAXFF_ERR_HIP, "wrap launch failed");
+  }
+  if (rebuilt) *rebuilt = 1;
+  return reaxff_build_lists(c, n, pos, type, box, st);
+}
+
 }  // namespace
 
 extern "C" {
@@ -238,6 +338,7 @@ int reaxff_create(const reaxff_params* params, const reaxff_cutoffs* cutoffs, in
       hipMalloc(&c->sc.need, sizeof(int32_t) * 8) != hipSuccess ||
       hipHostMalloc(&c->sc.totals_host, sizeof(int64_t) * 8, hipHostMallocDefault) != hipSuccess ||
       hipMalloc(&c->W.counters, sizeof(unsigned long long) * 4) != hipSuccess ||
+      hipMalloc(&c->dmax, sizeof(unsigned long long)) != hipSuccess ||
       hipMalloc(&c->W.epart, sizeof(double) * ESLOT * NTERMS) != hipSuccess ||
       hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
@@ -267,6 +368,8 @@ void reaxff_destroy(reaxff_ctx* c) {
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->sc.totals_host) (void)hipHostFree(c->sc.totals_host);
+  for (void* p : {(void*)c->dp_list, (void*)c->xref, (void*)c->dmax})
+    if (p) (void)hipFree(p);
   {
     rx::Qeq& Q = c->qeq;
     void* qp[] = {Q.hj, Q.hv, Q.hcnt, Q.x, Q.r, Q.p, Q.ap, Q.red, Q.need, Q.hist[0], Q.hist[1], Q.hist[2], Q.hist[3]};
@@ -293,10 +396,12 @@ int reaxff_build_lists(reaxff_ctx* c, int64_t n, const double* pos, const int32_
   c->built = false;
   c->forces_done = false;
   c->periodic = box != nullptr;
+  // list cutoff: r_nonb, plus the skin when lists are kept over several steps
+  const double r_list = c->cut.r_nonb + c->skin;
   if (box) {
     for (int k = 0; k < 3; ++k) {
-      if (!(std::isfinite(box[k]) && box[k] >= 2.0 * c->cut.r_nonb))
-        return fail(c, REAXFF_ERR_BOX, "periodic box edge below 2 r_nonb");
+      if (!(std::isfinite(box[k]) && box[k] >= 2.0 * r_list))
+        return fail(c, REAXFF_ERR_BOX, "periodic box edge below 2 (r_nonb + skin)");
       c->box[k] = box[k];
     }
   }
@@ -332,10 +437,10 @@ int reaxff_build_lists(reaxff_ctx* c, int64_t n, const double* pos, const int32_
   {
     double vol = 1.0;
     for (int k = 0; k < 3; ++k) vol *= c->periodic ? c->box[k] : std::max(hi[k] - lo[k], 1.0);
-    const double per_cell = (double)n / vol * std::pow(0.5 * c->cut.r_nonb, 3.0);
+    const double per_cell = (double)n / vol * std::pow(0.5 * r_list, 3.0);
     if (per_cell < 4.0) reach = 1;
   }
-  make_grid(c->grid, c->periodic, c->box, lo, hi, c->cut.r_nonb, reach);
+  make_grid(c->grid, c->periodic, c->box, lo, hi, r_list, reach);
   c->grid.shift_ok = 0;
   if (c->periodic && n > 0) {
     bool ok = true;
@@ -368,9 +473,9 @@ int reaxff_build_lists(reaxff_ctx* c, int64_t n, const double* pos, const int32_
     };
     c->L.far_upper = c->L.far_slots && !c->upper_off && !c->grid.full[0] && !c->grid.full[1] &&
                      !c->grid.full[2];
-    if (c->L.far_w == 0) c->L.far_w = c->L.far_upper ? est(c->cut.r_nonb) / 2 + 32 : est(c->cut.r_nonb);
-    if (c->L.hb_w == 0) c->L.hb_w = est(c->cut.r_hb);
-    if (c->L.ha_w == 0) c->L.ha_w = est(c->cut.r_hb);
+    if (c->L.far_w == 0) c->L.far_w = c->L.far_upper ? est(r_list) / 2 + 32 : est(r_list);
+    if (c->L.hb_w == 0) c->L.hb_w = est(c->cut.r_hb + c->skin);
+    if (c->L.ha_w == 0) c->L.ha_w = est(c->cut.r_hb + c->skin);
     if (c->sc.cand_w == 0) c->sc.cand_w = 32;
     if (c->sc.bond_w == 0) c->sc.bond_w = 16;
   }
@@ -396,7 +501,8 @@ int reaxff_build_lists(reaxff_ctx* c, int64_t n, const double* pos, const int32_
       if (grow(c, c->L.ha_j, t, rows * c->L.ha_w, 1.0)) return REAXFF_ERR_HIP;
       c->cap_ha = t;
     }
-    if (n > 0 && launch_sweep(c->dp, c->grid, n, (int)ncell, c->sc, c->L, c->prof, st))
+    if (n > 0 && launch_sweep(c->skin > 0.0 ? c->dp_list : c->dp, c->grid, n, (int)ncell,
+                              c->cut.r_bond * c->cut.r_bond, c->sc, c->L, c->prof, st))
       return fail(c, REAXFF_ERR_HIP, "sweep launch failed");
     if (n == 0) HIPCHK(c, hipMemsetAsync(c->sc.totals, 0, sizeof(int64_t) * 8, st));
     // bond offsets: counts with a trailing zero, exclusive scan, last element = total
@@ -453,25 +559,18 @@ int reaxff_build_lists(reaxff_ctx* c, int64_t n, const double* pos, const int32_
   }
   c->L.nbond = t32[0];
   c->L.nhb = th[4];
-  c->L.bound_ang = th[1];
-  c->L.bound_tor = th[2];
-  c->L.bound_don = th[3];
-  {
-    int64_t t = c->W.cap_ang;
-    if (grow(c, c->W.ang, t, std::max<int64_t>(c->L.bound_ang, 1))) return REAXFF_ERR_HIP;
-    c->W.cap_ang = t;
-    t = c->W.cap_tor;
-    if (grow(c, c->W.tor, t, std::max<int64_t>(c->L.bound_tor, 1))) return REAXFF_ERR_HIP;
-    c->W.cap_tor = t;
-    t = c->W.cap_don;
-    if (grow(c, c->W.don, t, std::max<int64_t>(c->L.bound_don, 1))) return REAXFF_ERR_HIP;
-    int64_t t2 = c->W.cap_don;
-    if (grow(c, c->W.donrec, t2, std::max<int64_t>(c->L.bound_don, 1))) return REAXFF_ERR_HIP;
-    c->W.cap_don = t;
-  }
+  if (set_task_bounds(c, th)) return REAXFF_ERR_HIP;
   if (alloc_bonds(c, std::max<int64_t>(c->L.nbond, 1))) return REAXFF_ERR_HIP;
   if (n > 0 && launch_compact(n, c->sc, c->L, c->prof, st))
     return fail(c, REAXFF_ERR_HIP, "compact launch failed");
+  c->L.cut_check = c->skin > 0.0 ? 1 : 0;
+  if (c->skin > 0.0 && n > 0) {
+    // reference positions for the displacement check of later refreshes
+    if (grow(c, c->xref, c->cap_xref, n)) return REAXFF_ERR_HIP;
+    HIPCHK(c, hipMemcpyAsync(c->xref, c->L.xs, sizeof(double4) * n, hipMemcpyDeviceToDevice, st));
+  }
+  c->since = 0;
+  ++c->nrebuild;
   c->built = true;
   return REAXFF_OK;
 }
@@ -509,10 +608,13 @@ int reaxff_step(reaxff_ctx* c, int64_t n, double* pos, double* vel, const int32_
   if ((rc = reaxff_build_lists(c, n, pos, type, box, st))) return rc;
   if ((rc = reaxff_compute_forces(c, n, pos, type, q, box, forces, energies, st))) return rc;
   launch_kinetic(n, vel, type, c->dp, energies + REAXFF_NTERMS, st);
+  // with skin lists, positions stay continuous between rebuilds (wrapped
+  // into the box only when the lists are built again)
+  const bool keep = c->skin > 0.0;
   for (int s = 1; s <= nsteps; ++s) {
     launch_kick(n, vel, forces, type, c->dp, 0.5 * dt, st);
-    launch_drift(n, pos, vel, dt, c->grid, st);
-    if ((rc = reaxff_build_lists(c, n, pos, type, box, st))) return rc;
+    launch_drift(n, pos, vel, dt, c->grid, !keep, st);
+    if ((rc = refresh_lists(c, n, pos, pos, type, box, nullptr, st))) return rc;
     if ((rc = reaxff_compute_forces(c, n, pos, type, q, box, forces, energies + s * row, st)))
       return rc;
     launch_kick(n, vel, forces, type, c->dp, 0.5 * dt, st);
@@ -553,6 +655,48 @@ int reaxff_export_lists(reaxff_ctx* c, int32_t* far, int32_t* bonds, int32_t* hb
 int reaxff_set_overlap(reaxff_ctx* c, int32_t enable) {
   if (!c) return REAXFF_ERR_ARG;
   c->overlap = enable != 0;
+  return REAXFF_OK;
+}
+
+int reaxff_set_skin(reaxff_ctx* c, double skin, int32_t every) {
+  if (!c) return REAXFF_ERR_ARG;
+  if (!(skin >= 0.0 && skin <= c->cut.r_nonb) || every < 1)
+    return fail(c, REAXFF_ERR_ARG, "reaxff_set_skin: skin must lie in [0, r_nonb] and every >= 1");
+  HIPCHK(c, hipSetDevice(c->device));
+  c->skin = skin;
+  c->every = every;
+  c->built = false;
+  c->forces_done = false;
+  c->L.far_w = 0;   // widths re-estimated for the new cutoffs
+  c->L.hb_w = 0;
+  c->L.ha_w = 0;
+  if (skin > 0.0) {
+    DevParams d = c->hd;
+    const double rl = c->cut.r_nonb + skin, rh = c->cut.r_hb + skin;
+    d.rn2 = rl * rl;
+    d.rh2 = rh * rh;
+    d.r_bond = c->cut.r_bond + skin;
+    for (int t = 0; t < NT * NT; ++t) {
+      const double r = std::sqrt(c->hd.pair[t].reach2) + skin;
+      d.pair[t].reach2 = r * r;
+    }
+    if (!c->dp_list) HIPCHK(c, hipMalloc(&c->dp_list, sizeof(DevParams)));
+    HIPCHK(c, hipMemcpy(c->dp_list, &d, sizeof(DevParams), hipMemcpyHostToDevice));
+  }
+  return REAXFF_OK;
+}
+
+int reaxff_refresh_lists(reaxff_ctx* c, int64_t n, const double* pos, const int32_t* type, const double* box,
+                         int32_t* rebuilt, hipStream_t st) {
+  if (!c) return REAXFF_ERR_ARG;
+  if (n < 0 || (n > 0 && (!pos || !type))) return fail(c, REAXFF_ERR_ARG, "bad n or null pointer");
+  return refresh_lists(c, n, pos, nullptr, type, box, rebuilt, st);
+}
+
+int reaxff_list_stats(const reaxff_ctx* c, int64_t stats[2]) {
+  if (!c || !stats) return REAXFF_ERR_ARG;
+  stats[0] = c->nrebuild;
+  stats[1] = c->nrefresh;
   return REAXFF_OK;
 }
 

@@ -404,13 +404,15 @@ __global__ __launch_bounds__(BS) void k_hbonds(const DevParams* __restrict__ P, 
       if (Z == X) continue;
       const double4 xz = L.xs[Z];   // position and type
       const HbP& hp = hbt[(tx * NT + th) * NT + (int)xz.w];
-      ++nhb;
       double dx = xz.x - xh.x, dy = xz.y - xh.y, dz = xz.z - xh.z;
       if (g.periodic) {
         dx = min_image(dx, g.L[0], g.invL[0]);
         dy = min_image(dy, g.L[1], g.invL[1]);
         dz = min_image(dz, g.L[2], g.invL[2]);
       }
+      // a skin entry beyond r_hb (the list's own predicate, same rounding)
+      if (L.cut_check && r2_of(dx, dy, dz) > P->rh2) continue;
+      ++nhb;
       const HbTerm o = hb_term(hp, bo, rx, dx, dy, dz);
       ehb += o.E;
       gbo += o.dE_dbo;
@@ -510,6 +512,7 @@ __global__ __launch_bounds__(BS) void k_hb_acceptors(const DevParams* __restrict
       dy = min_image(dy, g.L[1], g.invL[1]);
       dz = min_image(dz, g.L[2], g.invL[2]);
     }
+    if (L.cut_check && r2_of(dx, dy, dz) > P->rh2) return;   // a skin entry beyond r_hb
     const HbP& hp = hbt[(d.tX * NT + th) * NT + tz];
     const HbTerm o = hb_term(hp, d.bo, d.bd, dx, dy, dz);
     fz.x -= o.g_rz.x;
@@ -751,6 +754,7 @@ __global__ __launch_bounds__(NBC_BS) void k_nonbonded(const DevParams* __restric
             dz = min_image(dz, g.L[2], g.invL[2]);
           }
           const double r2 = dx * dx + dy * dy + dz * dz;
+          if (L.cut_check && r2 > P->rn2) continue;   // a skin entry beyond the cutoff
           const NbOut o = nb_pair(spi[tj], iR, pv, ipv, qi * qj, r2);
           evdw += o.ev;
           ecoul += o.eq;
@@ -880,7 +884,7 @@ __global__ __launch_bounds__(NBH_BS) void k_nonbonded_half(const DevParams* __re
       if (t < nup) fax[t] = fay[t] = faz[t] = 0.0;
     }
   }
-  const double iR = P->inv_r_nonb, pv = P->p_vdW1, ipv = P->inv_p_vdW1;
+  const double iR = P->inv_r_nonb, pv = P->p_vdW1, ipv = P->inv_p_vdW1, rn2c = P->rn2;
   double evdw = 0.0, ecoul = 0.0;
   for (int g0 = 0; g0 < m; g0 += NBC_MG) {
     const int mg = m - g0 < NBC_MG ? m - g0 : NBC_MG;
@@ -971,6 +975,7 @@ __global__ __launch_bounds__(NBH_BS) void k_nonbonded_half(const DevParams* __re
             dz = min_image(dz, g.L[2], g.invL[2]);
           }
           const double r2 = dx * dx + dy * dy + dz * dz;
+          if (L.cut_check && r2 > rn2c) continue;   // a skin entry beyond the cutoff
           const NbOut o = nb_pair(spi[sty[tnow]], iR, pv, ipv, qi * sxq[tnow], r2);
           evdw += o.ev;
           ecoul += o.eq;
@@ -1235,14 +1240,26 @@ __global__ void k_kick(int64_t n, double* __restrict__ vel, const double* __rest
   for (int k = 0; k < 3; ++k) vel[3 * i + k] += s * f[3 * i + k];
 }
 
+// positions advance by dt v; with wrap, every coordinate is put back into
+// [0, L) of a periodic box (lists kept over several steps need continuous
+// positions between their rebuilds, and wrap only then)
 __global__ void k_drift(int64_t n, double* __restrict__ pos, const double* __restrict__ vel, double dt,
-                        Grid g) {
+                        Grid g, int wrap) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   for (int k = 0; k < 3; ++k) {
     double x = pos[3 * i + k] + dt * vel[3 * i + k];
-    if (g.periodic) x -= g.L[k] * floor(x * g.invL[k]);
+    if (g.periodic && wrap) x -= g.L[k] * floor(x * g.invL[k]);
     pos[3 * i + k] = x;
+  }
+}
+
+__global__ void k_wrap(int64_t n, double* __restrict__ pos, Grid g) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = 0; k < 3; ++k) {
+    const double x = pos[3 * i + k];
+    pos[3 * i + k] = x - g.L[k] * floor(x * g.invL[k]);
   }
 }
 
@@ -1263,8 +1280,12 @@ int launch_kick(int64_t n, double* vel, const double* forces, const int32_t* typ
   if (n > 0) hipLaunchKernelGGL(k_kick, dim3(nblk(n, BS)), dim3(BS), 0, st, n, vel, forces, type, P, half_dt);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
-int launch_drift(int64_t n, double* pos, const double* vel, double dt, const Grid& g, hipStream_t st) {
-  if (n > 0) hipLaunchKernelGGL(k_drift, dim3(nblk(n, BS)), dim3(BS), 0, st, n, pos, vel, dt, g);
+int launch_drift(int64_t n, double* pos, const double* vel, double dt, const Grid& g, bool wrap, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_drift, dim3(nblk(n, BS)), dim3(BS), 0, st, n, pos, vel, dt, g, wrap ? 1 : 0);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+int launch_wrap(int64_t n, double* pos, const Grid& g, hipStream_t st) {
+  if (n > 0 && g.periodic) hipLaunchKernelGGL(k_wrap, dim3(nblk(n, BS)), dim3(BS), 0, st, n, pos, g);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 int launch_kinetic(int64_t n, const double* vel, const int32_t* type, const DevParams* P, double* out,

@@ -131,8 +131,12 @@ int launch_bbox(const double* pos, const int32_t* type, int64_t n, double* part,
                 int32_t* flag, Prof& pf, hipStream_t st);
 int launch_cell_sort(const double* pos, const int32_t* type, int64_t n, const Grid& g, int ncell,
                      Scratch& sc, Lists& L, Prof& pf, hipStream_t st);
-int launch_sweep(const DevParams* P, const Grid& g, int64_t n, int ncell, Scratch& sc, Lists& L,
+int launch_sweep(const DevParams* P, const Grid& g, int64_t n, int ncell, double rb2, Scratch& sc, Lists& L,
                  Prof& pf, hipStream_t st);
+int launch_bondtest(const DevParams* P, const Grid& g, int64_t n, double rb2, Scratch& sc, Lists& L, Prof& pf,
+                    hipStream_t st);
+int launch_refresh_gather(const double* pos, int64_t n, const double4* xref, Lists& L, unsigned long long* dmax,
+                          Prof& pf, hipStream_t st);
 int launch_compact(int64_t n, Scratch& sc, Lists& L, Prof& pf, hipStream_t st);
 int launch_export(const Grid& g, const Lists& L, int32_t* far, int32_t* bonds, int32_t* hb, Scratch& sc,
                   hipStream_t st);
@@ -142,7 +146,8 @@ int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, co
                   double* forces, double* energies, Scratch& sc, Prof& pf, hipStream_t st);
 int launch_kick(int64_t n, double* vel, const double* forces, const int32_t* type,
                 const DevParams* P, double half_dt, hipStream_t st);
-int launch_drift(int64_t n, double* pos, const double* vel, double dt, const Grid& g, hipStream_t st);
+int launch_drift(int64_t n, double* pos, const double* vel, double dt, const Grid& g, bool wrap, hipStream_t st);
+int launch_wrap(int64_t n, double* pos, const Grid& g, hipStream_t st);
 int launch_kinetic(int64_t n, const double* vel, const int32_t* type, const DevParams* P,
                    double* out, hipStream_t st);
 
@@ -172,6 +177,17 @@ struct reaxff_ctx {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool overlap = true;
   bool upper_off = false;   // a build found the half evaluation impossible: full far rows from then on
+  // Verlet-skin lists: far, H and bond-candidate lists built with the cutoffs
+  // plus `skin` and kept while no atom has moved more than skin / 2 since the
+  // build, for at most `every` refreshes; dp_list holds the enlarged cutoffs
+  double skin = 0.0;
+  int32_t every = 1;
+  int32_t since = 0;
+  rx::DevParams* dp_list = nullptr;
+  double4* xref = nullptr;          // sorted positions at the last build
+  int64_t cap_xref = 0;
+  unsigned long long* dmax = nullptr;
+  int64_t nrebuild = 0, nrefresh = 0;
   bool built = false;
   bool forces_done = false;  // bond orders of the current lists are computed
   double box[3] = {0, 0, 0};

@@ -383,7 +383,7 @@ __global__ __launch_bounds__(BT_BS) void k_bondtest(
     const DevParams* __restrict__ P, Grid g, int64_t n, const double4* __restrict__ xs,
     const int32_t* __restrict__ cnt_cand, const int32_t* __restrict__ cand_j, int cand_w,
     int32_t* __restrict__ cnt_bond, int32_t* __restrict__ bond_t, int bond_w,
-    int32_t* __restrict__ need, unsigned long long* __restrict__ tslot) {
+    int32_t* __restrict__ need, unsigned long long* __restrict__ tslot, double rb2) {
   __shared__ unsigned long long red[BT_BS / 64][3];
   __shared__ BondTestP bp[NT * NT];
   for (int t = threadIdx.x; t < NT * NT; t += BT_BS) {
@@ -440,7 +440,9 @@ __global__ __launch_bounds__(BT_BS) void k_bondtest(
           dz = min_image(dz, g.L[2], g.invL[2]);
         }
         const double r2 = r2_of(dx, dy, dz);
-        ok = bo_raw(bp[ti * NT + (int)xj.w], sqrt(r2), bo_cut) >= bo_cut;
+        // within r_bond (candidates found with a skin may lie beyond it), and
+        // the raw order at the threshold
+        ok = r2 <= rb2 && bo_raw(bp[ti * NT + (int)xj.w], sqrt(r2), bo_cut) >= bo_cut;
       }
       const unsigned mask = (unsigned)(ballot(ok) >> gsh) & ((1u << BT_GROUP) - 1u);
       if (ok) {
@@ -639,7 +641,7 @@ __global__ void k_fold_totals(const unsigned long long* __restrict__ tslot, cons
   }
 }
 
-int launch_sweep(const DevParams* P, const Grid& g, int64_t n, int ncell, Scratch& sc, Lists& L,
+int launch_sweep(const DevParams* P, const Grid& g, int64_t n, int ncell, double rb2, Scratch& sc, Lists& L,
                  Prof& pf, hipStream_t st) {
   if (stencil_chunks(g) > SWEEP_MAXQ) return -1;   // the sweep's chunk table
   (void)hipMemsetAsync(sc.need, 0, sizeof(int32_t) * 8, st);
@@ -663,13 +665,47 @@ int launch_sweep(const DevParams* P, const Grid& g, int64_t n, int ncell, Scratc
     else sweep(k_sweep<false, false>);
   }
   pf.end(st);
+  return launch_bondtest(P, g, n, rb2, sc, L, pf, st);
+}
+
+int launch_bondtest(const DevParams* P, const Grid& g, int64_t n, double rb2, Scratch& sc, Lists& L, Prof& pf,
+                    hipStream_t st) {
   pf.begin(KID_BONDTEST, st);
   hipLaunchKernelGGL(k_bondtest, dim3(xcd_grid(std::min<int64_t>(nblk(n, BT_TILE), 4096))), dim3(BT_BS), 0, st,
                      P, g, n, L.xs, sc.cnt_cand,
                      sc.cand_j, sc.cand_w, sc.cnt_bond, sc.bond_t, sc.bond_w, sc.need,
-                     reinterpret_cast<unsigned long long*>(sc.tslot));
+                     reinterpret_cast<unsigned long long*>(sc.tslot), rb2);
   hipLaunchKernelGGL(k_fold_totals, dim3(1), dim3(64), 0, st, reinterpret_cast<const unsigned long long*>(sc.tslot), sc.nslot,
                      reinterpret_cast<unsigned long long*>(sc.totals), sc.need);
+  pf.end(st);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// positions of the sorted layout from the caller's (the order fixed at the
+// last build), and the largest squared displacement since then (as the
+// order-preserving bits of a non-negative double)
+__global__ void k_refresh_gather(const double* __restrict__ pos, const int32_t* __restrict__ perm, int64_t n,
+                                 const double4* __restrict__ xref, double4* __restrict__ xs,
+                                 unsigned long long* __restrict__ dmax) {
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double d2 = 0.0;
+  if (s < n) {
+    const int i = perm[s];
+    const double4 r = xref[s];
+    const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+    xs[s] = make_double4(x, y, z, r.w);
+    d2 = (x - r.x) * (x - r.x) + (y - r.y) * (y - r.y) + (z - r.z) * (z - r.z);
+    if (!(d2 <= 1e300)) d2 = 1e300;   // non-finite: forces a rebuild, which reports it
+  }
+  for (int off = 32; off > 0; off >>= 1) d2 = fmax(d2, __shfl_down(d2, off, 64));
+  if ((threadIdx.x & 63) == 0 && d2 > 0.0) atomicMax(dmax, (unsigned long long)__double_as_longlong(d2));
+}
+
+int launch_refresh_gather(const double* pos, int64_t n, const double4* xref, Lists& L, unsigned long long* dmax,
+                          Prof& pf, hipStream_t st) {
+  pf.begin(KID_GATHER, st);
+  if (n > 0)
+    hipLaunchKernelGGL(k_refresh_gather, dim3(nblk(n, 256)), dim3(256), 0, st, pos, L.perm, n, xref, L.xs, dmax);
   pf.end(st);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -120,6 +120,9 @@ struct Lists {
   int32_t* ha_cnt;      // [n]
   int32_t* ha_j;
   int32_t ha_w;
+  // the far and H lists are supersets built with a skin (Verlet lists kept
+  // over several steps): the force kernels apply the exact cutoffs themselves
+  int32_t cut_check;
   int64_t nfar;         // unordered pairs (half the entries)
   int64_t nbond, nhb;
   // upper bounds on the interaction task lists (from the bond degrees)
