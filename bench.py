@@ -198,14 +198,20 @@ def bench_qeq(ff, n, far_pairs, reps=3, tol=1e-6):
     return out
 
 
-def bench_md(ff, params, steps=100, warmup_steps=5):
-    """reaxff_step: velocity-Verlet NVE, dt 0.1 fs, lists rebuilt every step, on
-    32,480 atoms (1,120 C5H8N4O12 units in a 69.2 A periodic box, Maxwell-Boltzmann
-    velocities at 300 K); atom-steps/s over `steps` steps in one call."""
+def bench_md(ff, params, steps=100, warmup_steps=5, workload="petn_32480", skin=0.0, every=10):
+    """reaxff_step: velocity-Verlet NVE, dt 0.1 fs, on the 32,480-atom box (1,120
+    C5H8N4O12 units in a 69.2 A periodic box) or another workload, Maxwell-Boltzmann
+    velocities at 300 K; lists built every step, or with skin > 0 kept (Verlet
+    skin, rebuilt every `every` steps or when an atom moved more than skin / 2);
+    atom-steps/s over `steps` steps in one call."""
     import torch
 
     import reaxff_synth as rs
-    s = rs.workload("petn_32480")
+    from paper_1706_07772_amd import ReaxFF
+    s = rs.workload(workload)
+    ff = ReaxFF(params)
+    if skin > 0:
+        ff.set_skin(skin, every)
     v0 = rs.maxwell_boltzmann(s.type, params.atom["mass"], 300.0, seed=101)
     dev = torch.device("cuda:0")
     P = torch.tensor(s.pos, dtype=torch.float64, device=dev)
@@ -221,8 +227,12 @@ def bench_md(ff, params, steps=100, warmup_steps=5):
     dt = time.perf_counter() - t0
     e = en.cpu().numpy()
     etot = e[:, :12].sum(1) + e[:, 12]
-    return {"workload": "petn_32480: 32,480 atoms, 69.2 A periodic box, MB 300 K, dt 0.1 fs, "
-                        "lists rebuilt every step",
+    stats = ff.list_stats()
+    ff.close()
+    lists = ("lists built every step" if skin <= 0 else
+             f"Verlet-skin lists: skin {skin} A, rebuilt every {every} steps or on a move beyond skin/2")
+    return {"workload": f"{workload}: {s.n} atoms, {s.box[0]} A periodic box, MB 300 K, dt 0.1 fs, {lists}",
+            "list_builds_and_refreshes": list(stats),
             "steps": steps, "seconds": dt, "ms_per_step": 1e3 * dt / steps,
             "atom_steps_per_s": s.n * steps / dt,
             "energy_span_kcal": float(etot.max() - etot.min()),
@@ -564,8 +574,11 @@ def main():
 
     md = None
     if not args.no_md:
-        print("bench: MD steps on 32,480 atoms", file=sys.stderr, flush=True)
-        md = bench_md(ff, params)
+        print("bench: MD steps (32,480 atoms; 1,044,000 with skin lists)", file=sys.stderr, flush=True)
+        md = {"exact_lists": bench_md(ff, params),
+              "skin_lists": bench_md(ff, params, skin=0.5, every=10),
+              "skin_lists_1044000": bench_md(ff, params, steps=20, warmup_steps=2, workload="petn_1044000",
+                                             skin=0.5, every=10)}
 
     batched = None
     if not args.no_batched:
@@ -602,7 +615,7 @@ def main():
         "roofline": roofline,
         "whole_step_roofline": whole,
         "cpu_baseline": cpu,
-        "md_32480": md,
+        "md": md,
         "qeq": qeq,
         "batched": batched,
         "surrogate": surrogate,

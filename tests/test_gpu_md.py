@@ -49,6 +49,19 @@ def test_trajectory_matches_oracle(params):
     assert np.allclose(e, e_r, rtol=1e-8, atol=1e-8 * np.abs(e_r).max())
 
 
+def test_trajectory_32480_matches_oracle(params):
+    """Ten steps on the 32,480-atom box at 300 K: positions, velocities and every
+    step's energies against the oracle's velocity-Verlet run at 1e-8."""
+    s = rs.workload("petn_32480")
+    v0 = rs.maxwell_boltzmann(s.type, params.atom["mass"], 300.0, seed=101)
+    pos, vel, f, e = run_gpu(params, s, v0, 0.1, 10)
+    print("oracle MD, 32,480 atoms, 10 steps", flush=True)
+    pos_r, vel_r, e_r = Oracle(s, params).md(v0, 0.1, 10)
+    assert np.abs(pos - pos_r).max() <= 1e-8
+    assert np.abs(vel - vel_r).max() <= 1e-8 * np.abs(vel_r).max()
+    assert np.allclose(e, e_r, rtol=1e-8, atol=1e-8 * np.abs(e_r).max())
+
+
 def test_nve_32480(params):
     """100 steps of 0.1 fs on the 32,480-atom box at 300 K (lists rebuilt every step)."""
     s = rs.workload("petn_32480")

@@ -96,6 +96,26 @@ def test_full_nonbonded_small_grid(ff, params):
     _parity_path(ff, params, rs.petn_lattice(30, 20.7, seed=4), half=False)
 
 
+def test_dense_fallbacks_then_normal_density(params):
+    """Twice the benchmark density (3,132 atoms at 0.2 atoms/A^3 in a 25.0 A box,
+    5 cells per edge): the upper stencil exceeds the half evaluation's LDS copy
+    (1,024 atoms), so the build sweeps again with full rows and the nonbonded
+    term evaluates every pair from both atoms; the whole-grid stencil (all
+    3,132 atoms) exceeds that kernel's LDS copy (2,048) too, so neighbours are
+    read from memory through the chunk table.  The same context then builds
+    the 1,856-atom box, keeping full far rows (the half evaluation reads the
+    rows' upper parts through far_lo)."""
+    from paper_1706_07772_amd import ReaxFF
+    dense = rs.petn_lattice(108, 25.0, seed=12)
+    assert dense.n / 25.0 ** 3 > 0.19
+    ff = ReaxFF(params)
+    try:
+        _parity_path(ff, params, dense, half=False)
+        _parity_path(ff, params, rs.workload("petn_1856"), half=True)
+    finally:
+        ff.close()
+
+
 def test_petn_1856_parity(ff, params):
     """The 1,856-atom periodic PETN-stoichiometry box (64 units, 26.7 A)."""
     s = rs.workload("petn_1856")

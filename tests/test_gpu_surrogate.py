@@ -278,3 +278,35 @@ def test_training_gains_over_untrained(ff, params):
     print("rmse kcal/mol/A trained", trained, "untrained", untrained, "zero", zero)
     assert np.all(trained < 0.7 * zero)
     assert np.all(trained < 0.7 * untrained)
+
+
+def test_fullsize_sampled_atoms(ff):
+    """The 1,044,000-atom evaluation at sampled atoms: member forces against the
+    oracle on the atoms within 10.5 A of each (a force depends on descriptors
+    of atoms within 5 A, which see atoms within 5 A more), non-periodic."""
+    import torch
+    from _common import extract_subsystem
+    from paper_1706_07772_amd import Surrogate
+    s = rs.workload("petn_1044000")
+    probe = rs.small_periodic(30, seed=21)
+    G0 = S.descriptors(probe.pos, probe.type, probe.box)
+    shift, scale = (f32(x) for x in S.normaliser(G0))
+    th = f32(S.init_params(2, seed=9, e_per_atom=-0.5))
+    sur = Surrogate(ff, 2)
+    try:
+        sur.set_params(th, shift, scale)
+        pos, typ, q, box = dev(s)
+        out = sur.evaluate(pos, typ, box)
+        torch.cuda.synchronize()
+        F = out["forces"].cpu().numpy().astype(np.float64)
+    finally:
+        sur.close()
+    fscale = np.linalg.norm(F, axis=2).max()
+    rng = np.random.default_rng(77)
+    for c in rng.choice(s.n, size=4, replace=False):
+        sub, ci, ids = extract_subsystem(s, int(c), 10.5)
+        Gs = S.descriptors(sub.pos, sub.type, None)
+        _, F_r = _oracle_members(th, shift, scale, sub, Gs)
+        err = np.linalg.norm(F[:, c] - F_r[:, ci], axis=1).max()
+        print("sampled atom", int(c), "neighbourhood", sub.n, "err", err / fscale, flush=True)
+        assert err <= 1e-2 * fscale
