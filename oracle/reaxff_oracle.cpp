@@ -139,9 +139,7 @@ inline Var sqrt(const Var& x) { const double v = std::sqrt(x.v); return un(v, x,
 inline Var pow(const Var& x, double p) {
   return un(std::pow(x.v, p), x, p * std::pow(x.v, p - 1.0));
 }
-inline Var acos(const Var& x) {
-  return un(std::acos(x.v), x, -1.0 / std::sqrt(1.0 - x.v * x.v));
-}
+inline Var atan(const Var& x) { return un(std::atan(x.v), x, 1.0 / (1.0 + x.v * x.v)); }
 }  // namespace ad
 
 using ad::Var;
@@ -375,6 +373,18 @@ inline T sq(const T& v) { return v * v; }
 template <class T>
 inline T dot3(const T a[3], const T b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
+// The angle in [0, pi] between two vectors a, b from y = |a x b| and x = a . b:
+// twice the angle whose tangent is y / (|a||b| + x), or its supplement when
+// x < 0, so that neither a straight nor a folded angle loses digits (the
+// arccosine of the cosine does, and so does its derivative).
+template <class T>
+inline T angle_of(const T& y, const T& x) {
+  using std::atan; using std::sqrt;
+  const T r = sqrt(x * x + y * y);
+  if (re(x) >= 0.0) return 2.0 * atan(y / (r + x));
+  return PI - 2.0 * atan(y / (r - x));
+}
+
 template <class T>
 inline void cross3(const T a[3], const T b[3], T out[3]) {
   out[0] = a[1] * b[2] - a[2] * b[1];
@@ -477,7 +487,7 @@ void bond_stage(const Sys& s, const T* x, BondStage<T>& B) {
 
 template <class T, class Sink>
 void energy(const Sys& s, const T* x, BondStage<T>& B, Sink& sink) {
-  using std::exp; using std::log; using std::pow; using std::sqrt; using std::acos;
+  using std::exp; using std::log; using std::pow; using std::sqrt;
   const Params& P = s.P;
   const Cutoffs& c = s.c;
   const int n = s.n, nb = (int)s.bi.size();
@@ -539,11 +549,9 @@ void energy(const Sys& s, const T* x, BondStage<T>& B, Sink& sink) {
         T rji[3], rjk[3];
         dvec(s, x, j, i, rji);
         dvec(s, x, j, k, rjk);
-        const T lji = sqrt(dot3(rji, rji)), ljk = sqrt(dot3(rjk, rjk));
-        T cth = dot3(rji, rjk) / (lji * ljk);
-        if (re(cth) > 1.0) cth = T(1.0);
-        if (re(cth) < -1.0) cth = T(-1.0);
-        const T theta = acos(cth);
+        T cr[3];
+        cross3(rji, rjk, cr);
+        const T theta = angle_of(sqrt(dot3(cr, cr)), dot3(rji, rjk));
         const T theta0 = PI - (PI / 180.0) * P.ang[theta00][ti][tj][tk] *
                                   (1.0 - exp(-pv10 * (2.0 - B.SBO2[j])));
         const double pv3 = P.a[a_p_val3][tj], pv4 = P.ang[p_val4][ti][tj][tk];
@@ -601,12 +609,8 @@ void energy(const Sys& s, const T* x, BondStage<T>& B, Sink& sink) {
         const T cw = dot3(c1, c2) / (n1 * n2);
         const T l1 = sqrt(dot3(b1, b1)), l2 = sqrt(dot3(b2, b2)), l3 = sqrt(dot3(b3, b3));
         // angle i-j-k between r_ji = -b1 and r_jk = b2; angle j-k-l between r_kj = -b2 and r_kl = b3
-        const T c_ijk = -dot3(b1, b2) / (l1 * l2);
-        const T c_jkl = -dot3(b2, b3) / (l2 * l3);
-        T s2a = 1.0 - c_ijk * c_ijk, s2b = 1.0 - c_jkl * c_jkl;
-        if (re(s2a) < 0.0) s2a = T(0.0);
-        if (re(s2b) < 0.0) s2b = T(0.0);
-        const T sin_ijk = sqrt(s2a), sin_jkl = sqrt(s2b);
+        // their sines from the cross products (|r_ji x r_jk| = |b1 x b2|)
+        const T sin_ijk = n1 / (l1 * l2), sin_jkl = n2 / (l2 * l3);
         const T BOA_ij = B.BO[bij] - c.thb_cut, BOA_jk = B.BO[b] - c.thb_cut,
                 BOA_kl = B.BO[bkl] - c.thb_cut;
         const T f10 = (1.0 - exp(-pt2 * BOA_ij)) * (1.0 - exp(-pt2 * BOA_jk)) *

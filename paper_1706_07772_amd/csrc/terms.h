@@ -445,12 +445,13 @@ __device__ __forceinline__ AngOut angle_eval(const DevParams* __restrict__ P, co
   const double4 ru = W.bd[u], rv = W.bd[v];
   const double B1 = bo_tot(W, u) - thb, B2 = bo_tot(W, v) - thb;
   const double Si = nview(W, i).x, Sk = nview(W, k).x;
-  // angle between r_ji (= bd[u]) and r_jk (= bd[v])
+  // angle between a = r_ji (= bd[u]) and b = r_jk (= bd[v]), from |a x b| and
+  // a . b (no digits lost next to a straight angle, unlike the arccosine)
   const double il1 = 1.0 / ru.w, il2 = 1.0 / rv.w;
-  double c = (ru.x * rv.x + ru.y * rv.y + ru.z * rv.z) * il1 * il2;
-  c = c > 1.0 ? 1.0 : (c < -1.0 ? -1.0 : c);
-  const double th = acos(c);
-  const double sn = fmax(sqrt(1.0 - c * c), 1e-5);
+  const double3 av = d3(ru), bv = d3(rv);
+  const double3 cr = cross(av, bv);
+  const double ncr = sqrt(dot(cr, cr));
+  const double th = atan2(ncr, dot(av, bv));
   const double th0 = PI - ap.theta00_rad * st.th0f;
   const double dth0 = -ap.theta00_rad * st.dth0f;     // d th0 / d SBO2
   // f7
@@ -495,17 +496,22 @@ __device__ __forceinline__ AngOut angle_eval(const DevParams* __restrict__ P, co
   o.ep = Ep;
   o.ec = Ec;
   o.gS = gS;
-  // geometry: dtheta/dc = -1/sin;  dE/dc = dE/dtheta * dtheta/dc = gdt / sin
-  const double gc = gdt / sn;
-  const double ca = c * il1 * il1, cb = c * il2 * il2, ab = il1 * il2;
-  o.gu[0] = gc * (rv.x * ab - ru.x * ca);
-  o.gu[1] = gc * (rv.y * ab - ru.y * ca);
-  o.gu[2] = gc * (rv.z * ab - ru.z * ca);
+  // geometry: d theta / d a = -(c x a) / (|a|^2 |c|) and d theta / d b =
+  // -(b x c) / (|b|^2 |c|), c = a x b: the in-plane directions away from the
+  // other bond, with no sine formed from the cosine; dE/dtheta = -gdt.  (At an
+  // exactly straight angle the direction is undefined and the term is left
+  // without a geometric gradient.)
+  const double inc = ncr > 0.0 ? 1.0 / ncr : 0.0;
+  const double3 ta = cross(cr, av), tb = cross(bv, cr);
+  const double ga = gdt * inc * il1 * il1, gb = gdt * inc * il2 * il2;
+  o.gu[0] = ga * ta.x;
+  o.gu[1] = ga * ta.y;
+  o.gu[2] = ga * ta.z;
   o.gu[3] = gB1;
   o.gu[4] = gSi;
-  o.gv[0] = gc * (ru.x * ab - rv.x * cb);
-  o.gv[1] = gc * (ru.y * ab - rv.y * cb);
-  o.gv[2] = gc * (ru.z * ab - rv.z * cb);
+  o.gv[0] = gb * tb.x;
+  o.gv[1] = gb * tb.y;
+  o.gv[2] = gb * tb.z;
   o.gv[3] = gB2;
   o.gv[4] = gSk;
   return o;
@@ -549,11 +555,11 @@ __device__ __forceinline__ TorOut torsion_terms(const DevParams* __restrict__ P,
   const double4 r1v = W.bd[eji], r2v = W.bd[ejk], r3v = W.bd[ekl];
   const double3 b1 = make_double3(-r1v.x, -r1v.y, -r1v.z), b2 = d3(r2v), b3 = d3(r3v);
   const double l1 = r1v.w, l2 = r2v.w, l3 = r3v.w;
-  const double c1 = -dot(b1, b2) / (l1 * l2);   // cos of angle i-j-k
-  const double c2 = -dot(b2, b3) / (l2 * l3);   // cos of angle j-k-l
-  const double s1 = sqrt(fmax(1.0 - c1 * c1, 0.0)), s2 = sqrt(fmax(1.0 - c2 * c2, 0.0));
   const double3 m = cross(b1, b2), nv = cross(b2, b3);
   const double nm = fmax(sqrt(dot(m, m)), 1e-20), nn = fmax(sqrt(dot(nv, nv)), 1e-20);
+  // sines of the angles i-j-k and j-k-l from the cross products
+  // (|r_ji x r_jk| = |b1 x b2|, |r_kj x r_kl| = |b2 x b3|)
+  const double s1 = nm / (l1 * l2), s2 = nn / (l2 * l3);
   const double cw = dot(m, nv) / (nm * nn);
   const double ss = s1 * s2;
   const double f10 = hij * hjk * hkl;
@@ -584,17 +590,18 @@ __device__ __forceinline__ TorOut torsion_terms(const DevParams* __restrict__ P,
   const double3 dcw_b1 = cross(b2, Gm);
   const double3 dcw_b2 = add3(cross(Gm, b1), cross(b3, Gn));
   const double3 dcw_b3 = cross(Gn, b2);
-  // sin = sqrt(1 - c^2): d sin / d c = -c / sin
-  const double gc1 = s1 > 1e-10 ? gss * s2 * (-c1 / s1) : 0.0;
-  const double gc2 = s2 > 1e-10 ? gss * s1 * (-c2 / s2) : 0.0;
+  // s1 = |m| / (l1 l2) with d|m| = (b2 x mh) . db1 + (mh x b1) . db2, mh = m / |m|
+  // (likewise s2 with n = b2 x b3)
+  const double gs1 = gss * s2, gs2 = gss * s1;
   const double i12 = 1.0 / (l1 * l2), i23 = 1.0 / (l2 * l3);
-  const double3 dc1_b1 = axpy(-c1 / (l1 * l1), b1, scale(-i12, b2));
-  const double3 dc1_b2 = axpy(-c1 / (l2 * l2), b2, scale(-i12, b1));
-  const double3 dc2_b2 = axpy(-c2 / (l2 * l2), b2, scale(-i23, b3));
-  const double3 dc2_b3 = axpy(-c2 / (l3 * l3), b3, scale(-i23, b2));
-  const double3 gb1 = axpy(gc1, dc1_b1, scale(gcw, dcw_b1));
-  const double3 gb2 = axpy(gc2, dc2_b2, axpy(gc1, dc1_b2, scale(gcw, dcw_b2)));
-  const double3 gb3 = axpy(gc2, dc2_b3, scale(gcw, dcw_b3));
+  const double3 mh = scale(1.0 / nm, m), nh = scale(1.0 / nn, nv);
+  const double3 ds1_b1 = axpy(-s1 / (l1 * l1), b1, scale(i12, cross(b2, mh)));
+  const double3 ds1_b2 = axpy(-s1 / (l2 * l2), b2, scale(i12, cross(mh, b1)));
+  const double3 ds2_b2 = axpy(-s2 / (l2 * l2), b2, scale(i23, cross(b3, nh)));
+  const double3 ds2_b3 = axpy(-s2 / (l3 * l3), b3, scale(i23, cross(nh, b2)));
+  const double3 gb1 = axpy(gs1, ds1_b1, scale(gcw, dcw_b1));
+  const double3 gb2 = axpy(gs2, ds2_b2, axpy(gs1, ds1_b2, scale(gcw, dcw_b2)));
+  const double3 gb3 = axpy(gs2, ds2_b3, scale(gcw, dcw_b3));
   // entry j->i holds r_ji = -b1; j->k holds b2; k->l holds b3
   TorOut o;
   o.gji = make_double3(-gb1.x, -gb1.y, -gb1.z);

@@ -94,3 +94,16 @@ def extract_subsystem(system, center, radius):
     ids = np.nonzero(r <= radius)[0]
     sub = rs.System(pos=x[center] + d[ids], type=system.type[ids], q=system.q[ids], box=None)
     return sub, int(np.searchsorted(ids, center)), ids
+
+
+def near_straight_chain(eps):
+    """C-C-C-N-O chain: atoms 0-1-2 deviate from a straight line by the angle eps
+    (sin of angle 0-1-2 is about eps), 1-2-3-4 is an ordinary bent chain, so the
+    straight angle enters a valence angle and two torsions."""
+    r = 1.35
+    pos = np.array([[0.0, 0.0, 0.0],
+                    [r, 0.0, 0.0],
+                    [r + r * np.cos(eps), r * np.sin(eps), 0.0],
+                    [2 * r + 0.9, 1.1, 0.2],
+                    [2 * r + 1.5, 2.3, -0.6]])
+    return rs.System(pos=pos, type=np.array([0, 0, 0, 2, 3], dtype=np.int32), q=np.zeros(5), box=None)

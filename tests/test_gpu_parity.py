@@ -13,7 +13,7 @@ import reaxff_synth as rs
 from oracle import TERM_NAMES, Oracle
 
 from _common import (assert_energy_parity, assert_force_parity, assert_lists_equal, gpu_eval,
-                     to_dev)
+                     near_straight_chain, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -114,6 +114,22 @@ def test_dense_fallbacks_then_normal_density(params):
         _parity_path(ff, params, rs.workload("petn_1856"), half=True)
     finally:
         ff.close()
+
+
+@pytest.mark.parametrize("eps", [1e-2, 1e-4, 1e-6])
+def test_near_straight_angle_parity(ff, params, eps):
+    """A valence angle and two torsions whose shared angle is straight to within
+    eps: both sides take the angle from |a x b| and a . b and the torsion's
+    sines from cross products, so no clamp or band exists, and the forces agree
+    down to the conditioning of the geometry itself."""
+    _parity(ff, params, near_straight_chain(eps))
+    # the same chain inside a cluster, so the angle sits among ordinary terms
+    c = rs.cluster(120, seed=9)
+    chain = near_straight_chain(eps)
+    pos = np.concatenate([c.pos, chain.pos + np.array([40.0, 40.0, 40.0])])
+    s = rs.System(pos=pos, type=np.concatenate([c.type, chain.type]).astype(np.int32),
+                  q=np.concatenate([c.q, chain.q]), box=None)
+    _parity(ff, params, s)
 
 
 def test_petn_1856_parity(ff, params):

@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 
 import reaxff_synth as rs
+from _common import near_straight_chain  # noqa: E402
 from oracle import TERM_NAMES, Oracle
 
 T = {name: k for k, name in enumerate(TERM_NAMES)}
@@ -525,3 +526,47 @@ def test_correction_uses_val_in_f1_and_val_boc_in_f4_f5(params):
     f45 = 0.5 / (1.0 + math.exp(0.5))
     assert bt[0] == pytest.approx(b * f1 * f45, rel=1e-12)
     assert bt[1] == pytest.approx(bt[5] * f1 * f1 * f45, rel=1e-12)
+
+
+@pytest.mark.parametrize("eps", [1e-3, 1e-6])
+def test_near_straight_angle_forces_match_complex_step(params, eps):
+    """Reverse-mode forces equal the complex-step derivatives next to a straight
+    angle (the differentiation of the angle from |a x b| and a . b)."""
+    s = near_straight_chain(eps)
+    o = Oracle(s, params)
+    e, f = o.forces()
+    assert e[4] != 0.0 and e[7] != 0.0          # a valence angle and a torsion are present
+    fcs = np.zeros_like(f)
+    for a in range(s.n):
+        for k in range(3):
+            _, d = o.energy_cs(a, k)
+            fcs[a, k] = -d.sum()
+    scale = np.abs(fcs).max()
+    assert np.abs(f - fcs).max() <= 1e-10 * scale, np.abs(f - fcs).max() / scale
+
+
+def _rotation(seed):
+    q = np.random.default_rng(seed).normal(size=4)
+    a, b, c, d = q / np.linalg.norm(q)
+    return np.array([[a * a + b * b - c * c - d * d, 2 * (b * c - a * d), 2 * (b * d + a * c)],
+                     [2 * (b * c + a * d), a * a - b * b + c * c - d * d, 2 * (c * d - a * b)],
+                     [2 * (b * d - a * c), 2 * (c * d + a * b), a * a - b * b - c * c + d * d]])
+
+
+@pytest.mark.parametrize("eps", [1e-6, 1e-7, 1e-8])
+def test_near_straight_angle_forces_rotate_with_the_molecule(params, eps):
+    """Forces turn with the molecule up to the conditioning of the geometry
+    itself: an offset of eps from a straight line fixes the bend direction only
+    to about (rounding of the positions) / eps.  The angle's derivative from
+    |a x b| and a . b stays within that (errors ~1e-17/eps of the largest
+    force); the arccosine of the cosine, whose derivative divides by
+    sqrt(1 - cos^2), misses it by far near a straight angle (~1e-23/eps^2)."""
+    s = near_straight_chain(eps)
+    _, f = Oracle(s, params).forces()
+    worst = 0.0
+    for seed in range(5):
+        R = _rotation(seed)
+        sr = rs.System(pos=s.pos @ R.T + 1.0, type=s.type, q=s.q, box=None)
+        _, fr = Oracle(sr, params).forces()
+        worst = max(worst, np.abs(fr - f @ R.T).max() / np.abs(f).max())
+    assert worst <= max(5e-17 / eps, 1e-12), worst
