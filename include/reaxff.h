@@ -100,10 +100,14 @@ typedef struct reaxff_ctx reaxff_ctx;
 /* Size in bytes of reaxff_params as compiled into the library (layout check). */
 int64_t reaxff_params_size(void);
 
-/* Create a context on HIP device `device`: uploads the parameters and sets
- * the cutoffs (NULL = defaults).  *out receives the context.  Device scratch
- * (cell arrays, lists, per-bond and per-atom work arrays) is owned by the
- * context and grows inside reaxff_build_lists. */
+/* Create a context on HIP device `device` for the force field whose terms
+ * Section 2.1 names (the parameter tables of those terms) with the distance
+ * and bond-order cutoffs of the lists of Section 3.3 (NULL = defaults):
+ * uploads the parameters.  *out receives the context; REAXFF_ERR_ARG for
+ * null pointers or inconsistent cutoffs, REAXFF_ERR_HIP when the device
+ * cannot be set up.  Device scratch (cell arrays, lists, per-bond and
+ * per-atom work arrays) is owned by the context and grows inside
+ * reaxff_build_lists; reaxff_destroy releases it. */
 int reaxff_create(const reaxff_params* params, const reaxff_cutoffs* cutoffs,
                   int device, reaxff_ctx** out);
 void reaxff_destroy(reaxff_ctx* ctx);
@@ -118,10 +122,49 @@ void reaxff_destroy(reaxff_ctx* ctx);
 int reaxff_build_lists(reaxff_ctx* ctx, int64_t n, const double* pos,
                        const int32_t* type, const double* box, hipStream_t stream);
 
-/* One force evaluation over the lists of the last reaxff_build_lists call,
- * which must have been made with the same n, pos and type.  q [dev] (n)
- * charges.  forces [dev] (n,3) and energies [dev] (REAXFF_NTERMS) are
- * overwritten.  Asynchronous on `stream`. */
+/* The three lists of reaxff_build_lists in device buffers the caller owns
+ * (Section 3.3's far-neighbour, bond and H-bond lists; the library never
+ * allocates, frees or keeps them beyond the next build).  Capacities are in
+ * entries.  far_j and hb_j hold one row per atom of a width the build chooses
+ * from the density (far rows: stencil slots of the neighbours, see
+ * reaxff_export_lists for the atom pairs; H rows: acceptors of each H atom),
+ * so they need n x width entries; bond_j and bond_mir hold the directed bond
+ * entries (partner and the position of the reverse entry), bond_cap of each. */
+typedef struct reaxff_lists {
+  int64_t far_cap;    /* entries of far_j */
+  int32_t* far_j;     /* [dev] far-list rows */
+  int64_t bond_cap;   /* entries of bond_j and of bond_mir */
+  int32_t* bond_j;    /* [dev] bond partners, rows per atom in the cell-sorted order */
+  int32_t* bond_mir;  /* [dev] reverse entry of each bond entry */
+  int64_t hb_cap;     /* entries of hb_j */
+  int32_t* hb_j;      /* [dev] H-bond rows */
+  int64_t required[3];/* [host] out: entries needed (far, bond, hb) */
+} reaxff_lists;
+
+/* reaxff_build_lists into the caller's buffers.  When a buffer is too small
+ * the call returns REAXFF_ERR_CAPACITY with required[] set (a list whose size
+ * is not known yet at that point reports an estimate), leaves the context
+ * without built lists and the buffers' contents unspecified; the caller
+ * grows the buffers to at least required[] and calls again (sizes can grow
+ * once more as the rows fill).  On success required[] holds the sizes used.
+ * Lists kept over several steps (reaxff_refresh_lists) stay in the
+ * context's own storage: after this call they are built again with it. */
+int reaxff_build_lists_into(reaxff_ctx* ctx, int64_t n, const double* pos, const int32_t* type,
+                            const double* box, reaxff_lists* lists, hipStream_t stream);
+
+/* reaxff_compute_forces over lists built by reaxff_build_lists_into into
+ * exactly these buffers (else REAXFF_ERR_STATE). */
+int reaxff_compute_forces_from(reaxff_ctx* ctx, int64_t n, const double* pos, const int32_t* type,
+                               const double* q, const double* box, const reaxff_lists* lists,
+                               double* forces, double* energies, hipStream_t stream);
+
+/* One force evaluation, the problem of Algorithms 1 and 2 (input: the atom
+ * list and positions; output: the potential energy and the forces), over
+ * the lists of the last reaxff_build_lists call, which must have been made
+ * with the same n, pos and type (else REAXFF_ERR_STATE).  q [dev] (n)
+ * charges (given; QEq is reaxff_qeq).  forces [dev] (n,3) = -dE/dx and
+ * energies [dev] (REAXFF_NTERMS, the terms of Section 2.1 in the order
+ * above) are overwritten.  Asynchronous on `stream`. */
 int reaxff_compute_forces(reaxff_ctx* ctx, int64_t n, const double* pos,
                           const int32_t* type, const double* q, const double* box,
                           double* forces, double* energies, hipStream_t stream);
@@ -171,7 +214,8 @@ int reaxff_list_stats(const reaxff_ctx* ctx, int64_t stats[2]);
  * sizes[1] bond-list entries (directed), sizes[2] H-list entries. [host] */
 int reaxff_list_sizes(const reaxff_ctx* ctx, int64_t sizes[3]);
 
-/* Copy the last built lists to host memory in the caller's atom order:
+/* Copy the last built lists of Section 3.3 to host memory in the caller's
+ * atom order (for inspection and checking):
  * far[2*sizes[0]] as (i,j) pairs, bonds[2*sizes[1]] as directed (i,j),
  * hb[2*sizes[2]] as (h,z).  Order within each array is unspecified.
  * Any pointer may be NULL to skip that list.  Synchronises the device. */
@@ -433,6 +477,14 @@ int reaxff_surrogate_train_step(reaxff_surrogate* s, int64_t n, const double* po
                                 const int32_t* type, const double* box, double eref,
                                 const double* fref, double wE, double wF, double lr,
                                 double* loss, hipStream_t stream);
+/* Input normalisation of the networks: over `rows` descriptor rows G [dev]
+ * (rows, 224) FP32 (e.g. the descriptors of several frames, concatenated),
+ * shift [host] (224) = the mean of each feature and scale [host] (224) =
+ * 1 / max(standard deviation, std_floor) (population deviation, FP64 sums).
+ * Synchronises once. */
+int reaxff_surrogate_normaliser(reaxff_surrogate* s, int64_t rows, const float* G, double std_floor,
+                                float* shift, float* scale, hipStream_t stream);
+
 /* [host] (members*4*param_count) gradient of the last train_step. */
 int reaxff_surrogate_get_grad(reaxff_surrogate* s, float* grad);
 

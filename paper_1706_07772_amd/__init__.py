@@ -5,4 +5,4 @@ include/reaxff.h; this package holds its sources (csrc/), its build script
 and a thin ctypes binding.
 """
 from .binding import (BATCH_MAX_ATOMS, NDESC, NTERMS, SCHEDULES, TERM_NAMES, Batch,  # noqa: F401
-                      ReaxFF, ReaxFFError, Surrogate, load_library)
+                      ListBuffers, ReaxFF, ReaxFFError, Surrogate, load_library)

@@ -50,6 +50,32 @@ class CCutoffs(ctypes.Structure):
                                   "hb_bo_cut")]
 
 
+class CLists(ctypes.Structure):
+    """reaxff_lists: caller-owned list buffers and the sizes a build requires."""
+    _fields_ = [("far_cap", ctypes.c_int64), ("far_j", ctypes.c_void_p),
+                ("bond_cap", ctypes.c_int64), ("bond_j", ctypes.c_void_p), ("bond_mir", ctypes.c_void_p),
+                ("hb_cap", ctypes.c_int64), ("hb_j", ctypes.c_void_p),
+                ("required", ctypes.c_int64 * 3)]
+
+
+class ListBuffers:
+    """Device buffers (int32 torch tensors) for reaxff_build_lists_into."""
+
+    def __init__(self, far: int = 0, bond: int = 0, hb: int = 0, device="cuda:0"):
+        self.device = device
+        self.resize(far, bond, hb)
+
+    def resize(self, far: int, bond: int, hb: int):
+        mk = lambda k: torch.empty(max(int(k), 1), dtype=torch.int32, device=self.device)
+        self.far, self.bond, self.mir, self.hb = mk(far), mk(bond), mk(bond), mk(hb)
+        self.c = CLists(int(far), self.far.data_ptr(), int(bond), self.bond.data_ptr(), self.mir.data_ptr(),
+                        int(hb), self.hb.data_ptr())
+
+    @property
+    def required(self):
+        return tuple(int(x) for x in self.c.required)
+
+
 class QeqParams(ctypes.Structure):
     """reaxff_qeq_params: electronegativity chi and self-Coulomb J per element."""
     _fields_ = [("chi", _d * 4), ("J", _d * 4)]
@@ -87,6 +113,8 @@ def load_library():
     lib.reaxff_compute_forces.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
     lib.reaxff_step.argtypes = [vp, i64, vp, vp, vp, vp, vp, _d, i32, vp, vp, vp]
     lib.reaxff_list_sizes.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.reaxff_build_lists_into.argtypes = [vp, i64, vp, vp, vp, ctypes.POINTER(CLists), vp]
+    lib.reaxff_compute_forces_from.argtypes = [vp, i64, vp, vp, vp, vp, ctypes.POINTER(CLists), vp, vp, vp]
     lib.reaxff_set_skin.argtypes = [vp, _d, i32]
     lib.reaxff_refresh_lists.argtypes = [vp, i64, vp, vp, vp, ctypes.POINTER(i32), vp]
     lib.reaxff_list_stats.argtypes = [vp, ctypes.POINTER(i64)]
@@ -116,6 +144,7 @@ def load_library():
     lib.reaxff_surrogate_evaluate.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.reaxff_surrogate_train_step.argtypes = [vp, i64, vp, vp, vp, _d, vp, _d, _d, _d, vp, vp]
     lib.reaxff_surrogate_get_grad.argtypes = [vp, vp]
+    lib.reaxff_surrogate_normaliser.argtypes = [vp, i64, vp, _d, vp, vp, vp]
     lib.reaxff_surrogate_gated_forces.argtypes = [vp, vp, i64, vp, vp, vp, vp, _d, vp, vp, vp,
                                                   ctypes.POINTER(i64), vp]
     lib.reaxff_profile.argtypes = [vp, i32]
@@ -213,6 +242,28 @@ class ReaxFF:
         b, bp = self._boxarg(box)
         self._check(self._lib.reaxff_build_lists(self._h, pos.shape[0], _ptr(pos), _ptr(type_), bp,
                                                  _stream()))
+
+    def build_lists_into(self, pos, type_, box, bufs: "ListBuffers", check: bool = True) -> int:
+        """reaxff_build_lists_into the caller-owned buffers; returns the code (0, or
+        REAXFF_ERR_CAPACITY with bufs.required set) unless check raises on errors."""
+        b, bp = self._boxarg(box)
+        rc = self._lib.reaxff_build_lists_into(self._h, pos.shape[0], _ptr(pos), _ptr(type_), bp,
+                                               ctypes.byref(bufs.c), _stream())
+        if check and rc not in (0, -2):
+            self._check(rc)
+        return int(rc)
+
+    def compute_forces_from(self, pos, type_, q, box, bufs: "ListBuffers", forces=None, energies=None):
+        n = pos.shape[0]
+        if forces is None:
+            forces = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+        if energies is None:
+            energies = torch.empty(NTERMS, dtype=torch.float64, device=pos.device)
+        b, bp = self._boxarg(box)
+        self._check(self._lib.reaxff_compute_forces_from(self._h, n, _ptr(pos), _ptr(type_), _ptr(q), bp,
+                                                         ctypes.byref(bufs.c), _ptr(forces), _ptr(energies),
+                                                         _stream()))
+        return forces, energies
 
     def set_skin(self, skin: float, every: int = 10):
         """reaxff_set_skin: Verlet-skin lists (skin in A, kept for at most `every` refreshes)."""
@@ -506,6 +557,16 @@ class Surrogate:
         sc = np.zeros(NDESC, dtype=np.float32)
         self._check(self._lib.reaxff_surrogate_get_params(self._h, t.ctypes.data, sh.ctypes.data, sc.ctypes.data))
         return t, sh, sc
+
+    def normaliser(self, G, std_floor: float = 1e-3):
+        """reaxff_surrogate_normaliser over descriptor rows G (rows, 224) float32 cuda:
+        (shift, scale) float32 numpy arrays."""
+        assert G.dtype == torch.float32 and G.is_cuda and G.is_contiguous() and G.shape[1] == NDESC
+        shift = np.zeros(NDESC, dtype=np.float32)
+        scale = np.zeros(NDESC, dtype=np.float32)
+        self._check(self._lib.reaxff_surrogate_normaliser(self._h, G.shape[0], _ptr(G), float(std_floor),
+                                                          shift.ctypes.data, scale.ctypes.data, _stream()))
+        return shift, scale
 
     def get_grad(self):
         g = np.zeros((self.members, 4, self.npar), dtype=np.float32)

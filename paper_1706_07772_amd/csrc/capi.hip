@@ -169,16 +169,33 @@ int alloc_atoms(reaxff_ctx* c, int64_t n) {
   return 0;
 }
 
-int alloc_bonds(reaxff_ctx* c, int64_t nb) {
-  if (nb + 1 <= c->cap_bond && c->L.bond_j) return 0;
-  int64_t cap = 0, tmp;
+// per-entry work arrays for nb bond entries; the entries themselves (bond_j,
+// bond_mir) in the context's storage, or in the caller's (ext)
+int alloc_bonds(reaxff_ctx* c, int64_t nb, const reaxff_lists* ext) {
+  if (!(nb + 1 <= c->cap_bond && c->W.bd)) {
+    int64_t cap = 0, tmp;
 #define G(ptr) do { tmp = c->cap_bond; if (grow(c, ptr, tmp, nb + 1)) return REAXFF_ERR_HIP; cap = tmp; } while (0)
-  G(c->L.bond_j); G(c->L.bond_i); G(c->L.bond_mir); G(c->W.bd); G(c->W.bop); G(c->W.dbop); G(c->W.bo);
-  G(c->W.gbo); G(c->W.gvec); G(c->W.gup);
-  G(c->W.cnt_ang); G(c->W.cnt_tor); G(c->W.cnt_don); G(c->W.off_ang); G(c->W.off_tor); G(c->W.off_don);
-  G(c->W.bo1);
+    G(c->L.bond_i); G(c->W.bd); G(c->W.bop); G(c->W.dbop); G(c->W.bo);
+    G(c->W.gbo); G(c->W.gvec); G(c->W.gup);
+    G(c->W.cnt_ang); G(c->W.cnt_tor); G(c->W.cnt_don); G(c->W.off_ang); G(c->W.off_tor); G(c->W.off_don);
+    G(c->W.bo1);
 #undef G
-  c->cap_bond = cap;
+    c->cap_bond = cap;
+  }
+  if (ext) {
+    c->L.bond_j = ext->bond_j;
+    c->L.bond_mir = ext->bond_mir;
+  } else {
+    if (!(nb + 1 <= c->cap_own_bj && c->own_bj)) {
+      int64_t t = c->cap_own_bj;
+      if (grow(c, c->own_bj, t, nb + 1)) return REAXFF_ERR_HIP;
+      int64_t t2 = c->cap_own_bj;
+      if (grow(c, c->own_mir, t2, nb + 1)) return REAXFF_ERR_HIP;
+      c->cap_own_bj = t;
+    }
+    c->L.bond_j = c->own_bj;
+    c->L.bond_mir = c->own_mir;
+  }
   return 0;
 }
 
@@ -207,8 +224,13 @@ int set_task_bounds(reaxff_ctx* c, const int64_t* th) {
 // over the stored candidates, compressed rows, mirror index, task bounds) are
 // made again.  Otherwise a full build, after wrapping pos_mut into a
 // periodic box when it is given.  *rebuilt tells which happened.
+int build_lists_impl(reaxff_ctx* c, int64_t n, const double* pos, const int32_t* type, const double* box,
+                     reaxff_lists* ext, hipStream_t st);
+
 int refresh_lists(reaxff_ctx* c, int64_t n, const double* pos, double* pos_mut, const int32_t* type,
                   const double* box, int32_t* rebuilt, hipStream_t st) {
+  if (c->ext_on && c->built)
+    return fail(c, REAXFF_ERR_STATE, "lists in caller buffers are built again with reaxff_build_lists_into");
   bool full = !(c->skin > 0.0) || !c->built || n != c->L.n || n == 0 || (box != nullptr) != c->periodic ||
               c->since + 1 >= c->every;
   if (!full && box)
@@ -258,7 +280,7 @@ int refresh_lists(reaxff_ctx* c, int64_t n, const double* pos, double* pos_mut, 
     if (!full) {
       c->L.nbond = nb;
       if (set_task_bounds(c, th)) return REAXFF_ERR_HIP;
-      if (alloc_bonds(c, std::max<int64_t>(c->L.nbond, 1))) return REAXFF_ERR_HIP;
+      if (alloc_bonds(c, std::max<int64_t>(c->L.nbond, 1), nullptr)) return REAXFF_ERR_HIP;
       if (launch_compact(n, sc, c->L, c->prof, st)) return fail(c, REAXFF_ERR_HIP, "compact launch failed");
       ++c->since;
       ++c->nrefresh;
@@ -279,7 +301,7 @@ int refresh_lists(reaxff_ctx* c, int64_t n, const double* pos, double* pos_mut, 
     if (launch_wrap(n, pos_mut, g, st)) return fail(c, REAXFF_ERR_HIP, "wrap launch failed");
   }
   if (rebuilt) *rebuilt = 1;
-  return reaxff_build_lists(c, n, pos, type, box, st);
+  return build_lists_impl(c, n, pos, type, box, nullptr, st);
 }
 
 }  // namespace
@@ -355,7 +377,7 @@ void reaxff_destroy(reaxff_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   void* ptrs[] = {c->dp, c->L.perm, c->L.type_s, c->L.xs, c->L.cell_start, c->L.far_cnt,
-                  c->L.far_j, c->L.bond_off, c->L.bond_j, c->L.bond_mir, c->L.hb_cnt, c->L.hb_j,
+                  c->own_far, c->L.bond_off, c->own_bj, c->own_mir, c->L.hb_cnt, c->own_hb,
                   c->L.ha_cnt, c->L.ha_j,
                   c->W.bd, c->W.bop, c->W.dbop, c->W.bo, c->W.gbo, c->W.gvec, c->W.gup, c->W.dp,
                   c->W.ast, c->W.gS, c->W.gSig, c->W.gRso, c->W.gSBO, c->W.gStot, c->W.gDp, c->W.fnb, c->W.fhb, c->W.don_rng, c->W.nv, c->W.bo1,
@@ -390,6 +412,36 @@ void reaxff_destroy(reaxff_ctx* c) {
 int reaxff_build_lists(reaxff_ctx* c, int64_t n, const double* pos, const int32_t* type,
                        const double* box, hipStream_t st) {
   if (!c) return REAXFF_ERR_ARG;
+  return build_lists_impl(c, n, pos, type, box, nullptr, st);
+}
+
+int reaxff_build_lists_into(reaxff_ctx* c, int64_t n, const double* pos, const int32_t* type,
+                            const double* box, reaxff_lists* lists, hipStream_t st) {
+  if (!c) return REAXFF_ERR_ARG;
+  if (!lists || lists->far_cap < 0 || lists->bond_cap < 0 || lists->hb_cap < 0 ||
+      (lists->far_cap > 0 && !lists->far_j) || (lists->hb_cap > 0 && !lists->hb_j) ||
+      (lists->bond_cap > 0 && (!lists->bond_j || !lists->bond_mir)))
+    return fail(c, REAXFF_ERR_ARG, "reaxff_build_lists_into: bad list descriptor");
+  return build_lists_impl(c, n, pos, type, box, lists, st);
+}
+
+int reaxff_compute_forces_from(reaxff_ctx* c, int64_t n, const double* pos, const int32_t* type, const double* q,
+                               const double* box, const reaxff_lists* lists, double* forces, double* energies,
+                               hipStream_t st) {
+  if (!c) return REAXFF_ERR_ARG;
+  if (!lists) return fail(c, REAXFF_ERR_ARG, "null list descriptor");
+  if (!c->built || !c->ext_on || lists->far_j != c->L.far_j || lists->hb_j != c->L.hb_j ||
+      lists->bond_j != c->L.bond_j || lists->bond_mir != c->L.bond_mir)
+    return fail(c, REAXFF_ERR_STATE, "lists were not built into these buffers by the last build");
+  return reaxff_compute_forces(c, n, pos, type, q, box, forces, energies, st);
+}
+
+}  // extern "C"
+
+namespace {
+
+int build_lists_impl(reaxff_ctx* c, int64_t n, const double* pos, const int32_t* type, const double* box,
+                     reaxff_lists* ext, hipStream_t st) {
   if (n < 0 || (n > 0 && (!pos || !type))) return fail(c, REAXFF_ERR_ARG, "bad n or null pointer");
   if (n >= (int64_t)INT32_MAX / 2) return fail(c, REAXFF_ERR_ARG, "n too large for 32-bit indices");
   HIPCHK(c, hipSetDevice(c->device));
@@ -485,18 +537,34 @@ int reaxff_build_lists(reaxff_ctx* c, int64_t n, const double* pos, const int32_
   for (int attempt = 0;; ++attempt) {
     const int64_t rows = std::max<int64_t>(n, 1);
     {
-      int64_t t = c->cap_far;
-      if (grow(c, c->L.far_j, t, rows * c->L.far_w, 1.0)) return REAXFF_ERR_HIP;
-      c->cap_far = t;
+      int64_t t;
+      if (ext) {
+        // the caller's row storage must hold n rows of the current widths
+        const int64_t nf = rows * c->L.far_w, nh = rows * c->L.hb_w;
+        if (ext->far_cap < nf || ext->hb_cap < nh) {
+          ext->required[0] = nf;
+          ext->required[1] = std::max<int64_t>(ext->required[1], 8 * rows);   // bonds: estimate until swept
+          ext->required[2] = nh;
+          return fail(c, REAXFF_ERR_CAPACITY, "caller list buffers too small; required[] holds the sizes");
+        }
+        c->L.far_j = ext->far_j;
+        c->L.hb_j = ext->hb_j;
+      } else {
+        t = c->cap_far;
+        if (grow(c, c->own_far, t, rows * c->L.far_w, 1.0)) return REAXFF_ERR_HIP;
+        c->cap_far = t;
+        t = c->cap_hb;
+        if (grow(c, c->own_hb, t, rows * c->L.hb_w, 1.0)) return REAXFF_ERR_HIP;
+        c->cap_hb = t;
+        c->L.far_j = c->own_far;
+        c->L.hb_j = c->own_hb;
+      }
       t = c->sc.cap_cand;
       if (grow(c, c->sc.cand_j, t, rows * c->sc.cand_w, 1.0)) return REAXFF_ERR_HIP;
       c->sc.cap_cand = t;
       t = c->sc.cap_bondt;
       if (grow(c, c->sc.bond_t, t, rows * c->sc.bond_w, 1.0)) return REAXFF_ERR_HIP;
       c->sc.cap_bondt = t;
-      t = c->cap_hb;
-      if (grow(c, c->L.hb_j, t, rows * c->L.hb_w, 1.0)) return REAXFF_ERR_HIP;
-      c->cap_hb = t;
       t = c->cap_ha;
       if (grow(c, c->L.ha_j, t, rows * c->L.ha_w, 1.0)) return REAXFF_ERR_HIP;
       c->cap_ha = t;
@@ -559,8 +627,16 @@ int reaxff_build_lists(reaxff_ctx* c, int64_t n, const double* pos, const int32_
   }
   c->L.nbond = t32[0];
   c->L.nhb = th[4];
+  if (ext) {
+    const int64_t rows = std::max<int64_t>(n, 1);
+    ext->required[0] = rows * c->L.far_w;
+    ext->required[1] = c->L.nbond;
+    ext->required[2] = rows * c->L.hb_w;
+    if (ext->bond_cap < c->L.nbond)
+      return fail(c, REAXFF_ERR_CAPACITY, "caller bond buffers too small; required[] holds the sizes");
+  }
   if (set_task_bounds(c, th)) return REAXFF_ERR_HIP;
-  if (alloc_bonds(c, std::max<int64_t>(c->L.nbond, 1))) return REAXFF_ERR_HIP;
+  if (alloc_bonds(c, std::max<int64_t>(c->L.nbond, 1), ext)) return REAXFF_ERR_HIP;
   if (n > 0 && launch_compact(n, c->sc, c->L, c->prof, st))
     return fail(c, REAXFF_ERR_HIP, "compact launch failed");
   c->L.cut_check = c->skin > 0.0 ? 1 : 0;
@@ -571,9 +647,14 @@ int reaxff_build_lists(reaxff_ctx* c, int64_t n, const double* pos, const int32_
   }
   c->since = 0;
   ++c->nrebuild;
+  c->ext_on = ext != nullptr;
   c->built = true;
   return REAXFF_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int reaxff_compute_forces(reaxff_ctx* c, int64_t n, const double* pos, const int32_t* type,
                           const double* q, const double* box, double* forces, double* energies,

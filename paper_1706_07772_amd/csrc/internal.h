@@ -193,6 +193,11 @@ struct reaxff_ctx {
   double box[3] = {0, 0, 0};
   bool periodic = false;
   int64_t cap_n = 0, cap_cell = 0, cap_far = 0, cap_bond = 0, cap_hb = 0, cap_ha = 0, cap_part = 0;
+  // list storage the context owns; the lists (L) point here, or into the
+  // caller's buffers after reaxff_build_lists_into (ext_on)
+  int32_t *own_far = nullptr, *own_hb = nullptr, *own_bj = nullptr, *own_mir = nullptr;
+  int64_t cap_own_bj = 0;
+  bool ext_on = false;
   std::string err;
   // autotuned batch configurations, keyed by a signature of the cluster sizes
   std::map<uint64_t, reaxff_batch_config> tuned;

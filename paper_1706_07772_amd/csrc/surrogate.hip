@@ -1141,6 +1141,43 @@ __global__ void k_sur_loss(int32_t members, const double* __restrict__ E, const 
 // ---------------------------------------------------------------------------
 using namespace rx::sur;
 
+namespace rx {
+// Normalisation statistics of descriptor rows G (rows x ND, FP32): per
+// feature the mean, then the mean square deviation from it (two passes, FP64
+// sums), one thread per feature over a block of 256 rows.
+__global__ __launch_bounds__(256) void k_col_stats(int64_t rows, const float* __restrict__ G,
+                                                   const double* __restrict__ mean, double* __restrict__ acc) {
+  const int c = threadIdx.x;
+  if (c >= ND) return;
+  const int64_t r0 = (int64_t)blockIdx.x * 256, r1 = r0 + 256 < rows ? r0 + 256 : rows;
+  double v = 0.0;
+  for (int64_t r = r0; r < r1; ++r) {
+    const double x = (double)G[r * ND + c];
+    if (mean) {
+      const double d = x - mean[c];
+      v += d * d;
+    } else {
+      v += x;
+    }
+  }
+  if (v != 0.0) atomicAdd(&acc[c], v);
+}
+
+// sums -> mean (in place) or shift = mean, scale = 1 / max(std, floor)
+__global__ void k_col_final(int64_t rows, double* __restrict__ sum, const double* __restrict__ sq,
+                            double floor_, float* __restrict__ shift, float* __restrict__ scale) {
+  const int c = threadIdx.x;
+  if (c >= ND) return;
+  if (!sq) {
+    sum[c] /= (double)rows;
+    return;
+  }
+  const double sd = sqrt(sq[c] / (double)rows);
+  shift[c] = (float)sum[c];
+  scale[c] = (float)(1.0 / (sd > floor_ ? sd : floor_));
+}
+}  // namespace rx
+
 struct reaxff_surrogate {
   reaxff_ctx* nb = nullptr;      // internal context: 5 A neighbour list
   int device = 0;
@@ -1520,6 +1557,38 @@ int reaxff_surrogate_train_step(reaxff_surrogate* s, int64_t n, const double* po
     if ((rc = convert_weights(s, stream))) return rc;
   }
   return hipGetLastError() == hipSuccess ? 0 : sfail(s, REAXFF_ERR_HIP, "train_step");
+}
+
+int reaxff_surrogate_normaliser(reaxff_surrogate* s, int64_t rows, const float* G, double std_floor, float* shift,
+                                float* scale, hipStream_t stream) {
+  if (!s || rows < 1 || !G || !shift || !scale || !(std_floor > 0.0))
+    return sfail(s, REAXFF_ERR_ARG, "normaliser: bad argument");
+  SHIP(s, hipSetDevice(s->device));
+  double* acc = nullptr;
+  float* out = nullptr;
+  SHIP(s, hipMalloc(&acc, sizeof(double) * 2 * ND));
+  const hipError_t ea = hipMalloc(&out, sizeof(float) * 2 * ND);
+  if (ea != hipSuccess) {
+    (void)hipFree(acc);
+    return sfail(s, REAXFF_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(ea));
+  }
+  const unsigned blocks = nb(rows, 256);
+  hipError_t e = hipMemsetAsync(acc, 0, sizeof(double) * 2 * ND, stream);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_col_stats, dim3(blocks), dim3(256), 0, stream, rows, G, (const double*)nullptr, acc);
+    hipLaunchKernelGGL(k_col_final, dim3(1), dim3(256), 0, stream, rows, acc, (const double*)nullptr, std_floor,
+                       out, out + ND);
+    hipLaunchKernelGGL(k_col_stats, dim3(blocks), dim3(256), 0, stream, rows, G, acc, acc + ND);
+    hipLaunchKernelGGL(k_col_final, dim3(1), dim3(256), 0, stream, rows, acc, acc + ND, std_floor, out, out + ND);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(shift, out, sizeof(float) * ND, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(scale, out + ND, sizeof(float) * ND, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  (void)hipFree(acc);
+  (void)hipFree(out);
+  if (e != hipSuccess) return sfail(s, REAXFF_ERR_HIP, std::string("normaliser: ") + hipGetErrorString(e));
+  return REAXFF_OK;
 }
 
 int reaxff_surrogate_get_grad(reaxff_surrogate* s, float* grad) {

@@ -74,12 +74,10 @@ def label(ff: ReaxFF, dev_frame):
 
 
 def fit_normaliser(sur: Surrogate, dev_frames):
-    """Per-feature mean and 1/max(std, 1e-3) of the descriptors of the given frames."""
-    Gs = [sur.descriptors(pos, typ, box).double() for pos, typ, q, box in dev_frames]
-    G = torch.cat(Gs)
-    shift = G.mean(0)
-    scale = 1.0 / torch.clamp(G.std(0, unbiased=False), min=1e-3)
-    return shift.float().cpu().numpy(), scale.float().cpu().numpy()
+    """Per-feature mean and 1/max(std, 1e-3) of the descriptors of the given frames
+    (reaxff_surrogate_normaliser over their rows)."""
+    G = torch.cat([sur.descriptors(pos, typ, box) for pos, typ, q, box in dev_frames]).contiguous()
+    return sur.normaliser(G, 1e-3)
 
 
 def train(sur: Surrogate, ff: ReaxFF, source: FrameSource, steps: int, nframes: int, lr: float = 1e-3,

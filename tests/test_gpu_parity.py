@@ -278,3 +278,50 @@ def test_overlap_matches_in_order(ff, params, system):
     scale = np.abs(e0).max()
     assert np.abs(e1 - e0).max() <= 1e-12 * scale
     assert np.abs(f1 - f0).max() <= 1e-11 * np.abs(f0).max()
+
+
+@pytest.mark.parametrize("name", ["petn_1856", "cluster300"])
+def test_caller_owned_lists_capacity_protocol(params, name):
+    """reaxff_build_lists_into: undersized caller buffers give REAXFF_ERR_CAPACITY
+    with required[] and no lists; buffers grown to required[] (again if the
+    rows outgrow the first estimate) give the lists, identical to the context's
+    own, and forces through them equal the oracle's."""
+    import torch
+    from paper_1706_07772_amd import ListBuffers, ReaxFF, ReaxFFError
+    s = rs.workload("petn_1856") if name == "petn_1856" else rs.cluster(300, seed=61)
+    ff = ReaxFF(params)
+    try:
+        pos, typ, q, box = to_dev(s)
+        bufs = ListBuffers(16, 16, 16)
+        rc = ff.build_lists_into(pos, typ, box, bufs)
+        assert rc == -2 and min(bufs.required) > 16
+        with pytest.raises(ReaxFFError) as ei:          # nothing was built
+            ff.compute_forces(pos, typ, q, box)
+        assert ei.value.code == -6
+        tries = 1
+        while rc == -2:
+            bufs.resize(*bufs.required)
+            rc = ff.build_lists_into(pos, typ, box, bufs)
+            tries += 1
+            assert tries <= 4
+        assert rc == 0
+        far, bonds, hb = ff.export_lists()
+        f, e = ff.compute_forces_from(pos, typ, q, box, bufs)
+        torch.cuda.synchronize()
+        assert bufs.required[1] == len(bonds)
+        o = Oracle(s, params)
+        assert_lists_equal((far, bonds, hb), o, o.lists())
+        e_ref, e_abs = o.energy_abs()
+        _, f_ref = o.forces()
+        assert_energy_parity(e.cpu().numpy(), e_ref, e_abs, names=TERM_NAMES)
+        assert_force_parity(f.cpu().numpy(), f_ref)
+        # the context's own lists: the same sets; the caller's buffers no longer match
+        ff.build_lists(pos, typ, box)
+        far2, bonds2, hb2 = ff.export_lists()
+        assert sorted(map(tuple, far.tolist())) == sorted(map(tuple, far2.tolist()))
+        assert sorted(map(tuple, bonds.tolist())) == sorted(map(tuple, bonds2.tolist()))
+        with pytest.raises(ReaxFFError) as ei:
+            ff.compute_forces_from(pos, typ, q, box, bufs)
+        assert ei.value.code == -6
+    finally:
+        ff.close()

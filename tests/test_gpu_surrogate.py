@@ -310,3 +310,16 @@ def test_fullsize_sampled_atoms(ff):
         err = np.linalg.norm(F[:, c] - F_r[:, ci], axis=1).max()
         print("sampled atom", int(c), "neighbourhood", sub.n, "err", err / fscale, flush=True)
         assert err <= 1e-2 * fscale
+
+
+def test_normaliser_matches_definition(sur4):
+    """reaxff_surrogate_normaliser against the mean and population deviation of
+    the same rows in FP64 (the oracle's normaliser)."""
+    import torch
+    frames = [rs.small_periodic(30, seed=21), rs.cluster(150, seed=31)]
+    Gs = [sur4.descriptors(*dev(f)[:2], dev(f)[3]) for f in frames]
+    G = torch.cat(Gs).contiguous()
+    shift, scale = sur4.normaliser(G, 1e-3)
+    ref_shift, ref_scale = S.normaliser(G.cpu().numpy().astype(np.float64))
+    np.testing.assert_allclose(shift, ref_shift, rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(scale, ref_scale, rtol=1e-6)
