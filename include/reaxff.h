@@ -286,6 +286,30 @@ int reaxff_qeq(reaxff_ctx* ctx, int64_t n, const reaxff_qeq_params* qp, double t
                int32_t maxit, int32_t guess, double* q, double* s_out, double* t_out,
                int32_t* iters, double* resid, hipStream_t stream);
 
+/* ---- Exact forces on a subset of the atoms ---------------------------------
+ *
+ * The force on an atom collects the terms whose inputs include its position
+ * (Section 2.1's terms): pair terms reach r_nonb; a bonded term reads
+ * positions up to three bond hops from its centre (corrected bond orders read
+ * the orders of their atoms' bonds; over/under-coordination and coalition
+ * read neighbours' total orders), so it moves atoms within three hops and
+ * reads atoms within six hops of them; a hydrogen bond reads its donor
+ * bond's order (two hops from H) and acceptors within r_hb of H.  Every input
+ * of every term that moves atom f thus lies within
+ *   R = max(r_nonb, 6 b, r_hb + 2 b)
+ * of f, b being the largest distance at which an uncorrected bond order
+ * reaches bo_cut (reaxff_dependency_radius returns R).  reaxff_forces_masked
+ * evaluates the atoms within R of the atoms with mask [dev] (n) != 0 (a
+ * superset from a grid of cells at least R/3 wide) as one system in the same
+ * box and writes their exact forces into forces [dev] (n,3) at the masked
+ * atoms only; other rows are left as they were.  *nsub [host] (may be NULL)
+ * the atoms evaluated.  The context's lists are those of the subsystem
+ * afterwards.  Synchronises two to three times. */
+double reaxff_dependency_radius(const reaxff_ctx* ctx);
+int reaxff_forces_masked(reaxff_ctx* ctx, int64_t n, const double* pos, const int32_t* type,
+                         const double* q, const double* box, const uint8_t* mask, double* forces,
+                         int64_t* nsub, hipStream_t stream);
+
 /* ---- In-situ molecular species analysis (Section 3.4) ---------------------
  *
  * Over the corrected bond orders of the last reaxff_compute_forces: two atoms
@@ -489,16 +513,18 @@ int reaxff_surrogate_normaliser(reaxff_surrogate* s, int64_t rows, const float* 
 int reaxff_surrogate_get_grad(reaxff_surrogate* s, float* grad);
 
 /* Gated forces: the ensemble mean force, except on atoms whose spread
- * exceeds `threshold` (kcal/(mol A)), which take the plain FP64 ReaxFF force
- * computed by `plain` (a context of this library, charges q [dev]).  The
- * plain evaluation runs only when some atom is flagged.  forces [dev] (n,3)
- * FP64, mask [dev] (n) 1 = fallback, energies [dev] (members) surrogate
- * totals, *nflagged [host] number of flagged atoms.  Synchronises once. */
+ * exceeds `threshold` (kcal/(mol A)), which take the exact plain FP64 ReaxFF
+ * force computed by `plain` (a context of this library, charges q [dev])
+ * through reaxff_forces_masked, so the fallback costs what the flagged atoms'
+ * neighbourhoods cost.  forces [dev] (n,3) FP64, mask [dev] (n) 1 = fallback,
+ * energies [dev] (members) surrogate totals, *nflagged [host] number of
+ * flagged atoms, *nsub [host] (may be NULL) atoms of the plain evaluation
+ * (0 when none is flagged).  Synchronises two to three times. */
 int reaxff_surrogate_gated_forces(reaxff_surrogate* s, reaxff_ctx* plain, int64_t n,
                                   const double* pos, const int32_t* type, const double* q,
                                   const double* box, double threshold, double* forces,
                                   uint8_t* mask, double* energies, int64_t* nflagged,
-                                  hipStream_t stream);
+                                  int64_t* nsub, hipStream_t stream);
 
 const char* reaxff_strerror(int code);
 const char* reaxff_last_error(const reaxff_ctx* ctx);

@@ -146,7 +146,10 @@ def load_library():
     lib.reaxff_surrogate_get_grad.argtypes = [vp, vp]
     lib.reaxff_surrogate_normaliser.argtypes = [vp, i64, vp, _d, vp, vp, vp]
     lib.reaxff_surrogate_gated_forces.argtypes = [vp, vp, i64, vp, vp, vp, vp, _d, vp, vp, vp,
-                                                  ctypes.POINTER(i64), vp]
+                                                  ctypes.POINTER(i64), ctypes.POINTER(i64), vp]
+    lib.reaxff_dependency_radius.restype = _d
+    lib.reaxff_dependency_radius.argtypes = [vp]
+    lib.reaxff_forces_masked.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, ctypes.POINTER(i64), vp]
     lib.reaxff_profile.argtypes = [vp, i32]
     lib.reaxff_set_overlap.argtypes = [vp, i32]
     lib.reaxff_profile_read.argtypes = [vp, i32, vp, vp, vp]
@@ -369,6 +372,21 @@ class ReaxFF:
         self._check(self._lib.reaxff_species(self._h, float(bo_threshold), _ptr(mol), _ptr(counts), _ptr(table),
                                              ctypes.byref(nm), ctypes.byref(ns), _stream()))
         return mol, counts[:nm.value], table[:ns.value]
+
+    def dependency_radius(self) -> float:
+        """reaxff_dependency_radius: the distance within which every input of every
+        term that moves an atom lies."""
+        return float(self._lib.reaxff_dependency_radius(self._h))
+
+    def forces_masked(self, pos, type_, q, box, mask, forces):
+        """reaxff_forces_masked: exact forces written into `forces` at the rows where
+        mask (n,) uint8 cuda is nonzero; returns the subsystem's atom count."""
+        assert mask.dtype == torch.uint8 and mask.is_cuda and mask.is_contiguous()
+        ns = ctypes.c_int64(0)
+        b, bp = self._boxarg(box)
+        self._check(self._lib.reaxff_forces_masked(self._h, pos.shape[0], _ptr(pos), _ptr(type_), _ptr(q), bp,
+                                                   _ptr(mask), _ptr(forces), ctypes.byref(ns), _stream()))
+        return int(ns.value)
 
     def compute_forces_batched(self, sys_off, max_atoms: int, pos, type_, q, forces=None, energies=None,
                                status=None):
@@ -621,8 +639,10 @@ class Surrogate:
         mask = torch.empty(n, dtype=torch.uint8, device=d)
         energies = torch.empty(self.members, dtype=torch.float64, device=d)
         nf = ctypes.c_int64(0)
+        ns = ctypes.c_int64(0)
         b, bp = self._boxarg(box)
         self._check(self._lib.reaxff_surrogate_gated_forces(
             self._h, plain._h, n, _ptr(pos), _ptr(type_), _ptr(q), bp, float(threshold), _ptr(forces),
-            _ptr(mask), _ptr(energies), ctypes.byref(nf), _stream()))
+            _ptr(mask), _ptr(energies), ctypes.byref(nf), ctypes.byref(ns), _stream()))
+        self.last_nsub = int(ns.value)
         return forces, mask, energies, int(nf.value)

@@ -398,6 +398,11 @@ void reaxff_destroy(reaxff_ctx* c) {
     for (void* p : qp)
       if (p) (void)hipFree(p);
     if (Q.red_host) (void)hipHostFree(Q.red_host);
+    rx::Masked& Mk = c->masked;
+    void* mp[] = {Mk.cid, Mk.sel, Mk.idx, Mk.stype, Mk.flag, Mk.mark, Mk.mark2, Mk.spos, Mk.sq, Mk.sforce,
+                  Mk.senergy, Mk.part};
+    for (void* p : mp)
+      if (p) (void)hipFree(p);
     rx::Species& S = c->species;
     void* sp[] = {S.parent, S.flag, S.rank, S.counts, S.order, S.order2, S.sid, S.key, S.key2, S.tmp};
     for (void* p : sp)

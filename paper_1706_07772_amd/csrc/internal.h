@@ -123,6 +123,17 @@ struct Species {
   int64_t cap = 0;
 };
 
+// work arrays of reaxff_forces_masked (device): cell of each atom, cell marks
+// (two, for the dilation passes), selection flags and their prefix sums, the
+// gathered subsystem and its forces and energies
+struct Masked {
+  int32_t *cid = nullptr, *sel = nullptr, *idx = nullptr, *stype = nullptr, *flag = nullptr;
+  uint8_t *mark = nullptr, *mark2 = nullptr;
+  double *spos = nullptr, *sq = nullptr, *sforce = nullptr, *senergy = nullptr, *part = nullptr;
+  int64_t cap_cid = 0, cap_sel = 0, cap_idx = 0, cap_stype = 0, cap_flag = 0, cap_mark = 0, cap_mark2 = 0;
+  int64_t cap_spos = 0, cap_sq = 0, cap_sforce = 0, cap_part = 0;
+};
+
 // exclusive prefix sums; out[n-1] holds the total when in[n-1] == 0
 int scan_i32(const int32_t* in, int32_t* out, int64_t n, Scratch& sc, hipStream_t st);
 int scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, Scratch& sc, hipStream_t st);
@@ -171,6 +182,7 @@ struct reaxff_ctx {
   rx::Prof prof;
   rx::Qeq qeq;
   rx::Species species;
+  rx::Masked masked;
   // the nonbonded term runs on a stream of its own, concurrent with the
   // bonded terms, between a fork and a join event on the caller's stream
   hipStream_t side = nullptr;

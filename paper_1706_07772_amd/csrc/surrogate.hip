@@ -1602,7 +1602,7 @@ int reaxff_surrogate_get_grad(reaxff_surrogate* s, float* grad) {
 int reaxff_surrogate_gated_forces(reaxff_surrogate* s, reaxff_ctx* plain, int64_t n, const double* pos,
                                   const int32_t* type, const double* q, const double* box, double threshold,
                                   double* forces, uint8_t* mask, double* energies, int64_t* nflagged,
-                                  hipStream_t stream) {
+                                  int64_t* nsub, hipStream_t stream) {
   if (!s || !plain || n < 0 || (n > 0 && (!pos || !type || !q || !forces || !mask)) || !energies)
     return sfail(s, REAXFF_ERR_ARG, "gated_forces: bad argument");
   SHIP(s, hipSetDevice(s->device));
@@ -1619,13 +1619,12 @@ int reaxff_surrogate_gated_forces(reaxff_surrogate* s, reaxff_ctx* plain, int64_
   SHIP(s, hipStreamSynchronize(stream));
   const int64_t nf = (int64_t)*s->nflag_host;
   if (nflagged) *nflagged = nf;
+  if (nsub) *nsub = 0;
   if (nf > 0) {
-    // fallback: the plain FP64 evaluation, taken for the flagged atoms
-    if ((rc = reaxff_build_lists(plain, n, pos, type, box, stream)))
-      return sfail(s, rc, std::string("fallback lists: ") + reaxff_last_error(plain));
-    if ((rc = reaxff_compute_forces(plain, n, pos, type, q, box, s->Freax, s->Ereax, stream)))
+    // fallback: exact plain FP64 forces on the flagged atoms, from the plain
+    // evaluation of the atoms their forces depend on (reaxff_forces_masked)
+    if ((rc = reaxff_forces_masked(plain, n, pos, type, q, box, mask, forces, nsub, stream)))
       return sfail(s, rc, std::string("fallback forces: ") + reaxff_last_error(plain));
-    hipLaunchKernelGGL(k_sur_merge, dim3(nb(n, 256)), dim3(256), 0, stream, n, mask, s->Freax, forces);
   }
   return hipGetLastError() == hipSuccess ? 0 : sfail(s, REAXFF_ERR_HIP, "gated_forces");
 }

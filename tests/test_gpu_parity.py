@@ -325,3 +325,52 @@ def test_caller_owned_lists_capacity_protocol(params, name):
         assert ei.value.code == -6
     finally:
         ff.close()
+
+
+@pytest.mark.parametrize("kind", ["clustered", "sparse", "open_cluster"])
+def test_masked_forces_exact_on_marked_atoms(params, kind):
+    """reaxff_forces_masked: the forces of the marked atoms from the plain
+    evaluation of the atoms within the dependency radius of them equal those of
+    the whole system (1e-9), while the evaluated subsystem stays smaller than
+    the system when the marked atoms are few or clustered."""
+    import torch
+    from paper_1706_07772_amd import ReaxFF
+    if kind == "open_cluster":
+        s = rs.cluster(20000, seed=71)   # about 59 A across
+    else:
+        s = rs.workload("petn_32480")
+    ff = ReaxFF(params)
+    try:
+        pos, typ, q, box = to_dev(s)
+        ff.build_lists(pos, typ, box)
+        f_all, _ = ff.compute_forces(pos, typ, q, box)
+        f_all = f_all.cpu().numpy()
+        R = ff.dependency_radius()
+        rng = np.random.default_rng(3)
+        if kind == "sparse":
+            mask = np.zeros(s.n, dtype=np.uint8)
+            mask[rng.choice(s.n, size=3, replace=False)] = 1
+        else:
+            c = s.pos[rng.integers(s.n)]
+            d = s.pos - c
+            if s.box is not None:
+                d -= s.box * np.rint(d / s.box)
+            mask = (np.sqrt((d * d).sum(1)) <= 5.0).astype(np.uint8)
+        out = torch.full((s.n, 3), 7.0, dtype=torch.float64, device="cuda:0")
+        nsub = ff.forces_masked(pos, typ, q, box, torch.tensor(mask, device="cuda:0"), out)
+        torch.cuda.synchronize()
+        out = out.cpu().numpy()
+        m = mask.astype(bool)
+        print(kind, "marked", int(m.sum()), "subsystem", nsub, "of", s.n, "R", R, flush=True)
+        assert 0 < m.sum() <= nsub < s.n
+        assert np.all(out[~m] == 7.0)                    # unmarked rows untouched
+        scale = np.linalg.norm(f_all, axis=1).max()
+        err = np.linalg.norm(out[m] - f_all[m], axis=1).max()
+        assert err <= 1e-9 * scale, err / scale
+        # every atom marked: the whole system
+        allm = torch.ones(s.n, dtype=torch.uint8, device="cuda:0")
+        out2 = torch.zeros((s.n, 3), dtype=torch.float64, device="cuda:0")
+        assert ff.forces_masked(pos, typ, q, box, allm, out2) == s.n
+        assert np.abs(out2.cpu().numpy() - f_all).max() <= 1e-12 * scale
+    finally:
+        ff.close()

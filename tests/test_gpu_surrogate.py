@@ -218,7 +218,7 @@ def test_gate_and_fallback(ff, sur4, params):
     fsc = np.abs(f_plain).max()
     F, mask, E, nf = sur4.gated_forces(ff, pos, typ, q, box, threshold=-1.0)
     torch.cuda.synchronize()
-    assert nf == s.n and mask.cpu().numpy().all()
+    assert nf == s.n and mask.cpu().numpy().all() and sur4.last_nsub == s.n
     np.testing.assert_allclose(F.cpu().numpy(), f_plain, rtol=0, atol=1e-12 * fsc)
     # none flagged: the ensemble mean (FP32 atomic sums: equal to rounding)
     F, mask, E, nf = sur4.gated_forces(ff, pos, typ, q, box, threshold=1e30)
