@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 # MI355X published peaks
 PEAK_FP64_VALU_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_MFMA_TFLOPS = 2500.0
 
 # Algorithmic work per unit, in FP64 operation equivalents (add/mul = 1,
 # fma = 2, exp 20, log 25, pow 60, div/sqrt 10, acos 40): fixed per-unit
@@ -144,15 +145,16 @@ def whole_step_work(counts, n):
     return sum(per.values()), per
 
 
-def read_profile(ff, lib):
+def read_profile(handle, lib):
+    """Per-kernel event times accumulated by a context's profiler (reaxff_profile_read)."""
     import ctypes
-    K = 40
+    K = 64
     ms = (ctypes.c_double * K)()
     calls = (ctypes.c_int64 * K)()
     names = (ctypes.c_char_p * K)()
     lib.reaxff_profile_read.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p]
-    k = lib.reaxff_profile_read(ff._h, K, ms, calls, names)
+    k = lib.reaxff_profile_read(handle, K, ms, calls, names)
     return {names[i].decode(): {"ms_total": ms[i], "launches": int(calls[i]), "ms_avg": ms[i] / calls[i]}
             for i in range(k) if calls[i]}
 
@@ -181,7 +183,7 @@ def bench_qeq(ff, n, far_pairs, reps=3, tol=1e-6):
     for _ in range(reps):
         ff.qeq(n, qp, tol=tol, guess=False, q=q)
     torch.cuda.synchronize()
-    kern = read_profile(ff, lib)
+    kern = read_profile(ff._h, lib)
     lib.reaxff_profile(ff._h, 0)
     nnz = 2 * far_pairs
     spmv = kern.get("qeq_spmv", {})
@@ -340,12 +342,17 @@ def bench_batched(ff, steps: int, warmup: int):
     }
 
 
-def bench_surrogate(ff, params, steps: int, warmup: int, train_steps: int = 200, nframes: int = 32):
+def bench_surrogate(ff, params, steps: int, warmup: int, nframes: int = 20000):
     """Learned surrogate: an ensemble of 4 networks trained here by the library's own
-    kernels on frames of 1,856 atoms (the workload recipe at 300-3000 K, labelled by the
-    plain GPU path); force errors on 3 held-out frames against the CPU oracle; throughput
-    at 1,044,000 atoms of the ensemble alone and of the gated evaluation (plain FP64
-    fallback where the members disagree by more than 0.1 eV/A)."""
+    kernels, one Adam step per fresh frame, on `nframes` streamed frames of 1,856 atoms
+    (the workload recipe -- stoichiometry, density, jittered lattice -- at 300-3000 K,
+    each labelled by the plain GPU path as it arrives); force errors on 3 held-out frames
+    against the CPU oracle; throughput at 1,044,000 atoms of the ensemble alone and of
+    the gated evaluation (exact plain FP64 forces, through the masked evaluation, where
+    the members disagree by more than 0.1 eV/A); the network kernel's share of the
+    BF16 matrix-core peak."""
+    import ctypes
+
     import numpy as np
     import torch
 
@@ -353,10 +360,12 @@ def bench_surrogate(ff, params, steps: int, warmup: int, train_steps: int = 200,
     from oracle import Oracle
     from paper_1706_07772_amd import Surrogate
     from paper_1706_07772_amd import training as T
+    from paper_1706_07772_amd.binding import load_library
 
     sur = Surrogate(ff, 4)
-    info = T.train(sur, ff, T.FrameSource(64, seed=1000), steps=train_steps, nframes=nframes, lr=2e-3)
-    print(f"bench: surrogate trained {train_steps} steps on {nframes} frames in {info['train_s']:.2f} s",
+    info = T.train_streamed(sur, ff, T.FrameSource(64, seed=1000), nframes=nframes, lr=2e-3,
+                            log=lambda m: print("bench: " + m, file=sys.stderr, flush=True))
+    print(f"bench: surrogate trained on {nframes} streamed frames in {info['seconds']:.1f} s",
           file=sys.stderr, flush=True)
     held = T.FrameSource(64, seed=99)
     errs = []
@@ -396,17 +405,41 @@ def bench_surrogate(ff, params, steps: int, warmup: int, train_steps: int = 200,
         _, _, _, nfl = sur.gated_forces(ff, pos, typ, q, box, thr)
     torch.cuda.synchronize()
     ms_gated = 1e3 * (time.perf_counter() - t0) / gsteps
+    nsub = sur.last_nsub
+    # per-kernel times of one evaluation (events on the launch stream), and the
+    # network kernel against the BF16 matrix-core peak: per atom and member the
+    # forward products (224x128, 128x128, 128) and their transposes for dE/dx
+    lib = load_library()
+    sctx = lib.reaxff_surrogate_context(sur._h)
+    lib.reaxff_profile(sctx, 1)
+    for _ in range(steps):
+        sur.evaluate(pos, typ, box)
+    torch.cuda.synchronize()
+    kern = read_profile(ctypes.c_void_p(sctx), lib)
+    lib.reaxff_profile(sctx, 0)
+    net_flops_atom = 2 * 2 * (224 * 128 + 128 * 128 + 128)
+    net = kern.get("sur_net", {})
+    mfma = None
+    if net:
+        fl = net_flops_atom * n * sur.members
+        ach = fl / (net["ms_avg"] * 1e-3) / 1e12
+        mfma = {"bound": "mfma", "achieved": ach, "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / PEAK_BF16_MFMA_TFLOPS, "flops_per_atom_member": net_flops_atom,
+                "avg_ms": net["ms_avg"]}
     sur.close()
     return {
         "ensemble": "4 members, 224 -> 128 -> 128 -> 1 SiLU per element, BF16 MFMA, FP32 accumulation",
-        "training": {"frames": nframes, "atoms_per_frame": info["atoms_per_frame"], "steps": train_steps,
-                     "seconds": info["train_s"], "ms_per_step": info["ms_per_step"],
+        "training": {"frames_streamed": nframes, "atoms_per_frame": info["atoms_per_frame"],
+                     "atom_environments": nframes * info["atoms_per_frame"],
+                     "seconds": info["seconds"], "ms_per_frame": info["ms_per_frame"],
                      "final_loss": info["losses"][-1][1]},
         "heldout_vs_oracle": errs,
         "atoms": n,
         "ensemble_ms_per_step": ms_sur, "ensemble_atom_steps_per_s": n / (ms_sur * 1e-3),
         "gated_ms_per_step": ms_gated, "gated_atom_steps_per_s": n / (ms_gated * 1e-3),
-        "gated_fallback_fraction": nfl / n, "threshold_ev_per_A": 0.1,
+        "gated_fallback_fraction": nfl / n, "gated_plain_subsystem_atoms": nsub, "threshold_ev_per_A": 0.1,
+        "kernels_ms_avg": {k: round(v["ms_avg"], 4) for k, v in kern.items()},
+        "network_mfma_roofline": mfma,
     }
 
 
@@ -509,7 +542,7 @@ def main():
         kernel_pass_ms = 1e3 * (time.perf_counter() - tk0) / args.steps
         ff.set_overlap(not args.no_overlap)
         print(f"bench: kernel pass {kernel_pass_ms:.3f} ms/step (terms in order)", file=sys.stderr, flush=True)
-        K = 32
+        K = 64
         ms = (ctypes.c_double * K)()
         calls = (ctypes.c_int64 * K)()
         names = (ctypes.c_char_p * K)()

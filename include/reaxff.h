@@ -509,6 +509,10 @@ int reaxff_surrogate_train_step(reaxff_surrogate* s, int64_t n, const double* po
 int reaxff_surrogate_normaliser(reaxff_surrogate* s, int64_t rows, const float* G, double std_floor,
                                 float* shift, float* scale, hipStream_t stream);
 
+/* The surrogate's own context (its 5 A neighbour lists), for reaxff_profile
+ * and reaxff_profile_read over the surrogate's kernels; owned by s. */
+reaxff_ctx* reaxff_surrogate_context(reaxff_surrogate* s);
+
 /* [host] (members*4*param_count) gradient of the last train_step. */
 int reaxff_surrogate_get_grad(reaxff_surrogate* s, float* grad);
 

@@ -145,6 +145,8 @@ def load_library():
     lib.reaxff_surrogate_train_step.argtypes = [vp, i64, vp, vp, vp, _d, vp, _d, _d, _d, vp, vp]
     lib.reaxff_surrogate_get_grad.argtypes = [vp, vp]
     lib.reaxff_surrogate_normaliser.argtypes = [vp, i64, vp, _d, vp, vp, vp]
+    lib.reaxff_surrogate_context.restype = vp
+    lib.reaxff_surrogate_context.argtypes = [vp]
     lib.reaxff_surrogate_gated_forces.argtypes = [vp, vp, i64, vp, vp, vp, vp, _d, vp, vp, vp,
                                                   ctypes.POINTER(i64), ctypes.POINTER(i64), vp]
     lib.reaxff_dependency_radius.restype = _d

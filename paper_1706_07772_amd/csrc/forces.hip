@@ -1132,7 +1132,8 @@ const char* const kKernelNames[KID_COUNT] = {
     "bbox", "cell_hist", "cell_scatter", "cell_sort", "gather_sorted", "list_sweep", "scan",
     "bondtest", "compact", "mirror", "zero", "gather_q", "bo_prime", "delta_prime", "bo_corr", "atom_state",
     "atom_energy", "tasks", "angles", "torsions", "hbonds", "hb_acceptors", "nonbonded", "back_s", "back_corr",
-    "back_dp", "forces", "batch", "nb_reduce", "nb_energy", "energy_fold", "qeq_rows", "qeq_spmv", "qeq_vec"};
+    "back_dp", "forces", "batch", "nb_reduce", "nb_energy", "energy_fold", "qeq_rows", "qeq_spmv", "qeq_vec", "sur_desc", "sur_net", "sur_pairw",
+    "sur_gather", "sur_mirror"};
 
 int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, const double* q,
                   hipStream_t side, hipEvent_t ev_fork, hipEvent_t ev_join, double* forces,

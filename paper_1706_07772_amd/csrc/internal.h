@@ -15,7 +15,8 @@ enum KernelId {
   KID_BONDTEST, KID_COMPACT, KID_MIRROR, KID_ZERO, KID_GATHER_Q, KID_BO_PRIME, KID_DELTA_PRIME, KID_BO_CORR,
   KID_ATOM_STATE, KID_ATOM_ENERGY, KID_TASKS, KID_ANGLES, KID_TORSIONS, KID_HBONDS, KID_HB_ACC, KID_NONBONDED,
   KID_BACK_S, KID_BACK_CORR, KID_BACK_DP, KID_FORCES, KID_BATCH, KID_NB_REDUCE, KID_NB_ENERGY, KID_ENERGY_FOLD,
-  KID_QEQ_ROWS, KID_QEQ_SPMV, KID_QEQ_VEC, KID_COUNT
+  KID_QEQ_ROWS, KID_QEQ_SPMV, KID_QEQ_VEC, KID_SUR_DESC, KID_SUR_NET, KID_SUR_PAIRW, KID_SUR_GATHER,
+  KID_SUR_MIRROR, KID_COUNT
 };
 extern const char* const kKernelNames[KID_COUNT];
 

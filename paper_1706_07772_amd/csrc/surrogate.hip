@@ -1280,8 +1280,10 @@ int prepare(reaxff_surrogate* s, int64_t n, const double* pos, const int32_t* ty
   if (s->sorted_rows) {
     hipLaunchKernelGGL(k_far_sort, dim3(nb(n, 4)), dim3(256), 0, st, n, L.far_cnt, L.far_j, L.far_w, L.type_s,
                        s->seg);
+    s->nb->prof.begin(KID_SUR_MIRROR, st);
     hipLaunchKernelGGL(k_far_mirror, dim3(nb(n, 4)), dim3(256), 0, st, n, L.far_cnt, L.far_j, L.far_w, L.type_s,
                        s->seg, s->mir);
+    s->nb->prof.end(st);
   } else {
     hipLaunchKernelGGL(k_far_mirror_scan, dim3(nb(n, 4)), dim3(256), 0, st, n, L.far_cnt, L.far_j, L.far_w,
                        s->mir);
@@ -1331,7 +1333,9 @@ int evaluate_frame(reaxff_surrogate* s, hipStream_t st) {
   {
     DescArgs da = desc_args(s, nullptr, s->xq, nullptr);
     da.mom = s->mom;
+    s->nb->prof.begin(KID_SUR_DESC, st);
     hipLaunchKernelGGL(k_desc<false>, dim3(nb(n, 32)), dim3(128), 0, st, da);
+    s->nb->prof.end(st);
   }
   NetArgs na{};
   na.theta = s->theta;
@@ -1346,7 +1350,9 @@ int evaluate_frame(reaxff_surrogate* s, hipStream_t st) {
   na.rows = rows;
   na.Erow = s->Erow;
   na.gG = s->gG;
+  s->nb->prof.begin(KID_SUR_NET, st);
   hipLaunchKernelGGL(k_net_infer, dim3((unsigned)(rows / TILE), M), dim3(256), 0, st, na);
+  s->nb->prof.end(st);
   hipLaunchKernelGGL(k_sur_energy, dim3(std::min<int64_t>(std::max<int64_t>(nb(rows, 256), 1), 128)), dim3(256), 0,
                      st, rows, M, s->R.rowatom, s->Erow, s->Etot);
   const rx::Lists& L = s->nb->L;
@@ -1366,9 +1372,13 @@ int evaluate_frame(reaxff_surrogate* s, hipStream_t st) {
   fa.mir = s->mir;
   fa.w = s->w;
   fa.Fown = s->Fown;
+  s->nb->prof.begin(KID_SUR_PAIRW, st);
   hipLaunchKernelGGL(k_sur_pairw, dim3(nb(n, 4)), dim3(256), 0, st, fa);
+  s->nb->prof.end(st);
+  s->nb->prof.begin(KID_SUR_GATHER, st);
   hipLaunchKernelGGL(k_sur_gather, dim3(nb(n, 4)), dim3(256), 0, st, n, M, s->cap_slots, L.far_cnt, L.far_j,
                      L.far_w, s->mir, s->w, s->Fown, s->F);
+  s->nb->prof.end(st);
   return hipGetLastError() == hipSuccess ? 0 : sfail(s, REAXFF_ERR_HIP, "surrogate kernels");
 }
 
@@ -1558,6 +1568,8 @@ int reaxff_surrogate_train_step(reaxff_surrogate* s, int64_t n, const double* po
   }
   return hipGetLastError() == hipSuccess ? 0 : sfail(s, REAXFF_ERR_HIP, "train_step");
 }
+
+reaxff_ctx* reaxff_surrogate_context(reaxff_surrogate* s) { return s ? s->nb : nullptr; }
 
 int reaxff_surrogate_normaliser(reaxff_surrogate* s, int64_t rows, const float* G, double std_floor, float* shift,
                                 float* scale, hipStream_t stream) {

@@ -115,6 +115,48 @@ def train(sur: Surrogate, ff: ReaxFF, source: FrameSource, steps: int, nframes: 
                 atoms_per_frame=int(frames[0][0][0].shape[0]), ms_per_step=1e3 * t_train / max(steps, 1))
 
 
+def train_streamed(sur: Surrogate, ff: ReaxFF, source: FrameSource, nframes: int, lr: float = 2e-3,
+                   lr_end: float = 1e-4, wE: float = 1.0, wF: float = 1.0, seed: int = 0,
+                   norm_frames: int = 8, log=None, log_every: int = 1000):
+    """One Adam step per fresh frame: `nframes` frames drawn from `source`, each labelled
+    by the plain FP64 path on the GPU as it arrives and used once (nothing stored), with
+    a cosine-decayed learning rate.  The normaliser is fitted on the first norm_frames
+    frames.  Returns a dict of losses (every log_every steps) and timings."""
+    t0 = time.perf_counter()
+    first = []
+    for _ in range(norm_frames):
+        sysf, temp = source.next()
+        d = to_device(sysf)
+        first.append((d, label(ff, d), temp))
+    shift, scale = fit_normaliser(sur, [f[0] for f in first])
+    e_atom = float(np.mean([f[1][0] / f[0][0].shape[0] for f in first]))
+    sur.set_params(init_params(sur.members, sur.npar, seed, e_atom), shift, scale)
+    losses = []
+    t_label = 0.0
+    t1 = time.perf_counter()
+    for it in range(nframes):
+        if it < norm_frames:
+            (pos, typ, q, box), (E, F), temp = first[it]
+        else:
+            tl = time.perf_counter()
+            sysf, temp = source.next()
+            pos, typ, q, box = to_device(sysf)
+            E, F = label(ff, (pos, typ, q, box))
+            t_label += time.perf_counter() - tl
+        c = 0.5 * (1.0 + math.cos(math.pi * it / max(nframes - 1, 1)))
+        rate = lr_end + (lr - lr_end) * c
+        loss = sur.train_step(pos, typ, box, E, F, wE, wF, rate)
+        if it % log_every == 0 or it == nframes - 1:
+            lv = loss.cpu().numpy()
+            losses.append((it, lv.tolist()))
+            if log:
+                log(f"streamed step {it}: loss {np.round(lv, 3).tolist()} lr {rate:.2e}")
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    return dict(losses=losses, frames=nframes, atoms_per_frame=int(first[0][0][0].shape[0]),
+                seconds=total, label_and_generate_s=t_label, ms_per_frame=1e3 * (time.perf_counter() - t1) / nframes)
+
+
 def evaluate(sur: Surrogate, ff: ReaxFF, dev_frame, threshold_ev: float = 0.1):
     """Force errors against the plain FP64 forces (eV/A): the ensemble mean, the gated
     forces, and the fallback fraction at the given spread threshold."""

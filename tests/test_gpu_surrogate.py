@@ -323,3 +323,19 @@ def test_normaliser_matches_definition(sur4):
     ref_shift, ref_scale = S.normaliser(G.cpu().numpy().astype(np.float64))
     np.testing.assert_allclose(shift, ref_shift, rtol=1e-6, atol=1e-7)
     np.testing.assert_allclose(scale, ref_scale, rtol=1e-6)
+
+
+def test_streamed_training_lowers_loss(ff):
+    """One Adam step per fresh frame, labelled by the plain path as it arrives: the
+    loss over the last frames is below the loss over the first."""
+    from paper_1706_07772_amd import Surrogate
+    from paper_1706_07772_amd import training as T
+    sur = Surrogate(ff, 2)
+    try:
+        info = T.train_streamed(sur, ff, T.FrameSource(64, seed=2000), nframes=400, lr=2e-3, log_every=50)
+    finally:
+        sur.close()
+    first = np.mean(info["losses"][0][1])
+    last = np.mean([np.mean(l) for _, l in info["losses"][-3:]])
+    print("streamed loss", first, "->", last, "ms per frame", info["ms_per_frame"], flush=True)
+    assert info["frames"] == 400 and last < 0.5 * first
