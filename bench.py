@@ -56,7 +56,7 @@ TRAFFIC = {
 
 PHASES = {
     "lists": ("bbox", "cell_hist", "scan", "cell_scatter", "cell_sort", "gather_sorted",
-              "list_sweep", "bondtest", "compact", "mirror"),
+              "list_sweep", "bondtest", "bond_merge", "compact", "mirror"),
     "bonded": ("gather_q", "bo_prime", "delta_prime", "bo_corr", "atom_state", "atom_energy",
                "tasks", "angles", "torsions", "hbonds", "hb_acceptors"),
     "nonbonded": ("nonbonded", "nb_reduce", "nb_energy"),

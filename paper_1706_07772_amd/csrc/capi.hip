@@ -160,11 +160,12 @@ int alloc_atoms(reaxff_ctx* c, int64_t n) {
 #define G(ptr) do { tmp = c->cap_n; if (grow(c, ptr, tmp, need)) return REAXFF_ERR_HIP; cap = tmp; } while (0)
   G(c->L.perm); G(c->L.type_s); G(c->L.xs); G(c->L.far_cnt); G(c->L.far_lo); G(c->L.bond_off); G(c->L.hb_cnt);
   G(c->L.ha_cnt);
-  G(c->sc.cid); G(c->sc.cell_s); G(c->sc.cnt_cand); G(c->sc.cnt_bond);
+  G(c->sc.cid); G(c->sc.cell_s); G(c->sc.cnt_cand); G(c->sc.cnt_bond); G(c->sc.cnt_lo);
   G(c->W.dp); G(c->W.ast); G(c->W.gS); G(c->W.gSig); G(c->W.gSBO); G(c->W.gStot); G(c->W.gDp);
   G(c->W.gRso);
   G(c->W.fnb); G(c->W.fhb); G(c->W.xq); G(c->W.don_rng); G(c->W.nv);
 #undef G
+
   c->cap_n = cap;
   return 0;
 }
@@ -384,7 +385,7 @@ void reaxff_destroy(reaxff_ctx* c) {
                   c->W.xq, c->W.counters, c->W.epart, c->W.cnt_ang, c->W.cnt_tor, c->W.cnt_don,
                   c->W.off_ang, c->W.off_tor, c->W.off_don, c->W.ang, c->W.tor, c->W.don, c->W.donrec, c->L.far_lo, c->W.nbpart, c->W.nbtab, c->W.nbe,
                   c->L.bond_i, c->sc.cid, c->sc.cell_s, c->sc.cell_count,
-                  c->sc.cell_cursor, c->sc.flag, c->sc.cnt_cand, c->sc.cnt_bond,
+                  c->sc.cell_cursor, c->sc.flag, c->sc.cnt_cand, c->sc.cnt_lo, c->sc.cnt_bond,
                   c->sc.cand_j, c->sc.bond_t, c->sc.need, c->sc.tslot, c->sc.nslot,
                   c->sc.part, c->sc.totals, c->sc.scan_tmp};
   for (void* p : ptrs)
@@ -575,7 +576,8 @@ int build_lists_impl(reaxff_ctx* c, int64_t n, const double* pos, const int32_t*
       c->cap_ha = t;
     }
     if (n > 0 && launch_sweep(c->skin > 0.0 ? c->dp_list : c->dp, c->grid, n, (int)ncell,
-                              c->cut.r_bond * c->cut.r_bond, c->sc, c->L, c->prof, st))
+                              c->cut.r_bond * c->cut.r_bond, true, c->sc, c->L,
+                              c->prof, st))
       return fail(c, REAXFF_ERR_HIP, "sweep launch failed");
     if (n == 0) HIPCHK(c, hipMemsetAsync(c->sc.totals, 0, sizeof(int64_t) * 8, st));
     // bond offsets: counts with a trailing zero, exclusive scan, last element = total
@@ -610,7 +612,7 @@ int build_lists_impl(reaxff_ctx* c, int64_t n, const double* pos, const int32_t*
       again = true;
     }
     if (!again) break;
-    if (attempt >= 3) return fail(c, REAXFF_ERR_CAPACITY, "list widths did not converge");
+    if (attempt >= 5) return fail(c, REAXFF_ERR_CAPACITY, "list widths did not converge");
   }
   c->L.nfar = c->L.far_upper ? th[0] : th[0] / 2;
   // half nonbonded evaluation when every cell's upper stencil fits in LDS

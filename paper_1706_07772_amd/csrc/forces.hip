@@ -1129,7 +1129,7 @@ __global__ void k_energy_fold(const double* __restrict__ epart, double* __restri
 }
 
 const char* const kKernelNames[KID_COUNT] = {
-    "bbox", "cell_hist", "cell_scatter", "cell_sort", "gather_sorted", "list_sweep", "scan",
+    "bbox", "cell_hist", "cell_scatter", "cell_sort", "gather_sorted", "list_sweep", "bond_merge", "scan",
     "bondtest", "compact", "mirror", "zero", "gather_q", "bo_prime", "delta_prime", "bo_corr", "atom_state",
     "atom_energy", "tasks", "angles", "torsions", "hbonds", "hb_acceptors", "nonbonded", "back_s", "back_corr",
     "back_dp", "forces", "batch", "nb_reduce", "nb_energy", "energy_fold", "qeq_rows", "qeq_spmv", "qeq_vec", "sur_desc", "sur_net", "sur_pairw",

@@ -11,7 +11,7 @@ namespace rx {
 
 // kernels timed by the optional event profiler (reaxff_profile)
 enum KernelId {
-  KID_BBOX, KID_CELL_HIST, KID_CELL_SCATTER, KID_CELL_SORT, KID_GATHER, KID_LIST_SWEEP, KID_SCAN,
+  KID_BBOX, KID_CELL_HIST, KID_CELL_SCATTER, KID_CELL_SORT, KID_GATHER, KID_LIST_SWEEP, KID_BOND_MERGE, KID_SCAN,
   KID_BONDTEST, KID_COMPACT, KID_MIRROR, KID_ZERO, KID_GATHER_Q, KID_BO_PRIME, KID_DELTA_PRIME, KID_BO_CORR,
   KID_ATOM_STATE, KID_ATOM_ENERGY, KID_TASKS, KID_ANGLES, KID_TORSIONS, KID_HBONDS, KID_HB_ACC, KID_NONBONDED,
   KID_BACK_S, KID_BACK_CORR, KID_BACK_DP, KID_FORCES, KID_BATCH, KID_NB_REDUCE, KID_NB_ENERGY, KID_ENERGY_FOLD,
@@ -75,6 +75,8 @@ struct Scratch {
   int32_t* flag = nullptr;        // error flags written by kernels
   int32_t* cnt_bond = nullptr;    // [n + 1]
   int32_t* cnt_cand = nullptr;    // [n] bond candidates
+  int32_t* cnt_lo = nullptr;      // [n] bonds written by partners (each-pair-once sweep)
+  bool half = false;              // the last sweep took each pair once
   // fixed-width rows (one per atom) staging the sweep's bond candidates and bonds
   int32_t* cand_j = nullptr;      // width cand_w
   int32_t* bond_t = nullptr;      // width bond_w
@@ -143,8 +145,8 @@ int launch_bbox(const double* pos, const int32_t* type, int64_t n, double* part,
                 int32_t* flag, Prof& pf, hipStream_t st);
 int launch_cell_sort(const double* pos, const int32_t* type, int64_t n, const Grid& g, int ncell,
                      Scratch& sc, Lists& L, Prof& pf, hipStream_t st);
-int launch_sweep(const DevParams* P, const Grid& g, int64_t n, int ncell, double rb2, Scratch& sc, Lists& L,
-                 Prof& pf, hipStream_t st);
+int launch_sweep(const DevParams* P, const Grid& g, int64_t n, int ncell, double rb2, bool half, Scratch& sc,
+                 Lists& L, Prof& pf, hipStream_t st);
 int launch_bondtest(const DevParams* P, const Grid& g, int64_t n, double rb2, Scratch& sc, Lists& L, Prof& pf,
                     hipStream_t st);
 int launch_refresh_gather(const double* pos, int64_t n, const double4* xref, Lists& L, unsigned long long* dmax,

@@ -1,15 +1,22 @@
-// List construction on the GPU: cell-sorted layout, far-neighbour half list,
-// full bond list with mirror index, and hydrogen-bond list.
+// List construction on the GPU: cell-sorted layout, far-neighbour list,
+// full bond list with mirror index, and hydrogen-bond lists.
 //
 // The paper builds the bond and H-bond lists in one pass over the half
-// neighbour list and serialises only the slot reservation (Section 3.3); the
-// 3-body list is counted, prefix-summed and then filled (Section 3.3,
-// "Three-body Interactions").  Here every list is built the latter way:
-// one thread per atom counts its entries of all three lists in one sweep over
-// its cell stencil, the counts are prefix-summed, and a second sweep writes
-// each entry at its atom's offset.  No slot is ever contended, the order of
-// entries is deterministic, and the only host synchronisation is the readback
-// of the three totals that size the buffers.
+// neighbour list (Section 3.3).  Here one sweep over each cell's stencil
+// writes all of them: a wavefront per cell loads the stencil's candidates 64
+// at a time, one per lane, and tests them against each of the cell's atoms
+// in turn, numbering the accepted ones with a ballot, so every row is filled
+// in slot order with no contended counter.  When no dimension is covered
+// whole, far and bond-candidate rows take each pair once (from the atom that
+// sees the other after its own slot), which halves those tests; H rows keep
+// both halves (the slots before a group's own are tested for H pairs only,
+// by its donor H and acceptor atoms).  Rows have fixed widths; an overflow
+// is counted and reported, and the host widens the rows and sweeps again.
+// Bond candidates are then tested on their raw bond order, each bond found
+// once is given to its partner's row as well, and the bond rows are
+// compacted in increasing partner order with their mirror index.  The only
+// host synchronisation is the readback of the totals that size the buffers.
+#include <climits>
 #include <type_traits>
 #include "reaxff_dev.h"
 #include "internal.h"
@@ -136,7 +143,12 @@ constexpr int SWEEP_WAVES = 4;
 constexpr int SWEEP_MAXQ = 64;   // chunks of a stencil: 2 (2 reach + 1)^2 <= 50
 
 // UPPER: far rows keep only the entries after the centre's own slot.
-template <bool MINIMG, bool UPPER>
+// HALF (with UPPER): far and bond-candidate rows take each pair once, from
+// the atom that sees the other after its own slot, so their tests cover half
+// the stencil; batches wholly before a group's own slots are only tested for
+// H pairs, by the donor H and acceptor centres.  The bonds' other halves are
+// added after the bond test (k_transpose, k_merge_bonds).
+template <bool MINIMG, bool UPPER, bool HALF>
 __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
     const DevParams* __restrict__ P, Grid g, int ncell, const double4* __restrict__ xs,
     const int32_t* __restrict__ cstart, int32_t* __restrict__ far_cnt, int32_t* __restrict__ far_j,
@@ -145,6 +157,7 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
     int32_t* __restrict__ ha_cnt, int32_t* __restrict__ ha_j, int ha_w, int slots,
     int32_t* __restrict__ far_lo, int32_t* __restrict__ need, unsigned long long* __restrict__ tslot,
     int32_t* __restrict__ nslot) {
+  static_assert(!HALF || UPPER, "each pair once needs the upper rows");
   __shared__ unsigned long long red[SWEEP_WAVES][2];
   __shared__ int q_s0[SWEEP_WAVES][SWEEP_MAXQ], q_base[SWEEP_WAVES][SWEEP_MAXQ + 1];
   __shared__ double q_sh[SWEEP_WAVES][SWEEP_MAXQ][3];
@@ -222,7 +235,9 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
           sz = q_sh[wv][q][2];
         }
       }
-      double4 xj = make_double4(0.0, 0.0, 0.0, 0.0);
+      // HALF: lanes past the stencil's end hold NaN, so every distance
+      // test fails there and no mask of valid lanes enters the predicates
+      double4 xj = make_double4(HALF ? __builtin_nan("") : 0.0, 0.0, 0.0, 0.0);
       if (valid) xj = xs[s];
       const int tj = (int)xj.w;
       // bond reach of this candidate's type against each centre type
@@ -232,6 +247,98 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
       // lane masks of the batch: the count masks below are ANDs of plain
       // compares with these, so no predicate is rebuilt for its ballot
       const unsigned long long vmask = ballot(valid), accl = ballot(valid && acc), donl = ballot(valid && don);
+      // the distance of candidate lanes from a centre (uniform position)
+      auto dist2 = [&](double4 xi4) {
+        double dx = xj.x - xi4.x, dy = xj.y - xi4.y, dz = xj.z - xi4.z;
+        if constexpr (MINIMG) {
+          dx = min_image(dx, g.L[0], g.invL[0]);
+          dy = min_image(dy, g.L[1], g.invL[1]);
+          dz = min_image(dz, g.L[2], g.invL[2]);
+        } else {
+          dx -= sx;
+          dy -= sy;
+          dz -= sz;
+        }
+        return r2_of(dx, dy, dz);
+      };
+      // a centre's H entries of this batch (its hb row for a donor H, its
+      // ha row for an acceptor), numbered with the ballot in slot order
+      auto hrow = [&](int l, int i, double r2) {
+        if ((donc >> l) & 1) {
+          const bool h = acc && r2 <= rh2;
+          const unsigned long long mh = ballot(h);
+          if (mh) {
+            const int k2 = readlane_i(kh, l);
+            if (h) {
+              const int k = k2 + __popcll(mh & below);
+              if (k < hb_w) __builtin_nontemporal_store(s, &hb_j[(int64_t)i * hb_w + k]);
+            }
+            kh = writelane_i(k2 + __popcll(mh), l, kh);
+          }
+        } else {
+          const bool h = don && r2 <= rh2;
+          const unsigned long long ma = ballot(h);
+          if (ma) {
+            const int k3 = readlane_i(ka, l);
+            if (h) {
+              const int k = k3 + __popcll(ma & below);
+              if (k < ha_w) __builtin_nontemporal_store(s, &ha_j[(int64_t)i * ha_w + k]);
+            }
+            ka = writelane_i(k3 + __popcll(ma), l, ka);
+          }
+        }
+      };
+      if constexpr (HALF) {
+        // H rows keep both halves (their pairs are few, and rows in slot
+        // order need no merging); far and bond-candidate rows only the pairs
+        // after each centre's own slot.  A batch wholly before the group's
+        // own slots holds H pairs only: the donor H and acceptor centres
+        // that have a partner class in it test it.
+        if (b0 + 64 <= own0 + ig) {
+          unsigned long long hm = (accl ? donc : 0ull) | (donl ? accc : 0ull);
+          while (hm) {
+            const int l = __builtin_ctzll(hm);
+            hm &= hm - 1;
+            const int i = a0 + ig + l;
+            hrow(l, i, dist2(xs[i]));
+          }
+          continue;
+        }
+        const double4* __restrict__ xcen = xs + (a0 + ig);
+        int32_t* __restrict__ frow = far_j + (int64_t)(a0 + ig) * far_w;
+        for (int l = 0; l < mi; ++l, ++xcen, frow += far_w) {
+          const int i = a0 + ig + l;
+          const double r2 = dist2(*xcen);
+          const int dl = own0 + ig + l - b0;   // the centre's own lane (uniform)
+          const bool f = r2 <= rn2 && lane > dl;
+          const unsigned long long mf = ballot(f);
+          if (mf) {
+            const int k0 = readlane_i(kf, l);
+            if (f) {
+              const int k = k0 + __popcll(mf & below);
+              if (k < far_w) __builtin_nontemporal_store(slot, &frow[k]);
+            }
+            kf = writelane_i(k0 + __popcll(mf), l, kf);
+            if (mf & ballot(r2 <= rb2)) {
+              const int ti = readlane_i(tmine, l);
+              const double qa = (ti & 1) ? q1 : q0, qbr = (ti & 1) ? q3 : q2;
+              const double qt = (ti & 2) ? qbr : qa;
+              const bool b = f && r2 <= qt;
+              const unsigned long long mb = ballot(b);
+              if (mb) {
+                const int k1 = readlane_i(kc, l);
+                if (b) {
+                  const int k = k1 + __popcll(mb & below);
+                  if (k < cand_w) __builtin_nontemporal_store(s, &cand_j[(int64_t)i * cand_w + k]);
+                }
+                kc = writelane_i(k1 + __popcll(mb), l, kc);
+              }
+            }
+          }
+          if (((donc | accc) >> l) & 1) hrow(l, i, r2);
+        }
+        continue;
+      }
       // batches holding some centre's own slot set that centre's count of
       // entries before it; the others run the loop without that code
       const bool hasown = !UPPER && halfable && b0 < own0 + ig + mi && b0 + 64 > own0 + ig;
@@ -383,7 +490,7 @@ __global__ __launch_bounds__(BT_BS) void k_bondtest(
     const DevParams* __restrict__ P, Grid g, int64_t n, const double4* __restrict__ xs,
     const int32_t* __restrict__ cnt_cand, const int32_t* __restrict__ cand_j, int cand_w,
     int32_t* __restrict__ cnt_bond, int32_t* __restrict__ bond_t, int bond_w,
-    int32_t* __restrict__ need, unsigned long long* __restrict__ tslot, double rb2) {
+    int32_t* __restrict__ need, unsigned long long* __restrict__ tslot, double rb2, int acct) {
   __shared__ unsigned long long red[BT_BS / 64][3];
   __shared__ BondTestP bp[NT * NT];
   for (int t = threadIdx.x; t < NT * NT; t += BT_BS) {
@@ -459,10 +566,12 @@ __global__ __launch_bounds__(BT_BS) void k_bondtest(
       // angles at i <= C(d,2); torsions about i's bonds <= ceil(d (d-1)^2 / 2)
       // (the sum over bonds of (d_j-1)(d_k-1) is at most half the sum of
       // squares); donor bonds <= d for an H atom
-      const unsigned long long d = (unsigned long long)nb;
-      ba += d * (d > 0 ? d - 1 : 0) / 2;
-      bt += (d * (d > 0 ? (d - 1) * (d - 1) : 0) + 1) / 2;
-      bd += P->atom[ti].hbond == 1 ? d : 0;
+      if (acct) {
+        const unsigned long long d = (unsigned long long)nb;
+        ba += d * (d > 0 ? d - 1 : 0) / 2;
+        bt += (d * (d > 0 ? (d - 1) * (d - 1) : 0) + 1) / 2;
+        bd += P->atom[ti].hbond == 1 ? d : 0;
+      }
     }
   }
   for (int off = 32; off > 0; off >>= 1) {
@@ -483,7 +592,8 @@ __global__ __launch_bounds__(BT_BS) void k_bondtest(
   }
 }
 
-// staged bond rows -> compressed rows, with the owner of each entry
+// staged bond rows -> compressed rows in increasing partner order, with the
+// owner of each entry
 __global__ void k_compact(int64_t n, const int32_t* __restrict__ cnt_bond,
                           const int32_t* __restrict__ bond_t, int bond_w,
                           const int32_t* __restrict__ bond_off, int32_t* __restrict__ bond_j,
@@ -493,8 +603,92 @@ __global__ void k_compact(int64_t n, const int32_t* __restrict__ cnt_bond,
   const int ob = bond_off[i], nb = cnt_bond[i];
   const int32_t* row = bond_t + i * (int64_t)bond_w;
   for (int k = 0; k < nb; ++k) {
-    bond_j[ob + k] = row[k];
+    const int v = row[k];
+    int t = k - 1;   // insertion into the sorted prefix (rows hold a few bonds)
+    while (t >= 0 && bond_j[ob + t] > v) {
+      bond_j[ob + t + 1] = bond_j[ob + t];
+      --t;
+    }
+    bond_j[ob + t + 1] = v;
     bond_i[ob + k] = (int32_t)i;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// the partners' halves of the rows of an each-pair-once sweep
+// ---------------------------------------------------------------------------
+// For each atom i and each of the first cnt[i] entries j of its row in src,
+// i is written into j's row of dst from the row's end (lo[j] counts them; an
+// entry beyond the width is counted and not written).  GROUP lanes per atom,
+// each taking up to four entries at a time so that their atomics are in
+// flight together.
+template <int GROUP>
+__global__ __launch_bounds__(256) void k_transpose(int64_t n, const int32_t* __restrict__ cnt,
+                                                   const int32_t* __restrict__ src, int sw,
+                                                   int32_t* __restrict__ lo, int32_t* __restrict__ dst, int dw) {
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GROUP;
+  const int sub = threadIdx.x & (GROUP - 1);
+  if (i >= n) return;
+  const int c = min(cnt[i], sw);
+  const int32_t* __restrict__ row = src + i * (int64_t)sw;
+  for (int k0 = 0; k0 < c; k0 += 4 * GROUP) {
+    int j[4], kl[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + u * GROUP + sub;
+      j[u] = k < c ? row[k] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) kl[u] = j[u] >= 0 ? atomicAdd(&lo[j[u]], 1) : dw;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (kl[u] < dw) dst[(int64_t)j[u] * dw + (dw - 1 - kl[u])] = (int32_t)i;
+  }
+}
+
+// Bond rows of an each-pair-once sweep: the partners' entries (written from
+// the row's end) moved next to the atom's own, one thread per row (the order
+// is fixed when the rows are compacted); the interaction task bounds are
+// taken from the full rows (as the bond test does for full sweeps).
+__global__ __launch_bounds__(256) void k_merge_bonds(const DevParams* __restrict__ P, int64_t n,
+                                                     const double4* __restrict__ xs, int32_t* __restrict__ cnt_bond,
+                                                     const int32_t* __restrict__ lo, int32_t* __restrict__ bond_t,
+                                                     int bond_w, int32_t* __restrict__ need,
+                                                     unsigned long long* __restrict__ tslot) {
+  __shared__ unsigned long long red[4][3];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long ba = 0, bt = 0, bd = 0;
+  if (i < n) {
+    const int cu = cnt_bond[i], cl = lo[i], tot = cu + cl;
+    if (tot > bond_w) {
+      atomicMax(&need[2], tot);
+    } else if (cl > 0) {
+      // the entries at [w - cl, w) that lie outside [cu, cu + cl) fill its gap
+      int32_t* __restrict__ row = bond_t + i * (int64_t)bond_w;
+      const int m = min(cl, bond_w - cl - cu), src0 = max(cu + cl, bond_w - cl);
+      for (int k = 0; k < m; ++k) row[cu + k] = row[src0 + k];
+    }
+    cnt_bond[i] = tot;
+    const unsigned long long d = (unsigned long long)tot;
+    ba = d * (d > 0 ? d - 1 : 0) / 2;
+    bt = (d * (d > 0 ? (d - 1) * (d - 1) : 0) + 1) / 2;
+    bd = P->atom[(int)xs[i].w].hbond == 1 ? d : 0;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    ba += __shfl_down(ba, off, 64);
+    bt += __shfl_down(bt, off, 64);
+    bd += __shfl_down(bd, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6][0] = ba;
+    red[threadIdx.x >> 6][1] = bt;
+    red[threadIdx.x >> 6][2] = bd;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    unsigned long long v = 0;
+    for (int w = 0; w < 4; ++w) v += red[w][threadIdx.x];
+    if (v) atomicAdd(&tslot[(blockIdx.x & (ESLOT - 1)) * 8 + threadIdx.x + 1], v);
   }
 }
 
@@ -641,13 +835,16 @@ __global__ void k_fold_totals(const unsigned long long* __restrict__ tslot, cons
   }
 }
 
-int launch_sweep(const DevParams* P, const Grid& g, int64_t n, int ncell, double rb2, Scratch& sc, Lists& L,
-                 Prof& pf, hipStream_t st) {
+int launch_sweep(const DevParams* P, const Grid& g, int64_t n, int ncell, double rb2, bool half, Scratch& sc,
+                 Lists& L, Prof& pf, hipStream_t st) {
   if (stencil_chunks(g) > SWEEP_MAXQ) return -1;   // the sweep's chunk table
+  // each pair once: upper rows of stencil slots, no dimension covered whole
+  half = half && L.far_upper && L.far_slots && !g.full[0] && !g.full[1] && !g.full[2];
   (void)hipMemsetAsync(sc.need, 0, sizeof(int32_t) * 8, st);
   (void)hipMemsetAsync(sc.totals, 0, sizeof(int64_t) * 8, st);
   (void)hipMemsetAsync(sc.tslot, 0, sizeof(int64_t) * 8 * ESLOT, st);
   (void)hipMemsetAsync(sc.nslot, 0, sizeof(int32_t) * ESLOT, st);
+  sc.half = half;
   pf.begin(KID_LIST_SWEEP, st);
   auto sweep = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3(nblk(ncell, SWEEP_WAVES)), dim3(64 * SWEEP_WAVES), 0, st, P, g, ncell, L.xs,
@@ -658,11 +855,13 @@ int launch_sweep(const DevParams* P, const Grid& g, int64_t n, int ncell, double
   };
   const bool minimg = g.periodic && !g.shift_ok;
   if (minimg) {
-    if (L.far_upper) sweep(k_sweep<true, true>);
-    else sweep(k_sweep<true, false>);
+    if (half) sweep(k_sweep<true, true, true>);
+    else if (L.far_upper) sweep(k_sweep<true, true, false>);
+    else sweep(k_sweep<true, false, false>);
   } else {
-    if (L.far_upper) sweep(k_sweep<false, true>);
-    else sweep(k_sweep<false, false>);
+    if (half) sweep(k_sweep<false, true, true>);
+    else if (L.far_upper) sweep(k_sweep<false, true, false>);
+    else sweep(k_sweep<false, false, false>);
   }
   pf.end(st);
   return launch_bondtest(P, g, n, rb2, sc, L, pf, st);
@@ -674,10 +873,22 @@ int launch_bondtest(const DevParams* P, const Grid& g, int64_t n, double rb2, Sc
   hipLaunchKernelGGL(k_bondtest, dim3(xcd_grid(std::min<int64_t>(nblk(n, BT_TILE), 4096))), dim3(BT_BS), 0, st,
                      P, g, n, L.xs, sc.cnt_cand,
                      sc.cand_j, sc.cand_w, sc.cnt_bond, sc.bond_t, sc.bond_w, sc.need,
-                     reinterpret_cast<unsigned long long*>(sc.tslot), rb2);
+                     reinterpret_cast<unsigned long long*>(sc.tslot), rb2, sc.half ? 0 : 1);
+  pf.end(st);
+  if (sc.half) {
+    pf.begin(KID_BOND_MERGE, st);
+    // candidates were each pair once, so are the bonds: each atom's bonds
+    // go to its partners' rows too
+    (void)hipMemsetAsync(sc.cnt_lo, 0, sizeof(int32_t) * n, st);
+    constexpr int BG = 2;
+    hipLaunchKernelGGL(k_transpose<BG>, dim3(nblk(n * BG, 256)), dim3(256), 0, st, n, sc.cnt_bond, sc.bond_t,
+                       sc.bond_w, sc.cnt_lo, sc.bond_t, sc.bond_w);
+    hipLaunchKernelGGL(k_merge_bonds, dim3(nblk(n, 256)), dim3(256), 0, st, P, n, L.xs, sc.cnt_bond, sc.cnt_lo,
+                       sc.bond_t, sc.bond_w, sc.need, reinterpret_cast<unsigned long long*>(sc.tslot));
+    pf.end(st);
+  }
   hipLaunchKernelGGL(k_fold_totals, dim3(1), dim3(64), 0, st, reinterpret_cast<const unsigned long long*>(sc.tslot), sc.nslot,
                      reinterpret_cast<unsigned long long*>(sc.totals), sc.need);
-  pf.end(st);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
