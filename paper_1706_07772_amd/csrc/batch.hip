@@ -6,8 +6,9 @@
 // (terms.h) as the one-launch-per-stage path, with
 //   * the cluster's atoms (x, y, z, q), types, bond-row offsets and the
 //     nonbonded/H-bond force accumulators in LDS;
-//   * the bond list built as the paper builds its lists (Section 3.3): count
-//     per atom, prefix sum, fill, here inside the workgroup;
+//   * the bond list built as the paper builds its lists (Section 3.3): each
+//     pair tested once, rows counted, prefix-summed and filled, here inside
+//     the workgroup;
 //   * far-neighbour and H-bond relations tested in place over all pairs of
 //     the cluster (same predicates as the stored lists of the large path);
 //   * the per-entry and per-atom work arrays in a private slice of device
@@ -137,6 +138,10 @@ __shared__ int32_t b_ty[BNMAX];
 __shared__ int32_t b_off[BNMAX + 1];  // bond rows
 __shared__ double4 b_f[BNMAX];        // nonbonded + H-bond forces
 __shared__ NbP b_nb[NT * NT];
+__shared__ HbP b_hb[NT * NT * NT];
+__shared__ double b_reach2[NT * NT];  // min(bond reach, r_bond)^2 of each type pair
+__shared__ int32_t b_alist[BNMAX];    // the cluster's acceptors, in index order
+__shared__ int32_t b_nacc;
 __shared__ double b_acc[NRED];        // per-cluster energies and counts
 __shared__ int32_t b_next;
 
@@ -220,8 +225,10 @@ __device__ __noinline__ int st_load(int64_t a0, int n) {
     b_x[i] = make_double4(A.pos[3 * (a0 + i)], A.pos[3 * (a0 + i) + 1], A.pos[3 * (a0 + i) + 2], A.q[a0 + i]);
     b_ty[i] = t;
     b_f[i] = make_double4(0.0, 0.0, 0.0, 0.0);
+    b_off[i + 1] = 0;
     W.gSBO[i] = 0.0;
   }
+  if (tid == 0) b_off[0] = 0;
   return bad;
 }
 
@@ -248,9 +255,10 @@ __device__ __noinline__ void st_fail(int c, int64_t a0, int n, int code, int nen
 
 // bond rows: count per atom (and far pairs, for the counts)
 template <int BSZ>
-__device__ __noinline__ void st_count(int n) {
+__device__ __noinline__ void st_count(int n, int far) {
   const BatchArgs A = uni_copy(b_args);
   n = uni(n);
+  far = uni(far);
   const DevParams* __restrict__ P = A.P;
   const double rn2 = P->rn2, rb2 = P->r_bond * P->r_bond, bo_cut = P->bo_cut;
   const int tid = threadIdx.x;
@@ -270,7 +278,7 @@ __device__ __noinline__ void st_count(int n) {
     b_off[i + 1] = nb;
   }
   if (tid == 0) b_off[0] = 0;
-  wave_acc(nfar, &b_acc[NTERMS + 3]);
+  if (far) wave_acc(nfar, &b_acc[NTERMS + 3]);
 }
 
 // bond rows: fill (same predicate, same order) and clear the entry adjoints
@@ -300,6 +308,90 @@ __device__ __noinline__ void st_fill(int n) {
         W.gvec[e] = make_double4(0.0, 0.0, 0.0, 0.0);
         ++e;
       }
+    }
+  }
+}
+
+// the cluster's acceptors listed in index order, by the first wavefront
+template <int BSZ>
+__device__ __noinline__ void st_acceptors(int n) {
+  const BatchArgs A = uni_copy(b_args);
+  n = uni(n);
+  if (threadIdx.x >= 64) return;
+  const int lane = threadIdx.x;
+  int na = 0;
+  for (int b = 0; b < n; b += 64) {
+    const int i = b + lane;
+    const bool a = i < n && A.P->atom[b_ty[i]].hbond == 2;
+    const unsigned long long m = ballot(a);
+    if (a) b_alist[na + __popcll(m & ((1ull << lane) - 1ull))] = i;
+    na += __popcll(m);
+  }
+  if (lane == 0) b_nacc = na;
+}
+
+// Bond rows with each pair tested once: one wavefront per atom i, one
+// partner j > i per lane.  A bond goes to both atoms' staging rows (BSTAGE
+// entries per atom, in the storage of the entries' bond-order derivatives,
+// which is written only later) at places taken with LDS atomics on the row
+// counts b_off[1..n]; far pairs are counted.  A count above BSTAGE means the
+// staging row overflowed (the caller then builds the rows by the two full
+// sweeps st_count and st_fill).
+constexpr int BSTAGE = 32;
+
+template <int BSZ>
+__device__ __noinline__ void st_pairs(int n) {
+  const BatchArgs A = uni_copy(b_args);
+  n = uni(n);
+  int32_t* __restrict__ stage =
+      reinterpret_cast<int32_t*>(A.scratch + (int64_t)blockIdx.x * A.lay.stride + A.lay.dbop);
+  const DevParams* __restrict__ P = A.P;
+  const double rn2 = P->rn2, bo_cut = P->bo_cut;
+  constexpr int NW = BSZ / 64;
+  const int lane = threadIdx.x & 63;
+  double nfar = 0.0;
+  for (int i = threadIdx.x >> 6; i < n; i += NW) {
+    const double4 xi = b_x[i];
+    const int ti = b_ty[i];
+    for (int j = i + 1 + lane; j < n; j += 64) {
+      const double4 xj = b_x[j];
+      const double r2 = r2_of(xj.x - xi.x, xj.y - xi.y, xj.z - xi.z);
+      if (r2 <= rn2) nfar += 1.0;
+      const int tj = b_ty[j];
+      if (r2 <= b_reach2[ti * NT + tj] && bo_raw(P->pair[ti * NT + tj], sqrt(r2), bo_cut) >= bo_cut) {
+        const int ki = atomicAdd(&b_off[i + 1], 1), kj = atomicAdd(&b_off[j + 1], 1);
+        if (ki < BSTAGE) stage[i * BSTAGE + ki] = j;
+        if (kj < BSTAGE) stage[j * BSTAGE + kj] = i;
+      }
+    }
+  }
+  wave_acc(nfar, &b_acc[NTERMS + 3]);
+}
+
+// staged bond rows -> the rows at their offsets, in increasing partner order
+// (insertion sort: rows hold a few bonds); entry adjoints cleared
+template <int BSZ>
+__device__ __noinline__ void st_rows(int n) {
+  const BatchArgs A = uni_copy(b_args);
+  n = uni(n);
+  Lists L;
+  Work W;
+  views(A, L, W);
+  const int32_t* __restrict__ stage =
+      reinterpret_cast<const int32_t*>(A.scratch + (int64_t)blockIdx.x * A.lay.stride + A.lay.dbop);
+  for (int i = threadIdx.x; i < n; i += BSZ) {
+    const int e0 = b_off[i], m = b_off[i + 1] - e0;
+    for (int k = 0; k < m; ++k) {
+      const int v = stage[i * BSTAGE + k];
+      int t = k - 1;
+      while (t >= 0 && L.bond_j[e0 + t] > v) {
+        L.bond_j[e0 + t + 1] = L.bond_j[e0 + t];
+        --t;
+      }
+      L.bond_j[e0 + t + 1] = v;
+      L.bond_i[e0 + k] = i;
+      W.gbo[e0 + k] = make_double4(0.0, 0.0, 0.0, 0.0);
+      W.gvec[e0 + k] = make_double4(0.0, 0.0, 0.0, 0.0);
     }
   }
 }
@@ -499,8 +591,10 @@ __device__ __noinline__ void st_torsions(int n) {
   wave_acc(ntor, &b_acc[NTERMS + 1]);
 }
 
-// hydrogen bonds of each H atom over the acceptors of the cluster within
-// r_hb; acceptor forces and the donor entry's adjoints with atomic adds
+// hydrogen bonds: one wavefront per H atom and donor bond, one acceptor of
+// the cluster's list per lane (those within r_hb); acceptor forces with LDS
+// atomic adds, the donor entry's adjoints and the force on H summed over the
+// wavefront
 template <int BSZ>
 __device__ __noinline__ void st_hbonds(int n) {
   const BatchArgs A = uni_copy(b_args);
@@ -510,8 +604,11 @@ __device__ __noinline__ void st_hbonds(int n) {
   views(A, L, W);
   const DevParams* __restrict__ P = A.P;
   const double rh2 = P->rh2, hb_bo_cut = P->hb_bo_cut;
+  constexpr int NW = BSZ / 64;
+  const int lane = threadIdx.x & 63;
+  const int nacc = b_nacc;
   double ehb = 0.0, nhb = 0.0;
-  for (int h = threadIdx.x; h < n; h += BSZ) {
+  for (int h = threadIdx.x >> 6; h < n; h += NW) {
     const int th = b_ty[h];
     if (P->atom[th].hbond != 1) continue;
     const double4 xh = b_x[h];
@@ -524,14 +621,13 @@ __device__ __noinline__ void st_hbonds(int n) {
       const double4 rx = W.bd[u];
       double gbo = 0.0;
       double3 gx = make_double3(0.0, 0.0, 0.0);
-      for (int Z = 0; Z < n; ++Z) {
+      for (int k = lane; k < nacc; k += 64) {
+        const int Z = b_alist[k];
         if (Z == X) continue;
-        const int tz = b_ty[Z];
-        if (P->atom[tz].hbond != 2) continue;
         const double4 xz = b_x[Z];
         const double dx = xz.x - xh.x, dy = xz.y - xh.y, dz = xz.z - xh.z;
         if (!(r2_of(dx, dy, dz) <= rh2)) continue;
-        const HbTerm o = hb_term(P->hb[(tx * NT + th) * NT + tz], bo, rx, dx, dy, dz);
+        const HbTerm o = hb_term(b_hb[(tx * NT + th) * NT + b_ty[Z]], bo, rx, dx, dy, dz);
         ehb += o.E;
         gbo += o.dE_dbo;
         gx = add3(gx, o.g_rx);
@@ -539,10 +635,23 @@ __device__ __noinline__ void st_hbonds(int n) {
         atomic_add3(&b_f[Z], -o.g_rz.x, -o.g_rz.y, -o.g_rz.z);
         nhb += 1.0;
       }
-      atomic_add3(&W.gvec[u], gx);
-      atomicAdd(&W.gbo[u].x, gbo);
+      for (int off = 32; off > 0; off >>= 1) {
+        gbo += __shfl_down(gbo, off, 64);
+        gx.x += __shfl_down(gx.x, off, 64);
+        gx.y += __shfl_down(gx.y, off, 64);
+        gx.z += __shfl_down(gx.z, off, 64);
+      }
+      if (lane == 0) {
+        atomic_add3(&W.gvec[u], gx);
+        atomicAdd(&W.gbo[u].x, gbo);
+      }
     }
-    atomic_add3(&b_f[h], fh);
+    for (int off = 32; off > 0; off >>= 1) {
+      fh.x += __shfl_down(fh.x, off, 64);
+      fh.y += __shfl_down(fh.y, off, 64);
+      fh.z += __shfl_down(fh.z, off, 64);
+    }
+    if (lane == 0) atomic_add3(&b_f[h], fh);
   }
   wave_acc(ehb, &b_acc[E_HB]);
   wave_acc(nhb, &b_acc[NTERMS + 2]);
@@ -598,11 +707,15 @@ __device__ __noinline__ void st_out(int c, int64_t a0, int n) {
 }
 
 template <int BSZ>
-// 3 waves per SIMD: the largest stages (torsions, angles) fit in 168 VGPRs
-__global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(3))) void k_batch(BatchArgs A) {
+// 2 waves per SIMD: the largest stages (torsions, angles) fit in 256 VGPRs without spills
+__global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(2))) void k_batch(BatchArgs A) {
   const int tid = threadIdx.x;
   if (tid == 0) b_args = A;
-  for (int k = tid; k < NT * NT; k += BSZ) b_nb[k] = nb_params(A.P->pair[k]);
+  for (int k = tid; k < NT * NT; k += BSZ) {
+    b_nb[k] = nb_params(A.P->pair[k]);
+    b_reach2[k] = fmin(A.P->pair[k].reach2, A.P->r_bond * A.P->r_bond);
+  }
+  for (int k = tid; k < NT * NT * NT; k += BSZ) b_hb[k] = A.P->hb[k];
   int pos_in_order = A.dynamic ? 0 : A.wg_first[blockIdx.x];
   const int pos_end = A.dynamic ? 0 : A.wg_first[blockIdx.x + 1];
   for (;;) {
@@ -629,8 +742,21 @@ __global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(3))) void k
       __syncthreads();
       continue;
     }
-    st_count<BSZ>(n);
-    __syncthreads();
+    st_acceptors<BSZ>(n);
+    // staging rows of BSTAGE entries per atom need BSTAGE n of the 8 ecap
+    // words of the entries' derivative storage
+    const bool staged = BSTAGE * n <= 8 * A.ecap;
+    bool over = !staged;
+    if (staged) {
+      st_pairs<BSZ>(n);
+      __syncthreads();
+      for (int i = tid; i < n; i += BSZ) over = over || b_off[i + 1] > BSTAGE;
+      over = __syncthreads_or(over);
+    }
+    if (over) {   // no staging, or a row overflowed: both sweeps over all pairs
+      st_count<BSZ>(n, staged ? 0 : 1);
+      __syncthreads();
+    }
     wave_scan_inplace(b_off, n);
     __syncthreads();
     const int nent = b_off[n];
@@ -639,7 +765,8 @@ __global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(3))) void k
       __syncthreads();
       continue;
     }
-    st_fill<BSZ>(n);
+    if (over) st_fill<BSZ>(n);
+    else st_rows<BSZ>(n);
     __syncthreads();
     st_bo_prime<BSZ>(n);
     __syncthreads();
