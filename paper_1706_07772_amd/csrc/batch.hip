@@ -331,16 +331,24 @@ __device__ __noinline__ void st_acceptors(int n) {
 }
 
 // Bond rows with each pair tested once: one wavefront per atom i, one
-// partner j > i per lane.  A bond goes to both atoms' staging rows (BSTAGE
-// entries per atom, in the storage of the entries' bond-order derivatives,
-// which is written only later) at places taken with LDS atomics on the row
-// counts b_off[1..n]; far pairs are counted.  A count above BSTAGE means the
-// staging row overflowed (the caller then builds the rows by the two full
-// sweeps st_count and st_fill).
+// partner j > i per lane.  Pairs within the bond reach of their types are
+// queued in LDS (per wavefront) and their raw bond orders evaluated 64 at a
+// time, so the bond-order test runs on full wavefronts.  A bond goes to both
+// atoms' staging rows (BSTAGE entries per atom, in the storage of the
+// entries' bond-order derivatives, which is written only later) at places
+// taken with LDS atomics on the row counts b_off[1..n]; far pairs are
+// counted.  A count above BSTAGE means the staging row overflowed (the caller
+// then builds the rows by the two full sweeps st_count and st_fill).
 constexpr int BSTAGE = 32;
+
+struct PairQ {
+  int32_t i, j;
+  double r2;
+};
 
 template <int BSZ>
 __device__ __noinline__ void st_pairs(int n) {
+  __shared__ PairQ cq[BSZ / 64][128];
   const BatchArgs A = uni_copy(b_args);
   n = uni(n);
   int32_t* __restrict__ stage =
@@ -349,22 +357,55 @@ __device__ __noinline__ void st_pairs(int n) {
   const double rn2 = P->rn2, bo_cut = P->bo_cut;
   constexpr int NW = BSZ / 64;
   const int lane = threadIdx.x & 63;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  PairQ* __restrict__ q = cq[threadIdx.x >> 6];
+  auto sync_wave = [] {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+  // the first cnt queued pairs, one per lane
+  auto test = [&](int cnt) {
+    if (lane < cnt) {
+      const PairQ e = q[lane];
+      const int ti = b_ty[e.i], tj = b_ty[e.j];
+      if (bo_raw(P->pair[ti * NT + tj], sqrt(e.r2), bo_cut) >= bo_cut) {
+        const int ki = atomicAdd(&b_off[e.i + 1], 1), kj = atomicAdd(&b_off[e.j + 1], 1);
+        if (ki < BSTAGE) stage[e.i * BSTAGE + ki] = e.j;
+        if (kj < BSTAGE) stage[e.j * BSTAGE + kj] = e.i;
+      }
+    }
+  };
+  int qn = 0;   // queued pairs (uniform)
   double nfar = 0.0;
   for (int i = threadIdx.x >> 6; i < n; i += NW) {
     const double4 xi = b_x[i];
     const int ti = b_ty[i];
-    for (int j = i + 1 + lane; j < n; j += 64) {
-      const double4 xj = b_x[j];
-      const double r2 = r2_of(xj.x - xi.x, xj.y - xi.y, xj.z - xi.z);
-      if (r2 <= rn2) nfar += 1.0;
-      const int tj = b_ty[j];
-      if (r2 <= b_reach2[ti * NT + tj] && bo_raw(P->pair[ti * NT + tj], sqrt(r2), bo_cut) >= bo_cut) {
-        const int ki = atomicAdd(&b_off[i + 1], 1), kj = atomicAdd(&b_off[j + 1], 1);
-        if (ki < BSTAGE) stage[i * BSTAGE + ki] = j;
-        if (kj < BSTAGE) stage[j * BSTAGE + kj] = i;
+    for (int j0 = i + 1; j0 < n; j0 += 64) {
+      const int j = j0 + lane;
+      bool cand = false;
+      double r2 = 0.0;
+      if (j < n) {
+        const double4 xj = b_x[j];
+        r2 = r2_of(xj.x - xi.x, xj.y - xi.y, xj.z - xi.z);
+        if (r2 <= rn2) nfar += 1.0;
+        cand = r2 <= b_reach2[ti * NT + b_ty[j]];
+      }
+      const unsigned long long m = ballot(cand);
+      if (cand) q[qn + __popcll(m & below)] = PairQ{i, j, r2};
+      qn += __popcll(m);
+      if (qn >= 64) {
+        sync_wave();
+        test(64);
+        sync_wave();
+        if (lane < qn - 64) q[lane] = q[64 + lane];
+        sync_wave();
+        qn -= 64;
       }
     }
   }
+  sync_wave();
+  test(qn);
   wave_acc(nfar, &b_acc[NTERMS + 3]);
 }
 
