@@ -105,6 +105,59 @@ __device__ __forceinline__ double rcbrt_f(double x) {
   return fma(y, e * fma(e, 2.0 / 9.0, 1.0 / 3.0), y);
 }
 
+// exp_r, log_r: exp_f and log_f with the same reductions and polynomials,
+// but the integer steps done on the bit pattern, with no conversion, frexp or
+// ldexp instruction.  exp_r rounds x log2(e) to an integer k with the
+// 1.5 * 2^52 shifter (k is then the low word of the sum) and multiplies by
+// 2^k by adding k to the exponent field of the polynomial's value (in
+// [0.70, 1.42]), so it needs |x| < 700.  log_r reads the exponent and the
+// mantissa of a positive normal x from its bits (the mantissa is halved when
+// its top 20 bits reach those of sqrt 2) and forms the exponent as a double
+// by the 2^52 + 2^31 offset.  The pair term calls them: its arguments stay
+// far inside these ranges.
+__device__ __forceinline__ double exp_r(double x) {
+  constexpr double SH = 0x1.8p52;
+  const double ks = fma(x, LOG2_E, SH);
+  const int k = __double2loint(ks);
+  const double kd = ks - SH;
+  double r = fma(-kd, LN2_HEAD, x);
+  r = fma(-kd, LN2_TAIL, r);
+  double p = 0x1.af781738d6a07p-26;
+  p = fma(p, r, 0x1.28b3cc02abb37p-22);
+  p = fma(p, r, 0x1.71dde78463672p-19);
+  p = fma(p, r, 0x1.a01991d2b4315p-16);
+  p = fma(p, r, 0x1.a01a01b7fa994p-13);
+  p = fma(p, r, 0x1.6c16c187f21d0p-10);
+  p = fma(p, r, 0x1.111111110db86p-7);
+  p = fma(p, r, 0x1.555555554f0f0p-5);
+  p = fma(p, r, 0x1.5555555555562p-3);
+  p = fma(p, r, 0x1.0000000000011p-1);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return __hiloint2double(__double2hiint(p) + (k << 20), __double2loint(p));
+}
+
+__device__ __forceinline__ double log_r(double x) {
+  const int hi = __double2hiint(x);
+  const int mb = hi & 0x000fffff;
+  const int up = mb >= 0x6a09e ? 1 : 0;   // mantissa at or above sqrt 2: halve it
+  const int e = (hi >> 20) - 1023 + up;
+  const double m = __hiloint2double(mb | ((1023 - up) << 20), __double2loint(x));
+  const double f = m - 1.0;
+  const double s = f * rcp_f(2.0 + f);
+  const double z = s * s;
+  double p = 0x1.2b4b69e452555p-4;
+  p = fma(p, z, 0x1.39ff0e0e536dep-4);
+  p = fma(p, z, 0x1.7462b13e69a0bp-4);
+  p = fma(p, z, 0x1.c71c62ecdd1abp-4);
+  p = fma(p, z, 0x1.2492492dee8abp-3);
+  p = fma(p, z, 0x1.99999999952e2p-3);
+  p = fma(p, z, 0x1.5555555555558p-2);
+  const double lm = fma(2.0 * s * z, p, 2.0 * s);
+  const double de = __hiloint2double(0x43300000, e ^ (int)0x80000000) - 0x1.00000800p52;
+  return fma(de, LN2_HEAD, fma(de, LN2_TAIL, lm));
+}
+
 __device__ __forceinline__ double exp_c(double x) {
   x = x < -1000.0 ? -1000.0 : (x > 1000.0 ? 1000.0 : x);
   return exp_f(x);
@@ -692,17 +745,17 @@ __device__ __forceinline__ NbOut nb_pair(const NbP& p, double iR, double pv, dou
   const double um = u - 1.0;
   const double dtap = (140.0 * iR) * (u2 * u) * (um * um * um);
   // shielded Morse with inner wall
-  const double pw = exp_f(pv * log_f(r));
+  const double pw = exp_r(pv * log_r(r));
   const double sum = pw + p.gw_pow;
   const double isum = rcp_f(sum);
-  const double f13 = exp_f(ipv * log_f(sum));
+  const double f13 = exp_r(ipv * log_r(sum));
   const double df13 = f13 * isum * pw * ir;
   const double t = 1.0 - f13 * p.inv_rv;
-  const double e2 = exp_f(p.halpha * t);
+  const double e2 = exp_r(p.halpha * t);
   const double e1 = e2 * e2;
   const double ev = p.D * (e1 - 2.0 * e2);
   const double dev = -p.Dar * (e1 - e2) * df13;
-  const double ecr = p.e_core * exp_f(fma(-p.acr, r, p.a_core));   // a_core (1 - r / r_core)
+  const double ecr = p.e_core * exp_r(fma(-p.acr, r, p.a_core));   // a_core (1 - r / r_core)
   const double decr = -ecr * p.acr;
   // shielded Coulomb: den = (r^3 + gamma^-3)^(1/3), 1/s3 = (1/den)^3
   const double s3 = r2 * r + p.g3;
