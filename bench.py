@@ -53,6 +53,9 @@ WORK = {
 TRAFFIC = {
     "nonbonded": 2.725e9,
 }
+# the same counters summed over one dispatch of every kernel of a step
+# (build_lists + compute_forces at 1,044,000 atoms)
+WHOLE_STEP_TRAFFIC = 15.42e9
 
 PHASES = {
     "lists": ("bbox", "cell_hist", "scan", "cell_scatter", "cell_sort", "gather_sorted",
@@ -463,6 +466,8 @@ def main():
     ap.add_argument("--no-qeq", action="store_true", help="skip the charge-equilibration measurement")
     ap.add_argument("--surrogate-only", action="store_true",
                     help="only the surrogate measurement (for profiling)")
+    ap.add_argument("--surrogate-frames", type=int, default=20000,
+                    help="streamed training frames of the surrogate (fewer only to profile its kernels)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -484,7 +489,7 @@ def main():
         return
     if args.surrogate_only:
         ff = ReaxFF(params)
-        out = bench_surrogate(ff, params, args.steps, args.warmup)
+        out = bench_surrogate(ff, params, args.steps, args.warmup, nframes=args.surrogate_frames)
         print(json.dumps({"surrogate": out}), flush=True)
         return
     system = rs.workload(args.workload)
@@ -594,6 +599,7 @@ def main():
     geo = geometric_counts(system)
     work, per_unit = whole_step_work({**counts, **geo}, n)
     whole = {"gflop_eq": work / 1e9, "achieved_tflops": work / (ms_per_step * 1e-3) / 1e12,
+             "traffic": WHOLE_STEP_TRAFFIC if args.workload == "petn_1044000" else None,
              "peak": PEAK_FP64_VALU_TFLOPS, "frac": work / (ms_per_step * 1e-3) / 1e12 / PEAK_FP64_VALU_TFLOPS,
              "units": {k: {"count": int(v / UNIT_FLOPS[k]), "flops_per_unit": UNIT_FLOPS[k]}
                        for k, v in per_unit.items()}}
@@ -621,7 +627,7 @@ def main():
     surrogate = None
     if not args.no_surrogate:
         print("bench: surrogate", file=sys.stderr, flush=True)
-        surrogate = bench_surrogate(ff, params, args.steps, args.warmup)
+        surrogate = bench_surrogate(ff, params, args.steps, args.warmup, nframes=args.surrogate_frames)
 
     cpu = None
     if not args.no_cpu_baseline:
