@@ -151,7 +151,7 @@ struct DonRec {
 
 // atoms of a cell's upper stencil (the centre cell from its first atom on,
 // and every later chunk) that the half nonbonded kernel holds in LDS
-constexpr int NB_HALF_CAP = 1024;
+constexpr int NB_HALF_CAP = 1280;
 // chunk-table entries per cell: 2 (2 reach + 1)^2 <= 50 chunks and the total
 constexpr int NB_QMAX = 64;
 
