@@ -152,11 +152,25 @@ __global__ __launch_bounds__(QB) void k_qeq_spmv(Lists L, const int32_t* __restr
     const int32_t* __restrict__ rj = hj + i * (int64_t)w;
     const double* __restrict__ rv = hv + i * (int64_t)w;
     double as = 0.0, at = 0.0;
-    for (int k = lane; k < cnt; k += 64) {
-      const double h = rv[k];
-      const double2 xj = x[rj[k]];
-      as = fma(h, xj.x, as);
-      at = fma(h, xj.y, at);
+    // eight entries per lane at a time: their index and value loads, then
+    // their gathers, are in flight together
+    for (int k0 = lane; k0 < cnt; k0 += 8 * 64) {
+      int jj[8];
+      double hh[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = k0 + u * 64;
+        jj[u] = k < cnt ? rj[k] : (int)i;
+        hh[u] = k < cnt ? rv[k] : 0.0;
+      }
+      double2 xj[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) xj[u] = x[jj[u]];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        as = fma(hh[u], xj[u].x, as);
+        at = fma(hh[u], xj[u].y, at);
+      }
     }
     for (int off = 32; off > 0; off >>= 1) {
       as += __shfl_down(as, off, 64);
