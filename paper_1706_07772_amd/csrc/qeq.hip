@@ -78,26 +78,57 @@ __device__ __forceinline__ void slot_add(double* __restrict__ set, const int* fi
 }
 
 // H rows, one wavefront per sorted atom i: every j != i of i's cell stencil
-// with r_ij^2 <= r_nonb^2 (minimum image, the far list's predicate)
+// with r_ij^2 <= r_nonb^2 (minimum image, the far list's predicate; the
+// chunk's image shift when it is the minimum image of every listed pair).
+// Accepted neighbours are numbered with the ballot and their indices stored
+// in stencil order; their (slot, type, r^2) are queued in LDS and the matrix
+// elements computed 64 at a time, so the taper and the shielded Coulomb run
+// on full wavefronts.
+struct QRowQ {
+  int32_t k, tj;
+  double r2;
+};
+
 __global__ __launch_bounds__(QB) void k_qeq_rows(const DevParams* __restrict__ P, Grid g, Lists L,
                                                  int32_t* __restrict__ hj, double* __restrict__ hv,
                                                  int32_t* __restrict__ hcnt, int32_t w,
                                                  int32_t* __restrict__ need) {
+  __shared__ QRowQ rq[QWAVES][128];
   const int lane = threadIdx.x & 63;
   const int64_t i = xcd_block() * QWAVES + (threadIdx.x >> 6);
-  if (i >= L.n) return;
+  if (i >= L.n) return;   // uniform over the wavefront
+  QRowQ* __restrict__ q = rq[threadIdx.x >> 6];
   const double4 xi = L.xs[i];
   const int ti = (int)xi.w;
   const int c = L.cell_of[i];
   const int nq = stencil_chunks(g);
+  const bool minimg = g.periodic && !g.shift_ok;
   const double rn2 = P->rn2, iR = P->inv_r_nonb;
   int32_t* __restrict__ rj = hj + i * (int64_t)w;
   double* __restrict__ rv = hv + i * (int64_t)w;
-  int cnt = 0;
-  for (int q = 0; q < nq; ++q) {
+  const unsigned long long below = lanes_below();
+  auto sync_wave = [] {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+  auto evaluate = [&](int m) {   // the first m queued elements, one per lane
+    if (lane < m) {
+      const QRowQ e = q[lane];
+      if (e.k < w) {
+        const double r = sqrt(e.r2);
+        const double u = r * iR;
+        const double u4 = (u * u) * (u * u);
+        const double tap = fma(u4, fma(u, fma(u, fma(u, 20.0, -70.0), 84.0), -35.0), 1.0);
+        rv[e.k] = tap * C_ELE * rcbrt_f(fma(e.r2, r, P->pair[ti * NT + e.tj].g3));
+      }
+    }
+  };
+  int cnt = 0, qn = 0;
+  for (int ch = 0; ch < nq; ++ch) {
     int s0, s1;
     double sx, sy, sz;
-    stencil_chunk(g, L.cell_start, c, q, s0, s1, sx, sy, sz);
+    stencil_chunk(g, L.cell_start, c, ch, s0, s1, sx, sy, sz);
     for (int j0 = s0; j0 < s1; j0 += 64) {
       const int j = j0 + lane;
       bool ok = j < s1 && j != (int)i;
@@ -106,10 +137,14 @@ __global__ __launch_bounds__(QB) void k_qeq_rows(const DevParams* __restrict__ P
       if (ok) {
         const double4 xj = L.xs[j];
         double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
-        if (g.periodic) {
+        if (minimg) {
           dx = min_image(dx, g.L[0], g.invL[0]);
           dy = min_image(dy, g.L[1], g.invL[1]);
           dz = min_image(dz, g.L[2], g.invL[2]);
+        } else {
+          dx -= sx;
+          dy -= sy;
+          dz -= sz;
         }
         r2 = r2_of(dx, dy, dz);
         tj = (int)xj.w;
@@ -117,20 +152,25 @@ __global__ __launch_bounds__(QB) void k_qeq_rows(const DevParams* __restrict__ P
       }
       const unsigned long long m = ballot(ok);
       if (ok) {
-        const int k = cnt + __popcll(m & lanes_below());
-        if (k < w) {
-          const double r = sqrt(r2);
-          const double u = r * iR;
-          const double u4 = (u * u) * (u * u);
-          const double tap = fma(u4, fma(u, fma(u, fma(u, 20.0, -70.0), 84.0), -35.0), 1.0);
-          const double h = tap * C_ELE * rcbrt_f(fma(r2, r, P->pair[ti * NT + tj].g3));
-          rj[k] = j;
-          rv[k] = h;
-        }
+        const int pos = __popcll(m & below);
+        const int k = cnt + pos;
+        if (k < w) rj[k] = j;
+        q[qn + pos] = QRowQ{k, tj, r2};
       }
       cnt += __popcll(m);
+      qn += __popcll(m);
+      if (qn >= 64) {
+        sync_wave();
+        evaluate(64);
+        sync_wave();
+        if (lane < qn - 64) q[lane] = q[64 + lane];
+        sync_wave();
+        qn -= 64;
+      }
     }
   }
+  sync_wave();
+  evaluate(qn);
   if (lane == 0) {
     hcnt[i] = cnt;
     if (cnt > w) atomicMax(need, cnt);
