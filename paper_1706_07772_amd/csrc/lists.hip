@@ -243,6 +243,7 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
       // bond reach of this candidate's type against each centre type
       const double q0 = fmin(P->pair[0 * NT + tj].reach2, rb2), q1 = fmin(P->pair[1 * NT + tj].reach2, rb2),
                    q2 = fmin(P->pair[2 * NT + tj].reach2, rb2), q3 = fmin(P->pair[3 * NT + tj].reach2, rb2);
+      const double qmx = fmax(fmax(q0, q1), fmax(q2, q3));   // the largest, whatever the centre's type
       const bool acc = (accmask >> tj) & 1, don = (donmask >> tj) & 1;
       // lane masks of the batch: the count masks below are ANDs of plain
       // compares with these, so no predicate is rebuilt for its ballot
@@ -319,7 +320,7 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
               if (k < far_w) __builtin_nontemporal_store(slot, &frow[k]);
             }
             kf = writelane_i(k0 + __popcll(mf), l, kf);
-            if (mf & ballot(r2 <= rb2)) {
+            if (mf & ballot(r2 <= qmx)) {
               const int ti = readlane_i(tmine, l);
               const double qa = (ti & 1) ? q1 : q0, qbr = (ti & 1) ? q3 : q2;
               const double qt = (ti & 2) ? qbr : qa;
@@ -391,8 +392,8 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
               kf = writelane_i(k0 + __popcll(mfu), l, kf);
             }
             // bond candidates: the pair reach (by the centre's type) is only
-            // selected when some lane lies within the largest one
-            if (mf & ballot(r2 <= rb2)) {
+            // selected when some lane lies within its largest one
+            if (mf & ballot(r2 <= qmx)) {
               const int ti = readlane_i(tmine, l);
               const double qa = (ti & 1) ? q1 : q0, qbr = (ti & 1) ? q3 : q2;
               const double qt = (ti & 2) ? qbr : qa;
