@@ -77,65 +77,103 @@ __device__ __forceinline__ void slot_add(double* __restrict__ set, const int* fi
   }
 }
 
-// H rows, one wavefront per sorted atom i: every j != i of i's cell stencil
-// with r_ij^2 <= r_nonb^2 (minimum image, the far list's predicate; the
-// chunk's image shift when it is the minimum image of every listed pair).
-// Accepted neighbours are numbered with the ballot and their indices stored
-// in stencil order; their (slot, type, r^2) are queued in LDS and the matrix
+// H rows, one wavefront per cell: every j != i of the cell's stencil with
+// r_ij^2 <= r_nonb^2 (minimum image, the far list's predicate; the chunk's
+// image shift when it is the minimum image of every listed pair), for each
+// atom i of the cell.  As in the list sweep, the stencil's chunks are laid
+// end to end and walked in batches of 64 candidates, one per lane, each
+// batch tested against the cell's atoms in turn; accepted neighbours are
+// numbered with the ballot and their indices stored in stencil order.
+// Their (row, place, type pair, r^2) are queued in LDS and the matrix
 // elements computed 64 at a time, so the taper and the shielded Coulomb run
 // on full wavefronts.
+constexpr int QRMAXQ = 64;   // chunks of a stencil: 2 (2 reach + 1)^2 <= 50
+
 struct QRowQ {
-  int32_t k, tj;
+  int32_t i, k, p, pad;
   double r2;
 };
 
-__global__ __launch_bounds__(QB) void k_qeq_rows(const DevParams* __restrict__ P, Grid g, Lists L,
+__global__ __launch_bounds__(QB) void k_qeq_rows(const DevParams* __restrict__ P, Grid g, Lists L, int ncell,
                                                  int32_t* __restrict__ hj, double* __restrict__ hv,
                                                  int32_t* __restrict__ hcnt, int32_t w,
                                                  int32_t* __restrict__ need) {
   __shared__ QRowQ rq[QWAVES][128];
-  const int lane = threadIdx.x & 63;
-  const int64_t i = xcd_block() * QWAVES + (threadIdx.x >> 6);
-  if (i >= L.n) return;   // uniform over the wavefront
-  QRowQ* __restrict__ q = rq[threadIdx.x >> 6];
-  const double4 xi = L.xs[i];
-  const int ti = (int)xi.w;
-  const int c = L.cell_of[i];
-  const int nq = stencil_chunks(g);
-  const bool minimg = g.periodic && !g.shift_ok;
-  const double rn2 = P->rn2, iR = P->inv_r_nonb;
-  int32_t* __restrict__ rj = hj + i * (int64_t)w;
-  double* __restrict__ rv = hv + i * (int64_t)w;
+  __shared__ int q_s0[QWAVES][QRMAXQ], q_base[QWAVES][QRMAXQ + 1];
+  __shared__ double q_sh[QWAVES][QRMAXQ][3];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = (int)(xcd_block() * QWAVES + wv);
+  if (c >= ncell) return;   // uniform over the wavefront
+  const int a0 = L.cell_start[c], m = L.cell_start[c + 1] - a0;
+  if (m == 0) return;
+  QRowQ* __restrict__ q = rq[wv];
+  int* __restrict__ qs0 = q_s0[wv];
+  int* __restrict__ qb = q_base[wv];
   const unsigned long long below = lanes_below();
   auto sync_wave = [] {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   };
-  auto evaluate = [&](int m) {   // the first m queued elements, one per lane
-    if (lane < m) {
+  const bool minimg = g.periodic && !g.shift_ok;
+  const int nq = stencil_chunks(g);
+  {
+    int len = 0;
+    if (lane < nq) {
+      int s0, s1;
+      double sx, sy, sz;
+      stencil_chunk(g, L.cell_start, c, lane, s0, s1, sx, sy, sz);
+      qs0[lane] = s0;
+      len = s1 - s0;
+      q_sh[wv][lane][0] = sx;
+      q_sh[wv][lane][1] = sy;
+      q_sh[wv][lane][2] = sz;
+    }
+    const int v = wave_incl_scan(len);
+    if (lane < nq) qb[lane + 1] = v;
+    if (lane == 0) qb[0] = 0;
+  }
+  sync_wave();
+  const int nst = __builtin_amdgcn_readfirstlane(qb[nq]);
+  const double rn2 = P->rn2, iR = P->inv_r_nonb;
+  auto evaluate = [&](int mq) {   // the first mq queued elements, one per lane
+    if (lane < mq) {
       const QRowQ e = q[lane];
       if (e.k < w) {
         const double r = sqrt(e.r2);
         const double u = r * iR;
         const double u4 = (u * u) * (u * u);
         const double tap = fma(u4, fma(u, fma(u, fma(u, 20.0, -70.0), 84.0), -35.0), 1.0);
-        rv[e.k] = tap * C_ELE * rcbrt_f(fma(e.r2, r, P->pair[ti * NT + e.tj].g3));
+        hv[(int64_t)e.i * w + e.k] = tap * C_ELE * rcbrt_f(fma(e.r2, r, P->pair[e.p].g3));
       }
     }
   };
-  int cnt = 0, qn = 0;
-  for (int ch = 0; ch < nq; ++ch) {
-    int s0, s1;
-    double sx, sy, sz;
-    stencil_chunk(g, L.cell_start, c, ch, s0, s1, sx, sy, sz);
-    for (int j0 = s0; j0 < s1; j0 += 64) {
-      const int j = j0 + lane;
-      bool ok = j < s1 && j != (int)i;
-      double r2 = 0.0;
-      int tj = 0;
-      if (ok) {
-        const double4 xj = L.xs[j];
+  int qn = 0;   // queued elements (uniform)
+  for (int ig = 0; ig < m; ig += 64) {   // the cell's atoms, 64 at a time, one per lane
+    const int mi = m - ig < 64 ? m - ig : 64;
+    int tmine = 0;
+    if (lane < mi) tmine = (int)L.xs[a0 + ig + lane].w;
+    int kc = 0;   // lane l: row length of the cell's atom ig + l
+    int cq = 0;   // this lane's chunk
+    for (int b0 = 0; b0 < nst; b0 += 64) {
+      const int slot = b0 + lane;
+      const bool valid = slot < nst;
+      int sj = 0;
+      double sx = 0.0, sy = 0.0, sz = 0.0;
+      if (valid) {
+        while (qb[cq + 1] <= slot) ++cq;
+        sj = qs0[cq] + (slot - qb[cq]);
+        sx = q_sh[wv][cq][0];
+        sy = q_sh[wv][cq][1];
+        sz = q_sh[wv][cq][2];
+      }
+      // lanes past the stencil's end hold NaN, so every distance test fails there
+      double4 xj = make_double4(__builtin_nan(""), 0.0, 0.0, 0.0);
+      if (valid) xj = L.xs[sj];
+      const int tj = (int)xj.w;
+      for (int l = 0; l < mi; ++l) {
+        const int i = a0 + ig + l;
+        const double4 xi = L.xs[i];   // uniform: a scalar load
         double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
         if (minimg) {
           dx = min_image(dx, g.L[0], g.invL[0]);
@@ -146,35 +184,38 @@ __global__ __launch_bounds__(QB) void k_qeq_rows(const DevParams* __restrict__ P
           dy -= sy;
           dz -= sz;
         }
-        r2 = r2_of(dx, dy, dz);
-        tj = (int)xj.w;
-        ok = r2 <= rn2;
+        const double r2 = r2_of(dx, dy, dz);
+        const bool ok = r2 <= rn2 && sj != i;
+        const int pij = readlane_i(tmine, l) * NT + tj;
+        const unsigned long long mk = ballot(ok);
+        if (mk) {
+          const int k0 = readlane_i(kc, l);
+          if (ok) {
+            const int pos = __popcll(mk & below);
+            const int k = k0 + pos;
+            if (k < w) hj[(int64_t)i * w + k] = sj;
+            q[qn + pos] = QRowQ{i, k, pij, 0, r2};
+          }
+          kc = writelane_i(k0 + __popcll(mk), l, kc);
+          qn += __popcll(mk);
+          if (qn >= 64) {
+            sync_wave();
+            evaluate(64);
+            sync_wave();
+            if (lane < qn - 64) q[lane] = q[64 + lane];
+            sync_wave();
+            qn -= 64;
+          }
+        }
       }
-      const unsigned long long m = ballot(ok);
-      if (ok) {
-        const int pos = __popcll(m & below);
-        const int k = cnt + pos;
-        if (k < w) rj[k] = j;
-        q[qn + pos] = QRowQ{k, tj, r2};
-      }
-      cnt += __popcll(m);
-      qn += __popcll(m);
-      if (qn >= 64) {
-        sync_wave();
-        evaluate(64);
-        sync_wave();
-        if (lane < qn - 64) q[lane] = q[64 + lane];
-        sync_wave();
-        qn -= 64;
-      }
+    }
+    if (lane < mi) {
+      hcnt[a0 + ig + lane] = kc;
+      if (kc > w) atomicMax(need, kc);
     }
   }
   sync_wave();
   evaluate(qn);
-  if (lane == 0) {
-    hcnt[i] = cnt;
-    if (cnt > w) atomicMax(need, cnt);
-  }
 }
 
 // y = H x for the pair of vectors (s, t), one wavefront per row; with `set`,
@@ -469,6 +510,9 @@ int reaxff_qeq(reaxff_ctx* c, int64_t n, const reaxff_qeq_params* qpar, double t
     Q.w = (int32_t)std::min<double>((double)std::max<int64_t>(n, 1), 1.3 * rho * 4.18879 * r * r * r + 64.0);
   }
   const unsigned gw = xcd_grid((n + QWAVES - 1) / QWAVES), ga = xcd_grid((n + QB - 1) / QB);
+  const int64_t ncell = (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
+  if (stencil_chunks(g) > QRMAXQ) return qfail(c, REAXFF_ERR_STATE, "reaxff_qeq: stencil beyond the chunk table");
+  const unsigned gc = xcd_grid((unsigned)((ncell + QWAVES - 1) / QWAVES));
   for (int attempt = 0;; ++attempt) {
     if (qgrow(c, Q.hj, Q.cap_rows, n * (int64_t)Q.w)) return REAXFF_ERR_HIP;
     int64_t capv = Q.cap_rowsv;
@@ -479,7 +523,8 @@ int reaxff_qeq(reaxff_ctx* c, int64_t n, const reaxff_qeq_params* qpar, double t
     }
     QHIP(c, hipMemsetAsync(Q.need, 0, sizeof(int32_t), st));
     c->prof.begin(KID_QEQ_ROWS, st);
-    hipLaunchKernelGGL(k_qeq_rows, dim3(gw), dim3(QB), 0, st, c->dp, g, L, Q.hj, Q.hv, Q.hcnt, Q.w, Q.need);
+    hipLaunchKernelGGL(k_qeq_rows, dim3(gc), dim3(QB), 0, st, c->dp, g, L, (int)ncell, Q.hj, Q.hv, Q.hcnt, Q.w,
+                       Q.need);
     c->prof.end(st);
     int32_t need = 0;
     QHIP(c, hipMemcpyAsync(&need, Q.need, sizeof(int32_t), hipMemcpyDeviceToHost, st));
