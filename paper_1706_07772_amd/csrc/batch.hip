@@ -592,9 +592,18 @@ __device__ __noinline__ void st_nonbonded(int n) {
   wave_acc(eq, &b_acc[E_COUL]);
 }
 
-// torsions about the bonds each atom owns (lower index), with atomic adds
+// torsions about the bonds each atom owns (lower index), with atomic adds.
+// Each lane walks the candidates (j-k, j-i, k-l) of its atom j one per step
+// (the central bond, then j's other bonds, then k's), all lanes stepping
+// together; the candidates that pass the thresholds are queued in LDS and
+// evaluated 64 at a time, so the torsion term runs on full wavefronts.
+struct TorQ {
+  int32_t u, a, b, pad;
+};
+
 template <int BSZ>
 __device__ __noinline__ void st_torsions(int n) {
+  __shared__ TorQ tq[BSZ / 64][128];
   const BatchArgs A = uni_copy(b_args);
   n = uni(n);
   Lists L;
@@ -602,31 +611,76 @@ __device__ __noinline__ void st_torsions(int n) {
   views(A, L, W);
   const DevParams* __restrict__ P = A.P;
   const double thb = P->thb_cut;
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  TorQ* __restrict__ q = tq[threadIdx.x >> 6];
+  auto sync_wave = [] {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
   double etor = 0.0, econj = 0.0, ntor = 0.0;
-  for (int j = threadIdx.x; j < n; j += BSZ) {
-    const int e0 = b_off[j], e1 = b_off[j + 1];
-    for (int u = e0; u < e1; ++u) {
-      const int k = L.bond_j[u];
-      const double bu = W.bo[u].x;
-      if (!(k > j && bu > thb)) continue;
-      const int f0 = b_off[k], f1 = b_off[k + 1];
-      for (int a = e0; a < e1; ++a) {
-        if (a == u) continue;
-        const double ba = W.bo[a].x;
-        if (!(ba > thb)) continue;
-        const int i = L.bond_j[a];
-        for (int b = f0; b < f1; ++b) {
-          const int l = L.bond_j[b];
-          if (l == j || l == i) continue;
-          const double bb = W.bo[b].x;
-          if (!(bb > thb)) continue;
-          if (!(ba * bu * bb > thb)) continue;
-          torsion_eval(P, L, W, u, a, b, etor, econj);
-          ntor += 1.0;
+  auto evaluate = [&](int m) {   // the first m queued torsions, one per lane
+    if (lane < m) {
+      const TorQ e = q[lane];
+      torsion_eval(P, L, W, e.u, e.a, e.b, etor, econj);
+      ntor += 1.0;
+    }
+  };
+  int qn = 0;   // queued torsions (uniform)
+  for (int jb = threadIdx.x - lane; jb < n; jb += BSZ) {
+    const int j = jb + lane;
+    const int e0 = j < n ? b_off[j] : 0, e1 = j < n ? b_off[j + 1] : 0;
+    // the next candidate is (u, a, b); a = e1 makes the first step look for
+    // the first central bond
+    int u = e0 - 1, a = e1, bb = 0, f0 = 0, f1 = 0;
+    double bu = 0.0;
+    bool on = j < n && e0 < e1;
+    while (ballot(on)) {
+      bool cand = false;
+      if (on) {
+        ++bb;
+        if (bb >= f1) {
+          ++a;
+          bb = f0;
         }
+        if (a >= e1) {   // next central bond j-k with k > j and BO > thb
+          ++u;
+          while (u < e1 && !(L.bond_j[u] > j && W.bo[u].x > thb)) ++u;
+          if (u < e1) {
+            const int k = L.bond_j[u];
+            bu = W.bo[u].x;
+            f0 = b_off[k];
+            f1 = b_off[k + 1];
+            a = e0;
+            bb = f0;
+          } else {
+            on = false;
+          }
+        }
+        if (on && a != u) {
+          const double ba = W.bo[a].x;
+          const int i = L.bond_j[a];
+          const int l = L.bond_j[bb];
+          const double bl = W.bo[bb].x;
+          cand = ba > thb && l != j && l != i && bl > thb && ba * bu * bl > thb;
+        }
+      }
+      const unsigned long long m = ballot(cand);
+      if (cand) q[qn + __popcll(m & below)] = TorQ{u, a, bb, 0};
+      qn += __popcll(m);
+      if (qn >= 64) {
+        sync_wave();
+        evaluate(64);
+        sync_wave();
+        if (lane < qn - 64) q[lane] = q[64 + lane];
+        sync_wave();
+        qn -= 64;
       }
     }
   }
+  sync_wave();
+  evaluate(qn);
   wave_acc(etor, &b_acc[E_TOR]);
   wave_acc(econj, &b_acc[E_CONJ]);
   wave_acc(ntor, &b_acc[NTERMS + 1]);
