@@ -141,6 +141,7 @@ __shared__ NbP b_nb[NT * NT];
 __shared__ HbP b_hb[NT * NT * NT];
 __shared__ double b_reach2[NT * NT];  // min(bond reach, r_bond)^2 of each type pair
 __shared__ int32_t b_alist[BNMAX];    // the cluster's acceptors, in index order
+__shared__ int32_t b_aoff[BNMAX + 1]; // angle counts per centre, then their offsets
 __shared__ int32_t b_nacc;
 __shared__ double b_acc[NRED];        // per-cluster energies and counts
 __shared__ int32_t b_next;
@@ -551,6 +552,168 @@ __device__ __noinline__ void st_angles(int n) {
   wave_acc(nang, &b_acc[NTERMS + 0]);
 }
 
+// Valence angles in three passes, when the cluster's angles fit in the
+// storage of the entries' correction adjoints (written only later, by the
+// backward pass): count each centre's angles (b_aoff), evaluate them 64 at a
+// time (every lane walks its centre's pairs one per step, all lanes together,
+// and the passing pairs are queued), each angle's adjoints stored at its
+// centre's offset, then one thread per centre adds its angles' adjoints to
+// its own entries in the order st_angles would, so no atomics are needed and
+// the sums are deterministic.
+constexpr int ANG_STAGE = 3;   // double4 records per staged angle
+
+template <int BSZ>
+__device__ __noinline__ void st_angle_count(int n) {
+  const BatchArgs A = uni_copy(b_args);
+  n = uni(n);
+  Lists L;
+  Work W;
+  views(A, L, W);
+  const double thb = A.P->thb_cut, thb2 = A.P->thb_cutsq;
+  for (int j = threadIdx.x; j < n; j += BSZ) {
+    const int e0 = b_off[j], e1 = b_off[j + 1];
+    int cnt = 0;
+    for (int u = e0; u < e1; ++u) {
+      const double bu = W.bo[u].x;
+      if (!(bu - thb > 0.0)) continue;
+      for (int v = u + 1; v < e1; ++v) {
+        const double bv = W.bo[v].x;
+        cnt += (bv - thb > 0.0 && bu * bv > thb2) ? 1 : 0;
+      }
+    }
+    b_aoff[j + 1] = cnt;
+  }
+  if (threadIdx.x == 0) b_aoff[0] = 0;
+}
+
+struct AngQ {
+  int32_t u, v, slot, pad;
+};
+
+template <int BSZ>
+__device__ __noinline__ void st_angle_eval(int n) {
+  __shared__ AngQ aq[BSZ / 64][128];
+  const BatchArgs A = uni_copy(b_args);
+  n = uni(n);
+  Lists L;
+  Work W;
+  views(A, L, W);
+  const DevParams* __restrict__ P = A.P;
+  const double thb = P->thb_cut, thb2 = P->thb_cutsq;
+  double4* __restrict__ stage = W.gup;
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  AngQ* __restrict__ q = aq[threadIdx.x >> 6];
+  auto sync_wave = [] {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+  double ev = 0.0, ep = 0.0, ec = 0.0, nang = 0.0;
+  auto evaluate = [&](int m) {   // the first m queued angles, one per lane
+    if (lane < m) {
+      const AngQ e = q[lane];
+      const AngOut o = angle_eval(P, L, W, e.u, e.v);
+      ev += o.ev;
+      ep += o.ep;
+      ec += o.ec;
+      nang += 1.0;
+      double4* __restrict__ r = stage + (int64_t)e.slot * ANG_STAGE;
+      r[0] = make_double4(o.gu[0], o.gu[1], o.gu[2], o.gu[3]);
+      r[1] = make_double4(o.gu[4], o.gv[0], o.gv[1], o.gv[2]);
+      r[2] = make_double4(o.gv[3], o.gv[4], o.gS, o.gSBO2);
+    }
+  };
+  int qn = 0;   // queued angles (uniform)
+  for (int jb = threadIdx.x - lane; jb < n; jb += BSZ) {
+    const int j = jb + lane;
+    const int e0 = j < n ? b_off[j] : 0, e1 = j < n ? b_off[j + 1] : 0;
+    int slot = j < n ? b_aoff[j] : 0;
+    // the next pair is (u, v); v = e1 makes the first step look for the first u
+    int u = e0 - 1, v = e1;
+    double bu = 0.0;
+    bool on = j < n && e1 - e0 > 1;
+    while (ballot(on)) {
+      bool cand = false;
+      if (on) {
+        ++v;
+        if (v >= e1) {   // next u with BO - thb > 0
+          ++u;
+          while (u < e1 && !(W.bo[u].x - thb > 0.0)) ++u;
+          if (u + 1 < e1) {
+            bu = W.bo[u].x;
+            v = u + 1;
+          } else {
+            on = false;
+          }
+        }
+        if (on) {
+          const double bv = W.bo[v].x;
+          cand = bv - thb > 0.0 && bu * bv > thb2;
+        }
+      }
+      const unsigned long long m = ballot(cand);
+      if (cand) q[qn + __popcll(m & below)] = AngQ{u, v, slot, 0};
+      slot += cand ? 1 : 0;
+      qn += __popcll(m);
+      if (qn >= 64) {
+        sync_wave();
+        evaluate(64);
+        sync_wave();
+        if (lane < qn - 64) q[lane] = q[64 + lane];
+        sync_wave();
+        qn -= 64;
+      }
+    }
+  }
+  sync_wave();
+  evaluate(qn);
+  wave_acc(ev, &b_acc[E_VAL]);
+  wave_acc(ep, &b_acc[E_PEN]);
+  wave_acc(ec, &b_acc[E_COA]);
+  wave_acc(nang, &b_acc[NTERMS + 0]);
+}
+
+template <int BSZ>
+__device__ __noinline__ void st_angle_gather(int n) {
+  const BatchArgs A = uni_copy(b_args);
+  n = uni(n);
+  Lists L;
+  Work W;
+  views(A, L, W);
+  const double thb = A.P->thb_cut, thb2 = A.P->thb_cutsq;
+  const double4* __restrict__ stage = W.gup;
+  for (int j = threadIdx.x; j < n; j += BSZ) {
+    const int e0 = b_off[j], e1 = b_off[j + 1];
+    int slot = b_aoff[j];
+    double gS = 0.0, gSBO2 = 0.0;
+    for (int u = e0; u < e1; ++u) {
+      const double bu = W.bo[u].x;
+      if (!(bu - thb > 0.0)) continue;
+      for (int v = u + 1; v < e1; ++v) {
+        const double bv = W.bo[v].x;
+        if (!(bv - thb > 0.0 && bu * bv > thb2)) continue;
+        const double4* __restrict__ r = stage + (int64_t)slot * ANG_STAGE;
+        ++slot;
+        const double4 r0 = r[0], r1 = r[1], r2 = r[2];
+        double4 gu = W.gvec[u], gv = W.gvec[v];
+        gu.x += r0.x; gu.y += r0.y; gu.z += r0.z;
+        gv.x += r1.y; gv.y += r1.z; gv.z += r1.w;
+        W.gvec[u] = gu;
+        W.gvec[v] = gv;
+        W.gbo[u].x += r0.w;
+        W.gbo[u].w += r1.x;
+        W.gbo[v].x += r2.x;
+        W.gbo[v].w += r2.y;
+        gS += r2.z;
+        gSBO2 += r2.w;
+      }
+    }
+    W.gS[j] += gS;
+    W.gSBO[j] = gSBO2;
+  }
+}
+
 // nonbonded: one wavefront per atom i, one partner j > i per lane, so every
 // unordered pair is evaluated once; the partner's force goes to the LDS force
 // array with atomic adds, the atom's own sum is reduced over the wavefront
@@ -874,7 +1037,17 @@ __global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(2))) void k
     st_atom_energy<BSZ>(n);
     st_nonbonded<BSZ>(n);
     __syncthreads();
-    st_angles<BSZ>(n);
+    st_angle_count<BSZ>(n);
+    __syncthreads();
+    wave_scan_inplace(b_aoff, n);
+    __syncthreads();
+    if ((int64_t)b_aoff[n] * ANG_STAGE <= A.ecap) {   // staged in the correction adjoints' storage
+      st_angle_eval<BSZ>(n);
+      __syncthreads();
+      st_angle_gather<BSZ>(n);
+    } else {
+      st_angles<BSZ>(n);
+    }
     __syncthreads();
     st_torsions<BSZ>(n);
     st_hbonds<BSZ>(n);
