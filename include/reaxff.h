@@ -248,6 +248,16 @@ int reaxff_profile_read(reaxff_ctx* ctx, int32_t max, double* ms, int64_t* launc
  * REAXFF_ERR_ARG for a null context. */
 int reaxff_set_overlap(reaxff_ctx* ctx, int32_t enable);
 
+/* Runs of the half nonbonded evaluation [host]: Algorithm 2 visits each
+ * far-list pair once (Section 3.1); the library evaluates the pairs of up to
+ * run_max consecutive cells of a grid column in one workgroup, which holds the
+ * neighbourhood common to those cells in its local memory once, and shortens
+ * the runs when the atoms are too dense for that copy (the build then sweeps
+ * again).  1 <= run_max <= 16; default 8.  Takes effect at the next build;
+ * results are the same up to the order of floating-point additions.  Returns
+ * REAXFF_OK, or REAXFF_ERR_ARG for a null context or run_max out of range. */
+int reaxff_set_nb_run(reaxff_ctx* ctx, int32_t run_max);
+
 /* ---- Charge equilibration (Section 3.3, QEq) ------------------------------
  *
  * The charges that minimise the electrostatic energy

@@ -154,6 +154,7 @@ def load_library():
     lib.reaxff_forces_masked.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, ctypes.POINTER(i64), vp]
     lib.reaxff_profile.argtypes = [vp, i32]
     lib.reaxff_set_overlap.argtypes = [vp, i32]
+    lib.reaxff_set_nb_run.argtypes = [vp, i32]
     lib.reaxff_profile_read.argtypes = [vp, i32, vp, vp, vp]
     lib.reaxff_last_error.restype = ctypes.c_char_p
     lib.reaxff_last_error.argtypes = [vp]
@@ -334,6 +335,10 @@ class ReaxFF:
     def set_overlap(self, enable: bool):
         """Run the nonbonded term concurrently with the bonded terms (default) or in order."""
         self._check(self._lib.reaxff_set_overlap(self._h, 1 if enable else 0))
+
+    def set_nb_run(self, run_max: int):
+        """Longest run of cells the half nonbonded evaluation takes per workgroup (1..16)."""
+        self._check(self._lib.reaxff_set_nb_run(self._h, int(run_max)))
 
     def qeq(self, n: int, qparams, tol: float = 1e-6, maxit: int = 500, guess: bool = True,
             q=None, want_st: bool = False, device=None, check: bool = True):

@@ -150,6 +150,7 @@ void make_grid(Grid& g, bool periodic, const double* box, const double lo[3], co
     g.full[k] = nc < 2 * reach + 1 ? 1 : 0;
     g.span[k] = nc < 2 * reach + 1 ? nc : 2 * reach + 1;
   }
+  g.run = 1;
 }
 
 int alloc_atoms(reaxff_ctx* c, int64_t n) {
@@ -531,6 +532,18 @@ int build_lists_impl(reaxff_ctx* c, int64_t n, const double* pos, const int32_t*
     };
     c->L.far_upper = c->L.far_slots && !c->upper_off && !c->grid.full[0] && !c->grid.full[1] &&
                      !c->grid.full[2];
+    // runs of cells for the half evaluation: the longest (up to 8 cells)
+    // whose upper window, at the mean density, fills at most 80% of the
+    // kernel's LDS copy; a run needs run + 2 reach <= nc[2] in a periodic box
+    if (c->L.far_upper && n > 0) {
+      const int R = reach, C = 2 * R * R + 2 * R;   // upper columns besides the centre's
+      const double per_cell = (double)n / (double)ncell;
+      const double room = 0.8 * NB_HALF_CAP / std::max(per_cell, 1e-3) - 2.0 * R * C - R;
+      int K = (int)std::floor(room / (C + 1));
+      K = std::min(K, c->nb_run_max);
+      K = std::min(K, c->periodic ? c->grid.nc[2] - 2 * R : c->grid.nc[2]);
+      c->grid.run = std::max(K, 1);
+    }
     if (c->L.far_w == 0) c->L.far_w = c->L.far_upper ? est(r_list) / 2 + 32 : est(r_list);
     if (c->L.hb_w == 0) c->L.hb_w = est(c->cut.r_hb + c->skin);
     if (c->L.ha_w == 0) c->L.ha_w = est(c->cut.r_hb + c->skin);
@@ -604,15 +617,21 @@ int build_lists_impl(reaxff_ctx* c, int64_t n, const double* pos, const int32_t*
     widen(c->sc.bond_w, need[2]);
     widen(c->L.hb_w, need[3]);
     widen(c->L.ha_w, need[4]);
-    // upper-only rows serve the half evaluation alone; without it, sweep
-    // again with full rows (and keep them for later builds)
+    // an upper window beyond the LDS copy: shorter runs; upper-only rows
+    // serve the half evaluation alone, so without it (one cell per run does
+    // not fit either) sweep again with full rows and keep them for later
+    // builds
     if (c->L.far_upper && n > 0 && !(need[5] > 0 && need[5] <= NB_HALF_CAP)) {
-      c->upper_off = true;
-      c->L.far_upper = 0;
+      if (c->grid.run > 1) {
+        c->grid.run /= 2;
+      } else {
+        c->upper_off = true;
+        c->L.far_upper = 0;
+      }
       again = true;
     }
     if (!again) break;
-    if (attempt >= 5) return fail(c, REAXFF_ERR_CAPACITY, "list widths did not converge");
+    if (attempt >= 8) return fail(c, REAXFF_ERR_CAPACITY, "list widths did not converge");
   }
   c->L.nfar = c->L.far_upper ? th[0] : th[0] / 2;
   // half nonbonded evaluation when every cell's upper stencil fits in LDS
@@ -625,11 +644,12 @@ int build_lists_impl(reaxff_ctx* c, int64_t n, const double* pos, const int32_t*
   }
   c->L.nb_half = c->L.far_slots && n > 0 && need[5] > 0 && need[5] <= NB_HALF_CAP;
   if (c->L.nb_half) {
+    const int64_t nrun = (int64_t)c->grid.nc[0] * c->grid.nc[1] * ((c->grid.nc[2] + c->grid.run - 1) / c->grid.run);
     int64_t t = c->W.cap_nbpart;
-    if (grow(c, c->W.nbpart, t, ncell * 3 * (int64_t)NB_HALF_CAP, 1.0)) return REAXFF_ERR_HIP;
+    if (grow(c, c->W.nbpart, t, nrun * 3 * (int64_t)NB_HALF_CAP, 1.0)) return REAXFF_ERR_HIP;
     c->W.cap_nbpart = t;
     t = c->W.cap_nbtab;
-    if (grow(c, c->W.nbtab, t, ncell * (int64_t)NB_QMAX, 1.0)) return REAXFF_ERR_HIP;
+    if (grow(c, c->W.nbtab, t, nrun * (int64_t)NB_QMAX, 1.0)) return REAXFF_ERR_HIP;
     c->W.cap_nbtab = t;
   }
   c->L.nbond = t32[0];
@@ -743,6 +763,13 @@ int reaxff_export_lists(reaxff_ctx* c, int32_t* far, int32_t* bonds, int32_t* hb
 int reaxff_set_overlap(reaxff_ctx* c, int32_t enable) {
   if (!c) return REAXFF_ERR_ARG;
   c->overlap = enable != 0;
+  return REAXFF_OK;
+}
+
+int reaxff_set_nb_run(reaxff_ctx* c, int32_t run_max) {
+  if (!c) return REAXFF_ERR_ARG;
+  if (run_max < 1 || run_max > 16) return fail(c, REAXFF_ERR_ARG, "reaxff_set_nb_run: run_max must lie in 1..16");
+  c->nb_run_max = run_max;
   return REAXFF_OK;
 }
 

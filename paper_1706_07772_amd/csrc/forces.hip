@@ -782,23 +782,34 @@ __global__ __launch_bounds__(NBC_BS) void k_nonbonded(const DevParams* __restric
 //     dimension covered whole, the neighbours of atom i at a larger slot than
 //     i's own are exactly those at a lexicographically positive cell offset
 //     (or after i in its own cell); of every pair, exactly one atom sees the
-//     other there.  The workgroup of cell c evaluates each such pair once,
-//     for the row suffix [far_lo[i], cnt_i) of each of its atoms, with only
-//     the upper stencil (from the cell's first atom on) in LDS.  Both atoms'
+//     other there.  Slots number the window of i's run (window_chunk, the
+//     stencils of the run's Grid::run cells of one column laid together), so
+//     the workgroup of a run stages the run's upper window once (from the
+//     run's first atom on) and evaluates each such pair once, for the row
+//     suffix [far_lo[i], cnt_i) of each atom of the run's cells.  Both atoms'
 //     forces are added to LDS accumulators on the staged slots (the centre's
-//     through a wavefront sum when the wavefront moves on, the partner's per
-//     pair); the accumulators are stored, not added, to the cell's partial
-//     array (x, y, z of a slot contiguous), and k_nb_reduce sums the partial
-//     arrays of the 63 cells whose upper stencil holds an atom.  Energies take each pair once.
-//     In a periodic box whose chunk shifts are the minimum images, the
-//     staged positions carry their chunk's shift, so a displacement is a
-//     plain difference; the centre sums use DPP row moves, not LDS.
+//     through a half-wavefront sum when the half moves on, the partner's per
+//     pair); the accumulators are stored, not added, to the run's partial
+//     array (x, y, z of a slot contiguous), and k_nb_reduce sums, for each
+//     atom, the partial arrays of the runs whose upper window holds it.
+//     Energies take each pair once.  In a periodic box whose chunk shifts are
+//     the minimum images, the staged positions carry their chunk's shift, so
+//     a displacement is a plain difference; the centre sums use DPP row
+//     moves, not LDS.
 // ---------------------------------------------------------------------------
-constexpr int NBH_BS = 512, NBH_WAVES = NBH_BS / 64;
+constexpr int NBH_BS = 1024, NBH_WAVES = NBH_BS / 64;
 
-__global__ __launch_bounds__(NBH_BS) void k_nonbonded_half(const DevParams* __restrict__ P, Grid g, Lists L,
-                                                           Work W, int ncell, int per_xcd,
-                                                           double* __restrict__ energies) {
+// runs of the grid and the cells of run r: first cell, count
+__host__ __device__ __forceinline__ int run_rows(const Grid& g) { return (g.nc[2] + g.run - 1) / g.run; }
+__device__ __forceinline__ void run_cells(const Grid& g, int r, int& cfirst, int& nk) {
+  const int nrz = run_rows(g), rz = r % nrz, col = r / nrz;
+  cfirst = col * g.nc[2] + rz * g.run;
+  nk = g.nc[2] - rz * g.run < g.run ? g.nc[2] - rz * g.run : g.run;
+}
+
+__global__ __launch_bounds__(NBH_BS) __attribute__((amdgpu_waves_per_eu(4))) void k_nonbonded_half(
+    const DevParams* __restrict__ P, Grid g, Lists L, Work W, int nrun, int per_xcd,
+    double* __restrict__ energies) {
   __shared__ NbP sp[NT * NT];
   __shared__ double sxx[NB_HALF_CAP], sxy[NB_HALF_CAP], sxz[NB_HALF_CAP], sxq[NB_HALF_CAP];
   __shared__ double fax[NB_HALF_CAP], fay[NB_HALF_CAP], faz[NB_HALF_CAP];
@@ -809,11 +820,13 @@ __global__ __launch_bounds__(NBH_BS) void k_nonbonded_half(const DevParams* __re
   __shared__ double ixx[NBC_MG], ixy[NBC_MG], ixz[NBC_MG], iqq[NBC_MG];
   __shared__ int ity[NBC_MG], icnt[NBC_MG], ilo[NBC_MG];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int c = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
-  if (c >= ncell) return;
-  const int a0 = L.cell_start[c], m = L.cell_start[c + 1] - a0;
-  if (m == 0) {   // no pairs; the reduce skips empty cells
-    if (tid == 0) W.nbe[c] = make_double2(0.0, 0.0);
+  const int r = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+  if (r >= nrun) return;
+  int c, nk;
+  run_cells(g, r, c, nk);
+  const int a0 = L.cell_start[c], m = L.cell_start[c + nk] - a0;
+  if (m == 0) {   // no pairs; the reduce skips empty runs
+    if (tid == 0) W.nbe[r] = make_double2(0.0, 0.0);
     return;
   }
   if (tid < NT * NT) sp[tid] = nb_params(P->pair[tid]);
@@ -825,7 +838,7 @@ __global__ __launch_bounds__(NBH_BS) void k_nonbonded_half(const DevParams* __re
   if (tid < nq) {
     int s0, s1;
     double sx, sy, sz;
-    stencil_chunk(g, L.cell_start, c, tid, s0, s1, sx, sy, sz);
+    window_chunk(g, L.cell_start, c, tid, s0, s1, sx, sy, sz);
     q_s0[tid] = s0;
     q_base[tid + 1] = s1 - s0;
     q_sh[tid][0] = shifted ? sx : 0.0;
@@ -840,16 +853,16 @@ __global__ __launch_bounds__(NBH_BS) void k_nonbonded_half(const DevParams* __re
   }
   __syncthreads();
   const int nst = q_base[nq];
-  // the centre cell's own chunk: its column is the middle one, and its
-  // unwrapped z range comes second when the column wraps below the cell
-  const int c2 = c % g.nc[2];
+  // the run's own chunk: its column is the middle one, and its unwrapped z
+  // range comes second when the window wraps below the run
+  const int z0 = c % g.nc[2];
   const int col_own = g.reach * g.span[1] + g.reach;
-  const bool wrap_first = g.periodic && c2 - g.reach < 0;
+  const bool wrap_first = g.periodic && z0 - g.reach < 0;
   const int q_own = 2 * col_own + (wrap_first ? 1 : 0);
-  const int S0 = q_base[q_own] + (a0 - q_s0[q_own]);   // slot of the cell's first atom
+  const int S0 = q_base[q_own] + (a0 - q_s0[q_own]);   // slot of the run's first atom
   const int nup = nst - S0;                            // <= NB_HALF_CAP (checked by the sweep)
   // chunk bases relative to S0, for the reduce
-  if (tid <= nq) W.nbtab[(int64_t)c * NB_QMAX + tid] = q_base[tid] - S0;
+  if (tid <= nq) W.nbtab[(int64_t)r * NB_QMAX + tid] = q_base[tid] - S0;
   for (int t0 = 0; t0 < nup; t0 += 2 * NBH_BS) {
     int idx[2], qq[2];
     double4 v[2];
@@ -918,23 +931,58 @@ __global__ __launch_bounds__(NBH_BS) void k_nonbonded_half(const DevParams* __re
     const int u0 = U * wu / NBH_WAVES, u1 = U * (wu + 1) / NBH_WAVES;
     if (u0 < u1) {
       const int hh = lane >> 5, sl = lane & 31;
-      auto locate = [&](int u, int& a) {
-        while (upre[a + 1] <= u) ++a;
+      // the row of centre a (uniform over the half) kept in registers: units
+      // [ua, un) are its, starting at entry lo, cn entries in all
+      int a = 0, ua = 0, un = 0, lo = 0, cn = 0;
+      const int32_t* __restrict__ rowp = L.far_j;
+      auto enter = [&](int na) {
+        a = na;
+        ua = upre[a];
+        un = upre[a + 1];
+        lo = ilo[a];
+        cn = icnt[a];
+        rowp = L.far_j + (int64_t)(a0 + g0 + a) * L.far_w;
       };
-      auto fetch = [&](int u, int a) {
-        const int k = ilo[a] + ((u - upre[a]) << 5) + sl;
-        const int32_t* __restrict__ row = L.far_j + (int64_t)(a0 + g0 + a) * L.far_w;
-        const int t = k < icnt[a] ? row[k] - S0 : -1;
-        return (unsigned)t < (unsigned)nup ? t : -1;   // always in range for a consistent list
+      // the raw row entry of this lane in unit u (0 when u is past the end or
+      // the entry past the row); ok says whether it is an entry
+      auto fetch = [&](int u, bool& ok) {
+        ok = false;
+        if (u >= u1) return 0;
+        if (un <= u) {
+          int na = a + 1;
+          while (upre[na + 1] <= u) ++na;
+          enter(na);
+        }
+        const int k = lo + ((u - ua) << 5) + sl;
+        ok = k < cn;
+        return ok ? rowp[k] : 0;
       };
-      int uh = u0 + hh;   // this half's unit
-      int a = last_le(upre, mg, uh < u1 ? uh : u1 - 1);
-      int slot = -1;
-      if (uh < u1) {
-        locate(uh, a);
-        slot = fetch(uh, a);
+      auto staged = [&](int raw, bool ok) {   // always in range for a consistent list
+        const int t = raw - S0;
+        return ok && (unsigned)t < (unsigned)nup ? t : -1;
+      };
+      // three units in flight per half: this iteration's (its partner's
+      // staged data loaded), the next one's (row entry loaded) and the one
+      // after, whose row entry is fetched during this iteration's pair
+      const int uh = u0 + hh;
+      enter(last_le(upre, mg, uh < u1 ? uh : u1 - 1));
+      bool ok0, ok1;
+      const int r0 = fetch(uh, ok0);
+      const int acur0 = a;
+      int r1 = fetch(uh + 2, ok1);
+      int anext = a;
+      int tnow = staged(r0, ok0), anow = acur0;
+      double jx, jy, jz, jq;
+      int jt;
+      {
+        const int t = tnow >= 0 ? tnow : 0;
+        jx = sxx[t];
+        jy = sxy[t];
+        jz = sxz[t];
+        jq = sxq[t];
+        jt = sty[t];
       }
-      int cur = a;
+      int cur = anow;
       double xix = ixx[cur], xiy = ixy[cur], xiz = ixz[cur], qi = iqq[cur];
       const NbP* __restrict__ spi = sp + ity[cur] * NT;
       double fx = 0.0, fy = 0.0, fz = 0.0;
@@ -951,12 +999,21 @@ __global__ __launch_bounds__(NBH_BS) void k_nonbonded_half(const DevParams* __re
         fx = fy = fz = 0.0;
       };
       for (int ub = u0; ub < u1; ub += 2) {
-        const int tnow = slot, anow = a;
-        const int unext = ub + 2 + hh;
-        slot = -1;
-        if (unext < u1) {
-          locate(unext, a);
-          slot = fetch(unext, a);
+        // the unit after next: its row entry is loaded during this pair
+        bool ok2;
+        const int r2n = fetch(ub + 4 + hh, ok2);
+        const int aafter = a;
+        // the next unit: its partner's staged data is loaded during this pair
+        const int tnext = staged(r1, ok1);
+        double nx, ny, nz, nq;
+        int nt;
+        {
+          const int t = tnext >= 0 ? tnext : 0;
+          nx = sxx[t];
+          ny = sxy[t];
+          nz = sxz[t];
+          nq = sxq[t];
+          nt = sty[t];
         }
         if (anow != cur) {
           flush();
@@ -968,38 +1025,49 @@ __global__ __launch_bounds__(NBH_BS) void k_nonbonded_half(const DevParams* __re
           spi = sp + ity[cur] * NT;
         }
         if (tnow >= 0) {
-          double dx = sxx[tnow] - xix, dy = sxy[tnow] - xiy, dz = sxz[tnow] - xiz;
+          double dx = jx - xix, dy = jy - xiy, dz = jz - xiz;
           if (minimg) {
             dx = min_image(dx, g.L[0], g.invL[0]);
             dy = min_image(dy, g.L[1], g.invL[1]);
             dz = min_image(dz, g.L[2], g.invL[2]);
           }
-          const double r2 = dx * dx + dy * dy + dz * dz;
-          if (L.cut_check && r2 > rn2c) continue;   // a skin entry beyond the cutoff
-          const NbOut o = nb_pair(spi[sty[tnow]], iR, pv, ipv, qi * sxq[tnow], r2);
-          evdw += o.ev;
-          ecoul += o.eq;
-          const double px = o.f * dx, py = o.f * dy, pz = o.f * dz;
-          fx += px;
-          fy += py;
-          fz += pz;
-          atomicAdd(&fax[tnow], -px);
-          atomicAdd(&fay[tnow], -py);
-          atomicAdd(&faz[tnow], -pz);
+          const double rr = dx * dx + dy * dy + dz * dz;
+          if (!(L.cut_check && rr > rn2c)) {   // else a skin entry beyond the cutoff
+            const NbOut o = nb_pair(spi[jt], iR, pv, ipv, qi * jq, rr);
+            evdw += o.ev;
+            ecoul += o.eq;
+            const double px = o.f * dx, py = o.f * dy, pz = o.f * dz;
+            fx += px;
+            fy += py;
+            fz += pz;
+            atomicAdd(&fax[tnow], -px);
+            atomicAdd(&fay[tnow], -py);
+            atomicAdd(&faz[tnow], -pz);
+          }
         }
+        tnow = tnext;
+        anow = anext;
+        jx = nx;
+        jy = ny;
+        jz = nz;
+        jq = nq;
+        jt = nt;
+        r1 = r2n;
+        ok1 = ok2;
+        anext = aafter;
       }
       flush();
     }
   }
   __syncthreads();
-  double* __restrict__ part = W.nbpart + (int64_t)c * 3 * NB_HALF_CAP;
+  double* __restrict__ part = W.nbpart + (int64_t)r * 3 * NB_HALF_CAP;
   for (int t = tid; t < nup; t += NBH_BS) {
     part[3 * t] = fax[t];
     part[3 * t + 1] = fay[t];
     part[3 * t + 2] = faz[t];
   }
   const double sv = block_sum<NBH_BS>(evdw), sq = block_sum<NBH_BS>(ecoul);
-  if (tid == 0) W.nbe[c] = make_double2(sv, sq);
+  if (tid == 0) W.nbe[r] = make_double2(sv, sq);
 }
 
 // the cells' nonbonded energies, summed into the two energy terms
@@ -1015,17 +1083,19 @@ __global__ __launch_bounds__(BS) void k_nb_energy(int ncell, const double2* __re
   block_add<BS>(eq, energies + E_COUL);
 }
 
-// Nonbonded force of each atom j from the partial arrays of the cells whose
-// upper stencil holds it: cells c = cell(j) - o for the offsets o with
-// (o_x, o_y) lexicographically positive, or o_x = o_y = 0 and o_z >= 0.  In
-// c's chunk sequence j lies in column (o_x, o_y) and in that column's
-// unwrapped or wrapped z range; its staged index is the chunk's base
-// (relative to c's first atom) plus its place in the chunk.  Writes the
-// per-atom accumulator the hydrogen-bond kernels then add to.
+// Nonbonded force of each atom j from the partial arrays of the runs whose
+// upper window holds it.  Those are the runs of the cells z - oz of the
+// columns at offsets (ox, oy) = column(j) - column(run) with (ox, oy)
+// lexicographically positive (oz in [-R, R]), or ox = oy = 0 (oz in [0, R]:
+// the window's upper part starts at the run's first cell).  In the run's chunk
+// sequence j lies in column (ox, oy) and in that column's unwrapped or wrapped
+// z range; its staged index is the chunk's base (relative to the run's first
+// atom) plus its place in the chunk.  Writes the per-atom accumulator the
+// hydrogen-bond kernels then add to.
 __global__ __launch_bounds__(BS) void k_nb_reduce(Grid g, Lists L, Work W) {
   const int64_t j = xcd_block() * blockDim.x + threadIdx.x;
   if (j >= L.n) return;
-  const int R = g.reach;
+  const int R = g.reach, nrz = run_rows(g);
   const int cj = L.cell_of[j];
   const int jz = cj % g.nc[2], jy = (cj / g.nc[2]) % g.nc[1], jx = cj / (g.nc[1] * g.nc[2]);
   const int jrow = (jx * g.nc[1] + jy) * g.nc[2];
@@ -1043,23 +1113,30 @@ __global__ __launch_bounds__(BS) void k_nb_reduce(Grid g, Lists L, Work W) {
         cy += cy < 0 ? g.nc[1] : -g.nc[1];
       }
       const int col = (ox + R) * g.span[1] + (oy + R);
+      int last = -1;   // cells of one run follow each other
       for (int oz = (ox == 0 && oy == 0) ? 0 : -R; oz <= R; ++oz) {
         int cz = jz - oz;
         if (cz < 0 || cz >= g.nc[2]) {
           if (!g.periodic) continue;
           cz += cz < 0 ? g.nc[2] : -g.nc[2];
         }
-        const int c = (cx * g.nc[1] + cy) * g.nc[2] + cz;
-        if (L.cell_start[c + 1] == L.cell_start[c]) continue;   // empty: no partial array
+        const int rz = cz / g.run;
+        if (rz == last) continue;
+        last = rz;
+        const int z0 = rz * g.run;
+        const int r = (cx * g.nc[1] + cy) * nrz + rz;
+        const int c0 = (cx * g.nc[1] + cy) * g.nc[2] + z0;
+        const int nk = g.nc[2] - z0 < g.run ? g.nc[2] - z0 : g.run;
+        if (L.cell_start[c0 + nk] == L.cell_start[c0]) continue;   // empty: no partial array
         int za0, za1, zb0, zb1;
-        column_ranges(g, cz, za0, za1, zb0, zb1);
+        window_ranges(g, z0, za0, za1, zb0, zb1);
         const bool in_a = jz >= za0 && jz < za1;
-        const bool wrap_first = zb1 > zb0 && cz - R < 0;
+        const bool wrap_first = zb1 > zb0 && z0 - R < 0;
         const int q = 2 * col + ((in_a != wrap_first) ? 0 : 1);
         const int s0 = L.cell_start[jrow + (in_a ? za0 : zb0)];
-        const int t = W.nbtab[(int64_t)c * NB_QMAX + q] + ((int)j - s0);
+        const int t = W.nbtab[(int64_t)r * NB_QMAX + q] + ((int)j - s0);
         if ((unsigned)t >= (unsigned)NB_HALF_CAP) continue;   // never taken for a consistent list
-        const double* __restrict__ part = W.nbpart + (int64_t)c * 3 * NB_HALF_CAP;
+        const double* __restrict__ part = W.nbpart + (int64_t)r * 3 * NB_HALF_CAP;
         fx += part[3 * t];
         fy += part[3 * t + 1];
         fz += part[3 * t + 2];
@@ -1158,8 +1235,9 @@ int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, co
     hipLaunchKernelGGL(__VA_ARGS__);                     \
     pf.end(st);                                          \
   } while (0)
-  // the nonbonded kernels read neighbours by stencil slot through a chunk table
-  if (!L.far_slots || stencil_chunks(g) > NBC_MAXQ) return -1;
+  // the nonbonded kernels read neighbours by slot through a chunk table; the
+  // per-cell kernel stages a cell's own stencil, so its slots must number it
+  if (!L.far_slots || stencil_chunks(g) > NBC_MAXQ || (!L.nb_half && g.run != 1)) return -1;
   LAUNCH(KID_GATHER_Q, k_gather_q, grid, blk, 0, st, q, L.perm, L.xs, n, W.xq);
   // fork: the nonbonded term (writing fnb) runs on the side stream while the
   // bonded terms run on the caller's stream; they share only the energy
@@ -1178,16 +1256,19 @@ int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, co
     hipLaunchKernelGGL(__VA_ARGS__);                     \
     pf.end(side);                                        \
   } while (0)
+    // one energy pair per run of the half evaluation, per cell otherwise
+    const int nrun = g.nc[0] * g.nc[1] * run_rows(g), per_run_xcd = (nrun + 7) / 8;
     if (L.nb_half) {
-      LAUNCH_SIDE(KID_NONBONDED, k_nonbonded_half, dim3(8u * (unsigned)per_xcd), dim3(NBH_BS), 0, side, P, g,
-                  L, W, ncell, per_xcd, energies);
+      LAUNCH_SIDE(KID_NONBONDED, k_nonbonded_half, dim3(8u * (unsigned)per_run_xcd), dim3(NBH_BS), 0, side, P,
+                  g, L, W, nrun, per_run_xcd, energies);
       LAUNCH_SIDE(KID_NB_REDUCE, k_nb_reduce, grid, blk, 0, side, g, L, W);
     } else {
       LAUNCH_SIDE(KID_NONBONDED, k_nonbonded, dim3(8u * (unsigned)per_xcd), dim3(NBC_BS), 0, side, P, g, L,
                   W, ncell, per_xcd, energies);
     }
-    LAUNCH_SIDE(KID_NB_ENERGY, k_nb_energy, dim3((unsigned)std::min<int64_t>(nblk(ncell, BS), 64)), blk, 0, side,
-                ncell, W.nbe, energies);
+    const int nnbe = L.nb_half ? nrun : ncell;
+    LAUNCH_SIDE(KID_NB_ENERGY, k_nb_energy, dim3((unsigned)std::min<int64_t>(nblk(nnbe, BS), 64)), blk, 0, side,
+                nnbe, W.nbe, energies);
 #undef LAUNCH_SIDE
   }
   if (fork) (void)hipEventRecord(ev_join, side);

@@ -191,6 +191,7 @@ struct reaxff_ctx {
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool overlap = true;
+  int nb_run_max = 8;       // longest run of cells of the half nonbonded evaluation
   bool upper_off = false;   // a build found the half evaluation impossible: full far rows from then on
   // Verlet-skin lists: far, H and bond-candidate lists built with the cutoffs
   // plus `skin` and kept while no atom has moved more than skin / 2 since the

@@ -133,10 +133,11 @@ __global__ void k_gather_sorted(const double* __restrict__ pos, const int32_t* _
 // candidates inside the per-type bond reach, H lists), in slot order.  Entries
 // beyond a row's width are counted but not written; the largest count of each
 // list is reported so the host can widen the rows and sweep again.  Far
-// entries are stencil slots when slots is set, sorted atom indices otherwise.
-// With far_lo set and no dimension covered whole, far_lo[i] counts the far
-// entries before i's own slot (the pairs the partner's cell owns) and need[5]
-// reports the largest upper stencil (the cell's first atom to the end).
+// entries are slots when slots is set (positions in the window of the cell's
+// run, window_chunk), sorted atom indices otherwise.  With far_lo set and no
+// dimension covered whole, far_lo[i] counts the far entries before i's own
+// slot (the pairs the partner's run owns) and need[5] reports the largest
+// upper window (the run's first atom to the window's end).
 // MINIMG: periodic box without stencil image shifts (minimum image per pair);
 // otherwise each chunk carries its image shift (zero in open boundaries).
 constexpr int SWEEP_WAVES = 4;
@@ -161,6 +162,7 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
   __shared__ unsigned long long red[SWEEP_WAVES][2];
   __shared__ int q_s0[SWEEP_WAVES][SWEEP_MAXQ], q_base[SWEEP_WAVES][SWEEP_MAXQ + 1];
   __shared__ double q_sh[SWEEP_WAVES][SWEEP_MAXQ][3];
+  __shared__ int q_wd[SWEEP_WAVES][SWEEP_MAXQ];
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int c = blockIdx.x * SWEEP_WAVES + wv;
   const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -208,8 +210,42 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
     const int c2 = c % g.nc[2];
     const int q_own = 2 * (g.reach * g.span[1] + g.reach) + (g.periodic && c2 - g.reach < 0 ? 1 : 0);
     own0 = __builtin_amdgcn_readfirstlane(qb[q_own] + (a0 - qs0[q_own]));
-    if (lane == 0) atomicMax(&nslot[(blockIdx.x * SWEEP_WAVES + wv) & (ESLOT - 1)], nst - own0);
+    if (g.run <= 1 && lane == 0) atomicMax(&nslot[(blockIdx.x * SWEEP_WAVES + wv) & (ESLOT - 1)], nst - own0);
   }
+  // far entries number the window of the cell's run: the slot of a candidate
+  // in chunk q is its slot here plus wd[q] (the window chunk of the same
+  // column and side, which holds this chunk, laid end to end with the others);
+  // need[5] then reports the largest upper window (the run's first atom to
+  // the window's end)
+  int* __restrict__ wd = q_wd[wv];
+  if (g.run > 1 && m > 0) {
+    int w0 = 0, w1 = 0;
+    if (lane < nq) {
+      double sx, sy, sz;
+      window_chunk(g, cstart, c, lane, w0, w1, sx, sy, sz);
+    }
+    const int wl = w1 - w0;
+    const int wb = wave_incl_scan(wl) - wl;   // the window chunk's first slot
+    const int pair0 = lane & ~1;
+    const int a_0 = __shfl(w0, pair0), l_0 = __shfl(wl, pair0), b_0 = __shfl(wb, pair0);
+    const int a_1 = __shfl(w0, pair0 + 1), b_1 = __shfl(wb, pair0 + 1);
+    if (lane < nq) {
+      const int cs0 = qs0[lane];
+      const bool in0 = cs0 >= a_0 && cs0 < a_0 + l_0;
+      wd[lane] = (in0 ? b_0 + (cs0 - a_0) : b_1 + (cs0 - a_1)) - qb[lane];
+    }
+    if (halfable) {
+      const int c2 = c % g.nc[2], z0 = c2 / g.run * g.run;
+      const int q_own = 2 * (g.reach * g.span[1] + g.reach) + (g.periodic && z0 - g.reach < 0 ? 1 : 0);
+      const int wend = readlane_i(wb + wl, nq - 1);
+      const int w_own = readlane_i(wb, q_own) + (cstart[c - (c2 - z0)] - readlane_i(w0, q_own));
+      if (lane == 0) atomicMax(&nslot[(blockIdx.x * SWEEP_WAVES + wv) & (ESLOT - 1)], wend - w_own);
+    }
+  } else if (lane < nq) {
+    wd[lane] = 0;
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   for (int ig = 0; ig < m; ig += 64) {       // the cell's atoms, 64 at a time, one per lane
     const int mi = m - ig < 64 ? m - ig : 64;
     double4 xmine = make_double4(0.0, 0.0, 0.0, 0.0);
@@ -224,11 +260,12 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
     for (int b0 = 0; b0 < nst; b0 += 64) {
       const int slot = b0 + lane;
       const bool valid = slot < nst;
-      int s = 0;
+      int s = 0, wdq = 0;
       double sx = 0.0, sy = 0.0, sz = 0.0;
       if (valid) {
         while (qb[q + 1] <= slot) ++q;
         s = qs0[q] + (slot - qb[q]);
+        wdq = wd[q];
         if constexpr (!MINIMG) {
           sx = q_sh[wv][q][0];
           sy = q_sh[wv][q][1];
@@ -317,7 +354,7 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
             const int k0 = readlane_i(kf, l);
             if (f) {
               const int k = k0 + __popcll(mf & below);
-              if (k < far_w) __builtin_nontemporal_store(slot, &frow[k]);
+              if (k < far_w) __builtin_nontemporal_store(slot + wdq, &frow[k]);
             }
             kf = writelane_i(k0 + __popcll(mf), l, kf);
             if (mf & ballot(r2 <= qmx)) {
@@ -387,7 +424,7 @@ __global__ __launch_bounds__(64 * SWEEP_WAVES) void k_sweep(
                 const int k = k0 + __popcll(mfu & below);
                 // list rows are streamed out (non-temporal), keeping the
                 // stencil's positions in L2
-                if (k < far_w) __builtin_nontemporal_store(slots ? slot : s, &frow[k]);
+                if (k < far_w) __builtin_nontemporal_store(slots ? slot + wdq : s, &frow[k]);
               }
               kf = writelane_i(k0 + __popcll(mfu), l, kf);
             }
@@ -714,8 +751,8 @@ __global__ void k_mirror(int64_t nbond, const int32_t* __restrict__ off, const i
 // export helpers: lists in caller indices
 // half far list from the full rows: the entries with j > i, at per-atom
 // offsets hoff (exclusive scan of the per-atom half counts).  Slot entries are
-// mapped back to sorted indices by walking the cell's chunk sequence along
-// the (increasing) row.
+// mapped back to sorted indices by walking the chunk sequence of the window of
+// the atom's run along the (increasing) row.
 template <bool WRITE>
 __global__ void k_export_far(int64_t n, Grid g, const int32_t* __restrict__ cstart,
                              const int32_t* __restrict__ cell_s, const int32_t* __restrict__ cnt,
@@ -731,13 +768,13 @@ __global__ void k_export_far(int64_t n, Grid g, const int32_t* __restrict__ csta
   const int c = slots ? cell_s[i] : 0, nq = stencil_chunks(g);
   int q = 0, s0 = 0, s1 = 0, base = 0;
   double sx, sy, sz;
-  if (slots) stencil_chunk(g, cstart, c, 0, s0, s1, sx, sy, sz);
+  if (slots) window_chunk(g, cstart, c, 0, s0, s1, sx, sy, sz);
   for (int k = 0; k < cnt[i]; ++k) {
     int j = row[k];
     if (slots) {
       while (j >= base + (s1 - s0) && q + 1 < nq) {
         base += s1 - s0;
-        stencil_chunk(g, cstart, c, ++q, s0, s1, sx, sy, sz);
+        window_chunk(g, cstart, c, ++q, s0, s1, sx, sy, sz);
       }
       j = s0 + (j - base);
     }

@@ -74,6 +74,13 @@ struct Grid {
   // image shift as its minimum image, and d - shift is bit-identical to
   // d - L rint(d / L)
   int shift_ok;
+  // cells per run: the cells of a column are grouped into runs of `run`
+  // consecutive z cells, and far-row slots number the window of the centre's
+  // run (its stencil columns over the run's z cells and reach on either side)
+  // instead of the centre cell's own stencil; 1: the cell's own stencil.
+  // Greater than 1 only with no dimension covered whole and, in a periodic
+  // box, run + 2 reach <= nc[2].
+  int run;
 };
 
 // --- lists and work arrays (device pointers, owned by the context) -------
@@ -86,21 +93,22 @@ struct Lists {
   int32_t* cell_start;  // [ncell + 1]
   // far-neighbour list, full (both directions of every pair), one row of
   // width far_w per atom: entry k of atom i is far_j[i * far_w + k], in
-  // increasing order.  With far_slots set an entry is the neighbour's stencil
-  // slot: its position in the chunk sequence of i's cell (stencil_chunk),
-  // which is also its place in the staged copy of that stencil; otherwise it
-  // is the neighbour's sorted index.
+  // increasing order.  With far_slots set an entry is the neighbour's slot:
+  // its position in the chunk sequence of the window of i's run
+  // (window_chunk; with Grid::run = 1 the stencil of i's cell), which is also
+  // its place in the staged copy of that window; otherwise it is the
+  // neighbour's sorted index.
   int32_t* far_cnt;     // [n]
   int32_t* far_j;
   int32_t far_w;
   int32_t far_slots;
   // half evaluation of the nonbonded term (slot form, no dimension covered
-  // whole, every cell's upper stencil within NB_HALF_CAP atoms): far_lo[i]
+  // whole, every run's upper window within NB_HALF_CAP atoms): far_lo[i]
   // entries of row i precede i's own slot; the pairs of the rest of the row
-  // are evaluated by i's cell, the others by the partner's cell
+  // are evaluated by i's run, the others by the partner's run
   int32_t* far_lo;      // [n]
   // far_upper: rows hold only the entries after the centre's own slot, so
-  // each pair appears once, in the row of the atom whose cell evaluates it
+  // each pair appears once, in the row of the atom whose run evaluates it
   // (far_lo is then 0).  Set when the half evaluation is expected; a build
   // that finds it impossible sweeps again with full rows.
   int32_t far_upper;
@@ -149,10 +157,10 @@ struct DonRec {
   int32_t X, tX;     // donor atom and its type
 };
 
-// atoms of a cell's upper stencil (the centre cell from its first atom on,
-// and every later chunk) that the half nonbonded kernel holds in LDS
-constexpr int NB_HALF_CAP = 1280;
-// chunk-table entries per cell: 2 (2 reach + 1)^2 <= 50 chunks and the total
+// atoms of a run's upper window (the centre column from the run's first atom
+// on, and every later chunk) that the half nonbonded kernel holds in LDS
+constexpr int NB_HALF_CAP = 2560;
+// chunk-table entries per run: 2 (2 reach + 1)^2 <= 50 chunks and the total
 constexpr int NB_QMAX = 64;
 
 struct Work {
@@ -202,14 +210,14 @@ struct Work {
   // (S, Delta - Dlp, Dang, prod W); null: read from ast
   double4* nv;
   int64_t cap_ang, cap_tor, cap_don;
-  // half nonbonded evaluation: per-cell partial forces on the upper stencil
-  // ([cell][NB_HALF_CAP][3]) and per-cell chunk bases relative to the cell's
-  // first atom ([cell][NB_QMAX])
+  // half nonbonded evaluation: per-run partial forces on the upper window
+  // ([run][NB_HALF_CAP][3]) and per-run chunk bases relative to the run's
+  // first atom ([run][NB_QMAX])
   double* nbpart;
   int32_t* nbtab;
   int64_t cap_nbpart, cap_nbtab;
-  // per-cell nonbonded energies (van der Waals, Coulomb), summed by a small
-  // reduction instead of one pair of same-address atomics per cell
+  // per-run nonbonded energies (van der Waals, Coulomb), summed by a small
+  // reduction instead of one pair of same-address atomics per run
   double2* nbe;
   int64_t cap_nbe;
 };
@@ -337,6 +345,27 @@ __device__ __forceinline__ void column_ranges(const Grid& g, int c2, int& za0, i
   }
 }
 
+// The same z ranges for the window of the run holding cell z = c2: the run's
+// cells [z0, z1) and reach cells on either side.
+__device__ __forceinline__ void window_ranges(const Grid& g, int c2, int& za0, int& za1, int& zb0,
+                                              int& zb1) {
+  if (g.run <= 1 || g.full[2]) {
+    column_ranges(g, c2, za0, za1, zb0, zb1);
+    return;
+  }
+  const int R = g.reach, nz = g.nc[2];
+  const int z0 = c2 / g.run * g.run, z1 = z0 + g.run < nz ? z0 + g.run : nz;
+  zb0 = zb1 = 0;
+  if (g.periodic) {
+    if (z0 - R < 0) { za0 = 0; za1 = z1 + R; zb0 = nz + z0 - R; zb1 = nz; }
+    else if (z1 + R > nz) { za0 = z0 - R; za1 = nz; zb0 = 0; zb1 = z1 + R - nz; }
+    else { za0 = z0 - R; za1 = z1 + R; }
+  } else {
+    za0 = z0 - R < 0 ? 0 : z0 - R;
+    za1 = z1 + R > nz ? nz : z1 + R;
+  }
+}
+
 // The stencil of cell c as a fixed sequence of chunks of contiguous sorted
 // atoms: chunk q (0 <= q < stencil_chunks) is column (a, b) = ((q/2) / span1,
 // (q/2) % span1) of the (x, y) stencil; within a column the z range at
@@ -352,8 +381,9 @@ __device__ __forceinline__ void column_ranges(const Grid& g, int c2, int& za0, i
 // it, has a larger slot than the centre itself.
 __host__ __device__ __forceinline__ int stencil_chunks(const Grid& g) { return 2 * g.span[0] * g.span[1]; }
 
-__device__ __forceinline__ void stencil_chunk(const Grid& g, const int32_t* __restrict__ cstart, int c, int q,
-                                              int& s0, int& s1, double& sx, double& sy, double& sz) {
+template <bool WIN>
+__device__ __forceinline__ void chunk_range(const Grid& g, const int32_t* __restrict__ cstart, int c, int q,
+                                            int& s0, int& s1, double& sx, double& sy, double& sz) {
   const int c2 = c % g.nc[2], c1 = (c / g.nc[2]) % g.nc[1], c0 = c / (g.nc[1] * g.nc[2]);
   const int col = q >> 1, a = col / g.span[1], bb = col % g.span[1];
   s0 = s1 = 0;
@@ -369,17 +399,33 @@ __device__ __forceinline__ void stencil_chunk(const Grid& g, const int32_t* __re
     else if (y >= g.nc[1]) { y -= g.nc[1]; sy = -g.L[1]; }
   } else if (y < 0 || y >= g.nc[1]) return;
   int za0, za1, zb0, zb1;
-  column_ranges(g, c2, za0, za1, zb0, zb1);
+  if constexpr (WIN) window_ranges(g, c2, za0, za1, zb0, zb1);
+  else column_ranges(g, c2, za0, za1, zb0, zb1);
+  // the cell whose reach decides which side wraps: the run's first for a window
+  const int zc = WIN && g.run > 1 ? c2 / g.run * g.run : c2;
   const int row = (x * g.nc[1] + y) * g.nc[2];
-  const bool wrap_first = zb1 > zb0 && c2 - g.reach < 0;
+  const bool wrap_first = zb1 > zb0 && zc - g.reach < 0;
   if (((q & 1) == 0) != wrap_first) {
     s0 = cstart[row + za0];
     s1 = cstart[row + za1];
   } else if (zb1 > zb0) {
     s0 = cstart[row + zb0];
     s1 = cstart[row + zb1];
-    sz = c2 - g.reach < 0 ? g.L[2] : -g.L[2];
+    sz = zc - g.reach < 0 ? g.L[2] : -g.L[2];
   }
+}
+// chunk q of cell c's own stencil (the candidates of its atoms)
+__device__ __forceinline__ void stencil_chunk(const Grid& g, const int32_t* __restrict__ cstart, int c, int q,
+                                              int& s0, int& s1, double& sx, double& sy, double& sz) {
+  chunk_range<false>(g, cstart, c, q, s0, s1, sx, sy, sz);
+}
+// chunk q of the window of c's run (the numbering of far-row slots): the same
+// columns and order over the run's z ranges; every chunk of a cell's stencil
+// lies inside the window's chunk of the same column and side, so slots keep
+// their order
+__device__ __forceinline__ void window_chunk(const Grid& g, const int32_t* __restrict__ cstart, int c, int q,
+                                             int& s0, int& s1, double& sx, double& sy, double& sz) {
+  chunk_range<true>(g, cstart, c, q, s0, s1, sx, sy, sz);
 }
 
 // largest k in [0, n) with b[k] <= t, for non-decreasing b with b[0] <= t

@@ -31,15 +31,22 @@ def ff(params):
     f.close()
 
 
-def _parity(ff, params, system, cutoffs=None):
-    if cutoffs is not None:
+def _oracle_ref(system, params, cutoffs=None):
+    o = Oracle(system, params, cutoffs)
+    e_ref, e_abs = o.energy_abs()
+    _, f_ref = o.forces()
+    return o, o.lists(), e_ref, e_abs, f_ref
+
+
+def _parity(ff, params, system, cutoffs=None, ff_cut=False, ref=None):
+    """ff_cut: ff was made with these cutoffs; otherwise a context is made for
+    them.  ref: the oracle's results for this system (_oracle_ref)."""
+    if cutoffs is not None and not ff_cut:
         from paper_1706_07772_amd import ReaxFF
         ff = ReaxFF(params, cutoffs)
     e, f, lists = gpu_eval(ff, system, lists=True)
-    o = Oracle(system, params, cutoffs)
-    nborder = assert_lists_equal(lists, o, o.lists())
-    e_ref, e_abs = o.energy_abs()
-    _, f_ref = o.forces()
+    o, olists, e_ref, e_abs, f_ref = ref if ref is not None else _oracle_ref(system, params, cutoffs)
+    nborder = assert_lists_equal(lists, o, olists)
     assert_energy_parity(e, e_ref, e_abs, names=TERM_NAMES)
     assert_force_parity(f, f_ref)
     return e, f, nborder
@@ -55,14 +62,14 @@ def _launches(ff):
     return {names[i].decode(): int(calls[i]) for i in range(k)}
 
 
-def _parity_path(ff, params, system, half):
+def _parity_path(ff, params, system, half, cutoffs=None, ref=None):
     """Parity, and that the nonbonded term took the expected path: the half
     evaluation (pairs once, partial arrays summed per atom) needs at least
     2 reach + 1 cells per edge; smaller grids evaluate every pair from both
-    atoms."""
+    atoms.  cutoffs: those ff was made with."""
     ff._lib.reaxff_profile(ff._h, 1)
     try:
-        out = _parity(ff, params, system)
+        out = _parity(ff, params, system, cutoffs, ff_cut=True, ref=ref)
         used = _launches(ff)
     finally:
         ff._lib.reaxff_profile(ff._h, 0)
@@ -96,22 +103,78 @@ def test_full_nonbonded_small_grid(ff, params):
     _parity_path(ff, params, rs.petn_lattice(30, 20.7, seed=4), half=False)
 
 
-def test_dense_fallbacks_then_normal_density(params):
-    """Twice the benchmark density (3,132 atoms at 0.2 atoms/A^3 in a 25.0 A box,
-    5 cells per edge): the upper stencil exceeds the half evaluation's LDS copy
-    (1,024 atoms), so the build sweeps again with full rows and the nonbonded
-    term evaluates every pair from both atoms; the whole-grid stencil (all
-    3,132 atoms) exceeds that kernel's LDS copy (2,048) too, so neighbours are
-    read from memory through the chunk table.  The same context then builds
-    the 1,856-atom box, keeping full far rows (the half evaluation reads the
-    rows' upper parts through far_lo)."""
+@pytest.mark.parametrize("run", [1, 2, 3, 4, 8])
+def test_half_nonbonded_run_lengths(params, run):
+    """Runs of 1-8 cells per workgroup (the 6,264-atom box has 8 cells per edge,
+    so runs of 3 leave a short last run, and the windows of the first and last
+    runs wrap below and above; 8 is capped at 4 = 8 - 2 reach) and in the open
+    3,000-atom cluster (windows clipped at the grid faces): the same pairs, each
+    once, and the same results."""
     from paper_1706_07772_amd import ReaxFF
-    dense = rs.petn_lattice(108, 25.0, seed=12)
-    assert dense.n / 25.0 ** 3 > 0.19
     ff = ReaxFF(params)
     try:
-        _parity_path(ff, params, dense, half=False)
-        _parity_path(ff, params, rs.workload("petn_1856"), half=True)
+        ff.set_nb_run(run)
+        for s in (rs.petn_lattice(216, 40.05, seed=11), rs.cluster(3000, seed=5)):
+            _parity_path(ff, params, s, half=True)
+    finally:
+        ff.close()
+
+
+def _slab():
+    """A 40 x 40 x 100 A block of 20 A PETN-density cubes in a periodic
+    100 x 40 x 100 A box (60 A of vacuum along x): the mean density over the
+    box is 40% of the block's."""
+    cube = rs.petn_lattice(27, 20.0, seed=21)
+    shifts = [np.array([20.0 * a, 20.0 * b, 20.0 * c]) for a in range(2) for b in range(2) for c in range(5)]
+    pos = np.concatenate([cube.pos + d for d in shifts])
+    typ = np.concatenate([cube.type] * len(shifts)).astype(np.int32)
+    q = np.concatenate([cube.q] * len(shifts))
+    return rs.System(pos=pos, type=typ, q=q, box=np.array([100.0, 40.0, 100.0]))
+
+
+def test_half_nonbonded_runs_shortened(params):
+    """Runs chosen from the mean density are too long where the atoms are:
+    with runs of up to 16 cells allowed, the block's windows (12 upper columns
+    of 20 cells and 18 cells of the centre column, about 3,150 atoms) exceed
+    the 2,560-atom copy, so the build halves the runs and sweeps again."""
+    from paper_1706_07772_amd import ReaxFF
+    s = _slab()
+    # the library's first choice: the longest run whose upper window at the
+    # mean density over the grid's cells fills at most 80% of the copy
+    nc = np.floor(s.box / 5.0).astype(int)
+    per_cell = s.n / nc.prod()
+    k0 = min(16, int(nc[2]) - 4, int(math.floor((0.8 * 2560 / per_cell - 50) / 13)))
+    assert k0 == 16
+    block = s.n / (40.0 * 40.0 * 100.0) * 125.0   # atoms per cell inside the block
+    assert block * (12 * (k0 + 4) + k0 + 2) > 2560 * 1.15
+    ff = ReaxFF(params)
+    try:
+        ff.set_nb_run(16)
+        _parity_path(ff, params, s, half=True)
+    finally:
+        ff.close()
+
+
+def test_dense_fallbacks_then_normal_density(params):
+    """A 15 A nonbonded cutoff (7.5 A cells) at the benchmark density: the
+    6,264-atom box has 5 cells per edge and an upper stencil of about 3,150
+    atoms, beyond the half evaluation's 2,560-atom LDS copy even for runs of one
+    cell, so the build sweeps again with full rows and the nonbonded term
+    evaluates every pair from both atoms; the whole-grid stencil (all 6,264
+    atoms) exceeds that kernel's LDS copy (2,048) too, so neighbours are read
+    from memory through the chunk table.  The same context then builds a box at
+    half that density, keeping full far rows (the half evaluation reads the
+    rows' upper parts through far_lo)."""
+    from paper_1706_07772_amd import ReaxFF
+    cut = dict(rs.DEFAULT_CUTOFFS, r_nonb=15.0)
+    dense = rs.petn_lattice(216, 40.05, seed=12)
+    assert dense.n * 63 / 125 > 2560 and dense.n > 2048
+    ff = ReaxFF(params, cut)
+    try:
+        _parity_path(ff, params, dense, half=False, cutoffs=cut)
+        sparse = rs.petn_lattice(108, 40.05, seed=13)
+        assert sparse.n * 63 / 125 < 0.8 * 2560
+        _parity_path(ff, params, sparse, half=True, cutoffs=cut)
     finally:
         ff.close()
 
