@@ -798,6 +798,7 @@ __global__ __launch_bounds__(NBC_BS) void k_nonbonded(const DevParams* __restric
 //     moves, not LDS.
 // ---------------------------------------------------------------------------
 constexpr int NBH_BS = 1024, NBH_WAVES = NBH_BS / 64;
+constexpr int NBH_MG = 128;   // centre atoms of a run per pass (two per lane of one wavefront)
 
 // runs of the grid and the cells of run r: first cell, count
 __host__ __device__ __forceinline__ int run_rows(const Grid& g) { return (g.nc[2] + g.run - 1) / g.run; }
@@ -816,9 +817,9 @@ __global__ __launch_bounds__(NBH_BS) __attribute__((amdgpu_waves_per_eu(4))) voi
   __shared__ unsigned char sty[NB_HALF_CAP];
   __shared__ int q_s0[NBC_MAXQ], q_base[NBC_MAXQ + 1];
   __shared__ double q_sh[NBC_MAXQ][3];
-  __shared__ int upre[NBC_MG + 1];
-  __shared__ double ixx[NBC_MG], ixy[NBC_MG], ixz[NBC_MG], iqq[NBC_MG];
-  __shared__ int ity[NBC_MG], icnt[NBC_MG], ilo[NBC_MG];
+  __shared__ int upre[NBH_MG + 1];
+  __shared__ double ixx[NBH_MG], ixy[NBH_MG], ixz[NBH_MG], iqq[NBH_MG];
+  __shared__ int ity[NBH_MG], icnt[NBH_MG], ilo[NBH_MG];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
   if (r >= nrun) return;
@@ -863,65 +864,68 @@ __global__ __launch_bounds__(NBH_BS) __attribute__((amdgpu_waves_per_eu(4))) voi
   const int nup = nst - S0;                            // <= NB_HALF_CAP (checked by the sweep)
   // chunk bases relative to S0, for the reduce
   if (tid <= nq) W.nbtab[(int64_t)r * NB_QMAX + tid] = q_base[tid] - S0;
-  for (int t0 = 0; t0 < nup; t0 += 2 * NBH_BS) {
-    int idx[2], qq[2];
-    double4 v[2];
-    int ty[2];
+  // staging: wavefront w copies the upper-window parts of chunks w, w + 16,
+  // ...; its lanes stride a chunk's atoms, which are contiguous in memory
+  for (int q = q_own + wv; q < nq; q += NBH_WAVES) {
+    const int b = q_base[q], e = q_base[q + 1];
+    const int sb = b > S0 ? b : S0, src = q_s0[q] - b;
+    const double hx = q_sh[q][0], hy = q_sh[q][1], hz = q_sh[q][2];
+    for (int s0 = sb; s0 < e; s0 += 128) {
+      double4 v[2];
+      int ty[2];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int t = t0 + u * NBH_BS + tid;
-      idx[u] = -1;
-      if (t < nup) {
-        const int slot = S0 + t;
-        const int q = last_le(q_base, nq, slot);
-        qq[u] = q;
-        idx[u] = q_s0[q] + (slot - q_base[q]);
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-      if (idx[u] >= 0) {
-        v[u] = W.xq[idx[u]];
-        ty[u] = L.type_s[idx[u]];
+      for (int u = 0; u < 2; ++u) {
+        const int s = s0 + 64 * u + lane;
+        if (s < e) {
+          v[u] = W.xq[src + s];
+          ty[u] = L.type_s[src + s];
+        }
       }
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int t = t0 + u * NBH_BS + tid;
-      if (idx[u] >= 0) {
-        sxx[t] = v[u].x - q_sh[qq[u]][0];
-        sxy[t] = v[u].y - q_sh[qq[u]][1];
-        sxz[t] = v[u].z - q_sh[qq[u]][2];
-        sxq[t] = v[u].w;
-        sty[t] = (unsigned char)ty[u];
+      for (int u = 0; u < 2; ++u) {
+        const int s = s0 + 64 * u + lane;
+        if (s < e) {
+          const int t = s - S0;
+          sxx[t] = v[u].x - hx;
+          sxy[t] = v[u].y - hy;
+          sxz[t] = v[u].z - hz;
+          sxq[t] = v[u].w;
+          sty[t] = (unsigned char)ty[u];
+          fax[t] = fay[t] = faz[t] = 0.0;
+        }
       }
-      if (t < nup) fax[t] = fay[t] = faz[t] = 0.0;
     }
   }
   const double iR = P->inv_r_nonb, pv = P->p_vdW1, ipv = P->inv_p_vdW1, rn2c = P->rn2;
   double evdw = 0.0, ecoul = 0.0;
-  for (int g0 = 0; g0 < m; g0 += NBC_MG) {
-    const int mg = m - g0 < NBC_MG ? m - g0 : NBC_MG;
-    __syncthreads();   // staging done / previous pass's units done
-    if (wv == 0) {
-      int nu = 0;
-      if (lane < mg) {
-        const int i = a0 + g0 + lane;
-        const int cnt = L.far_cnt[i], lo = L.far_lo[i];
-        const double4 xi = W.xq[i];
-        ixx[lane] = xi.x;
-        ixy[lane] = xi.y;
-        ixz[lane] = xi.z;
-        iqq[lane] = xi.w * C_ELE;
-        ity[lane] = L.type_s[i];
-        icnt[lane] = cnt;
-        ilo[lane] = lo;
-        nu = (cnt - lo + 31) >> 5;   // units of 32 entries
+  for (int g0 = 0; g0 < m; g0 += NBH_MG) {
+    const int mg = m - g0 < NBH_MG ? m - g0 : NBH_MG;
+    if (g0 > 0) __syncthreads();   // the previous pass's units done
+    if (wv == 0) {   // the pass's centres, two per lane: 2 lane and 2 lane + 1
+      int nu[2] = {0, 0};
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int k = 2 * lane + h;
+        if (k < mg) {
+          const int i = a0 + g0 + k;
+          const int cnt = L.far_cnt[i], lo = L.far_lo[i];
+          const double4 xi = W.xq[i];
+          ixx[k] = xi.x;
+          ixy[k] = xi.y;
+          ixz[k] = xi.z;
+          iqq[k] = xi.w * C_ELE;
+          ity[k] = L.type_s[i];
+          icnt[k] = cnt;
+          ilo[k] = lo;
+          nu[h] = (cnt - lo + 31) >> 5;   // units of 32 entries
+        }
       }
-      const int v = wave_incl_scan(nu);
-      if (lane < mg) upre[lane + 1] = v;
+      const int v = wave_incl_scan(nu[0] + nu[1]);
+      upre[2 * lane + 1] = v - nu[1];
+      upre[2 * lane + 2] = v;
       if (lane == 0) upre[0] = 0;
     }
-    __syncthreads();
+    __syncthreads();   // staging and the pass's centres in place
     // units of 32 row entries: each wavefront takes a contiguous share of the
     // units and works on two at a time, one per half (lanes 0-31, 32-63), so a
     // row's last unit wastes at most 31 lanes of a half; the centre atom is
