@@ -258,6 +258,34 @@ int reaxff_set_overlap(reaxff_ctx* ctx, int32_t enable);
  * REAXFF_OK, or REAXFF_ERR_ARG for a null context or run_max out of range. */
 int reaxff_set_nb_run(reaxff_ctx* ctx, int32_t run_max);
 
+/* ---- Elementary functions ----------------------------------------------------
+ *
+ * The force terms of Section 2.1 evaluate exponentials, logarithms, powers,
+ * x^(-1/3), reciprocals and x^(-1/2) in FP64 with the library's own
+ * functions (range reduction plus economized polynomials, or a hardware
+ * estimate plus Newton or series steps).  reaxff_math_eval applies function
+ * fn to n arguments x [dev] (and exponents y [dev] for REAXFF_MATH_POW,
+ * x^y; y may be NULL otherwise), writing out [dev] (n), asynchronously on
+ * `stream`; it needs no context.  Domains: EXP, LOG, POW any finite x > 0
+ * (POW also x = 0) with results in the normal range; EXP_R |x| < 700; LOG_R
+ * positive normal x; EXP_C any x (clamped to [-1000, 1000], NaN passes);
+ * RCBRT, RSQRT finite x > 0; RCP finite nonzero x.  Returns REAXFF_OK, or
+ * REAXFF_ERR_ARG for an unknown fn, n < 0 or a null array, REAXFF_ERR_HIP
+ * for a failed launch. */
+enum {
+  REAXFF_MATH_EXP = 0,    /* exp, Cody-Waite reduction and a degree-11 polynomial */
+  REAXFF_MATH_EXP_R = 1,  /* the same exp with the integer steps done on the bits */
+  REAXFF_MATH_EXP_C = 2,  /* exp of the argument clamped to [-1000, 1000] */
+  REAXFF_MATH_LOG = 3,    /* log, 2 atanh((m - 1)/(m + 1)) */
+  REAXFF_MATH_LOG_R = 4,  /* the same log with the exponent and mantissa read from the bits */
+  REAXFF_MATH_POW = 5,    /* x^y = exp(y log x) */
+  REAXFF_MATH_RCBRT = 6,  /* x^(-1/3) */
+  REAXFF_MATH_RCP = 7,    /* 1/x */
+  REAXFF_MATH_RSQRT = 8   /* x^(-1/2) */
+};
+int reaxff_math_eval(int32_t fn, int64_t n, const double* x, const double* y, double* out,
+                     hipStream_t stream);
+
 /* ---- Charge equilibration (Section 3.3, QEq) ------------------------------
  *
  * The charges that minimise the electrostatic energy

@@ -155,6 +155,7 @@ def load_library():
     lib.reaxff_profile.argtypes = [vp, i32]
     lib.reaxff_set_overlap.argtypes = [vp, i32]
     lib.reaxff_set_nb_run.argtypes = [vp, i32]
+    lib.reaxff_math_eval.argtypes = [i32, i64, vp, vp, vp, vp]
     lib.reaxff_profile_read.argtypes = [vp, i32, vp, vp, vp]
     lib.reaxff_last_error.restype = ctypes.c_char_p
     lib.reaxff_last_error.argtypes = [vp]
@@ -200,6 +201,25 @@ def _ptr(t):
 
 def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+#: reaxff_math_eval function codes
+MATH_FUNCTIONS = {"exp": 0, "exp_r": 1, "exp_c": 2, "log": 3, "log_r": 4, "pow": 5, "rcbrt": 6, "rcp": 7,
+                  "rsqrt": 8}
+
+
+def math_eval(name: str, x, y=None):
+    """reaxff_math_eval: the library's FP64 elementary function `name` on the
+    float64 device tensor x (and exponents y for "pow"); returns a new tensor."""
+    lib = load_library()
+    x = x.contiguous()
+    out = torch.empty_like(x)
+    if y is not None:
+        y = y.contiguous()
+    code = lib.reaxff_math_eval(MATH_FUNCTIONS[name], x.numel(), _ptr(x), _ptr(y), _ptr(out), _stream())
+    if code != 0:
+        raise ReaxFFError(code, "reaxff_math_eval failed")
+    return out
 
 
 class ReaxFF:

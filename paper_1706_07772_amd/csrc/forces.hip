@@ -788,14 +788,13 @@ __global__ __launch_bounds__(NBC_BS) void k_nonbonded(const DevParams* __restric
 //     run's first atom on) and evaluates each such pair once, for the row
 //     suffix [far_lo[i], cnt_i) of each atom of the run's cells.  Both atoms'
 //     forces are added to LDS accumulators on the staged slots (the centre's
-//     through a half-wavefront sum when the half moves on, the partner's per
+//     through sums over 16-lane rows when a half moves on, the partner's per
 //     pair); the accumulators are stored, not added, to the run's partial
 //     array (x, y, z of a slot contiguous), and k_nb_reduce sums, for each
 //     atom, the partial arrays of the runs whose upper window holds it.
 //     Energies take each pair once.  In a periodic box whose chunk shifts are
 //     the minimum images, the staged positions carry their chunk's shift, so
-//     a displacement is a plain difference; the centre sums use DPP row
-//     moves, not LDS.
+//     a displacement is a plain difference; the row sums use DPP moves.
 // ---------------------------------------------------------------------------
 constexpr int NBH_BS = 1024, NBH_WAVES = NBH_BS / 64;
 constexpr int NBH_MG = 128;   // centre atoms of a run per pass (two per lane of one wavefront)
@@ -990,11 +989,11 @@ __global__ __launch_bounds__(NBH_BS) __attribute__((amdgpu_waves_per_eu(4))) voi
       double xix = ixx[cur], xiy = ixy[cur], xiz = ixz[cur], qi = iqq[cur];
       const NbP* __restrict__ spi = sp + ity[cur] * NT;
       double fx = 0.0, fy = 0.0, fz = 0.0;
-      auto flush = [&]() {   // over the 32 lanes of this half, into its last lane
-        fx = half_sum_last(fx);
-        fy = half_sum_last(fy);
-        fz = half_sum_last(fz);
-        if (sl == 31) {
+      auto flush = [&]() {   // over each 16-lane row of this half, into its last lane
+        fx = row_sum_last(fx);
+        fy = row_sum_last(fy);
+        fz = row_sum_last(fz);
+        if ((sl & 15) == 15) {
           const int t = g0 + cur;   // the centre's staged index: slot - S0 = i - a0
           atomicAdd(&fax[t], fx);
           atomicAdd(&fay[t], fy);
