@@ -825,8 +825,9 @@ __global__ __launch_bounds__(NBH_BS) __attribute__((amdgpu_waves_per_eu(4))) voi
   int c, nk;
   run_cells(g, r, c, nk);
   const int a0 = L.cell_start[c], m = L.cell_start[c + nk] - a0;
-  if (m == 0) {   // no pairs; the reduce skips empty runs
+  if (m == 0) {   // no pairs: chunk offsets that send the reduce past every slot
     if (tid == 0) W.nbe[r] = make_double2(0.0, 0.0);
+    if (tid < stencil_chunks(g)) W.nbtab[(int64_t)r * NB_QMAX + tid] = -0x40000000;
     return;
   }
   if (tid < NT * NT) sp[tid] = nb_params(P->pair[tid]);
@@ -861,8 +862,8 @@ __global__ __launch_bounds__(NBH_BS) __attribute__((amdgpu_waves_per_eu(4))) voi
   const int q_own = 2 * col_own + (wrap_first ? 1 : 0);
   const int S0 = q_base[q_own] + (a0 - q_s0[q_own]);   // slot of the run's first atom
   const int nup = nst - S0;                            // <= NB_HALF_CAP (checked by the sweep)
-  // chunk bases relative to S0, for the reduce
-  if (tid <= nq) W.nbtab[(int64_t)r * NB_QMAX + tid] = q_base[tid] - S0;
+  // for the reduce: atom j of chunk q has staged index nbtab[q] + j
+  if (tid < nq) W.nbtab[(int64_t)r * NB_QMAX + tid] = q_base[tid] - S0 - q_s0[tid];
   // staging: wavefront w copies the upper-window parts of chunks w, w + 16,
   // ...; its lanes stride a chunk's atoms, which are contiguous in memory
   for (int q = q_own + wv; q < nq; q += NBH_WAVES) {
@@ -1092,16 +1093,47 @@ __global__ __launch_bounds__(BS) void k_nb_energy(int ncell, const double2* __re
 // lexicographically positive (oz in [-R, R]), or ox = oy = 0 (oz in [0, R]:
 // the window's upper part starts at the run's first cell).  In the run's chunk
 // sequence j lies in column (ox, oy) and in that column's unwrapped or wrapped
-// z range; its staged index is the chunk's base (relative to the run's first
-// atom) plus its place in the chunk.  Writes the per-atom accumulator the
-// hydrogen-bond kernels then add to.
+// z range, chunk q; its staged index is nbtab[q] + j (an empty run's offsets
+// put every atom out of range).  Writes the per-atom accumulator the
+// hydrogen-bond kernels then add to.  R: the stencil reach.
+template <int R>
 __global__ __launch_bounds__(BS) void k_nb_reduce(Grid g, Lists L, Work W) {
   const int64_t j = xcd_block() * blockDim.x + threadIdx.x;
   if (j >= L.n) return;
-  const int R = g.reach, nrz = run_rows(g);
+  const int nrz = run_rows(g);
   const int cj = L.cell_of[j];
   const int jz = cj % g.nc[2], jy = (cj / g.nc[2]) % g.nc[1], jx = cj / (g.nc[1] * g.nc[2]);
-  const int jrow = (jx * g.nc[1] + jy) * g.nc[2];
+  // the runs of the cells jz - oz, oz in [-R, R] (the same in every column):
+  // their z index, the side of their window holding j (chunk 2 col + side)
+  // and whether one of those cells has oz >= 0 (the centre column's upper part)
+  int nr = 0, rzs[2 * R + 1], side[2 * R + 1];
+  bool up[2 * R + 1];
+  {
+    int last = -1;
+#pragma unroll
+    for (int oz = -R; oz <= R; ++oz) {
+      int cz = jz - oz;
+      if (cz < 0 || cz >= g.nc[2]) {
+        if (!g.periodic) continue;
+        cz += cz < 0 ? g.nc[2] : -g.nc[2];
+      }
+      const int rz = cz / g.run;
+      if (rz == last) {   // cells of one run follow each other
+        up[nr - 1] = up[nr - 1] || oz >= 0;
+        continue;
+      }
+      last = rz;
+      const int z0 = rz * g.run;
+      int za0, za1, zb0, zb1;
+      window_ranges(g, z0, za0, za1, zb0, zb1);
+      const bool in_a = jz >= za0 && jz < za1;
+      const bool wrap_first = zb1 > zb0 && z0 - R < 0;
+      rzs[nr] = rz;
+      side[nr] = (in_a != wrap_first) ? 0 : 1;
+      up[nr] = oz >= 0;
+      ++nr;
+    }
+  }
   double fx = 0.0, fy = 0.0, fz = 0.0;
   for (int ox = 0; ox <= R; ++ox) {
     int cx = jx - ox;
@@ -1116,33 +1148,18 @@ __global__ __launch_bounds__(BS) void k_nb_reduce(Grid g, Lists L, Work W) {
         cy += cy < 0 ? g.nc[1] : -g.nc[1];
       }
       const int col = (ox + R) * g.span[1] + (oy + R);
-      int last = -1;   // cells of one run follow each other
-      for (int oz = (ox == 0 && oy == 0) ? 0 : -R; oz <= R; ++oz) {
-        int cz = jz - oz;
-        if (cz < 0 || cz >= g.nc[2]) {
-          if (!g.periodic) continue;
-          cz += cz < 0 ? g.nc[2] : -g.nc[2];
-        }
-        const int rz = cz / g.run;
-        if (rz == last) continue;
-        last = rz;
-        const int z0 = rz * g.run;
-        const int r = (cx * g.nc[1] + cy) * nrz + rz;
-        const int c0 = (cx * g.nc[1] + cy) * g.nc[2] + z0;
-        const int nk = g.nc[2] - z0 < g.run ? g.nc[2] - z0 : g.run;
-        if (L.cell_start[c0 + nk] == L.cell_start[c0]) continue;   // empty: no partial array
-        int za0, za1, zb0, zb1;
-        window_ranges(g, z0, za0, za1, zb0, zb1);
-        const bool in_a = jz >= za0 && jz < za1;
-        const bool wrap_first = zb1 > zb0 && z0 - R < 0;
-        const int q = 2 * col + ((in_a != wrap_first) ? 0 : 1);
-        const int s0 = L.cell_start[jrow + (in_a ? za0 : zb0)];
-        const int t = W.nbtab[(int64_t)r * NB_QMAX + q] + ((int)j - s0);
-        if ((unsigned)t >= (unsigned)NB_HALF_CAP) continue;   // never taken for a consistent list
-        const double* __restrict__ part = W.nbpart + (int64_t)r * 3 * NB_HALF_CAP;
-        fx += part[3 * t];
-        fy += part[3 * t + 1];
-        fz += part[3 * t + 2];
+      const int64_t rcol = (int64_t)(cx * g.nc[1] + cy) * nrz;
+      const bool own = ox == 0 && oy == 0;
+#pragma unroll
+      for (int k = 0; k < 2 * R + 1; ++k) {
+        if (k >= nr || (own && !up[k])) continue;
+        const int64_t r = rcol + rzs[k];
+        const int t = W.nbtab[r * NB_QMAX + 2 * col + side[k]] + (int)j;
+        if ((unsigned)t >= (unsigned)NB_HALF_CAP) continue;   // an empty run
+        const double* __restrict__ part = W.nbpart + r * 3 * NB_HALF_CAP + 3 * t;
+        fx += part[0];
+        fy += part[1];
+        fz += part[2];
       }
     }
   }
@@ -1264,7 +1281,8 @@ int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, co
     if (L.nb_half) {
       LAUNCH_SIDE(KID_NONBONDED, k_nonbonded_half, dim3(8u * (unsigned)per_run_xcd), dim3(NBH_BS), 0, side, P,
                   g, L, W, nrun, per_run_xcd, energies);
-      LAUNCH_SIDE(KID_NB_REDUCE, k_nb_reduce, grid, blk, 0, side, g, L, W);
+      if (g.reach == 1) LAUNCH_SIDE(KID_NB_REDUCE, k_nb_reduce<1>, grid, blk, 0, side, g, L, W);
+      else LAUNCH_SIDE(KID_NB_REDUCE, k_nb_reduce<2>, grid, blk, 0, side, g, L, W);
     } else {
       LAUNCH_SIDE(KID_NONBONDED, k_nonbonded, dim3(8u * (unsigned)per_xcd), dim3(NBC_BS), 0, side, P, g, L,
                   W, ncell, per_xcd, energies);
