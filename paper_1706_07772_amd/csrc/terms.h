@@ -38,7 +38,9 @@ namespace rx {
 //            infinity beyond; the reduction then stays exact); NaN passes.
 //   pow_c:   x^y = exp_c(y log x) for x > 0, with 0^y spelled out.
 // Each is within a few units in the last place, far inside the 1e-9
-// relative agreement asked of energies and forces.
+// relative agreement asked of energies and forces.  poly_coeffs.py beside
+// this file derives the exp and log coefficients (exact rationals rounded to
+// double).
 // ---------------------------------------------------------------------------
 constexpr double LN2_HEAD = 0x1.62e42ff000000p-1;
 constexpr double LN2_TAIL = -0x1.718432a1b0e26p-35;
