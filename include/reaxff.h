@@ -104,7 +104,8 @@ int64_t reaxff_params_size(void);
  * Section 2.1 names (the parameter tables of those terms) with the distance
  * and bond-order cutoffs of the lists of Section 3.3 (NULL = defaults):
  * uploads the parameters.  *out receives the context; REAXFF_ERR_ARG for
- * null pointers or inconsistent cutoffs, REAXFF_ERR_HIP when the device
+ * null pointers, inconsistent cutoffs or parameter tables without the
+ * symmetries reaxff_params states, REAXFF_ERR_HIP when the device
  * cannot be set up.  Device scratch (cell arrays, lists, per-bond and
  * per-atom work arrays) is owned by the context and grows inside
  * reaxff_build_lists; reaxff_destroy releases it. */

@@ -328,10 +328,41 @@ const char* reaxff_strerror(int code) {
 
 const char* reaxff_last_error(const reaxff_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
+// the symmetries reaxff_params states: pair tables [i][j] = [j][i], angle
+// tables [i][j][k] = [k][j][i], torsion tables [i][j][k][l] = [l][k][j][i]
+// (a bond found from one atom must be found from the other, and each
+// interaction has one parameter set whichever end it is read from)
+static bool params_symmetric(const reaxff_params& p) {
+  const double* pair = &p.r_s[0][0];
+  const int npair = (int)((&p.a_core[3][3] - pair) + 1) / 16;
+  for (int t = 0; t < npair; ++t)
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j)
+        if (!(pair[16 * t + 4 * i + j] == pair[16 * t + 4 * j + i])) return false;
+  const double* ang = &p.theta00[0][0][0];
+  const int nang = (int)((&p.p_coa1[3][3][3] - ang) + 1) / 64;
+  for (int t = 0; t < nang; ++t)
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j)
+        for (int k = 0; k < 4; ++k)
+          if (!(ang[64 * t + 16 * i + 4 * j + k] == ang[64 * t + 16 * k + 4 * j + i])) return false;
+  const double* tor = &p.V1[0][0][0][0];
+  const int ntor = (int)((&p.p_cot1[3][3][3][3] - tor) + 1) / 256;
+  for (int t = 0; t < ntor; ++t)
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j)
+        for (int k = 0; k < 4; ++k)
+          for (int l = 0; l < 4; ++l)
+            if (!(tor[256 * t + 64 * i + 16 * j + 4 * k + l] == tor[256 * t + 64 * l + 16 * k + 4 * j + i]))
+              return false;
+  return true;
+}
+
 int reaxff_create(const reaxff_params* params, const reaxff_cutoffs* cutoffs, int device,
                   reaxff_ctx** out) {
   if (!params || !out) return REAXFF_ERR_ARG;
   *out = nullptr;
+  if (!params_symmetric(*params)) return REAXFF_ERR_ARG;
   auto* c = new reaxff_ctx();
   c->device = device;
   c->hp = *params;

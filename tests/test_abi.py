@@ -38,3 +38,25 @@ def test_params_layout_matches_binding():
     from paper_1706_07772_amd.binding import CParams, load_library
     lib = load_library()
     assert lib.reaxff_params_size() == ctypes.sizeof(CParams)
+
+
+def test_create_rejects_asymmetric_tables():
+    """reaxff_create refuses parameter tables without the stated symmetries
+    (pair [i][j] = [j][i], angle [i][j][k] = [k][j][i], torsion reversal),
+    before it touches a device: a bond found from one atom must be found from
+    the other, and each interaction has one parameter set."""
+    import numpy as np
+    import reaxff_synth as rs
+    from paper_1706_07772_amd.binding import load_library, make_cparams
+    lib = load_library()
+    base = rs.draw_params(0)
+    for table, name, idx in (("pair", "r_s", (0, 2)), ("angle", "theta00", (0, 1, 3)),
+                             ("tors", "V2", (0, 1, 2, 3))):
+        p = rs.draw_params(0)
+        arr = getattr(p, table)[name].copy()
+        arr[idx] += 0.125
+        getattr(p, table)[name] = arr
+        out = ctypes.c_void_p()
+        code = lib.reaxff_create(ctypes.byref(make_cparams(p)), None, 0, ctypes.byref(out))
+        assert code == -1 and not out.value, (table, name, code)
+    assert np.array_equal(base.pair["r_s"], base.pair["r_s"].T)
