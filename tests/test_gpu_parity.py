@@ -120,6 +120,24 @@ def test_half_nonbonded_run_lengths(params, run):
         ff.close()
 
 
+def test_half_nonbonded_runs_minimum_image(params):
+    """A 31 A box (2,900 atoms, 6 cells per edge) has too few cells for the
+    staged image shifts, so every pair takes the minimum image; runs of 2
+    cells (6 - 2 reach) and of 1, with positions inside and outside the box."""
+    from paper_1706_07772_amd import ReaxFF
+    s = rs.petn_lattice(100, 31.0, seed=14)
+    moved = rs.System(pos=s.pos + np.array([31.0, -62.0, 0.5]), type=s.type, q=s.q, box=s.box)
+    ref = _oracle_ref(s, params)
+    for run in (8, 1):
+        ff = ReaxFF(params)
+        try:
+            ff.set_nb_run(run)
+            _parity_path(ff, params, s, half=True, ref=ref)
+            _parity_path(ff, params, moved, half=True)
+        finally:
+            ff.close()
+
+
 def _slab():
     """A 40 x 40 x 100 A block of 20 A PETN-density cubes in a periodic
     100 x 40 x 100 A box (60 A of vacuum along x): the mean density over the
@@ -343,15 +361,17 @@ def test_overlap_matches_in_order(ff, params, system):
     assert np.abs(f1 - f0).max() <= 1e-11 * np.abs(f0).max()
 
 
-@pytest.mark.parametrize("name", ["petn_1856", "cluster300"])
+@pytest.mark.parametrize("name", ["petn_1856", "cluster300", "petn_6264"])
 def test_caller_owned_lists_capacity_protocol(params, name):
     """reaxff_build_lists_into: undersized caller buffers give REAXFF_ERR_CAPACITY
     with required[] and no lists; buffers grown to required[] (again if the
     rows outgrow the first estimate) give the lists, identical to the context's
-    own, and forces through them equal the oracle's."""
+    own, and forces through them equal the oracle's.  The 6,264-atom box (8
+    cells per edge) numbers its far rows by windows of runs of 4 cells."""
     import torch
     from paper_1706_07772_amd import ListBuffers, ReaxFF, ReaxFFError
-    s = rs.workload("petn_1856") if name == "petn_1856" else rs.cluster(300, seed=61)
+    s = {"petn_1856": lambda: rs.workload("petn_1856"), "cluster300": lambda: rs.cluster(300, seed=61),
+         "petn_6264": lambda: rs.petn_lattice(216, 40.05, seed=11)}[name]()
     ff = ReaxFF(params)
     try:
         pos, typ, q, box = to_dev(s)
