@@ -788,7 +788,7 @@ __global__ __launch_bounds__(NBC_BS) void k_nonbonded(const DevParams* __restric
 //     run's first atom on) and evaluates each such pair once, for the row
 //     suffix [far_lo[i], cnt_i) of each atom of the run's cells.  Both atoms'
 //     forces are added to LDS accumulators on the staged slots (the centre's
-//     through sums over the 16 lanes of a unit when they move on, the partner's per
+//     through sums over the 8 lanes of a unit when they move on, the partner's per
 //     pair); the accumulators are stored, not added, to the run's partial
 //     array (x, y, z of a slot contiguous), and k_nb_reduce sums, for each
 //     atom, the partial arrays of the runs whose upper window holds it.
@@ -917,7 +917,7 @@ __global__ __launch_bounds__(NBH_BS) __attribute__((amdgpu_waves_per_eu(4))) voi
           ity[k] = L.type_s[i];
           icnt[k] = cnt;
           ilo[k] = lo;
-          nu[h] = (cnt - lo + 15) >> 4;   // units of 16 entries
+          nu[h] = (cnt - lo + 7) >> 3;   // units of 8 entries
         }
       }
       const int v = wave_incl_scan(nu[0] + nu[1]);
@@ -926,16 +926,16 @@ __global__ __launch_bounds__(NBH_BS) __attribute__((amdgpu_waves_per_eu(4))) voi
       if (lane == 0) upre[0] = 0;
     }
     __syncthreads();   // staging and the pass's centres in place
-    // units of 16 row entries: each wavefront takes a contiguous share of the
-    // units and works on four at a time, one per 16-lane row, so a far row's
-    // last unit wastes at most 15 lanes; the centre atom is uniform over each
-    // 16-lane row
+    // units of 8 row entries: each wavefront takes a contiguous share of the
+    // units and works on eight at a time, one per group of 8 lanes, so a far
+    // row's last unit idles at most 7 lanes; the centre atom is uniform over
+    // each group
     const int U = __builtin_amdgcn_readfirstlane(upre[mg]);
     const int wu = __builtin_amdgcn_readfirstlane(wv);
     const int u0 = U * wu / NBH_WAVES, u1 = U * (wu + 1) / NBH_WAVES;
     if (u0 < u1) {
-      const int hh = lane >> 4, sl = lane & 15;
-      // the far row of centre a (uniform over the 16 lanes) kept in registers: units
+      const int hh = lane >> 3, sl = lane & 7;
+      // the far row of centre a (uniform over the 8 lanes) kept in registers: units
       // [ua, un) are its, starting at entry lo, cn entries in all
       int a = 0, ua = 0, un = 0, lo = 0, cn = 0;
       const int32_t* __restrict__ rowp = L.far_j;
@@ -957,7 +957,7 @@ __global__ __launch_bounds__(NBH_BS) __attribute__((amdgpu_waves_per_eu(4))) voi
           while (upre[na + 1] <= u) ++na;
           enter(na);
         }
-        const int k = lo + ((u - ua) << 4) + sl;
+        const int k = lo + ((u - ua) << 3) + sl;
         ok = k < cn;
         return ok ? rowp[k] : 0;
       };
@@ -965,7 +965,7 @@ __global__ __launch_bounds__(NBH_BS) __attribute__((amdgpu_waves_per_eu(4))) voi
         const int t = raw - S0;
         return ok && (unsigned)t < (unsigned)nup ? t : -1;
       };
-      // three units in flight per 16 lanes: this iteration's (its partner's
+      // three units in flight per 8 lanes: this iteration's (its partner's
       // staged data loaded), the next one's (row entry loaded) and the one
       // after, whose row entry is fetched during this iteration's pair
       const int uh = u0 + hh;
@@ -973,7 +973,7 @@ __global__ __launch_bounds__(NBH_BS) __attribute__((amdgpu_waves_per_eu(4))) voi
       bool ok0, ok1;
       const int r0 = fetch(uh, ok0);
       const int acur0 = a;
-      int r1 = fetch(uh + 4, ok1);
+      int r1 = fetch(uh + 8, ok1);
       int anext = a;
       int tnow = staged(r0, ok0), anow = acur0;
       double jx, jy, jz, jq;
@@ -990,11 +990,11 @@ __global__ __launch_bounds__(NBH_BS) __attribute__((amdgpu_waves_per_eu(4))) voi
       double xix = ixx[cur], xiy = ixy[cur], xiz = ixz[cur], qi = iqq[cur];
       const NbP* __restrict__ spi = sp + ity[cur] * NT;
       double fx = 0.0, fy = 0.0, fz = 0.0;
-      auto flush = [&]() {   // over the 16 lanes, into the last
-        fx = row_sum_last(fx);
-        fy = row_sum_last(fy);
-        fz = row_sum_last(fz);
-        if ((sl & 15) == 15) {
+      auto flush = [&]() {   // over the 8 lanes, into the last
+        fx = oct_sum_last(fx);
+        fy = oct_sum_last(fy);
+        fz = oct_sum_last(fz);
+        if (sl == 7) {
           const int t = g0 + cur;   // the centre's staged index: slot - S0 = i - a0
           atomicAdd(&fax[t], fx);
           atomicAdd(&fay[t], fy);
@@ -1002,10 +1002,10 @@ __global__ __launch_bounds__(NBH_BS) __attribute__((amdgpu_waves_per_eu(4))) voi
         }
         fx = fy = fz = 0.0;
       };
-      for (int ub = u0; ub < u1; ub += 4) {
+      for (int ub = u0; ub < u1; ub += 8) {
         // the unit after next: its row entry is loaded during this pair
         bool ok2;
-        const int r2n = fetch(ub + 8 + hh, ok2);
+        const int r2n = fetch(ub + 16 + hh, ok2);
         const int aafter = a;
         // the next unit: its partner's staged data is loaded during this pair
         const int tnext = staged(r1, ok1);

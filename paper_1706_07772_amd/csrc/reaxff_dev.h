@@ -266,6 +266,16 @@ __device__ __forceinline__ double quad_sum(double v) {
   return v;
 }
 
+// Sum over each group of 8 lanes, left in the group's last lane (7, 15, ...):
+// row shifts by 1, 2, 4 (lanes shifted in from before a 16-lane row read 0);
+// every lane of a group must be active.
+__device__ __forceinline__ double oct_sum_last(double v) {
+  v += dpp_d<0x111>(v);          // row_shr:1
+  v += dpp_d<0x112>(v);          // row_shr:2
+  v += dpp_d<0x114>(v);          // row_shr:4
+  return v;
+}
+
 // Sum over each 16-lane row, left in the row's last lane (15, 31, 47, 63);
 // every lane of a row must be active.
 __device__ __forceinline__ double row_sum_last(double v) {
