@@ -286,19 +286,6 @@ __device__ __forceinline__ double row_sum_last(double v) {
   return v;
 }
 
-// Sum over each half wavefront (lanes 0-31, 32-63), left in the half's last
-// lane (31, 63); other lanes hold partial sums.  Row shifts by 1, 2, 4, 8
-// make lane 15 of each 16-lane row the row's sum; the broadcast of lane 15 of
-// rows 0 and 2 into rows 1 and 3 adds the half's first row.  Every lane of a
-// half must be active.
-__device__ __forceinline__ double half_sum_last(double v) {
-  v += dpp_d<0x111>(v);          // row_shr:1
-  v += dpp_d<0x112>(v);          // row_shr:2
-  v += dpp_d<0x114>(v);          // row_shr:4
-  v += dpp_d<0x118>(v);          // row_shr:8
-  v += dpp_d<0x142, 0xA>(v);     // row_bcast:15 into rows 1 and 3
-  return v;
-}
 // lane l takes the (uniform) value v, the other lanes keep old
 __device__ __forceinline__ int writelane_i(int v, int l, int old) {
   asm("v_writelane_b32 %0, %1, m0" : "+v"(old) : "s"(v), "{m0}"(l));
