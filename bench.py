@@ -162,49 +162,59 @@ def read_profile(handle, lib):
             for i in range(k) if calls[i]}
 
 
-def bench_qeq(ff, n, far_pairs, reps=3, tol=1e-6, traj=None):
-    """Charge equilibration over the lists of the last build (the 1,044,000-atom
-    workload): H rows, then both systems by preconditioned CG from a zero start to
-    the paper's relative residual of 1e-6; per-kernel times from a profiled pass.
-    The matrix-vector product is HBM-bound: algorithmic bytes per product =
-    stored entries x 12 B (index + value) + n x 40 B (both directions read, the
-    product written, row length and type read)."""
+def bench_qeq(ff, n, far_pairs, traj, reps=3, tol=1e-6):
+    """Charge equilibration over the lists of the 1,044,000-atom workload, with
+    each product (reaxff_set_qeq_product): "auto" (matrix-free over the half far
+    list, the default on this grid) and "stored" (H rows built once per call).
+    Both systems by preconditioned CG from a zero start to the paper's relative
+    residual of 1e-6, per-kernel times from a profiled pass; then along a
+    trajectory (below).  The stored rows' product is HBM-bound: algorithmic
+    bytes per product = stored entries x 12 B (index + value) + n x 40 B (both
+    directions read, the product written, row length and type read).
+    traj: (pos, type, q, box, velocities) of the workload."""
     import torch
 
     import reaxff_synth as rs
     from paper_1706_07772_amd.binding import load_library
     qp = rs.draw_qeq_params(0)
     lib = load_library()
-    q, it, res = ff.qeq(n, qp, tol=tol, guess=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        q, it, res = ff.qeq(n, qp, tol=tol, guess=False, q=q)
-    torch.cuda.synchronize()
-    ms = 1e3 * (time.perf_counter() - t0) / reps
-    lib.reaxff_profile(ff._h, 1)
-    for _ in range(reps):
-        ff.qeq(n, qp, tol=tol, guess=False, q=q)
-    torch.cuda.synchronize()
-    kern = read_profile(ff._h, lib)
-    lib.reaxff_profile(ff._h, 0)
+    pos, typ, qq, box, vel = traj
     nnz = 2 * far_pairs
-    spmv = kern.get("qeq_spmv", {})
-    out = {"workload": "petn_1044000 positions of the force benchmark; chi, J from seed 0",
-           "tol": tol, "iterations": it, "residuals": list(res), "ms_per_qeq": ms,
-           "kernels_ms_avg": {k: round(v["ms_avg"], 4) for k, v in kern.items() if k.startswith("qeq")},
-           "stored_entries": nnz}
-    if spmv:
-        byts = nnz * 12.0 + n * 40.0
-        ach = byts / (spmv["ms_avg"] * 1e-3) / 1e9
-        out["spmv_roofline"] = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                                "frac": ach / PEAK_HBM_GBS, "bytes_per_launch": byts,
-                                "avg_ms": spmv["ms_avg"]}
-    if traj is not None:
+
+    def measure(mode):
+        ff.set_qeq_product(mode)
+        ff.build_lists(pos, typ, box)
+        q, it, res = ff.qeq(n, qp, tol=tol, guess=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            q, it, res = ff.qeq(n, qp, tol=tol, guess=False, q=q)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / reps
+        lib.reaxff_profile(ff._h, 1)
+        for _ in range(reps):
+            ff.qeq(n, qp, tol=tol, guess=False, q=q)
+        torch.cuda.synchronize()
+        kern = read_profile(ff._h, lib)
+        lib.reaxff_profile(ff._h, 0)
+        out = {"tol": tol, "iterations": it, "residuals": list(res), "ms_per_qeq": ms,
+               "kernels_ms_avg": {k: round(v["ms_avg"], 4) for k, v in kern.items() if k.startswith("qeq")}}
+        if "qeq_half" in kern:
+            out["product"] = "matrix-free, half far list"
+            out["ms_per_product"] = kern["qeq_half"]["ms_avg"] + kern["qeq_hreduce"]["ms_avg"]
+        else:
+            out["product"] = "stored rows"
+            spmv = kern["qeq_spmv"]
+            out["ms_per_product"] = spmv["ms_avg"]
+            out["stored_entries"] = nnz
+            byts = nnz * 12.0 + n * 40.0
+            ach = byts / (spmv["ms_avg"] * 1e-3) / 1e9
+            out["spmv_roofline"] = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                    "frac": ach / PEAK_HBM_GBS, "bytes_per_launch": byts,
+                                    "avg_ms": spmv["ms_avg"]}
         # along a trajectory, as an MD run uses it: one velocity-Verlet step
         # (dt 0.1 fs, lists rebuilt at the new positions), then the charges
         # from the extrapolation of the previous solutions
-        pos, typ, qq, box, vel = traj
         P = pos.clone()
         V = vel.clone()
         ff.qeq(n, qp, tol=tol, guess=False)   # forget the zero-start solutions above
@@ -219,6 +229,15 @@ def bench_qeq(ff, n, far_pairs, reps=3, tol=1e-6, traj=None):
             its.append(it)
         out["trajectory"] = {"steps": 8, "dt_fs": 0.1, "iterations": its,
                              "ms_per_qeq": times, "ms_per_qeq_last4": sum(times[-4:]) / 4}
+        return out
+
+    try:
+        out = {"workload": "petn_1044000 positions of the force benchmark; chi, J from seed 0"}
+        out.update(measure("auto"))
+        out["stored"] = measure("stored")
+    finally:
+        ff.set_qeq_product("auto")
+        ff.build_lists(pos, typ, box)
     return out
 
 
@@ -630,7 +649,7 @@ def main():
         step()
         v0 = rs.maxwell_boltzmann(system.type, params.atom["mass"], 300.0, seed=103)
         qeq = bench_qeq(ff, n, counts["far_pairs"],
-                        traj=(pos, typ, q, box, torch.tensor(v0, dtype=torch.float64, device=dev)))
+                        (pos, typ, q, box, torch.tensor(v0, dtype=torch.float64, device=dev)))
 
     md = None
     if not args.no_md:

@@ -318,12 +318,30 @@ typedef struct reaxff_qeq_params {
  * 4x1 - 6x2 + 4x3 - x4, newest first), else from zero (and forget them).
  * q [dev] (n) the charges, s_out/t_out [dev] (n) or NULL the two solutions,
  * all in the caller's order; iters [host] or NULL the iterations taken;
- * resid [host] (2) or NULL the final relative residuals.  The context owns
- * H (n x row width entries of 12 bytes) and the solver vectors.  One host
+ * resid [host] (2) or NULL the final relative residuals.  The product with
+ * H is chosen by reaxff_set_qeq_product.  The context owns the solver vectors
+ * and, for stored rows, H (n x row width entries of 12 bytes).  One host
  * synchronisation per iteration (the residual norms). */
 int reaxff_qeq(reaxff_ctx* ctx, int64_t n, const reaxff_qeq_params* qp, double tol,
                int32_t maxit, int32_t guess, double* q, double* s_out, double* t_out,
                int32_t* iters, double* resid, hipStream_t stream);
+
+/* How reaxff_qeq multiplies by H [host].  REAXFF_QEQ_STORED: the paper's way
+ * (Section 3.3): the matrix elements within r_nonb are computed once per call
+ * into rows (both halves of the symmetric matrix, so a product only gathers)
+ * and each CG iteration reads them.  REAXFF_QEQ_AUTO (the default): when the
+ * last build left the far list in its half form (each pair once; grids of at
+ * least 2 reach + 1 cells per edge, the nonbonded term's half evaluation), no
+ * matrix is stored: each product evaluates H_ij of every far pair within
+ * r_nonb once and adds it to both atoms; otherwise the stored rows.  The
+ * matrix-free product skips the row build (about three products' time) and
+ * the rows' memory for ~15% more time per product, so it is the faster choice
+ * below ~20 iterations, as with an extrapolated start along a trajectory.
+ * Charges agree to the order of floating-point additions.  Returns REAXFF_OK,
+ * or REAXFF_ERR_ARG for a null context or another mode. */
+#define REAXFF_QEQ_AUTO 0
+#define REAXFF_QEQ_STORED 1
+int reaxff_set_qeq_product(reaxff_ctx* ctx, int32_t mode);
 
 /* ---- Exact forces on a subset of the atoms ---------------------------------
  *

@@ -155,6 +155,7 @@ def load_library():
     lib.reaxff_profile.argtypes = [vp, i32]
     lib.reaxff_set_overlap.argtypes = [vp, i32]
     lib.reaxff_set_nb_run.argtypes = [vp, i32]
+    lib.reaxff_set_qeq_product.argtypes = [vp, i32]
     lib.reaxff_math_eval.argtypes = [i32, i64, vp, vp, vp, vp]
     lib.reaxff_profile_read.argtypes = [vp, i32, vp, vp, vp]
     lib.reaxff_last_error.restype = ctypes.c_char_p
@@ -359,6 +360,14 @@ class ReaxFF:
     def set_nb_run(self, run_max: int):
         """Longest run of cells the half nonbonded evaluation takes per workgroup (1..16)."""
         self._check(self._lib.reaxff_set_nb_run(self._h, int(run_max)))
+
+    #: reaxff_set_qeq_product modes
+    QEQ_PRODUCTS = {"auto": 0, "stored": 1}
+
+    def set_qeq_product(self, mode: str):
+        """How qeq multiplies by H: "auto" (matrix-free over the half far list when
+        the last build left it, the default) or "stored" (rows built once per call)."""
+        self._check(self._lib.reaxff_set_qeq_product(self._h, self.QEQ_PRODUCTS[mode]))
 
     def qeq(self, n: int, qparams, tol: float = 1e-6, maxit: int = 500, guess: bool = True,
             q=None, want_st: bool = False, device=None, check: bool = True):

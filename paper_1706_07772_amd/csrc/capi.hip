@@ -427,7 +427,7 @@ void reaxff_destroy(reaxff_ctx* c) {
     if (p) (void)hipFree(p);
   {
     rx::Qeq& Q = c->qeq;
-    void* qp[] = {Q.hj, Q.hv, Q.hcnt, Q.x, Q.r, Q.p, Q.ap, Q.red, Q.need, Q.hist[0], Q.hist[1], Q.hist[2], Q.hist[3]};
+    void* qp[] = {Q.hj, Q.hv, Q.hcnt, Q.part, Q.tab, Q.x, Q.r, Q.p, Q.ap, Q.red, Q.need, Q.hist[0], Q.hist[1], Q.hist[2], Q.hist[3]};
     for (void* p : qp)
       if (p) (void)hipFree(p);
     if (Q.red_host) (void)hipHostFree(Q.red_host);

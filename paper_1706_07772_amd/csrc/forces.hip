@@ -799,14 +799,6 @@ __global__ __launch_bounds__(NBC_BS) void k_nonbonded(const DevParams* __restric
 constexpr int NBH_BS = 1024, NBH_WAVES = NBH_BS / 64;
 constexpr int NBH_MG = 128;   // centre atoms of a run per pass (two per lane of one wavefront)
 
-// runs of the grid and the cells of run r: first cell, count
-__host__ __device__ __forceinline__ int run_rows(const Grid& g) { return (g.nc[2] + g.run - 1) / g.run; }
-__device__ __forceinline__ void run_cells(const Grid& g, int r, int& cfirst, int& nk) {
-  const int nrz = run_rows(g), rz = r % nrz, col = r / nrz;
-  cfirst = col * g.nc[2] + rz * g.run;
-  nk = g.nc[2] - rz * g.run < g.run ? g.nc[2] - rz * g.run : g.run;
-}
-
 __global__ __launch_bounds__(NBH_BS) __attribute__((amdgpu_waves_per_eu(4))) void k_nonbonded_half(
     const DevParams* __restrict__ P, Grid g, Lists L, Work W, int nrun, int per_xcd,
     double* __restrict__ energies) {
@@ -1088,81 +1080,19 @@ __global__ __launch_bounds__(BS) void k_nb_energy(int ncell, const double2* __re
 }
 
 // Nonbonded force of each atom j from the partial arrays of the runs whose
-// upper window holds it.  Those are the runs of the cells z - oz of the
-// columns at offsets (ox, oy) = column(j) - column(run) with (ox, oy)
-// lexicographically positive (oz in [-R, R]), or ox = oy = 0 (oz in [0, R]:
-// the window's upper part starts at the run's first cell).  In the run's chunk
-// sequence j lies in column (ox, oy) and in that column's unwrapped or wrapped
-// z range, chunk q; its staged index is nbtab[q] + j (an empty run's offsets
-// put every atom out of range).  Writes the per-atom accumulator the
-// hydrogen-bond kernels then add to.  R: the stencil reach.
+// upper window holds it (for_upper_windows).  Writes the per-atom
+// accumulator the hydrogen-bond kernels then add to.  R: the stencil reach.
 template <int R>
 __global__ __launch_bounds__(BS) void k_nb_reduce(Grid g, Lists L, Work W) {
   const int64_t j = xcd_block() * blockDim.x + threadIdx.x;
   if (j >= L.n) return;
-  const int nrz = run_rows(g);
-  const int cj = L.cell_of[j];
-  const int jz = cj % g.nc[2], jy = (cj / g.nc[2]) % g.nc[1], jx = cj / (g.nc[1] * g.nc[2]);
-  // the runs of the cells jz - oz, oz in [-R, R] (the same in every column):
-  // their z index, the side of their window holding j (chunk 2 col + side)
-  // and whether one of those cells has oz >= 0 (the centre column's upper part)
-  int nr = 0, rzs[2 * R + 1], side[2 * R + 1];
-  bool up[2 * R + 1];
-  {
-    int last = -1;
-#pragma unroll
-    for (int oz = -R; oz <= R; ++oz) {
-      int cz = jz - oz;
-      if (cz < 0 || cz >= g.nc[2]) {
-        if (!g.periodic) continue;
-        cz += cz < 0 ? g.nc[2] : -g.nc[2];
-      }
-      const int rz = cz / g.run;
-      if (rz == last) {   // cells of one run follow each other
-        up[nr - 1] = up[nr - 1] || oz >= 0;
-        continue;
-      }
-      last = rz;
-      const int z0 = rz * g.run;
-      int za0, za1, zb0, zb1;
-      window_ranges(g, z0, za0, za1, zb0, zb1);
-      const bool in_a = jz >= za0 && jz < za1;
-      const bool wrap_first = zb1 > zb0 && z0 - R < 0;
-      rzs[nr] = rz;
-      side[nr] = (in_a != wrap_first) ? 0 : 1;
-      up[nr] = oz >= 0;
-      ++nr;
-    }
-  }
   double fx = 0.0, fy = 0.0, fz = 0.0;
-  for (int ox = 0; ox <= R; ++ox) {
-    int cx = jx - ox;
-    if (cx < 0) {
-      if (!g.periodic) continue;
-      cx += g.nc[0];
-    }
-    for (int oy = ox == 0 ? 0 : -R; oy <= R; ++oy) {
-      int cy = jy - oy;
-      if (cy < 0 || cy >= g.nc[1]) {
-        if (!g.periodic) continue;
-        cy += cy < 0 ? g.nc[1] : -g.nc[1];
-      }
-      const int col = (ox + R) * g.span[1] + (oy + R);
-      const int64_t rcol = (int64_t)(cx * g.nc[1] + cy) * nrz;
-      const bool own = ox == 0 && oy == 0;
-#pragma unroll
-      for (int k = 0; k < 2 * R + 1; ++k) {
-        if (k >= nr || (own && !up[k])) continue;
-        const int64_t r = rcol + rzs[k];
-        const int t = W.nbtab[r * NB_QMAX + 2 * col + side[k]] + (int)j;
-        if ((unsigned)t >= (unsigned)NB_HALF_CAP) continue;   // an empty run
-        const double* __restrict__ part = W.nbpart + r * 3 * NB_HALF_CAP + 3 * t;
-        fx += part[0];
-        fy += part[1];
-        fz += part[2];
-      }
-    }
-  }
+  for_upper_windows<R>(g, L.cell_of[j], W.nbtab, (int)j, [&](int64_t r, int t) {
+    const double* __restrict__ part = W.nbpart + r * 3 * NB_HALF_CAP + 3 * t;
+    fx += part[0];
+    fy += part[1];
+    fz += part[2];
+  });
   W.fnb[j] = make_double4(fx, fy, fz, 0.0);
 }
 
@@ -1230,7 +1160,7 @@ const char* const kKernelNames[KID_COUNT] = {
     "bondtest", "compact", "mirror", "zero", "gather_q", "bo_prime", "delta_prime", "bo_corr", "atom_state",
     "atom_energy", "tasks", "angles", "torsions", "hbonds", "hb_acceptors", "nonbonded", "back_s", "back_corr",
     "back_dp", "forces", "batch", "nb_reduce", "nb_energy", "energy_fold", "qeq_rows", "qeq_spmv", "qeq_vec", "sur_desc", "sur_net", "sur_pairw",
-    "sur_gather", "sur_mirror"};
+    "sur_gather", "sur_mirror", "qeq_half", "qeq_hreduce"};
 
 int launch_forces(const DevParams* P, const Grid& g, const Lists& L, Work& W, const double* q,
                   hipStream_t side, hipEvent_t ev_fork, hipEvent_t ev_join, double* forces,

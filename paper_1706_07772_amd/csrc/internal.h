@@ -16,7 +16,7 @@ enum KernelId {
   KID_ATOM_STATE, KID_ATOM_ENERGY, KID_TASKS, KID_ANGLES, KID_TORSIONS, KID_HBONDS, KID_HB_ACC, KID_NONBONDED,
   KID_BACK_S, KID_BACK_CORR, KID_BACK_DP, KID_FORCES, KID_BATCH, KID_NB_REDUCE, KID_NB_ENERGY, KID_ENERGY_FOLD,
   KID_QEQ_ROWS, KID_QEQ_SPMV, KID_QEQ_VEC, KID_SUR_DESC, KID_SUR_NET, KID_SUR_PAIRW, KID_SUR_GATHER,
-  KID_SUR_MIRROR, KID_COUNT
+  KID_SUR_MIRROR, KID_QEQ_HALF, KID_QEQ_HREDUCE, KID_COUNT
 };
 extern const char* const kKernelNames[KID_COUNT];
 
@@ -113,6 +113,10 @@ struct Qeq {
   double2* hist[4] = {nullptr, nullptr, nullptr, nullptr};
   int head = 0, nhist = 0;
   int64_t hist_n = -1;
+  double* part = nullptr;    // matrix-free product: per-run partial arrays [nrun][NB_HALF_CAP][2]
+  int32_t* tab = nullptr;    // and per-run chunk offsets [nrun][NB_QMAX]
+  int64_t cap_part = 0, cap_tab = 0;
+  int32_t mode = 0;          // REAXFF_QEQ_AUTO or REAXFF_QEQ_STORED
 };
 
 // species-analysis work arrays (device): union-find parents over caller

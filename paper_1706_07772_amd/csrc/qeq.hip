@@ -391,6 +391,312 @@ __global__ __launch_bounds__(QB) void k_qeq_charges(Lists L, const double2* __re
   }
 }
 
+// ---------------------------------------------------------------------------
+// Matrix-free product over the half far list.  When the last build left the
+// far rows in the half, run-window form (those the nonbonded term walks: each
+// pair within r_nonb once, as a slot in the window of the centre's run), H x
+// needs no stored matrix: the workgroup of a run stages its upper window
+// (positions and both search directions) in LDS, evaluates H_ij of each of
+// its pairs once, adds H_ij x_j to the centre (sums over the 8 lanes of a
+// unit) and H_ij x_i to the partner (an LDS accumulator), and stores the
+// accumulators to the run's partial array; k_qeq_hreduce then sums, for each
+// atom, the partial arrays of the runs whose upper window holds it and adds
+// J_i x_i and the dot products of the CG step.  H_ij is k_qeq_rows's element
+// (the same taper and shielded Coulomb), and each pair is taken once, as in
+// the paper's storage of unique entries.  Against the stored rows: no 12-byte
+// entries for both halves of the matrix (5.2 GB at 1.04M atoms) and no row
+// build, for ~15% more time per product.
+// ---------------------------------------------------------------------------
+constexpr int QH_BS = 1024, QH_WAVES = QH_BS / 64;
+constexpr int QH_MG = 128;   // centre atoms of a run per pass (two per lane of one wavefront)
+
+__global__ __launch_bounds__(QH_BS) void k_qeq_half(const DevParams* __restrict__ P, Grid g, Lists L, int nrun,
+                                                    int per_xcd, const double2* __restrict__ x,
+                                                    double* __restrict__ part, int32_t* __restrict__ tab) {
+  __shared__ double sg3[NT * NT];
+  __shared__ double sxx[NB_HALF_CAP], sxy[NB_HALF_CAP], sxz[NB_HALF_CAP], sxs[NB_HALF_CAP], sxt[NB_HALF_CAP];
+  __shared__ double fas[NB_HALF_CAP], fat[NB_HALF_CAP];
+  __shared__ unsigned char sty[NB_HALF_CAP];
+  __shared__ int q_s0[NB_QMAX], q_base[NB_QMAX + 1];
+  __shared__ double q_sh[NB_QMAX][3];
+  __shared__ int upre[QH_MG + 1];
+  __shared__ double ixx[QH_MG], ixy[QH_MG], ixz[QH_MG], ixs[QH_MG], ixt[QH_MG];
+  __shared__ int ity[QH_MG], icnt[QH_MG], ilo[QH_MG];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int r = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+  if (r >= nrun) return;
+  int c, nk;
+  run_cells(g, r, c, nk);
+  const int a0 = L.cell_start[c], m = L.cell_start[c + nk] - a0;
+  const int nq = stencil_chunks(g);
+  if (m == 0) {   // no pairs: chunk offsets that send the reduce past every slot
+    if (tid < nq) tab[(int64_t)r * NB_QMAX + tid] = -0x40000000;
+    return;
+  }
+  if (tid < NT * NT) sg3[tid] = P->pair[tid].g3;
+  const bool shifted = g.periodic && g.shift_ok;
+  const bool minimg = g.periodic && !g.shift_ok;
+  if (tid < nq) {
+    int s0, s1;
+    double sx, sy, sz;
+    window_chunk(g, L.cell_start, c, tid, s0, s1, sx, sy, sz);
+    q_s0[tid] = s0;
+    q_base[tid + 1] = s1 - s0;
+    q_sh[tid][0] = shifted ? sx : 0.0;
+    q_sh[tid][1] = shifted ? sy : 0.0;
+    q_sh[tid][2] = shifted ? sz : 0.0;
+  }
+  __syncthreads();
+  if (wv == 0) {
+    const int v = wave_incl_scan(lane < nq ? q_base[lane + 1] : 0);
+    if (lane < nq) q_base[lane + 1] = v;
+    if (lane == 0) q_base[0] = 0;
+  }
+  __syncthreads();
+  const int nst = q_base[nq];
+  // the run's own chunk: its column is the middle one, and its unwrapped z
+  // range comes second when the window wraps below the run
+  const int z0 = c % g.nc[2];
+  const int col_own = g.reach * g.span[1] + g.reach;
+  const bool wrap_first = g.periodic && z0 - g.reach < 0;
+  const int q_own = 2 * col_own + (wrap_first ? 1 : 0);
+  const int S0 = q_base[q_own] + (a0 - q_s0[q_own]);
+  const int nup = nst - S0;                            // <= NB_HALF_CAP (checked by the sweep)
+  // for the reduce: atom j of chunk q has staged index tab[q] + j
+  if (tid < nq) tab[(int64_t)r * NB_QMAX + tid] = q_base[tid] - S0 - q_s0[tid];
+  // staging: wavefront w copies the upper-window parts of chunks w, w + 16,
+  // ...; its lanes stride a chunk's atoms, which are contiguous in memory
+  for (int q = q_own + wv; q < nq; q += QH_WAVES) {
+    const int b = q_base[q], e = q_base[q + 1];
+    const int sb = b > S0 ? b : S0, src = q_s0[q] - b;
+    const double hx = q_sh[q][0], hy = q_sh[q][1], hz = q_sh[q][2];
+    for (int s0 = sb; s0 < e; s0 += 128) {
+      double4 v[2];
+      double2 xv[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int s = s0 + 64 * u + lane;
+        if (s < e) {
+          v[u] = L.xs[src + s];
+          xv[u] = x[src + s];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int s = s0 + 64 * u + lane;
+        if (s < e) {
+          const int t = s - S0;
+          sxx[t] = v[u].x - hx;
+          sxy[t] = v[u].y - hy;
+          sxz[t] = v[u].z - hz;
+          sty[t] = (unsigned char)(int)v[u].w;
+          sxs[t] = xv[u].x;
+          sxt[t] = xv[u].y;
+          fas[t] = fat[t] = 0.0;
+        }
+      }
+    }
+  }
+  const double iR = P->inv_r_nonb, rn2c = P->rn2;
+  for (int g0 = 0; g0 < m; g0 += QH_MG) {
+    const int mg = m - g0 < QH_MG ? m - g0 : QH_MG;
+    if (g0 > 0) __syncthreads();   // the previous pass's units done
+    if (wv == 0) {   // the pass's centres, two per lane: 2 lane and 2 lane + 1
+      int nu[2] = {0, 0};
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int k = 2 * lane + h;
+        if (k < mg) {
+          const int i = a0 + g0 + k;
+          const int cnt = L.far_cnt[i], lo = L.far_lo[i];
+          const double4 xi = L.xs[i];
+          const double2 vi = x[i];
+          ixx[k] = xi.x;
+          ixy[k] = xi.y;
+          ixz[k] = xi.z;
+          ixs[k] = vi.x;
+          ixt[k] = vi.y;
+          ity[k] = (int)xi.w;
+          icnt[k] = cnt;
+          ilo[k] = lo;
+          nu[h] = (cnt - lo + 7) >> 3;   // units of 8 entries
+        }
+      }
+      const int v = wave_incl_scan(nu[0] + nu[1]);
+      upre[2 * lane + 1] = v - nu[1];
+      upre[2 * lane + 2] = v;
+      if (lane == 0) upre[0] = 0;
+    }
+    __syncthreads();   // staging and the pass's centres in place
+    // units of 8 row entries, a contiguous share per wavefront, one unit per
+    // group of 8 lanes at a time (the centre is uniform over a group); the
+    // row entry of the unit after next and the staged data of the next one
+    // are loaded during each pair
+    const int U = __builtin_amdgcn_readfirstlane(upre[mg]);
+    const int wu = __builtin_amdgcn_readfirstlane(wv);
+    const int u0 = U * wu / QH_WAVES, u1 = U * (wu + 1) / QH_WAVES;
+    if (u0 < u1) {
+      const int hh = lane >> 3, sl = lane & 7;
+      int a = 0, ua = 0, un = 0, lo = 0, cn = 0;
+      const int32_t* __restrict__ rowp = L.far_j;
+      auto enter = [&](int na) {
+        a = na;
+        ua = upre[a];
+        un = upre[a + 1];
+        lo = ilo[a];
+        cn = icnt[a];
+        rowp = L.far_j + (int64_t)(a0 + g0 + a) * L.far_w;
+      };
+      auto fetch = [&](int u, bool& ok) {
+        ok = false;
+        if (u >= u1) return 0;
+        if (un <= u) {
+          int na = a + 1;
+          while (upre[na + 1] <= u) ++na;
+          enter(na);
+        }
+        const int k = lo + ((u - ua) << 3) + sl;
+        ok = k < cn;
+        return ok ? rowp[k] : 0;
+      };
+      auto staged = [&](int raw, bool ok) {
+        const int t = raw - S0;
+        return ok && (unsigned)t < (unsigned)nup ? t : -1;
+      };
+      const int uh = u0 + hh;
+      enter(last_le(upre, mg, uh < u1 ? uh : u1 - 1));
+      bool ok0, ok1;
+      const int r0 = fetch(uh, ok0);
+      const int acur0 = a;
+      int r1 = fetch(uh + 8, ok1);
+      int anext = a;
+      int tnow = staged(r0, ok0), anow = acur0;
+      double jx, jy, jz, js, jt;
+      int jty;
+      {
+        const int t = tnow >= 0 ? tnow : 0;
+        jx = sxx[t];
+        jy = sxy[t];
+        jz = sxz[t];
+        js = sxs[t];
+        jt = sxt[t];
+        jty = sty[t];
+      }
+      int cur = anow;
+      double xix = ixx[cur], xiy = ixy[cur], xiz = ixz[cur], vs = ixs[cur], vt = ixt[cur];
+      const double* __restrict__ g3i = sg3 + ity[cur] * NT;
+      double ys = 0.0, yt = 0.0;
+      auto flush = [&]() {   // over the 8 lanes, into the last
+        ys = oct_sum_last(ys);
+        yt = oct_sum_last(yt);
+        if (sl == 7) {
+          const int t = g0 + cur;   // the centre's staged index: slot - S0 = i - a0
+          atomicAdd(&fas[t], ys);
+          atomicAdd(&fat[t], yt);
+        }
+        ys = yt = 0.0;
+      };
+      for (int ub = u0; ub < u1; ub += 8) {
+        bool ok2;
+        const int r2n = fetch(ub + 16 + hh, ok2);
+        const int aafter = a;
+        const int tnext = staged(r1, ok1);
+        double nx, ny, nz, ns, nt;
+        int nty;
+        {
+          const int t = tnext >= 0 ? tnext : 0;
+          nx = sxx[t];
+          ny = sxy[t];
+          nz = sxz[t];
+          ns = sxs[t];
+          nt = sxt[t];
+          nty = sty[t];
+        }
+        if (anow != cur) {
+          flush();
+          cur = anow;
+          xix = ixx[cur];
+          xiy = ixy[cur];
+          xiz = ixz[cur];
+          vs = ixs[cur];
+          vt = ixt[cur];
+          g3i = sg3 + ity[cur] * NT;
+        }
+        if (tnow >= 0) {
+          double dx = jx - xix, dy = jy - xiy, dz = jz - xiz;
+          if (minimg) {
+            dx = min_image(dx, g.L[0], g.invL[0]);
+            dy = min_image(dy, g.L[1], g.invL[1]);
+            dz = min_image(dz, g.L[2], g.invL[2]);
+          }
+          const double rr = dx * dx + dy * dy + dz * dz;
+          if (!(L.cut_check && rr > rn2c)) {   // else a skin entry beyond r_nonb
+            const double rv = rr * rsq_f(rr);
+            const double u = rv * iR;
+            const double u4 = (u * u) * (u * u);
+            const double tap = fma(u4, fma(u, fma(u, fma(u, 20.0, -70.0), 84.0), -35.0), 1.0);
+            const double h = tap * C_ELE * rcbrt_f(fma(rr, rv, g3i[jty]));
+            ys = fma(h, js, ys);
+            yt = fma(h, jt, yt);
+            atomicAdd(&fas[tnow], h * vs);
+            atomicAdd(&fat[tnow], h * vt);
+          }
+        }
+        tnow = tnext;
+        anow = anext;
+        jx = nx;
+        jy = ny;
+        jz = nz;
+        js = ns;
+        jt = nt;
+        jty = nty;
+        r1 = r2n;
+        ok1 = ok2;
+        anext = aafter;
+      }
+      flush();
+    }
+  }
+  __syncthreads();
+  double* __restrict__ pr = part + (int64_t)r * 2 * NB_HALF_CAP;
+  for (int t = tid; t < nup; t += QH_BS) {
+    pr[2 * t] = fas[t];
+    pr[2 * t + 1] = fat[t];
+  }
+}
+
+// y = H x from the partial arrays of k_qeq_half: for each atom j, the sum
+// over the runs whose upper window holds it (for_upper_windows), plus
+// J_j x_j; with `set`, the block's sums of x . y per system go to the slot
+// fields 0 and 1.  R: the stencil reach.
+template <int R>
+__global__ __launch_bounds__(QB) void k_qeq_hreduce(Grid g, Lists L, const int32_t* __restrict__ tab,
+                                                    const double* __restrict__ part, QeqPar qp,
+                                                    const double2* __restrict__ x, double2* __restrict__ y,
+                                                    double* __restrict__ set) {
+  const int64_t j = xcd_block() * QB + threadIdx.x;
+  double ds = 0.0, dt = 0.0;
+  if (j < L.n) {
+    double as = 0.0, at = 0.0;
+    for_upper_windows<R>(g, L.cell_of[j], tab, (int)j, [&](int64_t r, int t) {
+      const double2 pv = *(const double2*)(part + r * 2 * NB_HALF_CAP + 2 * t);
+      as += pv.x;
+      at += pv.y;
+    });
+    const double2 xj = x[j];
+    const double Jj = qp.J[L.type_s[j]];
+    const double2 yj = make_double2(fma(Jj, xj.x, as), fma(Jj, xj.y, at));
+    y[j] = yj;
+    ds = xj.x * yj.x;
+    dt = xj.y * yj.y;
+  }
+  if (set) {
+    const int f[2] = {0, 1};
+    const double v[2] = {ds, dt};
+    slot_add<2>(set, f, v);
+  }
+}
+
 // initial guess from the history ring (caller order, newest first):
 // x_i = sum_k c_k hist_k[perm i]
 __global__ __launch_bounds__(QB) void k_qeq_guess(Lists L, const double2* __restrict__ h0,
@@ -457,6 +763,14 @@ int qgrow(reaxff_ctx* c, T*& p, int64_t& cap, int64_t need) {
 
 extern "C" {
 
+int reaxff_set_qeq_product(reaxff_ctx* c, int32_t mode) {
+  if (!c) return REAXFF_ERR_ARG;
+  if (mode != REAXFF_QEQ_AUTO && mode != REAXFF_QEQ_STORED)
+    return qfail(c, REAXFF_ERR_ARG, "reaxff_set_qeq_product: mode must be REAXFF_QEQ_AUTO or REAXFF_QEQ_STORED");
+  c->qeq.mode = mode;
+  return REAXFF_OK;
+}
+
 int reaxff_qeq(reaxff_ctx* c, int64_t n, const reaxff_qeq_params* qpar, double tol, int32_t maxit,
                int32_t guess, double* q, double* s_out, double* t_out, int32_t* iters, double* resid,
                hipStream_t st) {
@@ -499,7 +813,7 @@ int reaxff_qeq(reaxff_ctx* c, int64_t n, const reaxff_qeq_params* qpar, double t
   if (qgrow(c, Q.red, Q.cap_red, nsets * ESLOT * QF)) return REAXFF_ERR_HIP;
   if (!Q.red_host) QHIP(c, hipHostMalloc(&Q.red_host, sizeof(double) * ESLOT * QF, hipHostMallocDefault));
   if (!Q.need) QHIP(c, hipMalloc(&Q.need, sizeof(int32_t)));
-  // H rows: width from the density estimate, grown once if a row overflows
+  // stored rows: width from the density estimate
   const Lists& L = c->L;
   const Grid& g = c->grid;
   if (Q.w == 0) {
@@ -513,7 +827,34 @@ int reaxff_qeq(reaxff_ctx* c, int64_t n, const reaxff_qeq_params* qpar, double t
   const int64_t ncell = (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
   if (stencil_chunks(g) > QRMAXQ) return qfail(c, REAXFF_ERR_STATE, "reaxff_qeq: stencil beyond the chunk table");
   const unsigned gc = xcd_grid((unsigned)((ncell + QWAVES - 1) / QWAVES));
-  for (int attempt = 0;; ++attempt) {
+  // the product: matrix-free over the half far rows when the build left them
+  // (and the stored rows are not asked for), else the stored rows
+  const bool half = Q.mode == REAXFF_QEQ_AUTO && L.nb_half != 0 && g.reach <= 2;
+  const int nrun = g.nc[0] * g.nc[1] * run_rows(g), per_run_xcd = (nrun + 7) / 8;
+  if (half) {
+    if (qgrow(c, Q.part, Q.cap_part, (int64_t)nrun * 2 * NB_HALF_CAP)) return REAXFF_ERR_HIP;
+    if (qgrow(c, Q.tab, Q.cap_tab, (int64_t)nrun * NB_QMAX)) return REAXFF_ERR_HIP;
+  }
+  auto product = [&](const double2* xin, double2* yout, double* set) {
+    if (half) {
+      c->prof.begin(KID_QEQ_HALF, st);
+      hipLaunchKernelGGL(k_qeq_half, dim3(8u * (unsigned)per_run_xcd), dim3(QH_BS), 0, st, c->dp, g, L, nrun,
+                         per_run_xcd, xin, Q.part, Q.tab);
+      c->prof.end(st);
+      c->prof.begin(KID_QEQ_HREDUCE, st);
+      if (g.reach == 1)
+        hipLaunchKernelGGL(k_qeq_hreduce<1>, dim3(ga), dim3(QB), 0, st, g, L, Q.tab, Q.part, qp, xin, yout, set);
+      else
+        hipLaunchKernelGGL(k_qeq_hreduce<2>, dim3(ga), dim3(QB), 0, st, g, L, Q.tab, Q.part, qp, xin, yout, set);
+      c->prof.end(st);
+    } else {
+      c->prof.begin(KID_QEQ_SPMV, st);
+      hipLaunchKernelGGL(k_qeq_spmv, dim3(gw), dim3(QB), 0, st, L, Q.hj, Q.hv, Q.hcnt, Q.w, qp, xin, yout, set);
+      c->prof.end(st);
+    }
+  };
+  // the stored rows, the width grown if a row overflows
+  for (int attempt = 0; !half; ++attempt) {
     if (qgrow(c, Q.hj, Q.cap_rows, n * (int64_t)Q.w)) return REAXFF_ERR_HIP;
     int64_t capv = Q.cap_rowsv;
     if (qgrow(c, Q.hv, capv, n * (int64_t)Q.w)) return REAXFF_ERR_HIP;
@@ -546,10 +887,7 @@ int reaxff_qeq(reaxff_ctx* c, int64_t n, const reaxff_qeq_params* qpar, double t
     auto h = [&](int a) -> const double2* { return a < k ? Q.hist[(Q.head - a + 4) % 4] : nullptr; };
     hipLaunchKernelGGL(k_qeq_guess, dim3(ga), dim3(QB), 0, st, L, h(0), h(1), h(2), h(3),
                        make_double4(cf[0], cf[1], cf[2], cf[3]), Q.x);
-    c->prof.begin(KID_QEQ_SPMV, st);
-    hipLaunchKernelGGL(k_qeq_spmv, dim3(gw), dim3(QB), 0, st, L, Q.hj, Q.hv, Q.hcnt, Q.w, qp, Q.x, Q.ap,
-                       (double*)nullptr);
-    c->prof.end(st);
+    product(Q.x, Q.ap, nullptr);
     hipLaunchKernelGGL(k_qeq_start, dim3(ga), dim3(QB), 0, st, L, qp, Q.ap, Q.x, Q.r, Q.p, start);
   } else {
     hipLaunchKernelGGL(k_qeq_start, dim3(ga), dim3(QB), 0, st, L, qp, (const double2*)nullptr, Q.x, Q.r, Q.p,
@@ -578,9 +916,7 @@ int reaxff_qeq(reaxff_ctx* c, int64_t n, const reaxff_qeq_params* qpar, double t
   const double* last = start;
   while ((res[0] > tol || res[1] > tol) && it < maxit) {
     double* cur = set_of(it);
-    c->prof.begin(KID_QEQ_SPMV, st);
-    hipLaunchKernelGGL(k_qeq_spmv, dim3(gw), dim3(QB), 0, st, L, Q.hj, Q.hv, Q.hcnt, Q.w, qp, Q.p, Q.ap, cur);
-    c->prof.end(st);
+    product(Q.p, Q.ap, cur);
     c->prof.begin(KID_QEQ_VEC, st);
     hipLaunchKernelGGL(k_qeq_update, dim3(ga), dim3(QB), 0, st, L, qp, last, cur, Q.x, Q.r, Q.p, Q.ap);
     c->prof.end(st);

@@ -416,6 +416,15 @@ __device__ __forceinline__ void stencil_chunk(const Grid& g, const int32_t* __re
                                               int& s0, int& s1, double& sx, double& sy, double& sz) {
   chunk_range<false>(g, cstart, c, q, s0, s1, sx, sy, sz);
 }
+// runs of the grid (Grid::run consecutive z cells of one column; the last
+// run of a column may be shorter) and the cells of run r: first cell, count
+__host__ __device__ __forceinline__ int run_rows(const Grid& g) { return (g.nc[2] + g.run - 1) / g.run; }
+__device__ __forceinline__ void run_cells(const Grid& g, int r, int& cfirst, int& nk) {
+  const int nrz = run_rows(g), rz = r % nrz, col = r / nrz;
+  cfirst = col * g.nc[2] + rz * g.run;
+  nk = g.nc[2] - rz * g.run < g.run ? g.nc[2] - rz * g.run : g.run;
+}
+
 // chunk q of the window of c's run (the numbering of far-row slots): the same
 // columns and order over the run's z ranges; every chunk of a cell's stencil
 // lies inside the window's chunk of the same column and side, so slots keep
@@ -423,6 +432,79 @@ __device__ __forceinline__ void stencil_chunk(const Grid& g, const int32_t* __re
 __device__ __forceinline__ void window_chunk(const Grid& g, const int32_t* __restrict__ cstart, int c, int q,
                                              int& s0, int& s1, double& sx, double& sy, double& sz) {
   chunk_range<true>(g, cstart, c, q, s0, s1, sx, sy, sz);
+}
+
+// The runs whose upper window (the half evaluation's LDS copy: the centre
+// column from the run's first atom on, and every later chunk) holds atom j of
+// cell cj, and j's staged index t there: visit(r, t) for each.  Those are the
+// runs of the cells z - oz of the columns at offsets (ox, oy) = column(j) -
+// column(run) with (ox, oy) lexicographically positive (oz in [-R, R]), or
+// ox = oy = 0 (oz in [0, R]: the window's upper part starts at the run's
+// first cell).  In the run's chunk sequence j lies in column (ox, oy) and in
+// that column's unwrapped or wrapped z range, chunk q; its staged index is
+// tab[r NB_QMAX + q] + j (an empty run's offsets put every atom out of range).
+// R: the stencil reach.
+template <int R, class F>
+__device__ __forceinline__ void for_upper_windows(const Grid& g, int cj, const int32_t* __restrict__ tab, int j,
+                                                  F&& visit) {
+  const int nrz = run_rows(g);
+  const int jz = cj % g.nc[2], jy = (cj / g.nc[2]) % g.nc[1], jx = cj / (g.nc[1] * g.nc[2]);
+  // the runs of the cells jz - oz, oz in [-R, R] (the same in every column):
+  // their z index, the side of their window holding j (chunk 2 col + side)
+  // and whether one of those cells has oz >= 0 (the centre column's upper part)
+  int nr = 0, rzs[2 * R + 1], side[2 * R + 1];
+  bool up[2 * R + 1];
+  {
+    int last = -1;
+#pragma unroll
+    for (int oz = -R; oz <= R; ++oz) {
+      int cz = jz - oz;
+      if (cz < 0 || cz >= g.nc[2]) {
+        if (!g.periodic) continue;
+        cz += cz < 0 ? g.nc[2] : -g.nc[2];
+      }
+      const int rz = cz / g.run;
+      if (rz == last) {   // cells of one run follow each other
+        up[nr - 1] = up[nr - 1] || oz >= 0;
+        continue;
+      }
+      last = rz;
+      const int z0 = rz * g.run;
+      int za0, za1, zb0, zb1;
+      window_ranges(g, z0, za0, za1, zb0, zb1);
+      const bool in_a = jz >= za0 && jz < za1;
+      const bool wrap_first = zb1 > zb0 && z0 - R < 0;
+      rzs[nr] = rz;
+      side[nr] = (in_a != wrap_first) ? 0 : 1;
+      up[nr] = oz >= 0;
+      ++nr;
+    }
+  }
+  for (int ox = 0; ox <= R; ++ox) {
+    int cx = jx - ox;
+    if (cx < 0) {
+      if (!g.periodic) continue;
+      cx += g.nc[0];
+    }
+    for (int oy = ox == 0 ? 0 : -R; oy <= R; ++oy) {
+      int cy = jy - oy;
+      if (cy < 0 || cy >= g.nc[1]) {
+        if (!g.periodic) continue;
+        cy += cy < 0 ? g.nc[1] : -g.nc[1];
+      }
+      const int col = (ox + R) * g.span[1] + (oy + R);
+      const int64_t rcol = (int64_t)(cx * g.nc[1] + cy) * nrz;
+      const bool own = ox == 0 && oy == 0;
+#pragma unroll
+      for (int k = 0; k < 2 * R + 1; ++k) {
+        if (k >= nr || (own && !up[k])) continue;
+        const int64_t r = rcol + rzs[k];
+        const int t = tab[r * NB_QMAX + 2 * col + side[k]] + j;
+        if ((unsigned)t >= (unsigned)NB_HALF_CAP) continue;   // an empty run
+        visit(r, t);
+      }
+    }
+  }
 }
 
 // largest k in [0, n) with b[k] <= t, for non-decreasing b with b[0] <= t

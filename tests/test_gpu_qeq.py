@@ -46,6 +46,33 @@ def gpu_qeq(ff, system, qp, tol, maxit=1000, guess=False, build=True):
     return q.cpu().numpy(), it, res, s.cpu().numpy(), t.cpu().numpy()
 
 
+def launches(ff):
+    """Kernel launch counts since profiling was switched on (name -> launches)."""
+    import ctypes
+    K = 64
+    ms = (ctypes.c_double * K)()
+    calls = (ctypes.c_int64 * K)()
+    names = (ctypes.c_char_p * K)()
+    k = ff._lib.reaxff_profile_read(ff._h, K, ms, calls, names)
+    return {names[i].decode(): int(calls[i]) for i in range(k)}
+
+
+def qeq_path(ff, system, qp, tol, mode, **kw):
+    """gpu_qeq with the product `mode`, and the product that ran: "half"
+    (matrix-free over the half far list) or "stored"."""
+    ff.set_qeq_product(mode)
+    ff._lib.reaxff_profile(ff._h, 1)
+    try:
+        out = gpu_qeq(ff, system, qp, tol, **kw)
+        k = launches(ff)
+    finally:
+        ff._lib.reaxff_profile(ff._h, 0)
+        ff.set_qeq_product("auto")
+    half, rows = k.get("qeq_half", 0), k.get("qeq_rows", 0)
+    assert (half > 0) != (rows > 0), k
+    return out, "half" if half else "stored"
+
+
 def dense(system, params, qp):
     far, _, _ = Oracle(system, params).lists()
     H = Q.qeq_matrix(system, params, qp, far)
@@ -133,28 +160,39 @@ def test_extrapolated_start(ff, params, qp):
     assert sum(its[True][2:]) < sum(its[False][2:]), its
 
 
-def test_box_32480_against_sparse_oracle(ff, params, qp):
+@pytest.fixture(scope="module")
+def box32480(params, qp):
     s = rs.workload("petn_32480")
     print(f"qeq 32480: oracle lists", flush=True)
     far, _, _ = Oracle(s, params).lists()
-    Hs = Q.qeq_sparse(s, params, qp, far)
+    return s, Q.qeq_sparse(s, params, qp, far)
+
+
+@pytest.mark.parametrize("mode", ["auto", "stored"])
+def test_box_32480_against_sparse_oracle(ff, params, qp, box32480, mode):
+    """Both products: the matrix-free one over the half far list (what "auto"
+    takes on this grid) and the stored rows."""
+    s, Hs = box32480
     J, chi = Q.qeq_diag(s, qp)
     q_cg, s_cg, t_cg, it_cg, res_cg = Q.qeq_cg(Hs, chi, J, tol=1e-10)
-    q, it, res, sg, tg = gpu_qeq(ff, s, qp, tol=1e-10)
+    (q, it, res, sg, tg), path = qeq_path(ff, s, qp, 1e-10, mode)
+    assert path == ("half" if mode == "auto" else "stored")
     assert abs(it - it_cg) <= 1, (it, it_cg)
     assert np.abs(q - q_cg).max() <= 1e-8 * np.abs(q_cg).max()
     assert np.linalg.norm(Hs @ sg + chi) / np.linalg.norm(chi) <= 1e-10 * (1 + 1e-6)
 
 
-def test_full_size_sampled_stationarity(ff, params, qp):
-    """1,044,000 atoms: chi_i + (H q)_i equals the common multiplier on sampled
-    atoms (their rows of H recomputed on the host from the positions), and the
-    charges are neutral."""
+@pytest.mark.parametrize("mode", ["auto", "stored"])
+def test_full_size_sampled_stationarity(ff, params, qp, mode):
+    """1,044,000 atoms, both products: chi_i + (H q)_i equals the common
+    multiplier on sampled atoms (their rows of H recomputed on the host from
+    the positions), and the charges are neutral."""
     from scipy.spatial import cKDTree
     s = rs.workload("petn_1044000")
     tol = 1e-10
-    q, it, res, sg, tg = gpu_qeq(ff, s, qp, tol=tol)
-    print(f"qeq 1044000: {it} iterations, residuals {res}", flush=True)
+    (q, it, res, sg, tg), path = qeq_path(ff, s, qp, tol, mode)
+    assert path == ("half" if mode == "auto" else "stored")
+    print(f"qeq 1044000 ({path}): {it} iterations, residuals {res}", flush=True)
     assert max(res) <= tol
     assert abs(q.sum()) <= 1e-9 * np.abs(q).sum()
     box = np.asarray(s.box)
@@ -175,6 +213,40 @@ def test_full_size_sampled_stationarity(ff, params, qp):
     lam = -(sg.sum() / tg.sum())    # q = s + lam t
     bound = tol * (np.linalg.norm(chi) + abs(lam) * np.sqrt(s.n))
     assert np.ptp(g) <= 2 * bound, (np.ptp(g), bound)
+
+
+def test_matrix_free_on_kept_skin_lists(params, qp, box32480):
+    """Skin lists kept by a refresh after every atom moved (by less than
+    skin / 2): the half far rows then hold pairs out to r_nonb + skin, which
+    the matrix-free product must leave out; its charges at the moved positions
+    against the oracle's sparse CG there, and against the stored rows."""
+    import torch
+    from paper_1706_07772_amd import ReaxFF
+    s0, _ = box32480
+    rng = np.random.default_rng(77)
+    moved = rs.System(pos=s0.pos + rng.uniform(-0.25, 0.25, s0.pos.shape), type=s0.type, q=s0.q, box=s0.box)
+    ff = ReaxFF(params)
+    try:
+        ff.set_skin(1.0, 10)
+        d = torch.device("cuda:0")
+        T = torch.tensor(s0.type, dtype=torch.int32, device=d)
+        ff.build_lists(torch.tensor(s0.pos, dtype=torch.float64, device=d), T, s0.box)
+        rebuilt = ff.refresh_lists(torch.tensor(moved.pos, dtype=torch.float64, device=d), T, s0.box)
+        assert not rebuilt
+        (q, it, res, sg, tg), path = qeq_path(ff, moved, qp, 1e-10, "auto", build=False)
+        assert path == "half"
+        (q2, it2, _, _, _), path2 = qeq_path(ff, moved, qp, 1e-10, "stored", build=False)
+        assert path2 == "stored"
+    finally:
+        ff.close()
+    far, _, _ = Oracle(moved, params).lists()
+    Hs = Q.qeq_sparse(moved, params, qp, far)
+    J, chi = Q.qeq_diag(moved, qp)
+    q_cg, s_cg, t_cg, it_cg, _ = Q.qeq_cg(Hs, chi, J, tol=1e-10)
+    assert abs(it - it_cg) <= 1 and abs(it2 - it_cg) <= 1, (it, it2, it_cg)
+    assert np.abs(q - q_cg).max() <= 1e-8 * np.abs(q_cg).max()
+    assert np.abs(q2 - q_cg).max() <= 1e-8 * np.abs(q_cg).max()
+    assert np.linalg.norm(Hs @ sg + chi) / np.linalg.norm(chi) <= 1e-10 * (1 + 1e-6)
 
 
 def test_edge_cases(ff, params, qp):
