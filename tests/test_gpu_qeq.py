@@ -215,6 +215,27 @@ def test_full_size_sampled_stationarity(ff, params, qp, mode):
     assert np.ptp(g) <= 2 * bound, (np.ptp(g), bound)
 
 
+@pytest.mark.parametrize("run_max", [1, 3])
+def test_matrix_free_run_lengths(params, qp, box32480, run_max):
+    """The matrix-free product with runs of 1 and 3 cells per workgroup (other
+    window shapes and partial-array layouts than the default 8) against the
+    stored rows on the same lists."""
+    from paper_1706_07772_amd import ReaxFF
+    s, _ = box32480
+    ff = ReaxFF(params)
+    try:
+        ff.set_nb_run(run_max)
+        (q, it, res, sg, tg), path = qeq_path(ff, s, qp, 1e-10, "auto")
+        assert path == "half"
+        (q2, it2, _, _, _), path2 = qeq_path(ff, s, qp, 1e-10, "stored", build=False)
+        assert path2 == "stored"
+    finally:
+        ff.close()
+    assert abs(it - it2) <= 1, (it, it2)
+    assert max(res) <= 1e-10
+    assert np.abs(q - q2).max() <= 1e-9 * np.abs(q2).max()
+
+
 def test_matrix_free_on_kept_skin_lists(params, qp, box32480):
     """Skin lists kept by a refresh after every atom moved (by less than
     skin / 2): the half far rows then hold pairs out to r_nonb + skin, which
